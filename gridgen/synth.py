@@ -1,0 +1,336 @@
+"""Seeded synthetic inputs for the batched DC-loadflow screen.
+
+Input data only: grid topology, susceptances, balanced nodal injections,
+monitored / contingency branch sets, topology candidates and injection
+variants.  Nothing here solves a loadflow; branch ratings, which depend on the
+base-case flows, are derived by each consumer (the solver library computes
+them on the device, the CPU oracle computes its own).
+
+Grid recipe (random geometric meshed grid):
+  * bus positions uniform in [0, 1)^2;
+  * spanning tree: buses in random order, each attached to the nearest bus
+    already placed;
+  * chords: a random bus joined to one of its 2nd..5th nearest buses, no
+    duplicates, no self loops, until the branch count is reached;
+  * random orientation per branch, reactance x ~ lognormal(-2.5, 0.5) p.u.,
+    susceptance b = 1/x;
+  * injections P ~ N(0, 1) shifted to sum to zero; bus 0 is the slack.
+
+Candidate encoding (one record per topology candidate, CSR over elements):
+  kind 0 = remedial outage of branch ``id`` (the paper's t_d);
+  kind 1 = two-way split of bus ``id`` (the paper's t_b): bit i of ``mask``
+  moves the i-th incident branch of the bus (incident branches taken in
+  ascending branch id) onto the new busbar B; ``p_new`` is the injection that
+  moves with them (0: the bus injection stays on busbar A).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy.sparse import coo_matrix
+from scipy.sparse.csgraph import connected_components
+from scipy.spatial import cKDTree
+
+KIND_OUTAGE = 0
+KIND_SPLIT = 1
+MAX_RANK = 8          # elements per candidate
+MAX_SPLIT_DEGREE = 32  # incident branches addressable by a 32-bit mask
+
+
+@dataclass
+class Grid:
+    n_bus: int
+    f: np.ndarray      # int32 [m] from bus
+    t: np.ndarray      # int32 [m] to bus
+    x: np.ndarray      # float64 [m] reactance
+    b: np.ndarray      # float64 [m] susceptance 1/x
+    p: np.ndarray      # float64 [n] balanced base injections
+    pos: np.ndarray    # float64 [n, 2]
+    slack: int = 0
+
+    @property
+    def n_branch(self) -> int:
+        return int(self.f.shape[0])
+
+    def incident(self, bus: int) -> np.ndarray:
+        """Branch ids touching ``bus`` in ascending order (mask bit order)."""
+        return np.flatnonzero((self.f == bus) | (self.t == bus)).astype(np.int32)
+
+    def degree(self) -> np.ndarray:
+        return np.bincount(np.concatenate([self.f, self.t]), minlength=self.n_bus)
+
+
+@dataclass
+class Candidates:
+    off: np.ndarray     # int32 [n_cand + 1]
+    kind: np.ndarray    # int8  [n_elem]
+    id: np.ndarray      # int32 [n_elem]
+    mask: np.ndarray    # uint32 [n_elem]
+    p_new: np.ndarray   # float64 [n_elem]
+
+    @property
+    def n_cand(self) -> int:
+        return int(self.off.shape[0] - 1)
+
+    @property
+    def n_elem(self) -> int:
+        return int(self.kind.shape[0])
+
+    def elements(self, i: int):
+        """List of (kind, id, mask, p_new) tuples of candidate ``i``."""
+        a, e = int(self.off[i]), int(self.off[i + 1])
+        return [(int(self.kind[j]), int(self.id[j]), int(self.mask[j]), float(self.p_new[j]))
+                for j in range(a, e)]
+
+    def subset(self, idx) -> "Candidates":
+        return Candidates.from_lists([self.elements(int(i)) for i in idx])
+
+    @staticmethod
+    def from_lists(cands) -> "Candidates":
+        off = np.zeros(len(cands) + 1, np.int32)
+        kind, ids, masks, pn = [], [], [], []
+        for i, els in enumerate(cands):
+            off[i + 1] = off[i] + len(els)
+            for (k, d, m, p) in els:
+                kind.append(k)
+                ids.append(d)
+                masks.append(m)
+                pn.append(p)
+        return Candidates(off, np.asarray(kind, np.int8), np.asarray(ids, np.int32),
+                          np.asarray(masks, np.uint32), np.asarray(pn, np.float64))
+
+
+@dataclass
+class Workload:
+    name: str
+    grid: Grid
+    mon: np.ndarray          # int32 monitored branch ids (E_m)
+    out: np.ndarray          # int32 N-1 contingency branch ids (O)
+    cands: Candidates
+    inj: np.ndarray          # float64 [V, n] (shared) or [n_cand, V, n]
+    inj_shared: bool
+    rating_scale: float = 1.2
+    rating_offset: float = 0.1
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_var(self) -> int:
+        return int(self.inj.shape[-2])
+
+
+# ---------------------------------------------------------------- grid
+
+def make_grid(n_bus: int, n_branch: int, seed: int) -> Grid:
+    if n_branch < n_bus - 1:
+        raise ValueError("need at least n_bus - 1 branches for a connected grid")
+    rng = np.random.default_rng(seed)
+    pos = rng.random((n_bus, 2))
+    order = rng.permutation(n_bus)
+    edges = []
+    placed = np.empty((n_bus, 2))
+    placed_ids = np.empty(n_bus, np.int64)
+    placed[0] = pos[order[0]]
+    placed_ids[0] = order[0]
+    for i in range(1, n_bus):
+        u = order[i]
+        d = np.sum((placed[:i] - pos[u]) ** 2, axis=1)
+        v = placed_ids[int(np.argmin(d))]
+        edges.append((int(v), int(u)))
+        placed[i] = pos[u]
+        placed_ids[i] = u
+    have = {(min(a, c), max(a, c)) for a, c in edges}
+    kq = min(6, n_bus)
+    _, nbr = cKDTree(pos).query(pos, k=kq)
+    tries = 0
+    while len(edges) < n_branch:
+        tries += 1
+        if tries > 200 * n_branch:
+            raise RuntimeError("could not place the requested number of chords")
+        u = int(rng.integers(n_bus))
+        lo = min(2, kq - 1)
+        v = int(nbr[u, int(rng.integers(lo, kq))])
+        if u == v:
+            continue
+        key = (min(u, v), max(u, v))
+        if key in have:
+            continue
+        have.add(key)
+        edges.append((u, v))
+    e = np.asarray(edges, np.int64)
+    flip = rng.random(len(e)) < 0.5
+    f = np.where(flip, e[:, 1], e[:, 0]).astype(np.int32)
+    t = np.where(flip, e[:, 0], e[:, 1]).astype(np.int32)
+    x = rng.lognormal(mean=-2.5, sigma=0.5, size=len(e))
+    p = rng.normal(0.0, 1.0, n_bus)
+    p -= p.mean()
+    return Grid(n_bus=n_bus, f=f, t=t, x=x, b=1.0 / x, p=p, pos=pos, slack=0)
+
+
+# ------------------------------------------------------- topology helpers
+
+def candidate_topology(grid: Grid, elems):
+    """Post-change edge list of a candidate: (n_nodes, f, t, alive).
+
+    New busbar of the j-th split (in element order) gets node id n_bus + j.
+    """
+    f = grid.f.astype(np.int64).copy()
+    t = grid.t.astype(np.int64).copy()
+    alive = np.ones(grid.n_branch, bool)
+    n_new = 0
+    for (k, d, m, _p) in elems:
+        if k == KIND_SPLIT:
+            inc = grid.incident(d)
+            newbus = grid.n_bus + n_new
+            n_new += 1
+            for bit, br in enumerate(inc):
+                if (m >> bit) & 1:
+                    if grid.f[br] == d:
+                        f[br] = newbus
+                    else:
+                        t[br] = newbus
+        else:
+            alive[d] = False
+    return grid.n_bus + n_new, f, t, alive
+
+
+def is_connected(n_nodes: int, f, t, alive=None) -> bool:
+    if alive is not None:
+        f = f[alive]
+        t = t[alive]
+    if n_nodes <= 1:
+        return True
+    g = coo_matrix((np.ones(len(f)), (f, t)), shape=(n_nodes, n_nodes))
+    nc, _ = connected_components(g, directed=False)
+    return nc == 1
+
+
+def non_bridges(grid: Grid, rng, count: int) -> np.ndarray:
+    """``count`` distinct branch ids, uniform among non-bridges of the grid."""
+    chosen = []
+    for br in rng.permutation(grid.n_branch):
+        alive = np.ones(grid.n_branch, bool)
+        alive[br] = False
+        if is_connected(grid.n_bus, grid.f, grid.t, alive):
+            chosen.append(int(br))
+            if len(chosen) == count:
+                break
+    if len(chosen) < count:
+        raise ValueError("grid has fewer non-bridge branches than requested")
+    return np.sort(np.asarray(chosen, np.int32))
+
+
+def _split_buses(grid: Grid) -> np.ndarray:
+    deg = grid.degree()
+    return np.flatnonzero((deg >= 3) & (deg <= MAX_SPLIT_DEGREE))
+
+
+def random_split(grid: Grid, rng, bus: int):
+    """Canonical non-trivial mask: bit 0 clear (first branch stays on A)."""
+    d = len(grid.incident(bus))
+    m = int(rng.integers(1, 1 << (d - 1))) << 1
+    return (KIND_SPLIT, int(bus), m, 0.0)
+
+
+def sample_candidate(grid: Grid, rng, n_split: int, n_out: int, split_buses=None,
+                     max_tries: int = 200):
+    """One connected candidate with ``n_split`` bus splits then ``n_out``
+    remedial outages (outages drawn among non-bridges of the split grid)."""
+    if split_buses is None:
+        split_buses = _split_buses(grid)
+    for _ in range(max_tries):
+        buses = rng.choice(split_buses, size=n_split, replace=False) if n_split else []
+        elems = [random_split(grid, rng, int(bus)) for bus in buses]
+        n_nodes, f, t, alive = candidate_topology(grid, elems)
+        if not is_connected(n_nodes, f, t, alive):
+            continue
+        ok = True
+        for _o in range(n_out):
+            for _r in range(max_tries):
+                br = int(rng.integers(grid.n_branch))
+                if not alive[br]:
+                    continue
+                alive[br] = False
+                if is_connected(n_nodes, f, t, alive):
+                    elems.append((KIND_OUTAGE, br, 0, 0.0))
+                    break
+                alive[br] = True
+            else:
+                ok = False
+                break
+        if ok:
+            return elems
+    raise RuntimeError("could not sample a connected candidate")
+
+
+def balanced(p: np.ndarray, slack: int) -> np.ndarray:
+    """Return ``p`` with the slack entry set so every row sums to zero."""
+    q = np.array(p, dtype=np.float64, copy=True)
+    q[..., slack] = 0.0
+    q[..., slack] = -q.sum(axis=-1)
+    return q
+
+
+def perturbed_injections(grid: Grid, rng, shape, rel_sigma: float) -> np.ndarray:
+    """Load perturbations P_v = P_base (1 + rel_sigma g), g ~ N(0, 1) per bus."""
+    g = rng.normal(0.0, 1.0, tuple(shape) + (grid.n_bus,))
+    return balanced(grid.p * (1.0 + rel_sigma * g), grid.slack)
+
+
+# ------------------------------------------------------------- workloads
+
+def workload_tiny(seed: int = 0, n_cand: int = 100) -> Workload:
+    """30 buses / 41 branches, single-split candidates, one injection, N-1 over
+    every branch (bridges included), FP64."""
+    rng = np.random.default_rng(seed + 1000)
+    grid = make_grid(30, 41, seed)
+    allbr = np.arange(grid.n_branch, dtype=np.int32)
+    cands = Candidates.from_lists(
+        [sample_candidate(grid, rng, 1, 0) for _ in range(n_cand)])
+    inj = balanced(grid.p, grid.slack)[None, :]
+    return Workload("tiny-30bus", grid, allbr, allbr, cands, inj, True,
+                    meta=dict(n_bus=30, n_branch=41, n_cand=n_cand, n_var=1))
+
+
+def workload_medium(seed: int = 0, n_cand: int = 4096, n_var: int = 16,
+                    n_out: int = 500) -> Workload:
+    """1,000 buses / 1,600 branches, 1-3 splits plus 0-2 outages per candidate,
+    16 load-perturbed injection variants per candidate, the 500 contingency
+    branches are also the monitored set."""
+    rng = np.random.default_rng(seed + 2000)
+    grid = make_grid(1000, 1600, seed)
+    out = non_bridges(grid, rng, n_out)
+    sb = _split_buses(grid)
+    lists = []
+    for _ in range(n_cand):
+        ns = int(rng.integers(1, 4))
+        no = int(rng.integers(0, 3))
+        lists.append(sample_candidate(grid, rng, ns, no, sb))
+    cands = Candidates.from_lists(lists)
+    inj = perturbed_injections(grid, rng, (n_cand, n_var), 0.05)
+    return Workload("medium-1000bus", grid, out.copy(), out, cands, inj, False,
+                    meta=dict(n_bus=1000, n_branch=1600, n_cand=n_cand, n_var=n_var,
+                              n_out=n_out))
+
+
+def workload_uneven(seed: int = 0, n_cand: int = 65536, n_out: int = 2000,
+                    n_bus: int = 10000, n_branch: int = 15500) -> Workload:
+    """10,000 buses / 15,500 branches, rank uniform in 1..8 (each element a
+    split with probability 1/2, else an outage), one perturbed injection per
+    candidate, every branch monitored, 2,000 contingencies."""
+    rng = np.random.default_rng(seed + 3000)
+    grid = make_grid(n_bus, n_branch, seed)
+    out = non_bridges(grid, rng, n_out)
+    sb = _split_buses(grid)
+    lists = []
+    for _ in range(n_cand):
+        k = int(rng.integers(1, MAX_RANK + 1))
+        ns = int(rng.binomial(k, 0.5))
+        lists.append(sample_candidate(grid, rng, ns, k - ns, sb))
+    cands = Candidates.from_lists(lists)
+    inj = perturbed_injections(grid, rng, (n_cand, 1), 0.05)
+    mon = np.arange(grid.n_branch, dtype=np.int32)
+    return Workload("uneven-10000bus", grid, mon, out, cands, inj, False,
+                    meta=dict(n_bus=n_bus, n_branch=n_branch, n_cand=n_cand, n_var=1,
+                              n_out=n_out))
+

@@ -1,0 +1,358 @@
+"""Plain FP64 CPU oracle for the batched DC-loadflow screen.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the solver library imports, links or
+calls this module; only the tests, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it.
+
+It computes, slowly and directly, what the GPU path computes with low-rank
+updates: for every topology candidate the grid is rebuilt (busbar splits
+re-terminate branches on a new node, remedial outages drop branches), the
+reduced nodal susceptance system is factorised from scratch by dense LU
+(LAPACK getrf/getrs, partial pivoting) and solved for every injection variant.
+No base PTDF, BSDF or MODF is ever used.
+
+Paper passages followed (Westerbeck et al., "Accelerated DC loadflow solver
+for topology optimization"):
+  * Sec. II, definition of the weighted connectivity matrix C_w and of the
+    nodal susceptance matrix B (a graph Laplacian); slack exclusion (primes).
+  * Sec. II, Def. of the PTDF (PTDF' B' = C_w', slack column zero) and the N-0
+    flows p = PTDF P (Eq. ptdf_times_nodal_inj).
+  * Sec. II, Def. of the LODF and Eq. lodf_delta for N-1 flows, applied with
+    the candidate network's own PTDF.
+  * Sec. III-A, task definition: N-0 and N-1 flows over monitored branches,
+    agg_m = maximum relative branch load, t_i* = argmin over the injection
+    variants (Eq. solver_end_to_end).
+
+Readings where the paper is silent (each also listed in the design doc):
+  * the new busbar of the j-th split of a candidate is node n_bus + j;
+  * the slack absorbs any imbalance (its injection is minus the sum of the
+    others), which leaves all flows unchanged since its PTDF column is zero;
+  * an N-1 contingency that is a bridge of the candidate network islands part
+    of the grid: it is excluded from the score and counted;
+  * an N-1 contingency already removed by a remedial outage leaves the N-0
+    flows unchanged (it is still scored);
+  * agg_m covers N-0 and every valid N-1 case over the monitored branches;
+    the overload sum adds max(0, |p|/r - 1) over the same set for the best
+    variant; ties pick the lowest variant, then the lowest (outage, branch)
+    with the N-0 case first.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+KIND_OUTAGE = 0
+KIND_SPLIT = 1
+
+ST_DISCONNECTED = 1
+ST_SINGULAR = 2
+ST_NONFINITE = 4
+
+
+# ------------------------------------------------------------- matrices
+
+def weighted_connectivity(n, f, t, b):
+    """C_w[l, f_l] = b_l, C_w[l, t_l] = -b_l (Sec. II definition)."""
+    m = len(f)
+    cw = np.zeros((m, n))
+    rows = np.arange(m)
+    cw[rows, f] += b
+    cw[rows, t] -= b
+    return cw
+
+
+def nodal_susceptance(n, f, t, b):
+    """Graph Laplacian B: off-diagonal -b per edge, diagonal = sum of incident b."""
+    bm = np.zeros((n, n))
+    for fl, tl, bl in zip(f, t, b):
+        bm[fl, fl] += bl
+        bm[tl, tl] += bl
+        bm[fl, tl] -= bl
+        bm[tl, fl] -= bl
+    return bm
+
+
+def _keep(n, slack):
+    return np.array([i for i in range(n) if i != slack], dtype=np.int64)
+
+
+def ptdf(n, f, t, b, slack):
+    """Solution of PTDF' B' = C_w' with a zero slack column (Def. eq_ptdf)."""
+    keep = _keep(n, slack)
+    br = nodal_susceptance(n, f, t, b)[np.ix_(keep, keep)]
+    cw = weighted_connectivity(n, f, t, b)[:, keep]
+    # PTDF' = C_w' B'^-1 ; B' is symmetric, so solve B' Y = C_w'^T, PTDF' = Y^T.
+    y = sla.solve(br, cw.T)
+    h = np.zeros((len(f), n))
+    h[:, keep] = y.T
+    return h
+
+
+def dc_flows(n, f, t, b, slack, p):
+    """Branch flows for nodal injections ``p`` ([n] or [V, n]) by a dense LU
+    solve of the reduced system B' theta' = P' (theta_slack = 0)."""
+    p = np.atleast_2d(np.asarray(p, np.float64))
+    keep = _keep(n, slack)
+    br = nodal_susceptance(n, f, t, b)[np.ix_(keep, keep)]
+    theta = np.zeros((p.shape[0], n))
+    theta[:, keep] = sla.lu_solve(sla.lu_factor(br), p[:, keep].T).T
+    return b * (theta[:, f] - theta[:, t])
+
+
+# ------------------------------------------------------------ graph tests
+
+def connected(n, f, t):
+    """Union-find connectivity test."""
+    parent = list(range(n))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    comps = n
+    for a, c in zip(f, t):
+        ra, rc = find(int(a)), find(int(c))
+        if ra != rc:
+            parent[ra] = rc
+            comps -= 1
+    return comps == 1
+
+
+def bridges(n, f, t):
+    """Bridge edges of an undirected multigraph (Tarjan low-link, iterative).
+    Parallel edges are distinguished by edge id, so a doubled line is no bridge."""
+    m = len(f)
+    adj = [[] for _ in range(n)]
+    for e in range(m):
+        adj[int(f[e])].append((int(t[e]), e))
+        adj[int(t[e])].append((int(f[e]), e))
+    disc = [-1] * n
+    low = [0] * n
+    out = np.zeros(m, bool)
+    timer = 0
+    for root in range(n):
+        if disc[root] != -1:
+            continue
+        disc[root] = low[root] = timer
+        timer += 1
+        stack = [(root, -1, iter(adj[root]))]
+        while stack:
+            u, pe, it = stack[-1]
+            descended = False
+            for (w, e) in it:
+                if e == pe:
+                    continue
+                if disc[w] == -1:
+                    disc[w] = low[w] = timer
+                    timer += 1
+                    stack.append((w, e, iter(adj[w])))
+                    descended = True
+                    break
+                low[u] = min(low[u], disc[w])
+            if descended:
+                continue
+            stack.pop()
+            if stack:
+                par = stack[-1][0]
+                low[par] = min(low[par], low[u])
+                if low[u] > disc[par]:
+                    out[pe] = True
+    return out
+
+
+# ----------------------------------------------------- candidate rebuild
+
+def incident_branches(f, t, bus):
+    return np.flatnonzero((np.asarray(f) == bus) | (np.asarray(t) == bus))
+
+
+def rebuild(n, f, t, elems):
+    """Post-change network of a candidate (step 1 of the oracle).
+
+    Returns (n_nodes, f2, t2, alive, splits) where splits lists
+    (A, B, p_new) per split in element order; B = n + j for the j-th split.
+    Branch ids are kept; removed branches have alive = False.
+    """
+    f2 = np.asarray(f, np.int64).copy()
+    t2 = np.asarray(t, np.int64).copy()
+    alive = np.ones(len(f2), bool)
+    splits = []
+    for (kind, ident, mask, p_new) in elems:
+        if kind == KIND_SPLIT:
+            a = int(ident)
+            newbus = n + len(splits)
+            for bit, br in enumerate(incident_branches(f, t, a)):
+                if (int(mask) >> bit) & 1:
+                    if f[br] == a:
+                        f2[br] = newbus
+                    else:
+                        t2[br] = newbus
+            splits.append((a, newbus, float(p_new)))
+        elif kind == KIND_OUTAGE:
+            alive[int(ident)] = False
+        else:
+            raise ValueError(f"unknown element kind {kind}")
+    return n + len(splits), f2, t2, alive, splits
+
+
+def candidate_injections(n_nodes, x, splits, slack):
+    """Injections of the rebuilt network for base-numbered variants ``x``
+    ([V, n]): busbar B_j receives p_new_j, taken from its parent bus A_j; the
+    slack absorbs the imbalance."""
+    x = np.atleast_2d(np.asarray(x, np.float64))
+    v, n = x.shape
+    p = np.zeros((v, n_nodes))
+    p[:, :n] = x
+    for (a, bnew, pn) in splits:
+        p[:, bnew] += pn
+        p[:, a] -= pn
+    p[:, slack] = 0.0
+    p[:, slack] = -p.sum(axis=1)
+    return p
+
+
+def ratings(n, f, t, b, slack, p_base, mon, scale=1.2, offset=0.1):
+    """Workload rating rule: r = scale |base flow| + offset on monitored rows."""
+    fb = dc_flows(n, f, t, b, slack, p_base)[0]
+    return scale * np.abs(fb[np.asarray(mon)]) + offset
+
+
+# ---------------------------------------------------- per-candidate solve
+
+def candidate_flows(n, f, t, b, slack, elems, x, out):
+    """N-0 flows and N-1 flows of a candidate, by rebuild + dense LU.
+
+    Returns dict with
+      p0 [V, m]          N-0 flows (0 on removed branches);
+      state [|O|]        0 = valid LODF case, 1 = already removed (p1 = p0),
+                         2 = islanding (bridge of the candidate network);
+      lodf [m, |O|]      LODF columns of the candidate network (Def. eq_lodf,
+                         with LODF[c, c] = -1), zero for states 1 and 2;
+      den [|O|]          LODF denominators 1 - (PTDF'[c, f_c] - PTDF'[c, t_c]);
+      connected          False if the candidate network itself is islanded.
+    """
+    n2, f2, t2, alive, splits = rebuild(n, f, t, elems)
+    m = len(f2)
+    fa, ta, ba = f2[alive], t2[alive], np.asarray(b)[alive]
+    res = dict(n_nodes=n2, f=f2, t=t2, alive=alive, splits=splits)
+    if not connected(n2, fa, ta):
+        res["connected"] = False
+        return res
+    res["connected"] = True
+    keep = _keep(n2, slack)
+    br = nodal_susceptance(n2, fa, ta, ba)[np.ix_(keep, keep)]
+    lu = sla.lu_factor(br)
+    p = candidate_injections(n2, x, splits, slack)
+    theta = np.zeros((p.shape[0], n2))
+    theta[:, keep] = sla.lu_solve(lu, p[:, keep].T).T
+    p0 = np.zeros((p.shape[0], m))
+    p0[:, alive] = ba * (theta[:, fa] - theta[:, ta])
+    res["p0"] = p0
+
+    out = np.asarray(out, np.int64)
+    isb = np.zeros(m, bool)
+    isb[np.flatnonzero(alive)] = bridges(n2, fa, ta)
+    state = np.zeros(len(out), np.int8)
+    state[~alive[out]] = 1
+    state[alive[out] & isb[out]] = 2
+    lodf = np.zeros((m, len(out)))
+    den = np.zeros(len(out))
+    valid = np.flatnonzero(state == 0)
+    if len(valid):
+        cs = out[valid]
+        # PTDF' of the candidate network applied to the transfer d_c = e_f' - e_t'
+        d = np.zeros((n2, len(cs)))
+        d[f2[cs], np.arange(len(cs))] += 1.0
+        d[t2[cs], np.arange(len(cs))] -= 1.0
+        xs = np.zeros((n2, len(cs)))
+        xs[keep] = sla.lu_solve(lu, d[keep])
+        col = np.zeros((m, len(cs)))
+        col[alive] = ba[:, None] * (xs[fa] - xs[ta])
+        dd = 1.0 - col[cs, np.arange(len(cs))]
+        lodf[:, valid] = col / dd
+        lodf[cs, valid] = -1.0
+        den[valid] = dd
+    res.update(state=state, lodf=lodf, den=den)
+    return res
+
+
+def n1_flows_bruteforce(n, f, t, b, slack, elems, x, out):
+    """N-1 flows by rebuilding the candidate network without each contingency
+    and solving again (one factorisation per case).  Returns (p1 [V, |O|, m],
+    islanded [|O|])."""
+    n2, f2, t2, alive, splits = rebuild(n, f, t, elems)
+    p = candidate_injections(n2, x, splits, slack)
+    m = len(f2)
+    out = np.asarray(out, np.int64)
+    p1 = np.zeros((p.shape[0], len(out), m))
+    isl = np.zeros(len(out), bool)
+    keep = _keep(n2, slack)
+    for ci, c in enumerate(out):
+        al = alive.copy()
+        al[c] = False
+        fa, ta, ba = f2[al], t2[al], np.asarray(b)[al]
+        if not connected(n2, fa, ta):
+            isl[ci] = True
+            continue
+        br = nodal_susceptance(n2, fa, ta, ba)[np.ix_(keep, keep)]
+        theta = np.zeros((p.shape[0], n2))
+        theta[:, keep] = sla.solve(br, p[:, keep].T).T
+        p1[:, ci, al] = ba * (theta[:, fa] - theta[:, ta])
+    return p1, isl
+
+
+def score_candidate(n, f, t, b, slack, elems, x, mon, out, rating):
+    """Score one candidate over its injection variants (Sec. III-A).
+
+    Returns dict(max_load [V], best_variant, best_max_load, overload_sum,
+    worst_branch, worst_outage, n_island, status)."""
+    mon = np.asarray(mon, np.int64)
+    out = np.asarray(out, np.int64)
+    r = np.asarray(rating, np.float64)
+    cf = candidate_flows(n, f, t, b, slack, elems, x, out)
+    nv = np.atleast_2d(x).shape[0]
+    if not cf["connected"]:
+        return dict(max_load=np.full(nv, np.inf), best_variant=-1, best_max_load=np.inf,
+                    overload_sum=0.0, worst_branch=-1, worst_outage=-1, n_island=0,
+                    status=ST_DISCONNECTED, flows=cf)
+    p0 = cf["p0"]
+    state = cf["state"]
+    lodf = cf["lodf"]
+    scored = np.flatnonzero(state != 2)
+    # N-1 flows on the monitored rows: p1[v, c, l] = p0[v, l] + LODF[l, c] p0[v, c]
+    p1 = p0[:, None, mon] + lodf[mon][:, scored].T[None, :, :] * p0[:, out[scored]][:, :, None]
+    load0 = np.abs(p0[:, mon]) / r
+    load1 = np.abs(p1) / r
+    maxl = load0.max(axis=1)
+    if len(scored):
+        maxl = np.maximum(maxl, load1.reshape(nv, -1).max(axis=1))
+    best = int(np.argmin(maxl))
+    allload = np.concatenate([load0[best][None, :], load1[best]], axis=0)
+    ov = float(np.maximum(allload - 1.0, 0.0).sum())
+    flat = int(np.argmax(allload))
+    ci, li = divmod(flat, len(mon))
+    worst_out = -1 if ci == 0 else int(out[scored[ci - 1]])
+    status = 0
+    if not np.all(np.isfinite(maxl)):
+        status |= ST_NONFINITE
+    return dict(max_load=maxl, best_variant=best, best_max_load=float(maxl[best]),
+                overload_sum=ov, worst_branch=int(mon[li]), worst_outage=worst_out,
+                n_island=int((state == 2).sum()), status=status, flows=cf)
+
+
+def score_workload(w, idx=None, rating=None):
+    """Score the candidates ``idx`` (default all) of a gridgen Workload."""
+    g = w.grid
+    if rating is None:
+        rating = ratings(g.n_bus, g.f, g.t, g.b, g.slack, g.p, w.mon,
+                         w.rating_scale, w.rating_offset)
+    if idx is None:
+        idx = range(w.cands.n_cand)
+    res = []
+    for i in idx:
+        x = w.inj if w.inj_shared else w.inj[i]
+        res.append(score_candidate(g.n_bus, g.f, g.t, g.b, g.slack, w.cands.elements(int(i)),
+                                   x, w.mon, w.out, rating))
+    return res, rating

@@ -1,0 +1,349 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself:
+closed forms, physical invariants, brute force and the paper's own formulas."""
+import itertools
+
+import numpy as np
+import pytest
+
+import gridgen as G
+from oracle import dcflow_oracle as O
+from oracle import paper_formulas as PF
+
+
+def _incidence_balance(n, f, t, alive, flows, p):
+    """Net outflow minus injection at every node."""
+    bal = np.zeros((flows.shape[0], n))
+    fa, ta = f[alive], t[alive]
+    for v in range(flows.shape[0]):
+        np.add.at(bal[v], fa, flows[v, alive])
+        np.add.at(bal[v], ta, -flows[v, alive])
+    return bal - p
+
+
+# ------------------------------------------------------------ closed forms
+
+def test_triangle_ptdf_closed_form():
+    # equal reactances: a unit transfer splits 2/3 on the direct edge, 1/3 on the detour
+    f = np.array([1, 1, 2])
+    t = np.array([0, 2, 0])
+    b = np.ones(3) * 7.0
+    h = O.ptdf(3, f, t, b, 0)
+    np.testing.assert_allclose(h[:, 0], 0.0, atol=0)
+    np.testing.assert_allclose(h[:, 1], [2 / 3, 1 / 3, 1 / 3], atol=1e-15)
+    np.testing.assert_allclose(h[:, 2], [1 / 3, -1 / 3, 2 / 3], atol=1e-15)
+
+
+def test_triangle_score_by_hand():
+    # unit susceptances, +1 at bus 1 and +0.5 at bus 2 withdrawn at slack 0.
+    # N-0 = (5/6, 1/6, 2/3).  Losing edge 0 routes bus 1 over 1->2->0: (0, 1, 1.5);
+    # losing edge 1: (1, 0, 0.5); losing edge 2: (1.5, -0.5, 0).
+    f = np.array([1, 1, 2])
+    t = np.array([0, 2, 0])
+    b = np.ones(3)
+    x = np.array([[-1.5, 1.0, 0.5]])
+    r = np.array([1.0, 1.0, 1.2])
+    mon = out = np.arange(3)
+    sc = O.score_candidate(3, f, t, b, 0, [], x, mon, out, r)
+    np.testing.assert_allclose(sc["flows"]["p0"][0], [5 / 6, 1 / 6, 2 / 3], atol=1e-15)
+    assert sc["best_max_load"] == pytest.approx(1.5, abs=1e-14)
+    assert sc["overload_sum"] == pytest.approx(0.25 + 0.5, abs=1e-14)
+    assert sc["n_island"] == 0
+    assert (sc["worst_outage"], sc["worst_branch"]) == (2, 0)
+
+
+def _random_tree(n, seed):
+    rng = np.random.default_rng(seed)
+    par = np.array([-1] + [int(rng.integers(0, i)) for i in range(1, n)])
+    f = np.arange(1, n)
+    t = par[1:]
+    flip = rng.random(n - 1) < 0.5
+    f2 = np.where(flip, t, f)
+    t2 = np.where(flip, f, t)
+    return par, f2, t2, rng
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_radial_tree_closed_form(seed):
+    n = 25
+    par, f, t, rng = _random_tree(n, seed)
+    p = rng.normal(size=n)
+    p[0] = -p[1:].sum()
+    # subtree sums (slack = root 0): the edge (i, par i) carries sum of P below i, towards par
+    sub = p.copy()
+    for i in range(n - 1, 0, -1):
+        sub[par[i]] += sub[i]
+    expect = np.where(f == np.arange(1, n), sub[1:], -sub[1:])
+    for b in (np.ones(n - 1), rng.lognormal(-2.5, 0.5, n - 1)):
+        fl = O.dc_flows(n, f, t, b, 0, p)[0]
+        np.testing.assert_allclose(fl, expect, atol=1e-12)
+
+
+def test_parallel_lines_lodf_is_one():
+    # two identical lines 0-1 plus a line 1-2: losing one doubles the other
+    f = np.array([0, 0, 1])
+    t = np.array([1, 1, 2])
+    b = np.array([4.0, 4.0, 2.0])
+    x = np.array([[1.5, 0.5, -2.0]])
+    cf = O.candidate_flows(3, f, t, b, 0, [], x, [0, 1, 2])
+    assert cf["state"].tolist() == [0, 0, 2]          # line 1-2 is a bridge
+    assert cf["lodf"][1, 0] == pytest.approx(1.0, abs=1e-14)
+    assert cf["lodf"][0, 1] == pytest.approx(1.0, abs=1e-14)
+    assert cf["den"][0] == pytest.approx(0.5, abs=1e-14)
+
+
+def test_unicyclic_grid():
+    # 5-cycle 0..4 plus pendant buses 5 (on 2) and 6 (on 5); x random
+    rng = np.random.default_rng(4)
+    f = np.array([0, 1, 2, 3, 4, 2, 5])
+    t = np.array([1, 2, 3, 4, 0, 5, 6])
+    b = rng.lognormal(-2.5, 0.5, 7)
+    n = 7
+    p = rng.normal(size=n)
+    p[0] = -p[1:].sum()
+    out = np.arange(7)
+    cf = O.candidate_flows(n, f, t, b, 0, [], p, out)
+    assert cf["state"].tolist() == [0, 0, 0, 0, 0, 2, 2]
+    for c in range(5):
+        # losing a cycle edge leaves a tree: flows are the subtree sums
+        keep = np.array([e for e in range(7) if e != c])
+        p1_tree = O.dc_flows(n, f[keep], t[keep], np.ones(6), 0, p)[0]   # reactance-free
+        p1 = cf["p0"][0] + cf["lodf"][:, c] * cf["p0"][0, c]
+        np.testing.assert_allclose(p1[keep], p1_tree, atol=1e-11)
+        assert abs(p1[c]) < 1e-14
+
+
+# ---------------------------------------------------------- invariants
+
+def _mixed_workload(seed, n=60, m=95, n_cand=20):
+    rng = np.random.default_rng(seed)
+    g = G.make_grid(n, m, seed)
+    cands = []
+    for _ in range(n_cand):
+        ns = int(rng.integers(0, 4))
+        no = int(rng.integers(0 if ns else 1, 3))
+        cands.append(G.sample_candidate(g, rng, ns, no))
+    return g, cands, rng
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_kirchhoff_balance(seed):
+    g, cands, rng = _mixed_workload(seed)
+    x = G.perturbed_injections(g, rng, (3,), 0.3)
+    for els in cands:
+        for k, (kind, d, m, _p) in enumerate(els):
+            if kind == G.KIND_SPLIT:
+                els[k] = (kind, d, m, float(rng.normal()))    # move some injection too
+        cf = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, els, x, [])
+        n2, f2, t2, alive, splits = O.rebuild(g.n_bus, g.f, g.t, els)
+        p = O.candidate_injections(n2, x, splits, g.slack)
+        bal = _incidence_balance(n2, f2, t2, alive, cf["p0"], p)
+        assert np.abs(bal).max() < 1e-11
+        assert np.all(cf["p0"][:, ~alive] == 0)
+
+
+def test_slack_absorbs_imbalance():
+    g, cands, rng = _mixed_workload(3, n_cand=3)
+    x = G.perturbed_injections(g, rng, (2,), 0.1)
+    y = x.copy()
+    y[:, g.slack] += 5.0
+    for els in cands:
+        a = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, els, x, [])["p0"]
+        c = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, els, y, [])["p0"]
+        np.testing.assert_allclose(a, c, atol=1e-12)
+
+
+def test_lodf_matches_bruteforce_tiny_workload():
+    w = G.workload_tiny(0)
+    g = w.grid
+    for i in range(w.cands.n_cand):
+        els = w.cands.elements(i)
+        cf = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, els, w.inj, w.out)
+        p1b, isl = O.n1_flows_bruteforce(g.n_bus, g.f, g.t, g.b, g.slack, els, w.inj, w.out)
+        assert np.array_equal(isl, cf["state"] == 2)
+        ok = np.flatnonzero(cf["state"] == 0)
+        p1 = cf["p0"][:, None, :] + cf["lodf"].T[None] * cf["p0"][:, w.out][:, :, None]
+        np.testing.assert_allclose(p1[:, ok], p1b[:, ok], atol=1e-11)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_lodf_matches_bruteforce_with_outages_and_splits(seed):
+    g, cands, rng = _mixed_workload(seed, n_cand=8)
+    x = G.perturbed_injections(g, rng, (2,), 0.3)
+    out = np.arange(g.n_branch)
+    for els in cands:
+        cf = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, els, x, out)
+        p1b, isl = O.n1_flows_bruteforce(g.n_bus, g.f, g.t, g.b, g.slack, els, x, out)
+        st = cf["state"]
+        assert np.array_equal(isl & (st != 1), st == 2)
+        ok = np.flatnonzero(st != 2)
+        p1 = cf["p0"][:, None, :] + cf["lodf"].T[None] * cf["p0"][:, out][:, :, None]
+        np.testing.assert_allclose(p1[:, ok], p1b[:, ok], atol=1e-10)
+
+
+def test_bridges_match_bruteforce():
+    rng = np.random.default_rng(7)
+    for trial in range(30):
+        n = int(rng.integers(3, 12))
+        m = int(rng.integers(n - 1, 2 * n))
+        f = rng.integers(0, n, m)
+        t = (f + rng.integers(1, n, m)) % n
+        br = O.bridges(n, f, t)
+        base = O.connected(n, f, t)
+        for e in range(m):
+            keep = np.arange(m) != e
+            if base:
+                assert br[e] == (not O.connected(n, f[keep], t[keep]))
+
+
+def test_single_edge_split_equals_outage():
+    g, _, rng = _mixed_workload(5, n_cand=0)
+    x = G.perturbed_injections(g, rng, (2,), 0.3)
+    for a in np.flatnonzero(g.degree() >= 3)[:10]:
+        inc = g.incident(int(a))
+        for bit in range(1, len(inc)):
+            split = [(G.KIND_SPLIT, int(a), 1 << bit, 0.0)]
+            outage = [(G.KIND_OUTAGE, int(inc[bit]), 0, 0.0)]
+            n2, f2, t2, al, _ = O.rebuild(g.n_bus, g.f, g.t, outage)
+            if not O.connected(g.n_bus, f2[al], t2[al]):
+                continue
+            s = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, split, x, [])["p0"]
+            o = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, outage, x, [])["p0"]
+            np.testing.assert_allclose(s, o, atol=1e-12)
+
+
+def test_complement_mask_gives_same_flows():
+    g, _, rng = _mixed_workload(6, n_cand=0)
+    x = G.perturbed_injections(g, rng, (1,), 0.3)
+    for a in np.flatnonzero(g.degree() >= 3)[:12]:
+        el = G.random_split(g, rng, int(a))
+        d = len(g.incident(int(a)))
+        comp = ((1 << d) - 1) ^ el[2]
+        pn = 0.3
+        one = [(G.KIND_SPLIT, int(a), el[2], pn)]
+        two = [(G.KIND_SPLIT, int(a), comp, float(x[0, a]) - pn)]
+        r1 = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, one, x, [])
+        if not r1["connected"]:
+            continue
+        r2 = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, two, x, [])
+        if int(a) == g.slack:
+            continue   # the slack stays with busbar A, so the labels are not symmetric
+        np.testing.assert_allclose(r1["p0"], r2["p0"], atol=1e-11)
+
+
+def test_element_order_invariance():
+    g, cands, rng = _mixed_workload(8, n_cand=10)
+    x = G.perturbed_injections(g, rng, (3,), 0.2)
+    out = np.arange(g.n_branch)
+    r = O.ratings(g.n_bus, g.f, g.t, g.b, g.slack, g.p, out)
+    for els in cands:
+        if len(els) < 2:
+            continue
+        perm = list(reversed(els))
+        a = O.score_candidate(g.n_bus, g.f, g.t, g.b, g.slack, els, x, out, out, r)
+        c = O.score_candidate(g.n_bus, g.f, g.t, g.b, g.slack, perm, x, out, out, r)
+        np.testing.assert_allclose(a["max_load"], c["max_load"], rtol=1e-12)
+        assert a["n_island"] == c["n_island"]
+
+
+def test_disconnected_candidate_flagged():
+    # a split that moves every branch but one of a degree-3 bus whose kept branch ...
+    f = np.array([0, 1, 1, 2])
+    t = np.array([1, 2, 3, 3])
+    b = np.ones(4)
+    # split bus 0 (degree 1 is not splittable) -> use outage of bridge 0-1 instead
+    sc = O.score_candidate(4, f, t, b, 0, [(G.KIND_OUTAGE, 0, 0, 0.0)],
+                           np.zeros((2, 4)), [1, 2], [1, 2], np.ones(2))
+    assert sc["status"] & O.ST_DISCONNECTED
+    assert np.all(np.isinf(sc["max_load"]))
+
+
+# ------------------------------------------------ the paper's own formulas
+
+def test_paper_lodf_definition_matches_rebuild():
+    g = G.make_grid(20, 32, 11)
+    h = O.ptdf(g.n_bus, g.f, g.t, g.b, g.slack)
+    lodf = PF.lodf_matrix(h, g.f, g.t)
+    cf = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, [], g.p, np.arange(g.n_branch))
+    ok = cf["state"] == 0
+    np.testing.assert_allclose(lodf[:, ok], cf["lodf"][:, ok], atol=1e-11)
+
+
+def test_paper_modf_equals_sequential_lodf_and_rebuild():
+    g = G.make_grid(20, 32, 12)
+    h = O.ptdf(g.n_bus, g.f, g.t, g.b, g.slack)
+    rng = np.random.default_rng(0)
+    done = 0
+    for _ in range(50):
+        outs = rng.choice(g.n_branch, size=int(rng.integers(1, 5)), replace=False)
+        al = np.ones(g.n_branch, bool)
+        al[outs] = False
+        if not O.connected(g.n_bus, g.f[al], g.t[al]):
+            continue
+        ref = O.ptdf(g.n_bus, g.f[al], g.t[al], g.b[al], g.slack)
+        hm = PF.ptdf_after_modf(h, g.f, g.t, outs)
+        hs = h
+        for o in outs:
+            hs = PF.ptdf_after_outage(hs, g.f, g.t, o)
+        np.testing.assert_allclose(hm[al], ref, atol=1e-11)
+        np.testing.assert_allclose(hs[al], ref, atol=1e-11)
+        np.testing.assert_allclose(hm[~al], 0.0, atol=1e-11)   # row fix: no flow on outages
+        done += 1
+    assert done > 10
+
+
+def test_paper_bsdf_matches_rebuild_including_slack_split():
+    g = G.make_grid(16, 27, 3)
+    h = O.ptdf(g.n_bus, g.f, g.t, g.b, g.slack)
+    rng = np.random.default_rng(1)
+    checked = set()
+    for a in np.flatnonzero(g.degree() >= 3):
+        inc = g.incident(int(a))
+        for _ in range(3):
+            el = G.random_split(g, rng, int(a))
+            n2, f2, t2, al, _ = O.rebuild(g.n_bus, g.f, g.t, [el])
+            if not O.connected(n2, f2, t2):
+                continue
+            moved = [int(inc[i]) for i in range(len(inc)) if (el[2] >> i) & 1]
+            hp = PF.bsdf_split(h, g.f, g.t, g.b, int(a), moved, g.slack)
+            np.testing.assert_allclose(hp, O.ptdf(n2, f2, t2, g.b, g.slack), atol=1e-11)
+            checked.add(int(a))
+    assert g.slack in checked
+
+
+def test_repeated_bsdf_equals_joint_rebuild():
+    # Eq. bsdf_application applied split after split equals the rebuilt grid
+    g = G.make_grid(18, 30, 5)
+    rng = np.random.default_rng(2)
+    h0 = O.ptdf(g.n_bus, g.f, g.t, g.b, g.slack)
+    n_ok = 0
+    for _ in range(20):
+        els = G.sample_candidate(g, rng, 2, 0)
+        h = h0
+        f2, t2 = g.f.copy(), g.t.copy()
+        for (kind, a, m, _p) in els:
+            inc = g.incident(a)
+            moved = [int(inc[i]) for i in range(len(inc)) if (m >> i) & 1]
+            # split on the current topology (the second split sees the first)
+            h = PF.bsdf_split(h, f2, t2, g.b, a, moved, g.slack)
+            newbus = h.shape[1] - 1
+            for br in moved:
+                if f2[br] == a:
+                    f2[br] = newbus
+                else:
+                    t2[br] = newbus
+        n2, rf, rt, _, _ = O.rebuild(g.n_bus, g.f, g.t, els)
+        np.testing.assert_allclose(h, O.ptdf(n2, rf, rt, g.b, g.slack), atol=1e-10)
+        n_ok += 1
+    assert n_ok == 20
+
+
+def test_fig1_packing_counts_fixture():
+    import json
+    import os
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fig1_packing.json")))
+    ks = [len(c) for c in fx["candidates"]]
+    assert sum(ks) == fx["naive_applications"]
+    assert max(ks) * len(ks) == fx["padded_simd_applications"]
+    # shared-prefix tree: distinct prefixes of the sorted split lists
+    prefixes = {tuple(sorted(c)[:i + 1]) for c in fx["candidates"] for i in range(len(c))}
+    assert len(prefixes) == fx["tree_applications"]
