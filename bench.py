@@ -1,0 +1,189 @@
+"""Benchmark of the batched DC-loadflow screen on one MI355X.
+
+One step = the whole hot path over one batch of the medium workload
+(1,000-bus / 1,600-branch synthetic grid, 4,096 topology candidates with 1-3
+bus splits plus 0-2 outages, 16 load-perturbed injection variants each, N-1
+over 500 contingency branches that are also the monitored set):
+dcflow_eval_topologies -> dcflow_eval_injections -> dcflow_n1_score, with the
+candidate records and injections already resident in device memory.
+
+value = N-1 loadflows per second of the mixed path (FP32 MFMA GEMM and FP32
+N-1 scan, FP64 k x k solves / LODF denominators / LODF' tile build);
+loadflows = candidates x variants x contingencies per step.  The plain FP64
+path is timed the same way and reported beside it.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "N-1 loadflows/s on 1 MI355X at ≤1e-4 rating error, mixed vs plain FP64 path"
+PEAK_VALU_FMA_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12   # non-packed FMA issue, fp32 and fp64
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_medium_traffic.json")
+
+
+# ------------------------------------------------------------------ CPU baseline
+
+def _oracle_worker(args):
+    from threadpoolctl import threadpool_limits
+    from oracle import dcflow_oracle as O
+    n_bus, f, t, b, slack, elems, x, mon, out, rating = args
+    with threadpool_limits(limits=1):
+        O.score_candidate(n_bus, f, t, b, slack, elems, x, mon, out, rating)
+    return x.shape[0] * len(out)
+
+
+def cpu_baseline(w, n_sample: int):
+    """The oracle (dense LU per candidate) on the first n_sample candidates,
+    process-parallel over candidates, one BLAS thread per process."""
+    import multiprocessing as mp
+    from oracle import dcflow_oracle as O
+    g = w.grid
+    rating = O.ratings(g.n_bus, g.f, g.t, g.b, g.slack, g.p, w.mon, w.rating_scale,
+                       w.rating_offset)
+    cores = max(1, min(16, os.cpu_count() or 1))
+    jobs = [(g.n_bus, g.f, g.t, g.b, g.slack, w.cands.elements(i),
+             w.inj[i] if not w.inj_shared else w.inj, w.mon, w.out, rating)
+            for i in range(n_sample)]
+    ctx = mp.get_context("fork")     # forked before this process touches the GPU
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        lf = sum(pool.map(_oracle_worker, jobs, chunksize=1))
+    dt = time.perf_counter() - t0
+    return dict(value=lf / dt, unit="loadflows/s", cores=cores, kind="oracle",
+                sample=f"first {n_sample} of {w.cands.n_cand} candidates of the same workload "
+                       f"({lf} loadflows, {dt:.1f} s wall)")
+
+
+# ------------------------------------------------------------------ GPU timing
+
+def _source_hash():
+    h = hashlib.sha256()
+    for name in ("score.hip", "dcflow_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2501_17529_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def run_path(D, torch, plan, w, prec, steps, warmup):
+    nv = w.n_var
+    bt = D.Batch(plan, w.cands, nv)
+    x = torch.from_numpy(np.ascontiguousarray(w.inj)).cuda()
+    flows, _ = bt.flow_buffer(nv, prec)
+    out = torch.empty(bt.n_cand * D.SCORE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        bt.eval_topologies()
+        if ev:
+            ev[1].record(stream)
+        bt.eval_injections(x, nv, w.inj_shared, prec, flows=flows)
+        if ev:
+            ev[2].record(stream)
+        bt.n1_score(flows, nv, prec, out=out)
+        if ev:
+            ev[3].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phase = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
+                      for e in evs])   # ms
+    sc = D.Batch.scores_to_numpy(out, bt.n_cand)
+    return dict(wall=wall, phase_ms=phase.mean(axis=0), scores=sc, batch=bt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cands", type=int, default=4096)
+    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--prec", choices=["both", "fp32", "fp64"], default="both")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(candidates would shard across GPUs with no communication; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import gridgen as G
+    w = G.workload_medium(0, n_cand=a.cands)
+    cpu = None if a.no_cpu_baseline else cpu_baseline(w, min(a.cpu_sample, w.cands.n_cand))
+
+    import torch
+    from paper_2501_17529_amd import dcflow as D
+    torch.cuda.init()
+    t0 = time.perf_counter()
+    plan = D.Plan.from_workload(w)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+
+    n_lf = w.cands.n_cand * w.n_var * len(w.out)
+    res = {}
+    for prec in (["fp32", "fp64"] if a.prec == "both" else [a.prec]):
+        res[prec] = run_path(D, torch, plan, w, prec, a.steps, a.warmup)
+    main_prec = "fp32" if "fp32" in res else "fp64"
+    r = res[main_prec]
+    ms = r["wall"] / a.steps * 1e3
+    value = n_lf / (ms / 1e3)
+
+    # roofline of the dominant kernel (the N-1 scan, both passes): 2 flops (one FMA) per N-1
+    # element, (V + 1) variant sweeps (the winner is re-scanned once) over E_m x O per candidate
+    scan_ms = float(r["phase_ms"][2])
+    flops = 2.0 * w.cands.n_cand * (w.n_var + 1) * len(w.mon) * len(w.out)
+    achieved = flops / (scan_ms / 1e3) / 1e12
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tf = json.load(open(TRAFFIC_FILE))
+        if tf.get("source_hash") == _source_hash() and tf.get("prec") == main_prec:
+            traffic = tf.get("bytes_per_launch")
+    line = {
+        "metric": METRIC, "value": value, "unit": "loadflows/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": main_prec, "data": "synthetic",
+        "config": {"workload": "medium-1000bus: 1,000 buses / 1,600 branches, 4,096 candidates "
+                               "(1-3 bus splits + 0-2 outages), 16 injection variants each, "
+                               "N-1 over 500 contingencies = monitored branches",
+                   "n_bus": 1000, "n_branch": 1600, "candidates": w.cands.n_cand,
+                   "variants": w.n_var, "contingencies": len(w.out), "monitored": len(w.mon),
+                   "loadflows_per_step": n_lf, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "kernel": "k_scan (N-1 scan + winner pass)",
+                     "achieved": achieved, "peak": PEAK_VALU_FMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_VALU_FMA_TFLOPS, "traffic": traffic},
+        "phase_ms": {p: {"eval_topologies": float(v["phase_ms"][0]),
+                         "eval_injections": float(v["phase_ms"][1]),
+                         "n1_score": float(v["phase_ms"][2])} for p, v in res.items()},
+        "build_ptdf_s": build_s,
+    }
+    if "fp64" in res and main_prec != "fp64":
+        ms64 = res["fp64"]["wall"] / a.steps * 1e3
+        line["fp64_path"] = {"value": n_lf / (ms64 / 1e3), "ms_per_step": ms64}
+        s32, s64 = res["fp32"]["scores"], res["fp64"]["scores"]
+        line["fp32_vs_fp64_max_load_absdiff"] = float(np.abs(s32["max_load"] - s64["max_load"]).max())
+    line["cpu_baseline"] = cpu
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

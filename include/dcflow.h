@@ -1,0 +1,218 @@
+/*
+ * dcflow — batched DC loadflow over grid-topology candidates on one MI355X.
+ *
+ * C ABI of the solver library (libdcflow.so, gfx950).  The operations follow
+ * Westerbeck et al., "Accelerated DC loadflow solver for topology
+ * optimization":
+ *
+ *   dcflow_build_ptdf       Sec. II, Def. of the PTDF (PTDF' B' = C_w', slack
+ *                           column zero) restricted to the rows the screen
+ *                           needs, plus base flows (Eq. ptdf_times_nodal_inj).
+ *   dcflow_eval_topologies  Sec. III-C branch module: per candidate, the PTDF
+ *                           corrections for bus splits (Def. eq_bsdf,
+ *                           Eq. bsdf_application) and remedial outages
+ *                           (Def. eq_modf), joined into one k x k solve, and
+ *                           the LODF denominators of every contingency in the
+ *                           changed grid (Def. eq_lodf).
+ *   dcflow_eval_injections  Sec. III-C injection module step 8a: post-change
+ *                           N-0 flows F' = PTDF' P for every injection
+ *                           variant (Eq. ptdf_times_nodal_inj).
+ *   dcflow_n1_score         Steps 8b and 8e: N-1 flows p0 + LODF[:,c] p0[c]
+ *                           (Eq. lodf_delta) reduced to agg_m (maximum
+ *                           relative load), t_i* = argmin over the variants,
+ *                           then (metric-first, Sec. IV-B) the winner's
+ *                           overload sum and worst (branch, contingency).
+ *   Together: Eq. solver_end_to_end, (t_b, t_d, T_i) -> (agg_m, agg_i, t_i*).
+ *
+ * Conventions
+ *   - Memory: the caller allocates every device buffer (sizes come from the
+ *     *_bytes queries); the library never allocates or frees device memory.
+ *     Host structs hold host pointers that are read during the call only.
+ *   - Asynchrony: every call validates its arguments on the host and returns a
+ *     negative dcflow_status on error without launching anything; otherwise it
+ *     enqueues work on `stream` and returns DCFLOW_OK.  Device faults show up
+ *     as DCFLOW_E_HIP from a later call (or from the caller's own sync).
+ *   - Per-candidate problems (islanded candidate, singular correction, non-
+ *     finite values) are status bits in the result, never errors.
+ *   - Threading: a plan and its batches must not be used from two host
+ *     threads at once; separate plans are independent.  No global state.
+ *   - Indices are 0-based.  Node n_bus + j is the new busbar of the j-th split
+ *     of a candidate (element order).
+ */
+#ifndef DCFLOW_H
+#define DCFLOW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DCFLOW_OK = 0,
+  DCFLOW_E_ARG = -1,          /* null pointer, negative size, bad enum        */
+  DCFLOW_E_SHAPE = -2,        /* index out of range, duplicate id, size cap   */
+  DCFLOW_E_DISCONNECTED = -3, /* base grid is not connected                   */
+  DCFLOW_E_WORKSPACE = -4,    /* caller buffer smaller than the query said    */
+  DCFLOW_E_HIP = -5,          /* a HIP runtime call failed                    */
+  DCFLOW_E_CAND = -6          /* malformed candidate record (see bad_index)   */
+} dcflow_status;
+
+typedef enum {
+  DCFLOW_FP64 = 0,  /* every step in FP64 (plain path)                         */
+  DCFLOW_FP32 = 1   /* injection GEMM on FP32 MFMA, N-1 scan in FP32; the k x k
+                       solve, LODF denominators and LODF' tile build in FP64    */
+} dcflow_prec;
+
+/* Candidate element kinds. */
+#define DCFLOW_OUTAGE 0 /* remedial disconnection of branch `id` (t_d)          */
+#define DCFLOW_SPLIT 1  /* two-way split of bus `id` (t_b)                      */
+
+#define DCFLOW_MAX_RANK 8       /* elements per candidate                       */
+#define DCFLOW_MAX_SPLIT_DEG 32 /* incident branches of a splittable bus        */
+
+/* Status bits of dcflow_score.status. */
+#define DCFLOW_ST_DISCONNECTED 0x1u /* candidate grid islanded: max_load=+inf  */
+#define DCFLOW_ST_SINGULAR 0x2u     /* k x k correction singular (implies 0x1) */
+#define DCFLOW_ST_NONFINITE 0x4u    /* NaN/Inf met in the injections or flows  */
+#define DCFLOW_ST_ISLAND_SHIFT 8    /* bits 8..31: number of islanding N-1 cases */
+
+/* Grid description (host pointers, read during dcflow_build_ptdf only). */
+typedef struct {
+  int32_t n_bus;      /* >= 2                                                   */
+  int32_t n_branch;   /* >= 1                                                   */
+  int32_t slack;      /* slack bus, 0 <= slack < n_bus                          */
+  const int32_t *from;/* [n_branch] from bus                                    */
+  const int32_t *to;  /* [n_branch] to bus, != from                             */
+  const double *b;    /* [n_branch] susceptance 1/x, finite and > 0             */
+  int32_t n_mon;      /* monitored branches E_m (>= 1)                          */
+  const int32_t *mon; /* [n_mon] distinct branch ids                            */
+  int32_t n_out;      /* N-1 contingencies O (>= 0)                             */
+  const int32_t *out; /* [n_out] distinct branch ids                            */
+  const double *p_base;   /* [n_bus] base injections (base flows, rating rule)  */
+  const double *rating;   /* [n_mon] > 0, or NULL: rating_scale*|F_base| + rating_offset */
+  double rating_scale;
+  double rating_offset;
+} dcflow_grid_desc;
+
+/* Topology candidates in CSR form (host pointers).  Candidate i owns
+ * elements off[i] .. off[i+1]-1 (0 to DCFLOW_MAX_RANK of them; 0 = the
+ * unchanged grid).  For a split, bit q of mask moves the q-th incident branch
+ * of the bus (incident branches in ascending branch id) to the new busbar;
+ * at least one bit set, not every incident branch moved, at most one split
+ * per bus per candidate.  Outage ids are distinct within a candidate.
+ * p_new (may be NULL = all zero) is the injection that moves with a split's
+ * new busbar; the injection left on busbar A is the variant's value minus it. */
+typedef struct {
+  int32_t n_cand;
+  const int32_t *off;     /* [n_cand + 1], off[0] = 0, non-decreasing           */
+  const int8_t *kind;     /* [n_elem] DCFLOW_OUTAGE or DCFLOW_SPLIT             */
+  const int32_t *id;      /* [n_elem] branch id (outage) or bus id (split)      */
+  const uint32_t *mask;   /* [n_elem] split mask (ignored for outages)          */
+  const double *p_new;    /* [n_elem] or NULL                                   */
+} dcflow_cands;
+
+/* Result of one candidate (device array of n_cand, written by dcflow_n1_score). */
+typedef struct {
+  double max_load;       /* agg_m at t_i*: max over N-0 and valid N-1 of |p|/r  */
+  double overload_sum;   /* sum of max(0, |p|/r - 1) over the same set at t_i*  */
+  int32_t best_variant;  /* t_i* (lowest index on ties); -1 if disconnected     */
+  int32_t worst_branch;  /* monitored branch id of the maximum                  */
+  int32_t worst_outage;  /* contingency branch id of the maximum, -1 for N-0    */
+  uint32_t status;       /* DCFLOW_ST_* bits, island count in bits 8..31       */
+} dcflow_score;
+
+/* Device pointers into the plan workspace, for inspection and tests.  All
+ * matrices are row-major with the given leading dimensions (elements). */
+typedef struct {
+  int32_t n_bus, n_branch, n_mon, n_out, n_er; /* n_er = |E_m u O| rows kept   */
+  int32_t ld_h;      /* leading dim of ptdf (>= n_bus)                          */
+  int32_t ld_o;      /* leading dim of hdo  (>= n_out)                          */
+  const double *ptdf;    /* [n_branch][ld_h] full PTDF, slack column 0         */
+  const double *hdo;     /* [n_branch][ld_o] PTDF[:, f_c] - PTDF[:, t_c], c in O */
+  const double *f_base;  /* [n_branch] base flows PTDF p_base                   */
+  const double *rating;  /* [n_mon] ratings used by the score                   */
+  const int32_t *er;     /* [n_er] kept rows: E_m first, then O \ E_m          */
+} dcflow_plan_view;
+
+typedef struct dcflow_plan dcflow_plan;
+typedef struct dcflow_batch dcflow_batch;
+
+/* Bytes of device workspace that dcflow_build_ptdf needs for this grid. */
+int dcflow_plan_workspace_bytes(const dcflow_grid_desc *grid, size_t *bytes);
+
+/* One-time FP64 base build (Def. eq_ptdf with row restriction): reduced
+ * nodal susceptance matrix, its inverse (Gauss-Jordan, SPD), the full PTDF,
+ * node-major rows E_r, the contingency transfer columns PTDF[:,f_c]-PTDF[:,t_c],
+ * base flows and ratings.  `dev_ws` (>= dcflow_plan_workspace_bytes, 256-byte
+ * aligned) must stay allocated until dcflow_plan_destroy.  Returns
+ * DCFLOW_E_DISCONNECTED if the base grid is not connected.  The plan (host
+ * object) is owned by the caller and freed by dcflow_plan_destroy. */
+int dcflow_build_ptdf(const dcflow_grid_desc *grid, void *dev_ws, size_t ws_bytes,
+                      hipStream_t stream, dcflow_plan **plan_out);
+
+int dcflow_plan_view_get(const dcflow_plan *plan, dcflow_plan_view *view);
+void dcflow_plan_destroy(dcflow_plan *plan);
+
+/* Host-only validation of candidate records against a grid; touches no GPU.
+ * On DCFLOW_E_CAND, *bad_index (if non-NULL) is the offending element index,
+ * or -(candidate index)-1 for a bad offset.  *packed_slots receives the sum of
+ * candidate ranks (elements processed with no padding) and *padded_slots the
+ * slots a depth-padded batch would use (n_cand * max rank). */
+int dcflow_validate_candidates(const dcflow_grid_desc *grid, const dcflow_cands *cands,
+                               int32_t *bad_index, int64_t *packed_slots,
+                               int64_t *padded_slots);
+
+/* Device bytes for a batch of these candidates with up to n_var_max
+ * injection variants per candidate. */
+int dcflow_batch_bytes(const dcflow_plan *plan, const dcflow_cands *cands,
+                       int32_t n_var_max, size_t *bytes);
+
+/* Validate and pack the candidates (uneven ranks, no padding; work queue in
+ * descending rank) and upload them into `dev_buf` (>= dcflow_batch_bytes,
+ * 256-byte aligned, kept until dcflow_batch_destroy). */
+int dcflow_batch_create(dcflow_plan *plan, const dcflow_cands *cands, int32_t n_var_max,
+                        void *dev_buf, size_t bytes, hipStream_t stream,
+                        dcflow_batch **batch_out);
+void dcflow_batch_destroy(dcflow_batch *batch);
+
+/* Branch module (Sec. III-C steps 2-4): for every candidate the joint k x k
+ * correction (bus splits as in Def. eq_bsdf, outages as in Def. eq_modf),
+ * factors U (kept rows x k), K^-1 and W = K^-1 R (k x |O|), and the LODF
+ * denominators of the contingencies in the changed grid; |den| < 1e-9 marks
+ * an islanding contingency. */
+int dcflow_eval_topologies(dcflow_batch *batch, hipStream_t stream);
+
+/* Bytes of the flow buffer for n_var variants: [n_cand][n_var][ld_f] of
+ * double (FP64) or float (FP32). */
+int dcflow_flow_bytes(const dcflow_batch *batch, int32_t n_var, dcflow_prec prec,
+                      size_t *bytes, int32_t *ld_f);
+
+/* Injection module step 8a: post-change N-0 flows on the kept rows,
+ * F'[i][v][r] = (PTDF x_v)[E_r[r]] + U_i K_i^-1 (sigma_i . PTDF x_v - p_new_i).
+ * dev_inj (device, FP64): [n_cand][n_var][n_bus] or, if inj_shared,
+ * [n_var][n_bus]; injections are in base bus numbering (the slack entry is
+ * ignored).  dev_flows: see dcflow_flow_bytes.  Needs eval_topologies first. */
+int dcflow_eval_injections(dcflow_batch *batch, const double *dev_inj, int32_t n_var,
+                           int32_t inj_shared, dcflow_prec prec, void *dev_flows,
+                           size_t flow_bytes, hipStream_t stream);
+
+/* Steps 8b/8e: N-1 flows over the monitored rows and contingencies, per
+ * variant maximum relative load, t_i* = argmin, then the winner's overload
+ * sum and worst case.  dev_out: [n_cand] dcflow_score (device). */
+int dcflow_n1_score(dcflow_batch *batch, const void *dev_flows, int32_t n_var,
+                    dcflow_prec prec, dcflow_score *dev_out, hipStream_t stream);
+
+/* Per-variant maxima of the last n1_score call: device pointer to
+ * [n_cand][n_var_max] double (valid after the stream reaches it). */
+const double *dcflow_batch_variant_max(const dcflow_batch *batch);
+
+const char *dcflow_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DCFLOW_H */

@@ -339,7 +339,8 @@ def score_candidate(n, f, t, b, slack, elems, x, mon, out, rating):
         status |= ST_NONFINITE
     return dict(max_load=maxl, best_variant=best, best_max_load=float(maxl[best]),
                 overload_sum=ov, worst_branch=int(mon[li]), worst_outage=worst_out,
-                n_island=int((state == 2).sum()), status=status, flows=cf)
+                n_island=int((state == 2).sum()), status=status, flows=cf,
+                loads_best=allload, scored_out=out[scored])
 
 
 def score_workload(w, idx=None, rating=None):

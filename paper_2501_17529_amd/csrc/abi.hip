@@ -1,0 +1,500 @@
+// Host side of the C ABI: argument validation, workspace layout, candidate
+// packing (uneven ranks, no padding, descending-rank work order) and the
+// entry points declared in include/dcflow.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+
+#include "dcflow_internal.h"
+
+using namespace dcflow;
+
+namespace {
+
+// Sub-allocator over a caller-provided device buffer (256-byte aligned chunks).
+struct Arena {
+  char *base;
+  size_t used = 0;
+  explicit Arena(void *p) : base(static_cast<char *>(p)) {}
+  template <typename T>
+  T *take(size_t count) {
+    size_t bytes = (std::max<size_t>(count, 1) * sizeof(T) + 255) / 256 * 256;
+    T *p = base ? reinterpret_cast<T *>(base + used) : nullptr;
+    used += bytes;
+    return p;
+  }
+};
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int check_grid(const dcflow_grid_desc *g) {
+  if (!g || !g->from || !g->to || !g->b || !g->mon || !g->p_base) return DCFLOW_E_ARG;
+  if (g->n_bus < 2 || g->n_branch < 1 || g->n_mon < 1 || g->n_out < 0) return DCFLOW_E_SHAPE;
+  if (g->n_out > 0 && !g->out) return DCFLOW_E_ARG;
+  if (g->slack < 0 || g->slack >= g->n_bus) return DCFLOW_E_SHAPE;
+  for (int l = 0; l < g->n_branch; ++l) {
+    if (g->from[l] < 0 || g->from[l] >= g->n_bus || g->to[l] < 0 || g->to[l] >= g->n_bus ||
+        g->from[l] == g->to[l])
+      return DCFLOW_E_SHAPE;
+    if (!finite_pos(g->b[l])) return DCFLOW_E_ARG;
+  }
+  std::vector<uint8_t> seen(g->n_branch, 0);
+  for (int i = 0; i < g->n_mon; ++i) {
+    int l = g->mon[i];
+    if (l < 0 || l >= g->n_branch || seen[l]) return DCFLOW_E_SHAPE;
+    seen[l] = 1;
+  }
+  std::fill(seen.begin(), seen.end(), 0);
+  for (int i = 0; i < g->n_out; ++i) {
+    int l = g->out[i];
+    if (l < 0 || l >= g->n_branch || seen[l]) return DCFLOW_E_SHAPE;
+    seen[l] = 1;
+  }
+  for (int i = 0; i < g->n_bus; ++i)
+    if (!std::isfinite(g->p_base[i])) return DCFLOW_E_ARG;
+  if (g->rating) {
+    for (int i = 0; i < g->n_mon; ++i)
+      if (!finite_pos(g->rating[i])) return DCFLOW_E_ARG;
+  } else if (!std::isfinite(g->rating_scale) || !std::isfinite(g->rating_offset)) {
+    return DCFLOW_E_ARG;
+  }
+  return DCFLOW_OK;
+}
+
+bool grid_connected(const dcflow_grid_desc *g) {
+  std::vector<int> par(g->n_bus);
+  std::iota(par.begin(), par.end(), 0);
+  auto find = [&](int a) {
+    while (par[a] != a) a = par[a] = par[par[a]];
+    return a;
+  };
+  int comps = g->n_bus;
+  for (int l = 0; l < g->n_branch; ++l) {
+    int a = find(g->from[l]), c = find(g->to[l]);
+    if (a != c) {
+      par[a] = c;
+      --comps;
+    }
+  }
+  return comps == 1;
+}
+
+struct Dims {
+  int n, m, n_mon, n_out, n_er, ld_h, ld_er, ld_o, mon_pad;
+};
+
+Dims grid_dims(const dcflow_grid_desc *g) {
+  Dims d;
+  d.n = g->n_bus;
+  d.m = g->n_branch;
+  d.n_mon = g->n_mon;
+  d.n_out = g->n_out;
+  std::vector<uint8_t> inmon(d.m, 0);
+  for (int i = 0; i < g->n_mon; ++i) inmon[g->mon[i]] = 1;
+  int extra = 0;
+  for (int i = 0; i < g->n_out; ++i) extra += inmon[g->out[i]] ? 0 : 1;
+  d.n_er = d.n_mon + extra;
+  d.ld_h = round_up(d.n, 16);
+  d.ld_er = round_up(d.n_er, 128);
+  d.ld_o = std::max(64, round_up(d.n_out, 64));
+  d.mon_pad = round_up(d.n_mon, 64);
+  return d;
+}
+
+// Places every plan array in the arena (base may be null: size query).
+void plan_layout(dcflow_plan *p, const Dims &d, Arena &a) {
+  p->d_f = a.take<int32_t>(d.m);
+  p->d_t = a.take<int32_t>(d.m);
+  p->d_b = a.take<double>(d.m);
+  p->d_adj_off = a.take<int32_t>(d.n + 1);
+  p->d_adj_br = a.take<int32_t>(2 * (size_t)d.m);
+  p->d_mon = a.take<int32_t>(d.n_mon);
+  p->d_out = a.take<int32_t>(d.n_out);
+  p->d_er = a.take<int32_t>(d.n_er);
+  p->d_pos_of_br = a.take<int32_t>(d.m);
+  p->d_out_pos = a.take<int32_t>(d.n_out);
+  p->d_out_f = a.take<int32_t>(d.n_out);
+  p->d_out_t = a.take<int32_t>(d.n_out);
+  p->d_binv = a.take<double>((size_t)d.ld_h * d.ld_h);
+  p->d_piv = a.take<double>(4 * (size_t)d.ld_h);
+  p->d_hb = a.take<double>((size_t)d.m * d.ld_h);
+  p->d_ht = a.take<double>((size_t)d.n * d.ld_er);
+  p->d_he64 = a.take<double>((size_t)d.ld_er * d.ld_h);
+  p->d_he32 = a.take<float>((size_t)d.ld_er * d.ld_h);
+  p->d_hdo = a.take<double>((size_t)d.m * d.ld_o);
+  p->d_lsd = a.take<double>((size_t)d.mon_pad * d.ld_o);
+  p->d_fbase = a.take<double>(d.m);
+  p->d_pbase = a.take<double>(d.ld_h);
+  p->d_rating = a.take<double>(d.mon_pad);
+  p->d_inv_r = a.take<double>(d.mon_pad);
+}
+
+struct BatchDims {
+  int n_cand, n_elem, vmax;
+};
+
+void batch_layout(dcflow_batch *b, const dcflow_plan *p, const BatchDims &d, Arena &a) {
+  const size_t ne = std::max(d.n_elem, 1), nc = std::max(d.n_cand, 1);
+  b->d_off = a.take<int32_t>(nc + 1);
+  b->d_kind = a.take<int32_t>(ne);
+  b->d_id = a.take<int32_t>(ne);
+  b->d_order = a.take<int32_t>(nc);
+  b->d_mask = a.take<uint32_t>(ne);
+  b->d_pnew = a.take<double>(ne);
+  b->d_nsig = a.take<int32_t>(ne);
+  b->d_sig = a.take<int32_t>(ne * kMaxSig);
+  b->d_U = a.take<double>(ne * p->ld_er);
+  b->d_W = a.take<double>(ne * p->ld_o);
+  b->d_kinv = a.take<double>(nc * 64);
+  b->d_invden = a.take<double>(nc * p->ld_o);
+  b->d_isl = a.take<uint32_t>(nc * (p->ld_o / 32));
+  b->d_status = a.take<uint32_t>(nc);
+  b->d_z = a.take<double>(ne * d.vmax);
+  b->d_vmax = a.take<double>(nc * d.vmax);
+  b->d_f0 = a.take<double>((size_t)d.vmax * p->ld_er);
+}
+
+int check_cands(int n_bus, int n_branch, const std::vector<int32_t> &adj_off,
+                const dcflow_cands *c, int32_t *bad, int64_t *packed, int64_t *padded,
+                int *kmax_out) {
+  if (bad) *bad = 0;
+  if (!c || c->n_cand < 0) return DCFLOW_E_ARG;
+  if (c->n_cand > 0 && !c->off) return DCFLOW_E_ARG;
+  if (c->n_cand == 0) {
+    if (packed) *packed = 0;
+    if (padded) *padded = 0;
+    if (kmax_out) *kmax_out = 0;
+    return DCFLOW_OK;
+  }
+  if (c->off[0] != 0) {
+    if (bad) *bad = -1;
+    return DCFLOW_E_CAND;
+  }
+  int kmax = 0;
+  int64_t tot = 0;
+  for (int i = 0; i < c->n_cand; ++i) {
+    int k = c->off[i + 1] - c->off[i];
+    if (k < 0 || k > kMaxRank) {
+      if (bad) *bad = -i - 1;
+      return DCFLOW_E_CAND;
+    }
+    kmax = std::max(kmax, k);
+    tot += k;
+  }
+  if (tot > 0 && (!c->kind || !c->id || !c->mask)) return DCFLOW_E_ARG;
+  for (int i = 0; i < c->n_cand; ++i) {
+    int a = c->off[i], e = c->off[i + 1];
+    for (int j = a; j < e; ++j) {
+      bool ok = true;
+      if (c->kind[j] == DCFLOW_OUTAGE) {
+        ok = c->id[j] >= 0 && c->id[j] < n_branch;
+      } else if (c->kind[j] == DCFLOW_SPLIT) {
+        ok = c->id[j] >= 0 && c->id[j] < n_bus;
+        if (ok) {
+          int deg = adj_off[c->id[j] + 1] - adj_off[c->id[j]];
+          uint32_t mk = c->mask[j];
+          uint64_t full = deg >= 32 ? 0xffffffffull : ((1ull << deg) - 1);
+          ok = deg >= 2 && deg <= kMaxSig && mk != 0 && (uint64_t)mk <= full && (uint64_t)mk != full;
+        }
+      } else {
+        ok = false;
+      }
+      if (ok && c->p_new && !std::isfinite(c->p_new[j])) ok = false;
+      for (int q = a; ok && q < j; ++q)
+        if (c->kind[q] == c->kind[j] && c->id[q] == c->id[j]) ok = false;  // duplicate
+      if (!ok) {
+        if (bad) *bad = j;
+        return DCFLOW_E_CAND;
+      }
+    }
+  }
+  if (packed) *packed = tot;
+  if (padded) *padded = (int64_t)kmax * c->n_cand;
+  if (kmax_out) *kmax_out = kmax;
+  return DCFLOW_OK;
+}
+
+std::vector<int32_t> host_adj_off(const dcflow_grid_desc *g) {
+  std::vector<int32_t> off(g->n_bus + 1, 0);
+  for (int l = 0; l < g->n_branch; ++l) {
+    off[g->from[l] + 1]++;
+    off[g->to[l] + 1]++;
+  }
+  for (int i = 0; i < g->n_bus; ++i) off[i + 1] += off[i];
+  return off;
+}
+
+#define HIPCHECK(x)                       \
+  do {                                    \
+    if ((x) != hipSuccess) return DCFLOW_E_HIP; \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int dcflow_plan_workspace_bytes(const dcflow_grid_desc *grid, size_t *bytes) {
+  if (!bytes) return DCFLOW_E_ARG;
+  int rc = check_grid(grid);
+  if (rc != DCFLOW_OK) return rc;
+  dcflow_plan tmp;
+  Arena a(nullptr);
+  plan_layout(&tmp, grid_dims(grid), a);
+  *bytes = a.used;
+  return DCFLOW_OK;
+}
+
+int dcflow_build_ptdf(const dcflow_grid_desc *g, void *dev_ws, size_t ws_bytes, hipStream_t s,
+                      dcflow_plan **plan_out) {
+  if (!plan_out || !dev_ws) return DCFLOW_E_ARG;
+  *plan_out = nullptr;
+  int rc = check_grid(g);
+  if (rc != DCFLOW_OK) return rc;
+  if (reinterpret_cast<uintptr_t>(dev_ws) % 256) return DCFLOW_E_ARG;
+  if (!grid_connected(g)) return DCFLOW_E_DISCONNECTED;
+  Dims d = grid_dims(g);
+  dcflow_plan *p = new (std::nothrow) dcflow_plan();
+  if (!p) return DCFLOW_E_ARG;
+  Arena a(dev_ws);
+  plan_layout(p, d, a);
+  if (a.used > ws_bytes) {
+    delete p;
+    return DCFLOW_E_WORKSPACE;
+  }
+  p->n = d.n;
+  p->m = d.m;
+  p->slack = g->slack;
+  p->n_mon = d.n_mon;
+  p->n_out = d.n_out;
+  p->n_er = d.n_er;
+  p->ld_h = d.ld_h;
+  p->ld_er = d.ld_er;
+  p->ld_o = d.ld_o;
+  p->mon_pad = d.mon_pad;
+  p->f.assign(g->from, g->from + d.m);
+  p->t.assign(g->to, g->to + d.m);
+  p->adj_off = host_adj_off(g);
+  p->adj_br.assign(2 * (size_t)d.m, 0);
+  {
+    std::vector<int32_t> fill(p->adj_off.begin(), p->adj_off.end() - 1);
+    for (int l = 0; l < d.m; ++l) {  // ascending branch id per bus
+      p->adj_br[fill[g->from[l]]++] = l;
+      p->adj_br[fill[g->to[l]]++] = l;
+    }
+  }
+  p->out.assign(g->out, g->out + d.n_out);
+  std::vector<int32_t> er(g->mon, g->mon + d.n_mon);
+  p->pos_of_br.assign(d.m, -1);
+  for (int i = 0; i < d.n_mon; ++i) p->pos_of_br[g->mon[i]] = i;
+  std::vector<int32_t> out_pos(std::max(d.n_out, 1), 0), of(std::max(d.n_out, 1), 0),
+      ot(std::max(d.n_out, 1), 0);
+  p->is_out.assign(d.m, 0);
+  for (int c = 0; c < d.n_out; ++c) {
+    int l = g->out[c];
+    p->is_out[l] = 1;
+    if (p->pos_of_br[l] < 0) {
+      p->pos_of_br[l] = (int)er.size();
+      er.push_back(l);
+    }
+    out_pos[c] = p->pos_of_br[l];
+    of[c] = g->from[l];
+    ot[c] = g->to[l];
+  }
+  std::vector<double> pb(d.ld_h, 0.0);
+  std::copy(g->p_base, g->p_base + d.n, pb.begin());
+
+  auto up = [&](void *dst, const void *src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  if (up(p->d_f, g->from, 4 * (size_t)d.m) != hipSuccess ||
+      up(p->d_t, g->to, 4 * (size_t)d.m) != hipSuccess ||
+      up(p->d_b, g->b, 8 * (size_t)d.m) != hipSuccess ||
+      up(p->d_adj_off, p->adj_off.data(), 4 * p->adj_off.size()) != hipSuccess ||
+      up(p->d_adj_br, p->adj_br.data(), 4 * p->adj_br.size()) != hipSuccess ||
+      up(p->d_mon, g->mon, 4 * (size_t)d.n_mon) != hipSuccess ||
+      (d.n_out > 0 && up(p->d_out, g->out, 4 * (size_t)d.n_out) != hipSuccess) ||
+      up(p->d_er, er.data(), 4 * er.size()) != hipSuccess ||
+      up(p->d_pos_of_br, p->pos_of_br.data(), 4 * (size_t)d.m) != hipSuccess ||
+      up(p->d_out_pos, out_pos.data(), 4 * out_pos.size()) != hipSuccess ||
+      up(p->d_out_f, of.data(), 4 * of.size()) != hipSuccess ||
+      up(p->d_out_t, ot.data(), 4 * ot.size()) != hipSuccess ||
+      up(p->d_pbase, pb.data(), 8 * pb.size()) != hipSuccess) {
+    delete p;
+    return DCFLOW_E_HIP;
+  }
+  hipError_t e = launch_build(p, s, g->rating, g->rating_scale, g->rating_offset);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // host staging vectors die here
+  if (e != hipSuccess) {
+    delete p;
+    return DCFLOW_E_HIP;
+  }
+  *plan_out = p;
+  return DCFLOW_OK;
+}
+
+int dcflow_plan_view_get(const dcflow_plan *p, dcflow_plan_view *v) {
+  if (!p || !v) return DCFLOW_E_ARG;
+  v->n_bus = p->n;
+  v->n_branch = p->m;
+  v->n_mon = p->n_mon;
+  v->n_out = p->n_out;
+  v->n_er = p->n_er;
+  v->ld_h = p->ld_h;
+  v->ld_o = p->ld_o;
+  v->ptdf = p->d_hb;
+  v->hdo = p->d_hdo;
+  v->f_base = p->d_fbase;
+  v->rating = p->d_rating;
+  v->er = p->d_er;
+  return DCFLOW_OK;
+}
+
+void dcflow_plan_destroy(dcflow_plan *p) { delete p; }
+
+int dcflow_validate_candidates(const dcflow_grid_desc *g, const dcflow_cands *c,
+                               int32_t *bad_index, int64_t *packed, int64_t *padded) {
+  int rc = check_grid(g);
+  if (rc != DCFLOW_OK) return rc;
+  return check_cands(g->n_bus, g->n_branch, host_adj_off(g), c, bad_index, packed, padded,
+                     nullptr);
+}
+
+int dcflow_batch_bytes(const dcflow_plan *p, const dcflow_cands *c, int32_t n_var_max,
+                       size_t *bytes) {
+  if (!p || !c || !bytes || n_var_max < 1) return DCFLOW_E_ARG;
+  if (c->n_cand < 0 || (c->n_cand > 0 && !c->off)) return DCFLOW_E_ARG;
+  BatchDims d{c->n_cand, c->n_cand ? c->off[c->n_cand] : 0, n_var_max};
+  dcflow_batch tmp;
+  Arena a(nullptr);
+  batch_layout(&tmp, p, d, a);
+  *bytes = a.used;
+  return DCFLOW_OK;
+}
+
+int dcflow_batch_create(dcflow_plan *p, const dcflow_cands *c, int32_t n_var_max, void *dev_buf,
+                        size_t bytes, hipStream_t s, dcflow_batch **out) {
+  if (!p || !c || !out || !dev_buf || n_var_max < 1) return DCFLOW_E_ARG;
+  *out = nullptr;
+  if (reinterpret_cast<uintptr_t>(dev_buf) % 256) return DCFLOW_E_ARG;
+  int32_t bad = 0;
+  int64_t packed = 0, padded = 0;
+  int kmax = 0;
+  int rc = check_cands(p->n, p->m, p->adj_off, c, &bad, &packed, &padded, &kmax);
+  if (rc != DCFLOW_OK) return rc;
+  BatchDims d{c->n_cand, c->n_cand ? c->off[c->n_cand] : 0, n_var_max};
+  dcflow_batch *b = new (std::nothrow) dcflow_batch();
+  if (!b) return DCFLOW_E_ARG;
+  Arena a(dev_buf);
+  batch_layout(b, p, d, a);
+  if (a.used > bytes) {
+    delete b;
+    return DCFLOW_E_WORKSPACE;
+  }
+  b->plan = p;
+  b->n_cand = d.n_cand;
+  b->n_elem = d.n_elem;
+  b->vmax = n_var_max;
+  b->packed = packed;
+  b->padded = padded;
+  b->kmax = kmax;
+  b->factored = 0;
+  b->flows_prec = -1;
+  b->flows_nvar = 0;
+  if (d.n_cand > 0) {
+    // work queue: descending rank, stable
+    std::vector<int32_t> order(d.n_cand);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return (c->off[x + 1] - c->off[x]) > (c->off[y + 1] - c->off[y]);
+    });
+    const size_t ne = std::max(d.n_elem, 1);
+    std::vector<int32_t> kind(ne, 0), id(ne, 0);
+    std::vector<uint32_t> mask(ne, 0);
+    std::vector<double> pn(ne, 0.0);
+    for (int j = 0; j < d.n_elem; ++j) {
+      kind[j] = c->kind[j];
+      id[j] = c->id[j];
+      mask[j] = c->mask[j];
+      pn[j] = c->p_new ? c->p_new[j] : 0.0;
+    }
+    hipError_t e = hipMemcpyAsync(b->d_off, c->off, 4 * (size_t)(d.n_cand + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_order, order.data(), 4 * order.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_kind, kind.data(), 4 * ne, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_id, id.data(), 4 * ne, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_mask, mask.data(), 4 * ne, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_pnew, pn.data(), 8 * ne, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host staging vectors die here
+    if (e != hipSuccess) {
+      delete b;
+      return DCFLOW_E_HIP;
+    }
+  }
+  *out = b;
+  return DCFLOW_OK;
+}
+
+void dcflow_batch_destroy(dcflow_batch *b) { delete b; }
+
+int dcflow_eval_topologies(dcflow_batch *b, hipStream_t s) {
+  if (!b) return DCFLOW_E_ARG;
+  if (launch_factors(b, s) != hipSuccess) return DCFLOW_E_HIP;
+  b->factored = 1;
+  return DCFLOW_OK;
+}
+
+int dcflow_flow_bytes(const dcflow_batch *b, int32_t n_var, dcflow_prec prec, size_t *bytes,
+                      int32_t *ld_f) {
+  if (!b || !bytes || n_var < 1) return DCFLOW_E_ARG;
+  if (prec != DCFLOW_FP64 && prec != DCFLOW_FP32) return DCFLOW_E_ARG;
+  size_t el = prec == DCFLOW_FP64 ? 8 : 4;
+  *bytes = std::max<size_t>((size_t)b->n_cand * n_var * b->plan->ld_er * el, 256);
+  if (ld_f) *ld_f = b->plan->ld_er;
+  return DCFLOW_OK;
+}
+
+int dcflow_eval_injections(dcflow_batch *b, const double *dev_inj, int32_t n_var,
+                           int32_t inj_shared, dcflow_prec prec, void *dev_flows,
+                           size_t flow_bytes, hipStream_t s) {
+  if (!b || !dev_inj || !dev_flows) return DCFLOW_E_ARG;
+  if (n_var < 1 || n_var > b->vmax) return DCFLOW_E_SHAPE;
+  if (prec != DCFLOW_FP64 && prec != DCFLOW_FP32) return DCFLOW_E_ARG;
+  if (!b->factored) return DCFLOW_E_ARG;
+  size_t need = 0;
+  dcflow_flow_bytes(b, n_var, prec, &need, nullptr);
+  if (flow_bytes < need) return DCFLOW_E_WORKSPACE;
+  if (launch_injections(b, dev_inj, n_var, inj_shared ? 1 : 0, prec, dev_flows, s) != hipSuccess)
+    return DCFLOW_E_HIP;
+  b->flows_prec = prec;
+  b->flows_nvar = n_var;
+  return DCFLOW_OK;
+}
+
+int dcflow_n1_score(dcflow_batch *b, const void *dev_flows, int32_t n_var, dcflow_prec prec,
+                    dcflow_score *dev_out, hipStream_t s) {
+  if (!b || !dev_flows || !dev_out) return DCFLOW_E_ARG;
+  if (n_var < 1 || n_var > b->vmax) return DCFLOW_E_SHAPE;
+  if (prec != DCFLOW_FP64 && prec != DCFLOW_FP32) return DCFLOW_E_ARG;
+  if (!b->factored) return DCFLOW_E_ARG;
+  if (b->flows_prec != prec || b->flows_nvar != n_var) return DCFLOW_E_ARG;
+  if (launch_score(b, dev_flows, n_var, prec, dev_out, s) != hipSuccess) return DCFLOW_E_HIP;
+  return DCFLOW_OK;
+}
+
+const double *dcflow_batch_variant_max(const dcflow_batch *b) { return b ? b->d_vmax : nullptr; }
+
+const char *dcflow_strerror(int st) {
+  switch (st) {
+    case DCFLOW_OK: return "ok";
+    case DCFLOW_E_ARG: return "invalid argument";
+    case DCFLOW_E_SHAPE: return "index or size out of range";
+    case DCFLOW_E_DISCONNECTED: return "base grid is not connected";
+    case DCFLOW_E_WORKSPACE: return "device buffer too small";
+    case DCFLOW_E_HIP: return "HIP runtime error";
+    case DCFLOW_E_CAND: return "malformed candidate record";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

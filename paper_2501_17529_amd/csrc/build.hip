@@ -1,0 +1,216 @@
+// One-time FP64 base build (the paper's Sec. II, Def. eq_ptdf with the row
+// restriction that follows it, and Eq. ptdf_times_nodal_inj for base flows).
+//
+//   B'  : slack-reduced nodal susceptance matrix (Laplacian), assembled per bus
+//         from the adjacency lists (no atomics, deterministic);
+//   B'^-1 by in-place Gauss-Jordan (B' is symmetric positive definite for a
+//         connected grid, so no pivoting is needed); the slack row/column are a
+//         unit so the matrix stays n x n;
+//   PTDF rows H[l, x] = b_l (B'^-1[f_l, x] - B'^-1[t_l, x]), slack column 0,
+//         which is PTDF' = C_w' B'^-1 written out per row;
+//   derived operands: node-major kept rows (column gathers of the branch
+//         module), the GEMM operand in FP64/FP32, contingency transfer columns
+//         H[:, f_c] - H[:, t_c], base flows, ratings and the rating-scaled
+//         LODF seed Lsd = (hdo[mon] - [mon == c]) / r used by the N-1 scan.
+#include "dcflow_internal.h"
+
+namespace dcflow {
+namespace {
+
+__global__ void k_fill(double *p, size_t n, double v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_fill_f(float *p, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = 0.f;
+}
+
+// Row i of the reduced Laplacian is written by thread i only.
+__global__ void k_assemble(double *B, int ld, int n, int slack, const int32_t *adj_off,
+                           const int32_t *adj_br, const int32_t *f, const int32_t *t,
+                           const double *b) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double *row = B + (size_t)i * ld;
+  if (i == slack) {
+    row[i] = 1.0;
+    return;
+  }
+  double diag = 0.0;
+  for (int q = adj_off[i]; q < adj_off[i + 1]; ++q) {
+    int br = adj_br[q];
+    int other = f[br] == i ? t[br] : f[br];
+    diag += b[br];
+    if (other != slack) row[other] -= b[br];
+  }
+  row[i] += diag;
+}
+
+// Save pivot row/column 0 before the first Gauss-Jordan step.
+__global__ void k_gj_save0(const double *A, int ld, int n, double *prow, double *pcol) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) {
+    prow[j] = A[j];
+    pcol[j] = A[(size_t)j * ld];
+  }
+}
+
+// One Gauss-Jordan sweep on pivot p (in place), reading the old pivot row and
+// column from (prow, pcol) and saving the new row/column p+1 into (nrow, ncol).
+__global__ void k_gj_step(double *A, int ld, int n, int p, const double *prow,
+                          const double *pcol, double *nrow, double *ncol) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = blockIdx.y;
+  if (j >= n) return;
+  double ip = 1.0 / prow[p];
+  double v;
+  if (i == p) {
+    v = (j == p) ? ip : prow[j] * ip;
+  } else if (j == p) {
+    v = -pcol[i] * ip;
+  } else {
+    v = A[(size_t)i * ld + j] - pcol[i] * (prow[j] * ip);
+  }
+  A[(size_t)i * ld + j] = v;
+  if (i == p + 1) nrow[j] = v;
+  if (j == p + 1) ncol[i] = v;
+}
+
+__global__ void k_ptdf_rows(double *H, int ld, int n, int m, int slack, const double *Binv,
+                            const int32_t *f, const int32_t *t, const double *b) {
+  int x = blockIdx.x * blockDim.x + threadIdx.x;
+  int l = blockIdx.y;
+  if (x >= ld || l >= m) return;
+  double v = 0.0;
+  if (x < n && x != slack)
+    v = b[l] * (Binv[(size_t)f[l] * ld + x] - Binv[(size_t)t[l] * ld + x]);
+  H[(size_t)l * ld + x] = v;
+}
+
+// Ht[x][pos] = H[er[pos]][x] via 32 x 32 LDS tiles (coalesced on both sides).
+__global__ void k_rows_transpose(double *Ht, int ld_er, const double *H, int ld_h, int n,
+                                 const int32_t *er, int n_er) {
+  __shared__ double tile[32][33];
+  int x0 = blockIdx.x * 32, p0 = blockIdx.y * 32;
+  int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    int pos = p0 + r, x = x0 + tx;
+    double v = 0.0;
+    if (pos < n_er && x < n) v = H[(size_t)er[pos] * ld_h + x];
+    tile[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    int x = x0 + r, pos = p0 + tx;
+    if (x < n && pos < ld_er) Ht[(size_t)x * ld_er + pos] = tile[tx][r];
+  }
+}
+
+__global__ void k_copy_he(double *He, float *He32, int ld_h, const double *H, const int32_t *er,
+                          int n_er, int ld_er) {
+  int x = blockIdx.x * blockDim.x + threadIdx.x;
+  int pos = blockIdx.y;
+  if (x >= ld_h || pos >= ld_er) return;
+  double v = pos < n_er ? H[(size_t)er[pos] * ld_h + x] : 0.0;
+  He[(size_t)pos * ld_h + x] = v;
+  He32[(size_t)pos * ld_h + x] = (float)v;
+}
+
+__global__ void k_hdo(double *hdo, int ld_o, const double *H, int ld_h, int m,
+                      const int32_t *of, const int32_t *ot, int n_out) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  int l = blockIdx.y;
+  if (c >= ld_o || l >= m) return;
+  double v = 0.0;
+  if (c < n_out) v = H[(size_t)l * ld_h + of[c]] - H[(size_t)l * ld_h + ot[c]];
+  hdo[(size_t)l * ld_o + c] = v;
+}
+
+// One wave per branch: F_base[l] = H[l, :] . p_base.
+__global__ void k_fbase(double *fb, const double *H, int ld_h, const double *p, int m) {
+  int l = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  int lane = threadIdx.x % kWave;
+  if (l >= m) return;
+  double s = 0.0;
+  for (int x = lane; x < ld_h; x += kWave) s += H[(size_t)l * ld_h + x] * p[x];
+  s = wave_sum(s);
+  if (lane == 0) fb[l] = s;
+}
+
+__global__ void k_rating(double *r, double *inv_r, int mon_pad, const int32_t *mon, int n_mon,
+                         const double *fb, int use_given, double scale, double offset) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= mon_pad) return;
+  if (i < n_mon) {
+    double v = use_given ? r[i] : scale * fabs(fb[mon[i]]) + offset;
+    r[i] = v;
+    inv_r[i] = 1.0 / v;
+  } else {
+    r[i] = 1.0;
+    inv_r[i] = 0.0;
+  }
+}
+
+__global__ void k_lsd(double *lsd, int ld_o, const double *hdo, const int32_t *mon, int n_mon,
+                      const int32_t *out, int n_out, const double *inv_r, int mon_pad) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = blockIdx.y;
+  if (c >= ld_o || i >= mon_pad) return;
+  double v = 0.0;
+  if (i < n_mon && c < n_out) {
+    int l = mon[i];
+    v = (hdo[(size_t)l * ld_o + c] - (l == out[c] ? 1.0 : 0.0)) * inv_r[i];
+  }
+  lsd[(size_t)i * ld_o + c] = v;
+}
+
+inline unsigned nblk(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_build(dcflow_plan *p, hipStream_t s, const double *h_rating, double rscale,
+                        double roffset) {
+  const int n = p->n, m = p->m, ld = p->ld_h;
+  // reduced Laplacian and its inverse
+  hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, p->d_binv, (size_t)ld * ld, 0.0);
+  hipLaunchKernelGGL(k_assemble, dim3(nblk(n, 256)), dim3(256), 0, s, p->d_binv, ld, n, p->slack,
+                     p->d_adj_off, p->d_adj_br, p->d_f, p->d_t, p->d_b);
+  double *pr[2] = {p->d_piv, p->d_piv + 2 * ld};
+  double *pc[2] = {p->d_piv + ld, p->d_piv + 3 * ld};
+  hipLaunchKernelGGL(k_gj_save0, dim3(nblk(n, 256)), dim3(256), 0, s, p->d_binv, ld, n, pr[0],
+                     pc[0]);
+  for (int q = 0; q < n; ++q) {
+    int a = q & 1;
+    hipLaunchKernelGGL(k_gj_step, dim3(nblk(n, 256), n), dim3(256), 0, s, p->d_binv, ld, n, q,
+                       pr[a], pc[a], pr[a ^ 1], pc[a ^ 1]);
+  }
+  // PTDF and derived operands
+  hipLaunchKernelGGL(k_ptdf_rows, dim3(nblk(ld, 256), m), dim3(256), 0, s, p->d_hb, ld, n, m,
+                     p->slack, p->d_binv, p->d_f, p->d_t, p->d_b);
+  hipLaunchKernelGGL(k_rows_transpose, dim3(nblk(n, 32), nblk(p->ld_er, 32)), dim3(32, 8), 0, s,
+                     p->d_ht, p->ld_er, p->d_hb, ld, n, p->d_er, p->n_er);
+  hipLaunchKernelGGL(k_copy_he, dim3(nblk(ld, 256), p->ld_er), dim3(256), 0, s, p->d_he64,
+                     p->d_he32, ld, p->d_hb, p->d_er, p->n_er, p->ld_er);
+  hipLaunchKernelGGL(k_hdo, dim3(nblk(p->ld_o, 256), m), dim3(256), 0, s, p->d_hdo, p->ld_o,
+                     p->d_hb, ld, m, p->d_out_f, p->d_out_t, p->n_out);
+  hipLaunchKernelGGL(k_fbase, dim3(nblk(m, 4)), dim3(256), 0, s, p->d_fbase, p->d_hb, ld,
+                     p->d_pbase, m);
+  if (h_rating) {
+    hipError_t e = hipMemcpyAsync(p->d_rating, h_rating, sizeof(double) * p->n_mon,
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_rating, dim3(nblk(p->mon_pad, 256)), dim3(256), 0, s, p->d_rating,
+                     p->d_inv_r, p->mon_pad, p->d_mon, p->n_mon, p->d_fbase, h_rating ? 1 : 0,
+                     rscale, roffset);
+  hipLaunchKernelGGL(k_lsd, dim3(nblk(p->ld_o, 256), p->mon_pad), dim3(256), 0, s, p->d_lsd,
+                     p->ld_o, p->d_hdo, p->d_mon, p->n_mon, p->d_out, p->n_out, p->d_inv_r,
+                     p->mon_pad);
+  return hipGetLastError();
+}
+
+}  // namespace dcflow

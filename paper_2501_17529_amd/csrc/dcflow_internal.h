@@ -1,0 +1,110 @@
+// Internal layout of the plan and batch objects, launch parameters and the
+// small device helpers shared by the dcflow kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/dcflow.h"
+
+namespace dcflow {
+
+constexpr int kMaxRank = DCFLOW_MAX_RANK;
+constexpr int kMaxSig = DCFLOW_MAX_SPLIT_DEG;  // sensing branches per element
+constexpr int kWave = 64;
+constexpr double kIslandTol = 1e-9;   // |LODF denominator| below this: islanding
+constexpr double kSingularTol = 1e-10; // relative pivot threshold of the k x k solve
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+}  // namespace dcflow
+
+// Host-side plan: shapes, index maps and device pointers into the caller's
+// workspace.  All device matrices are row-major.
+struct dcflow_plan {
+  int n, m, slack, n_mon, n_out, n_er;
+  int ld_h;    // columns of Hb / Binv / He (n rounded up to 16, the GEMM K step)
+  int ld_er;   // rows kept, rounded up to the GEMM M tile (128); U, F, Ht stride
+  int ld_o;    // contingency columns rounded up to 64 (>= 64)
+  int mon_pad; // monitored rows rounded up to 64
+  // device arrays (all inside the workspace)
+  int32_t *d_f, *d_t, *d_adj_off, *d_adj_br;
+  double *d_b;
+  int32_t *d_mon, *d_out, *d_er, *d_pos_of_br, *d_out_pos, *d_out_f, *d_out_t;
+  double *d_binv;   // [ld_h][ld_h] inverse of the slack-reduced Laplacian (slack row/col: unit)
+  double *d_piv;    // [2][ld_h] pivot row/column scratch of the inversion
+  double *d_hb;     // [m][ld_h] PTDF, all branches
+  double *d_ht;     // [n][ld_er] PTDF transposed, kept rows only (node-major)
+  double *d_he64;   // [ld_er][ld_h] kept rows of the PTDF, GEMM operand
+  float *d_he32;    // [ld_er][ld_h] same in FP32
+  double *d_hdo;    // [m][ld_o] PTDF[:, f_c] - PTDF[:, t_c]
+  double *d_lsd;    // [mon_pad][ld_o] (hdo[mon] - [mon == out]) / rating
+  double *d_fbase;  // [m]
+  double *d_pbase;  // [ld_h]
+  double *d_rating; // [mon_pad]
+  double *d_inv_r;  // [mon_pad]
+  // host copies used for validation and packing
+  std::vector<int32_t> f, t, adj_off, adj_br, out, pos_of_br;
+  std::vector<uint8_t> is_out;  // per branch: contingency?
+};
+
+struct dcflow_batch {
+  dcflow_plan *plan;
+  int n_cand, n_elem, vmax;
+  int64_t packed, padded;
+  int kmax;
+  int32_t *d_off, *d_kind, *d_id, *d_order;
+  uint32_t *d_mask;
+  double *d_pnew;
+  int32_t *d_nsig;  // [n_elem]
+  int32_t *d_sig;   // [n_elem][kMaxSig] signed (branch + 1)
+  double *d_U;      // [n_elem][ld_er]
+  double *d_W;      // [n_elem][ld_o]
+  double *d_kinv;   // [n_cand][64]
+  double *d_invden; // [n_cand][ld_o]
+  uint32_t *d_isl;  // [n_cand][ld_o / 32] islanding contingency bits
+  uint32_t *d_status; // [n_cand]
+  double *d_z;      // [n_elem][vmax]
+  double *d_vmax;   // [n_cand][vmax]
+  double *d_f0;     // [vmax][ld_er] shared-injection GEMM output
+  int factored;     // eval_topologies enqueued
+  int flows_prec;   // precision of the last eval_injections (-1 none)
+  int flows_nvar;
+};
+
+namespace dcflow {
+
+// ------------------------------------------------------------ kernels
+// build (a1)
+hipError_t launch_build(dcflow_plan *p, hipStream_t s, const double *h_rating,
+                        double rscale, double roffset);
+// factors (a3)
+hipError_t launch_factors(dcflow_batch *b, hipStream_t s);
+// injections (a4)
+hipError_t launch_injections(dcflow_batch *b, const double *inj, int nvar, int shared,
+                             int prec, void *flows, hipStream_t s);
+// score (a5)
+hipError_t launch_score(dcflow_batch *b, const void *flows, int nvar, int prec,
+                        dcflow_score *out, hipStream_t s);
+
+// ------------------------------------------------------ device helpers
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = v > __shfl_xor(v, o) ? v : __shfl_xor(v, o);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+}  // namespace dcflow

@@ -1,0 +1,278 @@
+// Branch module: per-candidate low-rank factors (paper Sec. III-C steps 2-4).
+//
+// The paper applies each bus split by a BSDF update (Def. eq_bsdf,
+// Eq. bsdf_application), remedial outages by a MODF update (Def. eq_modf) and
+// then forms the LODF of the changed grid (Def. eq_lodf).  Here all k <= 8
+// changes of a candidate are joined into one k x k system (the same updates,
+// solved together instead of in sequence), and the changed PTDF is never
+// materialised:
+//
+//   element j  injection pattern a_j, flow correction c_j, sensing row sigma_j
+//     outage o       a = e_f - e_t,            c = e_o,        sigma = e_o
+//     split of A     a = e_A - sum_M w_l e_far(l),  c = sum_M s_l w_l e_l,
+//     moving M to B  sigma = sum_M s_l e_l,    w_l = b_l / sum_M b,
+//                    s_l = +1 if the branch leaves A, -1 if it enters A
+//                    (branches of M that are also outaged are left out)
+//   u_j = H a_j - c_j,  K = -[sigma_i . u_j],  PTDF' x = H x + U K^-1 (sigma . H x - pi . x)
+//   with pi_j . x the injection on the new busbar of split j.  The constraints
+//   are zero flow on outaged branches and Kirchhoff's law on each new busbar;
+//   K is singular exactly when the candidate grid is islanded.
+//
+//   For a contingency c (post-change terminals) the LODF column of the changed
+//   grid is col_c = H_O[:, c] + U W[:, c], W = K^-1 R,
+//   R[i, c] = sigma_i . H_O[:, c] - pi_i . d_c, den_c = 1 - col_c[c].
+//
+// Outputs per candidate (element-major, no padding between uneven ranks):
+//   U [elem][ld_er], W [elem][ld_o], K^-1 (8 x 8), 1/den_c (0 for islanding
+//   or already-removed contingencies), islanding bits, status, sensing lists.
+#include "dcflow_internal.h"
+
+namespace dcflow {
+namespace {
+
+struct Elem {
+  int kind, id, nsig, na;
+  int sig_br[kMaxSig];
+  double sig_s[kMaxSig];
+  double sig_w[kMaxSig];
+  int a_node[kMaxSig + 1];
+  double a_val[kMaxSig + 1];
+};
+
+__global__ void __launch_bounds__(256)
+k_factors(const int32_t *__restrict__ order, const int32_t *__restrict__ off,
+          const int32_t *__restrict__ kind, const int32_t *__restrict__ id,
+          const uint32_t *__restrict__ mask, const int32_t *__restrict__ f,
+          const int32_t *__restrict__ t, const double *__restrict__ b,
+          const int32_t *__restrict__ adj_off, const int32_t *__restrict__ adj_br,
+          const double *__restrict__ Hb, int ld_h, const double *__restrict__ Ht, int ld_er,
+          int n_er, const double *__restrict__ hdo, int ld_o, const int32_t *__restrict__ out,
+          const int32_t *__restrict__ out_pos, int n_out, const int32_t *__restrict__ pos_of_br,
+          int32_t *__restrict__ nsig_g, int32_t *__restrict__ sig_g, double *__restrict__ U,
+          double *__restrict__ W, double *__restrict__ kinv_g, double *__restrict__ invden,
+          uint32_t *__restrict__ isl, uint32_t *__restrict__ status) {
+  __shared__ Elem E[kMaxRank];
+  __shared__ double K[kMaxRank][2 * kMaxRank];
+  __shared__ double Ki[kMaxRank][kMaxRank];
+  __shared__ int s_flags;
+  __shared__ int s_island;
+
+  const int cand = order[blockIdx.x];
+  const int e0 = off[cand];
+  const int k = off[cand + 1] - e0;
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+  if (tid == 0) {
+    s_flags = 0;
+    s_island = 0;
+  }
+  __syncthreads();
+
+  // ---- decode elements
+  if (tid < k) {
+    Elem &el = E[tid];
+    el.kind = kind[e0 + tid];
+    el.id = id[e0 + tid];
+    if (el.kind == DCFLOW_OUTAGE) {
+      int o = el.id;
+      el.nsig = 1;
+      el.sig_br[0] = o;
+      el.sig_s[0] = 1.0;
+      el.sig_w[0] = 1.0;
+      el.na = 2;
+      el.a_node[0] = f[o];
+      el.a_val[0] = 1.0;
+      el.a_node[1] = t[o];
+      el.a_val[1] = -1.0;
+    } else {
+      int A = el.id;
+      uint32_t mk = mask[e0 + tid];
+      int deg = adj_off[A + 1] - adj_off[A];
+      double beta = 0.0;
+      int ns = 0;
+      for (int q = 0; q < deg; ++q) {
+        if (!((mk >> q) & 1u)) continue;
+        int br = adj_br[adj_off[A] + q];
+        bool removed = false;
+        for (int j = 0; j < k; ++j)
+          if (kind[e0 + j] == DCFLOW_OUTAGE && id[e0 + j] == br) removed = true;
+        if (removed) continue;
+        double s = f[br] == A ? 1.0 : -1.0;
+        el.sig_br[ns] = br;
+        el.sig_s[ns] = s;
+        el.sig_w[ns] = b[br];
+        el.a_node[1 + ns] = s > 0 ? t[br] : f[br];
+        beta += b[br];
+        ++ns;
+      }
+      el.nsig = ns;
+      el.na = ns + 1;
+      el.a_node[0] = A;
+      el.a_val[0] = 1.0;
+      for (int q = 0; q < ns; ++q) {
+        el.sig_w[q] /= beta;
+        el.a_val[1 + q] = -el.sig_w[q];
+      }
+      if (ns == 0) atomicOr(&s_flags, (int)(DCFLOW_ST_DISCONNECTED));
+    }
+    nsig_g[e0 + tid] = el.nsig;
+    for (int q = 0; q < kMaxSig; ++q)
+      sig_g[(size_t)(e0 + tid) * kMaxSig + q] =
+          q < el.nsig ? (el.sig_s[q] > 0 ? el.sig_br[q] + 1 : -(el.sig_br[q] + 1)) : 0;
+  }
+  __syncthreads();
+
+  // ---- K = -G, G_ij = sigma_i . H a_j - sigma_i . c_j   (one wave per entry)
+  for (int p = wv; p < k * k; p += 4) {
+    int i = p / k, j = p % k;
+    const Elem &ei = E[i];
+    const Elem &ej = E[j];
+    int terms = ei.nsig * ej.na;
+    double acc = 0.0;
+    for (int q = lane; q < terms; q += kWave) {
+      int qi = q / ej.na, qj = q % ej.na;
+      acc += ei.sig_s[qi] * ej.a_val[qj] * Hb[(size_t)ei.sig_br[qi] * ld_h + ej.a_node[qj]];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      double sc = 0.0;  // sigma_i . c_j
+      for (int qi = 0; qi < ei.nsig; ++qi)
+        for (int qj = 0; qj < ej.nsig; ++qj)
+          if (ei.sig_br[qi] == ej.sig_br[qj]) sc += ei.sig_s[qi] * ej.sig_s[qj] * ej.sig_w[qj];
+      K[i][j] = -(acc - sc);
+    }
+  }
+  __syncthreads();
+
+  // ---- K^-1 by Gauss-Jordan with partial pivoting (k <= 8, one thread)
+  if (tid == 0) {
+    double scale = 0.0;
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) {
+        scale = fmax(scale, fabs(K[i][j]));
+        K[i][k + j] = i == j ? 1.0 : 0.0;
+      }
+    bool sing = false;
+    for (int c = 0; c < k && !sing; ++c) {
+      int pr = c;
+      for (int r = c + 1; r < k; ++r)
+        if (fabs(K[r][c]) > fabs(K[pr][c])) pr = r;
+      if (!(fabs(K[pr][c]) > kSingularTol * fmax(scale, 1.0))) {
+        sing = true;
+        break;
+      }
+      if (pr != c)
+        for (int q = 0; q < 2 * k; ++q) {
+          double tmp = K[c][q];
+          K[c][q] = K[pr][q];
+          K[pr][q] = tmp;
+        }
+      double ip = 1.0 / K[c][c];
+      for (int q = 0; q < 2 * k; ++q) K[c][q] *= ip;
+      for (int r = 0; r < k; ++r) {
+        if (r == c) continue;
+        double fr = K[r][c];
+        if (fr != 0.0)
+          for (int q = 0; q < 2 * k; ++q) K[r][q] -= fr * K[c][q];
+      }
+    }
+    if (sing) s_flags |= (int)(DCFLOW_ST_DISCONNECTED | DCFLOW_ST_SINGULAR);
+    bool bad = s_flags != 0;
+    for (int i = 0; i < kMaxRank; ++i)
+      for (int j = 0; j < kMaxRank; ++j)
+        Ki[i][j] = (!bad && i < k && j < k) ? K[i][k + j] : 0.0;
+  }
+  __syncthreads();
+  const bool bad = s_flags != 0;
+  if (tid < 64) kinv_g[(size_t)cand * 64 + tid] = Ki[tid / 8][tid % 8];
+
+  // ---- U columns over the kept rows: u_j = H a_j (node-major gathers)
+  for (int j = 0; j < k; ++j) {
+    const Elem &ej = E[j];
+    double *Uj = U + (size_t)(e0 + j) * ld_er;
+    for (int pos = tid; pos < ld_er; pos += blockDim.x) {
+      double u = 0.0;
+      if (pos < n_er && !bad)
+        for (int r = 0; r < ej.na; ++r) u += ej.a_val[r] * Ht[(size_t)ej.a_node[r] * ld_er + pos];
+      Uj[pos] = u;
+    }
+  }
+  __syncthreads();
+  // ... minus c_j on the kept rows (each (j, branch) entry is touched once)
+  if (!bad && tid < k * kMaxSig) {
+    int j = tid / kMaxSig, q = tid % kMaxSig;
+    if (q < E[j].nsig) {
+      int pos = pos_of_br[E[j].sig_br[q]];
+      if (pos >= 0) U[(size_t)(e0 + j) * ld_er + pos] -= E[j].sig_s[q] * E[j].sig_w[q];
+    }
+  }
+  __syncthreads();
+
+  // ---- W = K^-1 R and LODF denominators per contingency
+  int nisl = 0;
+  for (int c = tid; c < ld_o; c += blockDim.x) {
+    double r[kMaxRank];
+    double w[kMaxRank];
+    bool removed = false;
+    if (c < n_out && !bad) {
+      int oc = out[c];
+      for (int i = 0; i < k; ++i) {
+        const Elem &ei = E[i];
+        double acc = 0.0;
+        for (int q = 0; q < ei.nsig; ++q) {
+          int br = ei.sig_br[q];
+          acc += ei.sig_s[q] * (hdo[(size_t)br * ld_o + c] - (br == oc ? 1.0 : 0.0));
+        }
+        r[i] = acc;
+        if (ei.kind == DCFLOW_OUTAGE && ei.id == oc) removed = true;
+      }
+      for (int j = 0; j < k; ++j) {
+        double acc = 0.0;
+        for (int i = 0; i < k; ++i) acc += Ki[j][i] * r[i];
+        w[j] = acc;
+      }
+    } else {
+      for (int j = 0; j < k; ++j) w[j] = 0.0;
+    }
+    for (int j = 0; j < k; ++j) W[(size_t)(e0 + j) * ld_o + c] = w[j];
+    double inv = 0.0;
+    bool island = false;
+    if (c < n_out && !bad && !removed) {
+      int pc = out_pos[c];
+      double col = hdo[(size_t)out[c] * ld_o + c];
+      for (int j = 0; j < k; ++j) col += U[(size_t)(e0 + j) * ld_er + pc] * w[j];
+      double den = 1.0 - col;
+      if (fabs(den) < kIslandTol) {
+        island = true;
+        ++nisl;
+      } else {
+        inv = 1.0 / den;
+      }
+    }
+    invden[(size_t)cand * ld_o + c] = inv;
+    // islanding bits, one 32-bit word per 32 contingencies (ballot within the wave)
+    unsigned long long bal = __ballot(island);
+    if ((c % 32) == 0) {
+      int sh = lane & 32;
+      isl[(size_t)cand * (ld_o / 32) + c / 32] = (uint32_t)(bal >> sh);
+    }
+  }
+  nisl = wave_sum(nisl);
+  if (lane == 0) atomicAdd(&s_island, nisl);
+  __syncthreads();
+  if (tid == 0) status[cand] = (uint32_t)s_flags | ((uint32_t)s_island << DCFLOW_ST_ISLAND_SHIFT);
+}
+
+}  // namespace
+
+hipError_t launch_factors(dcflow_batch *bt, hipStream_t s) {
+  dcflow_plan *p = bt->plan;
+  if (bt->n_cand == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_factors, dim3(bt->n_cand), dim3(256), 0, s, bt->d_order, bt->d_off,
+                     bt->d_kind, bt->d_id, bt->d_mask, p->d_f, p->d_t, p->d_b, p->d_adj_off,
+                     p->d_adj_br, p->d_hb, p->ld_h, p->d_ht, p->ld_er, p->n_er, p->d_hdo, p->ld_o,
+                     p->d_out, p->d_out_pos, p->n_out, p->d_pos_of_br, bt->d_nsig, bt->d_sig,
+                     bt->d_U, bt->d_W, bt->d_kinv, bt->d_invden, bt->d_isl, bt->d_status);
+  return hipGetLastError();
+}
+
+}  // namespace dcflow

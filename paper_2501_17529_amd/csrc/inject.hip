@@ -1,0 +1,287 @@
+// Injection module step 8a (paper Sec. III-C): post-change N-0 flows of every
+// injection variant, F' = PTDF' x  (Eq. ptdf_times_nodal_inj with the
+// candidate's corrected PTDF), computed as
+//
+//   F'[i][v] = H_Er x_v + U_i z_i[:, v],
+//   z_i = K_i^-1 (sigma_i . H x_v - pi_i . x_v)      (sensing rows, k x V)
+//
+// k_sense: per candidate, the sensing dot products sigma_j . H x_v as a small
+//   FP64 MFMA product (sensing rows of the full PTDF x the candidate's
+//   variants), then z = K^-1 h.
+// k_gemm:  F = X He^T on MFMA (FP64 16x16x4 or FP32 16x16x4), 128x128 tiles,
+//   LDS-staged operands with register prefetch, and the rank-k correction
+//   U z fused into the epilogue.  He is the kept-row PTDF; X holds one
+//   injection vector per output column (variant-major, K contiguous).
+// k_bcast: shared-injection mode, F0 = X He^T computed once and corrected per
+//   candidate.
+#include "dcflow_internal.h"
+
+namespace dcflow {
+namespace {
+
+// ---------------------------------------------------------------- sense
+__global__ void __launch_bounds__(256)
+k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
+        const int32_t *__restrict__ nsig, const int32_t *__restrict__ sig,
+        const double *__restrict__ pnew, const double *__restrict__ kinv,
+        const double *__restrict__ Hb, int ld_h, int n, const double *__restrict__ X, int nvar,
+        int shared, double *__restrict__ z, int vmax) {
+  __shared__ int rbr[kMaxRank * kMaxSig];
+  __shared__ double rsg[kMaxRank * kMaxSig];
+  __shared__ int relem[kMaxRank * kMaxSig];
+  __shared__ double hrow[kMaxRank * kMaxSig][16];
+  __shared__ double red[4][16][17];
+  __shared__ int s_R;
+  const int cand = blockIdx.x;
+  const int e0 = off[cand];
+  const int k = off[cand + 1] - e0;
+  if (k == 0) return;
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, g = lane / 16, li = lane % 16;
+  if (tid == 0) {
+    int R = 0;
+    for (int j = 0; j < k; ++j)
+      for (int q = 0; q < nsig[e0 + j]; ++q) {
+        int sb = sig[(size_t)(e0 + j) * kMaxSig + q];
+        rbr[R] = sb > 0 ? sb - 1 : -sb - 1;
+        rsg[R] = sb > 0 ? 1.0 : -1.0;
+        relem[R] = j;
+        ++R;
+      }
+    s_R = R;
+  }
+  __syncthreads();
+  const int R = s_R;
+  const int nch = (n + 15) / 16;
+  for (int v0 = 0; v0 < nvar; v0 += 16) {
+    for (int r0 = 0; r0 < R; r0 += 16) {
+      const int row = r0 + li;
+      const double *hrowp = row < R ? Hb + (size_t)rbr[row] * ld_h : nullptr;
+      const double sg = row < R ? rsg[row] : 0.0;
+      const int v = v0 + li;
+      const double *xr =
+          v < nvar ? X + (size_t)(shared ? v : (size_t)cand * nvar + v) * n : nullptr;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int ch = wv; ch < nch; ch += 4) {
+        const int nb = ch * 16 + 4 * g;
+        double a[4], bq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          a[q] = hrowp ? sg * hrowp[nb + q] : 0.0;  // rows padded to ld_h >= nch * 16
+          bq[q] = (xr && nb + q < n) ? xr[nb + q] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], bq[q], acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wv][4 * g + r][li] = acc[r];
+      __syncthreads();
+      {
+        int rt = tid / 16, vt = tid % 16;
+        if (r0 + rt < R)
+          hrow[r0 + rt][vt] = red[0][rt][vt] + red[1][rt][vt] + red[2][rt][vt] + red[3][rt][vt];
+      }
+      __syncthreads();
+    }
+    if (tid < 16) {
+      const int v = v0 + tid;
+      if (v < nvar) {
+        double h[kMaxRank];
+        for (int j = 0; j < kMaxRank; ++j) h[j] = 0.0;
+        for (int r = 0; r < R; ++r) h[relem[r]] += hrow[r][tid];
+        for (int j = 0; j < k; ++j)
+          if (kind[e0 + j] == DCFLOW_SPLIT) h[j] -= pnew[e0 + j];
+        const double *Ki = kinv + (size_t)cand * 64;
+        for (int j = 0; j < k; ++j) {
+          double s = 0.0;
+          for (int i = 0; i < k; ++i) s += Ki[j * 8 + i] * h[i];
+          z[(size_t)(e0 + j) * vmax + v] = s;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------- GEMM
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef d4 acc_t;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<float> {
+  typedef f4 acc_t;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int BM = 128, BN = 128, KT = 16, LDS_K = KT + 2;
+
+constexpr int kXcd = 8;  // MI355X: workgroups are dealt round-robin to 8 XCDs (own L2 each)
+
+// F[col][m] = sum_k X[xrow(col)][k] He[m][k] (+ U z correction), T in {double, float}.
+// 1-D grid, XCD-aware: the n_mt row tiles of one column tile run back to back on
+// one XCD, so the column tile of X is read from HBM once and then hits that L2.
+// 256 threads = 2 x 2 waves of 64 x 64.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, int ncols,
+       int nvar, int shared, T *__restrict__ F, int ld_f, const int32_t *__restrict__ off,
+       const double *__restrict__ U, int ld_er, const double *__restrict__ z, int vmax,
+       int correct, int n_mt, int n_nt) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T As[BM][LDS_K];
+  __shared__ T Bs[BN][LDS_K];
+  const int xcd = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
+  const int n_tile = (local / n_mt) * kXcd + xcd, m_tile = local % n_mt;
+  if (n_tile >= n_nt) return;
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, g = lane / 16, li = lane % 16;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int n0 = n_tile * BN, m0 = m_tile * BM;
+  // global -> register staging: thread loads 8 consecutive k of one row of A and of B
+  const int lr = tid >> 1, lk = (tid & 1) * 8;
+  const T *arow = He + (size_t)(m0 + lr) * ld_h;
+  const int bcol = n0 + lr;
+  const double *brow = nullptr;
+  if (bcol < ncols) brow = X + (size_t)bcol * n;
+  T ra[8], rb[8];
+  const int nk = (n + KT - 1) / KT;
+  auto gload = [&](int kt) {
+    const int kb = kt * KT + lk;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ra[q] = arow[kb + q];  // He padded to ld_h (multiple of 16)
+    if (brow && kb + 8 <= n) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) rb[q] = (T)brow[kb + q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) rb[q] = (brow && kb + q < n) ? (T)brow[kb + q] : (T)0;
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      As[lr][lk + q] = ra[q];
+      Bs[lr][lk + q] = rb[q];
+    }
+  };
+  acc_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+  gload(0);
+  sstore();
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) gload(kt + 1);
+#pragma unroll
+    for (int ks = 0; ks < KT / 4; ++ks) {
+      T af[4], bf[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) af[a] = As[wm * 64 + a * 16 + li][ks * 4 + g];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bf[b] = Bs[wn * 64 + b * 16 + li][ks * 4 + g];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::op(af[a], bf[b], acc[a][b]);
+    }
+    __syncthreads();
+    if (kt + 1 < nk) {
+      sstore();
+      __syncthreads();
+    }
+  }
+  // epilogue: rank-k correction and store
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int col = n0 + wn * 64 + b * 16 + li;
+    if (col >= ncols) continue;
+    int e0 = 0, e1 = 0, v = col;
+    if (correct) {
+      const int cand = col / nvar;
+      v = col - cand * nvar;
+      e0 = off[cand];
+      e1 = off[cand + 1];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int m = m0 + wm * 64 + a * 16 + 4 * g;
+      double o[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) o[r] = (double)acc[a][b][r];
+      for (int e = e0; e < e1; ++e) {
+        const double ze = z[(size_t)e * vmax + v];
+        const double *ue = U + (size_t)e * ld_er + m;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[r] += ue[r] * ze;
+      }
+      T *dst = F + (size_t)col * ld_f + m;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dst[r] = (T)o[r];
+    }
+  }
+}
+
+// Shared injections: F[i][v][m] = F0[v][m] + sum_e U[e][m] z[e][v].
+template <typename T>
+__global__ void k_bcast(const T *__restrict__ F0, T *__restrict__ F, int ld_f, int nvar,
+                        const int32_t *__restrict__ off, const double *__restrict__ U, int ld_er,
+                        const double *__restrict__ z, int vmax) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y, cand = blockIdx.z;
+  if (m >= ld_f) return;
+  double o = (double)F0[(size_t)v * ld_f + m];
+  for (int e = off[cand]; e < off[cand + 1]; ++e) o += U[(size_t)e * ld_er + m] * z[(size_t)e * vmax + v];
+  F[((size_t)cand * nvar + v) * ld_f + m] = (T)o;
+}
+
+template <typename T>
+hipError_t run_injections(dcflow_batch *bt, const T *He, const double *inj, int nvar, int shared,
+                          T *flows, hipStream_t s) {
+  dcflow_plan *p = bt->plan;
+  const int ld_f = p->ld_er;
+  hipLaunchKernelGGL(k_sense, dim3(bt->n_cand), dim3(256), 0, s, bt->d_off, bt->d_kind, bt->d_nsig,
+                     bt->d_sig, bt->d_pnew, bt->d_kinv, p->d_hb, p->ld_h, p->n, inj, nvar, shared,
+                     bt->d_z, bt->vmax);
+  if (!shared) {
+    const int ncols = bt->n_cand * nvar;
+    const int n_mt = p->ld_er / BM, n_nt = (ncols + BN - 1) / BN;
+    dim3 grid(kXcd * ((n_nt + kXcd - 1) / kXcd) * n_mt);
+    k_gemm<T><<<grid, dim3(256), 0, s>>>(He, p->ld_h, inj, p->n, ncols, nvar, 0, flows, ld_f,
+                                         bt->d_off, bt->d_U, p->ld_er, bt->d_z, bt->vmax, 1,
+                                         n_mt, n_nt);
+  } else {
+    T *f0 = reinterpret_cast<T *>(bt->d_f0);
+    const int n_mt = p->ld_er / BM, n_nt = (nvar + BN - 1) / BN;
+    dim3 grid(kXcd * ((n_nt + kXcd - 1) / kXcd) * n_mt);
+    k_gemm<T><<<grid, dim3(256), 0, s>>>(He, p->ld_h, inj, p->n, nvar, nvar, 1, f0, ld_f,
+                                         bt->d_off, bt->d_U, p->ld_er, bt->d_z, bt->vmax, 0,
+                                         n_mt, n_nt);
+    dim3 g2((ld_f + 255) / 256, nvar, bt->n_cand);
+    k_bcast<T><<<g2, dim3(256), 0, s>>>(f0, flows, ld_f, nvar, bt->d_off, bt->d_U, p->ld_er,
+                                        bt->d_z, bt->vmax);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_injections(dcflow_batch *bt, const double *inj, int nvar, int shared, int prec,
+                             void *flows, hipStream_t s) {
+  if (bt->n_cand == 0) return hipSuccess;
+  if (prec == DCFLOW_FP64)
+    return run_injections<double>(bt, bt->plan->d_he64, inj, nvar, shared,
+                                  static_cast<double *>(flows), s);
+  return run_injections<float>(bt, bt->plan->d_he32, inj, nvar, shared,
+                               static_cast<float *>(flows), s);
+}
+
+}  // namespace dcflow

@@ -1,0 +1,353 @@
+"""Thin Python binding of libdcflow.so (argument marshalling only).
+
+Every step of the screen runs in the library's HIP kernels; PyTorch provides
+device memory (the workspace, batch, flow and score buffers) and the stream.
+The entry points keep the C names: build_ptdf, eval_topologies,
+eval_injections, n1_score.  There is no CPU fallback: if the shared library is
+missing or fails to load, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdcflow.so")
+
+DCFLOW_FP64 = 0
+DCFLOW_FP32 = 1
+PREC = {"fp64": DCFLOW_FP64, "fp32": DCFLOW_FP32}
+
+ST_DISCONNECTED = 0x1
+ST_SINGULAR = 0x2
+ST_NONFINITE = 0x4
+ST_ISLAND_SHIFT = 8
+
+SCORE_DTYPE = np.dtype([("max_load", "<f8"), ("overload_sum", "<f8"), ("best_variant", "<i4"),
+                        ("worst_branch", "<i4"), ("worst_outage", "<i4"), ("status", "<u4")])
+
+
+class DcflowError(RuntimeError):
+    def __init__(self, code, what, bad_index=None):
+        self.code = code
+        self.bad_index = bad_index
+        msg = f"{what}: {_lib.dcflow_strerror(code).decode()} ({code})"
+        if bad_index is not None:
+            msg += f", bad index {bad_index}"
+        super().__init__(msg)
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("n_bus", ctypes.c_int32), ("n_branch", ctypes.c_int32), ("slack", ctypes.c_int32),
+                ("from_", ctypes.c_void_p), ("to", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("n_mon", ctypes.c_int32), ("mon", ctypes.c_void_p),
+                ("n_out", ctypes.c_int32), ("out", ctypes.c_void_p),
+                ("p_base", ctypes.c_void_p), ("rating", ctypes.c_void_p),
+                ("rating_scale", ctypes.c_double), ("rating_offset", ctypes.c_double)]
+
+
+class Cands(ctypes.Structure):
+    _fields_ = [("n_cand", ctypes.c_int32), ("off", ctypes.c_void_p), ("kind", ctypes.c_void_p),
+                ("id", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("p_new", ctypes.c_void_p)]
+
+
+class PlanView(ctypes.Structure):
+    _fields_ = [("n_bus", ctypes.c_int32), ("n_branch", ctypes.c_int32), ("n_mon", ctypes.c_int32),
+                ("n_out", ctypes.c_int32), ("n_er", ctypes.c_int32), ("ld_h", ctypes.c_int32),
+                ("ld_o", ctypes.c_int32), ("ptdf", ctypes.c_void_p), ("hdo", ctypes.c_void_p),
+                ("f_base", ctypes.c_void_p), ("rating", ctypes.c_void_p), ("er", ctypes.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2501_17529_amd.build_lib")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    sig = {
+        "dcflow_plan_workspace_bytes": (ctypes.c_int, [P, ctypes.POINTER(SZ)]),
+        "dcflow_build_ptdf": (ctypes.c_int, [P, P, SZ, P, ctypes.POINTER(P)]),
+        "dcflow_plan_view_get": (ctypes.c_int, [P, P]),
+        "dcflow_plan_destroy": (None, [P]),
+        "dcflow_validate_candidates": (ctypes.c_int, [P, P, ctypes.POINTER(I32),
+                                                      ctypes.POINTER(ctypes.c_int64),
+                                                      ctypes.POINTER(ctypes.c_int64)]),
+        "dcflow_batch_bytes": (ctypes.c_int, [P, P, I32, ctypes.POINTER(SZ)]),
+        "dcflow_batch_create": (ctypes.c_int, [P, P, I32, P, SZ, P, ctypes.POINTER(P)]),
+        "dcflow_batch_destroy": (None, [P]),
+        "dcflow_eval_topologies": (ctypes.c_int, [P, P]),
+        "dcflow_flow_bytes": (ctypes.c_int, [P, I32, ctypes.c_int, ctypes.POINTER(SZ),
+                                             ctypes.POINTER(I32)]),
+        "dcflow_eval_injections": (ctypes.c_int, [P, P, I32, I32, ctypes.c_int, P, SZ, P]),
+        "dcflow_n1_score": (ctypes.c_int, [P, P, I32, ctypes.c_int, P, P]),
+        "dcflow_batch_variant_max": (P, [P]),
+        "dcflow_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("dcflow_plan_workspace_bytes", "dcflow_build_ptdf", "dcflow_plan_view_get",
+            "dcflow_plan_destroy", "dcflow_validate_candidates", "dcflow_batch_bytes",
+            "dcflow_batch_create", "dcflow_batch_destroy", "dcflow_eval_topologies",
+            "dcflow_flow_bytes", "dcflow_eval_injections", "dcflow_n1_score",
+            "dcflow_batch_variant_max", "dcflow_strerror")
+
+
+def _check(rc, what, bad=None):
+    if rc != 0:
+        raise DcflowError(rc, what, bad)
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class _GridArgs:
+    """Keeps the host arrays of a grid description alive."""
+
+    def __init__(self, n_bus, f, t, b, mon, out, p_base, slack=0, rating=None,
+                 rating_scale=1.2, rating_offset=0.1):
+        self.f = _arr(f, np.int32)
+        self.t = _arr(t, np.int32)
+        self.b = _arr(b, np.float64)
+        self.mon = _arr(mon, np.int32)
+        self.out = _arr(out, np.int32)
+        self.p = _arr(p_base, np.float64)
+        self.r = None if rating is None else _arr(rating, np.float64)
+        self.desc = GridDesc(
+            int(n_bus), len(self.f), int(slack), self.f.ctypes.data, self.t.ctypes.data,
+            self.b.ctypes.data, len(self.mon), self.mon.ctypes.data, len(self.out),
+            self.out.ctypes.data if len(self.out) else None, self.p.ctypes.data,
+            None if self.r is None else self.r.ctypes.data, float(rating_scale),
+            float(rating_offset))
+
+
+class _CandArgs:
+    def __init__(self, off, kind, ids, mask, p_new=None):
+        self.off = _arr(off, np.int32)
+        self.kind = _arr(kind, np.int8)
+        self.id = _arr(ids, np.int32)
+        self.mask = _arr(mask, np.uint32)
+        self.p_new = None if p_new is None else _arr(p_new, np.float64)
+        ne = len(self.kind)
+        self.desc = Cands(len(self.off) - 1, self.off.ctypes.data,
+                          self.kind.ctypes.data if ne else None,
+                          self.id.ctypes.data if ne else None,
+                          self.mask.ctypes.data if ne else None,
+                          None if self.p_new is None or ne == 0 else self.p_new.ctypes.data)
+
+
+def cand_args(cands):
+    """Candidate arrays from any object with off/kind/id/mask/p_new attributes."""
+    return _CandArgs(cands.off, cands.kind, cands.id, cands.mask, getattr(cands, "p_new", None))
+
+
+def validate_candidates(grid_args: _GridArgs, cands):
+    """Host-only validation; returns (packed_slots, padded_slots)."""
+    ca = cands if isinstance(cands, _CandArgs) else cand_args(cands)
+    bad = ctypes.c_int32(0)
+    packed = ctypes.c_int64(0)
+    padded = ctypes.c_int64(0)
+    rc = _lib.dcflow_validate_candidates(ctypes.byref(grid_args.desc), ctypes.byref(ca.desc),
+                                         ctypes.byref(bad), ctypes.byref(packed),
+                                         ctypes.byref(padded))
+    _check(rc, "dcflow_validate_candidates", bad.value if rc == -6 else None)
+    return packed.value, padded.value
+
+
+class Plan:
+    """dcflow_build_ptdf: one-time FP64 base build on the current CUDA device."""
+
+    def __init__(self, n_bus, f, t, b, mon, out, p_base, slack=0, rating=None,
+                 rating_scale=1.2, rating_offset=0.1, device="cuda", stream=None):
+        import torch
+        self.args = _GridArgs(n_bus, f, t, b, mon, out, p_base, slack, rating, rating_scale,
+                              rating_offset)
+        nbytes = ctypes.c_size_t(0)
+        _check(_lib.dcflow_plan_workspace_bytes(ctypes.byref(self.args.desc), ctypes.byref(nbytes)),
+               "dcflow_plan_workspace_bytes")
+        self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(_lib.dcflow_build_ptdf(ctypes.byref(self.args.desc), ctypes.c_void_p(self.ws.data_ptr()),
+                                      nbytes.value, _stream(stream), ctypes.byref(h)),
+               "dcflow_build_ptdf")
+        self.h = h
+        self.device = device
+        v = PlanView()
+        _check(_lib.dcflow_plan_view_get(h, ctypes.byref(v)), "dcflow_plan_view_get")
+        self.view = v
+
+    @classmethod
+    def from_workload(cls, w, rating=None, **kw):
+        g = w.grid
+        return cls(g.n_bus, g.f, g.t, g.b, w.mon, w.out, g.p, g.slack, rating,
+                   w.rating_scale, w.rating_offset, **kw)
+
+    def _dev(self, ptr, shape, dtype):
+        import torch
+        n = int(np.prod(shape))
+        el = torch.empty(0, dtype=dtype).element_size()
+        base = self.ws.data_ptr()
+        off = ptr - base
+        assert off % el == 0 and 0 <= off and off + n * el <= self.ws.numel()
+        return self.ws[off:off + n * el].view(dtype).view(*shape)
+
+    def ptdf(self):
+        import torch
+        v = self.view
+        return self._dev(v.ptdf, (v.n_branch, v.ld_h), torch.float64)[:, :v.n_bus]
+
+    def hdo(self):
+        import torch
+        v = self.view
+        return self._dev(v.hdo, (v.n_branch, v.ld_o), torch.float64)[:, :v.n_out]
+
+    def f_base(self):
+        import torch
+        return self._dev(self.view.f_base, (self.view.n_branch,), torch.float64)
+
+    def rating(self):
+        import torch
+        return self._dev(self.view.rating, (self.view.n_mon,), torch.float64)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            _lib.dcflow_plan_destroy(h)
+            self.h = None
+
+
+class Batch:
+    """dcflow_batch_create (validate, pack, upload) plus the three per-batch calls."""
+
+    def __init__(self, plan: Plan, cands, n_var_max: int, stream=None):
+        import torch
+        self.plan = plan
+        self.ca = cands if isinstance(cands, _CandArgs) else cand_args(cands)
+        nbytes = ctypes.c_size_t(0)
+        _check(_lib.dcflow_batch_bytes(plan.h, ctypes.byref(self.ca.desc), int(n_var_max),
+                                       ctypes.byref(nbytes)), "dcflow_batch_bytes")
+        self.buf = torch.empty(nbytes.value, dtype=torch.uint8, device=plan.device)
+        h = ctypes.c_void_p()
+        rc = _lib.dcflow_batch_create(plan.h, ctypes.byref(self.ca.desc), int(n_var_max),
+                                      ctypes.c_void_p(self.buf.data_ptr()), nbytes.value,
+                                      _stream(stream), ctypes.byref(h))
+        if rc == -6:
+            validate_candidates(plan.args, self.ca)   # raises with the bad index
+        _check(rc, "dcflow_batch_create")
+        self.h = h
+        self.n_cand = len(self.ca.off) - 1
+        self.n_var_max = int(n_var_max)
+
+    def eval_topologies(self, stream=None):
+        _check(_lib.dcflow_eval_topologies(self.h, _stream(stream)), "dcflow_eval_topologies")
+
+    def flow_buffer(self, n_var, prec):
+        import torch
+        nbytes = ctypes.c_size_t(0)
+        ld = ctypes.c_int32(0)
+        _check(_lib.dcflow_flow_bytes(self.h, int(n_var), PREC[prec], ctypes.byref(nbytes),
+                                      ctypes.byref(ld)), "dcflow_flow_bytes")
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        el = 8 if prec == "fp64" else 4
+        t = torch.empty(nbytes.value // el, dtype=dt, device=self.plan.device)
+        return t, ld.value
+
+    def eval_injections(self, inj, n_var, shared, prec, flows=None, stream=None):
+        """inj: CUDA float64 tensor [n_cand, n_var, n_bus] or [n_var, n_bus] (shared).
+        Returns the flow tensor viewed as [n_cand, n_var, ld_f]."""
+        import torch
+        assert inj.is_cuda and inj.dtype == torch.float64 and inj.is_contiguous()
+        if flows is None:
+            flows, _ = self.flow_buffer(n_var, prec)
+        _check(_lib.dcflow_eval_injections(self.h, ctypes.c_void_p(inj.data_ptr()), int(n_var),
+                                           int(bool(shared)), PREC[prec],
+                                           ctypes.c_void_p(flows.data_ptr()),
+                                           flows.numel() * flows.element_size(), _stream(stream)),
+               "dcflow_eval_injections")
+        self.flows = flows
+        return flows
+
+    def flows_view(self, flows, n_var):
+        ld = _ld_er(self)
+        return flows[: self.n_cand * n_var * ld].view(self.n_cand, n_var, ld)
+
+    def n1_score(self, flows, n_var, prec, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(max(self.n_cand, 1) * SCORE_DTYPE.itemsize, dtype=torch.uint8,
+                              device=self.plan.device)
+        _check(_lib.dcflow_n1_score(self.h, ctypes.c_void_p(flows.data_ptr()), int(n_var),
+                                    PREC[prec], ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+               "dcflow_n1_score")
+        return out
+
+    def variant_max(self, n_var):
+        import torch
+        ptr = _lib.dcflow_batch_variant_max(self.h)
+        off = ptr - self.buf.data_ptr()
+        n = self.n_cand * self.n_var_max
+        return self.buf[off:off + 8 * n].view(torch.float64).view(self.n_cand, self.n_var_max)[:, :n_var]
+
+    @staticmethod
+    def scores_to_numpy(out, n_cand):
+        raw = out.cpu().numpy()[: n_cand * SCORE_DTYPE.itemsize]
+        return raw.view(SCORE_DTYPE)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            _lib.dcflow_batch_destroy(h)
+            self.h = None
+
+
+def _ld_er(batch):
+    nbytes = ctypes.c_size_t(0)
+    ld = ctypes.c_int32(0)
+    _check(_lib.dcflow_flow_bytes(batch.h, 1, DCFLOW_FP64, ctypes.byref(nbytes), ctypes.byref(ld)),
+           "dcflow_flow_bytes")
+    return ld.value
+
+
+# ---- the C entry points under their own names ---------------------------------------------
+
+def build_ptdf(n_bus, f, t, b, mon, out, p_base, slack=0, rating=None, rating_scale=1.2,
+               rating_offset=0.1, device="cuda", stream=None) -> Plan:
+    return Plan(n_bus, f, t, b, mon, out, p_base, slack, rating, rating_scale, rating_offset,
+                device, stream)
+
+
+def eval_topologies(plan: Plan, cands, n_var_max: int, stream=None) -> Batch:
+    bt = Batch(plan, cands, n_var_max, stream)
+    bt.eval_topologies(stream)
+    return bt
+
+
+def eval_injections(batch: Batch, inj, n_var, shared, prec="fp32", stream=None):
+    return batch.eval_injections(inj, n_var, shared, prec, stream=stream)
+
+
+def n1_score(batch: Batch, flows, n_var, prec="fp32", stream=None):
+    return batch.n1_score(flows, n_var, prec, stream=stream)
+
+
+def screen(plan: Plan, cands, inj, n_var, shared, prec="fp32", stream=None):
+    """Whole path for one batch; returns the numpy score records."""
+    import torch
+    bt = eval_topologies(plan, cands, n_var, stream)
+    flows = eval_injections(bt, inj, n_var, shared, prec, stream)
+    out = n1_score(bt, flows, n_var, prec, stream)
+    torch.cuda.synchronize()
+    return Batch.scores_to_numpy(out, bt.n_cand), bt, flows

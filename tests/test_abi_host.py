@@ -1,0 +1,98 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+entry point, and rejects malformed input before touching a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gridgen as G
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def d():
+    from paper_2501_17529_amd import dcflow
+    return dcflow
+
+
+def test_header_symbols_exported(d):
+    hdr = open(os.path.join(ROOT, "include", "dcflow.h")).read()
+    declared = set(re.findall(r"^(?:int|void|const char \*|const double \*)\s*(dcflow_[a-z0-9_]+)\(",
+                              hdr, flags=re.M))
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(d._lib, name), name
+    assert declared == set(d.EXPORTED)
+
+
+def _grid_args(d, w):
+    g = w.grid
+    return d._GridArgs(g.n_bus, g.f, g.t, g.b, w.mon, w.out, g.p, g.slack)
+
+
+def test_fig1_packing_counts(d):
+    import json
+    fx = json.load(open(os.path.join(ROOT, "tests", "golden", "fig1_packing.json")))
+    w = G.workload_tiny(0)
+    g = w.grid
+    buses = [int(x) for x in np.flatnonzero(g.degree() >= 3)[:3]]
+    split = {f"S{i + 1}": G.random_split(g, np.random.default_rng(i), b) for i, b in enumerate(buses)}
+    lists = [[split[s] for s in c] for c in fx["candidates"]]
+    packed, padded = d.validate_candidates(_grid_args(d, w), G.Candidates.from_lists(lists))
+    assert packed == fx["naive_applications"]
+    assert padded == fx["padded_simd_applications"]
+
+
+def _bad(d, w, lists, expect_index):
+    with pytest.raises(d.DcflowError) as ei:
+        d.validate_candidates(_grid_args(d, w), G.Candidates.from_lists(lists))
+    assert ei.value.code == -6
+    assert ei.value.bad_index == expect_index
+
+
+def test_candidate_validation_errors(d):
+    w = G.workload_tiny(0)
+    g = w.grid
+    a = int(np.flatnonzero(g.degree() >= 3)[0])
+    deg = len(g.incident(a))
+    ok = (G.KIND_SPLIT, a, 2, 0.0)
+    _bad(d, w, [[ok], [(G.KIND_OUTAGE, g.n_branch, 0, 0.0)]], 1)          # branch out of range
+    _bad(d, w, [[(G.KIND_SPLIT, a, 0, 0.0)]], 0)                           # empty mask
+    _bad(d, w, [[(G.KIND_SPLIT, a, (1 << deg) - 1, 0.0)]], 0)              # moves every branch
+    _bad(d, w, [[(G.KIND_SPLIT, a, 1 << deg, 0.0)]], 0)                    # bit beyond degree
+    _bad(d, w, [[ok, ok]], 1)                                              # two splits of one bus
+    _bad(d, w, [[(G.KIND_OUTAGE, 3, 0, 0.0), (G.KIND_OUTAGE, 3, 0, 0.0)]], 1)  # duplicate outage
+    _bad(d, w, [[(G.KIND_OUTAGE, i, 0, 0.0) for i in range(9)]], -1)       # rank 9 > 8
+    _bad(d, w, [[(G.KIND_SPLIT, a, 2, float("nan"))]], 0)                  # non-finite p_new
+    deg1 = np.flatnonzero(g.degree() == 1)
+    if len(deg1):
+        _bad(d, w, [[(G.KIND_SPLIT, int(deg1[0]), 1, 0.0)]], 0)            # degree-1 bus
+
+
+def test_empty_and_rank_zero_candidates_are_valid(d):
+    w = G.workload_tiny(0)
+    assert d.validate_candidates(_grid_args(d, w), G.Candidates.from_lists([])) == (0, 0)
+    assert d.validate_candidates(_grid_args(d, w), G.Candidates.from_lists([[], []])) == (0, 0)
+
+
+def test_grid_validation_errors(d):
+    w = G.workload_tiny(0)
+    g = w.grid
+    f = g.f.copy()
+    f[0] = g.t[0]                      # self loop
+    ga = d._GridArgs(g.n_bus, f, g.t, g.b, w.mon, w.out, g.p)
+    with pytest.raises(d.DcflowError) as ei:
+        d.validate_candidates(ga, w.cands)
+    assert ei.value.code == -2
+    b = g.b.copy()
+    b[3] = -1.0                        # negative susceptance
+    ga = d._GridArgs(g.n_bus, g.f, g.t, b, w.mon, w.out, g.p)
+    with pytest.raises(d.DcflowError) as ei:
+        d.validate_candidates(ga, w.cands)
+    assert ei.value.code == -1
+    ga = d._GridArgs(g.n_bus, g.f, g.t, g.b, w.mon, np.array([1, 1]), g.p)   # duplicate contingency
+    with pytest.raises(d.DcflowError) as ei:
+        d.validate_candidates(ga, w.cands)
+    assert ei.value.code == -2
