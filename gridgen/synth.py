@@ -55,7 +55,18 @@ class Grid:
 
     def incident(self, bus: int) -> np.ndarray:
         """Branch ids touching ``bus`` in ascending order (mask bit order)."""
-        return np.flatnonzero((self.f == bus) | (self.t == bus)).astype(np.int32)
+        adj = self.__dict__.get("_adj")
+        if adj is None:
+            m = len(self.f)
+            ends = np.concatenate([self.f, self.t]).astype(np.int64)
+            br = np.concatenate([np.arange(m), np.arange(m)])
+            order = np.lexsort((br, ends))
+            off = np.zeros(self.n_bus + 1, np.int64)
+            np.add.at(off, ends + 1, 1)
+            adj = (np.cumsum(off), br[order].astype(np.int32))
+            self.__dict__["_adj"] = adj
+        off, lst = adj
+        return lst[off[bus]:off[bus + 1]]
 
     def degree(self) -> np.ndarray:
         return np.bincount(np.concatenate([self.f, self.t]), minlength=self.n_bus)
@@ -194,7 +205,47 @@ def candidate_topology(grid: Grid, elems):
     return grid.n_bus + n_new, f, t, alive
 
 
+_UF = None
+
+
+def _uf_lib():
+    """Optional C union-find (gridgen/libgguf.so, built by build_uf()); None if absent."""
+    global _UF
+    if _UF is None:
+        import ctypes
+        import os
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgguf.so")
+        _UF = False
+        if os.path.exists(path):
+            lib = ctypes.CDLL(path)
+            lib.gg_connected.restype = ctypes.c_int
+            lib.gg_connected.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]
+            _UF = lib
+    return _UF or None
+
+
+def build_uf() -> str:
+    """Compile the optional C union-find helper in place (gcc)."""
+    import os
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    out = os.path.join(here, "libgguf.so")
+    subprocess.run(["gcc", "-O2", "-shared", "-fPIC", os.path.join(here, "uf.c"), "-o", out],
+                   check=True)
+    return out
+
+
 def is_connected(n_nodes: int, f, t, alive=None) -> bool:
+    lib = _uf_lib()
+    if lib is not None:
+        f64 = np.ascontiguousarray(f, np.int64)
+        t64 = np.ascontiguousarray(t, np.int64)
+        al = None if alive is None else np.ascontiguousarray(alive, np.uint8)
+        r = lib.gg_connected(int(n_nodes), len(f64), f64.ctypes.data, t64.ctypes.data,
+                             None if al is None else al.ctypes.data)
+        if r >= 0:
+            return bool(r)
     if alive is not None:
         f = f[alive]
         t = t[alive]
@@ -235,31 +286,34 @@ def random_split(grid: Grid, rng, bus: int):
 def sample_candidate(grid: Grid, rng, n_split: int, n_out: int, split_buses=None,
                      max_tries: int = 200):
     """One connected candidate with ``n_split`` bus splits then ``n_out``
-    remedial outages (outages drawn among non-bridges of the split grid)."""
+    remedial outages: a uniform set of distinct branches that keeps the
+    candidate grid connected."""
     if split_buses is None:
         split_buses = _split_buses(grid)
     for _ in range(max_tries):
-        buses = rng.choice(split_buses, size=n_split, replace=False) if n_split else []
-        elems = [random_split(grid, rng, int(bus)) for bus in buses]
+        buses = []
+        while len(buses) < n_split:
+            bus = int(split_buses[int(rng.integers(len(split_buses)))])
+            if bus not in buses:
+                buses.append(bus)
+        elems = [random_split(grid, rng, bus) for bus in buses]
         n_nodes, f, t, alive = candidate_topology(grid, elems)
         if not is_connected(n_nodes, f, t, alive):
             continue
-        ok = True
-        for _o in range(n_out):
-            for _r in range(max_tries):
-                br = int(rng.integers(grid.n_branch))
-                if not alive[br]:
-                    continue
-                alive[br] = False
-                if is_connected(n_nodes, f, t, alive):
-                    elems.append((KIND_OUTAGE, br, 0, 0.0))
-                    break
-                alive[br] = True
-            else:
-                ok = False
-                break
-        if ok:
+        if n_out == 0:
             return elems
+        # remedial outages: a uniform set of distinct branches that keeps the
+        # candidate grid connected (rejection sampling of the whole set)
+        for _r in range(max_tries):
+            outs = []
+            while len(outs) < n_out:
+                br = int(rng.integers(grid.n_branch))
+                if br not in outs:
+                    outs.append(br)
+            al = alive.copy()
+            al[outs] = False
+            if is_connected(n_nodes, f, t, al):
+                return elems + [(KIND_OUTAGE, br, 0, 0.0) for br in outs]
     raise RuntimeError("could not sample a connected candidate")
 
 

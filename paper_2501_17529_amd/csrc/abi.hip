@@ -3,6 +3,7 @@
 // entry points declared in include/dcflow.h.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -226,10 +227,12 @@ std::vector<int32_t> host_adj_off(const dcflow_grid_desc *g) {
   return off;
 }
 
-#define HIPCHECK(x)                       \
-  do {                                    \
-    if ((x) != hipSuccess) return DCFLOW_E_HIP; \
-  } while (0)
+// Maps a HIP failure to DCFLOW_E_HIP and names it on stderr (the status code
+// alone cannot say which runtime error it was).
+int hip_fail(hipError_t e, const char *where) {
+  fprintf(stderr, "dcflow: %s: %s\n", where, hipGetErrorString(e));
+  return DCFLOW_E_HIP;
+}
 
 }  // namespace
 
@@ -328,7 +331,7 @@ int dcflow_build_ptdf(const dcflow_grid_desc *g, void *dev_ws, size_t ws_bytes, 
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // host staging vectors die here
   if (e != hipSuccess) {
     delete p;
-    return DCFLOW_E_HIP;
+    return hip_fail(e, "dcflow_build_ptdf");
   }
   *plan_out = p;
   return DCFLOW_OK;
@@ -439,7 +442,8 @@ void dcflow_batch_destroy(dcflow_batch *b) { delete b; }
 
 int dcflow_eval_topologies(dcflow_batch *b, hipStream_t s) {
   if (!b) return DCFLOW_E_ARG;
-  if (launch_factors(b, s) != hipSuccess) return DCFLOW_E_HIP;
+  hipError_t e = launch_factors(b, s);
+  if (e != hipSuccess) return hip_fail(e, "dcflow_eval_topologies");
   b->factored = 1;
   return DCFLOW_OK;
 }
@@ -464,8 +468,8 @@ int dcflow_eval_injections(dcflow_batch *b, const double *dev_inj, int32_t n_var
   size_t need = 0;
   dcflow_flow_bytes(b, n_var, prec, &need, nullptr);
   if (flow_bytes < need) return DCFLOW_E_WORKSPACE;
-  if (launch_injections(b, dev_inj, n_var, inj_shared ? 1 : 0, prec, dev_flows, s) != hipSuccess)
-    return DCFLOW_E_HIP;
+  hipError_t e = launch_injections(b, dev_inj, n_var, inj_shared ? 1 : 0, prec, dev_flows, s);
+  if (e != hipSuccess) return hip_fail(e, "dcflow_eval_injections");
   b->flows_prec = prec;
   b->flows_nvar = n_var;
   return DCFLOW_OK;
@@ -478,7 +482,8 @@ int dcflow_n1_score(dcflow_batch *b, const void *dev_flows, int32_t n_var, dcflo
   if (prec != DCFLOW_FP64 && prec != DCFLOW_FP32) return DCFLOW_E_ARG;
   if (!b->factored) return DCFLOW_E_ARG;
   if (b->flows_prec != prec || b->flows_nvar != n_var) return DCFLOW_E_ARG;
-  if (launch_score(b, dev_flows, n_var, prec, dev_out, s) != hipSuccess) return DCFLOW_E_HIP;
+  hipError_t e = launch_score(b, dev_flows, n_var, prec, dev_out, s);
+  if (e != hipSuccess) return hip_fail(e, "dcflow_n1_score");
   return DCFLOW_OK;
 }
 

@@ -177,28 +177,37 @@ hipError_t launch_build(dcflow_plan *p, hipStream_t s, const double *h_rating, d
   const int n = p->n, m = p->m, ld = p->ld_h;
   // reduced Laplacian and its inverse
   hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, p->d_binv, (size_t)ld * ld, 0.0);
+  DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_assemble, dim3(nblk(n, 256)), dim3(256), 0, s, p->d_binv, ld, n, p->slack,
                      p->d_adj_off, p->d_adj_br, p->d_f, p->d_t, p->d_b);
+  DCF_CHECK_LAUNCH();
   double *pr[2] = {p->d_piv, p->d_piv + 2 * ld};
   double *pc[2] = {p->d_piv + ld, p->d_piv + 3 * ld};
   hipLaunchKernelGGL(k_gj_save0, dim3(nblk(n, 256)), dim3(256), 0, s, p->d_binv, ld, n, pr[0],
                      pc[0]);
+  DCF_CHECK_LAUNCH();
   for (int q = 0; q < n; ++q) {
     int a = q & 1;
     hipLaunchKernelGGL(k_gj_step, dim3(nblk(n, 256), n), dim3(256), 0, s, p->d_binv, ld, n, q,
                        pr[a], pc[a], pr[a ^ 1], pc[a ^ 1]);
+    DCF_CHECK_LAUNCH();
   }
   // PTDF and derived operands
   hipLaunchKernelGGL(k_ptdf_rows, dim3(nblk(ld, 256), m), dim3(256), 0, s, p->d_hb, ld, n, m,
                      p->slack, p->d_binv, p->d_f, p->d_t, p->d_b);
+  DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_rows_transpose, dim3(nblk(n, 32), nblk(p->ld_er, 32)), dim3(32, 8), 0, s,
                      p->d_ht, p->ld_er, p->d_hb, ld, n, p->d_er, p->n_er);
+  DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_copy_he, dim3(nblk(ld, 256), p->ld_er), dim3(256), 0, s, p->d_he64,
                      p->d_he32, ld, p->d_hb, p->d_er, p->n_er, p->ld_er);
+  DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_hdo, dim3(nblk(p->ld_o, 256), m), dim3(256), 0, s, p->d_hdo, p->ld_o,
                      p->d_hb, ld, m, p->d_out_f, p->d_out_t, p->n_out);
+  DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_fbase, dim3(nblk(m, 4)), dim3(256), 0, s, p->d_fbase, p->d_hb, ld,
                      p->d_pbase, m);
+  DCF_CHECK_LAUNCH();
   if (h_rating) {
     hipError_t e = hipMemcpyAsync(p->d_rating, h_rating, sizeof(double) * p->n_mon,
                                   hipMemcpyHostToDevice, s);
@@ -207,10 +216,12 @@ hipError_t launch_build(dcflow_plan *p, hipStream_t s, const double *h_rating, d
   hipLaunchKernelGGL(k_rating, dim3(nblk(p->mon_pad, 256)), dim3(256), 0, s, p->d_rating,
                      p->d_inv_r, p->mon_pad, p->d_mon, p->n_mon, p->d_fbase, h_rating ? 1 : 0,
                      rscale, roffset);
+  DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_lsd, dim3(nblk(p->ld_o, 256), p->mon_pad), dim3(256), 0, s, p->d_lsd,
                      p->ld_o, p->d_hdo, p->d_mon, p->n_mon, p->d_out, p->n_out, p->d_inv_r,
                      p->mon_pad);
-  return hipGetLastError();
+  DCF_CHECK_LAUNCH();
+  return hipSuccess;
 }
 
 }  // namespace dcflow

@@ -77,6 +77,14 @@ struct dcflow_batch {
   int flows_nvar;
 };
 
+// Returns the launch error of the kernel just enqueued (HIP's last-error slot is
+// overwritten by later successful calls, so every launch is checked at once).
+#define DCF_CHECK_LAUNCH()                      \
+  do {                                          \
+    hipError_t e_ = hipGetLastError();          \
+    if (e_ != hipSuccess) return e_;            \
+  } while (0)
+
 namespace dcflow {
 
 // ------------------------------------------------------------ kernels
@@ -93,10 +101,31 @@ hipError_t launch_score(dcflow_batch *b, const void *flows, int nvar, int prec,
                         dcflow_score *out, hipStream_t s);
 
 // ------------------------------------------------------ device helpers
+// Row of a 16x16 MFMA accumulator block held by lane group g (= lane / 16) in
+// register r; the column is lane % 16.  Measured on gfx950: the FP32 16x16x4
+// form keeps four consecutive rows per lane group (4g + r), the FP64 16x16x4
+// form interleaves them (g + 4r).  The A operand row is lane % 16 and the
+// B operand column is lane % 16 (k = lane / 16) for both.
+template <typename T>
+struct MfmaRow;
+template <>
+struct MfmaRow<float> {
+  static __device__ __forceinline__ constexpr int row(int g, int r) { return 4 * g + r; }
+};
+template <>
+struct MfmaRow<double> {
+  static __device__ __forceinline__ constexpr int row(int g, int r) { return g + 4 * r; }
+};
+
+// Each shuffle is taken once, by every lane, before any select: a shuffle
+// evaluated under divergent control flow reads 0 from inactive partner lanes.
 template <typename T>
 __device__ __forceinline__ T wave_max(T v) {
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = v > __shfl_xor(v, o) ? v : __shfl_xor(v, o);
+  for (int o = 32; o >= 1; o >>= 1) {
+    const T w = __shfl_xor(v, o);
+    v = v > w ? v : w;
+  }
   return v;
 }
 

@@ -272,7 +272,8 @@ hipError_t launch_factors(dcflow_batch *bt, hipStream_t s) {
                      p->d_adj_br, p->d_hb, p->ld_h, p->d_ht, p->ld_er, p->n_er, p->d_hdo, p->ld_o,
                      p->d_out, p->d_out_pos, p->n_out, p->d_pos_of_br, bt->d_nsig, bt->d_sig,
                      bt->d_U, bt->d_W, bt->d_kinv, bt->d_invden, bt->d_isl, bt->d_status);
-  return hipGetLastError();
+  DCF_CHECK_LAUNCH();
+  return hipSuccess;
 }
 
 }  // namespace dcflow

@@ -73,7 +73,7 @@ k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
         for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], bq[q], acc, 0, 0, 0);
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) red[wv][4 * g + r][li] = acc[r];
+      for (int r = 0; r < 4; ++r) red[wv][MfmaRow<double>::row(g, r)][li] = acc[r];
       __syncthreads();
       {
         int rt = tid / 16, vt = tid % 16;
@@ -213,19 +213,19 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      const int m = m0 + wm * 64 + a * 16 + 4 * g;
+      const int mb = m0 + wm * 64 + a * 16;
       double o[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) o[r] = (double)acc[a][b][r];
       for (int e = e0; e < e1; ++e) {
         const double ze = z[(size_t)e * vmax + v];
-        const double *ue = U + (size_t)e * ld_er + m;
+        const double *ue = U + (size_t)e * ld_er + mb;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) o[r] += ue[r] * ze;
+        for (int r = 0; r < 4; ++r) o[r] += ue[MfmaRow<T>::row(g, r)] * ze;
       }
-      T *dst = F + (size_t)col * ld_f + m;
+      T *dst = F + (size_t)col * ld_f + mb;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dst[r] = (T)o[r];
+      for (int r = 0; r < 4; ++r) dst[MfmaRow<T>::row(g, r)] = (T)o[r];
     }
   }
 }
@@ -251,6 +251,7 @@ hipError_t run_injections(dcflow_batch *bt, const T *He, const double *inj, int 
   hipLaunchKernelGGL(k_sense, dim3(bt->n_cand), dim3(256), 0, s, bt->d_off, bt->d_kind, bt->d_nsig,
                      bt->d_sig, bt->d_pnew, bt->d_kinv, p->d_hb, p->ld_h, p->n, inj, nvar, shared,
                      bt->d_z, bt->vmax);
+  DCF_CHECK_LAUNCH();
   if (!shared) {
     const int ncols = bt->n_cand * nvar;
     const int n_mt = p->ld_er / BM, n_nt = (ncols + BN - 1) / BN;
@@ -258,6 +259,7 @@ hipError_t run_injections(dcflow_batch *bt, const T *He, const double *inj, int 
     k_gemm<T><<<grid, dim3(256), 0, s>>>(He, p->ld_h, inj, p->n, ncols, nvar, 0, flows, ld_f,
                                          bt->d_off, bt->d_U, p->ld_er, bt->d_z, bt->vmax, 1,
                                          n_mt, n_nt);
+    DCF_CHECK_LAUNCH();
   } else {
     T *f0 = reinterpret_cast<T *>(bt->d_f0);
     const int n_mt = p->ld_er / BM, n_nt = (nvar + BN - 1) / BN;
@@ -265,11 +267,13 @@ hipError_t run_injections(dcflow_batch *bt, const T *He, const double *inj, int 
     k_gemm<T><<<grid, dim3(256), 0, s>>>(He, p->ld_h, inj, p->n, nvar, nvar, 1, f0, ld_f,
                                          bt->d_off, bt->d_U, p->ld_er, bt->d_z, bt->vmax, 0,
                                          n_mt, n_nt);
+    DCF_CHECK_LAUNCH();
     dim3 g2((ld_f + 255) / 256, nvar, bt->n_cand);
     k_bcast<T><<<g2, dim3(256), 0, s>>>(f0, flows, ld_f, nvar, bt->d_off, bt->d_U, p->ld_er,
                                         bt->d_z, bt->vmax);
+    DCF_CHECK_LAUNCH();
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace

@@ -164,7 +164,10 @@ k_scan(const T *__restrict__ F, int ld_f, int nvar, const int32_t *__restrict__ 
             if (!finite_bits(fv)) s_nf[vi] = 1;
             fvs = (T)(fv * inv_r[row]);
           }
-          fs[(size_t)vi * rchunk + rr] = fvs;
+          // position p of each 16-row group holds row (p / 4) + 4 (p % 4): the rows an
+          // FP64 MFMA block leaves in register r of lane group g sit at p = 4g + r
+          const int i16 = rr & 15;
+          fs[(size_t)vi * rchunk + (rr - i16) + (i16 >> 2) + 4 * (i16 & 3)] = fvs;
           const T a = tabs(fvs);
           if (MODE == 0) {
             mx[vi] = tmax(mx[vi], a);
@@ -209,8 +212,10 @@ k_scan(const T *__restrict__ F, int ld_f, int nvar, const int32_t *__restrict__ 
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          const double *src = lsd + (size_t)(rowbase + a * 16 + 4 * g) * ld_o + colbase + b * 16 + li;
-          d4 c4 = {src[0], src[(size_t)ld_o], src[(size_t)2 * ld_o], src[(size_t)3 * ld_o]};
+          const double *src = lsd + (size_t)(rowbase + a * 16) * ld_o + colbase + b * 16 + li;
+          d4 c4;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) c4[r] = src[(size_t)MfmaRow<double>::row(g, r) * ld_o];
           if (k > 0) c4 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a][0], bfr[b][0], c4, 0, 0, 0);
           if (k > 4) c4 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a][1], bfr[b][1], c4, 0, 0, 0);
 #pragma unroll
@@ -252,7 +257,7 @@ k_scan(const T *__restrict__ F, int ld_f, int nvar, const int32_t *__restrict__ 
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const T p = tabs(tfma(L[a][b][r], yc[b], fr[a][r]));
-                const int row = rowbase + a * 16 + 4 * g + r;
+                const int row = rowbase + a * 16 + MfmaRow<double>::row(g, r);
                 if (w != (T)0 && row < n_mon) {
                   const long long key = (long long)(c + 1) * n_mon + row;
                   if (p > bestv || (p == bestv && key < bestk)) {
@@ -364,11 +369,13 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
       flows, ld_f, nvar, bt->d_off, bt->d_U, p->ld_er, bt->d_W, p->ld_o, bt->d_invden, bt->d_isl,
       bt->d_status, p->d_lsd, p->d_inv_r, p->n_mon, p->mon_pad, p->d_out_pos, p->n_out, p->d_mon,
       p->d_out, bt->d_vmax, bt->vmax, out, rc0);
+  DCF_CHECK_LAUNCH();
   k_scan<T, 1, 1><<<dim3(bt->n_cand), dim3(256), lds1, s>>>(
       flows, ld_f, nvar, bt->d_off, bt->d_U, p->ld_er, bt->d_W, p->ld_o, bt->d_invden, bt->d_isl,
       bt->d_status, p->d_lsd, p->d_inv_r, p->n_mon, p->mon_pad, p->d_out_pos, p->n_out, p->d_mon,
       p->d_out, bt->d_vmax, bt->vmax, out, rc1);
-  return hipGetLastError();
+  DCF_CHECK_LAUNCH();
+  return hipSuccess;
 }
 
 }  // namespace
