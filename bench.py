@@ -168,7 +168,7 @@ def main():
                    "n_bus": 1000, "n_branch": 1600, "candidates": w.cands.n_cand,
                    "variants": w.n_var, "contingencies": len(w.out), "monitored": len(w.mon),
                    "loadflows_per_step": n_lf, "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "kernel": "k_scan (N-1 scan + winner pass)",
+        "roofline": {"bound": "alu", "kernel": "k_scan (per-variant N-1 maxima + winner pass)",
                      "achieved": achieved, "peak": PEAK_VALU_FMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_FMA_TFLOPS, "traffic": traffic},
         "phase_ms": {p: {"eval_topologies": float(v["phase_ms"][0]),

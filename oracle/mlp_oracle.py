@@ -1,0 +1,104 @@
+"""FP64 reference of the learned proposal network (test infrastructure only).
+
+TEST INFRASTRUCTURE ONLY: used by the tests, never by the solver library.
+
+The network ranks single-bus-split actions so that the exact solver evaluates
+the most promising first (an addition to the paper, whose optimiser that
+proposes candidates is out of its scope, Sec. III-A).  This module restates it
+plainly so the GPU kernels can be checked:
+
+  * per-action features from the base-case flows of a load snapshot;
+  * a 3-layer perceptron d_in -> 256 -> 256 -> 1 with ReLU;
+  * mean squared error on standardised labels, its gradients by the chain rule;
+  * one Adam step (Kingma & Ba, 2015) with bias correction.
+
+Parity of the gradients is pinned by central finite differences.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+D_MAX = 14            # incident-branch slots per action
+N_SLOT_FEAT = 5       # oriented flow / rating, rating, |flow| / rating, moved bit, present bit
+N_FEAT = 3 + D_MAX * N_SLOT_FEAT + 2   # 75
+D_IN = 96             # padded input width
+
+
+def action_features(n_bus, f, t, flows, rating_all, p, bus, mask, inj_moves, glob2):
+    """Feature vector of one split action (float64 [D_IN]).
+
+    flows: base-case flows of the snapshot on every branch; rating_all: per
+    branch normaliser; p: snapshot injections; glob2: (max N-0 load, max N-1
+    load) of the snapshot's unchanged grid."""
+    inc = np.flatnonzero((np.asarray(f) == bus) | (np.asarray(t) == bus))
+    x = np.zeros(D_IN)
+    x[0] = len(inc)
+    x[1] = p[bus]
+    x[2] = 1.0 if inj_moves else 0.0
+    for q, br in enumerate(inc[:D_MAX]):
+        s = 1.0 if f[br] == bus else -1.0
+        r = rating_all[br]
+        base = 3 + q * N_SLOT_FEAT
+        x[base + 0] = s * flows[br] / r
+        x[base + 1] = r
+        x[base + 2] = abs(flows[br]) / r
+        x[base + 3] = 1.0 if (mask >> q) & 1 else 0.0
+        x[base + 4] = 1.0
+    x[3 + D_MAX * N_SLOT_FEAT + 0] = glob2[0]
+    x[3 + D_MAX * N_SLOT_FEAT + 1] = glob2[1]
+    return x
+
+
+def init_params(rng, d_in=D_IN, h=256):
+    """He-uniform initialisation, FP64."""
+    def lin(fan_in, fan_out):
+        lim = np.sqrt(6.0 / fan_in)
+        return rng.uniform(-lim, lim, (fan_in, fan_out)), np.zeros(fan_out)
+    w1, b1 = lin(d_in, h)
+    w2, b2 = lin(h, h)
+    w3, b3 = lin(h, 1)
+    return dict(w1=w1, b1=b1, w2=w2, b2=b2, w3=w3, b3=b3)
+
+
+def forward(params, x):
+    """Returns (y [B], cache)."""
+    z1 = x @ params["w1"] + params["b1"]
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ params["w2"] + params["b2"]
+    h2 = np.maximum(z2, 0.0)
+    y = (h2 @ params["w3"] + params["b3"])[:, 0]
+    return y, (x, z1, h1, z2, h2)
+
+
+def loss(params, x, target):
+    y, _ = forward(params, x)
+    return float(np.mean((y - target) ** 2))
+
+
+def backward(params, x, target):
+    """Gradients of the mean squared error with respect to every parameter."""
+    y, (x, z1, h1, z2, h2) = forward(params, x)
+    bsz = x.shape[0]
+    dy = (2.0 / bsz) * (y - target)[:, None]          # [B, 1]
+    g = {}
+    g["w3"] = h2.T @ dy
+    g["b3"] = dy.sum(axis=0)
+    dh2 = dy @ params["w3"].T
+    dz2 = dh2 * (z2 > 0)
+    g["w2"] = h1.T @ dz2
+    g["b2"] = dz2.sum(axis=0)
+    dh1 = dz2 @ params["w2"].T
+    dz1 = dh1 * (z1 > 0)
+    g["w1"] = x.T @ dz1
+    g["b1"] = dz1.sum(axis=0)
+    return g
+
+
+def adam_step(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update in place; ``step`` counts from 1."""
+    for k in params:
+        m[k] = beta1 * m[k] + (1.0 - beta1) * grads[k]
+        v[k] = beta2 * v[k] + (1.0 - beta2) * grads[k] ** 2
+        mh = m[k] / (1.0 - beta1 ** step)
+        vh = v[k] / (1.0 - beta2 ** step)
+        params[k] = params[k] - lr * mh / (np.sqrt(vh) + eps)

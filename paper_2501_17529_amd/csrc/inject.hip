@@ -20,6 +20,11 @@ namespace dcflow {
 namespace {
 
 // ---------------------------------------------------------------- sense
+// One workgroup per candidate.  The sensing rows (signed rows of the full PTDF)
+// times the candidate's variants is a small FP64 MFMA product: 16 rows x 16
+// variants per block, K = n_bus split over the 4 waves, 4 independent
+// accumulators per wave (one per K sub-step) so the MFMA chain does not
+// serialise.  Row results are folded into per-element sums h[j][v] in LDS.
 __global__ void __launch_bounds__(256)
 k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
         const int32_t *__restrict__ nsig, const int32_t *__restrict__ sig,
@@ -29,8 +34,8 @@ k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
   __shared__ int rbr[kMaxRank * kMaxSig];
   __shared__ double rsg[kMaxRank * kMaxSig];
   __shared__ int relem[kMaxRank * kMaxSig];
-  __shared__ double hrow[kMaxRank * kMaxSig][16];
   __shared__ double red[4][16][17];
+  __shared__ double hacc[kMaxRank][16];
   __shared__ int s_R;
   const int cand = blockIdx.x;
   const int e0 = off[cand];
@@ -53,6 +58,7 @@ k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
   const int R = s_R;
   const int nch = (n + 15) / 16;
   for (int v0 = 0; v0 < nvar; v0 += 16) {
+    if (tid < kMaxRank * 16) hacc[tid / 16][tid % 16] = 0.0;
     for (int r0 = 0; r0 < R; r0 += 16) {
       const int row = r0 + li;
       const double *hrowp = row < R ? Hb + (size_t)rbr[row] * ld_h : nullptr;
@@ -60,7 +66,9 @@ k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
       const int v = v0 + li;
       const double *xr =
           v < nvar ? X + (size_t)(shared ? v : (size_t)cand * nvar + v) * n : nullptr;
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      d4 acc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
       for (int ch = wv; ch < nch; ch += 4) {
         const int nb = ch * 16 + 4 * g;
         double a[4], bq[4];
@@ -70,15 +78,17 @@ k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
           bq[q] = (xr && nb + q < n) ? xr[nb + q] : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], bq[q], acc, 0, 0, 0);
+        for (int q = 0; q < 4; ++q)
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], bq[q], acc[q], 0, 0, 0);
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) red[wv][MfmaRow<double>::row(g, r)][li] = acc[r];
+      for (int r = 0; r < 4; ++r)
+        red[wv][MfmaRow<double>::row(g, r)][li] = acc[0][r] + acc[1][r] + acc[2][r] + acc[3][r];
       __syncthreads();
-      {
-        int rt = tid / 16, vt = tid % 16;
-        if (r0 + rt < R)
-          hrow[r0 + rt][vt] = red[0][rt][vt] + red[1][rt][vt] + red[2][rt][vt] + red[3][rt][vt];
+      if (tid < 16) {  // thread tid owns variant column tid of hacc
+        for (int rt = 0; rt < 16 && r0 + rt < R; ++rt)
+          hacc[relem[r0 + rt]][tid] += red[0][rt][tid] + red[1][rt][tid] + red[2][rt][tid] +
+                                       red[3][rt][tid];
       }
       __syncthreads();
     }
@@ -86,14 +96,16 @@ k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
       const int v = v0 + tid;
       if (v < nvar) {
         double h[kMaxRank];
-        for (int j = 0; j < kMaxRank; ++j) h[j] = 0.0;
-        for (int r = 0; r < R; ++r) h[relem[r]] += hrow[r][tid];
-        for (int j = 0; j < k; ++j)
-          if (kind[e0 + j] == DCFLOW_SPLIT) h[j] -= pnew[e0 + j];
+#pragma unroll
+        for (int j = 0; j < kMaxRank; ++j)
+          h[j] = j < k ? hacc[j][tid] - (kind[e0 + j] == DCFLOW_SPLIT ? pnew[e0 + j] : 0.0) : 0.0;
         const double *Ki = kinv + (size_t)cand * 64;
-        for (int j = 0; j < k; ++j) {
+#pragma unroll
+        for (int j = 0; j < kMaxRank; ++j) {
+          if (j >= k) break;
           double s = 0.0;
-          for (int i = 0; i < k; ++i) s += Ki[j * 8 + i] * h[i];
+#pragma unroll
+          for (int i = 0; i < kMaxRank; ++i) s += Ki[j * 8 + i] * h[i];   // K^-1 zero-padded
           z[(size_t)(e0 + j) * vmax + v] = s;
         }
       }

@@ -65,7 +65,7 @@ k_scan(const T *__restrict__ F, int ld_f, int nvar, const int32_t *__restrict__ 
        const double *__restrict__ inv_r, int n_mon, int mon_pad,
        const int32_t *__restrict__ out_pos, int n_out, const int32_t *__restrict__ mon,
        const int32_t *__restrict__ out, double *__restrict__ vmaxbuf, int vmax_ld,
-       dcflow_score *__restrict__ res, int rchunk) {
+       dcflow_score *__restrict__ res, int rchunk, int single) {
   constexpr int TM = 64, TN = ScanCfg<T>::TN, NB = TN / 16;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   T *ys = reinterpret_cast<T *>(smem_raw);       // [VC][ld_o]
@@ -95,7 +95,8 @@ k_scan(const T *__restrict__ F, int ld_f, int nvar, const int32_t *__restrict__ 
     for (int i = 0; i < VC; ++i) vlist[i] = vbeg + i < nvar ? vbeg + i : -1;
     nv = min(VC, nvar - vbeg);
   } else {
-    if (tid == 0) {
+    if (tid == 0 && single) s_vstar = 0;
+    if (tid == 0 && !single) {
       int best = 0;
       double bv = vmaxbuf[(size_t)cand * vmax_ld];
       bool any_inf = !finite_bits(bv);
@@ -143,6 +144,8 @@ k_scan(const T *__restrict__ F, int ld_f, int nvar, const int32_t *__restrict__ 
   T mx[VC];
 #pragma unroll
   for (int i = 0; i < VC; ++i) mx[i] = (T)0;
+  // winner pass: running maximum, the lowest (contingency, branch) key
+  // attaining it (N-0 rows first: key = row), and the overload sum
   T bestv = (T)-1;
   long long bestk = 0x7fffffffffffffffLL;
   double ov = 0.0;
@@ -248,26 +251,50 @@ k_scan(const T *__restrict__ F, int ld_f, int nvar, const int32_t *__restrict__ 
               }
           mx[vi] = m;
         } else {
+          T pv[4][NB][4];
+          T m = (T)0;
 #pragma unroll
           for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-              const int c = colbase + b * 16 + li;
-              const T w = colw[c];
+            for (int b = 0; b < NB; ++b)
 #pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const T p = tabs(tfma(L[a][b][r], yc[b], fr[a][r]));
-                const int row = rowbase + a * 16 + MfmaRow<double>::row(g, r);
-                if (w != (T)0 && row < n_mon) {
+              for (int r = 0; r < 4; r += 2) {
+                pv[a][b][r] = tfma(L[a][b][r], yc[b], fr[a][r]);
+                pv[a][b][r + 1] = tfma(L[a][b][r + 1], yc[b], fr[a][r + 1]);
+                m = absmax3(m, pv[a][b][r], pv[a][b][r + 1]);
+              }
+          if (m > (T)1) {  // overloads in this lane's part of the tile
+            T o = (T)0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+              for (int b = 0; b < NB; ++b) {
+                const T w = colw[colbase + b * 16 + li];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                  o = tfma(w, tmax(tabs(pv[a][b][r]) - (T)1, (T)0), o);
+              }
+            ov += (double)o;
+          }
+          if (m >= bestv) {  // a new (or tied) maximum in this tile: locate it
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+              for (int b = 0; b < NB; ++b) {
+                const int c = colbase + b * 16 + li;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  const int row = rowbase + a * 16 + MfmaRow<double>::row(g, r);
                   const long long key = (long long)(c + 1) * n_mon + row;
-                  if (p > bestv || (p == bestv && key < bestk)) {
-                    bestv = p;
+                  const T av = tabs(pv[a][b][r]);
+                  if (colw[c] != (T)0 && row < n_mon &&
+                      (av > bestv || (av == bestv && key < bestk))) {
+                    bestv = av;
                     bestk = key;
                   }
-                  ov += fmax((double)p - 1.0, 0.0);
                 }
               }
-            }
+          }
         }
       }
     }
@@ -287,17 +314,16 @@ k_scan(const T *__restrict__ F, int ld_f, int nvar, const int32_t *__restrict__ 
       vmaxbuf[(size_t)cand * vmax_ld + blockIdx.y * VC + tid] = m;  // variant vbeg + tid
     }
   } else {
-    // (max, lowest key) across the wave, then across waves
+    // (max, lowest key) across the wave, then across waves; overload sum
     double bv = (double)bestv;
     long long bk = bestk;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
-      double ov2 = __shfl_xor(bv, o);
-      long long ok2 = __shfl_xor(bk, o);
-      if (ov2 > bv || (ov2 == bv && ok2 < bk)) {
-        bv = ov2;
-        bk = ok2;
-      }
+      const double ov2 = __shfl_xor(bv, o);
+      const long long ok2 = __shfl_xor(bk, o);
+      const bool take = ov2 > bv || (ov2 == bv && ok2 < bk);
+      bv = take ? ov2 : bv;
+      bk = take ? ok2 : bk;
     }
     double os = wave_sum(ov);
     if (lane == 0) {
@@ -327,15 +353,17 @@ k_scan(const T *__restrict__ F, int ld_f, int nvar, const int32_t *__restrict__ 
         r.worst_branch = -1;
         r.worst_outage = -1;
       } else {
-        const int c = (int)(k2 / n_mon) - 1;
-        const int row = (int)(k2 % n_mon);
+        const bool found = k2 != 0x7fffffffffffffffLL;
+        const int c = found ? (int)(k2 / n_mon) - 1 : -1;
+        const int row = found ? (int)(k2 % n_mon) : -1;
         r.max_load = s_nf[0] == 1 ? __builtin_inf() : b2;
         r.overload_sum = osum;
         r.best_variant = vlist[0];
-        r.worst_branch = mon[row];
+        r.worst_branch = found ? mon[row] : -1;
         r.worst_outage = c >= 0 ? out[c] : -1;
       }
       res[cand] = r;
+      if (single) vmaxbuf[(size_t)cand * vmax_ld] = r.max_load;
     }
   }
 }
@@ -365,15 +393,18 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   dim3 g0(bt->n_cand, (nvar + VC - 1) / VC);
   const size_t lds0 = scan_lds<T, VC>(p->ld_o, rc0, 0);
   const size_t lds1 = scan_lds<T, 1>(p->ld_o, rc1, 1);
-  k_scan<T, VC, 0><<<g0, dim3(256), lds0, s>>>(
-      flows, ld_f, nvar, bt->d_off, bt->d_U, p->ld_er, bt->d_W, p->ld_o, bt->d_invden, bt->d_isl,
-      bt->d_status, p->d_lsd, p->d_inv_r, p->n_mon, p->mon_pad, p->d_out_pos, p->n_out, p->d_mon,
-      p->d_out, bt->d_vmax, bt->vmax, out, rc0);
-  DCF_CHECK_LAUNCH();
+  const int single = nvar == 1;  // one variant: the winner pass alone gives everything
+  if (!single) {
+    k_scan<T, VC, 0><<<g0, dim3(256), lds0, s>>>(
+        flows, ld_f, nvar, bt->d_off, bt->d_U, p->ld_er, bt->d_W, p->ld_o, bt->d_invden,
+        bt->d_isl, bt->d_status, p->d_lsd, p->d_inv_r, p->n_mon, p->mon_pad, p->d_out_pos,
+        p->n_out, p->d_mon, p->d_out, bt->d_vmax, bt->vmax, out, rc0, 0);
+    DCF_CHECK_LAUNCH();
+  }
   k_scan<T, 1, 1><<<dim3(bt->n_cand), dim3(256), lds1, s>>>(
       flows, ld_f, nvar, bt->d_off, bt->d_U, p->ld_er, bt->d_W, p->ld_o, bt->d_invden, bt->d_isl,
       bt->d_status, p->d_lsd, p->d_inv_r, p->n_mon, p->mon_pad, p->d_out_pos, p->n_out, p->d_mon,
-      p->d_out, bt->d_vmax, bt->vmax, out, rc1);
+      p->d_out, bt->d_vmax, bt->vmax, out, rc1, single);
   DCF_CHECK_LAUNCH();
   return hipSuccess;
 }
