@@ -212,6 +212,73 @@ const double *dcflow_batch_variant_max(const dcflow_batch *batch);
 
 const char *dcflow_strerror(int status);
 
+/* ---------------------------------------------------------------------------
+ * Learned proposal network (an addition: the paper leaves the optimiser that
+ * proposes candidates out of scope, Sec. III-A).  A 96 -> 256 -> 256 -> 1 ReLU
+ * perceptron scores single-bus-split actions; the exact screen verifies the
+ * best-scored ones and exhaustive screening stays the fallback and judge.
+ * All pointers are device pointers; buffers are caller-owned.
+ * ------------------------------------------------------------------------- */
+#define DCFLOW_MLP_DIN 96     /* feature width (75 used, rest zero)            */
+#define DCFLOW_MLP_HIDDEN 256
+#define DCFLOW_TOPK_MAX 1024
+
+/* Number of FP32 parameters: w1 [96][256], b1 [256], w2 [256][256], b2 [256],
+ * w3 [256], b3 [1], 3 floats of padding (this order, one flat array). */
+int dcflow_mlp_param_count(void);
+/* Bytes of the BF16 weight copies used by dcflow_mlp_infer. */
+size_t dcflow_mlp_bf16_bytes(void);
+/* Bytes of training/forward workspace for a batch of `batch` samples. */
+size_t dcflow_mlp_workspace_bytes(int32_t batch);
+
+/* Base-case flows of load snapshots on every branch (Eq. ptdf_times_nodal_inj):
+ * inj [n_snap][n_bus] -> flows [n_snap][n_branch]; n0max [n_snap] (or NULL)
+ * receives the largest N-0 load |p|/r over the monitored branches. */
+int dcflow_snapshot_flows(const dcflow_plan *plan, const double *inj, int32_t n_snap,
+                          double *flows, double *n0max, hipStream_t stream);
+
+/* Feature vectors [n_act][96] (FP32) of split actions: action a splits bus
+ * bus[a] with mask[a] (incident-branch bits as in dcflow_cands) in snapshot
+ * snap[a]; side[a] != 0 moves the bus injection to the new busbar.  worst
+ * [n_snap][2] = (monitored branch id l*, contingency branch id c* or -1) of the
+ * snapshot's unchanged grid; rho = PTDF[l*,:] + LODF[l*,c*] PTDF[c*,:] (Def.
+ * eq_lodf) is the critical flow's sensitivity to injections.  Features:
+ * degree, bus injection, side bit, rho[bus]; per incident branch (ascending
+ * id, up to 14): flow oriented out of the bus / r, moved bit, present bit,
+ * sigma = rho[bus] - rho[far end], sigma * oriented flow / r(l*), with
+ * r = rating_scale |F_base| + rating_offset; then glob[2 s], glob[2 s + 1]. */
+int dcflow_action_features(const dcflow_plan *plan, const double *flows, const double *inj,
+                           const double *glob, const int32_t *worst, int32_t n_act,
+                           const int32_t *snap, const int32_t *bus, const uint32_t *mask,
+                           const int32_t *side, float *feat, hipStream_t stream);
+
+/* FP32 forward pass y [n] of x [n][96] (ws >= dcflow_mlp_workspace_bytes(n)). */
+int dcflow_mlp_forward(const float *params, const float *x, int32_t n, float *y, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+/* Gradient of the mean squared error mean((y - t)^2) over a batch: grad has
+ * the parameter layout; loss [1] receives the batch loss. */
+int dcflow_mlp_grad(const float *params, const float *x, const float *t, int32_t batch,
+                    float *grad, float *loss, void *ws, size_t ws_bytes, hipStream_t stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 master weights;
+ * m, v are the moment buffers (zero before step 1); step counts from 1. */
+int dcflow_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t step, float lr,
+                    hipStream_t stream);
+/* BF16 copies of w1, w2 for inference (bf16 >= dcflow_mlp_bf16_bytes()). */
+int dcflow_mlp_pack_bf16(const float *params, void *bf16, hipStream_t stream);
+/* Fused inference on BF16 MFMA with FP32 accumulation: y [n] for x [n][96]. */
+int dcflow_mlp_infer(const float *params, const void *bf16, const float *x, int32_t n, float *y,
+                     hipStream_t stream);
+/* Per-column mean and 1 / standard deviation (floored at 1e-6) of x [rows][cols]. */
+int dcflow_column_stats(const float *x, int32_t rows, int32_t cols, float *mean, float *inv_std,
+                        hipStream_t stream);
+/* In place: x[i][j] = (x[i][j] - mean[j]) * inv_std[j]. */
+int dcflow_standardize(float *x, int64_t rows, int32_t cols, const float *mean,
+                       const float *inv_std, hipStream_t stream);
+/* Indices of the k smallest of scores [n] (ties: lowest index), in ascending
+ * (score, index) order; 1 <= k <= min(n, DCFLOW_TOPK_MAX). */
+int dcflow_topk_smallest(const float *scores, int32_t n, int32_t k, int32_t *idx,
+                         hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,33 +19,48 @@ from __future__ import annotations
 import numpy as np
 
 D_MAX = 14            # incident-branch slots per action
-N_SLOT_FEAT = 5       # oriented flow / rating, rating, |flow| / rating, moved bit, present bit
-N_FEAT = 3 + D_MAX * N_SLOT_FEAT + 2   # 75
+N_SLOT_FEAT = 5       # oriented flow / r, moved bit, present bit, sigma, sigma * flow / r*
+N_FEAT = 4 + D_MAX * N_SLOT_FEAT + 2   # 76
 D_IN = 96             # padded input width
 
 
-def action_features(n_bus, f, t, flows, rating_all, p, bus, mask, inj_moves, glob2):
+def critical_row(h, f, t, l_star, c_star):
+    """Sensitivity of the critical post-contingency flow to nodal injections:
+    PTDF[l*, :] + LODF[l*, c*] PTDF[c*, :] (Def. eq_lodf, Eq. lodf_delta applied
+    to the PTDF); c* = -1 means the N-0 case (row l* alone)."""
+    if c_star < 0:
+        return h[l_star].copy()
+    d = h[:, f[c_star]] - h[:, t[c_star]]
+    lw = d[l_star] / (1.0 - d[c_star])
+    return h[l_star] + lw * h[c_star]
+
+
+def action_features(n_bus, f, t, flows, rating_all, p, bus, mask, inj_moves, glob2, rho, r_star):
     """Feature vector of one split action (float64 [D_IN]).
 
     flows: base-case flows of the snapshot on every branch; rating_all: per
     branch normaliser; p: snapshot injections; glob2: (max N-0 load, max N-1
-    load) of the snapshot's unchanged grid."""
+    load) of the snapshot's unchanged grid; rho: critical_row(...) of its worst
+    case, r_star the normaliser of that case's monitored branch."""
     inc = np.flatnonzero((np.asarray(f) == bus) | (np.asarray(t) == bus))
     x = np.zeros(D_IN)
     x[0] = len(inc)
     x[1] = p[bus]
     x[2] = 1.0 if inj_moves else 0.0
+    x[3] = rho[bus]
     for q, br in enumerate(inc[:D_MAX]):
-        s = 1.0 if f[br] == bus else -1.0
-        r = rating_all[br]
-        base = 3 + q * N_SLOT_FEAT
-        x[base + 0] = s * flows[br] / r
-        x[base + 1] = r
-        x[base + 2] = abs(flows[br]) / r
-        x[base + 3] = 1.0 if (mask >> q) & 1 else 0.0
-        x[base + 4] = 1.0
-    x[3 + D_MAX * N_SLOT_FEAT + 0] = glob2[0]
-    x[3 + D_MAX * N_SLOT_FEAT + 1] = glob2[1]
+        leaves = f[br] == bus
+        far = t[br] if leaves else f[br]
+        fo = (1.0 if leaves else -1.0) * flows[br]
+        sig = rho[bus] - rho[far]
+        base = 4 + q * N_SLOT_FEAT
+        x[base + 0] = fo / rating_all[br]
+        x[base + 1] = 1.0 if (mask >> q) & 1 else 0.0
+        x[base + 2] = 1.0
+        x[base + 3] = sig
+        x[base + 4] = sig * fo / r_star
+    x[4 + D_MAX * N_SLOT_FEAT + 0] = glob2[0]
+    x[4 + D_MAX * N_SLOT_FEAT + 1] = glob2[1]
     return x
 
 

@@ -276,6 +276,8 @@ int dcflow_build_ptdf(const dcflow_grid_desc *g, void *dev_ws, size_t ws_bytes, 
   p->ld_er = d.ld_er;
   p->ld_o = d.ld_o;
   p->mon_pad = d.mon_pad;
+  p->rating_scale = g->rating ? 1.2 : g->rating_scale;
+  p->rating_offset = g->rating ? 0.1 : g->rating_offset;
   p->f.assign(g->from, g->from + d.m);
   p->t.assign(g->to, g->to + d.m);
   p->adj_off = host_adj_off(g);

@@ -32,6 +32,7 @@ struct dcflow_plan {
   int ld_er;   // rows kept, rounded up to the GEMM M tile (128); U, F, Ht stride
   int ld_o;    // contingency columns rounded up to 64 (>= 64)
   int mon_pad; // monitored rows rounded up to 64
+  double rating_scale, rating_offset;  // rating rule (also the feature normaliser)
   // device arrays (all inside the workspace)
   int32_t *d_f, *d_t, *d_adj_off, *d_adj_br;
   double *d_b;

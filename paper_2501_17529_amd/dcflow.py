@@ -83,6 +83,19 @@ def _load():
         "dcflow_n1_score": (ctypes.c_int, [P, P, I32, ctypes.c_int, P, P]),
         "dcflow_batch_variant_max": (P, [P]),
         "dcflow_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "dcflow_mlp_param_count": (ctypes.c_int, []),
+        "dcflow_mlp_bf16_bytes": (SZ, []),
+        "dcflow_mlp_workspace_bytes": (SZ, [I32]),
+        "dcflow_snapshot_flows": (ctypes.c_int, [P, P, I32, P, P, P]),
+        "dcflow_action_features": (ctypes.c_int, [P, P, P, P, P, I32, P, P, P, P, P, P]),
+        "dcflow_mlp_forward": (ctypes.c_int, [P, P, I32, P, P, SZ, P]),
+        "dcflow_mlp_grad": (ctypes.c_int, [P, P, P, I32, P, P, P, SZ, P]),
+        "dcflow_mlp_adam": (ctypes.c_int, [P, P, P, P, I32, ctypes.c_float, P]),
+        "dcflow_mlp_pack_bf16": (ctypes.c_int, [P, P, P]),
+        "dcflow_mlp_infer": (ctypes.c_int, [P, P, P, I32, P, P]),
+        "dcflow_column_stats": (ctypes.c_int, [P, I32, I32, P, P, P]),
+        "dcflow_standardize": (ctypes.c_int, [P, ctypes.c_int64, I32, P, P, P]),
+        "dcflow_topk_smallest": (ctypes.c_int, [P, I32, I32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -96,7 +109,11 @@ EXPORTED = ("dcflow_plan_workspace_bytes", "dcflow_build_ptdf", "dcflow_plan_vie
             "dcflow_plan_destroy", "dcflow_validate_candidates", "dcflow_batch_bytes",
             "dcflow_batch_create", "dcflow_batch_destroy", "dcflow_eval_topologies",
             "dcflow_flow_bytes", "dcflow_eval_injections", "dcflow_n1_score",
-            "dcflow_batch_variant_max", "dcflow_strerror")
+            "dcflow_batch_variant_max", "dcflow_strerror", "dcflow_mlp_param_count",
+            "dcflow_mlp_bf16_bytes", "dcflow_mlp_workspace_bytes", "dcflow_snapshot_flows",
+            "dcflow_action_features", "dcflow_mlp_forward", "dcflow_mlp_grad", "dcflow_mlp_adam",
+            "dcflow_mlp_pack_bf16", "dcflow_mlp_infer", "dcflow_column_stats",
+            "dcflow_standardize", "dcflow_topk_smallest")
 
 
 def _check(rc, what, bad=None):

@@ -19,7 +19,7 @@ def d():
 
 def test_header_symbols_exported(d):
     hdr = open(os.path.join(ROOT, "include", "dcflow.h")).read()
-    declared = set(re.findall(r"^(?:int|void|const char \*|const double \*)\s*(dcflow_[a-z0-9_]+)\(",
+    declared = set(re.findall(r"^(?:int|void|size_t|const char \*|const double \*)\s*(dcflow_[a-z0-9_]+)\(",
                               hdr, flags=re.M))
     assert declared, "no declarations found"
     for name in declared:

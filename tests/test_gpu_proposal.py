@@ -1,0 +1,221 @@
+"""GPU tests of the learned proposal: the library's training and inference
+kernels against the FP64 reference MLP, and what the trained network gains
+over random selection when the exact solver may evaluate only 512 actions."""
+import numpy as np
+import pytest
+
+import gridgen as G
+from oracle import dcflow_oracle as O
+from oracle import mlp_oracle as M
+
+from _gpu_common import gpu_available, say
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _params_np(prop):
+    p = prop.params.cpu().numpy().astype(np.float64)
+    din, h = 96, 256
+    o = 0
+    w1 = p[o:o + din * h].reshape(din, h); o += din * h
+    b1 = p[o:o + h]; o += h
+    w2 = p[o:o + h * h].reshape(h, h); o += h * h
+    b2 = p[o:o + h]; o += h
+    w3 = p[o:o + h].reshape(h, 1); o += h
+    b3 = p[o:o + 1]
+    return dict(w1=w1, b1=b1, w2=w2, b2=b2, w3=w3, b3=b3)
+
+
+def _flat(d):
+    return np.concatenate([d["w1"].ravel(), d["b1"], d["w2"].ravel(), d["b2"], d["w3"].ravel(),
+                           d["b3"], np.zeros(3)])
+
+
+@pytest.fixture(scope="module")
+def medium():
+    from paper_2501_17529_amd import dcflow as D
+    w = G.workload_medium(0, n_cand=4, n_var=1)
+    return w, D.Plan.from_workload(w)
+
+
+def test_grad_forward_adam_match_reference(medium):
+    import torch
+    from paper_2501_17529_amd import proposal as PR
+    _, plan = medium
+    say("mlp grad/forward/adam parity")
+    prop = PR.Proposal(plan, seed=3)
+    rng = np.random.default_rng(4)
+    B = 96
+    x = rng.normal(size=(B, 96)).astype(np.float32)
+    t = rng.normal(size=B).astype(np.float32)
+    xd = torch.from_numpy(x).cuda()
+    td = torch.from_numpy(t).cuda()
+    ref = _params_np(prop)
+    # forward
+    y = prop.forward_fp32(xd).cpu().numpy()
+    yr, _ = M.forward(ref, x.astype(np.float64))
+    assert np.abs(y - yr).max() <= 1e-4 * max(1.0, np.abs(yr).max())
+    # gradients
+    import ctypes
+    from paper_2501_17529_amd import dcflow as D
+    ws = torch.empty(D._lib.dcflow_mlp_workspace_bytes(B), dtype=torch.uint8, device="cuda")
+    D._check(D._lib.dcflow_mlp_grad(PR._ptr(prop.params), PR._ptr(xd), PR._ptr(td), B,
+                                    PR._ptr(prop.grad), PR._ptr(prop.loss), PR._ptr(ws),
+                                    ws.numel(), D._stream()), "grad")
+    g = prop.grad.cpu().numpy().astype(np.float64)
+    gr = _flat(M.backward(ref, x.astype(np.float64), t.astype(np.float64)))
+    for name, sl in (("w1", slice(0, 96 * 256)), ("w2", slice(96 * 256 + 256, 96 * 256 + 256 + 65536)),
+                     ("all", slice(0, len(gr)))):
+        err = np.linalg.norm(g[sl] - gr[sl]) / np.linalg.norm(gr[sl])
+        assert err <= 1e-4, (name, err)
+    assert abs(prop.loss.item() - M.loss(ref, x.astype(np.float64), t)) <= 1e-4 * M.loss(
+        ref, x.astype(np.float64), t)
+    # two Adam steps against the reference update
+    mr = {k: np.zeros_like(v) for k, v in ref.items()}
+    vr = {k: np.zeros_like(v) for k, v in ref.items()}
+    for step in (1, 2):
+        D._check(D._lib.dcflow_mlp_adam(PR._ptr(prop.params), PR._ptr(prop.grad), PR._ptr(prop.m),
+                                        PR._ptr(prop.v), step, ctypes.c_float(1e-3), D._stream()),
+                 "adam")
+        gd = M.backward(ref, x.astype(np.float64), t.astype(np.float64)) if step == 1 else gd
+        M.adam_step(ref, gd, mr, vr, step, lr=1e-3)
+    got = prop.params.cpu().numpy().astype(np.float64)
+    assert np.abs(got - _flat(ref)).max() <= 1e-5
+
+
+def test_bf16_inference_close_to_fp32(medium):
+    import torch
+    from paper_2501_17529_amd import proposal as PR
+    _, plan = medium
+    say("bf16 fused inference")
+    prop = PR.Proposal(plan, seed=5)
+    rng = np.random.default_rng(6)
+    n = 1000   # ragged: not a multiple of the 64-action tile
+    x = torch.from_numpy(rng.normal(size=(n, 96)).astype(np.float32)).cuda()
+    prop.pack()
+    yb = prop.infer(x).cpu().numpy()
+    yr, _ = M.forward(_params_np(prop), x.cpu().numpy().astype(np.float64))
+    err = np.abs(yb - yr).max() / np.abs(yr).std()
+    say(f"bf16 max error / output std = {err:.3e}")
+    assert err <= 5e-2
+    assert np.corrcoef(yb, yr)[0, 1] > 0.999
+
+
+def test_features_match_reference(medium):
+    import torch
+    from paper_2501_17529_amd import proposal as PR
+    w, plan = medium
+    g = w.grid
+    say("action features")
+    rng = np.random.default_rng(7)
+    xs = G.perturbed_injections(g, rng, (2,), 0.2)
+    prop = PR.Proposal(plan)
+    x_dev, flows, glob = prop.snapshot_summary(xs)
+    bus, mask, side = PR.enumerate_actions(g)
+    pick = rng.choice(len(bus), size=300, replace=False)
+    snap = rng.integers(0, 2, size=300).astype(np.int32)
+    feat = prop.features(x_dev, flows, glob, snap, bus[pick], mask[pick], side[pick]).cpu().numpy()
+    fb = O.dc_flows(g.n_bus, g.f, g.t, g.b, g.slack, g.p)[0]
+    r_all = w.rating_scale * np.abs(fb) + w.rating_offset
+    fl = O.dc_flows(g.n_bus, g.f, g.t, g.b, g.slack, xs)
+    gl = glob.cpu().numpy()
+    h = O.ptdf(g.n_bus, g.f, g.t, g.b, g.slack)
+    worst = prop.worst_host
+    rho = [M.critical_row(h, g.f, g.t, int(worst[s, 0]), int(worst[s, 1])) for s in range(2)]
+    for q, a in enumerate(pick):
+        sn = snap[q]
+        ref = M.action_features(g.n_bus, g.f, g.t, fl[sn], r_all, xs[sn], int(bus[a]),
+                                int(mask[a]), bool(side[a]), gl[sn], rho[sn],
+                                r_all[int(worst[sn, 0])])
+        np.testing.assert_allclose(feat[q], ref, rtol=2e-6, atol=2e-6)
+    # the global features: N-0 maximum from the oracle, N-1 maximum from the exact screen
+    r = O.ratings(g.n_bus, g.f, g.t, g.b, g.slack, g.p, w.mon)
+    n0 = (np.abs(fl[:, w.mon]) / r).max(axis=1)
+    np.testing.assert_allclose(gl[:, 0], n0, rtol=1e-9)
+    for s in range(2):
+        o = O.score_candidate(g.n_bus, g.f, g.t, g.b, g.slack, [], xs[s], w.mon, w.out, r)
+        assert abs(gl[s, 1] - o["best_max_load"]) <= 1e-6
+        assert (worst[s, 0], worst[s, 1]) == (o["worst_branch"], o["worst_outage"])
+
+
+def test_topk_and_standardize():
+    import torch
+    from paper_2501_17529_amd import dcflow as D
+    from paper_2501_17529_amd import proposal as PR
+    say("top-k and standardisation")
+    rng = np.random.default_rng(8)
+    for n, k in ((50000, 512), (1000, 1000), (777, 1), (4096, 1024)):
+        s = rng.normal(size=n).astype(np.float32)
+        s[::7] = np.round(s[::7], 1)          # plenty of exact ties
+        idx = PR.topk_smallest(torch.from_numpy(s).cuda(), k).cpu().numpy()
+        ref = np.lexsort((np.arange(n), s))[:k]
+        np.testing.assert_array_equal(idx, ref)
+    x = rng.normal(3.0, 2.0, size=(5000, 96)).astype(np.float32)
+    xd = torch.from_numpy(x).cuda()
+    mu = torch.empty(96, device="cuda")
+    isd = torch.empty(96, device="cuda")
+    D._check(D._lib.dcflow_column_stats(PR._ptr(xd), 5000, 96, PR._ptr(mu), PR._ptr(isd),
+                                        D._stream()), "stats")
+    np.testing.assert_allclose(mu.cpu().numpy(), x.mean(axis=0), rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(isd.cpu().numpy(), 1.0 / x.std(axis=0), rtol=1e-5)
+    D._check(D._lib.dcflow_standardize(PR._ptr(xd), 5000, 96, PR._ptr(mu), PR._ptr(isd),
+                                       D._stream()), "std")
+    z = xd.cpu().numpy()
+    np.testing.assert_allclose(z.mean(axis=0), 0.0, atol=1e-4)
+
+
+def test_proposal_gain_over_random(medium):
+    """Train on 9 load snapshots (about 200k solver-labelled pairs), then on 2
+    held-out snapshots let the exact solver evaluate only the network's top-512
+    actions vs 512 random ones; the exhaustive screen is the judge."""
+    import torch
+    from paper_2501_17529_amd import proposal as PR
+    w, plan = medium
+    g = w.grid
+    rng = np.random.default_rng(9)
+    n_train, n_test = 9, 2
+    xs = G.perturbed_injections(g, rng, (n_train + n_test,), 0.2)
+    bus, mask, side = PR.enumerate_actions(g)
+    na = len(bus)
+    say(f"proposal gain: {na} actions per snapshot")
+    labels = np.stack([PR.exact_scores(plan, PR.action_candidates(bus, mask, side, xs[s]), xs[s])
+                       for s in range(n_train + n_test)])
+    prop = PR.Proposal(plan, seed=1)
+    x_dev, flows, glob = prop.snapshot_summary(xs)
+    # training pairs in one shuffled order (contiguous minibatches)
+    snap = np.repeat(np.arange(n_train, dtype=np.int32), na)
+    act = np.tile(np.arange(na), n_train)
+    y = labels[:n_train].reshape(-1)
+    ok = np.isfinite(y)
+    perm = rng.permutation(np.flatnonzero(ok))
+    snap, act, y = snap[perm], act[perm], y[perm]
+    say(f"training pairs: {len(y)}")
+    feat = prop.features(x_dev, flows, glob, snap, bus[act], mask[act], side[act])
+    yt = torch.from_numpy(y.astype(np.float32)).cuda()
+    prop.set_standardization(feat, yt)
+    prop.standardize(feat, yt)
+    losses = prop.train(feat, yt, epochs=8, batch=1024, lr=1e-3)
+    say(f"training loss per epoch: {np.round(losses, 4).tolist()}")
+    assert losses[-1] < 0.5 * losses[0]
+    prop.pack()
+    gaps_net, gaps_rand, recalls = [], [], []
+    for s in range(n_train, n_train + n_test):
+        ls = labels[s]
+        f = prop.features(x_dev, flows, glob, np.full(na, s, np.int32), bus, mask, side)
+        prop.standardize(f)
+        score = prop.infer(f)
+        top = PR.topk_smallest(score, 512).cpu().numpy()
+        # exact verification of the proposed 512 (the judge's labels are the exhaustive screen)
+        ver = PR.exact_scores(plan, PR.action_candidates(bus[top], mask[top], side[top], xs[s]), xs[s])
+        np.testing.assert_allclose(ver, ls[top], rtol=0, atol=1e-9)
+        best = np.min(ls[np.isfinite(ls)])
+        rnd = rng.choice(na, size=512, replace=False)
+        gaps_net.append(float(np.min(ver) - best))
+        gaps_rand.append(float(np.min(ls[rnd]) - best))
+        top10 = np.argsort(np.where(np.isfinite(ls), ls, np.inf), kind="stable")[:10]
+        recalls.append(len(set(top10.tolist()) & set(top.tolist())) / 10.0)
+    say(f"gap to exhaustive best: network {gaps_net}, random {gaps_rand}; "
+        f"recall of exhaustive top-10 in network top-512: {recalls}")
+    assert np.mean(gaps_net) <= np.mean(gaps_rand)
+    assert np.mean(recalls) >= 0.3

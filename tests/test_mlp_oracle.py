@@ -49,16 +49,32 @@ def test_feature_vector_by_hand():
     flows = np.array([0.5, -0.25, 0.75])
     r = np.array([1.0, 2.0, 4.0])
     p = np.array([-1.0, 0.25, 0.75])
-    x = M.action_features(3, f, t, flows, r, p, 1, 0b10, True, (0.3, 0.9))
+    rho = np.array([0.0, 0.6, 0.2])
+    x = M.action_features(3, f, t, flows, r, p, 1, 0b10, True, (0.3, 0.9), rho, 2.0)
     assert x.shape == (M.D_IN,)
-    assert (x[0], x[1], x[2]) == (2.0, 0.25, 1.0)
-    # slot 0 = branch 0 (leaves bus 1): oriented flow 0.5 / 1
-    np.testing.assert_allclose(x[3:8], [0.5, 1.0, 0.5, 0.0, 1.0])
-    # slot 1 = branch 1 (leaves bus 1), moved
-    np.testing.assert_allclose(x[8:13], [-0.125, 2.0, 0.125, 1.0, 1.0])
-    assert np.all(x[13:3 + M.D_MAX * M.N_SLOT_FEAT] == 0)
-    np.testing.assert_allclose(x[73:75], [0.3, 0.9])
-    assert np.all(x[75:] == 0)
+    assert (x[0], x[1], x[2], x[3]) == (2.0, 0.25, 1.0, 0.6)
+    # slot 0 = branch 0 (leaves bus 1 towards 0): flow 0.5 / 1, sigma 0.6 - 0.0
+    np.testing.assert_allclose(x[4:9], [0.5, 0.0, 1.0, 0.6, 0.6 * 0.5 / 2.0])
+    # slot 1 = branch 1 (leaves bus 1 towards 2), moved: flow -0.25 / 2, sigma 0.6 - 0.2
+    np.testing.assert_allclose(x[9:14], [-0.125, 1.0, 1.0, 0.4, 0.4 * -0.25 / 2.0])
+    assert np.all(x[14:4 + M.D_MAX * M.N_SLOT_FEAT] == 0)
+    np.testing.assert_allclose(x[74:76], [0.3, 0.9])
+    assert np.all(x[76:] == 0)
+
+
+def test_critical_row_is_post_contingency_sensitivity():
+    # the critical row equals the PTDF row of l* in the grid without c* (brute force)
+    from oracle import dcflow_oracle as O
+    import gridgen as G
+    g = G.make_grid(14, 22, 2)
+    h = O.ptdf(g.n_bus, g.f, g.t, g.b, g.slack)
+    nb = np.flatnonzero(~O.bridges(g.n_bus, g.f, g.t))
+    l_star, c_star = int(nb[0]), int(nb[3])
+    keep = np.arange(g.n_branch) != c_star
+    h2 = O.ptdf(g.n_bus, g.f[keep], g.t[keep], g.b[keep], g.slack)
+    row = M.critical_row(h, g.f, g.t, l_star, c_star)
+    np.testing.assert_allclose(row, h2[np.flatnonzero(keep) == l_star][0], atol=1e-12)
+    np.testing.assert_allclose(M.critical_row(h, g.f, g.t, l_star, -1), h[l_star])
 
 
 def test_training_reduces_loss():
