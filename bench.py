@@ -122,8 +122,8 @@ def main():
     ap.add_argument("--prec", choices=["both", "fp32", "fp64"], default="both")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(candidates would shard across GPUs with no communication; see DESIGN.md)",
+        print("bench.py runs on one GPU only: there is no multi-GPU path here "
+              "(candidates would shard across GPUs with no communication)",
               file=sys.stderr)
         sys.exit(2)
 

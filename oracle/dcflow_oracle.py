@@ -23,7 +23,7 @@ for topology optimization"):
     agg_m = maximum relative branch load, t_i* = argmin over the injection
     variants (Eq. solver_end_to_end).
 
-Readings where the paper is silent (each also listed in the design doc):
+Readings where the paper is silent:
   * the new busbar of the j-th split of a candidate is node n_bus + j;
   * the slack absorbs any imbalance (its injection is minus the sum of the
     others), which leaves all flows unchanged since its PTDF column is zero;

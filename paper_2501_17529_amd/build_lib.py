@@ -17,8 +17,12 @@ SOURCES = ["abi.hip", "build.hip", "factors.hip", "inject.hip", "score.hip", "ml
            "mlp_abi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
-         # packed FP32 VALU forms are disabled on purpose
+         # packed FP32 VALU forms are kept off: every kernel is written for the
+         # unpacked FP32 FMA / max instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # MFMA sources and results in ordinary VGPRs (no AGPR copies): the scan
+         # consumes each L~ block with VALU instructions right after it is built
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wno-unused-result"]
 
 

@@ -126,6 +126,7 @@ void plan_layout(dcflow_plan *p, const Dims &d, Arena &a) {
   p->d_he32 = a.take<float>((size_t)d.ld_er * d.ld_h);
   p->d_hdo = a.take<double>((size_t)d.m * d.ld_o);
   p->d_lsd = a.take<double>((size_t)d.mon_pad * d.ld_o);
+  p->d_lsd32 = a.take<float>((size_t)d.mon_pad * d.ld_o);
   p->d_fbase = a.take<double>(d.m);
   p->d_pbase = a.take<double>(d.ld_h);
   p->d_rating = a.take<double>(d.mon_pad);

@@ -168,6 +168,23 @@ __global__ void k_lsd(double *lsd, int ld_o, const double *hdo, const int32_t *m
   lsd[(size_t)i * ld_o + c] = v;
 }
 
+// FP32 copy of Lsd in the accumulator order of the FP32 16x16x4 MFMA, so that the
+// scan seeds each block with one 16-byte load per lane.
+__global__ void k_lsd32(float *dst, const double *lsd, int ld_o, int mon_pad) {
+  const int ncb = ld_o / 16;
+  const size_t total = (size_t)(mon_pad / 16) * ncb * kWave;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int lane = (int)(idx % kWave);
+  const size_t blk = idx / kWave;
+  const int cb = (int)(blk % ncb), rb = (int)(blk / ncb);
+  const int row0 = rb * 16 + 4 * (lane / 16), col = cb * 16 + lane % 16;
+  f4 v;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = (float)lsd[(size_t)(row0 + r) * ld_o + col];
+  reinterpret_cast<f4 *>(dst)[idx] = v;
+}
+
 inline unsigned nblk(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -220,6 +237,9 @@ hipError_t launch_build(dcflow_plan *p, hipStream_t s, const double *h_rating, d
   hipLaunchKernelGGL(k_lsd, dim3(nblk(p->ld_o, 256), p->mon_pad), dim3(256), 0, s, p->d_lsd,
                      p->ld_o, p->d_hdo, p->d_mon, p->n_mon, p->d_out, p->n_out, p->d_inv_r,
                      p->mon_pad);
+  DCF_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_lsd32, dim3(nblk((size_t)p->mon_pad * p->ld_o / 4, 256)), dim3(256), 0, s,
+                     p->d_lsd32, p->d_lsd, p->ld_o, p->mon_pad);
   DCF_CHECK_LAUNCH();
   return hipSuccess;
 }

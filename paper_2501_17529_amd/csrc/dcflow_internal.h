@@ -45,6 +45,8 @@ struct dcflow_plan {
   float *d_he32;    // [ld_er][ld_h] same in FP32
   double *d_hdo;    // [m][ld_o] PTDF[:, f_c] - PTDF[:, t_c]
   double *d_lsd;    // [mon_pad][ld_o] (hdo[mon] - [mon == out]) / rating
+  float *d_lsd32;   // same in FP32, fragment-major: 16 x 16 blocks [mon_pad/16][ld_o/16], each
+                    // 64 lanes x 4 rows in the FP32 MFMA accumulator order (rows 4 (lane/16) + r)
   double *d_fbase;  // [m]
   double *d_pbase;  // [ld_h]
   double *d_rating; // [mon_pad]

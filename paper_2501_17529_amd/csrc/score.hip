@@ -12,11 +12,20 @@
 //     L~ = (H_O[E_m, :] - [l == c]) / r  +  (U / r) W      (LODF' numerators, -den on the diagonal)
 //     y[c, v] = F'[c, v] / den_c                         (0 for islanding / removed c)
 //
-// L~ is built per 16 x 16 block on the matrix cores: one FP64 MFMA
-// (16x16x4, two when k > 4) with the shared seed Lsd as the accumulator input,
-// U/r as A and W as B.  The block stays in registers (converted to T) and is
-// reused for every variant of the chunk; the variants' F~ and y are staged in
-// LDS.  The scan is VALU work: one FMA plus an absolute max per element.
+// L~ is built per 16 x 16 block on the matrix cores, with the shared seed Lsd as
+// the accumulator input, U/r as A and W as B (k <= 4: one MFMA, k <= 8: two).
+// The FP32 path seeds from an FP32 copy of Lsd stored in accumulator order (one
+// 16-byte load per lane and block) and uses the FP32 16x16x4 MFMA; the FP64
+// path uses FP64 Lsd and the FP64 16x16x4 MFMA.  A 64-row tile stays in
+// registers and is reused for every variant of the launch; the variants' F~ and
+// y are staged in LDS.  The scan is VALU work: one FMA plus half a three-way
+// absolute maximum per element.
+//
+// Pass 1 (k_scan_max) writes the per-variant maxima.  Pass 2 (k_scan_win)
+// rescans the winning variant once: overload sum, running maximum per lane and
+// the tile where each lane first reached it; only the tiles that hold the final
+// maximum are built a third time to find the lowest (contingency, branch) key.
+// Both passes build tiles with the same code, so the maxima agree bit for bit.
 #include "dcflow_internal.h"
 
 namespace dcflow {
@@ -32,6 +41,7 @@ __device__ __forceinline__ double tabs(double x) { return __builtin_fabs(x); }
 __device__ __forceinline__ float tmax(float a, float b) { return __builtin_fmaxf(a, b); }
 __device__ __forceinline__ double tmax(double a, double b) { return __builtin_fmax(a, b); }
 __device__ __forceinline__ float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 // max(m, |a|, |b|) in one VALU instruction (the compiler does not fold the abs
 // modifiers into v_max3_f32 on its own).  Inputs are FMA results (canonical).
 __device__ __forceinline__ float absmax3(float m, float a, float b) {
@@ -42,7 +52,41 @@ __device__ __forceinline__ float absmax3(float m, float a, float b) {
 __device__ __forceinline__ double absmax3(double m, double a, double b) {
   return __builtin_fmax(__builtin_fmax(m, __builtin_fabs(a)), __builtin_fabs(b));
 }
-__device__ __forceinline__ double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// running maximum of non-negative values in LDS: their IEEE bit patterns order
+// like the values, so an unsigned integer atomic max suffices
+__device__ __forceinline__ void lds_max_nonneg(float *p, float v) {
+  atomicMax(reinterpret_cast<unsigned int *>(p), __float_as_uint(v));
+}
+__device__ __forceinline__ void lds_max_nonneg(double *p, double v) {
+  atomicMax(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+// kernel arguments shared by both passes
+struct ScanArgs {
+  const void *F;  // [n_cand][nvar][ld_f] flows of the kept rows (T)
+  int ld_f, nvar;
+  const int32_t *off;
+  const double *U;  // [n_elem][ld_er]
+  int ld_er;
+  const double *W;  // [n_elem][ld_o]
+  int ld_o;
+  const double *invden;   // [n_cand][ld_o]
+  const uint32_t *isl;    // [n_cand][ld_o / 32]
+  const uint32_t *status; // [n_cand]
+  const double *lsd;      // [mon_pad][ld_o]
+  const float *lsd32;     // fragment-major FP32 copy
+  const double *inv_r;    // [mon_pad]
+  int n_mon, mon_pad;
+  const int32_t *out_pos;
+  int n_out;
+  const int32_t *mon, *out;
+  double *vmax;  // [n_cand][vmax_ld]
+  int vmax_ld;
+  dcflow_score *res;
+  int rchunk;  // rows per LDS chunk (multiple of 64)
+  int single;  // one variant: pass 2 alone
+};
 
 template <typename T>
 struct ScanCfg;
@@ -55,176 +99,181 @@ struct ScanCfg<double> {
   static constexpr int TN = 32;
 };
 
-// MODE 0: per-variant maxima for variants [vbeg, vbeg + VC).  MODE 1: winner pass.
-template <typename T, int VC, int MODE>
-__global__ void __launch_bounds__(256)
-k_scan(const T *__restrict__ F, int ld_f, int nvar, const int32_t *__restrict__ off,
-       const double *__restrict__ U, int ld_er, const double *__restrict__ W, int ld_o,
-       const double *__restrict__ invden, const uint32_t *__restrict__ isl,
-       const uint32_t *__restrict__ status, const double *__restrict__ lsd,
-       const double *__restrict__ inv_r, int n_mon, int mon_pad,
-       const int32_t *__restrict__ out_pos, int n_out, const int32_t *__restrict__ mon,
-       const int32_t *__restrict__ out, double *__restrict__ vmaxbuf, int vmax_ld,
-       dcflow_score *__restrict__ res, int rchunk, int single) {
+// Position of chunk row rr in the staged F~ array: the rows that a block leaves
+// in register r of lane group g must sit at 16-row offset 4 g + r.
+__device__ __forceinline__ int fs_pos(float *, int rr) { return rr; }
+__device__ __forceinline__ int fs_pos(double *, int rr) {
+  const int i16 = rr & 15;
+  return (rr - i16) + (i16 >> 2) + 4 * (i16 & 3);
+}
+
+// A (U / r) and B (W) fragments of k-step h: lane group g supplies element
+// 4 h + g.  Every lane loads from a valid element (k >= 1) and zeroes the
+// fragment past k, so the loads are unconditional and issue together.
+template <typename T, int NB>
+__device__ __forceinline__ void update_frags(T (&af)[4], T (&bfr)[NB], const ScanArgs &A, int e0,
+                                             int k, int h, int rowbase, int colbase, int g, int li) {
+  const int e = h * 4 + g;
+  const int es = e0 + (e < k ? e : k - 1);
+  const double *u = A.U + (size_t)es * A.ld_er;
+  const double *w = A.W + (size_t)es * A.ld_o;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int row = rowbase + a * 16 + li;
+    const double v = u[row] * A.inv_r[row];
+    af[a] = e < k ? (T)v : (T)0;
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const double v = w[colbase + b * 16 + li];
+    bfr[b] = e < k ? (T)v : (T)0;
+  }
+}
+
+// L~ for the 64 x 64 tile at (rowbase, colbase), FP32 matrix cores.  The 16
+// seed blocks are loaded first, then the one or two MFMA k-steps run.
+__device__ __forceinline__ void build_tile(float (&L)[4][4][4], const ScanArgs &A, int e0, int k,
+                                           int rowbase, int colbase, int g, int li, int lane) {
+  const f4 *seed = reinterpret_cast<const f4 *>(A.lsd32) +
+                   ((size_t)(rowbase / 16) * (A.ld_o / 16) + colbase / 16) * kWave + lane;
+  const size_t rstride = (size_t)(A.ld_o / 16) * kWave;
+  f4 c[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) c[a][b] = seed[a * rstride + b * kWave];
+  for (int h = 0; h * 4 < k; ++h) {  // wave-uniform: one step for k <= 4, two for k <= 8
+    float af[4], bfr[4];
+    update_frags(af, bfr, A, e0, k, h, rowbase, colbase, g, li);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        c[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a], bfr[b], c[a][b], 0, 0, 0);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) L[a][b][r] = c[a][b][r];
+}
+
+// L~ for the 64 x 32 tile at (rowbase, colbase), FP64 matrix cores.
+__device__ __forceinline__ void build_tile(double (&L)[4][2][4], const ScanArgs &A, int e0, int k,
+                                           int rowbase, int colbase, int g, int li, int lane) {
+  d4 c[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const double *src = A.lsd + (size_t)(rowbase + a * 16) * A.ld_o + colbase + b * 16 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) c[a][b][r] = src[(size_t)MfmaRow<double>::row(g, r) * A.ld_o];
+    }
+  for (int h = 0; h * 4 < k; ++h) {
+    double af[4], bfr[2];
+    update_frags(af, bfr, A, e0, k, h, rowbase, colbase, g, li);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bfr[b], c[a][b], 0, 0, 0);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) L[a][b][r] = c[a][b][r];
+  (void)lane;
+}
+
+// F~ of monitored row `row` for one variant (the same expression in every pass)
+template <typename T>
+__device__ __forceinline__ T ftilde(const T *Fv, const double *inv_r, int row, int n_mon,
+                                    bool &nonfinite) {
+  if (row >= n_mon) return (T)0;
+  const double fv = (double)Fv[row];
+  if (!finite_bits(fv)) nonfinite = true;
+  return (T)(fv * inv_r[row]);
+}
+
+// y = F'[c] / den_c
+template <typename T>
+__device__ __forceinline__ T ycol(const T *Fv, const ScanArgs &A, int cand, int c, bool &nonfinite) {
+  if (c >= A.n_out) return (T)0;
+  const double fv = (double)Fv[A.out_pos[c]];
+  if (!finite_bits(fv)) nonfinite = true;
+  return (T)(fv * A.invden[(size_t)cand * A.ld_o + c]);
+}
+
+// ---------------------------------------------------------------- pass 1
+template <typename T, int VC, int MINW>
+__global__ void __launch_bounds__(256, MINW) k_scan_max(ScanArgs A) {
   constexpr int TM = 64, TN = ScanCfg<T>::TN, NB = TN / 16;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-  T *ys = reinterpret_cast<T *>(smem_raw);       // [VC][ld_o]
-  T *fs = ys + (size_t)VC * ld_o;                // [VC][rchunk]
-  T *colw = fs + (size_t)VC * rchunk;            // [ld_o] (winner pass)
+  const int ld_o = A.ld_o, rchunk = A.rchunk;
+  T *ys = reinterpret_cast<T *>(smem_raw);  // [VC][ld_o]
+  T *fs = ys + (size_t)VC * ld_o;           // [VC][rchunk]
   __shared__ double s_red[4][VC];
-  __shared__ long long s_key[4];
-  __shared__ double s_ov[4];
+  __shared__ T s_n0[VC];
   __shared__ int s_nf[VC];
-  __shared__ int s_vstar;
 
   const int cand = blockIdx.x;
   const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, g = lane / 16, li = lane % 16;
-  const int e0 = off[cand];
-  const int k = off[cand + 1] - e0;
-  const uint32_t st = status[cand];
-
-  if (tid < VC) s_nf[tid] = 0;
+  const int e0 = A.off[cand];
+  const int k = A.off[cand + 1] - e0;
+  const uint32_t st = A.status[cand];
+  const int vbeg = blockIdx.y * VC;
+  const int nv = min(VC, A.nvar - vbeg);
+  if (st & DCFLOW_ST_DISCONNECTED) {
+    if (tid < nv) A.vmax[(size_t)cand * A.vmax_ld + vbeg + tid] = __builtin_inf();
+    return;
+  }
+  if (tid < VC) {
+    s_nf[tid] = 0;
+    s_n0[tid] = (T)0;
+  }
   __syncthreads();
+  const T *F = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vbeg) * A.ld_f;
 
-  // variants of this launch
-  int vlist[VC];
-  int nv = 0;
-  if (MODE == 0) {
-    const int vbeg = blockIdx.y * VC;
-#pragma unroll
-    for (int i = 0; i < VC; ++i) vlist[i] = vbeg + i < nvar ? vbeg + i : -1;
-    nv = min(VC, nvar - vbeg);
-  } else {
-    if (tid == 0 && single) s_vstar = 0;
-    if (tid == 0 && !single) {
-      int best = 0;
-      double bv = vmaxbuf[(size_t)cand * vmax_ld];
-      bool any_inf = !finite_bits(bv);
-      for (int v = 1; v < nvar; ++v) {
-        double x = vmaxbuf[(size_t)cand * vmax_ld + v];
-        any_inf |= !finite_bits(x);
-        if (x < bv) {
-          bv = x;
-          best = v;
-        }
-      }
-      s_vstar = best;
-      // a variant whose flows were not finite was given +inf by the first pass
-      if (any_inf && !(st & DCFLOW_ST_DISCONNECTED)) s_nf[0] = 2;
-    }
-    __syncthreads();
-    vlist[0] = s_vstar;
-    nv = 1;
+  // y for every contingency column and variant of the launch; a non-finite
+  // flow marks its variant in s_nf at once (rare, so not kept in registers)
+  for (int vi = 0; vi < nv; ++vi) {
+    bool nf = false;
+    for (int c = tid; c < ld_o; c += blockDim.x)
+      ys[(size_t)vi * ld_o + c] = ycol(F + (size_t)vi * A.ld_f, A, cand, c, nf);
+    if (nf) s_nf[vi] = 1;
   }
 
-  // stage y = F'[c] / den_c for all contingencies
-#pragma unroll
-  for (int vi = 0; vi < VC; ++vi) {
-    if (vi < nv) {
-      const T *Fv = F + ((size_t)cand * nvar + vlist[vi]) * ld_f;
-      for (int c = tid; c < ld_o; c += blockDim.x) {
-        T y = (T)0;
-        if (c < n_out) {
-          const double fv = (double)Fv[out_pos[c]];
-          if (!finite_bits(fv)) s_nf[vi] = 1;
-          y = (T)(fv * invden[(size_t)cand * ld_o + c]);
-        }
-        ys[(size_t)vi * ld_o + c] = y;
-      }
-    }
-  }
-  if (MODE == 1) {
-    for (int c = tid; c < ld_o; c += blockDim.x) {
-      bool valid = c < n_out && !((isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
-      colw[c] = valid ? (T)1 : (T)0;
-    }
-  }
-
-  // per-lane running results
   T mx[VC];
 #pragma unroll
   for (int i = 0; i < VC; ++i) mx[i] = (T)0;
-  // winner pass: running maximum, the lowest (contingency, branch) key
-  // attaining it (N-0 rows first: key = row), and the overload sum
-  T bestv = (T)-1;
-  long long bestk = 0x7fffffffffffffffLL;
-  double ov = 0.0;
 
   const int ntc = ld_o / TN;
-  for (int rc0 = 0; rc0 < mon_pad; rc0 += rchunk) {
-    const int rows = min(rchunk, mon_pad - rc0);
+  for (int rc0 = 0; rc0 < A.mon_pad; rc0 += rchunk) {
+    const int rows = min(rchunk, A.mon_pad - rc0);
     __syncthreads();
-    // stage F~ = F' / r for the monitored rows of this chunk (N-0 loads)
-#pragma unroll
-    for (int vi = 0; vi < VC; ++vi) {
-      if (vi < nv) {
-        const T *Fv = F + ((size_t)cand * nvar + vlist[vi]) * ld_f;
-        for (int rr = tid; rr < rows; rr += blockDim.x) {
-          const int row = rc0 + rr;
-          T fvs = (T)0;
-          if (row < n_mon) {
-            const double fv = (double)Fv[row];
-            if (!finite_bits(fv)) s_nf[vi] = 1;
-            fvs = (T)(fv * inv_r[row]);
-          }
-          // position p of each 16-row group holds row (p / 4) + 4 (p % 4): the rows an
-          // FP64 MFMA block leaves in register r of lane group g sit at p = 4g + r
-          const int i16 = rr & 15;
-          fs[(size_t)vi * rchunk + (rr - i16) + (i16 >> 2) + 4 * (i16 & 3)] = fvs;
-          const T a = tabs(fvs);
-          if (MODE == 0) {
-            mx[vi] = tmax(mx[vi], a);
-          } else if (row < n_mon) {
-            if (a > bestv || (a == bestv && (long long)row < bestk)) {
-              bestv = a;
-              bestk = row;
-            }
-            ov += fmax((double)a - 1.0, 0.0);
-          }
-        }
-      }
+    // F~ of this chunk's rows; the N-0 loads enter the maxima here
+    // (every thread takes a share of the variant x row pairs; the N-0 maxima
+    // are kept in LDS by integer atomics on the non-negative bit patterns)
+    for (int i = tid; i < nv * rows; i += blockDim.x) {
+      const int vi = i / rows, rr = i - vi * rows;
+      bool nf = false;
+      const T fv = ftilde(F + (size_t)vi * A.ld_f, A.inv_r, rc0 + rr, A.n_mon, nf);
+      fs[(size_t)vi * rchunk + fs_pos(fs, rr)] = fv;
+      lds_max_nonneg(&s_n0[vi], tabs(fv));
+      if (nf) s_nf[vi] = 1;
     }
     __syncthreads();
 
-    const int ntr = rows / TM;
-    for (int tile = wv; tile < ntr * ntc; tile += 4) {
+    const int nt = (rows / TM) * ntc;
+    for (int tile = wv; tile < nt; tile += 4) {
       const int tr = tile / ntc, tc = tile - tr * ntc;
       const int rowbase = rc0 + tr * TM, colbase = tc * TN;
-      // A (U / r) and B (W) fragments of the k-column update
-      double af[4][2], bfr[NB][2];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int row = rowbase + a * 16 + li;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int e = h * 4 + g;
-          af[a][h] = e < k ? U[(size_t)(e0 + e) * ld_er + row] * inv_r[row] : 0.0;
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int col = colbase + b * 16 + li;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int e = h * 4 + g;
-          bfr[b][h] = e < k ? W[(size_t)(e0 + e) * ld_o + col] : 0.0;
-        }
-      }
       T L[4][NB][4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          const double *src = lsd + (size_t)(rowbase + a * 16) * ld_o + colbase + b * 16 + li;
-          d4 c4;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) c4[r] = src[(size_t)MfmaRow<double>::row(g, r) * ld_o];
-          if (k > 0) c4 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a][0], bfr[b][0], c4, 0, 0, 0);
-          if (k > 4) c4 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a][1], bfr[b][1], c4, 0, 0, 0);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) L[a][b][r] = (T)c4[r];
-        }
-      // scan the variants
+      build_tile(L, A, e0, k, rowbase, colbase, g, li, lane);
 #pragma unroll
       for (int vi = 0; vi < VC; ++vi) {
         if (vi >= nv) continue;
@@ -237,174 +286,337 @@ k_scan(const T *__restrict__ F, int ld_f, int nvar, const int32_t *__restrict__ 
           for (int r = 0; r < 4; ++r) fr[a][r] = fsv[a * 16 + r];
 #pragma unroll
         for (int b = 0; b < NB; ++b) yc[b] = ysv[b * 16];
-        if (MODE == 0) {
-          T m = mx[vi];
+        T m = mx[vi];
 #pragma unroll
-          for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
+          for (int b = 0; b < NB; ++b)
 #pragma unroll
-              for (int r = 0; r < 4; r += 2) {
-                const T p0 = tfma(L[a][b][r], yc[b], fr[a][r]);
-                const T p1 = tfma(L[a][b][r + 1], yc[b], fr[a][r + 1]);
-                m = absmax3(m, p0, p1);
-              }
-          mx[vi] = m;
-        } else {
-          T pv[4][NB][4];
-          T m = (T)0;
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-#pragma unroll
-              for (int r = 0; r < 4; r += 2) {
-                pv[a][b][r] = tfma(L[a][b][r], yc[b], fr[a][r]);
-                pv[a][b][r + 1] = tfma(L[a][b][r + 1], yc[b], fr[a][r + 1]);
-                m = absmax3(m, pv[a][b][r], pv[a][b][r + 1]);
-              }
-          if (m > (T)1) {  // overloads in this lane's part of the tile
-            T o = (T)0;
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-              for (int b = 0; b < NB; ++b) {
-                const T w = colw[colbase + b * 16 + li];
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                  o = tfma(w, tmax(tabs(pv[a][b][r]) - (T)1, (T)0), o);
-              }
-            ov += (double)o;
-          }
-          if (m >= bestv) {  // a new (or tied) maximum in this tile: locate it
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-              for (int b = 0; b < NB; ++b) {
-                const int c = colbase + b * 16 + li;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                  const int row = rowbase + a * 16 + MfmaRow<double>::row(g, r);
-                  const long long key = (long long)(c + 1) * n_mon + row;
-                  const T av = tabs(pv[a][b][r]);
-                  if (colw[c] != (T)0 && row < n_mon &&
-                      (av > bestv || (av == bestv && key < bestk))) {
-                    bestv = av;
-                    bestk = key;
-                  }
-                }
-              }
-          }
-        }
+            for (int r = 0; r < 4; r += 2) {
+              const T p0 = tfma(L[a][b][r], yc[b], fr[a][r]);
+              const T p1 = tfma(L[a][b][r + 1], yc[b], fr[a][r + 1]);
+              m = absmax3(m, p0, p1);
+            }
+        mx[vi] = m;
       }
     }
   }
 
-  // ---- reductions
-  if (MODE == 0) {
 #pragma unroll
-    for (int i = 0; i < VC; ++i) {
-      T m = wave_max(mx[i]);
-      if (lane == 0) s_red[wv][i] = (double)m;
+  for (int i = 0; i < VC; ++i) {
+    const T m = wave_max(mx[i]);
+    if (lane == 0) s_red[wv][i] = (double)m;
+  }
+  __syncthreads();
+  if (tid < nv) {
+    double m = fmax(fmax(s_red[0][tid], s_red[1][tid]), fmax(s_red[2][tid], s_red[3][tid]));
+    m = fmax(m, (double)s_n0[tid]);
+    if (s_nf[tid]) m = __builtin_inf();
+    A.vmax[(size_t)cand * A.vmax_ld + vbeg + tid] = m;
+  }
+}
+
+// ---------------------------------------------------------------- pass 2
+template <typename T>
+__global__ void __launch_bounds__(256) k_scan_win(ScanArgs A) {
+  constexpr int TM = 64, TN = ScanCfg<T>::TN, NB = TN / 16;
+  constexpr long long kNoKey = 0x7fffffffffffffffLL;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  const int ld_o = A.ld_o, rchunk = A.rchunk;
+  T *ys = reinterpret_cast<T *>(smem_raw);  // [ld_o]
+  T *colw = ys + ld_o;                      // [ld_o] 1 for scored contingencies
+  T *fs = colw + ld_o;                      // [rchunk]
+  __shared__ double s_m0[4], s_m1[4], s_ov[4];
+  __shared__ long long s_key[4];
+  __shared__ int s_nf, s_vstar;
+
+  const int cand = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, g = lane / 16, li = lane % 16;
+  const int e0 = A.off[cand];
+  const int k = A.off[cand + 1] - e0;
+  const uint32_t st = A.status[cand];
+  if (st & DCFLOW_ST_DISCONNECTED) {
+    if (tid == 0) {
+      dcflow_score r;
+      r.max_load = __builtin_inf();
+      r.overload_sum = 0.0;
+      r.best_variant = -1;
+      r.worst_branch = -1;
+      r.worst_outage = -1;
+      r.status = st;
+      A.res[cand] = r;
+      if (A.single) A.vmax[(size_t)cand * A.vmax_ld] = r.max_load;
+    }
+    return;
+  }
+
+  // winning variant: argmin of the pass-1 maxima (the lowest index on ties)
+  if (tid == 0) {
+    int best = 0, nfl = 0;
+    if (!A.single) {
+      double bv = A.vmax[(size_t)cand * A.vmax_ld];
+      bool any_inf = !finite_bits(bv);
+      for (int v = 1; v < A.nvar; ++v) {
+        const double x = A.vmax[(size_t)cand * A.vmax_ld + v];
+        any_inf |= !finite_bits(x);
+        if (x < bv) {
+          bv = x;
+          best = v;
+        }
+      }
+      // a variant whose flows were not finite was given +inf by pass 1
+      if (any_inf) nfl = 2;
+    }
+    s_vstar = best;
+    s_nf = nfl;
+  }
+  __syncthreads();
+  const int vstar = s_vstar;
+  const T *Fv = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vstar) * A.ld_f;
+  bool nf = false;
+  for (int c = tid; c < ld_o; c += blockDim.x) {
+    ys[c] = ycol(Fv, A, cand, c, nf);
+    const bool valid =
+        c < A.n_out && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
+    colw[c] = valid ? (T)1 : (T)0;
+  }
+
+  // N-0 rows: maximum and the lowest row attaining it
+  T b0 = (T)-1;
+  int k0 = 0x7fffffff;
+  // N-1: running maximum per lane, the first tile where it was reached, and
+  // whether a later tile reached it again
+  T run = (T)-1;
+  int first = -1, tie = 0;
+  double ov = 0.0;
+
+  const int ntc = ld_o / TN;
+  for (int rc0 = 0; rc0 < A.mon_pad; rc0 += rchunk) {
+    const int rows = min(rchunk, A.mon_pad - rc0);
+    __syncthreads();
+    for (int rr = tid; rr < rows; rr += blockDim.x) {
+      const int row = rc0 + rr;
+      const T fv = ftilde(Fv, A.inv_r, row, A.n_mon, nf);
+      fs[fs_pos(fs, rr)] = fv;
+      if (row < A.n_mon) {
+        const T a = tabs(fv);
+        if (a > b0) {  // rows are visited in increasing order per thread
+          b0 = a;
+          k0 = row;
+        }
+        ov += fmax((double)a - 1.0, 0.0);
+      }
     }
     __syncthreads();
-    if (tid < nv) {
-      double m = fmax(fmax(s_red[0][tid], s_red[1][tid]), fmax(s_red[2][tid], s_red[3][tid]));
-      if (s_nf[tid] || (st & DCFLOW_ST_DISCONNECTED)) m = __builtin_inf();
-      vmaxbuf[(size_t)cand * vmax_ld + blockIdx.y * VC + tid] = m;  // variant vbeg + tid
-    }
-  } else {
-    // (max, lowest key) across the wave, then across waves; overload sum
-    double bv = (double)bestv;
-    long long bk = bestk;
+
+    const int nt = (rows / TM) * ntc;
+    for (int tile = wv; tile < nt; tile += 4) {
+      const int tr = tile / ntc, tc = tile - tr * ntc;
+      const int rowbase = rc0 + tr * TM, colbase = tc * TN;
+      const int tid_tile = (rowbase / TM) * ntc + tc;
+      T L[4][NB][4];
+      build_tile(L, A, e0, k, rowbase, colbase, g, li, lane);
+      const T *fsv = fs + (rowbase - rc0) + 4 * g;
+      T fr[4][4], yc[NB];
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      const double ov2 = __shfl_xor(bv, o);
-      const long long ok2 = __shfl_xor(bk, o);
-      const bool take = ov2 > bv || (ov2 == bv && ok2 < bk);
-      bv = take ? ov2 : bv;
-      bk = take ? ok2 : bk;
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) fr[a][r] = fsv[a * 16 + r];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) yc[b] = ys[colbase + b * 16 + li];
+      T pv[4][NB][4];
+      T mt = (T)0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; r += 2) {
+            pv[a][b][r] = tfma(L[a][b][r], yc[b], fr[a][r]);
+            pv[a][b][r + 1] = tfma(L[a][b][r + 1], yc[b], fr[a][r + 1]);
+            mt = absmax3(mt, pv[a][b][r], pv[a][b][r + 1]);
+          }
+      const bool gt = mt > run;
+      tie = gt ? 0 : (mt == run ? 1 : tie);
+      first = gt ? tid_tile : first;
+      run = gt ? mt : run;
+      if (mt > (T)1) {  // overloads in this lane's part of the tile
+        T o = (T)0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const T w = colw[colbase + b * 16 + li];
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) o = tfma(w, tmax(tabs(pv[a][b][r]) - (T)1, (T)0), o);
+        }
+        ov += (double)o;
+      }
     }
-    double os = wave_sum(ov);
+  }
+
+  // ---- maxima: N-0 and N-1 over the block
+  {
+    const T w0 = wave_max(b0), w1 = wave_max(run);
+    const double os = wave_sum(ov);
     if (lane == 0) {
-      s_red[wv][0] = bv;
-      s_key[wv] = bk;
+      s_m0[wv] = (double)w0;
+      s_m1[wv] = (double)w1;
       s_ov[wv] = os;
     }
-    __syncthreads();
-    if (tid == 0) {
-      double b2 = s_red[0][0];
-      long long k2 = s_key[0];
-      double osum = s_ov[0];
-      for (int w = 1; w < 4; ++w) {
-        if (s_red[w][0] > b2 || (s_red[w][0] == b2 && s_key[w] < k2)) {
-          b2 = s_red[w][0];
-          k2 = s_key[w];
+    if (nf) s_nf = 1;
+  }
+  __syncthreads();
+  const T M0 = (T)fmax(fmax(s_m0[0], s_m0[1]), fmax(s_m0[2], s_m0[3]));
+  const T M1 = (T)fmax(fmax(s_m1[0], s_m1[1]), fmax(s_m1[2], s_m1[3]));
+
+  // ---- lowest key attaining the maximum: N-0 rows first (key = row), then
+  // contingency-major (key = (c + 1) n_mon + row)
+  long long bestk = kNoKey;
+  if (M0 >= M1) {
+    bestk = b0 == M0 ? (long long)k0 : kNoKey;
+  } else {
+    const int ntall = (A.mon_pad / TM) * ntc;
+    // a lane that reached the maximum again in a later tile may hide a lower
+    // key anywhere: then the wave rebuilds every tile (rare exact ties)
+    const bool want = run == M1;
+    const bool all = __any(want && tie);
+    bool done = !want;
+    int t = all ? 0 : -1;
+    while (true) {
+      if (!all) {
+        int c = done ? 0x7fffffff : first;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+          const int w = __shfl_xor(c, o);
+          c = w < c ? w : c;
         }
-        osum += s_ov[w];
+        if (c == 0x7fffffff) break;
+        t = c;
+        done = done || first == t;
+      } else if (t >= ntall) {
+        break;
       }
-      dcflow_score r;
-      uint32_t stat = st | (s_nf[0] ? DCFLOW_ST_NONFINITE : 0u);
-      r.status = stat;
-      if (st & DCFLOW_ST_DISCONNECTED) {
-        r.max_load = __builtin_inf();
-        r.overload_sum = 0.0;
-        r.best_variant = -1;
-        r.worst_branch = -1;
-        r.worst_outage = -1;
-      } else {
-        const bool found = k2 != 0x7fffffffffffffffLL;
-        const int c = found ? (int)(k2 / n_mon) - 1 : -1;
-        const int row = found ? (int)(k2 % n_mon) : -1;
-        r.max_load = s_nf[0] == 1 ? __builtin_inf() : b2;
-        r.overload_sum = osum;
-        r.best_variant = vlist[0];
-        r.worst_branch = found ? mon[row] : -1;
-        r.worst_outage = c >= 0 ? out[c] : -1;
-      }
-      res[cand] = r;
-      if (single) vmaxbuf[(size_t)cand * vmax_ld] = r.max_load;
+      const int tr = t / ntc, tc = t - tr * ntc;
+      const int rowbase = tr * TM, colbase = tc * TN;
+      T L[4][NB][4];
+      build_tile(L, A, e0, k, rowbase, colbase, g, li, lane);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rowbase + a * 16 + MfmaRow<T>::row(g, r);
+          bool dummy = false;
+          const T fv = ftilde(Fv, A.inv_r, row, A.n_mon, dummy);
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const int c = colbase + b * 16 + li;
+            const T p = tfma(L[a][b][r], ys[c], fv);
+            const long long key = (long long)(c + 1) * A.n_mon + row;
+            if (tabs(p) == M1 && colw[c] != (T)0 && row < A.n_mon && key < bestk) bestk = key;
+          }
+        }
+      if (all) ++t;
     }
   }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const long long w = __shfl_xor(bestk, o);
+    bestk = w < bestk ? w : bestk;
+  }
+  if (lane == 0) s_key[wv] = bestk;
+  __syncthreads();
+  if (tid == 0) {
+    long long k2 = s_key[0];
+    for (int w = 1; w < 4; ++w) k2 = s_key[w] < k2 ? s_key[w] : k2;
+    const double osum = s_ov[0] + s_ov[1] + s_ov[2] + s_ov[3];
+    const double M = (double)(M0 > M1 ? M0 : M1);
+    dcflow_score r;
+    r.status = st | (s_nf ? DCFLOW_ST_NONFINITE : 0u);
+    const bool found = k2 != kNoKey;
+    const int c = found ? (int)(k2 / A.n_mon) - 1 : -1;
+    const int row = found ? (int)(k2 % A.n_mon) : -1;
+    r.max_load = s_nf == 1 ? __builtin_inf() : M;
+    r.overload_sum = osum;
+    r.best_variant = vstar;
+    r.worst_branch = found ? A.mon[row] : -1;
+    r.worst_outage = c >= 0 ? A.out[c] : -1;
+    A.res[cand] = r;
+    if (A.single) A.vmax[(size_t)cand * A.vmax_ld] = r.max_load;
+  }
 }
 
-template <typename T, int VC>
-size_t scan_lds(int ld_o, int rchunk, int mode) {
-  return sizeof(T) * ((size_t)VC * ld_o + (size_t)VC * rchunk + (mode ? ld_o : 0));
+// ---------------------------------------------------------------- launch
+constexpr size_t kLdsBudget = 64 * 1024;   // dynamic LDS per workgroup, at most
+constexpr size_t kLdsOccupancy = 38 * 1024; // fits four workgroups per CU
+
+// rows per chunk: the largest multiple of 64 keeping the block within `target`
+// bytes (at least 64 rows), capped at the padded monitored rows
+inline int pick_rchunk(size_t fixed, size_t per_row, int mon_pad, size_t target) {
+  const size_t cap = target > fixed ? (target - fixed) / per_row : 0;
+  int rc = (int)(cap / 64 * 64);
+  if (rc < 64) rc = 64;
+  return rc < mon_pad ? rc : mon_pad;
 }
 
-// rows per LDS chunk: as many as fit in the LDS budget, a multiple of 64
-template <typename T, int VC>
-int pick_rchunk(const dcflow_plan *p, int mode) {
-  const size_t budget = 64 * 1024;
-  size_t fixed = sizeof(T) * ((size_t)VC * p->ld_o + (mode ? p->ld_o : 0));
-  if (fixed + sizeof(T) * VC * 64 > budget) return -1;
-  int rc = (int)((budget - fixed) / (sizeof(T) * VC)) / 64 * 64;
-  return min(rc, p->mon_pad);
+template <typename T, int VC, int MINW>
+hipError_t launch_max(const ScanArgs &a0, int n_cand, int nvar, hipStream_t s) {
+  ScanArgs a = a0;
+  const size_t fixed = sizeof(T) * (size_t)VC * a.ld_o;
+  a.rchunk = pick_rchunk(fixed, sizeof(T) * VC, a.mon_pad, kLdsOccupancy);
+  const size_t lds = fixed + sizeof(T) * (size_t)VC * a.rchunk;
+  if (lds > kLdsBudget) return hipErrorInvalidValue;
+  k_scan_max<T, VC, MINW><<<dim3(n_cand, (nvar + VC - 1) / VC), dim3(256), lds, s>>>(a);
+  DCF_CHECK_LAUNCH();
+  return hipSuccess;
 }
 
-template <typename T, int VC>
+template <typename T>
 hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *out, hipStream_t s) {
   dcflow_plan *p = bt->plan;
-  const int ld_f = p->ld_er;
-  int rc0 = pick_rchunk<T, VC>(p, 0);
-  int rc1 = pick_rchunk<T, 1>(p, 1);
-  if (rc0 <= 0 || rc1 <= 0) return hipErrorInvalidValue;
-  dim3 g0(bt->n_cand, (nvar + VC - 1) / VC);
-  const size_t lds0 = scan_lds<T, VC>(p->ld_o, rc0, 0);
-  const size_t lds1 = scan_lds<T, 1>(p->ld_o, rc1, 1);
-  const int single = nvar == 1;  // one variant: the winner pass alone gives everything
-  if (!single) {
-    k_scan<T, VC, 0><<<g0, dim3(256), lds0, s>>>(
-        flows, ld_f, nvar, bt->d_off, bt->d_U, p->ld_er, bt->d_W, p->ld_o, bt->d_invden,
-        bt->d_isl, bt->d_status, p->d_lsd, p->d_inv_r, p->n_mon, p->mon_pad, p->d_out_pos,
-        p->n_out, p->d_mon, p->d_out, bt->d_vmax, bt->vmax, out, rc0, 0);
-    DCF_CHECK_LAUNCH();
+  ScanArgs a;
+  a.F = flows;
+  a.ld_f = p->ld_er;
+  a.nvar = nvar;
+  a.off = bt->d_off;
+  a.U = bt->d_U;
+  a.ld_er = p->ld_er;
+  a.W = bt->d_W;
+  a.ld_o = p->ld_o;
+  a.invden = bt->d_invden;
+  a.isl = bt->d_isl;
+  a.status = bt->d_status;
+  a.lsd = p->d_lsd;
+  a.lsd32 = p->d_lsd32;
+  a.inv_r = p->d_inv_r;
+  a.n_mon = p->n_mon;
+  a.mon_pad = p->mon_pad;
+  a.out_pos = p->d_out_pos;
+  a.n_out = p->n_out;
+  a.mon = p->d_mon;
+  a.out = p->d_out;
+  a.vmax = bt->d_vmax;
+  a.vmax_ld = bt->vmax;
+  a.res = out;
+  a.single = nvar == 1;  // one variant: the winner pass alone gives everything
+  if (!a.single) {
+    // the widest variant group whose y fits the LDS budget with one 64-row chunk
+    constexpr int kV0 = sizeof(T) == 4 ? 16 : 8, kV1 = kV0 / 4;
+    auto fits = [&](int vc) { return sizeof(T) * (size_t)vc * (p->ld_o + 64) <= kLdsBudget; };
+    hipError_t e;
+    if (fits(kV0) && nvar > kV1)
+      e = launch_max<T, kV0, sizeof(T) == 4 ? 4 : 2>(a, bt->n_cand, nvar, s);
+    else if (fits(kV1) && nvar > 1)
+      e = launch_max<T, kV1, 1>(a, bt->n_cand, nvar, s);
+    else
+      e = launch_max<T, 1, 1>(a, bt->n_cand, nvar, s);
+    if (e != hipSuccess) return e;
   }
-  k_scan<T, 1, 1><<<dim3(bt->n_cand), dim3(256), lds1, s>>>(
-      flows, ld_f, nvar, bt->d_off, bt->d_U, p->ld_er, bt->d_W, p->ld_o, bt->d_invden, bt->d_isl,
-      bt->d_status, p->d_lsd, p->d_inv_r, p->n_mon, p->mon_pad, p->d_out_pos, p->n_out, p->d_mon,
-      p->d_out, bt->d_vmax, bt->vmax, out, rc1, single);
+  const size_t fixed = sizeof(T) * 2 * (size_t)p->ld_o;
+  a.rchunk = pick_rchunk(fixed, sizeof(T), p->mon_pad, kLdsOccupancy);
+  const size_t lds = fixed + sizeof(T) * (size_t)a.rchunk;
+  if (lds > kLdsBudget) return hipErrorInvalidValue;
+  k_scan_win<T><<<dim3(bt->n_cand), dim3(256), lds, s>>>(a);
   DCF_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -414,8 +626,8 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
 hipError_t launch_score(dcflow_batch *bt, const void *flows, int nvar, int prec, dcflow_score *out,
                         hipStream_t s) {
   if (bt->n_cand == 0) return hipSuccess;
-  if (prec == DCFLOW_FP64) return run_scan<double, 8>(bt, static_cast<const double *>(flows), nvar, out, s);
-  return run_scan<float, 16>(bt, static_cast<const float *>(flows), nvar, out, s);
+  if (prec == DCFLOW_FP64) return run_scan<double>(bt, static_cast<const double *>(flows), nvar, out, s);
+  return run_scan<float>(bt, static_cast<const float *>(flows), nvar, out, s);
 }
 
 }  // namespace dcflow

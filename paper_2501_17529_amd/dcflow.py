@@ -63,6 +63,9 @@ class PlanView(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2501_17529_amd.build_lib")
+    # torch first: its HIP runtime (same soname as the one the library links) must
+    # be the one loaded, since device pointers and streams come from torch
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
     sig = {
@@ -241,7 +244,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
+        if h and _lib is not None:  # module globals may already be gone at interpreter exit
             _lib.dcflow_plan_destroy(h)
             self.h = None
 
@@ -325,7 +328,7 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
+        if h and _lib is not None:  # module globals may already be gone at interpreter exit
             _lib.dcflow_batch_destroy(h)
             self.h = None
 

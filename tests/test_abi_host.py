@@ -96,3 +96,20 @@ def test_grid_validation_errors(d):
     with pytest.raises(d.DcflowError) as ei:
         d.validate_candidates(ga, w.cands)
     assert ei.value.code == -2
+
+
+def test_library_binds_to_torch_hip_runtime():
+    """Importing the binding first must still leave one HIP runtime in the
+    process, torch's: the library shares torch's device pointers and streams."""
+    import subprocess
+    import sys
+    code = ("import paper_2501_17529_amd.dcflow, torch, os\n"
+            "maps = open('/proc/self/maps').read()\n"
+            "libs = {l.split()[-1] for l in maps.splitlines() if 'libamdhip64' in l}\n"
+            "tdir = os.path.dirname(torch.__file__)\n"
+            "print(len(libs), all(p.startswith(tdir) for p in libs))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.split() == ["1", "True"], r.stdout
