@@ -219,7 +219,8 @@ const char *dcflow_strerror(int status);
  * best-scored ones and exhaustive screening stays the fallback and judge.
  * All pointers are device pointers; buffers are caller-owned.
  * ------------------------------------------------------------------------- */
-#define DCFLOW_MLP_DIN 96     /* feature width (75 used, rest zero)            */
+#define DCFLOW_MLP_DIN 96     /* feature width (86 used, rest zero)            */
+#define DCFLOW_MLP_PAIRS 8    /* tracked (branch, contingency) pairs per snapshot */
 #define DCFLOW_MLP_HIDDEN 256
 #define DCFLOW_TOPK_MAX 1024
 
@@ -237,20 +238,41 @@ size_t dcflow_mlp_workspace_bytes(int32_t batch);
 int dcflow_snapshot_flows(const dcflow_plan *plan, const double *inj, int32_t n_snap,
                           double *flows, double *n0max, hipStream_t stream);
 
+/* The DCFLOW_MLP_PAIRS largest relative loads of each snapshot's unchanged
+ * grid over N-0 rows and N-1 cases (Eq. lodf_delta, islanding contingencies
+ * excluded; ties to the lower position, N-0 rows first, then contingency-major):
+ * flows [n_snap][n_branch] from dcflow_snapshot_flows -> pairs [n_snap][8][2] =
+ * (monitored branch id, contingency branch id or -1) and their loads
+ * [n_snap][8] (double).  Unused slots (fewer scored cases) hold (-1, -1), 0. */
+int dcflow_snapshot_pairs(const dcflow_plan *plan, const double *flows, int32_t n_snap,
+                          int32_t *pairs, double *loads, hipStream_t stream);
+
 /* Feature vectors [n_act][96] (FP32) of split actions: action a splits bus
  * bus[a] with mask[a] (incident-branch bits as in dcflow_cands) in snapshot
  * snap[a]; side[a] != 0 moves the bus injection to the new busbar.  worst
  * [n_snap][2] = (monitored branch id l*, contingency branch id c* or -1) of the
  * snapshot's unchanged grid; rho = PTDF[l*,:] + LODF[l*,c*] PTDF[c*,:] (Def.
  * eq_lodf) is the critical flow's sensitivity to injections.  Features:
- * degree, bus injection, side bit, rho[bus]; per incident branch (ascending
- * id, up to 14): flow oriented out of the bus / r, moved bit, present bit,
- * sigma = rho[bus] - rho[far end], sigma * oriented flow / r(l*), with
- * r = rating_scale |F_base| + rating_offset; then glob[2 s], glob[2 s + 1]. */
+ * [0] degree, [1] bus injection, [2] side bit, [3] rho[bus]; per incident
+ * branch (ascending id, up to 14), 5 values from [4]: flow oriented out of the
+ * bus / r, moved bit, present bit, sigma = rho[bus] - rho[far end],
+ * sigma * oriented flow / r(l*), with r = rating_scale |F_base| + rating_offset;
+ * [74], [75] = glob[2 s], glob[2 s + 1]; [76..83] the exact loads after the split
+ * of the snapshot's pairs (from dcflow_snapshot_pairs), by the split factor of
+ * Def. eq_bsdf / Eq. bsdf_application and the post-split LODF (Def. eq_lodf),
+ * normalised by the monitored ratings; [84] their maximum; [85] = 1 when the
+ * split cuts the new busbar off (then [76..84] are 0). */
 int dcflow_action_features(const dcflow_plan *plan, const double *flows, const double *inj,
-                           const double *glob, const int32_t *worst, int32_t n_act,
-                           const int32_t *snap, const int32_t *bus, const uint32_t *mask,
-                           const int32_t *side, float *feat, hipStream_t stream);
+                           const double *glob, const int32_t *worst, const int32_t *pairs,
+                           int32_t n_act, const int32_t *snap, const int32_t *bus,
+                           const uint32_t *mask, const int32_t *side, float *feat,
+                           hipStream_t stream);
+
+/* Training labels of exact-screen results: labels[i] = min(log(max_load[i] /
+ * glob[2 snap[i] + 1]), 0), the gain over the unchanged grid's maximum load
+ * (0 = none, also for an islanded candidate with max_load = +inf). */
+int dcflow_improvement_labels(const double *max_load, const int32_t *snap, const double *glob,
+                              int32_t n, float *labels, hipStream_t stream);
 
 /* FP32 forward pass y [n] of x [n][96] (ws >= dcflow_mlp_workspace_bytes(n)). */
 int dcflow_mlp_forward(const float *params, const float *x, int32_t n, float *y, void *ws,

@@ -7,7 +7,9 @@ the most promising first (an addition to the paper, whose optimiser that
 proposes candidates is out of its scope, Sec. III-A).  This module restates it
 plainly so the GPU kernels can be checked:
 
-  * per-action features from the base-case flows of a load snapshot;
+  * per-action features from the base-case flows of a load snapshot, among
+    them the exact post-split N-1 loads of the snapshot's K_PAIRS worst
+    (branch, contingency) pairs of the unchanged grid, by plain rebuild;
   * a 3-layer perceptron d_in -> 256 -> 256 -> 1 with ReLU;
   * mean squared error on standardised labels, its gradients by the chain rule;
   * one Adam step (Kingma & Ba, 2015) with bias correction.
@@ -20,8 +22,10 @@ import numpy as np
 
 D_MAX = 14            # incident-branch slots per action
 N_SLOT_FEAT = 5       # oriented flow / r, moved bit, present bit, sigma, sigma * flow / r*
-N_FEAT = 4 + D_MAX * N_SLOT_FEAT + 2   # 76
+K_PAIRS = 8           # tracked (branch, contingency) pairs per snapshot
+N_FEAT = 4 + D_MAX * N_SLOT_FEAT + 2 + K_PAIRS + 2   # 86
 D_IN = 96             # padded input width
+X_PAIRS = 4 + D_MAX * N_SLOT_FEAT + 2                # first pair-load slot (76)
 
 
 def critical_row(h, f, t, l_star, c_star):
@@ -35,7 +39,58 @@ def critical_row(h, f, t, l_star, c_star):
     return h[l_star] + lw * h[c_star]
 
 
-def action_features(n_bus, f, t, flows, rating_all, p, bus, mask, inj_moves, glob2, rho, r_star):
+def base_pairs(n, f, t, b, slack, p, mon, out, rating, k=K_PAIRS):
+    """The k largest relative loads of the unchanged grid under injections p,
+    over N-0 rows and every non-islanding contingency (Sec. III-A loads), as
+    (branch l, contingency branch c or -1, load); ties go to the lower
+    position in the order N-0 rows first, then contingency-major."""
+    from . import dcflow_oracle as O
+    o = O.score_candidate(n, f, t, b, slack, [], p, mon, out, rating)
+    L = o["loads_best"]            # [1 + scored][n_mon], rows in that order
+    sc = o["scored_out"]
+    flat = L.ravel()
+    order = np.lexsort((np.arange(flat.size), -flat))[:k]
+    res = []
+    for q in order:
+        ci, li = divmod(int(q), len(mon))
+        res.append((int(mon[li]), -1 if ci == 0 else int(sc[ci - 1]), float(flat[q])))
+    return res
+
+
+def split_pair_loads(n, f, t, b, slack, p, bus, mask, inj_moves, pairs, rating_of):
+    """Exact loads of the tracked pairs after one split of ``bus`` (branches of
+    ``mask`` to the new busbar, the bus injection with them if inj_moves):
+    the split network is rebuilt and its N-0 flows and LODF computed directly
+    (Def. eq_lodf, Eq. lodf_delta).  A pair whose contingency islands the split
+    network keeps its N-0 load.  Returns (loads [len(pairs)], connected)."""
+    from . import dcflow_oracle as O
+    pnew = p[bus] if inj_moves else 0.0
+    outs = [c for _, c in pairs if c >= 0]
+    cf = O.candidate_flows(n, f, t, b, slack, [(O.KIND_SPLIT, bus, mask, pnew)], p, outs)
+    if not cf["connected"]:
+        return np.zeros(len(pairs)), False
+    p0 = cf["p0"][0]
+    res, k = [], 0
+    for (l, c) in pairs:
+        v = p0[l]
+        if c >= 0:
+            if cf["state"][k] == 0:
+                v = p0[l] + cf["lodf"][l, k] * p0[c]
+            k += 1
+        res.append(abs(v) / rating_of[l])
+    return np.asarray(res), True
+
+
+def improvement_label(max_load, base_max):
+    """Training label: log of the candidate's maximum load relative to the
+    unchanged grid's, clipped at 0 (no gain); an islanded candidate gets 0."""
+    if not np.isfinite(max_load):
+        return 0.0
+    return min(np.log(max_load / base_max), 0.0)
+
+
+def action_features(n_bus, f, t, flows, rating_all, p, bus, mask, inj_moves, glob2, rho, r_star,
+                    pair_loads=None, connected=True):
     """Feature vector of one split action (float64 [D_IN]).
 
     flows: base-case flows of the snapshot on every branch; rating_all: per
@@ -61,6 +116,12 @@ def action_features(n_bus, f, t, flows, rating_all, p, bus, mask, inj_moves, glo
         x[base + 4] = sig * fo / r_star
     x[4 + D_MAX * N_SLOT_FEAT + 0] = glob2[0]
     x[4 + D_MAX * N_SLOT_FEAT + 1] = glob2[1]
+    if pair_loads is not None:
+        if connected:
+            x[X_PAIRS:X_PAIRS + K_PAIRS] = pair_loads
+            x[X_PAIRS + K_PAIRS] = np.max(pair_loads)
+        else:
+            x[X_PAIRS + K_PAIRS + 1] = 1.0
     return x
 
 

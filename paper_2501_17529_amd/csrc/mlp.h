@@ -5,10 +5,12 @@
 
 namespace dcflow {
 
-constexpr int kMlpDin = 96;    // padded feature width (75 used)
+constexpr int kMlpDin = 96;    // padded feature width (86 used)
 constexpr int kMlpH = 256;     // hidden width
 constexpr int kMlpDmax = 14;   // incident-branch slots per action
 constexpr int kMlpSlot = 5;    // values per slot
+constexpr int kMlpPairs = 8;   // tracked (branch, contingency) pairs per snapshot
+constexpr int kXPairs = 4 + kMlpDmax * kMlpSlot + 2;  // first pair-load feature
 // FP32 master parameters, one flat array: w1 [96][256], b1 [256], w2 [256][256],
 // b2 [256], w3 [256], b3 [1] (+3 padding)
 constexpr int kOffW1 = 0;
@@ -27,10 +29,14 @@ constexpr int kTopkMax = 1024;  // largest k of the top-k selection (power of tw
 
 hipError_t launch_snapshot(const dcflow_plan *p, const double *X, int S, double *F,
                            double *n0max, hipStream_t s);
+hipError_t launch_pairs(const dcflow_plan *p, const double *F, int S, int32_t *pairs,
+                        double *loads, hipStream_t s);
 hipError_t launch_features(const dcflow_plan *p, const double *Fs, const double *X,
-                           const double *glob, const int32_t *worst, int n_act,
-                           const int32_t *snap, const int32_t *bus, const uint32_t *mask,
-                           const int32_t *side, float *out, hipStream_t s);
+                           const double *glob, const int32_t *worst, const int32_t *pairs,
+                           int n_act, const int32_t *snap, const int32_t *bus,
+                           const uint32_t *mask, const int32_t *side, float *out, hipStream_t s);
+hipError_t launch_improvement(const double *max_load, const int32_t *snap, const double *glob,
+                              int n, float *out, hipStream_t s);
 hipError_t launch_gemm32(int M, int N, int K, const float *A, long sai, long sak, const float *B,
                          long sbk, long sbj, float *C, int ldc, const float *bias, int epi,
                          const float *mask, int ldm, hipStream_t s);

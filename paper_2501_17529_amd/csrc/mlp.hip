@@ -64,15 +64,34 @@ __global__ void k_snapshot_n0max(const double *__restrict__ F, int m, const int3
 //   with sigma_q = rho[A] - rho[far_q] (critical-flow change per unit moved
 //   along branch q), r = scale |F_base| + offset, r* that of l*;
 //   [74] snapshot max N-0 load, [75] snapshot max N-1 load.
+//   [76..83] exact post-split loads of the snapshot's tracked pairs (below),
+//   [84] their maximum, [85] 1 if the split islands the network (then 76..84 are 0).
+//
+// Pair loads.  Splitting bus A moves the masked branches to a new node B; the
+// rest (the stay set) keeps A.  By the split factor of the paper (Def. eq_bsdf,
+// Eq. bsdf_application) the post-split PTDF row of branch x is
+//   H'_x = hx_x + v_x bbc,   v_x = (hx_x . p_shift + p_corr_x) / D,
+//   D = 1 - bbc . p_shift,
+// with hx the PTDF extended by column B := column A, bbc = e_A - sum_stay s_j hx_j
+// (coupler row; slack column 0, shifted by -1 when A is the slack),
+// p_shift = -e_B + sum_stay (b_j / beta) e_far_j, beta = sum_stay b_j, and
+// p_corr_x = s_j b_j / beta for x = stay branch j.  The N-0 flow becomes
+// F'_x = F_x + v_x f_cpl with the coupler flow f_cpl = bbc . p (injection left on A
+// minus what the stay branches carry away).  The tracked pair (l, c) then loads
+// |F'_l + LODF'_lc F'_c| / r_l with LODF'_lc = H'_l d / (1 - H'_c d), d the
+// transfer between c's post-split terminals (Def. eq_lodf, Eq. lodf_delta);
+// a contingency that islands the split network leaves the N-0 load.
 __global__ void k_features(const int32_t *__restrict__ f, const int32_t *__restrict__ t,
+                           const double *__restrict__ bsus, int slack,
                            const int32_t *__restrict__ adj_off,
                            const int32_t *__restrict__ adj_br, const double *__restrict__ fbase,
                            double rscale, double roffset, const double *__restrict__ Hb, int ld_h,
                            const double *__restrict__ hdo, int ld_o,
                            const int32_t *__restrict__ out, int n_out,
+                           const int32_t *__restrict__ pos_of_br, const double *__restrict__ inv_r,
                            const double *__restrict__ Fs, int m,
                            const double *__restrict__ X, int n, const double *__restrict__ glob,
-                           const int32_t *__restrict__ worst,
+                           const int32_t *__restrict__ worst, const int32_t *__restrict__ pairs,
                            int n_act, const int32_t *__restrict__ a_snap,
                            const int32_t *__restrict__ a_bus, const uint32_t *__restrict__ a_mask,
                            const int32_t *__restrict__ a_side, float *__restrict__ o_all) {
@@ -117,6 +136,183 @@ __global__ void k_features(const int32_t *__restrict__ f, const int32_t *__restr
   }
   o[4 + kMlpDmax * kMlpSlot + 0] = (float)glob[2 * s + 0];
   o[4 + kMlpDmax * kMlpSlot + 1] = (float)glob[2 * s + 1];
+
+  // ---- exact post-split loads of the tracked pairs
+  const int a0 = adj_off[A];
+  const double *Fv = Fs + (size_t)s * m;
+  const double *xs = X + (size_t)s * n;
+  double beta = 0.0;
+  for (int q = 0; q < deg; ++q)
+    if (!((mk >> q) & 1u)) beta += bsus[adj_br[a0 + q]];
+  auto stay_s = [&](int br) { return f[br] == A ? 1.0 : -1.0; };
+  auto stay_far = [&](int br) { return f[br] == A ? t[br] : f[br]; };
+  auto hx = [&](int br, int x) { return Hb[(size_t)br * ld_h + (x < 0 ? A : x)]; };
+  auto bbc = [&](int x) {  // coupler row at node x (x < 0: the new node B)
+    double v = x == A ? 1.0 : 0.0;
+    for (int q = 0; q < deg; ++q) {
+      if ((mk >> q) & 1u) continue;
+      const int br = adj_br[a0 + q];
+      v -= stay_s(br) * hx(br, x);
+    }
+    if (A == slack) v -= 1.0;
+    if (x >= 0 && x == slack) v = 0.0;
+    return v;
+  };
+  double dsum = bbc(-1);
+  for (int q = 0; q < deg; ++q) {
+    if ((mk >> q) & 1u) continue;
+    const int br = adj_br[a0 + q];
+    dsum -= bsus[br] / beta * bbc(stay_far(br));
+  }
+  const double D = 1.0 + dsum;
+  float *po = o + kXPairs;
+  if (!(beta > 0.0) || fabs(D) < 1e-9) {  // the new node is cut off
+    po[kMlpPairs + 1] = 1.f;
+    return;
+  }
+  // injection left on A: the slack's own is minus the sum of the others
+  double pA = xs[A];
+  if (A == slack) {
+    pA = 0.0;
+    for (int x = 0; x < n; ++x)
+      if (x != slack) pA -= xs[x];
+  }
+  double fcpl = pA - (a_side[a] ? xs[A] : 0.0);
+  for (int q = 0; q < deg; ++q) {
+    if ((mk >> q) & 1u) continue;
+    const int br = adj_br[a0 + q];
+    fcpl -= stay_s(br) * Fv[br];
+  }
+  auto vrow = [&](int x) {  // v_x
+    double hp = -hx(x, A);
+    for (int q = 0; q < deg; ++q) {
+      if ((mk >> q) & 1u) continue;
+      const int br = adj_br[a0 + q];
+      hp += bsus[br] / beta * hx(x, stay_far(br));
+      if (br == x) hp += stay_s(br) * bsus[br] / beta;
+    }
+    return hp / D;
+  };
+  auto moved = [&](int br) {
+    for (int q = 0; q < deg; ++q)
+      if (adj_br[a0 + q] == br) return ((mk >> q) & 1u) != 0u;
+    return false;
+  };
+  float pmax = 0.f;
+  for (int k = 0; k < kMlpPairs; ++k) {
+    const int l = pairs[((size_t)s * kMlpPairs + k) * 2 + 0];
+    const int c = pairs[((size_t)s * kMlpPairs + k) * 2 + 1];
+    double load = 0.0;
+    if (l >= 0 && l != c) {
+      const double ir = inv_r[pos_of_br[l]];
+      const double vl = vrow(l);
+      const double f0l = Fv[l] + vl * fcpl;
+      load = fabs(f0l) * ir;
+      if (c >= 0) {
+        const double vc = vrow(c);
+        const double f0c = Fv[c] + vc * fcpl;
+        const bool mv = moved(c);
+        const int fc = mv && f[c] == A ? -1 : f[c];
+        const int tc = mv && t[c] == A ? -1 : t[c];
+        const double dbb = bbc(fc) - bbc(tc);
+        const double num = hx(l, fc) - hx(l, tc) + vl * dbb;
+        const double den = 1.0 - (hx(c, fc) - hx(c, tc) + vc * dbb);
+        if (fabs(den) >= 1e-9) load = fabs(f0l + num / den * f0c) * ir;
+      }
+    }
+    po[k] = (float)load;
+    pmax = fmaxf(pmax, (float)load);
+  }
+  po[kMlpPairs] = pmax;
+}
+
+// One workgroup per snapshot: the kMlpPairs largest relative N-0 / N-1 loads of
+// the unchanged grid (Eq. lodf_delta with the base LODF, islanding
+// contingencies excluded), ties to the lower position key = (c + 1) n_mon + row.
+// Each thread keeps a sorted list of its best entries; thread 0 merges the lists.
+__global__ void __launch_bounds__(256)
+k_base_pairs(const double *__restrict__ F, int m, const int32_t *__restrict__ mon, int n_mon,
+             const int32_t *__restrict__ out, int n_out, const double *__restrict__ hdo, int ld_o,
+             const double *__restrict__ inv_r, int32_t *__restrict__ pairs,
+             double *__restrict__ loads) {
+  constexpr int K = kMlpPairs;
+  __shared__ double sv[256][K];
+  __shared__ long long sk[256][K];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  const double *Fv = F + (size_t)s * m;
+  double bv[K];
+  long long bk[K];
+  for (int i = 0; i < K; ++i) {
+    bv[i] = -1.0;
+    bk[i] = 0x7fffffffffffffffLL;
+  }
+  const long long total = (long long)(n_out + 1) * n_mon;
+  for (long long e = tid; e < total; e += blockDim.x) {
+    const int ci = (int)(e / n_mon) - 1, li = (int)(e % n_mon);
+    const int l = mon[li];
+    double v;
+    if (ci < 0) {
+      v = fabs(Fv[l]) * inv_r[li];
+    } else {
+      const int c = out[ci];
+      const double den = 1.0 - hdo[(size_t)c * ld_o + ci];
+      if (fabs(den) < 1e-9) continue;  // islanding contingency
+      const double num = hdo[(size_t)l * ld_o + ci] - (l == c ? 1.0 : 0.0);
+      v = fabs(Fv[l] + num / den * Fv[c]) * inv_r[li];
+    }
+    if (!(v > bv[K - 1] || (v == bv[K - 1] && e < bk[K - 1]))) continue;
+    int j = K - 1;  // insertion into the sorted list
+    while (j > 0 && (v > bv[j - 1] || (v == bv[j - 1] && e < bk[j - 1]))) {
+      bv[j] = bv[j - 1];
+      bk[j] = bk[j - 1];
+      --j;
+    }
+    bv[j] = v;
+    bk[j] = e;
+  }
+  for (int i = 0; i < K; ++i) {
+    sv[tid][i] = bv[i];
+    sk[tid][i] = bk[i];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int head[256];
+    for (int i = 0; i < 256; ++i) head[i] = 0;
+    for (int q = 0; q < K; ++q) {
+      int bt = -1;
+      for (int i = 0; i < (int)blockDim.x; ++i) {
+        if (head[i] >= K) continue;
+        const double v = sv[i][head[i]];
+        const long long kk = sk[i][head[i]];
+        if (kk == 0x7fffffffffffffffLL) continue;
+        if (bt < 0 || v > sv[bt][head[bt]] || (v == sv[bt][head[bt]] && kk < sk[bt][head[bt]])) bt = i;
+      }
+      int32_t *pp = pairs + ((size_t)s * K + q) * 2;
+      if (bt < 0) {  // fewer scored entries than K
+        pp[0] = -1;
+        pp[1] = -1;
+        loads[(size_t)s * K + q] = 0.0;
+        continue;
+      }
+      const long long e = sk[bt][head[bt]];
+      const int ci = (int)(e / n_mon) - 1, li = (int)(e % n_mon);
+      pp[0] = mon[li];
+      pp[1] = ci < 0 ? -1 : out[ci];
+      loads[(size_t)s * K + q] = sv[bt][head[bt]];
+      ++head[bt];
+    }
+  }
+}
+
+// Training label: log(max_load / base maximum) clipped at 0, 0 for an islanded candidate.
+__global__ void k_improvement(const double *__restrict__ max_load, const int32_t *__restrict__ snap,
+                              const double *__restrict__ glob, int n, float *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = max_load[i];
+  const uint64_t u = __double_as_longlong(v);
+  const bool finite = ((u >> 52) & 0x7ff) != 0x7ff;
+  out[i] = finite ? (float)fmin(log(v / glob[2 * snap[i] + 1]), 0.0) : 0.f;
 }
 
 // ------------------------------------------------------ FP32 GEMM
@@ -475,13 +671,28 @@ hipError_t launch_snapshot(const dcflow_plan *p, const double *X, int S, double 
 }
 
 hipError_t launch_features(const dcflow_plan *p, const double *Fs, const double *X,
-                           const double *glob, const int32_t *worst, int n_act,
-                           const int32_t *snap, const int32_t *bus, const uint32_t *mask,
-                           const int32_t *side, float *out, hipStream_t s) {
+                           const double *glob, const int32_t *worst, const int32_t *pairs,
+                           int n_act, const int32_t *snap, const int32_t *bus,
+                           const uint32_t *mask, const int32_t *side, float *out, hipStream_t s) {
   k_features<<<nblk(n_act, 128), 128, 0, s>>>(
-      p->d_f, p->d_t, p->d_adj_off, p->d_adj_br, p->d_fbase, p->rating_scale, p->rating_offset,
-      p->d_hb, p->ld_h, p->d_hdo, p->ld_o, p->d_out, p->n_out, Fs, p->m, X, p->n, glob, worst,
-      n_act, snap, bus, mask, side, out);
+      p->d_f, p->d_t, p->d_b, p->slack, p->d_adj_off, p->d_adj_br, p->d_fbase, p->rating_scale,
+      p->rating_offset, p->d_hb, p->ld_h, p->d_hdo, p->ld_o, p->d_out, p->n_out, p->d_pos_of_br,
+      p->d_inv_r, Fs, p->m, X, p->n, glob, worst, pairs, n_act, snap, bus, mask, side, out);
+  DCF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+hipError_t launch_pairs(const dcflow_plan *p, const double *F, int S, int32_t *pairs,
+                        double *loads, hipStream_t s) {
+  k_base_pairs<<<S, 256, 0, s>>>(F, p->m, p->d_mon, p->n_mon, p->d_out, p->n_out, p->d_hdo,
+                                 p->ld_o, p->d_inv_r, pairs, loads);
+  DCF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+hipError_t launch_improvement(const double *max_load, const int32_t *snap, const double *glob,
+                              int n, float *out, hipStream_t s) {
+  k_improvement<<<nblk(n, 256), 256, 0, s>>>(max_load, snap, glob, n, out);
   DCF_CHECK_LAUNCH();
   return hipSuccess;
 }

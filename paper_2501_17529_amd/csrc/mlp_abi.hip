@@ -37,16 +37,33 @@ int dcflow_snapshot_flows(const dcflow_plan *p, const double *inj, int32_t n_sna
   return e == hipSuccess ? DCFLOW_OK : fail(e, "dcflow_snapshot_flows");
 }
 
+int dcflow_snapshot_pairs(const dcflow_plan *p, const double *flows, int32_t n_snap,
+                          int32_t *pairs, double *loads, hipStream_t s) {
+  if (!p || !flows || !pairs || !loads || n_snap < 1) return DCFLOW_E_ARG;
+  hipError_t e = launch_pairs(p, flows, n_snap, pairs, loads, s);
+  return e == hipSuccess ? DCFLOW_OK : fail(e, "dcflow_snapshot_pairs");
+}
+
 int dcflow_action_features(const dcflow_plan *p, const double *flows, const double *inj,
-                           const double *glob, const int32_t *worst, int32_t n_act,
-                           const int32_t *snap, const int32_t *bus, const uint32_t *mask,
-                           const int32_t *side, float *feat, hipStream_t s) {
-  if (!p || !flows || !inj || !glob || !worst || !snap || !bus || !mask || !side || !feat)
+                           const double *glob, const int32_t *worst, const int32_t *pairs,
+                           int32_t n_act, const int32_t *snap, const int32_t *bus,
+                           const uint32_t *mask, const int32_t *side, float *feat, hipStream_t s) {
+  if (!p || !flows || !inj || !glob || !worst || !pairs || !snap || !bus || !mask || !side ||
+      !feat)
     return DCFLOW_E_ARG;
   if (n_act < 0) return DCFLOW_E_SHAPE;
   if (n_act == 0) return DCFLOW_OK;
-  hipError_t e = launch_features(p, flows, inj, glob, worst, n_act, snap, bus, mask, side, feat, s);
+  hipError_t e =
+      launch_features(p, flows, inj, glob, worst, pairs, n_act, snap, bus, mask, side, feat, s);
   return e == hipSuccess ? DCFLOW_OK : fail(e, "dcflow_action_features");
+}
+
+int dcflow_improvement_labels(const double *max_load, const int32_t *snap, const double *glob,
+                              int32_t n, float *labels, hipStream_t s) {
+  if (!max_load || !snap || !glob || !labels || n < 0) return DCFLOW_E_ARG;
+  if (n == 0) return DCFLOW_OK;
+  hipError_t e = launch_improvement(max_load, snap, glob, n, labels, s);
+  return e == hipSuccess ? DCFLOW_OK : fail(e, "dcflow_improvement_labels");
 }
 
 int dcflow_mlp_forward(const float *prm, const float *x, int32_t n, float *y, void *ws,

@@ -90,7 +90,9 @@ def _load():
         "dcflow_mlp_bf16_bytes": (SZ, []),
         "dcflow_mlp_workspace_bytes": (SZ, [I32]),
         "dcflow_snapshot_flows": (ctypes.c_int, [P, P, I32, P, P, P]),
-        "dcflow_action_features": (ctypes.c_int, [P, P, P, P, P, I32, P, P, P, P, P, P]),
+        "dcflow_snapshot_pairs": (ctypes.c_int, [P, P, I32, P, P, P]),
+        "dcflow_action_features": (ctypes.c_int, [P, P, P, P, P, P, I32, P, P, P, P, P, P]),
+        "dcflow_improvement_labels": (ctypes.c_int, [P, P, P, I32, P, P]),
         "dcflow_mlp_forward": (ctypes.c_int, [P, P, I32, P, P, SZ, P]),
         "dcflow_mlp_grad": (ctypes.c_int, [P, P, P, I32, P, P, P, SZ, P]),
         "dcflow_mlp_adam": (ctypes.c_int, [P, P, P, P, I32, ctypes.c_float, P]),
@@ -114,7 +116,8 @@ EXPORTED = ("dcflow_plan_workspace_bytes", "dcflow_build_ptdf", "dcflow_plan_vie
             "dcflow_flow_bytes", "dcflow_eval_injections", "dcflow_n1_score",
             "dcflow_batch_variant_max", "dcflow_strerror", "dcflow_mlp_param_count",
             "dcflow_mlp_bf16_bytes", "dcflow_mlp_workspace_bytes", "dcflow_snapshot_flows",
-            "dcflow_action_features", "dcflow_mlp_forward", "dcflow_mlp_grad", "dcflow_mlp_adam",
+            "dcflow_snapshot_pairs", "dcflow_action_features", "dcflow_improvement_labels",
+            "dcflow_mlp_forward", "dcflow_mlp_grad", "dcflow_mlp_adam",
             "dcflow_mlp_pack_bf16", "dcflow_mlp_infer", "dcflow_column_stats",
             "dcflow_standardize", "dcflow_topk_smallest")
 

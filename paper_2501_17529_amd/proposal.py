@@ -19,6 +19,7 @@ from . import dcflow as D
 
 _lib = D._lib
 P = ctypes.c_void_p
+PAIRS = 8  # tracked (branch, contingency) pairs per snapshot
 
 
 def _ptr(t):
@@ -130,6 +131,12 @@ class Proposal:
         worst = np.stack([sc["worst_branch"], sc["worst_outage"]], axis=1).astype(np.int32)
         self.worst_host = worst
         self.worst = torch.from_numpy(np.ascontiguousarray(worst)).cuda()
+        # the snapshot's worst (branch, contingency) pairs, tracked through each split
+        self.pairs = torch.empty((S, PAIRS, 2), dtype=torch.int32, device="cuda")
+        self.pair_loads = torch.empty((S, PAIRS), dtype=torch.float64, device="cuda")
+        _chk(_lib.dcflow_snapshot_pairs(self.plan.h, _ptr(flows), S, _ptr(self.pairs),
+                                        _ptr(self.pair_loads), s), "dcflow_snapshot_pairs")
+        self.glob = glob
         return x, flows, glob
 
     def features(self, x_dev, flows, glob, snap, bus, mask, side):
@@ -140,9 +147,21 @@ class Proposal:
                 for a in (snap.astype(np.int32), bus.astype(np.int32), mask.astype(np.int32),
                           side.astype(np.int32))]
         _chk(_lib.dcflow_action_features(self.plan.h, _ptr(flows), _ptr(x_dev), _ptr(glob),
-                                         _ptr(self.worst), n, *[_ptr(a) for a in arrs], _ptr(feat),
-                                         D._stream()), "dcflow_action_features")
+                                         _ptr(self.worst), _ptr(self.pairs), n,
+                                         *[_ptr(a) for a in arrs], _ptr(feat), D._stream()),
+             "dcflow_action_features")
         return feat
+
+    def improvement_labels(self, max_load, snap):
+        """Training labels of exact-screen maxima (device): the log gain over
+        the snapshot's unchanged grid, clipped at 0."""
+        import torch
+        ml = torch.as_tensor(np.ascontiguousarray(max_load, dtype=np.float64)).cuda()
+        sn = torch.as_tensor(np.ascontiguousarray(snap, dtype=np.int32)).cuda()
+        out = torch.empty(ml.shape[0], dtype=torch.float32, device="cuda")
+        _chk(_lib.dcflow_improvement_labels(_ptr(ml), _ptr(sn), _ptr(self.glob), ml.shape[0],
+                                            _ptr(out), D._stream()), "dcflow_improvement_labels")
+        return out
 
     def set_standardization(self, feat, labels):
         """Standardisation constants from the training set (on the device)."""

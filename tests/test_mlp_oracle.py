@@ -88,3 +88,106 @@ def test_training_reduces_loss():
     for step in range(1, 301):
         M.adam_step(p, M.backward(p, x, t), m, v, step, lr=3e-3)
     assert M.loss(p, x, t) < 0.2 * l0
+
+
+def _tiny():
+    import gridgen as G
+    from oracle import dcflow_oracle as O
+    w = G.workload_tiny(0)
+    g = w.grid
+    f, t, b = np.asarray(g.f), np.asarray(g.t), np.asarray(g.b)
+    r = O.ratings(g.n_bus, f, t, b, g.slack, g.p, w.mon)
+    r_of = np.zeros(len(f))
+    r_of[np.asarray(w.mon)] = r
+    return w, g, f, t, b, r, r_of
+
+
+def test_split_pair_loads_match_bsdf_route():
+    """Plain rebuild vs the paper's split factor (Def. eq_bsdf, Eq.
+    bsdf_application) followed by the LODF of the post-split PTDF: the same
+    post-split N-1 loads by two independent routes, slack-bus splits included."""
+    from oracle import dcflow_oracle as O
+    from oracle import paper_formulas as PF
+    w, g, f, t, b, r, r_of = _tiny()
+    n, sl = g.n_bus, g.slack
+    h = O.ptdf(n, f, t, b, sl)
+    rng = np.random.default_rng(11)
+    p = g.p + 0.1 * rng.normal(size=n)
+    mon, out = np.asarray(w.mon), np.asarray(w.out)
+    deg = g.degree()
+    buses = [sl] + [int(a) for a in np.flatnonzero(deg >= 3)[:6] if a != sl]
+    checked = 0
+    for a in buses:
+        inc = np.flatnonzero((f == a) | (t == a))
+        for mask in (2, (1 << len(inc)) - 2):
+            for side in (0, 1):
+                moved = [int(inc[q]) for q in range(len(inc)) if (mask >> q) & 1]
+                pairs = [(int(mon[3]), -1), (int(mon[5]), int(out[7])), (int(mon[1]), int(inc[0])),
+                         (int(inc[-1]), int(out[2]))]
+                pairs = [(l, c) for l, c in pairs if l != c]
+                got, ok = M.split_pair_loads(n, f, t, b, sl, p, a, mask, side, pairs, r_of)
+                if not ok:
+                    continue
+                hs = PF.bsdf_split(h, f, t, b, a, moved, slack=sl)   # [m][n + 1], node B = n
+                pe = np.concatenate([p, [0.0]])
+                pn = p[a] if side else 0.0
+                pe[a] -= pn
+                pe[n] += pn
+                p0 = hs @ pe
+                f2 = f.copy()
+                t2 = t.copy()
+                for l in moved:
+                    if f[l] == a:
+                        f2[l] = n
+                    else:
+                        t2[l] = n
+                ref = []
+                for (l, c) in pairs:
+                    v = p0[l]
+                    if c >= 0:
+                        dlt = hs[:, f2[c]] - hs[:, t2[c]]
+                        den = 1.0 - dlt[c]
+                        if abs(den) > 1e-9:
+                            v = p0[l] + dlt[l] / den * p0[c]
+                    ref.append(abs(v) / r_of[l])
+                np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-12)
+                checked += 1
+    assert checked >= 10
+
+
+def test_base_pairs_match_brute_force():
+    from oracle import dcflow_oracle as O
+    w, g, f, t, b, r, r_of = _tiny()
+    n, sl = g.n_bus, g.slack
+    mon, out = np.asarray(w.mon), np.asarray(w.out)
+    p = g.p
+    pairs = M.base_pairs(n, f, t, b, sl, p, mon, out, r, k=8)
+    p1, isl = O.n1_flows_bruteforce(n, f, t, b, sl, [], p, out)
+    p0 = O.dc_flows(n, f, t, b, sl, p)[0]
+    cand = [(abs(p0[l]) / r_of[l], (0, i), int(l), -1) for i, l in enumerate(mon)]
+    for ci, c in enumerate(out):
+        if isl[ci]:
+            continue
+        for i, l in enumerate(mon):
+            cand.append((abs(p1[0, ci, l]) / r_of[l], (ci + 1, i), int(l), int(c)))
+    cand.sort(key=lambda z: (-z[0], z[1]))
+    for (l, c, v), ref in zip(pairs, cand[:8]):
+        assert abs(v - ref[0]) <= 1e-9 * max(1.0, ref[0])
+        assert (l, c) == (ref[2], ref[3])
+
+
+def test_improvement_label():
+    assert M.improvement_label(np.inf, 2.0) == 0.0
+    assert M.improvement_label(3.0, 2.0) == 0.0
+    assert abs(M.improvement_label(1.0, 2.0) - np.log(0.5)) < 1e-15
+
+
+def test_pair_slots_of_the_feature_vector():
+    w, g, f, t, b, r, r_of = _tiny()
+    x = M.action_features(g.n_bus, f, t, np.zeros(len(f)), np.ones(len(f)), g.p, 3, 2, False,
+                          (0.5, 0.7), np.zeros(g.n_bus), 1.0, pair_loads=np.arange(8.0) / 8.0)
+    np.testing.assert_array_equal(x[M.X_PAIRS:M.X_PAIRS + 8], np.arange(8.0) / 8.0)
+    assert x[M.X_PAIRS + 8] == 7.0 / 8.0 and x[M.X_PAIRS + 9] == 0.0
+    y = M.action_features(g.n_bus, f, t, np.zeros(len(f)), np.ones(len(f)), g.p, 3, 2, False,
+                          (0.5, 0.7), np.zeros(g.n_bus), 1.0, pair_loads=np.ones(8), connected=False)
+    assert not y[M.X_PAIRS:M.X_PAIRS + 9].any() and y[M.X_PAIRS + 9] == 1.0
