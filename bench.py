@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "N-1 loadflows/s on 1 MI355X at ≤1e-4 rating error, mixed vs plain FP64 path"
 PEAK_VALU_FMA_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12   # non-packed FMA issue, fp32 and fp64
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_medium_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_medium_traffic.txt")
 
 
 # ------------------------------------------------------------------ CPU baseline
@@ -75,40 +75,66 @@ def _source_hash():
     return h.hexdigest()[:16]
 
 
-def run_path(D, torch, plan, w, prec, steps, warmup):
+def run_path(D, torch, plan, w, prec, steps, warmup, tune=True, graph=True):
     nv = w.n_var
     bt = D.Batch(plan, w.cands, nv)
     x = torch.from_numpy(np.ascontiguousarray(w.inj)).cuda()
     flows, _ = bt.flow_buffer(nv, prec)
     out = torch.empty(bt.n_cand * D.SCORE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()   # a non-null stream: graphs are captured from it
+    res = {}
+    with torch.cuda.stream(stream):
+        def step(ev=None):
+            if ev:
+                ev[0].record(stream)
+            bt.eval_topologies()
+            if ev:
+                ev[1].record(stream)
+            bt.eval_injections(x, nv, w.inj_shared, prec, flows=flows)
+            if ev:
+                ev[2].record(stream)
+            bt.n1_score(flows, nv, prec, out=out)
+            if ev:
+                ev[3].record(stream)
 
-    def step(ev=None):
-        if ev:
-            ev[0].record(stream)
-        bt.eval_topologies()
-        if ev:
-            ev[1].record(stream)
-        bt.eval_injections(x, nv, w.inj_shared, prec, flows=flows)
-        if ev:
-            ev[2].record(stream)
-        bt.n1_score(flows, nv, prec, out=out)
-        if ev:
-            ev[3].record(stream)
-
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
-    t0 = time.perf_counter()
-    for i in range(steps):
-        step(evs[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    phase = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
-                      for e in evs])   # ms
-    sc = D.Batch.scores_to_numpy(out, bt.n_cand)
-    return dict(wall=wall, phase_ms=phase.mean(axis=0), scores=sc, batch=bt)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        if tune:
+            from paper_2501_17529_amd import autotune
+            cfg, times = autotune.tune_scan(bt, flows, nv, prec, use_cache=False)
+            res["tuning"] = cfg
+            step()
+        # eager steps, phase by phase
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(evs[i])
+        torch.cuda.synchronize()
+        res["wall_eager"] = time.perf_counter() - t0
+        res["phase_ms"] = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]),
+                                     e[2].elapsed_time(e[3])] for e in evs]).mean(axis=0)
+        sc_eager = D.Batch.scores_to_numpy(out, bt.n_cand)
+        res["wall"] = res["wall_eager"]
+        if graph:
+            # the whole step captured once, replayed with one launch per step
+            bt.capture(x, nv, w.inj_shared, prec, flows, out, stream)
+            for _ in range(warmup):
+                bt.replay(stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                bt.replay(stream)
+            torch.cuda.synchronize()
+            res["wall_graph"] = time.perf_counter() - t0
+            sc = D.Batch.scores_to_numpy(out, bt.n_cand)
+            for k in ("max_load", "best_variant", "worst_branch", "worst_outage"):
+                assert np.array_equal(sc[k], sc_eager[k]), f"graph replay differs in {k}"
+            res["wall"] = res["wall_graph"]
+    res["scores"] = sc_eager
+    res["batch"] = bt
+    return res
 
 
 def main():
@@ -120,12 +146,27 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", choices=["both", "fp32", "fp64"], default="both")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run three plain device copies of MIB MiB (HBM counter scale)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: there is no multi-GPU path here "
               "(candidates would shard across GPUs with no communication)",
               file=sys.stderr)
         sys.exit(2)
+
+    if a.copy_calibration:
+        import torch
+        n = a.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 3}))
+        return
 
     import gridgen as G
     w = G.workload_medium(0, n_cand=a.cands)
@@ -142,7 +183,8 @@ def main():
     n_lf = w.cands.n_cand * w.n_var * len(w.out)
     res = {}
     for prec in (["fp32", "fp64"] if a.prec == "both" else [a.prec]):
-        res[prec] = run_path(D, torch, plan, w, prec, a.steps, a.warmup)
+        res[prec] = run_path(D, torch, plan, w, prec, a.steps, a.warmup, tune=not a.no_autotune,
+                             graph=not a.no_graph)
     main_prec = "fp32" if "fp32" in res else "fp64"
     r = res[main_prec]
     ms = r["wall"] / a.steps * 1e3
@@ -175,6 +217,9 @@ def main():
                          "eval_injections": float(v["phase_ms"][1]),
                          "n1_score": float(v["phase_ms"][2])} for p, v in res.items()},
         "build_ptdf_s": build_s,
+        "step_mode": "hip graph replay" if "wall_graph" in r else "eager",
+        "eager_ms_per_step": r["wall_eager"] / a.steps * 1e3,
+        "scan_tuning": {p: v.get("tuning") for p, v in res.items()},
     }
     if "fp64" in res and main_prec != "fp64":
         ms64 = res["fp64"]["wall"] / a.steps * 1e3

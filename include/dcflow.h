@@ -213,6 +213,37 @@ const double *dcflow_batch_variant_max(const dcflow_batch *batch);
 const char *dcflow_strerror(int status);
 
 /* ---------------------------------------------------------------------------
+ * Orchestration.  Launch shapes of the N-1 scan, chosen per batch (the
+ * package's autotuner times them and caches the fastest), and capture of one
+ * whole step (eval_topologies -> eval_injections -> n1_score) into a HIP graph
+ * that is replayed with one launch.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t scan_vc;     /* variants per pass-1 workgroup: 0 = automatic; FP32 runs accept
+                          16, 8, 4, 1 and FP64 runs 8, 4, 2, 1 (others: automatic) */
+  int32_t scan_rchunk; /* monitored rows per LDS chunk, a multiple of 64; 0 = automatic */
+  int32_t persistent;  /* nonzero: the scan runs as resident workgroups (4 per compute
+                          unit) that take candidates from a queue in descending rank */
+} dcflow_tuning;
+
+/* Sets / reads the batch's launch shapes (defaults: all zero).  E_ARG for a
+ * negative value or a row chunk that is not a multiple of 64. */
+int dcflow_batch_set_tuning(dcflow_batch *batch, const dcflow_tuning *tuning);
+int dcflow_batch_get_tuning(const dcflow_batch *batch, dcflow_tuning *tuning);
+
+/* Captures one step with exactly these arguments (see the three calls above)
+ * from `stream` into a graph held by the batch, replacing any earlier one.
+ * Nothing runs during the capture.  The stream must not be the null stream.
+ * The buffers named here must stay valid while the graph is used; tuning
+ * changes need a new capture.  Errors as for the three calls, E_HIP if the
+ * runtime refuses the capture. */
+int dcflow_graph_capture(dcflow_batch *batch, const double *dev_inj, int32_t n_var,
+                         int32_t inj_shared, dcflow_prec prec, void *dev_flows,
+                         size_t flow_bytes, dcflow_score *dev_out, hipStream_t stream);
+/* Replays the captured step on `stream` (E_ARG if nothing was captured). */
+int dcflow_graph_launch(dcflow_batch *batch, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Learned proposal network (an addition: the paper leaves the optimiser that
  * proposes candidates out of scope, Sec. III-A).  A 96 -> 256 -> 256 -> 1 ReLU
  * perceptron scores single-bus-split actions; the exact screen verifies the

@@ -156,6 +156,7 @@ void batch_layout(dcflow_batch *b, const dcflow_plan *p, const BatchDims &d, Are
   b->d_z = a.take<double>(ne * d.vmax);
   b->d_vmax = a.take<double>(nc * d.vmax);
   b->d_f0 = a.take<double>((size_t)d.vmax * p->ld_er);
+  b->d_queue = a.take<int32_t>(16);
 }
 
 int check_cands(int n_bus, int n_branch, const std::vector<int32_t> &adj_off,
@@ -408,6 +409,17 @@ int dcflow_batch_create(dcflow_plan *p, const dcflow_cands *c, int32_t n_var_max
   b->factored = 0;
   b->flows_prec = -1;
   b->flows_nvar = 0;
+  b->tune = dcflow_tuning{0, 0, 0};
+  b->graph = nullptr;
+  b->graph_exec = nullptr;
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu < 1)
+      ncu = 256;
+    b->n_cu = ncu;
+  }
   if (d.n_cand > 0) {
     // work queue: descending rank, stable
     std::vector<int32_t> order(d.n_cand);
@@ -441,7 +453,69 @@ int dcflow_batch_create(dcflow_plan *p, const dcflow_cands *c, int32_t n_var_max
   return DCFLOW_OK;
 }
 
-void dcflow_batch_destroy(dcflow_batch *b) { delete b; }
+namespace {
+void drop_graph(dcflow_batch *b) {
+  if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->graph_exec = nullptr;
+  b->graph = nullptr;
+}
+}  // namespace
+
+void dcflow_batch_destroy(dcflow_batch *b) {
+  if (!b) return;
+  drop_graph(b);
+  delete b;
+}
+
+int dcflow_batch_set_tuning(dcflow_batch *b, const dcflow_tuning *t) {
+  if (!b || !t) return DCFLOW_E_ARG;
+  if (t->scan_vc < 0 || t->scan_rchunk < 0 || t->scan_rchunk % 64 || t->persistent < 0)
+    return DCFLOW_E_ARG;
+  b->tune = *t;
+  return DCFLOW_OK;
+}
+
+int dcflow_batch_get_tuning(const dcflow_batch *b, dcflow_tuning *t) {
+  if (!b || !t) return DCFLOW_E_ARG;
+  *t = b->tune;
+  return DCFLOW_OK;
+}
+
+int dcflow_graph_capture(dcflow_batch *b, const double *dev_inj, int32_t n_var,
+                         int32_t inj_shared, dcflow_prec prec, void *dev_flows, size_t flow_bytes,
+                         dcflow_score *dev_out, hipStream_t s) {
+  if (!b || !s) return DCFLOW_E_ARG;
+  drop_graph(b);
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return hip_fail(e, "dcflow_graph_capture");
+  int rc = dcflow_eval_topologies(b, s);
+  if (rc == DCFLOW_OK)
+    rc = dcflow_eval_injections(b, dev_inj, n_var, inj_shared, prec, dev_flows, flow_bytes, s);
+  if (rc == DCFLOW_OK) rc = dcflow_n1_score(b, dev_flows, n_var, prec, dev_out, s);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(s, &g);
+  if (rc != DCFLOW_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "dcflow_graph_capture");
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(e, "dcflow_graph_capture");
+  }
+  b->graph = g;
+  b->graph_exec = x;
+  return DCFLOW_OK;
+}
+
+int dcflow_graph_launch(dcflow_batch *b, hipStream_t s) {
+  if (!b || !b->graph_exec) return DCFLOW_E_ARG;
+  hipError_t e = hipGraphLaunch(b->graph_exec, s);
+  return e == hipSuccess ? DCFLOW_OK : hip_fail(e, "dcflow_graph_launch");
+}
 
 int dcflow_eval_topologies(dcflow_batch *b, hipStream_t s) {
   if (!b) return DCFLOW_E_ARG;

@@ -75,6 +75,11 @@ struct dcflow_batch {
   double *d_z;      // [n_elem][vmax]
   double *d_vmax;   // [n_cand][vmax]
   double *d_f0;     // [vmax][ld_er] shared-injection GEMM output
+  int32_t *d_queue; // [16] work-queue counters of the persistent scan
+  dcflow_tuning tune;
+  int n_cu;               // compute units of the device the batch was created on
+  hipGraph_t graph;       // captured step (dcflow_graph_capture), or null
+  hipGraphExec_t graph_exec;
   int factored;     // eval_topologies enqueued
   int flows_prec;   // precision of the last eval_injections (-1 none)
   int flows_nvar;

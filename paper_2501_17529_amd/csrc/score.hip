@@ -86,7 +86,37 @@ struct ScanArgs {
   dcflow_score *res;
   int rchunk;  // rows per LDS chunk (multiple of 64)
   int single;  // one variant: pass 2 alone
+  // persistent mode: resident workgroups take candidates from a queue (descending rank)
+  int persistent;
+  int n_cand;
+  const int32_t *order;  // [n_cand] queue order
+  int32_t *queue;        // counters: [variant group] for pass 1, [kQueueWin] for pass 2
 };
+
+constexpr int kQueueWin = 15;  // counter slot of pass 2
+
+// Resident workgroups per CU assumed by the persistent launches (the scan is
+// shaped for four; more would only wait, fewer still drain the queue).
+constexpr int kPersistPerCu = 4;
+
+// Runs body(cand) for this workgroup's candidates: its own (blockIdx.x) or, in
+// persistent mode, queue positions taken one at a time until the queue is empty.
+template <typename F>
+__device__ __forceinline__ void for_each_candidate(const ScanArgs &A, int slot, F body) {
+  if (!A.persistent) {
+    body(blockIdx.x);
+    return;
+  }
+  __shared__ int s_pos;
+  while (true) {
+    __syncthreads();  // the previous candidate is done with shared memory
+    if (threadIdx.x == 0) s_pos = atomicAdd(A.queue + slot, 1);
+    __syncthreads();
+    const int pos = s_pos;
+    if (pos >= A.n_cand) break;
+    body(A.order[pos]);
+  }
+}
 
 template <typename T>
 struct ScanCfg;
@@ -209,8 +239,8 @@ __device__ __forceinline__ T ycol(const T *Fv, const ScanArgs &A, int cand, int 
 }
 
 // ---------------------------------------------------------------- pass 1
-template <typename T, int VC, int MINW>
-__global__ void __launch_bounds__(256, MINW) k_scan_max(ScanArgs A) {
+template <typename T, int VC>
+__device__ __forceinline__ void scan_max_cand(const ScanArgs &A, int cand) {
   constexpr int TM = 64, TN = ScanCfg<T>::TN, NB = TN / 16;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int ld_o = A.ld_o, rchunk = A.rchunk;
@@ -220,7 +250,6 @@ __global__ void __launch_bounds__(256, MINW) k_scan_max(ScanArgs A) {
   __shared__ T s_n0[VC];
   __shared__ int s_nf[VC];
 
-  const int cand = blockIdx.x;
   const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, g = lane / 16, li = lane % 16;
   const int e0 = A.off[cand];
   const int k = A.off[cand + 1] - e0;
@@ -316,9 +345,14 @@ __global__ void __launch_bounds__(256, MINW) k_scan_max(ScanArgs A) {
   }
 }
 
+template <typename T, int VC, int MINW>
+__global__ void __launch_bounds__(256, MINW) k_scan_max(ScanArgs A) {
+  for_each_candidate(A, blockIdx.y, [&](int cand) { scan_max_cand<T, VC>(A, cand); });
+}
+
 // ---------------------------------------------------------------- pass 2
 template <typename T>
-__global__ void __launch_bounds__(256) k_scan_win(ScanArgs A) {
+__device__ __forceinline__ void scan_win_cand(const ScanArgs &A, int cand) {
   constexpr int TM = 64, TN = ScanCfg<T>::TN, NB = TN / 16;
   constexpr long long kNoKey = 0x7fffffffffffffffLL;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -330,7 +364,6 @@ __global__ void __launch_bounds__(256) k_scan_win(ScanArgs A) {
   __shared__ long long s_key[4];
   __shared__ int s_nf, s_vstar;
 
-  const int cand = blockIdx.x;
   const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, g = lane / 16, li = lane % 16;
   const int e0 = A.off[cand];
   const int k = A.off[cand + 1] - e0;
@@ -546,29 +579,74 @@ __global__ void __launch_bounds__(256) k_scan_win(ScanArgs A) {
   }
 }
 
+template <typename T, int MINW>
+__global__ void __launch_bounds__(256, MINW) k_scan_win(ScanArgs A) {
+  for_each_candidate(A, kQueueWin, [&](int cand) { scan_win_cand<T>(A, cand); });
+}
+
+// Clears the work-queue counters (a kernel, so that a captured graph resets them too).
+__global__ void k_queue_reset(int32_t *q, int n) {
+  if ((int)threadIdx.x < n) q[threadIdx.x] = 0;
+}
+
 // ---------------------------------------------------------------- launch
 constexpr size_t kLdsBudget = 64 * 1024;   // dynamic LDS per workgroup, at most
 constexpr size_t kLdsOccupancy = 38 * 1024; // fits four workgroups per CU
 
-// rows per chunk: the largest multiple of 64 keeping the block within `target`
-// bytes (at least 64 rows), capped at the padded monitored rows
-inline int pick_rchunk(size_t fixed, size_t per_row, int mon_pad, size_t target) {
-  const size_t cap = target > fixed ? (target - fixed) / per_row : 0;
-  int rc = (int)(cap / 64 * 64);
-  if (rc < 64) rc = 64;
+// Rows per chunk: the requested count (a multiple of 64, capped at the padded
+// monitored rows) or, by default, the largest multiple of 64 that keeps the
+// block within `target` bytes (at least 64 rows).
+inline int choose_rchunk(int req, size_t fixed, size_t per_row, int mon_pad, size_t target) {
+  int rc = req;
+  if (rc <= 0) {
+    const size_t cap = target > fixed ? (target - fixed) / per_row : 0;
+    rc = (int)(cap / 64 * 64);
+    if (rc < 64) rc = 64;
+  }
   return rc < mon_pad ? rc : mon_pad;
 }
 
+inline int grid_x(const dcflow_batch *bt, const ScanArgs &a) {
+  if (!a.persistent) return bt->n_cand;
+  const int resident = bt->n_cu * kPersistPerCu;
+  return bt->n_cand < resident ? bt->n_cand : resident;
+}
+
 template <typename T, int VC, int MINW>
-hipError_t launch_max(const ScanArgs &a0, int n_cand, int nvar, hipStream_t s) {
+hipError_t launch_max(const ScanArgs &a0, const dcflow_batch *bt, int nvar, hipStream_t s) {
   ScanArgs a = a0;
   const size_t fixed = sizeof(T) * (size_t)VC * a.ld_o;
-  a.rchunk = pick_rchunk(fixed, sizeof(T) * VC, a.mon_pad, kLdsOccupancy);
+  a.rchunk = choose_rchunk(bt->tune.scan_rchunk, fixed, sizeof(T) * VC, a.mon_pad, kLdsOccupancy);
   const size_t lds = fixed + sizeof(T) * (size_t)VC * a.rchunk;
   if (lds > kLdsBudget) return hipErrorInvalidValue;
-  k_scan_max<T, VC, MINW><<<dim3(n_cand, (nvar + VC - 1) / VC), dim3(256), lds, s>>>(a);
+  const int ny = (nvar + VC - 1) / VC;
+  if (ny > kQueueWin) a.persistent = 0;  // one counter per variant group
+  k_scan_max<T, VC, MINW><<<dim3(grid_x(bt, a), ny), dim3(256), lds, s>>>(a);
   DCF_CHECK_LAUNCH();
   return hipSuccess;
+}
+
+// variant-group widths compiled per precision (pass 1)
+template <typename T>
+struct VcSet;
+template <>
+struct VcSet<float> {
+  static constexpr int v[4] = {16, 8, 4, 1};
+};
+template <>
+struct VcSet<double> {
+  static constexpr int v[4] = {8, 4, 2, 1};
+};
+
+template <typename T>
+hipError_t launch_max_vc(const ScanArgs &a, const dcflow_batch *bt, int nvar, int vc,
+                         hipStream_t s) {
+  constexpr bool F32 = sizeof(T) == 4;
+  constexpr int V0 = VcSet<T>::v[0], V1 = VcSet<T>::v[1], V2 = VcSet<T>::v[2];
+  if (vc == V0) return launch_max<T, V0, F32 ? 4 : 2>(a, bt, nvar, s);
+  if (vc == V1) return launch_max<T, V1, F32 ? 4 : 2>(a, bt, nvar, s);
+  if (vc == V2) return launch_max<T, V2, 1>(a, bt, nvar, s);
+  return launch_max<T, 1, 1>(a, bt, nvar, s);
 }
 
 template <typename T>
@@ -599,24 +677,37 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   a.vmax_ld = bt->vmax;
   a.res = out;
   a.single = nvar == 1;  // one variant: the winner pass alone gives everything
+  a.persistent = bt->tune.persistent ? 1 : 0;
+  a.n_cand = bt->n_cand;
+  a.order = bt->d_order;
+  a.queue = bt->d_queue;
+  a.rchunk = 0;
+  if (a.persistent) {
+    k_queue_reset<<<1, 64, 0, s>>>(bt->d_queue, kQueueWin + 1);
+    DCF_CHECK_LAUNCH();
+  }
   if (!a.single) {
-    // the widest variant group whose y fits the LDS budget with one 64-row chunk
-    constexpr int kV0 = sizeof(T) == 4 ? 16 : 8, kV1 = kV0 / 4;
+    // the requested variant group, else the widest whose y fits the LDS budget
+    // with one 64-row chunk and that the variants fill
     auto fits = [&](int vc) { return sizeof(T) * (size_t)vc * (p->ld_o + 64) <= kLdsBudget; };
-    hipError_t e;
-    if (fits(kV0) && nvar > kV1)
-      e = launch_max<T, kV0, sizeof(T) == 4 ? 4 : 2>(a, bt->n_cand, nvar, s);
-    else if (fits(kV1) && nvar > 1)
-      e = launch_max<T, kV1, 1>(a, bt->n_cand, nvar, s);
-    else
-      e = launch_max<T, 1, 1>(a, bt->n_cand, nvar, s);
+    int vc = bt->tune.scan_vc;
+    bool known = false;
+    for (int i = 0; i < 4; ++i) known |= vc == VcSet<T>::v[i];
+    if (!known || !fits(vc)) {
+      vc = 1;
+      for (int i = 2; i >= 0; --i) {
+        const int c = VcSet<T>::v[i];
+        if (fits(c) && (i == 2 ? nvar > 1 : nvar > VcSet<T>::v[i + 1])) vc = c;
+      }
+    }
+    const hipError_t e = launch_max_vc<T>(a, bt, nvar, vc, s);
     if (e != hipSuccess) return e;
   }
   const size_t fixed = sizeof(T) * 2 * (size_t)p->ld_o;
-  a.rchunk = pick_rchunk(fixed, sizeof(T), p->mon_pad, kLdsOccupancy);
+  a.rchunk = choose_rchunk(bt->tune.scan_rchunk, fixed, sizeof(T), p->mon_pad, kLdsOccupancy);
   const size_t lds = fixed + sizeof(T) * (size_t)a.rchunk;
   if (lds > kLdsBudget) return hipErrorInvalidValue;
-  k_scan_win<T><<<dim3(bt->n_cand), dim3(256), lds, s>>>(a);
+  k_scan_win<T, sizeof(T) == 4 ? 4 : 1><<<dim3(grid_x(bt, a)), dim3(256), lds, s>>>(a);
   DCF_CHECK_LAUNCH();
   return hipSuccess;
 }

@@ -53,6 +53,15 @@ class Cands(ctypes.Structure):
                 ("id", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("p_new", ctypes.c_void_p)]
 
 
+class Tuning(ctypes.Structure):
+    """dcflow_tuning: launch shapes of the N-1 scan (0 = automatic)."""
+    _fields_ = [("scan_vc", ctypes.c_int32), ("scan_rchunk", ctypes.c_int32),
+                ("persistent", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class PlanView(ctypes.Structure):
     _fields_ = [("n_bus", ctypes.c_int32), ("n_branch", ctypes.c_int32), ("n_mon", ctypes.c_int32),
                 ("n_out", ctypes.c_int32), ("n_er", ctypes.c_int32), ("ld_h", ctypes.c_int32),
@@ -90,6 +99,10 @@ def _load():
         "dcflow_mlp_bf16_bytes": (SZ, []),
         "dcflow_mlp_workspace_bytes": (SZ, [I32]),
         "dcflow_snapshot_flows": (ctypes.c_int, [P, P, I32, P, P, P]),
+        "dcflow_batch_set_tuning": (ctypes.c_int, [P, P]),
+        "dcflow_batch_get_tuning": (ctypes.c_int, [P, P]),
+        "dcflow_graph_capture": (ctypes.c_int, [P, P, I32, I32, ctypes.c_int, P, SZ, P, P]),
+        "dcflow_graph_launch": (ctypes.c_int, [P, P]),
         "dcflow_snapshot_pairs": (ctypes.c_int, [P, P, I32, P, P, P]),
         "dcflow_action_features": (ctypes.c_int, [P, P, P, P, P, P, I32, P, P, P, P, P, P]),
         "dcflow_improvement_labels": (ctypes.c_int, [P, P, P, I32, P, P]),
@@ -114,7 +127,8 @@ EXPORTED = ("dcflow_plan_workspace_bytes", "dcflow_build_ptdf", "dcflow_plan_vie
             "dcflow_plan_destroy", "dcflow_validate_candidates", "dcflow_batch_bytes",
             "dcflow_batch_create", "dcflow_batch_destroy", "dcflow_eval_topologies",
             "dcflow_flow_bytes", "dcflow_eval_injections", "dcflow_n1_score",
-            "dcflow_batch_variant_max", "dcflow_strerror", "dcflow_mlp_param_count",
+            "dcflow_batch_variant_max", "dcflow_strerror", "dcflow_batch_set_tuning",
+            "dcflow_batch_get_tuning", "dcflow_graph_capture", "dcflow_graph_launch", "dcflow_mlp_param_count",
             "dcflow_mlp_bf16_bytes", "dcflow_mlp_workspace_bytes", "dcflow_snapshot_flows",
             "dcflow_snapshot_pairs", "dcflow_action_features", "dcflow_improvement_labels",
             "dcflow_mlp_forward", "dcflow_mlp_grad", "dcflow_mlp_adam",
@@ -316,6 +330,29 @@ class Batch:
                                     PREC[prec], ctypes.c_void_p(out.data_ptr()), _stream(stream)),
                "dcflow_n1_score")
         return out
+
+    def set_tuning(self, scan_vc=0, scan_rchunk=0, persistent=0):
+        t = Tuning(int(scan_vc), int(scan_rchunk), int(persistent))
+        _check(_lib.dcflow_batch_set_tuning(self.h, ctypes.byref(t)), "dcflow_batch_set_tuning")
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(_lib.dcflow_batch_get_tuning(self.h, ctypes.byref(t)), "dcflow_batch_get_tuning")
+        return t.as_dict()
+
+    def capture(self, inj, n_var, shared, prec, flows, out, stream):
+        """Captures eval_topologies -> eval_injections -> n1_score with these
+        buffers into the batch's HIP graph (stream: a torch.cuda.Stream, not the
+        null stream); replay() then runs the whole step with one launch."""
+        _check(_lib.dcflow_graph_capture(self.h, ctypes.c_void_p(inj.data_ptr()), int(n_var),
+                                         int(bool(shared)), PREC[prec],
+                                         ctypes.c_void_p(flows.data_ptr()),
+                                         flows.numel() * flows.element_size(),
+                                         ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+               "dcflow_graph_capture")
+
+    def replay(self, stream=None):
+        _check(_lib.dcflow_graph_launch(self.h, _stream(stream)), "dcflow_graph_launch")
 
     def variant_max(self, n_var):
         import torch
