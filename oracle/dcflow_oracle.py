@@ -221,7 +221,44 @@ def ratings(n, f, t, b, slack, p_base, mon, scale=1.2, offset=0.1):
 
 # ---------------------------------------------------- per-candidate solve
 
-def candidate_flows(n, f, t, b, slack, elems, x, out):
+def control_terms(n2, f2, t2, alive, b, controls, ctrl):
+    """Nodal injections and direct branch-flow terms of the controls (the end of
+    Sec. II names phase shifters and HVDC links, modelled through PSDF/DCDF,
+    without formulas; the DC models used here):
+
+      * a phase-shifting transformer of angle alpha (rad) in series with branch l:
+        p_l = b_l (theta_f - theta_t - alpha), i.e. Kirchhoff's law sees an extra
+        injection b_l alpha at f and -b_l alpha at t, and the flow on l itself
+        carries -b_l alpha on top of b_l (theta_f - theta_t); a phase shifter on
+        a removed branch does nothing;
+      * an HVDC link from bus i to bus j with setpoint P withdraws P at i and
+        injects it at j.
+
+    controls = dict(pst=[branch ids], hvdc=[(i, j)], pst_scale (rad per unit of
+    ctrl), hvdc_scale (p.u. per unit of ctrl)); ctrl [V, n_pst + n_hvdc].
+    Terminals are those of the (possibly rebuilt) network f2, t2.
+    Returns (dp [V, n2], dflow [V, m])."""
+    ctrl = np.atleast_2d(np.asarray(ctrl, np.float64))
+    v = ctrl.shape[0]
+    pst = list(controls.get("pst", []))
+    hvdc = list(controls.get("hvdc", []))
+    dp = np.zeros((v, n2))
+    dflow = np.zeros((v, len(f2)))
+    for q, l in enumerate(pst):
+        if not alive[l]:
+            continue
+        a = ctrl[:, q] * controls.get("pst_scale", np.pi / 180.0)
+        dp[:, f2[l]] += b[l] * a
+        dp[:, t2[l]] -= b[l] * a
+        dflow[:, l] -= b[l] * a
+    for q, (i, j) in enumerate(hvdc):
+        pv = ctrl[:, len(pst) + q] * controls.get("hvdc_scale", 1.0)
+        dp[:, i] -= pv
+        dp[:, j] += pv
+    return dp, dflow
+
+
+def candidate_flows(n, f, t, b, slack, elems, x, out, controls=None, ctrl=None):
     """N-0 flows and N-1 flows of a candidate, by rebuild + dense LU.
 
     Returns dict with
@@ -245,10 +282,17 @@ def candidate_flows(n, f, t, b, slack, elems, x, out):
     br = nodal_susceptance(n2, fa, ta, ba)[np.ix_(keep, keep)]
     lu = sla.lu_factor(br)
     p = candidate_injections(n2, x, splits, slack)
+    dflow = None
+    if controls is not None:
+        dp, dflow = control_terms(n2, f2, t2, alive, np.asarray(b), controls, ctrl)
+        p = p + dp
+        p[:, slack] = 0.0
     theta = np.zeros((p.shape[0], n2))
     theta[:, keep] = sla.lu_solve(lu, p[:, keep].T).T
     p0 = np.zeros((p.shape[0], m))
     p0[:, alive] = ba * (theta[:, fa] - theta[:, ta])
+    if dflow is not None:
+        p0 = p0 + dflow
     res["p0"] = p0
 
     out = np.asarray(out, np.int64)
@@ -278,10 +322,11 @@ def candidate_flows(n, f, t, b, slack, elems, x, out):
     return res
 
 
-def n1_flows_bruteforce(n, f, t, b, slack, elems, x, out):
+def n1_flows_bruteforce(n, f, t, b, slack, elems, x, out, controls=None, ctrl=None):
     """N-1 flows by rebuilding the candidate network without each contingency
-    and solving again (one factorisation per case).  Returns (p1 [V, |O|, m],
-    islanded [|O|])."""
+    and solving again (one factorisation per case), controls included with the
+    model of control_terms on each post-contingency network.  Returns
+    (p1 [V, |O|, m], islanded [|O|])."""
     n2, f2, t2, alive, splits = rebuild(n, f, t, elems)
     p = candidate_injections(n2, x, splits, slack)
     m = len(f2)
@@ -297,13 +342,19 @@ def n1_flows_bruteforce(n, f, t, b, slack, elems, x, out):
             isl[ci] = True
             continue
         br = nodal_susceptance(n2, fa, ta, ba)[np.ix_(keep, keep)]
+        pc, dflow = p, None
+        if controls is not None:
+            dp, dflow = control_terms(n2, f2, t2, al, np.asarray(b), controls, ctrl)
+            pc = p + dp
         theta = np.zeros((p.shape[0], n2))
-        theta[:, keep] = sla.solve(br, p[:, keep].T).T
+        theta[:, keep] = sla.solve(br, pc[:, keep].T).T
         p1[:, ci, al] = ba * (theta[:, fa] - theta[:, ta])
+        if dflow is not None:
+            p1[:, ci, :] += dflow
     return p1, isl
 
 
-def score_candidate(n, f, t, b, slack, elems, x, mon, out, rating):
+def score_candidate(n, f, t, b, slack, elems, x, mon, out, rating, controls=None, ctrl=None):
     """Score one candidate over its injection variants (Sec. III-A).
 
     Returns dict(max_load [V], best_variant, best_max_load, overload_sum,
@@ -311,7 +362,11 @@ def score_candidate(n, f, t, b, slack, elems, x, mon, out, rating):
     mon = np.asarray(mon, np.int64)
     out = np.asarray(out, np.int64)
     r = np.asarray(rating, np.float64)
-    cf = candidate_flows(n, f, t, b, slack, elems, x, out)
+    if controls is not None:
+        # the N-1 step below superposes the LODF on the N-0 flows, which holds for a
+        # fixed phase shift only while the tripped branch carries none
+        assert not set(int(c) for c in out) & set(int(l) for l in controls.get("pst", []))
+    cf = candidate_flows(n, f, t, b, slack, elems, x, out, controls, ctrl)
     nv = np.atleast_2d(x).shape[0]
     if not cf["connected"]:
         return dict(max_load=np.full(nv, np.inf), best_variant=-1, best_max_load=np.inf,

@@ -347,3 +347,64 @@ def test_fig1_packing_counts_fixture():
     # shared-prefix tree: distinct prefixes of the sorted split lists
     prefixes = {tuple(sorted(c)[:i + 1]) for c in fx["candidates"] for i in range(len(c))}
     assert len(prefixes) == fx["tree_applications"]
+
+
+# ------------------------------------------------ controls (phase shifters, HVDC)
+
+def test_pst_parallel_lines_closed_form():
+    """Two parallel lines 0-1 (b1 carries a phase shifter of angle a), injection P
+    at bus 1, slack 0: p_A = -(b1 P + b1 b2 a)/(b1 + b2), p_B = -(b2 P - b1 b2 a)/(b1 + b2)
+    (a loop flow b1 b2 a/(b1 + b2) circulates)."""
+    f, t = np.array([0, 0]), np.array([1, 1])
+    b1, b2, P, a_deg = 4.0, 6.0, 0.7, 7.0
+    b = np.array([b1, b2])
+    a = np.deg2rad(a_deg)
+    cf = O.candidate_flows(2, f, t, b, 0, [], np.array([[0.0, P]]), [],
+                           controls=dict(pst=[0]), ctrl=np.array([[a_deg]]))
+    p = cf["p0"][0]
+    assert abs(p[0] - (-(b1 * P + b1 * b2 * a) / (b1 + b2))) < 1e-13
+    assert abs(p[1] - (-(b2 * P - b1 * b2 * a) / (b1 + b2))) < 1e-13
+
+
+def test_hvdc_on_a_tree_closed_form():
+    """On a path graph an HVDC transfer of P from bus i to bus j loads every branch
+    between them with P (in the direction j -> i in the AC network), the rest 0."""
+    n = 6
+    f, t = np.arange(n - 1), np.arange(1, n)
+    b = np.linspace(1.0, 3.0, n - 1)
+    P = 0.9   # level 3 at 0.3 p.u. per level
+    cf = O.candidate_flows(n, f, t, b, 0, [], np.zeros((1, n)), [],
+                           controls=dict(hvdc=[(1, 4)], hvdc_scale=0.3), ctrl=np.array([[3.0]]))
+    p = cf["p0"][0]
+    # bus 1 gives P, bus 4 takes P: the AC network returns P from 4 to 1 over branches 1..3
+    np.testing.assert_allclose(p, [0.0, -P, -P, -P, 0.0], atol=1e-13)
+
+
+def test_n1_with_controls_matches_bruteforce():
+    """LODF superposition on N-0 flows with phase shifters and HVDC links equals
+    re-solving every post-contingency network with the control model, when the
+    contingencies are not phase-shifter branches (also after splits and outages)."""
+    w = G.workload_tiny(0)
+    g = w.grid
+    nb = np.flatnonzero(~O.bridges(g.n_bus, g.f, g.t))
+    pst = [int(nb[0]), int(nb[4])]
+    controls = dict(pst=pst, hvdc=[(3, 17), (8, 25)], hvdc_scale=0.25)
+    rng = np.random.default_rng(2)
+    ctrl = np.column_stack([rng.integers(-10, 11, size=(4, 2)), rng.integers(0, 8, size=(4, 2))])
+    x = G.perturbed_injections(g, rng, (4,), 0.2)
+    out = [int(c) for c in nb if int(c) not in pst][:12]
+    a = int(np.flatnonzero(g.degree() >= 3)[2])
+    cands = [[], [(G.KIND_OUTAGE, out[5], 0, 0.0)], [(G.KIND_SPLIT, a, 2, 0.4)]]
+    for els in cands:
+        if any(k == G.KIND_SPLIT and (g.f[pst] == d).any() | (g.t[pst] == d).any()
+               for k, d, _, _ in els):
+            continue
+        cf = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, els, x, out, controls, ctrl)
+        p1, isl = O.n1_flows_bruteforce(g.n_bus, g.f, g.t, g.b, g.slack, els, x, out, controls,
+                                        ctrl)
+        for ci, c in enumerate(out):
+            if cf["state"][ci] != 0:
+                continue
+            sup = cf["p0"] + cf["lodf"][:, ci][None, :] * cf["p0"][:, c][:, None]
+            sup[:, c] = 0.0
+            np.testing.assert_allclose(sup, p1[:, ci, :], atol=1e-10)
