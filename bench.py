@@ -75,9 +75,11 @@ def _source_hash():
     return h.hexdigest()[:16]
 
 
-def run_path(D, torch, plan, w, prec, steps, warmup, tune=True, graph=True):
+def run_path(D, torch, plan, w, prec, steps, warmup, tune=True, graph=True, persistent=False):
     nv = w.n_var
     bt = D.Batch(plan, w.cands, nv)
+    if persistent:
+        bt.set_tuning(persistent=1)
     x = torch.from_numpy(np.ascontiguousarray(w.inj)).cuda()
     flows, _ = bt.flow_buffer(nv, prec)
     out = torch.empty(bt.n_cand * D.SCORE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
@@ -137,15 +139,28 @@ def run_path(D, torch, plan, w, prec, steps, warmup, tune=True, graph=True):
     return res
 
 
+WORKLOADS = {
+    "medium": ("medium-1000bus: 1,000 buses / 1,600 branches, 4,096 candidates (1-3 bus splits + "
+               "0-2 outages), 16 injection variants each, N-1 over 500 contingencies = monitored "
+               "branches"),
+    "uneven": ("uneven-10000bus, one GPU's share: 10,000 buses / 15,500 branches, {n} candidates "
+               "of rank uniform in 1..8 (of the 65,536-candidate batch), 1 injection each, every "
+               "branch monitored, N-1 over 2,000 contingencies, persistent launch"),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cands", type=int, default=4096)
-    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="medium")
+    ap.add_argument("--cands", type=int, default=0, help="candidates (default: 4,096 medium, "
+                    "8,192 uneven)")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="oracle sample size (default: 128 medium, 2 uneven)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--prec", choices=["both", "fp32", "fp64"], default="both")
+    ap.add_argument("--prec", choices=["all", "fp32", "fp64", "bf16x6", "bf16"], default="all")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -169,8 +184,15 @@ def main():
         return
 
     import gridgen as G
-    w = G.workload_medium(0, n_cand=a.cands)
-    cpu = None if a.no_cpu_baseline else cpu_baseline(w, min(a.cpu_sample, w.cands.n_cand))
+    if a.workload == "medium":
+        w = G.workload_medium(0, n_cand=a.cands or 4096)
+        precs = ["fp32", "fp64", "bf16x6"] if a.prec == "all" else [a.prec]
+        sample = a.cpu_sample or 128
+    else:
+        w = G.workload_uneven(0, n_cand=a.cands or 8192)
+        precs = ["fp32", "bf16x6"] if a.prec == "all" else [a.prec]
+        sample = a.cpu_sample or 2
+    cpu = None if a.no_cpu_baseline else cpu_baseline(w, min(sample, w.cands.n_cand))
 
     import torch
     from paper_2501_17529_amd import dcflow as D
@@ -182,32 +204,33 @@ def main():
 
     n_lf = w.cands.n_cand * w.n_var * len(w.out)
     res = {}
-    for prec in (["fp32", "fp64"] if a.prec == "both" else [a.prec]):
+    for prec in precs:
         res[prec] = run_path(D, torch, plan, w, prec, a.steps, a.warmup, tune=not a.no_autotune,
-                             graph=not a.no_graph)
-    main_prec = "fp32" if "fp32" in res else "fp64"
+                             graph=not a.no_graph, persistent=a.workload == "uneven")
+    main_prec = precs[0]
     r = res[main_prec]
     ms = r["wall"] / a.steps * 1e3
     value = n_lf / (ms / 1e3)
 
     # roofline of the dominant kernel (the N-1 scan, both passes): 2 flops (one FMA) per N-1
-    # element, (V + 1) variant sweeps (the winner is re-scanned once) over E_m x O per candidate
+    # element, (V + 1) variant sweeps (the winner is re-scanned once; with one variant the
+    # winner pass is the only sweep) over E_m x O per candidate
     scan_ms = float(r["phase_ms"][2])
-    flops = 2.0 * w.cands.n_cand * (w.n_var + 1) * len(w.mon) * len(w.out)
+    sweeps = w.n_var + 1 if w.n_var > 1 else 1
+    flops = 2.0 * w.cands.n_cand * sweeps * len(w.mon) * len(w.out)
     achieved = flops / (scan_ms / 1e3) / 1e12
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
+    if a.workload == "medium" and os.path.exists(TRAFFIC_FILE):
         tf = json.load(open(TRAFFIC_FILE))
         if tf.get("source_hash") == _source_hash() and tf.get("prec") == main_prec:
             traffic = tf.get("bytes_per_launch")
+    g = w.grid
     line = {
         "metric": METRIC, "value": value, "unit": "loadflows/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": main_prec, "data": "synthetic",
-        "config": {"workload": "medium-1000bus: 1,000 buses / 1,600 branches, 4,096 candidates "
-                               "(1-3 bus splits + 0-2 outages), 16 injection variants each, "
-                               "N-1 over 500 contingencies = monitored branches",
-                   "n_bus": 1000, "n_branch": 1600, "candidates": w.cands.n_cand,
+        "config": {"workload": WORKLOADS[a.workload].format(n=f"{w.cands.n_cand:,}"),
+                   "n_bus": g.n_bus, "n_branch": g.n_branch, "candidates": w.cands.n_cand,
                    "variants": w.n_var, "contingencies": len(w.out), "monitored": len(w.mon),
                    "loadflows_per_step": n_lf, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": "k_scan (per-variant N-1 maxima + winner pass)",
@@ -221,11 +244,14 @@ def main():
         "eager_ms_per_step": r["wall_eager"] / a.steps * 1e3,
         "scan_tuning": {p: v.get("tuning") for p, v in res.items()},
     }
-    if "fp64" in res and main_prec != "fp64":
-        ms64 = res["fp64"]["wall"] / a.steps * 1e3
-        line["fp64_path"] = {"value": n_lf / (ms64 / 1e3), "ms_per_step": ms64}
-        s32, s64 = res["fp32"]["scores"], res["fp64"]["scores"]
-        line["fp32_vs_fp64_max_load_absdiff"] = float(np.abs(s32["max_load"] - s64["max_load"]).max())
+    for p, v in res.items():
+        if p == main_prec:
+            continue
+        msp = v["wall"] / a.steps * 1e3
+        line[f"{p}_path"] = {"value": n_lf / (msp / 1e3), "ms_per_step": msp}
+        if p != "bf16":
+            line[f"{main_prec}_vs_{p}_max_load_absdiff"] = float(
+                np.abs(r["scores"]["max_load"] - v["scores"]["max_load"]).max())
     line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 

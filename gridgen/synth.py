@@ -27,6 +27,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass, field
 
+from typing import Optional
+
 import numpy as np
 from scipy.sparse import coo_matrix
 from scipy.sparse.csgraph import connected_components
@@ -124,6 +126,9 @@ class Workload:
     rating_scale: float = 1.2
     rating_offset: float = 0.1
     meta: dict = field(default_factory=dict)
+    # controls: None or dict(pst=[branch ids], pst_scale, hvdc=[(i, j)], hvdc_scale);
+    # their values follow the n nodal entries of every injection vector
+    controls: Optional[dict] = None
 
     @property
     def n_var(self) -> int:
@@ -284,7 +289,7 @@ def random_split(grid: Grid, rng, bus: int):
 
 
 def sample_candidate(grid: Grid, rng, n_split: int, n_out: int, split_buses=None,
-                     max_tries: int = 200):
+                     max_tries: int = 200, forbid_out=()):
     """One connected candidate with ``n_split`` bus splits then ``n_out``
     remedial outages: a uniform set of distinct branches that keeps the
     candidate grid connected."""
@@ -308,7 +313,7 @@ def sample_candidate(grid: Grid, rng, n_split: int, n_out: int, split_buses=None
             outs = []
             while len(outs) < n_out:
                 br = int(rng.integers(grid.n_branch))
-                if br not in outs:
+                if br not in outs and br not in forbid_out:
                     outs.append(br)
             al = alive.copy()
             al[outs] = False
@@ -388,3 +393,61 @@ def workload_uneven(seed: int = 0, n_cand: int = 65536, n_out: int = 2000,
                     meta=dict(n_bus=n_bus, n_branch=n_branch, n_cand=n_cand, n_var=1,
                               n_out=n_out))
 
+
+
+def _hops(grid: Grid, src: int) -> np.ndarray:
+    """Breadth-first hop counts from bus ``src``."""
+    adj = [[] for _ in range(grid.n_bus)]
+    for a, c in zip(grid.f, grid.t):
+        adj[int(a)].append(int(c))
+        adj[int(c)].append(int(a))
+    d = np.full(grid.n_bus, -1)
+    d[src] = 0
+    q = [src]
+    for u in q:
+        for v in adj[u]:
+            if d[v] < 0:
+                d[v] = d[u] + 1
+                q.append(v)
+    return d
+
+
+def workload_brute(seed: int = 0, n_topo: int = 1024, n_comb: int = 4096, n_out: int = 1000,
+                   n_bus: int = 2000, n_branch: int = 3100, n_pst: int = 20,
+                   n_hvdc: int = 4) -> Workload:
+    """Injection brute force: 2,000 buses / 3,100 branches with 20 phase shifters
+    (random non-bridges) and 4 HVDC links (random bus pairs at least 5 hops
+    apart); topologies as in the medium workload (1-3 splits + 0-2 outages) that
+    leave the phase shifters and their buses alone; the same n_comb control and
+    load combinations for every topology (integer shifter degrees in -10..10,
+    HVDC levels 0..7 of 0.25 p.u., loads perturbed by N(0, 0.05)); every branch
+    monitored, n_out contingencies among the non-bridges that are not shifters."""
+    rng = np.random.default_rng(seed + 4000)
+    grid = make_grid(n_bus, n_branch, seed)
+    pst = [int(x) for x in non_bridges(grid, rng, n_pst)]
+    hvdc = []
+    while len(hvdc) < n_hvdc:
+        i = int(rng.integers(n_bus))
+        far = np.flatnonzero(_hops(grid, i) >= 5)
+        if len(far):
+            hvdc.append((i, int(rng.choice(far))))
+    pst_set = set(pst)
+    cand_out = [int(x) for x in non_bridges(grid, rng, n_out + n_pst) if int(x) not in pst_set]
+    out = np.sort(np.asarray(cand_out[:n_out], np.int32))
+    pst_bus = {int(grid.f[l]) for l in pst} | {int(grid.t[l]) for l in pst}
+    sb = np.asarray([a for a in _split_buses(grid) if int(a) not in pst_bus])
+    lists = []
+    for _ in range(n_topo):
+        lists.append(sample_candidate(grid, rng, int(rng.integers(1, 4)), int(rng.integers(0, 3)),
+                                      sb, forbid_out=pst_set))
+    cands = Candidates.from_lists(lists)
+    loads = perturbed_injections(grid, rng, (n_comb,), 0.05)
+    deg = rng.integers(-10, 11, size=(n_comb, n_pst)).astype(np.float64)
+    lev = rng.integers(0, 8, size=(n_comb, n_hvdc)).astype(np.float64)
+    inj = np.concatenate([loads, deg, lev], axis=1)
+    mon = np.arange(grid.n_branch, dtype=np.int32)
+    controls = dict(pst=pst, pst_scale=np.pi / 180.0, hvdc=hvdc, hvdc_scale=0.25)
+    return Workload("brute-2000bus", grid, mon, out, cands, inj, True,
+                    meta=dict(n_bus=n_bus, n_branch=n_branch, n_topo=n_topo, n_comb=n_comb,
+                              n_out=n_out, n_pst=n_pst, n_hvdc=n_hvdc),
+                    controls=controls)

@@ -62,9 +62,20 @@ typedef enum {
 } dcflow_status;
 
 typedef enum {
-  DCFLOW_FP64 = 0,  /* every step in FP64 (plain path)                         */
-  DCFLOW_FP32 = 1   /* injection GEMM on FP32 MFMA, N-1 scan in FP32; the k x k
-                       solve, LODF denominators and LODF' tile build in FP64    */
+  DCFLOW_FP64 = 0,   /* every step in FP64 (plain path)                         */
+  DCFLOW_FP32 = 1,   /* injection GEMM on FP32 MFMA, LODF' tile build and N-1
+                        scan in FP32; the k x k solve, U, W, z and the LODF
+                        denominators in FP64.  The GEMM of every mode takes
+                        x - p_base and adds the FP64 base flows back
+                        (Eq. ptdf_times_nodal_inj is linear), which keeps the
+                        cancellation of large grids out of the FP32 sums        */
+  DCFLOW_BF16 = 2,   /* as FP32, but the injection GEMM takes BF16 operands
+                        (FP32 accumulation): fast and coarse (flow errors of the
+                        order of 0.1 of the smallest ratings), for pre-screening */
+  DCFLOW_BF16X6 = 3  /* as FP32, but the injection GEMM splits each operand into
+                        three BF16 parts and sums the six cross products of
+                        order <= 2 on BF16 MFMA with FP32 accumulation: FP32-level
+                        flow accuracy at a fraction of the FP32 MFMA time         */
 } dcflow_prec;
 
 /* Candidate element kinds. */
@@ -96,6 +107,24 @@ typedef struct {
   const double *rating;   /* [n_mon] > 0, or NULL: rating_scale*|F_base| + rating_offset */
   double rating_scale;
   double rating_offset;
+  /* Controls (optional: zero counts and NULL pointers for none).  Each control is
+   * one more entry of every injection vector, after the n_bus nodal injections:
+   * injection vectors have n_inj = n_bus + n_pst + n_hvdc entries, the phase
+   * shifters first.  Their flow sensitivities (PSDF, DCDF; named at the end of
+   * Sec. II) become extra PTDF columns:
+   *   phase shifter on branch l (from f to t), value a:  p_l = b_l (theta_f -
+   *     theta_t - pst_scale a), column pst_scale b_l (PTDF[:, f] - PTDF[:, t] - e_l);
+   *   HVDC link from bus i to bus j, value P: moves hvdc_scale P from i to j,
+   *     column hvdc_scale (PTDF[:, j] - PTDF[:, i]).
+   * The base case has all controls at 0.  Phase-shifter branches may not be
+   * contingencies, outaged or moved by a split (E_ARG / E_CAND). */
+  int32_t n_pst;
+  const int32_t *pst_branch;   /* [n_pst] distinct branch ids                    */
+  double pst_scale;            /* radians per unit (pi / 180 for degrees)        */
+  int32_t n_hvdc;
+  const int32_t *hvdc_from;    /* [n_hvdc] bus ids                               */
+  const int32_t *hvdc_to;      /* [n_hvdc] bus ids, != hvdc_from                 */
+  double hvdc_scale;           /* p.u. per unit                                  */
 } dcflow_grid_desc;
 
 /* Topology candidates in CSR form (host pointers).  Candidate i owns
@@ -136,6 +165,7 @@ typedef struct {
   const double *f_base;  /* [n_branch] base flows PTDF p_base                   */
   const double *rating;  /* [n_mon] ratings used by the score                   */
   const int32_t *er;     /* [n_er] kept rows: E_m first, then O \ E_m          */
+  int32_t n_inj;         /* entries per injection vector (n_bus + controls)    */
 } dcflow_plan_view;
 
 typedef struct dcflow_plan dcflow_plan;

@@ -60,7 +60,8 @@ def _store(path, data):
 def candidates(batch: "D.Batch", n_var: int, prec: str):
     """The launch shapes worth timing for this batch."""
     mon_pad = (batch.plan.view.n_mon + 63) // 64 * 64
-    vcs = [0] + [v for v in VC_SETS[prec] if v <= max(1, n_var) and v > 1]
+    vcs = [0] + [v for v in VC_SETS["fp64" if prec == "fp64" else "fp32"]
+                 if v <= max(1, n_var) and v > 1]
     rcs = sorted({0} | {r for r in (64, 128, 256, 512) if r <= mon_pad})
     return [dict(scan_vc=vc, scan_rchunk=rc, persistent=pe)
             for vc in vcs for rc in rcs for pe in (0, 1)]

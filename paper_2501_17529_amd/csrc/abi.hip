@@ -55,6 +55,25 @@ int check_grid(const dcflow_grid_desc *g) {
   }
   for (int i = 0; i < g->n_bus; ++i)
     if (!std::isfinite(g->p_base[i])) return DCFLOW_E_ARG;
+  if (g->n_pst < 0 || g->n_hvdc < 0) return DCFLOW_E_SHAPE;
+  if (g->n_pst > 0) {
+    if (!g->pst_branch || !std::isfinite(g->pst_scale)) return DCFLOW_E_ARG;
+    std::vector<uint8_t> is_out(g->n_branch, 0), is_pst(g->n_branch, 0);
+    for (int i = 0; i < g->n_out; ++i) is_out[g->out[i]] = 1;
+    for (int q = 0; q < g->n_pst; ++q) {
+      const int l = g->pst_branch[q];
+      if (l < 0 || l >= g->n_branch || is_pst[l]) return DCFLOW_E_SHAPE;
+      if (is_out[l]) return DCFLOW_E_ARG;  // a tripped phase shifter is not a superposition
+      is_pst[l] = 1;
+    }
+  }
+  if (g->n_hvdc > 0) {
+    if (!g->hvdc_from || !g->hvdc_to || !std::isfinite(g->hvdc_scale)) return DCFLOW_E_ARG;
+    for (int q = 0; q < g->n_hvdc; ++q) {
+      const int i = g->hvdc_from[q], j = g->hvdc_to[q];
+      if (i < 0 || i >= g->n_bus || j < 0 || j >= g->n_bus || i == j) return DCFLOW_E_SHAPE;
+    }
+  }
   if (g->rating) {
     for (int i = 0; i < g->n_mon; ++i)
       if (!finite_pos(g->rating[i])) return DCFLOW_E_ARG;
@@ -83,7 +102,7 @@ bool grid_connected(const dcflow_grid_desc *g) {
 }
 
 struct Dims {
-  int n, m, n_mon, n_out, n_er, ld_h, ld_er, ld_o, mon_pad;
+  int n, m, n_mon, n_out, n_er, ld_h, ld_er, ld_o, mon_pad, n_ctrl;
 };
 
 Dims grid_dims(const dcflow_grid_desc *g) {
@@ -97,7 +116,8 @@ Dims grid_dims(const dcflow_grid_desc *g) {
   int extra = 0;
   for (int i = 0; i < g->n_out; ++i) extra += inmon[g->out[i]] ? 0 : 1;
   d.n_er = d.n_mon + extra;
-  d.ld_h = round_up(d.n, 16);
+  d.n_ctrl = g->n_pst + g->n_hvdc;
+  d.ld_h = round_up(d.n + d.n_ctrl, 16);
   d.ld_er = round_up(d.n_er, 128);
   d.ld_o = std::max(64, round_up(d.n_out, 64));
   d.mon_pad = round_up(d.n_mon, 64);
@@ -124,13 +144,21 @@ void plan_layout(dcflow_plan *p, const Dims &d, Arena &a) {
   p->d_ht = a.take<double>((size_t)d.n * d.ld_er);
   p->d_he64 = a.take<double>((size_t)d.ld_er * d.ld_h);
   p->d_he32 = a.take<float>((size_t)d.ld_er * d.ld_h);
+  p->d_heb = a.take<__bf16>(3 * (size_t)d.ld_er * d.ld_h);
   p->d_hdo = a.take<double>((size_t)d.m * d.ld_o);
   p->d_lsd = a.take<double>((size_t)d.mon_pad * d.ld_o);
   p->d_lsd32 = a.take<float>((size_t)d.mon_pad * d.ld_o);
   p->d_fbase = a.take<double>(d.m);
+  p->d_fber = a.take<double>(d.ld_er);
   p->d_pbase = a.take<double>(d.ld_h);
   p->d_rating = a.take<double>(d.mon_pad);
   p->d_inv_r = a.take<double>(d.mon_pad);
+  const size_t nc = std::max(d.n_ctrl, 1);
+  p->d_ctl_a = a.take<int32_t>(nc);
+  p->d_ctl_c = a.take<int32_t>(nc);
+  p->d_ctl_br = a.take<int32_t>(nc);
+  p->d_ctl_w = a.take<double>(nc);
+  p->d_ctl_d = a.take<double>(nc);
 }
 
 struct BatchDims {
@@ -159,7 +187,24 @@ void batch_layout(dcflow_batch *b, const dcflow_plan *p, const BatchDims &d, Are
   b->d_queue = a.take<int32_t>(16);
 }
 
+void pst_flags(const dcflow_grid_desc *g, std::vector<uint8_t> &br, std::vector<uint8_t> &bus) {
+  br.clear();
+  bus.clear();
+  if (g->n_pst <= 0) return;
+  br.assign(g->n_branch, 0);
+  bus.assign(g->n_bus, 0);
+  for (int q = 0; q < g->n_pst; ++q) {
+    const int l = g->pst_branch[q];
+    br[l] = 1;
+    bus[g->from[l]] = 1;
+    bus[g->to[l]] = 1;
+  }
+}
+
+// pst_br / pst_bus: phase-shifter branches and their terminal buses (may be
+// empty); candidates may not outage the former nor split the latter.
 int check_cands(int n_bus, int n_branch, const std::vector<int32_t> &adj_off,
+                const std::vector<uint8_t> &pst_br, const std::vector<uint8_t> &pst_bus,
                 const dcflow_cands *c, int32_t *bad, int64_t *packed, int64_t *padded,
                 int *kmax_out) {
   if (bad) *bad = 0;
@@ -192,9 +237,9 @@ int check_cands(int n_bus, int n_branch, const std::vector<int32_t> &adj_off,
     for (int j = a; j < e; ++j) {
       bool ok = true;
       if (c->kind[j] == DCFLOW_OUTAGE) {
-        ok = c->id[j] >= 0 && c->id[j] < n_branch;
+        ok = c->id[j] >= 0 && c->id[j] < n_branch && (pst_br.empty() || !pst_br[c->id[j]]);
       } else if (c->kind[j] == DCFLOW_SPLIT) {
-        ok = c->id[j] >= 0 && c->id[j] < n_bus;
+        ok = c->id[j] >= 0 && c->id[j] < n_bus && (pst_bus.empty() || !pst_bus[c->id[j]]);
         if (ok) {
           int deg = adj_off[c->id[j] + 1] - adj_off[c->id[j]];
           uint32_t mk = c->mask[j];
@@ -278,6 +323,9 @@ int dcflow_build_ptdf(const dcflow_grid_desc *g, void *dev_ws, size_t ws_bytes, 
   p->ld_er = d.ld_er;
   p->ld_o = d.ld_o;
   p->mon_pad = d.mon_pad;
+  p->n_ctrl = d.n_ctrl;
+  p->n_inj = d.n + d.n_ctrl;
+  pst_flags(g, p->pst_br, p->pst_bus);
   p->rating_scale = g->rating ? 1.2 : g->rating_scale;
   p->rating_offset = g->rating ? 0.1 : g->rating_offset;
   p->f.assign(g->from, g->from + d.m);
@@ -309,8 +357,27 @@ int dcflow_build_ptdf(const dcflow_grid_desc *g, void *dev_ws, size_t ws_bytes, 
     of[c] = g->from[l];
     ot[c] = g->to[l];
   }
-  std::vector<double> pb(d.ld_h, 0.0);
+  std::vector<double> pb(d.ld_h, 0.0);  // controls of the base case: 0
   std::copy(g->p_base, g->p_base + d.n, pb.begin());
+  // control columns: phase shifter on l = f -> t: pst_scale b_l (e_f - e_t) injection pattern
+  // and -pst_scale b_l on l itself; HVDC i -> j: hvdc_scale (e_j - e_i)
+  std::vector<int32_t> ca, cc, cbr;
+  std::vector<double> cw, cd;
+  for (int q = 0; q < g->n_pst; ++q) {
+    const int l = g->pst_branch[q];
+    ca.push_back(g->from[l]);
+    cc.push_back(g->to[l]);
+    cbr.push_back(l);
+    cw.push_back(g->pst_scale * g->b[l]);
+    cd.push_back(-g->pst_scale * g->b[l]);
+  }
+  for (int q = 0; q < g->n_hvdc; ++q) {
+    ca.push_back(g->hvdc_to[q]);
+    cc.push_back(g->hvdc_from[q]);
+    cbr.push_back(-1);
+    cw.push_back(g->hvdc_scale);
+    cd.push_back(0.0);
+  }
 
   auto up = [&](void *dst, const void *src, size_t bytes) {
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
@@ -327,7 +394,12 @@ int dcflow_build_ptdf(const dcflow_grid_desc *g, void *dev_ws, size_t ws_bytes, 
       up(p->d_out_pos, out_pos.data(), 4 * out_pos.size()) != hipSuccess ||
       up(p->d_out_f, of.data(), 4 * of.size()) != hipSuccess ||
       up(p->d_out_t, ot.data(), 4 * ot.size()) != hipSuccess ||
-      up(p->d_pbase, pb.data(), 8 * pb.size()) != hipSuccess) {
+      up(p->d_pbase, pb.data(), 8 * pb.size()) != hipSuccess ||
+      (d.n_ctrl > 0 && (up(p->d_ctl_a, ca.data(), 4 * ca.size()) != hipSuccess ||
+                        up(p->d_ctl_c, cc.data(), 4 * cc.size()) != hipSuccess ||
+                        up(p->d_ctl_br, cbr.data(), 4 * cbr.size()) != hipSuccess ||
+                        up(p->d_ctl_w, cw.data(), 8 * cw.size()) != hipSuccess ||
+                        up(p->d_ctl_d, cd.data(), 8 * cd.size()) != hipSuccess))) {
     delete p;
     return DCFLOW_E_HIP;
   }
@@ -355,6 +427,7 @@ int dcflow_plan_view_get(const dcflow_plan *p, dcflow_plan_view *v) {
   v->f_base = p->d_fbase;
   v->rating = p->d_rating;
   v->er = p->d_er;
+  v->n_inj = p->n_inj;
   return DCFLOW_OK;
 }
 
@@ -364,8 +437,10 @@ int dcflow_validate_candidates(const dcflow_grid_desc *g, const dcflow_cands *c,
                                int32_t *bad_index, int64_t *packed, int64_t *padded) {
   int rc = check_grid(g);
   if (rc != DCFLOW_OK) return rc;
-  return check_cands(g->n_bus, g->n_branch, host_adj_off(g), c, bad_index, packed, padded,
-                     nullptr);
+  std::vector<uint8_t> pbr, pbus;
+  pst_flags(g, pbr, pbus);
+  return check_cands(g->n_bus, g->n_branch, host_adj_off(g), pbr, pbus, c, bad_index, packed,
+                     padded, nullptr);
 }
 
 int dcflow_batch_bytes(const dcflow_plan *p, const dcflow_cands *c, int32_t n_var_max,
@@ -388,7 +463,8 @@ int dcflow_batch_create(dcflow_plan *p, const dcflow_cands *c, int32_t n_var_max
   int32_t bad = 0;
   int64_t packed = 0, padded = 0;
   int kmax = 0;
-  int rc = check_cands(p->n, p->m, p->adj_off, c, &bad, &packed, &padded, &kmax);
+  int rc = check_cands(p->n, p->m, p->adj_off, p->pst_br, p->pst_bus, c, &bad, &packed, &padded,
+                       &kmax);
   if (rc != DCFLOW_OK) return rc;
   BatchDims d{c->n_cand, c->n_cand ? c->off[c->n_cand] : 0, n_var_max};
   dcflow_batch *b = new (std::nothrow) dcflow_batch();
@@ -528,7 +604,7 @@ int dcflow_eval_topologies(dcflow_batch *b, hipStream_t s) {
 int dcflow_flow_bytes(const dcflow_batch *b, int32_t n_var, dcflow_prec prec, size_t *bytes,
                       int32_t *ld_f) {
   if (!b || !bytes || n_var < 1) return DCFLOW_E_ARG;
-  if (prec != DCFLOW_FP64 && prec != DCFLOW_FP32) return DCFLOW_E_ARG;
+  if (!prec_valid(prec)) return DCFLOW_E_ARG;
   size_t el = prec == DCFLOW_FP64 ? 8 : 4;
   *bytes = std::max<size_t>((size_t)b->n_cand * n_var * b->plan->ld_er * el, 256);
   if (ld_f) *ld_f = b->plan->ld_er;
@@ -540,7 +616,7 @@ int dcflow_eval_injections(dcflow_batch *b, const double *dev_inj, int32_t n_var
                            size_t flow_bytes, hipStream_t s) {
   if (!b || !dev_inj || !dev_flows) return DCFLOW_E_ARG;
   if (n_var < 1 || n_var > b->vmax) return DCFLOW_E_SHAPE;
-  if (prec != DCFLOW_FP64 && prec != DCFLOW_FP32) return DCFLOW_E_ARG;
+  if (!prec_valid(prec)) return DCFLOW_E_ARG;
   if (!b->factored) return DCFLOW_E_ARG;
   size_t need = 0;
   dcflow_flow_bytes(b, n_var, prec, &need, nullptr);
@@ -556,7 +632,7 @@ int dcflow_n1_score(dcflow_batch *b, const void *dev_flows, int32_t n_var, dcflo
                     dcflow_score *dev_out, hipStream_t s) {
   if (!b || !dev_flows || !dev_out) return DCFLOW_E_ARG;
   if (n_var < 1 || n_var > b->vmax) return DCFLOW_E_SHAPE;
-  if (prec != DCFLOW_FP64 && prec != DCFLOW_FP32) return DCFLOW_E_ARG;
+  if (!prec_valid(prec)) return DCFLOW_E_ARG;
   if (!b->factored) return DCFLOW_E_ARG;
   if (b->flows_prec != prec || b->flows_nvar != n_var) return DCFLOW_E_ARG;
   hipError_t e = launch_score(b, dev_flows, n_var, prec, dev_out, s);

@@ -110,14 +110,24 @@ __global__ void k_rows_transpose(double *Ht, int ld_er, const double *H, int ld_
   }
 }
 
-__global__ void k_copy_he(double *He, float *He32, int ld_h, const double *H, const int32_t *er,
-                          int n_er, int ld_er) {
+// Kept PTDF rows as GEMM operands: FP64, FP32 and three BF16 parts whose sum
+// reproduces the FP64 value to about 2^-24 relative (each part rounds what the
+// previous ones left).
+__global__ void k_copy_he(double *He, float *He32, __bf16 *Heb, int ld_h, const double *H,
+                          const int32_t *er, int n_er, int ld_er) {
   int x = blockIdx.x * blockDim.x + threadIdx.x;
   int pos = blockIdx.y;
   if (x >= ld_h || pos >= ld_er) return;
   double v = pos < n_er ? H[(size_t)er[pos] * ld_h + x] : 0.0;
-  He[(size_t)pos * ld_h + x] = v;
-  He32[(size_t)pos * ld_h + x] = (float)v;
+  const size_t i = (size_t)pos * ld_h + x;
+  He[i] = v;
+  He32[i] = (float)v;
+  const size_t part = (size_t)ld_er * ld_h;
+  for (int q = 0; q < 3; ++q) {
+    const __bf16 b = (__bf16)(float)v;
+    Heb[q * part + i] = b;
+    v -= (double)(float)b;
+  }
 }
 
 __global__ void k_hdo(double *hdo, int ld_o, const double *H, int ld_h, int m,
@@ -168,6 +178,24 @@ __global__ void k_lsd(double *lsd, int ld_o, const double *hdo, const int32_t *m
   lsd[(size_t)i * ld_o + c] = v;
 }
 
+// Control columns of the PTDF (phase-shifter and HVDC distribution factors):
+// column n + q of row l = w_q (PTDF[l, a_q] - PTDF[l, c_q]) + [l == br_q] d_q.
+__global__ void k_ctrl_cols(double *Hb, int ld_h, int m, int n, int n_ctrl, const int32_t *ca,
+                            const int32_t *cc, const int32_t *cbr, const double *cw,
+                            const double *cd) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (l >= m || q >= n_ctrl) return;
+  double *row = Hb + (size_t)l * ld_h;
+  row[n + q] = cw[q] * (row[ca[q]] - row[cc[q]]) + (l == cbr[q] ? cd[q] : 0.0);
+}
+
+// Base flows of the kept rows (the offset of the reduced-precision GEMM).
+__global__ void k_fber(double *fber, const double *fb, const int32_t *er, int n_er, int ld_er) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ld_er) fber[i] = i < n_er ? fb[er[i]] : 0.0;
+}
+
 // FP32 copy of Lsd in the accumulator order of the FP32 16x16x4 MFMA, so that the
 // scan seeds each block with one 16-byte load per lane.
 __global__ void k_lsd32(float *dst, const double *lsd, int ld_o, int mon_pad) {
@@ -213,17 +241,26 @@ hipError_t launch_build(dcflow_plan *p, hipStream_t s, const double *h_rating, d
   hipLaunchKernelGGL(k_ptdf_rows, dim3(nblk(ld, 256), m), dim3(256), 0, s, p->d_hb, ld, n, m,
                      p->slack, p->d_binv, p->d_f, p->d_t, p->d_b);
   DCF_CHECK_LAUNCH();
+  if (p->n_ctrl > 0) {
+    hipLaunchKernelGGL(k_ctrl_cols, dim3(nblk(m, 256), p->n_ctrl), dim3(256), 0, s, p->d_hb, ld,
+                       m, n, p->n_ctrl, p->d_ctl_a, p->d_ctl_c, p->d_ctl_br, p->d_ctl_w,
+                       p->d_ctl_d);
+    DCF_CHECK_LAUNCH();
+  }
   hipLaunchKernelGGL(k_rows_transpose, dim3(nblk(n, 32), nblk(p->ld_er, 32)), dim3(32, 8), 0, s,
                      p->d_ht, p->ld_er, p->d_hb, ld, n, p->d_er, p->n_er);
   DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_copy_he, dim3(nblk(ld, 256), p->ld_er), dim3(256), 0, s, p->d_he64,
-                     p->d_he32, ld, p->d_hb, p->d_er, p->n_er, p->ld_er);
+                     p->d_he32, p->d_heb, ld, p->d_hb, p->d_er, p->n_er, p->ld_er);
   DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_hdo, dim3(nblk(p->ld_o, 256), m), dim3(256), 0, s, p->d_hdo, p->ld_o,
                      p->d_hb, ld, m, p->d_out_f, p->d_out_t, p->n_out);
   DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_fbase, dim3(nblk(m, 4)), dim3(256), 0, s, p->d_fbase, p->d_hb, ld,
                      p->d_pbase, m);
+  DCF_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_fber, dim3(nblk(p->ld_er, 256)), dim3(256), 0, s, p->d_fber, p->d_fbase,
+                     p->d_er, p->n_er, p->ld_er);
   DCF_CHECK_LAUNCH();
   if (h_rating) {
     hipError_t e = hipMemcpyAsync(p->d_rating, h_rating, sizeof(double) * p->n_mon,

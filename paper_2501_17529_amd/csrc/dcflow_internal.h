@@ -21,6 +21,11 @@ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// True when the precision's flows (and N-1 scan) are FP32.
+inline bool prec_is_f32(int prec) { return prec == DCFLOW_FP32 || prec == DCFLOW_BF16 || prec == DCFLOW_BF16X6; }
+inline bool prec_valid(int prec) { return prec == DCFLOW_FP64 || prec_is_f32(prec); }
 
 }  // namespace dcflow
 
@@ -28,6 +33,8 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // workspace.  All device matrices are row-major.
 struct dcflow_plan {
   int n, m, slack, n_mon, n_out, n_er;
+  int n_ctrl;  // control columns (phase shifters, then HVDC links)
+  int n_inj;   // entries per injection vector: n + n_ctrl
   int ld_h;    // columns of Hb / Binv / He (n rounded up to 16, the GEMM K step)
   int ld_er;   // rows kept, rounded up to the GEMM M tile (128); U, F, Ht stride
   int ld_o;    // contingency columns rounded up to 64 (>= 64)
@@ -43,17 +50,23 @@ struct dcflow_plan {
   double *d_ht;     // [n][ld_er] PTDF transposed, kept rows only (node-major)
   double *d_he64;   // [ld_er][ld_h] kept rows of the PTDF, GEMM operand
   float *d_he32;    // [ld_er][ld_h] same in FP32
+  __bf16 *d_heb;    // [3][ld_er][ld_h] same split into three BF16 parts (sum = FP64 value to ~2^-24)
   double *d_hdo;    // [m][ld_o] PTDF[:, f_c] - PTDF[:, t_c]
   double *d_lsd;    // [mon_pad][ld_o] (hdo[mon] - [mon == out]) / rating
   float *d_lsd32;   // same in FP32, fragment-major: 16 x 16 blocks [mon_pad/16][ld_o/16], each
                     // 64 lanes x 4 rows in the FP32 MFMA accumulator order (rows 4 (lane/16) + r)
   double *d_fbase;  // [m]
+  double *d_fber;   // [ld_er] base flows of the kept rows (0 on padding)
   double *d_pbase;  // [ld_h]
   double *d_rating; // [mon_pad]
   double *d_inv_r;  // [mon_pad]
+  // control column q of the PTDF: w_q (PTDF[:, a_q] - PTDF[:, c_q]) + d_q e_{br_q}
+  int32_t *d_ctl_a, *d_ctl_c, *d_ctl_br;
+  double *d_ctl_w, *d_ctl_d;
   // host copies used for validation and packing
   std::vector<int32_t> f, t, adj_off, adj_br, out, pos_of_br;
   std::vector<uint8_t> is_out;  // per branch: contingency?
+  std::vector<uint8_t> pst_br, pst_bus;  // phase-shifter branches / terminals (empty: none)
 };
 
 struct dcflow_batch {

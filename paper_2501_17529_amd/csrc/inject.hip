@@ -145,7 +145,8 @@ __global__ void __launch_bounds__(256)
 k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, int ncols,
        int nvar, int shared, T *__restrict__ F, int ld_f, const int32_t *__restrict__ off,
        const double *__restrict__ U, int ld_er, const double *__restrict__ z, int vmax,
-       int correct, int n_mt, int n_nt) {
+       int correct, int n_mt, int n_nt, const double *__restrict__ pbase,
+       const double *__restrict__ fber) {
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T As[BM][LDS_K];
   __shared__ T Bs[BN][LDS_K];
@@ -169,10 +170,11 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
     for (int q = 0; q < 8; ++q) ra[q] = arow[kb + q];  // He padded to ld_h (multiple of 16)
     if (brow && kb + 8 <= n) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) rb[q] = (T)brow[kb + q];
+      for (int q = 0; q < 8; ++q) rb[q] = (T)(brow[kb + q] - pbase[kb + q]);
     } else {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) rb[q] = (brow && kb + q < n) ? (T)brow[kb + q] : (T)0;
+      for (int q = 0; q < 8; ++q)
+        rb[q] = (brow && kb + q < n) ? (T)(brow[kb + q] - pbase[kb + q]) : (T)0;
     }
   };
   auto sstore = [&]() {
@@ -228,7 +230,7 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
       const int mb = m0 + wm * 64 + a * 16;
       double o[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) o[r] = (double)acc[a][b][r];
+      for (int r = 0; r < 4; ++r) o[r] = (double)acc[a][b][r] + fber[mb + MfmaRow<T>::row(g, r)];
       for (int e = e0; e < e1; ++e) {
         const double ze = z[(size_t)e * vmax + v];
         const double *ue = U + (size_t)e * ld_er + mb;
@@ -240,6 +242,147 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
       for (int r = 0; r < 4; ++r) dst[MfmaRow<T>::row(g, r)] = (T)o[r];
     }
   }
+}
+
+// ------------------------------------------------------------ BF16 GEMM
+// F[col][m] = sum_k X[xrow(col)][k] He[m][k] (+ U z) on v_mfma_f32_16x16x32_bf16
+// with FP32 accumulation.  NP = 1: one BF16 product (BF16 mode).  NP = 3: both
+// operands are split into three BF16 parts (He's precomputed in the plan, X's in
+// the staging), and the six cross products of order i + j <= 2 are summed
+// (BF16X6 mode): every product of parts is exact in the FP32 accumulator, and
+// the dropped terms are of order 2^-24 relative.  128 x 128 tile, K step 32;
+// lane group g feeds k = 8 g .. 8 g + 7 of each 32-step (A and B alike).
+constexpr int BKT = 32, BLD = BKT + 8;  // K step and LDS row stride (bf16)
+
+template <int NP>
+__global__ void __launch_bounds__(256)
+k_gemm_bf(const __bf16 *__restrict__ Hp, size_t part, int ld_h, const double *__restrict__ X,
+          int n, int ncols, int nvar, int shared, float *__restrict__ F, int ld_f,
+          const int32_t *__restrict__ off, const double *__restrict__ U, int ld_er,
+          const double *__restrict__ z, int vmax, int correct, int n_mt, int n_nt,
+          const double *__restrict__ pbase, const double *__restrict__ fber) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[NP][BM * BLD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[NP][BN * BLD];
+  const int xcd = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
+  const int n_tile = (local / n_mt) * kXcd + xcd, m_tile = local % n_mt;
+  if (n_tile >= n_nt) return;
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, g = lane / 16, li = lane % 16;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int n0 = n_tile * BN, m0 = m_tile * BM;
+  // staging: each thread 16 consecutive k of one row of A and of B
+  const int lr = tid >> 1, lk = (tid & 1) * 16;
+  const int bcol = n0 + lr;
+  const double *brow = bcol < ncols ? X + (size_t)bcol * n : nullptr;
+  f4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  const int nk = (n + BKT - 1) / BKT;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int kb = kt * BKT + lk;
+    // A parts (zero past the padded width; ld_h is a multiple of 16)
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      bf8 v0, v1;
+      if (kb < ld_h) {
+        const bf8 *src = reinterpret_cast<const bf8 *>(Hp + q * part + (size_t)(m0 + lr) * ld_h + kb);
+        v0 = src[0];
+        v1 = src[1];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          v0[e] = (__bf16)0.f;
+          v1[e] = (__bf16)0.f;
+        }
+      }
+      bf8 *dst = reinterpret_cast<bf8 *>(&As[q][lr * BLD + lk]);
+      dst[0] = v0;
+      dst[1] = v1;
+    }
+    // B: 16 injections in FP64, split into NP BF16 parts
+    double xv[16];  // injection minus the base case (the base flows are added in FP64)
+    if (brow && kb + 16 <= n) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) xv[e] = brow[kb + e] - pbase[kb + e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) xv[e] = (brow && kb + e < n) ? brow[kb + e] - pbase[kb + e] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      bf8 v0, v1;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const __bf16 b0 = (__bf16)(float)xv[e], b1 = (__bf16)(float)xv[e + 8];
+        v0[e] = b0;
+        v1[e] = b1;
+        xv[e] -= (double)(float)b0;
+        xv[e + 8] -= (double)(float)b1;
+      }
+      bf8 *dst = reinterpret_cast<bf8 *>(&Bs[q][lr * BLD + lk]);
+      dst[0] = v0;
+      dst[1] = v1;
+    }
+    __syncthreads();
+    bf8 af[NP][4], bfr[NP][4];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        af[q][a] = *reinterpret_cast<const bf8 *>(&As[q][(wm * 64 + a * 16 + li) * BLD + g * 8]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        bfr[q][b] = *reinterpret_cast<const bf8 *>(&Bs[q][(wn * 64 + b * 16 + li) * BLD + g * 8]);
+    }
+    // smallest terms first: (2,0), (0,2), (1,1), (1,0), (0,1), (0,0)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        f4 c = acc[a][b];
+        if (NP == 3) {
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2 % NP][a], bfr[0][b], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][a], bfr[2 % NP][b], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1 % NP][a], bfr[1 % NP][b], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1 % NP][a], bfr[0][b], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][a], bfr[1 % NP][b], c, 0, 0, 0);
+        }
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][a], bfr[0][b], c, 0, 0, 0);
+        acc[a][b] = c;
+      }
+    __syncthreads();
+  }
+  // epilogue: rank-k correction and store (rows 4 g + r of each block)
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int col = n0 + wn * 64 + b * 16 + li;
+    if (col >= ncols) continue;
+    int e0 = 0, e1 = 0, v = col;
+    if (correct) {
+      const int cand = col / nvar;
+      v = col - cand * nvar;
+      e0 = off[cand];
+      e1 = off[cand + 1];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int mb = m0 + wm * 64 + a * 16;
+      double o[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) o[r] = (double)acc[a][b][r] + fber[mb + MfmaRow<float>::row(g, r)];
+      for (int e = e0; e < e1; ++e) {
+        const double ze = z[(size_t)e * vmax + v];
+        const double *ue = U + (size_t)e * ld_er + mb;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[r] += ue[MfmaRow<float>::row(g, r)] * ze;
+      }
+      float *dst = F + (size_t)col * ld_f + mb;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dst[MfmaRow<float>::row(g, r)] = (float)o[r];
+    }
+  }
+  (void)shared;
 }
 
 // Shared injections: F[i][v][m] = F0[v][m] + sum_e U[e][m] z[e][v].
@@ -255,31 +398,58 @@ __global__ void k_bcast(const T *__restrict__ F0, T *__restrict__ F, int ld_f, i
   F[((size_t)cand * nvar + v) * ld_f + m] = (T)o;
 }
 
+// The GEMM F = X He^T (+ U z) with T operands, or BF16 parts (np = 1 or 3) when T = float
+// and np > 0.
 template <typename T>
-hipError_t run_injections(dcflow_batch *bt, const T *He, const double *inj, int nvar, int shared,
-                          T *flows, hipStream_t s) {
+hipError_t launch_gemm(const dcflow_plan *p, const T *He, int np, const double *X, int ncols,
+                       int nvar, int shared, T *F, const dcflow_batch *bt, int correct,
+                       hipStream_t s) {
+  const int n_mt = p->ld_er / BM, n_nt = (ncols + BN - 1) / BN;
+  dim3 grid(kXcd * ((n_nt + kXcd - 1) / kXcd) * n_mt);
+  if constexpr (sizeof(T) == 4) {
+    const size_t part = (size_t)p->ld_er * p->ld_h;
+    if (np == 3) {
+      k_gemm_bf<3><<<grid, dim3(256), 0, s>>>(p->d_heb, part, p->ld_h, X, p->n_inj, ncols, nvar,
+                                              shared, F, p->ld_er, bt->d_off, bt->d_U, p->ld_er,
+                                              bt->d_z, bt->vmax, correct, n_mt, n_nt, p->d_pbase,
+                                              p->d_fber);
+      DCF_CHECK_LAUNCH();
+      return hipSuccess;
+    }
+    if (np == 1) {
+      k_gemm_bf<1><<<grid, dim3(256), 0, s>>>(p->d_heb, part, p->ld_h, X, p->n_inj, ncols, nvar,
+                                              shared, F, p->ld_er, bt->d_off, bt->d_U, p->ld_er,
+                                              bt->d_z, bt->vmax, correct, n_mt, n_nt, p->d_pbase,
+                                              p->d_fber);
+      DCF_CHECK_LAUNCH();
+      return hipSuccess;
+    }
+  }
+  // the GEMM takes x - p_base and the FP64 base flows are added back (the injections are
+  // variants of the base case, so this keeps most cancellation out of the sums)
+  k_gemm<T><<<grid, dim3(256), 0, s>>>(He, p->ld_h, X, p->n_inj, ncols, nvar, shared, F, p->ld_er,
+                                       bt->d_off, bt->d_U, p->ld_er, bt->d_z, bt->vmax, correct,
+                                       n_mt, n_nt, p->d_pbase, p->d_fber);
+  DCF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t run_injections(dcflow_batch *bt, const T *He, int np, const double *inj, int nvar,
+                          int shared, T *flows, hipStream_t s) {
   dcflow_plan *p = bt->plan;
   const int ld_f = p->ld_er;
   hipLaunchKernelGGL(k_sense, dim3(bt->n_cand), dim3(256), 0, s, bt->d_off, bt->d_kind, bt->d_nsig,
-                     bt->d_sig, bt->d_pnew, bt->d_kinv, p->d_hb, p->ld_h, p->n, inj, nvar, shared,
+                     bt->d_sig, bt->d_pnew, bt->d_kinv, p->d_hb, p->ld_h, p->n_inj, inj, nvar, shared,
                      bt->d_z, bt->vmax);
   DCF_CHECK_LAUNCH();
   if (!shared) {
-    const int ncols = bt->n_cand * nvar;
-    const int n_mt = p->ld_er / BM, n_nt = (ncols + BN - 1) / BN;
-    dim3 grid(kXcd * ((n_nt + kXcd - 1) / kXcd) * n_mt);
-    k_gemm<T><<<grid, dim3(256), 0, s>>>(He, p->ld_h, inj, p->n, ncols, nvar, 0, flows, ld_f,
-                                         bt->d_off, bt->d_U, p->ld_er, bt->d_z, bt->vmax, 1,
-                                         n_mt, n_nt);
-    DCF_CHECK_LAUNCH();
+    const hipError_t e = launch_gemm<T>(p, He, np, inj, bt->n_cand * nvar, nvar, 0, flows, bt, 1, s);
+    if (e != hipSuccess) return e;
   } else {
     T *f0 = reinterpret_cast<T *>(bt->d_f0);
-    const int n_mt = p->ld_er / BM, n_nt = (nvar + BN - 1) / BN;
-    dim3 grid(kXcd * ((n_nt + kXcd - 1) / kXcd) * n_mt);
-    k_gemm<T><<<grid, dim3(256), 0, s>>>(He, p->ld_h, inj, p->n, nvar, nvar, 1, f0, ld_f,
-                                         bt->d_off, bt->d_U, p->ld_er, bt->d_z, bt->vmax, 0,
-                                         n_mt, n_nt);
-    DCF_CHECK_LAUNCH();
+    const hipError_t e = launch_gemm<T>(p, He, np, inj, nvar, nvar, 1, f0, bt, 0, s);
+    if (e != hipSuccess) return e;
     dim3 g2((ld_f + 255) / 256, nvar, bt->n_cand);
     k_bcast<T><<<g2, dim3(256), 0, s>>>(f0, flows, ld_f, nvar, bt->d_off, bt->d_U, p->ld_er,
                                         bt->d_z, bt->vmax);
@@ -294,9 +464,10 @@ hipError_t launch_injections(dcflow_batch *bt, const double *inj, int nvar, int 
                              void *flows, hipStream_t s) {
   if (bt->n_cand == 0) return hipSuccess;
   if (prec == DCFLOW_FP64)
-    return run_injections<double>(bt, bt->plan->d_he64, inj, nvar, shared,
+    return run_injections<double>(bt, bt->plan->d_he64, 0, inj, nvar, shared,
                                   static_cast<double *>(flows), s);
-  return run_injections<float>(bt, bt->plan->d_he32, inj, nvar, shared,
+  const int np = prec == DCFLOW_BF16X6 ? 3 : prec == DCFLOW_BF16 ? 1 : 0;
+  return run_injections<float>(bt, bt->plan->d_he32, np, inj, nvar, shared,
                                static_cast<float *>(flows), s);
 }
 

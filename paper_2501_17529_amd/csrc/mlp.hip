@@ -90,7 +90,8 @@ __global__ void k_features(const int32_t *__restrict__ f, const int32_t *__restr
                            const int32_t *__restrict__ out, int n_out,
                            const int32_t *__restrict__ pos_of_br, const double *__restrict__ inv_r,
                            const double *__restrict__ Fs, int m,
-                           const double *__restrict__ X, int n, const double *__restrict__ glob,
+                           const double *__restrict__ X, int n, int n_bus,
+                           const double *__restrict__ glob,
                            const int32_t *__restrict__ worst, const int32_t *__restrict__ pairs,
                            int n_act, const int32_t *__restrict__ a_snap,
                            const int32_t *__restrict__ a_bus, const uint32_t *__restrict__ a_mask,
@@ -174,7 +175,7 @@ __global__ void k_features(const int32_t *__restrict__ f, const int32_t *__restr
   double pA = xs[A];
   if (A == slack) {
     pA = 0.0;
-    for (int x = 0; x < n; ++x)
+    for (int x = 0; x < n_bus; ++x)
       if (x != slack) pA -= xs[x];
   }
   double fcpl = pA - (a_side[a] ? xs[A] : 0.0);
@@ -661,7 +662,7 @@ hipError_t launch_standardize(float *X, long rows, int cols, const float *mean,
 
 hipError_t launch_snapshot(const dcflow_plan *p, const double *X, int S, double *F,
                            double *n0max, hipStream_t s) {
-  k_snapshot_flows<<<nblk((long)S * p->m, 4), 256, 0, s>>>(p->d_hb, p->ld_h, p->n, p->m, X, S, F);
+  k_snapshot_flows<<<nblk((long)S * p->m, 4), 256, 0, s>>>(p->d_hb, p->ld_h, p->n_inj, p->m, X, S, F);
   DCF_CHECK_LAUNCH();
   if (n0max) {
     k_snapshot_n0max<<<S, 256, 0, s>>>(F, p->m, p->d_mon, p->d_inv_r, p->n_mon, n0max);
@@ -677,7 +678,7 @@ hipError_t launch_features(const dcflow_plan *p, const double *Fs, const double 
   k_features<<<nblk(n_act, 128), 128, 0, s>>>(
       p->d_f, p->d_t, p->d_b, p->slack, p->d_adj_off, p->d_adj_br, p->d_fbase, p->rating_scale,
       p->rating_offset, p->d_hb, p->ld_h, p->d_hdo, p->ld_o, p->d_out, p->n_out, p->d_pos_of_br,
-      p->d_inv_r, Fs, p->m, X, p->n, glob, worst, pairs, n_act, snap, bus, mask, side, out);
+      p->d_inv_r, Fs, p->m, X, p->n_inj, p->n, glob, worst, pairs, n_act, snap, bus, mask, side, out);
   DCF_CHECK_LAUNCH();
   return hipSuccess;
 }

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libdcflow.so")
 
 DCFLOW_FP64 = 0
 DCFLOW_FP32 = 1
-PREC = {"fp64": DCFLOW_FP64, "fp32": DCFLOW_FP32}
+PREC = {"fp64": DCFLOW_FP64, "fp32": DCFLOW_FP32, "bf16": 2, "bf16x6": 3}
 
 ST_DISCONNECTED = 0x1
 ST_SINGULAR = 0x2
@@ -45,7 +45,11 @@ class GridDesc(ctypes.Structure):
                 ("n_mon", ctypes.c_int32), ("mon", ctypes.c_void_p),
                 ("n_out", ctypes.c_int32), ("out", ctypes.c_void_p),
                 ("p_base", ctypes.c_void_p), ("rating", ctypes.c_void_p),
-                ("rating_scale", ctypes.c_double), ("rating_offset", ctypes.c_double)]
+                ("rating_scale", ctypes.c_double), ("rating_offset", ctypes.c_double),
+                ("n_pst", ctypes.c_int32), ("pst_branch", ctypes.c_void_p),
+                ("pst_scale", ctypes.c_double), ("n_hvdc", ctypes.c_int32),
+                ("hvdc_from", ctypes.c_void_p), ("hvdc_to", ctypes.c_void_p),
+                ("hvdc_scale", ctypes.c_double)]
 
 
 class Cands(ctypes.Structure):
@@ -66,7 +70,8 @@ class PlanView(ctypes.Structure):
     _fields_ = [("n_bus", ctypes.c_int32), ("n_branch", ctypes.c_int32), ("n_mon", ctypes.c_int32),
                 ("n_out", ctypes.c_int32), ("n_er", ctypes.c_int32), ("ld_h", ctypes.c_int32),
                 ("ld_o", ctypes.c_int32), ("ptdf", ctypes.c_void_p), ("hdo", ctypes.c_void_p),
-                ("f_base", ctypes.c_void_p), ("rating", ctypes.c_void_p), ("er", ctypes.c_void_p)]
+                ("f_base", ctypes.c_void_p), ("rating", ctypes.c_void_p), ("er", ctypes.c_void_p),
+                ("n_inj", ctypes.c_int32)]
 
 
 def _load():
@@ -155,7 +160,14 @@ class _GridArgs:
     """Keeps the host arrays of a grid description alive."""
 
     def __init__(self, n_bus, f, t, b, mon, out, p_base, slack=0, rating=None,
-                 rating_scale=1.2, rating_offset=0.1):
+                 rating_scale=1.2, rating_offset=0.1, controls=None):
+        """controls: None or dict(pst=[branch ids], pst_scale=rad per unit,
+        hvdc=[(from bus, to bus)], hvdc_scale=p.u. per unit)."""
+        c = controls or {}
+        self.pst = _arr(c.get("pst", []), np.int32)
+        hv = np.asarray(c.get("hvdc", []), np.int32).reshape(-1, 2)
+        self.hv_from = _arr(hv[:, 0], np.int32)
+        self.hv_to = _arr(hv[:, 1], np.int32)
         self.f = _arr(f, np.int32)
         self.t = _arr(t, np.int32)
         self.b = _arr(b, np.float64)
@@ -168,7 +180,11 @@ class _GridArgs:
             self.b.ctypes.data, len(self.mon), self.mon.ctypes.data, len(self.out),
             self.out.ctypes.data if len(self.out) else None, self.p.ctypes.data,
             None if self.r is None else self.r.ctypes.data, float(rating_scale),
-            float(rating_offset))
+            float(rating_offset), len(self.pst), self.pst.ctypes.data if len(self.pst) else None,
+            float(c.get("pst_scale", np.pi / 180.0)), len(self.hv_from),
+            self.hv_from.ctypes.data if len(self.hv_from) else None,
+            self.hv_to.ctypes.data if len(self.hv_to) else None,
+            float(c.get("hvdc_scale", 1.0)))
 
 
 class _CandArgs:
@@ -208,10 +224,10 @@ class Plan:
     """dcflow_build_ptdf: one-time FP64 base build on the current CUDA device."""
 
     def __init__(self, n_bus, f, t, b, mon, out, p_base, slack=0, rating=None,
-                 rating_scale=1.2, rating_offset=0.1, device="cuda", stream=None):
+                 rating_scale=1.2, rating_offset=0.1, device="cuda", stream=None, controls=None):
         import torch
         self.args = _GridArgs(n_bus, f, t, b, mon, out, p_base, slack, rating, rating_scale,
-                              rating_offset)
+                              rating_offset, controls)
         nbytes = ctypes.c_size_t(0)
         _check(_lib.dcflow_plan_workspace_bytes(ctypes.byref(self.args.desc), ctypes.byref(nbytes)),
                "dcflow_plan_workspace_bytes")
@@ -229,6 +245,7 @@ class Plan:
     @classmethod
     def from_workload(cls, w, rating=None, **kw):
         g = w.grid
+        kw.setdefault("controls", getattr(w, "controls", None))
         return cls(g.n_bus, g.f, g.t, g.b, w.mon, w.out, g.p, g.slack, rating,
                    w.rating_scale, w.rating_offset, **kw)
 
@@ -241,10 +258,13 @@ class Plan:
         assert off % el == 0 and 0 <= off and off + n * el <= self.ws.numel()
         return self.ws[off:off + n * el].view(dtype).view(*shape)
 
-    def ptdf(self):
+    def ptdf(self, controls=False):
+        """PTDF [n_branch][n_bus], with controls=True [n_branch][n_inj] including the
+        phase-shifter and HVDC columns."""
         import torch
         v = self.view
-        return self._dev(v.ptdf, (v.n_branch, v.ld_h), torch.float64)[:, :v.n_bus]
+        return self._dev(v.ptdf, (v.n_branch, v.ld_h), torch.float64)[
+            :, : (v.n_inj if controls else v.n_bus)]
 
     def hdo(self):
         import torch

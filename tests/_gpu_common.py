@@ -6,7 +6,7 @@ import numpy as np
 
 from oracle import dcflow_oracle as O
 
-TOL = {"fp64": 1e-6, "fp32": 1e-4}   # max |dp| / rating
+TOL = {"fp64": 1e-6, "fp32": 1e-4, "bf16x6": 1e-4}   # max |dp| / rating
 
 
 def say(msg):
@@ -98,10 +98,22 @@ def compare(w, gpu, oracle_res, rating, idx, prec, check_flows=True):
     return worst_err
 
 
-def oracle_scores(w, idx, rating):
-    return [O.score_candidate(w.grid.n_bus, w.grid.f, w.grid.t, w.grid.b, w.grid.slack,
-                              w.cands.elements(int(i)), w.inj if w.inj_shared else w.inj[int(i)],
-                              w.mon, w.out, rating) for i in idx]
+def oracle_scores(w, idx, rating, variants=None):
+    """Oracle scores of candidates idx (all variants, or the listed ones); with
+    controls, the injection vectors' tail holds the control values."""
+    g = w.grid
+    res = []
+    for i in idx:
+        x = w.inj if w.inj_shared else w.inj[int(i)]
+        if variants is not None:
+            x = x[np.asarray(variants)]
+        kw = {}
+        if getattr(w, "controls", None):
+            kw = dict(controls=w.controls, ctrl=x[:, g.n_bus:])
+            x = x[:, :g.n_bus]
+        res.append(O.score_candidate(g.n_bus, g.f, g.t, g.b, g.slack, w.cands.elements(int(i)),
+                                     x, w.mon, w.out, rating, **kw))
+    return res
 
 
 def oracle_rating(w):

@@ -52,7 +52,7 @@ def test_ptdf_build_matches_oracle():
         np.testing.assert_allclose(hdo, ho[:, g.f[w.out]] - ho[:, g.t[w.out]], atol=1e-11)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
 def test_tiny_workload_all_candidates(prec):
     w = G.workload_tiny(0)
     r = oracle_rating(w)
@@ -66,7 +66,7 @@ def test_tiny_workload_all_candidates(prec):
     assert sum(int(x["n_island"]) for x in res) > 0
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
 @pytest.mark.parametrize("seed", [0, 1])
 def test_uneven_rank_mixed_elements(prec, seed):
     w = _mixed_workload(seed)
@@ -113,7 +113,7 @@ def test_edge_cases():
     inj = G.perturbed_injections(g, rng, (len(lists), 4), 0.3)
     w = G.Workload("edge", g, w0.mon, w0.out, cands, inj, False)
     r = oracle_rating(w)
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x6"):
         say(f"edge cases {prec}")
         gpu = run_gpu(w, prec)
         res = oracle_scores(w, range(len(lists)), r)
@@ -143,7 +143,7 @@ def test_repeat_is_bitwise_identical():
     assert np.array_equal(a["vmax"], b["vmax"])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "bf16x6"])
 def test_medium_full_batch_sampled(prec):
     """1,000-bus grid, 4,096 candidates x 16 variants, 500 contingencies: the
     full batch runs on the GPU; 12 sampled candidates are checked against the
@@ -163,3 +163,30 @@ def test_medium_full_batch_sampled(prec):
     res = oracle_scores(w, idx, r)
     err = compare(w, gpu, res, r, idx, prec)
     say(f"medium {prec}: worst |d max_load| on the sample = {err:.3e}")
+
+
+def test_bf16_flows_within_rounding_bound():
+    """Plain BF16 mode: every N-0 flow within the bound that BF16 rounding of
+    both GEMM operands allows, |dF| <= 2^-7 sum_k |H_lk x_k| (plus the FP32
+    accumulation), element by element against the oracle's flows."""
+    w = _mixed_workload(7, n_cand=12, n_var=3)
+    say("bf16 flows bound")
+    g = w.grid
+    gpu = run_gpu(w, "bf16")
+    from _gpu_common import kept_rows
+    er = kept_rows(w.mon, w.out)
+    h = O.ptdf(g.n_bus, g.f, g.t, g.b, g.slack)
+    worst = 0.0
+    for i in range(w.cands.n_cand):
+        els = w.cands.elements(i)
+        cf = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, els, w.inj[i], w.out)
+        if not cf["connected"]:
+            continue
+        p0 = cf["p0"][:, er]                       # [V, n_er]
+        got = gpu["flows"][i][:, : len(er)]
+        # the GEMM part is H_er x; the rank-k correction is FP64, so bound the GEMM error
+        bound = 2.0 ** -7 * (np.abs(h[er]) @ np.abs(w.inj[i]).T).T + 1e-5
+        err = np.abs(got - p0)
+        worst = max(worst, float((err / bound).max()))
+        assert (err <= bound).all(), (i, float((err / bound).max()))
+    say(f"bf16: worst error / bound = {worst:.3f}")
