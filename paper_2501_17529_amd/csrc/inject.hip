@@ -132,7 +132,17 @@ struct Mfma<float> {
   }
 };
 
-constexpr int BM = 128, BN = 128, KT = 16, LDS_K = KT + 2;
+constexpr int BM = 128, BN = 128, KT = 16;
+// LDS row stride: 16-byte aligned rows so that stores and fragment reads are vector
+// accesses (lane group g reads the 4 consecutive k it owns in one access)
+template <typename T>
+struct Ldk {
+  static constexpr int v = KT + 16 / (int)sizeof(T);
+};
+template <typename T>
+struct alignas(16) V4 {
+  T x[4];
+};
 
 constexpr int kXcd = 8;  // MI355X: workgroups are dealt round-robin to 8 XCDs (own L2 each)
 
@@ -141,15 +151,16 @@ constexpr int kXcd = 8;  // MI355X: workgroups are dealt round-robin to 8 XCDs (
 // one XCD, so the column tile of X is read from HBM once and then hits that L2.
 // 256 threads = 2 x 2 waves of 64 x 64.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2)
 k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, int ncols,
        int nvar, int shared, T *__restrict__ F, int ld_f, const int32_t *__restrict__ off,
        const double *__restrict__ U, int ld_er, const double *__restrict__ z, int vmax,
        int correct, int n_mt, int n_nt, const double *__restrict__ pbase,
        const double *__restrict__ fber) {
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T As[BM][LDS_K];
-  __shared__ T Bs[BN][LDS_K];
+  constexpr int LDS_K = Ldk<T>::v;
+  __shared__ __attribute__((aligned(16))) T As[BM][LDS_K];
+  __shared__ __attribute__((aligned(16))) T Bs[BN][LDS_K];
   const int xcd = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
   const int n_tile = (local / n_mt) * kXcd + xcd, m_tile = local % n_mt;
   if (n_tile >= n_nt) return;
@@ -179,9 +190,15 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
   };
   auto sstore = [&]() {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      As[lr][lk + q] = ra[q];
-      Bs[lr][lk + q] = rb[q];
+    for (int h = 0; h < 2; ++h) {
+      V4<T> va, vb;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        va.x[q] = ra[4 * h + q];
+        vb.x[q] = rb[4 * h + q];
+      }
+      *reinterpret_cast<V4<T> *>(&As[lr][lk + 4 * h]) = va;
+      *reinterpret_cast<V4<T> *>(&Bs[lr][lk + 4 * h]) = vb;
     }
   };
   acc_t acc[4][4];
@@ -190,23 +207,28 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
+  // single LDS stage (measured faster here than two stages with one barrier): the
+  // next k-tile waits in registers while the current one is consumed
   gload(0);
   sstore();
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     if (kt + 1 < nk) gload(kt + 1);
+    // lane group g owns k = 4 g .. 4 g + 3 of the stage and feeds them to the 4 MFMA
+    // steps in turn (A and B alike, so every k meets its partner)
+    V4<T> af[4], bf[4];
 #pragma unroll
-    for (int ks = 0; ks < KT / 4; ++ks) {
-      T af[4], bf[4];
+    for (int a = 0; a < 4; ++a)
+      af[a] = *reinterpret_cast<const V4<T> *>(&As[wm * 64 + a * 16 + li][4 * g]);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) af[a] = As[wm * 64 + a * 16 + li][ks * 4 + g];
+    for (int b = 0; b < 4; ++b)
+      bf[b] = *reinterpret_cast<const V4<T> *>(&Bs[wn * 64 + b * 16 + li][4 * g]);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) bf[b] = Bs[wn * 64 + b * 16 + li][ks * 4 + g];
+    for (int ks = 0; ks < KT / 4; ++ks)
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::op(af[a], bf[b], acc[a][b]);
-    }
+        for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::op(af[a].x[ks], bf[b].x[ks], acc[a][b]);
     __syncthreads();
     if (kt + 1 < nk) {
       sstore();
@@ -279,35 +301,41 @@ k_gemm_bf(const __bf16 *__restrict__ Hp, size_t part, int ld_h, const double *__
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
   const int nk = (n + BKT - 1) / BKT;
-  for (int kt = 0; kt < nk; ++kt) {
+  // register stage of the next K step: A parts (zero past the padded width; ld_h is a
+  // multiple of 16) and 16 injections minus the base case (base flows added in FP64)
+  bf8 ra[NP][2];
+  double xv[16];
+  auto gload = [&](int kt) {
     const int kb = kt * BKT + lk;
-    // A parts (zero past the padded width; ld_h is a multiple of 16)
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-      bf8 v0, v1;
       if (kb < ld_h) {
         const bf8 *src = reinterpret_cast<const bf8 *>(Hp + q * part + (size_t)(m0 + lr) * ld_h + kb);
-        v0 = src[0];
-        v1 = src[1];
+        ra[q][0] = src[0];
+        ra[q][1] = src[1];
       } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          v0[e] = (__bf16)0.f;
-          v1[e] = (__bf16)0.f;
+          ra[q][0][e] = (__bf16)0.f;
+          ra[q][1][e] = (__bf16)0.f;
         }
       }
-      bf8 *dst = reinterpret_cast<bf8 *>(&As[q][lr * BLD + lk]);
-      dst[0] = v0;
-      dst[1] = v1;
     }
-    // B: 16 injections in FP64, split into NP BF16 parts
-    double xv[16];  // injection minus the base case (the base flows are added in FP64)
     if (brow && kb + 16 <= n) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) xv[e] = brow[kb + e] - pbase[kb + e];
     } else {
 #pragma unroll
       for (int e = 0; e < 16; ++e) xv[e] = (brow && kb + e < n) ? brow[kb + e] - pbase[kb + e] : 0.0;
+    }
+  };
+  // register stage -> LDS, X split into NP BF16 parts on the way
+  auto sstore = [&]() {
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      bf8 *dst = reinterpret_cast<bf8 *>(&As[q][lr * BLD + lk]);
+      dst[0] = ra[q][0];
+      dst[1] = ra[q][1];
     }
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
@@ -324,7 +352,12 @@ k_gemm_bf(const __bf16 *__restrict__ Hp, size_t part, int ld_h, const double *__
       dst[0] = v0;
       dst[1] = v1;
     }
+  };
+  gload(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    sstore();
     __syncthreads();
+    if (kt + 1 < nk) gload(kt + 1);  // in flight during this step's MFMAs
     bf8 af[NP][4], bfr[NP][4];
 #pragma unroll
     for (int q = 0; q < NP; ++q) {

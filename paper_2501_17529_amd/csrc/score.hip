@@ -285,14 +285,18 @@ __device__ __forceinline__ void scan_max_cand(const ScanArgs &A, int cand) {
     const int rows = min(rchunk, A.mon_pad - rc0);
     __syncthreads();
     // F~ of this chunk's rows; the N-0 loads enter the maxima here
-    // (every thread takes a share of the variant x row pairs; the N-0 maxima
-    // are kept in LDS by integer atomics on the non-negative bit patterns)
-    for (int i = tid; i < nv * rows; i += blockDim.x) {
-      const int vi = i / rows, rr = i - vi * rows;
+    // (every thread takes a share of the variant x row pairs; rows is a multiple
+    // of 64, so the 64 pairs of one wave belong to one variant: their N-0 maximum is
+    // reduced across the wave, then kept in LDS by one integer atomic on the
+    // non-negative bit pattern)
+    for (int i0 = tid - lane; i0 < nv * rows; i0 += blockDim.x) {
+      const int i = i0 + lane;
+      const int vi = i0 / rows, rr = i - vi * rows;
       bool nf = false;
       const T fv = ftilde(F + (size_t)vi * A.ld_f, A.inv_r, rc0 + rr, A.n_mon, nf);
       fs[(size_t)vi * rchunk + fs_pos(fs, rr)] = fv;
-      lds_max_nonneg(&s_n0[vi], tabs(fv));
+      const T m = wave_max(tabs(fv));
+      if (lane == 0) lds_max_nonneg(&s_n0[vi], m);
       if (nf) s_nf[vi] = 1;
     }
     __syncthreads();
