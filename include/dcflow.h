@@ -253,11 +253,16 @@ typedef struct {
                           16, 8, 4, 1 and FP64 runs 8, 4, 2, 1 (others: automatic) */
   int32_t scan_rchunk; /* monitored rows per LDS chunk, a multiple of 64; 0 = automatic */
   int32_t persistent;  /* nonzero: the scan runs as resident workgroups (4 per compute
-                          unit) that take candidates from a queue in descending rank */
+                          unit) that take work items from a queue                    */
+  int32_t scan_band;   /* monitored rows per work item (a multiple of 64, rounded to the
+                          row chunk); 0 = automatic: all rows when the scan's seed block
+                          is small, else bands whose seed slice stays in L2          */
 } dcflow_tuning;
 
 /* Sets / reads the batch's launch shapes (defaults: all zero).  E_ARG for a
- * negative value or a row chunk that is not a multiple of 64. */
+ * negative value or a row chunk or band that is not a multiple of 64.  The scan
+ * runs over work items (candidate, band of monitored rows), band-major, with the
+ * candidates of a band in descending rank. */
 int dcflow_batch_set_tuning(dcflow_batch *batch, const dcflow_tuning *tuning);
 int dcflow_batch_get_tuning(const dcflow_batch *batch, dcflow_tuning *tuning);
 

@@ -2,8 +2,8 @@
 
 For one batch shape (grid sizes, candidates, variants, precision, device
 architecture) it times dcflow_n1_score under every launch shape the library
-offers (variants per pass-1 workgroup, monitored rows per LDS chunk,
-persistent or one-workgroup-per-candidate launch), keeps only shapes whose
+offers (variants per pass-1 workgroup, monitored rows per LDS chunk and per
+work item, persistent or one-workgroup-per-item launch), keeps only shapes whose
 scores agree with the library's default, and caches the fastest.  The cache
 file is DCFLOW_AUTOTUNE_CACHE or ~/.cache/dcflow/autotune.json.
 
@@ -63,8 +63,18 @@ def candidates(batch: "D.Batch", n_var: int, prec: str):
     vcs = [0] + [v for v in VC_SETS["fp64" if prec == "fp64" else "fp32"]
                  if v <= max(1, n_var) and v > 1]
     rcs = sorted({0} | {r for r in (64, 128, 256, 512) if r <= mon_pad})
-    return [dict(scan_vc=vc, scan_rchunk=rc, persistent=pe)
-            for vc in vcs for rc in rcs for pe in (0, 1)]
+    # row bands matter only when the seed block outgrows L2
+    seed = mon_pad * batch.plan.view.ld_o * (8 if prec == "fp64" else 4)
+    bands = [0] + ([b for b in (64, 128, 256, 512, 1024) if b < mon_pad] if seed > (2 << 20) else [])
+    out = []
+    for vc in vcs:
+        for rc in rcs:
+            for band in bands:
+                if band and rc and rc > band:
+                    continue  # the chunk is capped at the band: same as rc = band
+                for pe in (0, 1):
+                    out.append(dict(scan_vc=vc, scan_rchunk=rc, persistent=pe, scan_band=band))
+    return out
 
 
 def _time_scan(batch, flows, n_var, prec, out, reps):
@@ -116,7 +126,7 @@ def tune_scan(batch: "D.Batch", flows, n_var: int, prec: str, reps: int = 3,
         if same and t < best_t:
             best, best_t = cfg, t
     if best is None:
-        best = dict(scan_vc=0, scan_rchunk=0, persistent=0)
+        best = dict(scan_vc=0, scan_rchunk=0, persistent=0, scan_band=0)
     batch.set_tuning(**best)
     if use_cache:
         cache = _load(path)

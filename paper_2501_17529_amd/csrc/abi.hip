@@ -185,6 +185,11 @@ void batch_layout(dcflow_batch *b, const dcflow_plan *p, const BatchDims &d, Are
   b->d_vmax = a.take<double>(nc * d.vmax);
   b->d_f0 = a.take<double>((size_t)d.vmax * p->ld_er);
   b->d_queue = a.take<int32_t>(16);
+  const size_t np = nc * (size_t)(p->mon_pad / 64);
+  b->d_part_m = a.take<double>(np);
+  b->d_part_ov = a.take<double>(np);
+  b->d_part_k = a.take<long long>(np);
+  b->d_part_nf = a.take<int32_t>(np);
 }
 
 void pst_flags(const dcflow_grid_desc *g, std::vector<uint8_t> &br, std::vector<uint8_t> &bus) {
@@ -485,7 +490,8 @@ int dcflow_batch_create(dcflow_plan *p, const dcflow_cands *c, int32_t n_var_max
   b->factored = 0;
   b->flows_prec = -1;
   b->flows_nvar = 0;
-  b->tune = dcflow_tuning{0, 0, 0};
+  b->tune = dcflow_tuning{0, 0, 0, 0};
+  b->max_bands = p->mon_pad / 64;
   b->graph = nullptr;
   b->graph_exec = nullptr;
   {
@@ -546,7 +552,8 @@ void dcflow_batch_destroy(dcflow_batch *b) {
 
 int dcflow_batch_set_tuning(dcflow_batch *b, const dcflow_tuning *t) {
   if (!b || !t) return DCFLOW_E_ARG;
-  if (t->scan_vc < 0 || t->scan_rchunk < 0 || t->scan_rchunk % 64 || t->persistent < 0)
+  if (t->scan_vc < 0 || t->scan_rchunk < 0 || t->scan_rchunk % 64 || t->persistent < 0 ||
+      t->scan_band < 0 || t->scan_band % 64)
     return DCFLOW_E_ARG;
   b->tune = *t;
   return DCFLOW_OK;

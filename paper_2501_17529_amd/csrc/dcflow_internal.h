@@ -89,6 +89,10 @@ struct dcflow_batch {
   double *d_vmax;   // [n_cand][vmax]
   double *d_f0;     // [vmax][ld_er] shared-injection GEMM output
   int32_t *d_queue; // [16] work-queue counters of the persistent scan
+  int max_bands;    // mon_pad / 64: most row bands of one candidate
+  double *d_part_m, *d_part_ov;  // [n_cand][max_bands] band partials of the winner pass
+  long long *d_part_k;
+  int32_t *d_part_nf;
   dcflow_tuning tune;
   int n_cu;               // compute units of the device the batch was created on
   hipGraph_t graph;       // captured step (dcflow_graph_capture), or null

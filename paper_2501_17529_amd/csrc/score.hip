@@ -84,13 +84,21 @@ struct ScanArgs {
   double *vmax;  // [n_cand][vmax_ld]
   int vmax_ld;
   dcflow_score *res;
-  int rchunk;  // rows per LDS chunk (multiple of 64)
-  int single;  // one variant: pass 2 alone
-  // persistent mode: resident workgroups take candidates from a queue (descending rank)
-  int persistent;
-  int n_cand;
-  const int32_t *order;  // [n_cand] queue order
+  int rchunk;     // rows per LDS chunk (multiple of 64)
+  int band_rows;  // rows per work item (a multiple of rchunk)
+  int single;     // one variant: pass 2 alone
+  // work items: (candidate, band of rchunk monitored rows), band-major so that the
+  // workgroups in flight share one band of the seed in L2; candidates in queue order
+  // (descending rank) within a band
+  int n_cand, nbands;
+  const int32_t *order;  // [n_cand]
+  int persistent;        // resident workgroups take items from a queue
   int32_t *queue;        // counters: [variant group] for pass 1, [kQueueWin] for pass 2
+  // per-band partial results of pass 2 ([n_cand][nbands])
+  double *part_m;      // band maximum
+  long long *part_k;   // lowest key attaining it in the band
+  double *part_ov;     // overload sum of the band
+  int32_t *part_nf;    // nonfinite flows of the winning variant seen in the band
 };
 
 constexpr int kQueueWin = 15;  // counter slot of pass 2
@@ -99,23 +107,34 @@ constexpr int kQueueWin = 15;  // counter slot of pass 2
 // shaped for four; more would only wait, fewer still drain the queue).
 constexpr int kPersistPerCu = 4;
 
-// Runs body(cand) for this workgroup's candidates: its own (blockIdx.x) or, in
-// persistent mode, queue positions taken one at a time until the queue is empty.
+// Runs body(cand, band) for this workgroup's work items: its own (blockIdx.x) or,
+// in persistent mode, queue positions taken one at a time until none are left.
 template <typename F>
-__device__ __forceinline__ void for_each_candidate(const ScanArgs &A, int slot, F body) {
+__device__ __forceinline__ void for_each_item(const ScanArgs &A, int slot, F body) {
+  const int n_items = A.n_cand * A.nbands;
+  auto run = [&](int q) {
+    const int band = q / A.n_cand;
+    body(A.order[q - band * A.n_cand], band);
+  };
   if (!A.persistent) {
-    body(blockIdx.x);
+    run(blockIdx.x);
     return;
   }
   __shared__ int s_pos;
   while (true) {
-    __syncthreads();  // the previous candidate is done with shared memory
+    __syncthreads();  // the previous item is done with shared memory
     if (threadIdx.x == 0) s_pos = atomicAdd(A.queue + slot, 1);
     __syncthreads();
     const int pos = s_pos;
-    if (pos >= A.n_cand) break;
-    body(A.order[pos]);
+    if (pos >= n_items) break;
+    run(pos);
   }
+}
+
+// running maximum of non-negative doubles in global memory (bit patterns order
+// like the values)
+__device__ __forceinline__ void global_max_nonneg(double *p, double v) {
+  atomicMax(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
 }
 
 template <typename T>
@@ -239,8 +258,11 @@ __device__ __forceinline__ T ycol(const T *Fv, const ScanArgs &A, int cand, int 
 }
 
 // ---------------------------------------------------------------- pass 1
+// Item (cand, band): maxima of the band's N-0 rows and of its N-1 rows against
+// every contingency, for the VC variants of blockIdx.y, merged into vmax by
+// atomic maxima (vmax is cleared by k_clear first).
 template <typename T, int VC>
-__device__ __forceinline__ void scan_max_cand(const ScanArgs &A, int cand) {
+__device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int band) {
   constexpr int TM = 64, TN = ScanCfg<T>::TN, NB = TN / 16;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int ld_o = A.ld_o, rchunk = A.rchunk;
@@ -256,16 +278,18 @@ __device__ __forceinline__ void scan_max_cand(const ScanArgs &A, int cand) {
   const uint32_t st = A.status[cand];
   const int vbeg = blockIdx.y * VC;
   const int nv = min(VC, A.nvar - vbeg);
+  double *vm = A.vmax + (size_t)cand * A.vmax_ld + vbeg;
   if (st & DCFLOW_ST_DISCONNECTED) {
-    if (tid < nv) A.vmax[(size_t)cand * A.vmax_ld + vbeg + tid] = __builtin_inf();
+    if (tid < nv && band == 0) global_max_nonneg(vm + tid, __builtin_inf());
     return;
   }
   if (tid < VC) {
     s_nf[tid] = 0;
     s_n0[tid] = (T)0;
   }
-  __syncthreads();
   const T *F = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vbeg) * A.ld_f;
+  const int r0 = band * A.band_rows, r1 = min(r0 + A.band_rows, A.mon_pad);
+  __syncthreads();
 
   // y for every contingency column and variant of the launch; a non-finite
   // flow marks its variant in s_nf at once (rare, so not kept in registers)
@@ -279,16 +303,14 @@ __device__ __forceinline__ void scan_max_cand(const ScanArgs &A, int cand) {
   T mx[VC];
 #pragma unroll
   for (int i = 0; i < VC; ++i) mx[i] = (T)0;
-
   const int ntc = ld_o / TN;
-  for (int rc0 = 0; rc0 < A.mon_pad; rc0 += rchunk) {
-    const int rows = min(rchunk, A.mon_pad - rc0);
+  for (int rc0 = r0; rc0 < r1; rc0 += rchunk) {
+    const int rows = min(rchunk, r1 - rc0);
     __syncthreads();
-    // F~ of this chunk's rows; the N-0 loads enter the maxima here
-    // (every thread takes a share of the variant x row pairs; rows is a multiple
-    // of 64, so the 64 pairs of one wave belong to one variant: their N-0 maximum is
-    // reduced across the wave, then kept in LDS by one integer atomic on the
-    // non-negative bit pattern)
+    // F~ of the chunk's rows; the N-0 loads enter the maxima here (every thread
+    // takes a share of the variant x row pairs; rows is a multiple of 64, so the 64
+    // pairs of one wave belong to one variant: their N-0 maximum is reduced across
+    // the wave, then kept in LDS by one integer atomic on the non-negative bit pattern)
     for (int i0 = tid - lane; i0 < nv * rows; i0 += blockDim.x) {
       const int i = i0 + lane;
       const int vi = i0 / rows, rr = i - vi * rows;
@@ -345,18 +367,24 @@ __device__ __forceinline__ void scan_max_cand(const ScanArgs &A, int cand) {
     double m = fmax(fmax(s_red[0][tid], s_red[1][tid]), fmax(s_red[2][tid], s_red[3][tid]));
     m = fmax(m, (double)s_n0[tid]);
     if (s_nf[tid]) m = __builtin_inf();
-    A.vmax[(size_t)cand * A.vmax_ld + vbeg + tid] = m;
+    global_max_nonneg(vm + tid, m);
   }
 }
 
 template <typename T, int VC, int MINW>
 __global__ void __launch_bounds__(256, MINW) k_scan_max(ScanArgs A) {
-  for_each_candidate(A, blockIdx.y, [&](int cand) { scan_max_cand<T, VC>(A, cand); });
+  for_each_item(A, blockIdx.y, [&](int cand, int band) { scan_max_item<T, VC>(A, cand, band); });
 }
 
 // ---------------------------------------------------------------- pass 2
+// Item (cand, band) of the winning variant v* (argmin of the pass-1 maxima, the
+// lowest index on ties): the band's maximum, the lowest (contingency, branch)
+// key attaining it (N-0 rows first: key = row), and its overload sum, written
+// as partials that k_scan_fin combines.  Per lane: the running maximum, the
+// first tile reaching it and whether a later tile reached it again; only the
+// tiles where a lane first reached the band maximum are built again for the key.
 template <typename T>
-__device__ __forceinline__ void scan_win_cand(const ScanArgs &A, int cand) {
+__device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int band) {
   constexpr int TM = 64, TN = ScanCfg<T>::TN, NB = TN / 16;
   constexpr long long kNoKey = 0x7fffffffffffffffLL;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -372,40 +400,23 @@ __device__ __forceinline__ void scan_win_cand(const ScanArgs &A, int cand) {
   const int e0 = A.off[cand];
   const int k = A.off[cand + 1] - e0;
   const uint32_t st = A.status[cand];
-  if (st & DCFLOW_ST_DISCONNECTED) {
-    if (tid == 0) {
-      dcflow_score r;
-      r.max_load = __builtin_inf();
-      r.overload_sum = 0.0;
-      r.best_variant = -1;
-      r.worst_branch = -1;
-      r.worst_outage = -1;
-      r.status = st;
-      A.res[cand] = r;
-      if (A.single) A.vmax[(size_t)cand * A.vmax_ld] = r.max_load;
-    }
-    return;
-  }
+  const size_t pidx = (size_t)cand * A.nbands + band;
+  if (st & DCFLOW_ST_DISCONNECTED) return;  // k_scan_fin writes the record
 
-  // winning variant: argmin of the pass-1 maxima (the lowest index on ties)
   if (tid == 0) {
-    int best = 0, nfl = 0;
+    int best = 0;
     if (!A.single) {
       double bv = A.vmax[(size_t)cand * A.vmax_ld];
-      bool any_inf = !finite_bits(bv);
       for (int v = 1; v < A.nvar; ++v) {
         const double x = A.vmax[(size_t)cand * A.vmax_ld + v];
-        any_inf |= !finite_bits(x);
         if (x < bv) {
           bv = x;
           best = v;
         }
       }
-      // a variant whose flows were not finite was given +inf by pass 1
-      if (any_inf) nfl = 2;
     }
     s_vstar = best;
-    s_nf = nfl;
+    s_nf = 0;
   }
   __syncthreads();
   const int vstar = s_vstar;
@@ -417,19 +428,19 @@ __device__ __forceinline__ void scan_win_cand(const ScanArgs &A, int cand) {
         c < A.n_out && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
     colw[c] = valid ? (T)1 : (T)0;
   }
+  const int r0 = band * A.band_rows, r1 = min(r0 + A.band_rows, A.mon_pad);
 
-  // N-0 rows: maximum and the lowest row attaining it
+  // N-0 rows of the band: maximum and the lowest row attaining it
   T b0 = (T)-1;
   int k0 = 0x7fffffff;
-  // N-1: running maximum per lane, the first tile where it was reached, and
-  // whether a later tile reached it again
+  double ov = 0.0;
+  // N-1: running maximum per lane, the first tile (global id) where it was
+  // reached, and whether a later tile reached it again
   T run = (T)-1;
   int first = -1, tie = 0;
-  double ov = 0.0;
-
   const int ntc = ld_o / TN;
-  for (int rc0 = 0; rc0 < A.mon_pad; rc0 += rchunk) {
-    const int rows = min(rchunk, A.mon_pad - rc0);
+  for (int rc0 = r0; rc0 < r1; rc0 += rchunk) {
+    const int rows = min(rchunk, r1 - rc0);
     __syncthreads();
     for (int rr = tid; rr < rows; rr += blockDim.x) {
       const int row = rc0 + rr;
@@ -492,7 +503,7 @@ __device__ __forceinline__ void scan_win_cand(const ScanArgs &A, int cand) {
     }
   }
 
-  // ---- maxima: N-0 and N-1 over the block
+  // ---- band maxima over the block
   {
     const T w0 = wave_max(b0), w1 = wave_max(run);
     const double os = wave_sum(ov);
@@ -507,19 +518,18 @@ __device__ __forceinline__ void scan_win_cand(const ScanArgs &A, int cand) {
   const T M0 = (T)fmax(fmax(s_m0[0], s_m0[1]), fmax(s_m0[2], s_m0[3]));
   const T M1 = (T)fmax(fmax(s_m1[0], s_m1[1]), fmax(s_m1[2], s_m1[3]));
 
-  // ---- lowest key attaining the maximum: N-0 rows first (key = row), then
-  // contingency-major (key = (c + 1) n_mon + row)
+  // ---- lowest key attaining the band maximum
   long long bestk = kNoKey;
   if (M0 >= M1) {
     bestk = b0 == M0 ? (long long)k0 : kNoKey;
   } else {
-    const int ntall = (A.mon_pad / TM) * ntc;
     // a lane that reached the maximum again in a later tile may hide a lower
-    // key anywhere: then the wave rebuilds every tile (rare exact ties)
+    // key anywhere: then the wave rebuilds every tile of the band (exact ties only)
+    const int t_end = (r1 / TM) * ntc;
     const bool want = run == M1;
     const bool all = __any(want && tie);
     bool done = !want;
-    int t = all ? 0 : -1;
+    int t = all ? (r0 / TM) * ntc : -1;
     while (true) {
       if (!all) {
         int c = done ? 0x7fffffff : first;
@@ -531,7 +541,7 @@ __device__ __forceinline__ void scan_win_cand(const ScanArgs &A, int cand) {
         if (c == 0x7fffffff) break;
         t = c;
         done = done || first == t;
-      } else if (t >= ntall) {
+      } else if (t >= t_end) {
         break;
       }
       const int tr = t / ntc, tc = t - tr * ntc;
@@ -566,38 +576,89 @@ __device__ __forceinline__ void scan_win_cand(const ScanArgs &A, int cand) {
   if (tid == 0) {
     long long k2 = s_key[0];
     for (int w = 1; w < 4; ++w) k2 = s_key[w] < k2 ? s_key[w] : k2;
-    const double osum = s_ov[0] + s_ov[1] + s_ov[2] + s_ov[3];
-    const double M = (double)(M0 > M1 ? M0 : M1);
-    dcflow_score r;
-    r.status = st | (s_nf ? DCFLOW_ST_NONFINITE : 0u);
-    const bool found = k2 != kNoKey;
-    const int c = found ? (int)(k2 / A.n_mon) - 1 : -1;
-    const int row = found ? (int)(k2 % A.n_mon) : -1;
-    r.max_load = s_nf == 1 ? __builtin_inf() : M;
-    r.overload_sum = osum;
-    r.best_variant = vstar;
-    r.worst_branch = found ? A.mon[row] : -1;
-    r.worst_outage = c >= 0 ? A.out[c] : -1;
-    A.res[cand] = r;
-    if (A.single) A.vmax[(size_t)cand * A.vmax_ld] = r.max_load;
+    A.part_m[pidx] = (double)(M0 > M1 ? M0 : M1);
+    A.part_k[pidx] = k2;
+    A.part_ov[pidx] = s_ov[0] + s_ov[1] + s_ov[2] + s_ov[3];
+    A.part_nf[pidx] = s_nf;
   }
 }
 
 template <typename T, int MINW>
 __global__ void __launch_bounds__(256, MINW) k_scan_win(ScanArgs A) {
-  for_each_candidate(A, kQueueWin, [&](int cand) { scan_win_cand<T>(A, cand); });
+  for_each_item(A, kQueueWin, [&](int cand, int band) { scan_win_item<T>(A, cand, band); });
 }
 
-// Clears the work-queue counters (a kernel, so that a captured graph resets them too).
-__global__ void k_queue_reset(int32_t *q, int n) {
-  if ((int)threadIdx.x < n) q[threadIdx.x] = 0;
+// One thread per candidate: combines the band partials into the score record.
+__global__ void k_scan_fin(ScanArgs A) {
+  const int cand = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cand >= A.n_cand) return;
+  constexpr long long kNoKey = 0x7fffffffffffffffLL;
+  const uint32_t st = A.status[cand];
+  dcflow_score r;
+  if (st & DCFLOW_ST_DISCONNECTED) {
+    r.max_load = __builtin_inf();
+    r.overload_sum = 0.0;
+    r.best_variant = -1;
+    r.worst_branch = -1;
+    r.worst_outage = -1;
+    r.status = st;
+    A.res[cand] = r;
+    if (A.single) A.vmax[(size_t)cand * A.vmax_ld] = r.max_load;
+    return;
+  }
+  int best = 0, any_inf = 0;
+  if (!A.single) {
+    double bv = A.vmax[(size_t)cand * A.vmax_ld];
+    any_inf = !finite_bits(bv);
+    for (int v = 1; v < A.nvar; ++v) {
+      const double x = A.vmax[(size_t)cand * A.vmax_ld + v];
+      any_inf |= !finite_bits(x);
+      if (x < bv) {
+        bv = x;
+        best = v;
+      }
+    }
+  }
+  const double *pm = A.part_m + (size_t)cand * A.nbands;
+  const long long *pk = A.part_k + (size_t)cand * A.nbands;
+  double M = pm[0], ov = 0.0;
+  int nf = 0;
+  for (int b = 0; b < A.nbands; ++b) {
+    M = fmax(M, pm[b]);
+    ov += A.part_ov[(size_t)cand * A.nbands + b];
+    nf |= A.part_nf[(size_t)cand * A.nbands + b];
+  }
+  long long key = kNoKey;
+  for (int b = 0; b < A.nbands; ++b)
+    if (pm[b] == M && pk[b] < key) key = pk[b];
+  // a variant whose flows were not finite was given +inf by pass 1; the
+  // winner's own non-finite flows make its maximum +inf
+  r.status = st | ((nf || any_inf) ? DCFLOW_ST_NONFINITE : 0u);
+  const bool found = key != kNoKey;
+  const int c = found ? (int)(key / A.n_mon) - 1 : -1;
+  const int row = found ? (int)(key % A.n_mon) : -1;
+  r.max_load = nf ? __builtin_inf() : M;
+  r.overload_sum = ov;
+  r.best_variant = best;
+  r.worst_branch = found ? A.mon[row] : -1;
+  r.worst_outage = c >= 0 ? A.out[c] : -1;
+  A.res[cand] = r;
+  if (A.single) A.vmax[(size_t)cand * A.vmax_ld] = r.max_load;
+}
+
+// Clears the work-queue counters and the per-variant maxima (a kernel, so that a
+// captured graph clears them too).
+__global__ void k_clear(int32_t *q, int nq, double *vmax, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (size_t)nq) q[i] = 0;
+  if (i < n) vmax[i] = 0.0;
 }
 
 // ---------------------------------------------------------------- launch
 constexpr size_t kLdsBudget = 64 * 1024;   // dynamic LDS per workgroup, at most
 constexpr size_t kLdsOccupancy = 38 * 1024; // fits four workgroups per CU
 
-// Rows per chunk: the requested count (a multiple of 64, capped at the padded
+// Rows per band: the requested count (a multiple of 64, capped at the padded
 // monitored rows) or, by default, the largest multiple of 64 that keeps the
 // block within `target` bytes (at least 64 rows).
 inline int choose_rchunk(int req, size_t fixed, size_t per_row, int mon_pad, size_t target) {
@@ -610,17 +671,40 @@ inline int choose_rchunk(int req, size_t fixed, size_t per_row, int mon_pad, siz
   return rc < mon_pad ? rc : mon_pad;
 }
 
+// Rows per work item (band) and per LDS chunk.  The band is the requested count
+// or, by default, all monitored rows when the seed block (rows x ld_o values) fits
+// a fraction of L2, else about kBandSeed bytes of seed, so that the candidates in
+// flight, which all work on one band, share its seed in L2.  The chunk never
+// exceeds the band, and the band is a whole number of chunks.
+constexpr size_t kSeedL2 = 2u << 20, kBandSeed = 4u << 20;
+inline void choose_rows(const dcflow_batch *bt, size_t fixed, size_t per_row, int mon_pad,
+                        int ld_o, size_t elem, ScanArgs &a) {
+  int band = bt->tune.scan_band;
+  if (band <= 0) {
+    const size_t seed = (size_t)mon_pad * ld_o * elem;
+    band = seed <= kSeedL2 ? mon_pad : (int)(kBandSeed / ((size_t)ld_o * elem)) / 64 * 64;
+  }
+  if (band < 64) band = 64;
+  if (band > mon_pad) band = mon_pad;
+  int rc = choose_rchunk(bt->tune.scan_rchunk, fixed, per_row, mon_pad, kLdsOccupancy);
+  if (rc > band) rc = band;
+  a.rchunk = rc;
+  a.band_rows = band < mon_pad ? band / rc * rc : mon_pad;
+  a.nbands = (mon_pad + a.band_rows - 1) / a.band_rows;
+}
+
 inline int grid_x(const dcflow_batch *bt, const ScanArgs &a) {
-  if (!a.persistent) return bt->n_cand;
+  const int items = a.n_cand * a.nbands;
+  if (!a.persistent) return items;
   const int resident = bt->n_cu * kPersistPerCu;
-  return bt->n_cand < resident ? bt->n_cand : resident;
+  return items < resident ? items : resident;
 }
 
 template <typename T, int VC, int MINW>
 hipError_t launch_max(const ScanArgs &a0, const dcflow_batch *bt, int nvar, hipStream_t s) {
   ScanArgs a = a0;
   const size_t fixed = sizeof(T) * (size_t)VC * a.ld_o;
-  a.rchunk = choose_rchunk(bt->tune.scan_rchunk, fixed, sizeof(T) * VC, a.mon_pad, kLdsOccupancy);
+  choose_rows(bt, fixed, sizeof(T) * VC, a.mon_pad, a.ld_o, sizeof(T), a);
   const size_t lds = fixed + sizeof(T) * (size_t)VC * a.rchunk;
   if (lds > kLdsBudget) return hipErrorInvalidValue;
   const int ny = (nvar + VC - 1) / VC;
@@ -685,14 +769,23 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   a.n_cand = bt->n_cand;
   a.order = bt->d_order;
   a.queue = bt->d_queue;
+  a.part_m = bt->d_part_m;
+  a.part_k = bt->d_part_k;
+  a.part_ov = bt->d_part_ov;
+  a.part_nf = bt->d_part_nf;
   a.rchunk = 0;
-  if (a.persistent) {
-    k_queue_reset<<<1, 64, 0, s>>>(bt->d_queue, kQueueWin + 1);
+  a.band_rows = 0;
+  a.nbands = 1;
+  {
+    const size_t nv = a.single ? 0 : (size_t)bt->n_cand * bt->vmax;
+    const size_t n = nv > (size_t)(kQueueWin + 1) ? nv : (size_t)(kQueueWin + 1);
+    k_clear<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(bt->d_queue, kQueueWin + 1, bt->d_vmax,
+                                                        nv);
     DCF_CHECK_LAUNCH();
   }
   if (!a.single) {
     // the requested variant group, else the widest whose y fits the LDS budget
-    // with one 64-row chunk and that the variants fill
+    // with one 64-row band and that the variants fill
     auto fits = [&](int vc) { return sizeof(T) * (size_t)vc * (p->ld_o + 64) <= kLdsBudget; };
     int vc = bt->tune.scan_vc;
     bool known = false;
@@ -708,10 +801,13 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
     if (e != hipSuccess) return e;
   }
   const size_t fixed = sizeof(T) * 2 * (size_t)p->ld_o;
-  a.rchunk = choose_rchunk(bt->tune.scan_rchunk, fixed, sizeof(T), p->mon_pad, kLdsOccupancy);
+  choose_rows(bt, fixed, sizeof(T), p->mon_pad, p->ld_o, sizeof(T), a);
+  if (a.nbands > bt->max_bands) return hipErrorInvalidValue;
   const size_t lds = fixed + sizeof(T) * (size_t)a.rchunk;
   if (lds > kLdsBudget) return hipErrorInvalidValue;
   k_scan_win<T, sizeof(T) == 4 ? 4 : 1><<<dim3(grid_x(bt, a)), dim3(256), lds, s>>>(a);
+  DCF_CHECK_LAUNCH();
+  k_scan_fin<<<(bt->n_cand + 255) / 256, 256, 0, s>>>(a);
   DCF_CHECK_LAUNCH();
   return hipSuccess;
 }

@@ -60,7 +60,7 @@ class Cands(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """dcflow_tuning: launch shapes of the N-1 scan (0 = automatic)."""
     _fields_ = [("scan_vc", ctypes.c_int32), ("scan_rchunk", ctypes.c_int32),
-                ("persistent", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("scan_band", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -351,8 +351,8 @@ class Batch:
                "dcflow_n1_score")
         return out
 
-    def set_tuning(self, scan_vc=0, scan_rchunk=0, persistent=0):
-        t = Tuning(int(scan_vc), int(scan_rchunk), int(persistent))
+    def set_tuning(self, scan_vc=0, scan_rchunk=0, persistent=0, scan_band=0):
+        t = Tuning(int(scan_vc), int(scan_rchunk), int(persistent), int(scan_band))
         _check(_lib.dcflow_batch_set_tuning(self.h, ctypes.byref(t)), "dcflow_batch_set_tuning")
 
     def get_tuning(self):

@@ -1,5 +1,5 @@
 """GPU tests of the orchestration layer: launch shapes (variant groups, row
-chunks, persistent queue) give the same scores as the default launch, a
+chunks, row bands, persistent queue) give the same scores as the default launch, a
 captured HIP graph of the whole step replays to the eager result (several
 replays, with eager work and new injections in between), and the autotuner
 records and re-applies its choice."""
@@ -68,7 +68,11 @@ def test_launch_shapes_agree(prec):
     flows = bt.eval_injections(x, nv, False, prec)
     ref = _scores(D, bt, flows, nv, prec)
     say(f"launch shapes {prec}: {len(autotune.candidates(bt, nv, prec))}")
-    for cfg in autotune.candidates(bt, nv, prec):
+    # row bands: the scan split into (candidate, band) work items whose partials
+    # are combined afterwards (the autotuner offers them only for large seeds)
+    banded = [dict(scan_vc=0, scan_rchunk=rc, persistent=pe, scan_band=b)
+              for b in (64, 128) for rc in (0, 64) for pe in (0, 1)]
+    for cfg in autotune.candidates(bt, nv, prec) + banded:
         bt.set_tuning(**cfg)
         assert bt.get_tuning() == cfg
         _same(_scores(D, bt, flows, nv, prec), ref, f"{prec} {cfg}")
@@ -87,7 +91,7 @@ def test_tuning_rejects_bad_values():
     w = _workload(n_cand=3, n_var=2)
     plan = D.Plan.from_workload(w)
     bt = D.Batch(plan, w.cands, 2)
-    for bad in ((0, 65, 0), (-1, 0, 0), (0, 0, -1)):
+    for bad in ((0, 65, 0, 0), (-1, 0, 0, 0), (0, 0, -1, 0), (0, 0, 0, 96), (0, 0, 0, -64)):
         t = D.Tuning(*bad)
         assert D._lib.dcflow_batch_set_tuning(bt.h, ctypes.byref(t)) == -1
     assert D._lib.dcflow_graph_launch(bt.h, None) == -1   # nothing captured

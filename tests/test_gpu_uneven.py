@@ -63,3 +63,12 @@ def test_uneven_share(uneven, prec):
                flows={i: bt.flows_view(flows, 1)[i].double().cpu().numpy() for i in idx})
     err = compare(w, gpu, res, r, idx, prec)
     say(f"uneven share {prec}: worst |d max_load| on the sample = {err:.3e}")
+    # one work item per candidate (every monitored row in one band): same scores
+    mon_pad = (len(w.mon) + 63) // 64 * 64
+    bt.set_tuning(persistent=1, scan_band=mon_pad)
+    out2 = bt.n1_score(flows, 1, prec)
+    torch.cuda.synchronize()
+    sc2 = D.Batch.scores_to_numpy(out2, bt.n_cand)
+    for key in ("max_load", "worst_branch", "worst_outage", "status"):
+        np.testing.assert_array_equal(sc2[key], sc[key], err_msg=key)
+    np.testing.assert_allclose(sc2["overload_sum"], sc["overload_sum"], rtol=1e-9, atol=1e-12)
