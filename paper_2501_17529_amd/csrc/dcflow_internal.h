@@ -88,6 +88,9 @@ struct dcflow_batch {
   double *d_z;      // [n_elem][vmax]
   double *d_vmax;   // [n_cand][vmax]
   double *d_f0;     // [vmax][ld_er] shared-injection GEMM output
+  __bf16 *d_xs;     // [3][xs_cols][ldx] BF16 parts of x - p_base (BF16 GEMM modes)
+  int ldx;          // n_inj rounded up to 32
+  size_t xs_cols;   // n_cand * vmax
   int32_t *d_queue; // [16] work-queue counters of the persistent scan
   int max_bands;    // mon_pad / 64: most row bands of one candidate
   double *d_part_m, *d_part_ov;  // [n_cand][max_bands] band partials of the winner pass

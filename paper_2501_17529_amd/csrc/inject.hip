@@ -276,13 +276,48 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
 // lane group g feeds k = 8 g .. 8 g + 7 of each 32-step (A and B alike).
 constexpr int BKT = 32, BLD = BKT + 8;  // K step and LDS row stride (bf16)
 
+// x - p_base split into NP BF16 parts, once per call (the GEMM's column tiles
+// are read by every row tile): part q of column col at Xs[q * xpart + col * ldx
+// + k], K padded with zeros to ldx (a multiple of BKT).  Each thread takes 8
+// consecutive k of one column: 64 bytes read, 16 bytes written per part.
 template <int NP>
 __global__ void __launch_bounds__(256)
-k_gemm_bf(const __bf16 *__restrict__ Hp, size_t part, int ld_h, const double *__restrict__ X,
-          int n, int ncols, int nvar, int shared, float *__restrict__ F, int ld_f,
-          const int32_t *__restrict__ off, const double *__restrict__ U, int ld_er,
+k_split_x(const double *__restrict__ X, int n, const double *__restrict__ pbase, int ncols,
+          int ldx, __bf16 *__restrict__ Xs, size_t xpart) {
+  const int groups = ldx / 8;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)ncols * groups) return;
+  const int col = (int)(idx / groups), k0 = (int)(idx - (size_t)col * groups) * 8;
+  const double *src = X + (size_t)col * n;
+  double xv[8];
+  if (k0 + 8 <= n) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) xv[e] = src[k0 + e] - pbase[k0 + e];
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) xv[e] = k0 + e < n ? src[k0 + e] - pbase[k0 + e] : 0.0;
+  }
+  __bf16 *dst = Xs + (size_t)col * ldx + k0;
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    bf8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const __bf16 b = (__bf16)(float)xv[e];
+      v[e] = b;
+      xv[e] -= (double)(float)b;
+    }
+    *reinterpret_cast<bf8 *>(dst + q * xpart) = v;
+  }
+}
+
+template <int NP>
+__global__ void __launch_bounds__(256)
+k_gemm_bf(const __bf16 *__restrict__ Hp, size_t part, int ld_h, const __bf16 *__restrict__ Xs,
+          size_t xpart, int ldx, int n, int ncols, int nvar, int shared, float *__restrict__ F,
+          int ld_f, const int32_t *__restrict__ off, const double *__restrict__ U, int ld_er,
           const double *__restrict__ z, int vmax, int correct, int n_mt, int n_nt,
-          const double *__restrict__ pbase, const double *__restrict__ fber) {
+          const double *__restrict__ fber) {
   __shared__ __attribute__((aligned(16))) __bf16 As[NP][BM * BLD];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[NP][BN * BLD];
   const int xcd = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
@@ -294,7 +329,7 @@ k_gemm_bf(const __bf16 *__restrict__ Hp, size_t part, int ld_h, const double *__
   // staging: each thread 16 consecutive k of one row of A and of B
   const int lr = tid >> 1, lk = (tid & 1) * 16;
   const int bcol = n0 + lr;
-  const double *brow = bcol < ncols ? X + (size_t)bcol * n : nullptr;
+  const __bf16 *bsrc = bcol < ncols ? Xs + (size_t)bcol * ldx : nullptr;
   f4 acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -302,9 +337,9 @@ k_gemm_bf(const __bf16 *__restrict__ Hp, size_t part, int ld_h, const double *__
     for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
   const int nk = (n + BKT - 1) / BKT;
   // register stage of the next K step: A parts (zero past the padded width; ld_h is a
-  // multiple of 16) and 16 injections minus the base case (base flows added in FP64)
-  bf8 ra[NP][2];
-  double xv[16];
+  // multiple of 16) and the parts of 16 injections minus the base case (base flows
+  // added in FP64; ldx covers every K step)
+  bf8 ra[NP][2], rb[NP][2];
   auto gload = [&](int kt) {
     const int kb = kt * BKT + lk;
 #pragma unroll
@@ -321,36 +356,31 @@ k_gemm_bf(const __bf16 *__restrict__ Hp, size_t part, int ld_h, const double *__
         }
       }
     }
-    if (brow && kb + 16 <= n) {
 #pragma unroll
-      for (int e = 0; e < 16; ++e) xv[e] = brow[kb + e] - pbase[kb + e];
-    } else {
+    for (int q = 0; q < NP; ++q) {
+      if (bsrc) {
+        const bf8 *src = reinterpret_cast<const bf8 *>(bsrc + q * xpart + kb);
+        rb[q][0] = src[0];
+        rb[q][1] = src[1];
+      } else {
 #pragma unroll
-      for (int e = 0; e < 16; ++e) xv[e] = (brow && kb + e < n) ? brow[kb + e] - pbase[kb + e] : 0.0;
+        for (int e = 0; e < 8; ++e) {
+          rb[q][0][e] = (__bf16)0.f;
+          rb[q][1][e] = (__bf16)0.f;
+        }
+      }
     }
   };
-  // register stage -> LDS, X split into NP BF16 parts on the way
+  // register stage -> LDS
   auto sstore = [&]() {
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-      bf8 *dst = reinterpret_cast<bf8 *>(&As[q][lr * BLD + lk]);
-      dst[0] = ra[q][0];
-      dst[1] = ra[q][1];
-    }
-#pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      bf8 v0, v1;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const __bf16 b0 = (__bf16)(float)xv[e], b1 = (__bf16)(float)xv[e + 8];
-        v0[e] = b0;
-        v1[e] = b1;
-        xv[e] -= (double)(float)b0;
-        xv[e + 8] -= (double)(float)b1;
-      }
-      bf8 *dst = reinterpret_cast<bf8 *>(&Bs[q][lr * BLD + lk]);
-      dst[0] = v0;
-      dst[1] = v1;
+      bf8 *da = reinterpret_cast<bf8 *>(&As[q][lr * BLD + lk]);
+      da[0] = ra[q][0];
+      da[1] = ra[q][1];
+      bf8 *db = reinterpret_cast<bf8 *>(&Bs[q][lr * BLD + lk]);
+      db[0] = rb[q][0];
+      db[1] = rb[q][1];
     }
   };
   gload(0);
@@ -441,19 +471,28 @@ hipError_t launch_gemm(const dcflow_plan *p, const T *He, int np, const double *
   dim3 grid(kXcd * ((n_nt + kXcd - 1) / kXcd) * n_mt);
   if constexpr (sizeof(T) == 4) {
     const size_t part = (size_t)p->ld_er * p->ld_h;
-    if (np == 3) {
-      k_gemm_bf<3><<<grid, dim3(256), 0, s>>>(p->d_heb, part, p->ld_h, X, p->n_inj, ncols, nvar,
-                                              shared, F, p->ld_er, bt->d_off, bt->d_U, p->ld_er,
-                                              bt->d_z, bt->vmax, correct, n_mt, n_nt, p->d_pbase,
-                                              p->d_fber);
-      DCF_CHECK_LAUNCH();
-      return hipSuccess;
-    }
-    if (np == 1) {
-      k_gemm_bf<1><<<grid, dim3(256), 0, s>>>(p->d_heb, part, p->ld_h, X, p->n_inj, ncols, nvar,
-                                              shared, F, p->ld_er, bt->d_off, bt->d_U, p->ld_er,
-                                              bt->d_z, bt->vmax, correct, n_mt, n_nt, p->d_pbase,
-                                              p->d_fber);
+    if (np == 3 || np == 1) {
+      if ((size_t)ncols > bt->xs_cols) return hipErrorInvalidValue;
+      const size_t xpart = bt->xs_cols * (size_t)bt->ldx;
+      const size_t nthr = (size_t)ncols * (bt->ldx / 8);
+      const dim3 sg((unsigned)((nthr + 255) / 256));
+      if (np == 3) {
+        k_split_x<3><<<sg, dim3(256), 0, s>>>(X, p->n_inj, p->d_pbase, ncols, bt->ldx, bt->d_xs,
+                                              xpart);
+        DCF_CHECK_LAUNCH();
+        k_gemm_bf<3><<<grid, dim3(256), 0, s>>>(p->d_heb, part, p->ld_h, bt->d_xs, xpart, bt->ldx,
+                                                p->n_inj, ncols, nvar, shared, F, p->ld_er,
+                                                bt->d_off, bt->d_U, p->ld_er, bt->d_z, bt->vmax,
+                                                correct, n_mt, n_nt, p->d_fber);
+      } else {
+        k_split_x<1><<<sg, dim3(256), 0, s>>>(X, p->n_inj, p->d_pbase, ncols, bt->ldx, bt->d_xs,
+                                              xpart);
+        DCF_CHECK_LAUNCH();
+        k_gemm_bf<1><<<grid, dim3(256), 0, s>>>(p->d_heb, part, p->ld_h, bt->d_xs, xpart, bt->ldx,
+                                                p->n_inj, ncols, nvar, shared, F, p->ld_er,
+                                                bt->d_off, bt->d_U, p->ld_er, bt->d_z, bt->vmax,
+                                                correct, n_mt, n_nt, p->d_fber);
+      }
       DCF_CHECK_LAUNCH();
       return hipSuccess;
     }

@@ -53,6 +53,19 @@ __device__ __forceinline__ double absmax3(double m, double a, double b) {
   return __builtin_fmax(__builtin_fmax(m, __builtin_fabs(a)), __builtin_fabs(b));
 }
 
+// acc + max(|a|, 1) + max(|b|, 1) in four VALU instructions (the compiler's fmax
+// spends three per element, and it puts a wait state after each asm statement)
+__device__ __forceinline__ float add_absmax1(float acc, float a, float b) {
+  float t, u;
+  asm("v_max_f32 %1, |%3|, 1.0\n\tv_max_f32 %2, |%4|, 1.0\n\t"
+      "v_add_f32 %0, %0, %1\n\tv_add_f32 %0, %0, %2"
+      : "+v"(acc), "=&v"(t), "=&v"(u) : "v"(a), "v"(b));
+  return acc;
+}
+__device__ __forceinline__ double add_absmax1(double acc, double a, double b) {
+  return acc + __builtin_fmax(__builtin_fabs(a), 1.0) + __builtin_fmax(__builtin_fabs(b), 1.0);
+}
+
 // running maximum of non-negative values in LDS: their IEEE bit patterns order
 // like the values, so an unsigned integer atomic max suffices
 __device__ __forceinline__ void lds_max_nonneg(float *p, float v) {
@@ -489,15 +502,20 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
       first = gt ? tid_tile : first;
       run = gt ? mt : run;
       if (mt > (T)1) {  // overloads in this lane's part of the tile
+        // per column: sum of max(|p|, 1) over the lane's 16 rows, less 16.  Loads
+        // within the rating add exactly 1, so rounding enters only where a
+        // row is overloaded, and the difference with 16 is exact.
+        T acc[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[b] = (T)0;
+#pragma unroll
+        for (int i = 0; i < 16; i += 2)
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+            acc[b] = add_absmax1(acc[b], pv[i / 4][b][i % 4], pv[i / 4][b][i % 4 + 1]);
         T o = (T)0;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          const T w = colw[colbase + b * 16 + li];
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) o = tfma(w, tmax(tabs(pv[a][b][r]) - (T)1, (T)0), o);
-        }
+        for (int b = 0; b < NB; ++b) o = tfma(colw[colbase + b * 16 + li], acc[b] - (T)16, o);
         ov += (double)o;
       }
     }
