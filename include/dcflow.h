@@ -22,6 +22,8 @@
  *                           relative load), t_i* = argmin over the variants,
  *                           then (metric-first, Sec. IV-B) the winner's
  *                           overload sum and worst (branch, contingency).
+ *   dcflow_n1_worst         agg_i: the k worst N-1 cases of the winning
+ *                           variant, recomputed after the score (Sec. IV-B).
  *   Together: Eq. solver_end_to_end, (t_b, t_d, T_i) -> (agg_m, agg_i, t_i*).
  *
  * Conventions
@@ -235,6 +237,37 @@ int dcflow_eval_injections(dcflow_batch *batch, const double *dev_inj, int32_t n
  * sum and worst case.  dev_out: [n_cand] dcflow_score (device). */
 int dcflow_n1_score(dcflow_batch *batch, const void *dev_flows, int32_t n_var,
                     dcflow_prec prec, dcflow_score *dev_out, hipStream_t stream);
+
+/* One case of the worst-case list (agg_i of Sec. III-A). */
+typedef struct {
+  double load;      /* |p| / rating; -1 for an unused entry                      */
+  int32_t branch;   /* monitored branch id; -1 for an unused entry               */
+  int32_t outage;   /* contingency branch id, -1 for the N-0 case (or unused)    */
+} dcflow_case;
+
+#define DCFLOW_WORST_MAX 16 /* most cases per candidate in one call */
+
+/* Device bytes of the workspace of dcflow_n1_worst for top_k cases. */
+int dcflow_n1_worst_workspace_bytes(const dcflow_batch *batch, int32_t top_k, size_t *bytes);
+
+/* agg_i (Sec. III-A) in metric-first mode (Sec. IV-B: the details are computed
+ * for the chosen variant only): for every candidate, the top_k largest relative
+ * loads of its winning variant over the monitored branches in N-0 and in every
+ * scored N-1 case (islanding contingencies excluded, as in the score), ordered
+ * by load descending, ties by case (N-0 first, then contingencies in the
+ * order of the grid's list) and then by the branch's position in the monitored
+ * list.  The winner is dev_scores[i].best_variant from a dcflow_n1_score call on
+ * the same batch and flows (device array, read on the stream); the entry with
+ * the largest load equals that call's (max_load, worst_branch, worst_outage).
+ * Candidates that are disconnected or have non-finite flows, and entries past
+ * the number of scored cases, are unused (load -1).  dev_ws: workspace of
+ * dcflow_n1_worst_workspace_bytes bytes; dev_out: [n_cand][top_k] (device).
+ * E_ARG for top_k outside 1..DCFLOW_WORST_MAX, or if (n_out + 1) * n_mon
+ * exceeds 2^31 - 1 (the case keys are 32-bit); E_WORKSPACE if ws_bytes is too
+ * small. */
+int dcflow_n1_worst(dcflow_batch *batch, const void *dev_flows, int32_t n_var, dcflow_prec prec,
+                    const dcflow_score *dev_scores, int32_t top_k, void *dev_ws, size_t ws_bytes,
+                    dcflow_case *dev_out, hipStream_t stream);
 
 /* Per-variant maxima of the last n1_score call: device pointer to
  * [n_cand][n_var_max] double (valid after the stream reaches it). */

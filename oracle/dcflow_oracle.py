@@ -398,6 +398,37 @@ def score_candidate(n, f, t, b, slack, elems, x, mon, out, rating, controls=None
                 loads_best=allload, scored_out=out[scored])
 
 
+def worst_cases(sc, mon, out, k):
+    """agg_i of Sec. III-A for the winning variant (metric-first mode, Sec. IV-B:
+    the details are produced for t_i* only): the k largest relative loads over
+    the monitored branches in N-0 and in every scored N-1 case, as a list of
+    (load, branch, outage) with outage -1 for N-0.  Order: load descending, ties
+    by case (N-0 first, then contingencies in the order of `out`), then by the
+    branch's position in `mon`.  `sc` is a result of score_candidate; a
+    disconnected candidate has no entries."""
+    if sc["best_variant"] < 0:
+        return []
+    mon = np.asarray(mon, np.int64)
+    out = np.asarray(out, np.int64)
+    loads = sc["loads_best"]               # [1 + n_scored, n_mon]
+    pos = {int(o): i for i, o in enumerate(out)}
+    cases = np.asarray([-1] + [int(o) for o in sc["scored_out"]], np.int64)
+    # ordering key of every entry: the branch's position for N-0, else
+    # (position of the contingency in `out` + 1) * n_mon + position
+    first = np.asarray([0] + [(pos[int(o)] + 1) * len(mon) for o in cases[1:]], np.int64)
+    keys = first[:, None] + np.arange(len(mon))[None, :]
+    flat = loads.ravel()
+    k = min(k, flat.size)
+    if k == 0:
+        return []
+    # every entry at or above the k-th largest load, then an exact sort of those
+    kth = np.partition(flat, flat.size - k)[flat.size - k]
+    sel = np.flatnonzero(flat >= kth)
+    order = sel[np.lexsort((keys.ravel()[sel], -flat[sel]))][:k]
+    ci, li = np.divmod(order, len(mon))
+    return [(float(flat[j]), int(mon[b]), int(cases[c])) for j, c, b in zip(order, ci, li)]
+
+
 def score_workload(w, idx=None, rating=None):
     """Score the candidates ``idx`` (default all) of a gridgen Workload."""
     g = w.grid

@@ -125,6 +125,11 @@ hipError_t launch_factors(dcflow_batch *b, hipStream_t s);
 hipError_t launch_injections(dcflow_batch *b, const double *inj, int nvar, int shared,
                              int prec, void *flows, hipStream_t s);
 // score (a5)
+// worst-case lists (agg_i) of the winners; worst_bands = row bands of that pass
+int worst_bands(const dcflow_plan *p);
+hipError_t launch_worst(dcflow_batch *b, const void *flows, int nvar, int prec,
+                        const dcflow_score *scores, int top_k, void *ws, dcflow_case *out,
+                        hipStream_t s);
 hipError_t launch_score(dcflow_batch *b, const void *flows, int nvar, int prec,
                         dcflow_score *out, hipStream_t s);
 

@@ -75,6 +75,12 @@ __device__ __forceinline__ void lds_max_nonneg(double *p, double v) {
   atomicMax(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
 }
 
+// one entry of a band's worst-case list: load, key (row for N-0, (c + 1) n_mon + row)
+struct WEntry {
+  double v;
+  int k, pad;
+};
+
 // kernel arguments shared by both passes
 struct ScanArgs {
   const void *F;  // [n_cand][nvar][ld_f] flows of the kept rows (T)
@@ -112,6 +118,10 @@ struct ScanArgs {
   long long *part_k;   // lowest key attaining it in the band
   double *part_ov;     // overload sum of the band
   int32_t *part_nf;    // nonfinite flows of the winning variant seen in the band
+  // worst-case lists (dcflow_n1_worst)
+  const dcflow_score *scores;  // [n_cand] winners of a preceding n1_score
+  int top_k;
+  WEntry *wpart;       // [n_cand][nbands][top_k] band lists of dcflow_n1_worst
 };
 
 constexpr int kQueueWin = 15;  // counter slot of pass 2
@@ -672,6 +682,253 @@ __global__ void k_clear(int32_t *q, int nq, double *vmax, size_t n) {
   if (i < n) vmax[i] = 0.0;
 }
 
+// ---------------------------------------------------------------- worst cases
+// agg_i for the winner (metric-first recompute): the top_k largest loads of
+// v* over the band's N-0 rows and valid N-1 cases, ordered by load descending,
+// then key ascending (key = row for N-0, (c + 1) n_mon + row for N-1).  Each
+// lane keeps a sorted list of KM entries in registers; a tile is examined
+// element by element only when its lane maximum reaches the lane's last entry.
+// The band's list is then taken from the lanes' heads, one entry per round.
+template <typename T>
+__device__ __forceinline__ bool better(T v, int k, T w, int kw) {
+  return v > w || (v == w && k < kw);
+}
+
+template <typename T, int KM>
+__device__ __forceinline__ void list_insert(T (&lv)[KM], int (&lk)[KM], T v, int k) {
+#pragma unroll
+  for (int j = KM - 1; j > 0; --j) {
+    const bool up = better(v, k, lv[j - 1], lk[j - 1]);
+    const bool here = better(v, k, lv[j], lk[j]);
+    lv[j] = up ? lv[j - 1] : (here ? v : lv[j]);
+    lk[j] = up ? lk[j - 1] : (here ? k : lk[j]);
+  }
+  if (better(v, k, lv[0], lk[0])) {
+    lv[0] = v;
+    lk[0] = k;
+  }
+}
+
+template <typename T, int KM>
+__device__ __forceinline__ void scan_worst_item(const ScanArgs &A, int cand, int band) {
+  constexpr int TM = 64, TN = ScanCfg<T>::TN, NB = TN / 16, NE = 4 * NB;
+  constexpr int kEmpty = 0x7fffffff;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  const int ld_o = A.ld_o, rchunk = A.rchunk;
+  T *ys = reinterpret_cast<T *>(smem_raw);  // [ld_o]
+  T *colw = ys + ld_o;                      // [ld_o]
+  T *fs = colw + ld_o;                      // [rchunk]
+  T *tv = fs + rchunk;                      // [4 waves][NE][64] values of a block under review
+  __shared__ T s_bv[4];
+  __shared__ int s_bk[4];
+
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, g = lane / 16, li = lane % 16;
+  const int e0 = A.off[cand];
+  const int k = A.off[cand + 1] - e0;
+  const dcflow_score sc = A.scores[cand];
+  WEntry *dst = A.wpart + ((size_t)cand * A.nbands + band) * A.top_k;
+  const bool skip = (sc.status & (DCFLOW_ST_DISCONNECTED | DCFLOW_ST_NONFINITE)) != 0 ||
+                    sc.best_variant < 0 || sc.best_variant >= A.nvar;
+  T lv[KM];
+  int lk[KM];
+#pragma unroll
+  for (int j = 0; j < KM; ++j) {
+    lv[j] = (T)-1;
+    lk[j] = kEmpty;
+  }
+  if (!skip) {
+    const T *Fv = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + sc.best_variant) * A.ld_f;
+    T *tvw = tv + (size_t)wv * NE * kWave;
+    bool nf = false;
+    for (int c = tid; c < ld_o; c += blockDim.x) {
+      ys[c] = ycol(Fv, A, cand, c, nf);
+      const bool valid =
+          c < A.n_out && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
+      colw[c] = valid ? (T)1 : (T)0;
+    }
+    const int r0 = band * A.band_rows, r1 = min(r0 + A.band_rows, A.mon_pad);
+    const int ntc = ld_o / TN;
+    for (int rc0 = r0; rc0 < r1; rc0 += rchunk) {
+      const int rows = min(rchunk, r1 - rc0);
+      __syncthreads();
+      for (int rr = tid; rr < rows; rr += blockDim.x) {
+        const int row = rc0 + rr;
+        const T fv = ftilde(Fv, A.inv_r, row, A.n_mon, nf);
+        fs[fs_pos(fs, rr)] = fv;
+        if (row < A.n_mon && better(tabs(fv), row, lv[KM - 1], lk[KM - 1]))
+          list_insert(lv, lk, tabs(fv), row);
+      }
+      __syncthreads();
+      const int nt = (rows / TM) * ntc;
+      for (int tile = wv; tile < nt; tile += 4) {
+        const int tr = tile / ntc, tc = tile - tr * ntc;
+        const int rowbase = rc0 + tr * TM, colbase = tc * TN;
+        T L[4][NB][4];
+        build_tile(L, A, e0, k, rowbase, colbase, g, li, lane);
+        const T *fsv = fs + (rowbase - rc0) + 4 * g;
+        T fr[4][4], yc[NB];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) fr[a][r] = fsv[a * 16 + r];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) yc[b] = ys[colbase + b * 16 + li];
+        T pv[4][NB][4], ma[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          ma[a] = (T)0;
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; r += 2) {
+              pv[a][b][r] = tfma(L[a][b][r], yc[b], fr[a][r]);
+              pv[a][b][r + 1] = tfma(L[a][b][r + 1], yc[b], fr[a][r + 1]);
+              ma[a] = absmax3(ma[a], pv[a][b][r], pv[a][b][r + 1]);
+            }
+        }
+        // The best of the lanes' last entries bounds the wave's top_k-th case
+        // from below: a value under it cannot enter the result.  A 16-row block
+        // whose lane maximum reaches both bounds is reviewed element by element
+        // through the wave's LDS slot (element i of a lane at i * 64 + lane), so
+        // that one copy of the insertion code serves all its elements.
+        T wt = lv[KM - 1];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) wt = tmax(wt, __shfl_xor(wt, o));
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          if (!__any(ma[a] >= lv[KM - 1] && ma[a] >= wt)) continue;
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tvw[(b * 4 + r) * kWave + lane] = pv[a][b][r];
+#pragma unroll 1
+          for (int i = 0; i < NE; ++i) {
+            const int b = i / 4, r = i % 4;
+            const int row = rowbase + a * 16 + MfmaRow<T>::row(g, r);
+            const int c = colbase + b * 16 + li;
+            const T v = tabs(tvw[i * kWave + lane]);
+            const int key = (c + 1) * A.n_mon + row;
+            const bool ok = colw[c] != (T)0 && row < A.n_mon && v >= wt &&
+                            better(v, key, lv[KM - 1], lk[KM - 1]);
+            if (ok) list_insert(lv, lk, v, key);
+          }
+        }
+      }
+    }
+  }
+  // the band's list: rounds of "best head over the block"; the winning lane pops.
+  // Keys are unique among real entries, and empty entries never win.
+  for (int j = 0; j < A.top_k; ++j) {
+    T bv = lv[0];
+    int bk = lk[0];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const T ov = __shfl_xor(bv, o);
+      const int ok = __shfl_xor(bk, o);
+      if (better(ov, ok, bv, bk)) {
+        bv = ov;
+        bk = ok;
+      }
+    }
+    if (lane == 0) {
+      s_bv[wv] = bv;
+      s_bk[wv] = bk;
+    }
+    __syncthreads();
+    T wbv = s_bv[0];
+    int wbk = s_bk[0];
+#pragma unroll
+    for (int w = 1; w < 4; ++w)
+      if (better(s_bv[w], s_bk[w], wbv, wbk)) {
+        wbv = s_bv[w];
+        wbk = s_bk[w];
+      }
+    if (tid == 0) {
+      WEntry e;
+      e.v = wbk == kEmpty ? -1.0 : (double)wbv;
+      e.k = wbk;
+      e.pad = 0;
+      dst[j] = e;
+    }
+    if (wbk != kEmpty && lk[0] == wbk) {
+#pragma unroll
+      for (int q = 0; q < KM - 1; ++q) {
+        lv[q] = lv[q + 1];
+        lk[q] = lk[q + 1];
+      }
+      lv[KM - 1] = (T)-1;
+      lk[KM - 1] = kEmpty;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int KM, int MINW>
+__global__ void __launch_bounds__(256, MINW) k_scan_worst(ScanArgs A) {
+  for_each_item(A, kQueueWin, [&](int cand, int band) { scan_worst_item<T, KM>(A, cand, band); });
+}
+
+// One wave per candidate: merges the bands' sorted lists (lane b walks bands b,
+// b + 64, ..., at most kFinBands in all) into the final list of top_k cases.
+constexpr int kFinBandsPerLane = 8, kFinBands = 64 * kFinBandsPerLane;
+
+__global__ void __launch_bounds__(64) k_worst_fin(ScanArgs A, dcflow_case *out) {
+  constexpr int kEmpty = 0x7fffffff;
+  const int cand = blockIdx.x, lane = threadIdx.x;
+  const WEntry *base = A.wpart + (size_t)cand * A.nbands * A.top_k;
+  int pos[kFinBandsPerLane];
+#pragma unroll
+  for (int q = 0; q < kFinBandsPerLane; ++q) pos[q] = 0;
+  for (int j = 0; j < A.top_k; ++j) {
+    double bv = -1.0;
+    int bk = kEmpty, bq = -1;
+#pragma unroll
+    for (int q = 0; q < kFinBandsPerLane; ++q) {
+      const int b = lane + 64 * q;
+      if (b < A.nbands && pos[q] < A.top_k) {
+        const WEntry e = base[(size_t)b * A.top_k + pos[q]];
+        if (e.k != kEmpty && better(e.v, e.k, bv, bk)) {
+          bv = e.v;
+          bk = e.k;
+          bq = q;
+        }
+      }
+    }
+    double wv = bv;
+    int wk = bk;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double ov = __shfl_xor(wv, o);
+      const int ok = __shfl_xor(wk, o);
+      if (better(ov, ok, wv, wk)) {
+        wv = ov;
+        wk = ok;
+      }
+    }
+    if (bq >= 0 && bk == wk && wk != kEmpty) {
+#pragma unroll
+      for (int q = 0; q < kFinBandsPerLane; ++q)
+        if (q == bq) ++pos[q];
+    }
+    if (lane == 0) {
+      dcflow_case e;
+      if (wk == kEmpty) {
+        e.load = -1.0;
+        e.branch = -1;
+        e.outage = -1;
+      } else {
+        const bool n0 = wk < A.n_mon;
+        const int row = n0 ? wk : wk % A.n_mon;
+        const int c = n0 ? -1 : wk / A.n_mon - 1;
+        e.load = wv;
+        e.branch = A.mon[row];
+        e.outage = c >= 0 ? A.out[c] : -1;
+      }
+      out[(size_t)cand * A.top_k + j] = e;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launch
 constexpr size_t kLdsBudget = 64 * 1024;   // dynamic LDS per workgroup, at most
 constexpr size_t kLdsOccupancy = 38 * 1024; // fits four workgroups per CU
@@ -830,7 +1087,95 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   return hipSuccess;
 }
 
+// Row bands of the worst-case pass: a fixed rule (all rows when the FP32 seed is
+// small, else about kBandSeed of FP64 seed, at most kFinBands bands), so that the
+// workspace size depends on the batch alone.
+inline int worst_band_rows(const dcflow_plan *p) {
+  const int mon_pad = p->mon_pad;
+  if ((size_t)mon_pad * p->ld_o * sizeof(float) <= kSeedL2) return mon_pad;
+  int band = (int)(kBandSeed / ((size_t)p->ld_o * sizeof(double))) / 64 * 64;
+  if (band < 64) band = 64;
+  const int least = (mon_pad + kFinBands - 1) / kFinBands;
+  if (band < least) band = (least + 63) / 64 * 64;
+  return band < mon_pad ? band : mon_pad;
+}
+
+template <typename T>
+hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_score *scores,
+                     int top_k, void *ws, dcflow_case *out, hipStream_t s) {
+  dcflow_plan *p = bt->plan;
+  constexpr int NB = ScanCfg<T>::TN / 16;
+  ScanArgs a;
+  a.F = flows;
+  a.ld_f = p->ld_er;
+  a.nvar = nvar;
+  a.off = bt->d_off;
+  a.U = bt->d_U;
+  a.ld_er = p->ld_er;
+  a.W = bt->d_W;
+  a.ld_o = p->ld_o;
+  a.invden = bt->d_invden;
+  a.isl = bt->d_isl;
+  a.status = bt->d_status;
+  a.lsd = p->d_lsd;
+  a.lsd32 = p->d_lsd32;
+  a.inv_r = p->d_inv_r;
+  a.n_mon = p->n_mon;
+  a.mon_pad = p->mon_pad;
+  a.out_pos = p->d_out_pos;
+  a.n_out = p->n_out;
+  a.mon = p->d_mon;
+  a.out = p->d_out;
+  a.vmax = nullptr;
+  a.vmax_ld = 0;
+  a.res = nullptr;
+  a.single = 0;
+  a.persistent = 0;
+  a.n_cand = bt->n_cand;
+  a.order = bt->d_order;
+  a.queue = nullptr;
+  a.part_m = nullptr;
+  a.part_k = nullptr;
+  a.part_ov = nullptr;
+  a.part_nf = nullptr;
+  a.scores = scores;
+  a.top_k = top_k;
+  a.wpart = static_cast<WEntry *>(ws);
+  const size_t fixed = sizeof(T) * (2 * (size_t)p->ld_o + 4 * (size_t)(4 * NB) * kWave);
+  int band = worst_band_rows(p);
+  int rc = choose_rchunk(0, fixed, sizeof(T), p->mon_pad, kLdsOccupancy);
+  if (rc > band) rc = band;
+  a.rchunk = rc;
+  a.band_rows = band;  // a multiple of 64; the last chunk of a band may be shorter
+  a.nbands = worst_bands(p);
+  const size_t lds = fixed + sizeof(T) * (size_t)rc;
+  if (lds > kLdsBudget) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((size_t)a.n_cand * a.nbands));
+  if (top_k <= 8)
+    k_scan_worst<T, 8, 1><<<grid, dim3(256), lds, s>>>(a);
+  else
+    k_scan_worst<T, 16, 1><<<grid, dim3(256), lds, s>>>(a);
+  DCF_CHECK_LAUNCH();
+  k_worst_fin<<<dim3(bt->n_cand), dim3(64), 0, s>>>(a, out);
+  DCF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
 }  // namespace
+
+int worst_bands(const dcflow_plan *p) {
+  const int band = worst_band_rows(p);
+  return (p->mon_pad + band - 1) / band;
+}
+
+hipError_t launch_worst(dcflow_batch *bt, const void *flows, int nvar, int prec,
+                        const dcflow_score *scores, int top_k, void *ws, dcflow_case *out,
+                        hipStream_t s) {
+  if (bt->n_cand == 0) return hipSuccess;
+  if (prec == DCFLOW_FP64)
+    return run_worst<double>(bt, static_cast<const double *>(flows), nvar, scores, top_k, ws, out, s);
+  return run_worst<float>(bt, static_cast<const float *>(flows), nvar, scores, top_k, ws, out, s);
+}
 
 hipError_t launch_score(dcflow_batch *bt, const void *flows, int nvar, int prec, dcflow_score *out,
                         hipStream_t s) {

@@ -27,6 +27,8 @@ ST_ISLAND_SHIFT = 8
 
 SCORE_DTYPE = np.dtype([("max_load", "<f8"), ("overload_sum", "<f8"), ("best_variant", "<i4"),
                         ("worst_branch", "<i4"), ("worst_outage", "<i4"), ("status", "<u4")])
+CASE_DTYPE = np.dtype([("load", "<f8"), ("branch", "<i4"), ("outage", "<i4")])
+WORST_MAX = 16
 
 
 class DcflowError(RuntimeError):
@@ -104,6 +106,8 @@ def _load():
         "dcflow_mlp_bf16_bytes": (SZ, []),
         "dcflow_mlp_workspace_bytes": (SZ, [I32]),
         "dcflow_snapshot_flows": (ctypes.c_int, [P, P, I32, P, P, P]),
+        "dcflow_n1_worst_workspace_bytes": (ctypes.c_int, [P, I32, P]),
+        "dcflow_n1_worst": (ctypes.c_int, [P, P, I32, ctypes.c_int, P, I32, P, SZ, P, P]),
         "dcflow_batch_set_tuning": (ctypes.c_int, [P, P]),
         "dcflow_batch_get_tuning": (ctypes.c_int, [P, P]),
         "dcflow_graph_capture": (ctypes.c_int, [P, P, I32, I32, ctypes.c_int, P, SZ, P, P]),
@@ -132,7 +136,8 @@ EXPORTED = ("dcflow_plan_workspace_bytes", "dcflow_build_ptdf", "dcflow_plan_vie
             "dcflow_plan_destroy", "dcflow_validate_candidates", "dcflow_batch_bytes",
             "dcflow_batch_create", "dcflow_batch_destroy", "dcflow_eval_topologies",
             "dcflow_flow_bytes", "dcflow_eval_injections", "dcflow_n1_score",
-            "dcflow_batch_variant_max", "dcflow_strerror", "dcflow_batch_set_tuning",
+            "dcflow_batch_variant_max", "dcflow_strerror", "dcflow_n1_worst_workspace_bytes",
+            "dcflow_n1_worst", "dcflow_batch_set_tuning",
             "dcflow_batch_get_tuning", "dcflow_graph_capture", "dcflow_graph_launch", "dcflow_mlp_param_count",
             "dcflow_mlp_bf16_bytes", "dcflow_mlp_workspace_bytes", "dcflow_snapshot_flows",
             "dcflow_snapshot_pairs", "dcflow_action_features", "dcflow_improvement_labels",
@@ -350,6 +355,31 @@ class Batch:
                                     PREC[prec], ctypes.c_void_p(out.data_ptr()), _stream(stream)),
                "dcflow_n1_score")
         return out
+
+    def n1_worst(self, flows, n_var, prec, scores, top_k, out=None, stream=None):
+        """The top_k worst cases of every candidate's winning variant (agg_i);
+        `scores` is the device output of n1_score on the same flows.  Returns a
+        device uint8 tensor of n_cand x top_k CASE_DTYPE records."""
+        import torch
+        nb = ctypes.c_size_t(0)
+        _check(_lib.dcflow_n1_worst_workspace_bytes(self.h, int(top_k), ctypes.byref(nb)),
+               "dcflow_n1_worst_workspace_bytes")
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=self.plan.device)
+        if out is None:
+            out = torch.empty(max(self.n_cand, 1) * int(top_k) * CASE_DTYPE.itemsize,
+                              dtype=torch.uint8, device=self.plan.device)
+        _check(_lib.dcflow_n1_worst(self.h, ctypes.c_void_p(flows.data_ptr()), int(n_var),
+                                    PREC[prec], ctypes.c_void_p(scores.data_ptr()), int(top_k),
+                                    ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(nb.value),
+                                    ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+               "dcflow_n1_worst")
+        self._worst_ws = ws  # kept until the stream is done with it (next call or object end)
+        return out
+
+    @staticmethod
+    def cases_to_numpy(out, n_cand, top_k):
+        raw = out.cpu().numpy()[: n_cand * top_k * CASE_DTYPE.itemsize]
+        return raw.view(CASE_DTYPE).reshape(n_cand, top_k)
 
     def set_tuning(self, scan_vc=0, scan_rchunk=0, persistent=0, scan_band=0):
         t = Tuning(int(scan_vc), int(scan_rchunk), int(persistent), int(scan_band))

@@ -119,3 +119,34 @@ def oracle_scores(w, idx, rating, variants=None):
 def oracle_rating(w):
     g = w.grid
     return O.ratings(g.n_bus, g.f, g.t, g.b, g.slack, g.p, w.mon, w.rating_scale, w.rating_offset)
+
+
+def compare_worst(w, cases, score, oracle_sc, top_k, prec, ctx=""):
+    """One candidate's worst-case list from the GPU against the oracle's: the
+    sorted loads agree within the tolerance rank by rank; every listed case is a
+    scored case whose oracle load matches; no case repeats; the first entry is
+    the score record's maximum and worst case, bit for bit.  Near-equal loads
+    may come in either order."""
+    tol = TOL[prec]
+    want = O.worst_cases(oracle_sc, w.mon, w.out, top_k)
+    used = cases[cases["branch"] >= 0]
+    assert len(used) == len(want), (ctx, len(used), len(want))
+    if not len(want):
+        assert np.all(cases["load"] == -1.0), ctx
+        return 0.0
+    np.testing.assert_allclose(used["load"], [v for v, _, _ in want], atol=tol, rtol=0,
+                               err_msg=f"{ctx}: ranked loads")
+    assert np.all(np.diff(used["load"]) <= 0), (ctx, "not sorted")
+    pairs = list(zip(used["branch"].tolist(), used["outage"].tolist()))
+    assert len(set(pairs)) == len(pairs), (ctx, "repeated case")
+    # oracle load of every listed case
+    mon_pos = {int(b): i for i, b in enumerate(w.mon)}
+    cases_o = [-1] + [int(o) for o in oracle_sc["scored_out"]]
+    row_of = {o: ci for ci, o in enumerate(cases_o)}
+    for (b, o), v in zip(pairs, used["load"]):
+        assert o in row_of, (ctx, "not a scored case", b, o)
+        lo = oracle_sc["loads_best"][row_of[o], mon_pos[b]]
+        assert abs(lo - v) <= tol, (ctx, b, o, lo, v)
+    assert used["load"][0] == score["max_load"], (ctx, used["load"][0], score["max_load"])
+    assert (used["branch"][0], used["outage"][0]) == (score["worst_branch"], score["worst_outage"]), ctx
+    return float(np.abs(used["load"] - np.array([v for v, _, _ in want])).max())

@@ -9,7 +9,7 @@ import pytest
 
 import gridgen as G
 
-from _gpu_common import compare, gpu_available, oracle_rating, oracle_scores, say
+from _gpu_common import compare, compare_worst, gpu_available, oracle_rating, oracle_scores, say
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
@@ -72,3 +72,8 @@ def test_uneven_share(uneven, prec):
     for key in ("max_load", "worst_branch", "worst_outage", "status"):
         np.testing.assert_array_equal(sc2[key], sc[key], err_msg=key)
     np.testing.assert_allclose(sc2["overload_sum"], sc["overload_sum"], rtol=1e-9, atol=1e-12)
+    # agg_i of the winners (row bands merged), sampled against the oracle
+    cases = D.Batch.cases_to_numpy(bt.n1_worst(flows, 1, prec, out, 16), bt.n_cand, 16)
+    assert np.all(cases["load"][:, 0] == sc["max_load"])
+    for ci, i in enumerate(idx):
+        compare_worst(w, cases[i], sc[i], res[ci], 16, prec, f"uneven {prec} cand {i}")

@@ -51,6 +51,56 @@ def test_triangle_score_by_hand():
     assert (sc["worst_outage"], sc["worst_branch"]) == (2, 0)
 
 
+def test_triangle_worst_cases_by_hand():
+    # the triangle above: N-0 loads (5/6, 1/6, 5/9); losing edge 0: (0, 1, 1.25); edge 1:
+    # (1, 0, 5/12); edge 2: (1.5, 0.5, 0).  Two loads of exactly 1 tie: the case of edge
+    # 0 comes first.
+    f = np.array([1, 1, 2])
+    t = np.array([0, 2, 0])
+    x = np.array([[-1.5, 1.0, 0.5]])
+    r = np.array([1.0, 1.0, 1.2])
+    mon = out = np.arange(3)
+    sc = O.score_candidate(3, f, t, np.ones(3), 0, [], x, mon, out, r)
+    got = O.worst_cases(sc, mon, out, 7)
+    want = [(1.5, 0, 2), (1.25, 2, 0), (1.0, 1, 0), (1.0, 0, 1), (5 / 6, 0, -1), (5 / 9, 2, -1),
+            (0.5, 1, 2)]
+    np.testing.assert_allclose([v for v, _, _ in got], [v for v, _, _ in want], atol=1e-14)
+    # the two loads of 1 are equal only up to rounding: either order is right
+    assert [(b, o) for _, b, o in got[:2]] == [(0, 2), (2, 0)]
+    assert {(b, o) for _, b, o in got[2:4]} == {(1, 0), (0, 1)}
+    assert [(b, o) for _, b, o in got[4:]] == [(0, -1), (2, -1), (1, 2)]
+    assert O.worst_cases(sc, mon, out, 1)[0][1:] == (sc["worst_branch"], sc["worst_outage"])
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_worst_cases_match_bruteforce(seed):
+    """The k worst cases of the winner, by re-factorising per contingency."""
+    w = G.workload_tiny(seed)
+    g = w.grid
+    r = O.ratings(g.n_bus, g.f, g.t, g.b, g.slack, g.p, w.mon, w.rating_scale, w.rating_offset)
+    rng = np.random.default_rng(seed)
+    for i in rng.choice(w.cands.n_cand, size=5, replace=False):
+        el = w.cands.elements(int(i))
+        x = w.inj if w.inj_shared else w.inj[int(i)]
+        sc = O.score_candidate(g.n_bus, g.f, g.t, g.b, g.slack, el, x, w.mon, w.out, r)
+        got = O.worst_cases(sc, w.mon, w.out, 12)
+        p1, isl = O.n1_flows_bruteforce(g.n_bus, g.f, g.t, g.b, g.slack, el, x, w.out)
+        v = sc["best_variant"]
+        p0 = sc["flows"]["p0"][v]
+        ent = [(abs(p0[l]) / r[li], li, int(l), -1) for li, l in enumerate(w.mon)]
+        for c, o in enumerate(w.out):
+            if isl[c]:
+                continue
+            ent += [(abs(p1[v, c, l]) / r[li], (c + 1) * len(w.mon) + li, int(l), int(o))
+                    for li, l in enumerate(w.mon)]
+        ent.sort(key=lambda e: (-e[0], e[1]))
+        np.testing.assert_allclose([e[0] for e in got], [e[0] for e in ent[:12]], atol=1e-10)
+        # ties within rounding may swap places: compare the cases as sets up to the last load
+        last = ent[11][0]
+        strict = [(e[2], e[3]) for e in ent[:12] if e[0] > last + 1e-9]
+        assert strict == [(b, o) for v_, b, o in got[:len(strict)]]
+
+
 def _random_tree(n, seed):
     rng = np.random.default_rng(seed)
     par = np.array([-1] + [int(rng.integers(0, i)) for i in range(1, n)])
