@@ -177,6 +177,8 @@ void batch_layout(dcflow_batch *b, const dcflow_plan *p, const BatchDims &d, Are
   b->d_sig = a.take<int32_t>(ne * kMaxSig);
   b->d_U = a.take<double>(ne * p->ld_er);
   b->d_W = a.take<double>(ne * p->ld_o);
+  b->d_ur32 = a.take<float>(ne * p->mon_pad);
+  b->d_w32 = a.take<float>(ne * p->ld_o);
   b->d_kinv = a.take<double>(nc * 64);
   b->d_invden = a.take<double>(nc * p->ld_o);
   b->d_isl = a.take<uint32_t>(nc * (p->ld_o / 32));

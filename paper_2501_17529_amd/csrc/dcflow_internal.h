@@ -81,6 +81,8 @@ struct dcflow_batch {
   int32_t *d_sig;   // [n_elem][kMaxSig] signed (branch + 1)
   double *d_U;      // [n_elem][ld_er]
   double *d_W;      // [n_elem][ld_o]
+  float *d_ur32;    // [n_elem][mon_pad] FP32 U / r (monitored rows) for the FP32 scan
+  float *d_w32;     // [n_elem][ld_o] FP32 W
   double *d_kinv;   // [n_cand][64]
   double *d_invden; // [n_cand][ld_o]
   uint32_t *d_isl;  // [n_cand][ld_o / 32] islanding contingency bits

@@ -264,6 +264,25 @@ k_factors(const int32_t *__restrict__ order, const int32_t *__restrict__ off,
 
 }  // namespace
 
+// Operands of the FP32 scan's tile build, rounded once per evaluation instead
+// of once per tile: U / r on the padded monitored rows and W, in FP32 (the same
+// FP64 products the tile build would round).
+__global__ void __launch_bounds__(256)
+k_frags(const double *__restrict__ U, int ld_er, const double *__restrict__ inv_r, int mon_pad,
+        const double *__restrict__ W, int ld_o, size_t n_elem, float *__restrict__ ur32,
+        float *__restrict__ w32) {
+  const size_t nu = n_elem * mon_pad, nw = n_elem * ld_o;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nu + nw;
+       i += (size_t)gridDim.x * blockDim.x) {
+    if (i < nu) {
+      const size_t e = i / mon_pad, r = i - e * mon_pad;
+      ur32[i] = (float)(U[e * ld_er + r] * inv_r[r]);
+    } else {
+      w32[i - nu] = (float)W[i - nu];
+    }
+  }
+}
+
 hipError_t launch_factors(dcflow_batch *bt, hipStream_t s) {
   dcflow_plan *p = bt->plan;
   if (bt->n_cand == 0) return hipSuccess;
@@ -273,6 +292,14 @@ hipError_t launch_factors(dcflow_batch *bt, hipStream_t s) {
                      p->d_out, p->d_out_pos, p->n_out, p->d_pos_of_br, bt->d_nsig, bt->d_sig,
                      bt->d_U, bt->d_W, bt->d_kinv, bt->d_invden, bt->d_isl, bt->d_status);
   DCF_CHECK_LAUNCH();
+  const size_t n_elem = bt->n_elem, tot = n_elem * (p->mon_pad + p->ld_o);
+  if (tot) {
+    const size_t nb = std::min<size_t>((tot + 255) / 256, 8192);
+    k_frags<<<dim3((unsigned)nb), dim3(256), 0, s>>>(bt->d_U, p->ld_er, p->d_inv_r, p->mon_pad,
+                                                     bt->d_W, p->ld_o, n_elem, bt->d_ur32,
+                                                     bt->d_w32);
+    DCF_CHECK_LAUNCH();
+  }
   return hipSuccess;
 }
 

@@ -96,6 +96,8 @@ struct ScanArgs {
   const double *lsd;      // [mon_pad][ld_o]
   const float *lsd32;     // fragment-major FP32 copy
   const double *inv_r;    // [mon_pad]
+  const float *ur32;      // [n_elem][mon_pad] FP32 U / r
+  const float *w32;       // [n_elem][ld_o] FP32 W
   int n_mon, mon_pad;
   const int32_t *out_pos;
   int n_out;
@@ -135,7 +137,7 @@ constexpr int kPersistPerCu = 4;
 template <typename F>
 __device__ __forceinline__ void for_each_item(const ScanArgs &A, int slot, F body) {
   const int n_items = A.n_cand * A.nbands;
-  auto run = [&](int q) {
+  auto run = [&](int q) __attribute__((always_inline)) {
     const int band = q / A.n_cand;
     body(A.order[q - band * A.n_cand], band);
   };
@@ -180,61 +182,81 @@ __device__ __forceinline__ int fs_pos(double *, int rr) {
 }
 
 // A (U / r) and B (W) fragments of k-step h: lane group g supplies element
-// 4 h + g.  Every lane loads from a valid element (k >= 1) and zeroes the
-// fragment past k, so the loads are unconditional and issue together.
-template <typename T, int NB>
-__device__ __forceinline__ void update_frags(T (&af)[4], T (&bfr)[NB], const ScanArgs &A, int e0,
-                                             int k, int h, int rowbase, int colbase, int g, int li) {
+// 4 h + g.  The loads are unconditional (issued together, never waited on in a
+// branch): every lane reads a valid element of the batch (clamped to the
+// candidate's last one, and to the first element of the batch when the
+// candidate has none), and frag_mask zeroes the fragments past k only where
+// the MFMA consumes them.  The FP32 path reads U / r and W rounded to FP32 once
+// per evaluation (the same values the FP64 products would round to).
+template <int NB>
+__device__ __forceinline__ void update_frags(double (&af)[4], double (&bfr)[NB], const ScanArgs &A,
+                                             int e0, int k, int h, int rowbase, int colbase, int g,
+                                             int li) {
   const int e = h * 4 + g;
-  const int es = e0 + (e < k ? e : k - 1);
+  const int es = max(e0 + (e < k ? e : k - 1), 0);
   const double *u = A.U + (size_t)es * A.ld_er;
   const double *w = A.W + (size_t)es * A.ld_o;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     const int row = rowbase + a * 16 + li;
-    const double v = u[row] * A.inv_r[row];
-    af[a] = e < k ? (T)v : (T)0;
+    af[a] = u[row] * A.inv_r[row];
   }
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const double v = w[colbase + b * 16 + li];
-    bfr[b] = e < k ? (T)v : (T)0;
-  }
+  for (int b = 0; b < NB; ++b) bfr[b] = w[colbase + b * 16 + li];
+}
+template <int NB>
+__device__ __forceinline__ void update_frags(float (&af)[4], float (&bfr)[NB], const ScanArgs &A,
+                                             int e0, int k, int h, int rowbase, int colbase, int g,
+                                             int li) {
+  const int e = h * 4 + g;
+  const int es = max(e0 + (e < k ? e : k - 1), 0);
+  const float *u = A.ur32 + (size_t)es * A.mon_pad;
+  const float *w = A.w32 + (size_t)es * A.ld_o;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) af[a] = u[rowbase + a * 16 + li];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) bfr[b] = w[colbase + b * 16 + li];
+}
+template <typename T, int NB>
+__device__ __forceinline__ void frag_mask(T (&af)[4], T (&bfr)[NB], int k, int h, int g) {
+  const bool on = h * 4 + g < k;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) af[a] = on ? af[a] : (T)0;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) bfr[b] = on ? bfr[b] : (T)0;
 }
 
-// L~ for the 64 x 64 tile at (rowbase, colbase), FP32 matrix cores.  The 16
-// seed blocks are loaded first, then the one or two MFMA k-steps run.
-__device__ __forceinline__ void build_tile(float (&L)[4][4][4], const ScanArgs &A, int e0, int k,
-                                           int rowbase, int colbase, int g, int li, int lane) {
+// A tile of L~ in MFMA accumulator form: FP32 64 x 64 (16 blocks of f4), FP64
+// 64 x 32 (8 blocks of d4).  L[a][b][r] is row 16 a + MfmaRow(g, r), column
+// 16 b + li of the tile.
+template <typename T>
+struct TileOf;
+template <>
+struct TileOf<float> {
+  typedef f4 blk;
+  static constexpr int NB = 4;
+};
+template <>
+struct TileOf<double> {
+  typedef d4 blk;
+  static constexpr int NB = 2;
+};
+
+// The seed blocks of a tile, loaded into the MFMA accumulators.
+__device__ __forceinline__ void tile_load_seed(f4 (&c)[4][4], const ScanArgs &A, int rowbase,
+                                               int colbase, int g, int li, int lane) {
   const f4 *seed = reinterpret_cast<const f4 *>(A.lsd32) +
                    ((size_t)(rowbase / 16) * (A.ld_o / 16) + colbase / 16) * kWave + lane;
   const size_t rstride = (size_t)(A.ld_o / 16) * kWave;
-  f4 c[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) c[a][b] = seed[a * rstride + b * kWave];
-  for (int h = 0; h * 4 < k; ++h) {  // wave-uniform: one step for k <= 4, two for k <= 8
-    float af[4], bfr[4];
-    update_frags(af, bfr, A, e0, k, h, rowbase, colbase, g, li);
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        c[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[a], bfr[b], c[a][b], 0, 0, 0);
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) L[a][b][r] = c[a][b][r];
+  (void)g;
+  (void)li;
 }
-
-// L~ for the 64 x 32 tile at (rowbase, colbase), FP64 matrix cores.
-__device__ __forceinline__ void build_tile(double (&L)[4][2][4], const ScanArgs &A, int e0, int k,
-                                           int rowbase, int colbase, int g, int li, int lane) {
-  d4 c[4][2];
+__device__ __forceinline__ void tile_load_seed(d4 (&c)[4][2], const ScanArgs &A, int rowbase,
+                                               int colbase, int g, int li, int lane) {
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -243,22 +265,44 @@ __device__ __forceinline__ void build_tile(double (&L)[4][2][4], const ScanArgs 
 #pragma unroll
       for (int r = 0; r < 4; ++r) c[a][b][r] = src[(size_t)MfmaRow<double>::row(g, r) * A.ld_o];
     }
-  for (int h = 0; h * 4 < k; ++h) {
-    double af[4], bfr[2];
-    update_frags(af, bfr, A, e0, k, h, rowbase, colbase, g, li);
+  (void)lane;
+}
+// One k step of L = seed + (U / r) W on the matrix cores.
+__device__ __forceinline__ void tile_mfma_step(f4 (&c)[4][4], const float (&fa)[4],
+                                               const float (&fb)[4]) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
-        c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bfr[b], c[a][b], 0, 0, 0);
-  }
+    for (int b = 0; b < 4; ++b)
+      c[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[b], c[a][b], 0, 0, 0);
+}
+__device__ __forceinline__ void tile_mfma_step(d4 (&c)[4][2], const double (&fa)[4],
+                                               const double (&fb)[2]) {
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
+      c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], c[a][b], 0, 0, 0);
+}
+// L~ for the tile at (rowbase, colbase): the seed blocks, then per k step (one
+// for k <= 4, two for k <= 8; wave-uniform) its fragments and MFMAs.
+template <typename T, int NB>
+__device__ __forceinline__ void build_tile(T (&L)[4][NB][4], const ScanArgs &A, int e0, int k,
+                                           int rowbase, int colbase, int g, int li, int lane) {
+  typename TileOf<T>::blk c[4][NB];
+  T fa[4], fb[NB];
+  tile_load_seed(c, A, rowbase, colbase, g, li, lane);
+  for (int h = 0; h * 4 < k; ++h) {  // wave-uniform
+    update_frags(fa, fb, A, e0, k, h, rowbase, colbase, g, li);
+    frag_mask(fa, fb, k, h, g);
+    tile_mfma_step(c, fa, fb);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) L[a][b][r] = c[a][b][r];
-  (void)lane;
 }
 
 // F~ of monitored row `row` for one variant (the same expression in every pass)
@@ -396,7 +440,7 @@ __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int b
 
 template <typename T, int VC, int MINW>
 __global__ void __launch_bounds__(256, MINW) k_scan_max(ScanArgs A) {
-  for_each_item(A, blockIdx.y, [&](int cand, int band) { scan_max_item<T, VC>(A, cand, band); });
+  for_each_item(A, blockIdx.y, [&](int cand, int band) __attribute__((always_inline)) { scan_max_item<T, VC>(A, cand, band); });
 }
 
 // ---------------------------------------------------------------- pass 2
@@ -613,7 +657,7 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
 
 template <typename T, int MINW>
 __global__ void __launch_bounds__(256, MINW) k_scan_win(ScanArgs A) {
-  for_each_item(A, kQueueWin, [&](int cand, int band) { scan_win_item<T>(A, cand, band); });
+  for_each_item(A, kQueueWin, [&](int cand, int band) __attribute__((always_inline)) { scan_win_item<T>(A, cand, band); });
 }
 
 // One thread per candidate: combines the band partials into the score record.
@@ -865,7 +909,7 @@ __device__ __forceinline__ void scan_worst_item(const ScanArgs &A, int cand, int
 
 template <typename T, int KM, int MINW>
 __global__ void __launch_bounds__(256, MINW) k_scan_worst(ScanArgs A) {
-  for_each_item(A, kQueueWin, [&](int cand, int band) { scan_worst_item<T, KM>(A, cand, band); });
+  for_each_item(A, kQueueWin, [&](int cand, int band) __attribute__((always_inline)) { scan_worst_item<T, KM>(A, cand, band); });
 }
 
 // One wave per candidate: merges the bands' sorted lists (lane b walks bands b,
@@ -953,7 +997,7 @@ inline int choose_rchunk(int req, size_t fixed, size_t per_row, int mon_pad, siz
 // exceeds the band, and the band is a whole number of chunks.
 constexpr size_t kSeedL2 = 2u << 20, kBandSeed = 4u << 20;
 inline void choose_rows(const dcflow_batch *bt, size_t fixed, size_t per_row, int mon_pad,
-                        int ld_o, size_t elem, ScanArgs &a) {
+                        int ld_o, size_t elem, size_t lds_target, ScanArgs &a) {
   int band = bt->tune.scan_band;
   if (band <= 0) {
     const size_t seed = (size_t)mon_pad * ld_o * elem;
@@ -961,7 +1005,7 @@ inline void choose_rows(const dcflow_batch *bt, size_t fixed, size_t per_row, in
   }
   if (band < 64) band = 64;
   if (band > mon_pad) band = mon_pad;
-  int rc = choose_rchunk(bt->tune.scan_rchunk, fixed, per_row, mon_pad, kLdsOccupancy);
+  int rc = choose_rchunk(bt->tune.scan_rchunk, fixed, per_row, mon_pad, lds_target);
   if (rc > band) rc = band;
   a.rchunk = rc;
   a.band_rows = band < mon_pad ? band / rc * rc : mon_pad;
@@ -979,7 +1023,7 @@ template <typename T, int VC, int MINW>
 hipError_t launch_max(const ScanArgs &a0, const dcflow_batch *bt, int nvar, hipStream_t s) {
   ScanArgs a = a0;
   const size_t fixed = sizeof(T) * (size_t)VC * a.ld_o;
-  choose_rows(bt, fixed, sizeof(T) * VC, a.mon_pad, a.ld_o, sizeof(T), a);
+  choose_rows(bt, fixed, sizeof(T) * VC, a.mon_pad, a.ld_o, sizeof(T), kLdsOccupancy, a);
   const size_t lds = fixed + sizeof(T) * (size_t)VC * a.rchunk;
   if (lds > kLdsBudget) return hipErrorInvalidValue;
   const int ny = (nvar + VC - 1) / VC;
@@ -1030,6 +1074,8 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   a.lsd = p->d_lsd;
   a.lsd32 = p->d_lsd32;
   a.inv_r = p->d_inv_r;
+  a.ur32 = bt->d_ur32;
+  a.w32 = bt->d_w32;
   a.n_mon = p->n_mon;
   a.mon_pad = p->mon_pad;
   a.out_pos = p->d_out_pos;
@@ -1076,7 +1122,7 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
     if (e != hipSuccess) return e;
   }
   const size_t fixed = sizeof(T) * 2 * (size_t)p->ld_o;
-  choose_rows(bt, fixed, sizeof(T), p->mon_pad, p->ld_o, sizeof(T), a);
+  choose_rows(bt, fixed, sizeof(T), p->mon_pad, p->ld_o, sizeof(T), kLdsOccupancy, a);
   if (a.nbands > bt->max_bands) return hipErrorInvalidValue;
   const size_t lds = fixed + sizeof(T) * (size_t)a.rchunk;
   if (lds > kLdsBudget) return hipErrorInvalidValue;
@@ -1120,6 +1166,8 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   a.lsd = p->d_lsd;
   a.lsd32 = p->d_lsd32;
   a.inv_r = p->d_inv_r;
+  a.ur32 = bt->d_ur32;
+  a.w32 = bt->d_w32;
   a.n_mon = p->n_mon;
   a.mon_pad = p->mon_pad;
   a.out_pos = p->d_out_pos;
