@@ -75,7 +75,8 @@ def _source_hash():
     return h.hexdigest()[:16]
 
 
-def run_path(D, torch, plan, w, prec, steps, warmup, tune=True, graph=True, persistent=False):
+def run_path(D, torch, plan, w, prec, steps, warmup, tune=True, graph=True, persistent=False,
+             tune_cache=None):
     nv = w.n_var
     bt = D.Batch(plan, w.cands, nv)
     if persistent:
@@ -104,7 +105,9 @@ def run_path(D, torch, plan, w, prec, steps, warmup, tune=True, graph=True, pers
         torch.cuda.synchronize()
         if tune:
             from paper_2501_17529_amd import autotune
-            cfg, times = autotune.tune_scan(bt, flows, nv, prec, use_cache=False)
+            if tune_cache:
+                os.environ["DCFLOW_AUTOTUNE_CACHE"] = tune_cache
+            cfg, times = autotune.tune_scan(bt, flows, nv, prec, use_cache=bool(tune_cache))
             res["tuning"] = cfg
             step()
         # eager steps, phase by phase
@@ -163,6 +166,9 @@ def main():
     ap.add_argument("--prec", choices=["all", "fp32", "fp64", "bf16x6", "bf16"], default="all")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--tune-cache", default="", metavar="PATH",
+                    help="autotuner cache file: shapes found there are reused without a sweep "
+                         "(so that a profiled run times the same launch shapes as the bench run)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run three plain device copies of MIB MiB (HBM counter scale)")
     a = ap.parse_args()
@@ -206,6 +212,7 @@ def main():
     res = {}
     for prec in precs:
         res[prec] = run_path(D, torch, plan, w, prec, a.steps, a.warmup, tune=not a.no_autotune,
+                             tune_cache=a.tune_cache or None,
                              graph=not a.no_graph, persistent=a.workload == "uneven")
     main_prec = precs[0]
     r = res[main_prec]

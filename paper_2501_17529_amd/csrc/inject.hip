@@ -25,6 +25,8 @@ namespace {
 // variants per block, K = n_bus split over the 4 waves, 4 independent
 // accumulators per wave (one per K sub-step) so the MFMA chain does not
 // serialise.  Row results are folded into per-element sums h[j][v] in LDS.
+constexpr int kSenseUnroll = 4;  // K chunks per wave whose loads are in flight together
+
 __global__ void __launch_bounds__(256)
 k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
         const int32_t *__restrict__ nsig, const int32_t *__restrict__ sig,
@@ -60,26 +62,42 @@ k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
   for (int v0 = 0; v0 < nvar; v0 += 16) {
     if (tid < kMaxRank * 16) hacc[tid / 16][tid % 16] = 0.0;
     for (int r0 = 0; r0 < R; r0 += 16) {
+      // Every lane reads valid memory (row 0 / the candidate's first variant
+      // stand in for missing rows and variants, the last entry for k past n),
+      // and the zeroing happens at the MFMA: the loads of kSenseUnroll chunks are
+      // issued together instead of one wait per guarded load.
       const int row = r0 + li;
-      const double *hrowp = row < R ? Hb + (size_t)rbr[row] * ld_h : nullptr;
-      const double sg = row < R ? rsg[row] : 0.0;
+      const double *hp = Hb + (size_t)(row < R ? rbr[row] : 0) * ld_h;  // rows padded to
+      const double sg = row < R ? rsg[row] : 0.0;                        // ld_h >= nch * 16
       const int v = v0 + li;
-      const double *xr =
-          v < nvar ? X + (size_t)(shared ? v : (size_t)cand * nvar + v) * n : nullptr;
+      const bool vok = v < nvar;
+      const double *xp =
+          X + (size_t)(shared ? (vok ? v : 0) : (size_t)cand * nvar + (vok ? v : 0)) * n;
       d4 acc[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-      for (int ch = wv; ch < nch; ch += 4) {
-        const int nb = ch * 16 + 4 * g;
-        double a[4], bq[4];
+      for (int ch0 = wv; ch0 < nch; ch0 += 4 * kSenseUnroll) {
+        double a[kSenseUnroll][4], bq[kSenseUnroll][4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          a[q] = hrowp ? sg * hrowp[nb + q] : 0.0;  // rows padded to ld_h >= nch * 16
-          bq[q] = (xr && nb + q < n) ? xr[nb + q] : 0.0;
+        for (int u = 0; u < kSenseUnroll; ++u) {
+          const int nb = min(ch0 + 4 * u, nch - 1) * 16 + 4 * g;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            a[u][q] = hp[nb + q];
+            bq[u][q] = xp[min(nb + q, n - 1)];
+          }
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], bq[q], acc[q], 0, 0, 0);
+        for (int u = 0; u < kSenseUnroll; ++u) {
+          const int ch = ch0 + 4 * u;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int kk = ch * 16 + 4 * g + q;
+            const double av = ch < nch ? sg * a[u][q] : 0.0;
+            const double bv = ch < nch && vok && kk < n ? bq[u][q] : 0.0;
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+          }
+        }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r)
