@@ -25,7 +25,9 @@ namespace {
 // variants per block, K = n_bus split over the 4 waves, 4 independent
 // accumulators per wave (one per K sub-step) so the MFMA chain does not
 // serialise.  Row results are folded into per-element sums h[j][v] in LDS.
-constexpr int kSenseUnroll = 4;  // K chunks per wave whose loads are in flight together
+constexpr int kSenseUnroll = 4;
+// four doubles at an 8-byte-aligned address (a row of X starts anywhere)
+typedef double d4u __attribute__((ext_vector_type(4), aligned(8)));  // K chunks per wave whose loads are in flight together
 
 __global__ void __launch_bounds__(256)
 k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
@@ -82,9 +84,20 @@ k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
         for (int u = 0; u < kSenseUnroll; ++u) {
           const int nb = min(ch0 + 4 * u, nch - 1) * 16 + 4 * g;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            a[u][q] = hp[nb + q];
-            bq[u][q] = xp[min(nb + q, n - 1)];
+          for (int q = 0; q < 4; ++q) a[u][q] = hp[nb + q];
+          if (n >= 4) {
+            // four consecutive entries in one 32-byte load, its start clamped so that
+            // it stays inside the row; past the row's end the shift drops them
+            const int base = min(nb, n - 4), sh = nb - base;
+            const d4u xv = *reinterpret_cast<const d4u *>(xp + base);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int i = q + sh;
+              bq[u][q] = i == 0 ? xv[0] : i == 1 ? xv[1] : i == 2 ? xv[2] : xv[3];
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bq[u][q] = xp[min(nb + q, n - 1)];
           }
         }
 #pragma unroll
