@@ -123,7 +123,27 @@ def run_path(D, torch, plan, w, prec, steps, warmup, tune=True, graph=True, pers
         sc_eager = D.Batch.scores_to_numpy(out, bt.n_cand)
         res["wall"] = res["wall_eager"]
         if graph:
-            # the whole step captured once, replayed with one launch per step
+            # the whole step captured once, replayed with one launch per step; for
+            # per-candidate injections the step's candidate chunks (GEMM of one
+            # chunk beside the scan of the previous) are chosen by timing replays
+            base_cfg = bt.get_tuning()
+            chunk_ms = {}
+            for ch in ((1, 2, 4, 8) if tune and not w.inj_shared else (base_cfg["step_chunks"],)):
+                bt.set_tuning(**dict(base_cfg, step_chunks=ch))
+                bt.capture(x, nv, w.inj_shared, prec, flows, out, stream)
+                for _ in range(2):
+                    bt.replay(stream)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(5):
+                    bt.replay(stream)
+                e1.record(stream)
+                e1.synchronize()
+                chunk_ms[ch] = e0.elapsed_time(e1) / 5
+            best = min(chunk_ms, key=chunk_ms.get)
+            res["step_chunks"] = best
+            res["step_chunk_ms"] = chunk_ms
+            bt.set_tuning(**dict(base_cfg, step_chunks=best))
             bt.capture(x, nv, w.inj_shared, prec, flows, out, stream)
             for _ in range(warmup):
                 bt.replay(stream)
@@ -250,6 +270,8 @@ def main():
         "step_mode": "hip graph replay" if "wall_graph" in r else "eager",
         "eager_ms_per_step": r["wall_eager"] / a.steps * 1e3,
         "scan_tuning": {p: v.get("tuning") for p, v in res.items()},
+        "step_chunks": {p: v.get("step_chunks") for p, v in res.items()},
+        "step_chunk_ms": {p: v.get("step_chunk_ms") for p, v in res.items()},
     }
     for p, v in res.items():
         if p == main_prec:

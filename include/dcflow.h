@@ -290,17 +290,33 @@ typedef struct {
   int32_t scan_band;   /* monitored rows per work item (a multiple of 64, rounded to the
                           row chunk); 0 = automatic: all rows when the scan's seed block
                           is small, else bands whose seed slice stays in L2          */
+  int32_t step_chunks; /* dcflow_step and captured steps: 0 or 1 = eval_injections then
+                          n1_score over the batch; 2..16 = that many candidate chunks,
+                          the injections of chunk i + 1 running beside the scan of
+                          chunk i on a second stream of the batch (per-candidate
+                          injections only; the results are the same)               */
 } dcflow_tuning;
 
 /* Sets / reads the batch's launch shapes (defaults: all zero).  E_ARG for a
- * negative value or a row chunk or band that is not a multiple of 64.  The scan
- * runs over work items (candidate, band of monitored rows), band-major, with the
- * candidates of a band in descending rank. */
+ * negative value, a row chunk or band that is not a multiple of 64, or more
+ * than 16 step chunks.  The scan runs over work items (candidate, band of
+ * monitored rows), band-major, with the candidates of a band in descending rank
+ * (candidate order within a step chunk).  Asking for step chunks creates the
+ * batch's second stream (default priority) and its events here. */
 int dcflow_batch_set_tuning(dcflow_batch *batch, const dcflow_tuning *tuning);
 int dcflow_batch_get_tuning(const dcflow_batch *batch, dcflow_tuning *tuning);
 
-/* Captures one step with exactly these arguments (see the three calls above)
- * from `stream` into a graph held by the batch, replacing any earlier one.
+/* One whole step on `stream`: dcflow_eval_topologies, dcflow_eval_injections and
+ * dcflow_n1_score with these arguments (same results, same errors), split into
+ * the tuning's step_chunks candidate chunks so that the injection GEMM of one
+ * chunk runs beside the N-1 scan of the previous one.  Returns when enqueued;
+ * the stream waits for the second stream's work before anything enqueued after. */
+int dcflow_step(dcflow_batch *batch, const double *dev_inj, int32_t n_var, int32_t inj_shared,
+                dcflow_prec prec, void *dev_flows, size_t flow_bytes, dcflow_score *dev_out,
+                hipStream_t stream);
+
+/* Captures one step (dcflow_step) with exactly these arguments from `stream`
+ * into a graph held by the batch, replacing any earlier one.
  * Nothing runs during the capture.  The stream must not be the null stream.
  * The buffers named here must stay valid while the graph is used; tuning
  * changes need a new capture.  Errors as for the three calls, E_HIP if the

@@ -495,7 +495,9 @@ int dcflow_batch_create(dcflow_plan *p, const dcflow_cands *c, int32_t n_var_max
   b->factored = 0;
   b->flows_prec = -1;
   b->flows_nvar = 0;
-  b->tune = dcflow_tuning{0, 0, 0, 0};
+  b->tune = dcflow_tuning{0, 0, 0, 0, 0};
+  b->aux = nullptr;
+  for (int i = 0; i <= kMaxStepChunks; ++i) b->step_ev[i] = nullptr;
   b->max_bands = p->mon_pad / 64;
   b->graph = nullptr;
   b->graph_exec = nullptr;
@@ -552,16 +554,86 @@ void drop_graph(dcflow_batch *b) {
 void dcflow_batch_destroy(dcflow_batch *b) {
   if (!b) return;
   drop_graph(b);
+  for (int i = 0; i <= kMaxStepChunks; ++i)
+    if (b->step_ev[i]) (void)hipEventDestroy(b->step_ev[i]);
+  if (b->aux) (void)hipStreamDestroy(b->aux);
   delete b;
 }
+
+namespace {
+// the second stream and the events of the chunked step, made once per batch
+// (outside any capture when the tuning asks for chunks)
+hipError_t ensure_step_streams(dcflow_batch *b) {
+  hipError_t e = hipSuccess;
+  if (!b->aux) e = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking);
+  for (int i = 0; e == hipSuccess && i <= kMaxStepChunks; ++i)
+    if (!b->step_ev[i]) e = hipEventCreateWithFlags(&b->step_ev[i], hipEventDisableTiming);
+  return e;
+}
+
+// One whole step: eval_topologies, then eval_injections and n1_score over the
+// batch, or over step_chunks candidate chunks with the injections of chunk i + 1
+// (stream s) running beside the scan of chunk i (the batch's second stream).
+int run_step(dcflow_batch *b, const double *inj, int nvar, int shared, int prec, void *flows,
+             dcflow_score *out, hipStream_t s) {
+  hipError_t e = launch_factors(b, s);
+  if (e != hipSuccess) return hip_fail(e, "dcflow_step");
+  b->factored = 1;
+  int nch = b->tune.step_chunks;
+  if (shared || nch > b->n_cand) nch = shared ? 1 : b->n_cand;
+  if (nch <= 1) {
+    e = launch_injections(b, inj, nvar, shared, prec, flows, 0, b->n_cand, s);
+    if (e == hipSuccess) e = launch_score(b, flows, nvar, prec, out, 0, b->n_cand, s);
+  } else {
+    e = ensure_step_streams(b);
+    for (int i = 0; e == hipSuccess && i < nch; ++i) {
+      const int c0 = (int)((int64_t)b->n_cand * i / nch), c1 = (int)((int64_t)b->n_cand * (i + 1) / nch);
+      e = launch_injections(b, inj, nvar, 0, prec, flows, c0, c1, s);
+      if (e == hipSuccess) e = hipEventRecord(b->step_ev[i], s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->aux, b->step_ev[i], 0);
+      if (e == hipSuccess) e = launch_score(b, flows, nvar, prec, out, c0, c1, b->aux);
+    }
+    if (e == hipSuccess) e = hipEventRecord(b->step_ev[nch], b->aux);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, b->step_ev[nch], 0);
+  }
+  if (e != hipSuccess) return hip_fail(e, "dcflow_step");
+  b->flows_prec = prec;
+  b->flows_nvar = nvar;
+  return DCFLOW_OK;
+}
+
+int check_step(dcflow_batch *b, const double *dev_inj, int32_t n_var, dcflow_prec prec,
+               void *dev_flows, size_t flow_bytes, dcflow_score *dev_out) {
+  if (!b || !dev_inj || !dev_flows || !dev_out) return DCFLOW_E_ARG;
+  if (n_var < 1 || n_var > b->vmax) return DCFLOW_E_SHAPE;
+  if (!prec_valid(prec)) return DCFLOW_E_ARG;
+  size_t need = 0;
+  dcflow_flow_bytes(b, n_var, prec, &need, nullptr);
+  if (flow_bytes < need) return DCFLOW_E_WORKSPACE;
+  return DCFLOW_OK;
+}
+}  // namespace
 
 int dcflow_batch_set_tuning(dcflow_batch *b, const dcflow_tuning *t) {
   if (!b || !t) return DCFLOW_E_ARG;
   if (t->scan_vc < 0 || t->scan_rchunk < 0 || t->scan_rchunk % 64 || t->persistent < 0 ||
-      t->scan_band < 0 || t->scan_band % 64)
+      t->scan_band < 0 || t->scan_band % 64 || t->step_chunks < 0 ||
+      t->step_chunks > kMaxStepChunks)
     return DCFLOW_E_ARG;
+  if (t->step_chunks > 1) {
+    const hipError_t e = ensure_step_streams(b);
+    if (e != hipSuccess) return hip_fail(e, "dcflow_batch_set_tuning");
+  }
   b->tune = *t;
   return DCFLOW_OK;
+}
+
+int dcflow_step(dcflow_batch *b, const double *dev_inj, int32_t n_var, int32_t inj_shared,
+                dcflow_prec prec, void *dev_flows, size_t flow_bytes, dcflow_score *dev_out,
+                hipStream_t s) {
+  const int rc = check_step(b, dev_inj, n_var, prec, dev_flows, flow_bytes, dev_out);
+  if (rc != DCFLOW_OK) return rc;
+  return run_step(b, dev_inj, n_var, inj_shared ? 1 : 0, prec, dev_flows, dev_out, s);
 }
 
 int dcflow_batch_get_tuning(const dcflow_batch *b, dcflow_tuning *t) {
@@ -574,13 +646,12 @@ int dcflow_graph_capture(dcflow_batch *b, const double *dev_inj, int32_t n_var,
                          int32_t inj_shared, dcflow_prec prec, void *dev_flows, size_t flow_bytes,
                          dcflow_score *dev_out, hipStream_t s) {
   if (!b || !s) return DCFLOW_E_ARG;
+  int rc = check_step(b, dev_inj, n_var, prec, dev_flows, flow_bytes, dev_out);
+  if (rc != DCFLOW_OK) return rc;
   drop_graph(b);
   hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return hip_fail(e, "dcflow_graph_capture");
-  int rc = dcflow_eval_topologies(b, s);
-  if (rc == DCFLOW_OK)
-    rc = dcflow_eval_injections(b, dev_inj, n_var, inj_shared, prec, dev_flows, flow_bytes, s);
-  if (rc == DCFLOW_OK) rc = dcflow_n1_score(b, dev_flows, n_var, prec, dev_out, s);
+  rc = run_step(b, dev_inj, n_var, inj_shared ? 1 : 0, prec, dev_flows, dev_out, s);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(s, &g);
   if (rc != DCFLOW_OK) {
@@ -633,7 +704,8 @@ int dcflow_eval_injections(dcflow_batch *b, const double *dev_inj, int32_t n_var
   size_t need = 0;
   dcflow_flow_bytes(b, n_var, prec, &need, nullptr);
   if (flow_bytes < need) return DCFLOW_E_WORKSPACE;
-  hipError_t e = launch_injections(b, dev_inj, n_var, inj_shared ? 1 : 0, prec, dev_flows, s);
+  hipError_t e =
+      launch_injections(b, dev_inj, n_var, inj_shared ? 1 : 0, prec, dev_flows, 0, b->n_cand, s);
   if (e != hipSuccess) return hip_fail(e, "dcflow_eval_injections");
   b->flows_prec = prec;
   b->flows_nvar = n_var;
@@ -647,7 +719,7 @@ int dcflow_n1_score(dcflow_batch *b, const void *dev_flows, int32_t n_var, dcflo
   if (!prec_valid(prec)) return DCFLOW_E_ARG;
   if (!b->factored) return DCFLOW_E_ARG;
   if (b->flows_prec != prec || b->flows_nvar != n_var) return DCFLOW_E_ARG;
-  hipError_t e = launch_score(b, dev_flows, n_var, prec, dev_out, s);
+  hipError_t e = launch_score(b, dev_flows, n_var, prec, dev_out, 0, b->n_cand, s);
   if (e != hipSuccess) return hip_fail(e, "dcflow_n1_score");
   return DCFLOW_OK;
 }

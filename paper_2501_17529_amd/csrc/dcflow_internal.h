@@ -14,6 +14,7 @@ namespace dcflow {
 constexpr int kMaxRank = DCFLOW_MAX_RANK;
 constexpr int kMaxSig = DCFLOW_MAX_SPLIT_DEG;  // sensing branches per element
 constexpr int kWave = 64;
+constexpr int kMaxStepChunks = 16;  // most candidate chunks of the overlapped step
 constexpr double kIslandTol = 1e-9;   // |LODF denominator| below this: islanding
 constexpr double kSingularTol = 1e-10; // relative pivot threshold of the k x k solve
 
@@ -99,6 +100,8 @@ struct dcflow_batch {
   long long *d_part_k;
   int32_t *d_part_nf;
   dcflow_tuning tune;
+  hipStream_t aux;                 // second stream of the chunked step (default priority)
+  hipEvent_t step_ev[dcflow::kMaxStepChunks + 1];  // fork points and the join of the chunked step
   int n_cu;               // compute units of the device the batch was created on
   hipGraph_t graph;       // captured step (dcflow_graph_capture), or null
   hipGraphExec_t graph_exec;
@@ -124,16 +127,19 @@ hipError_t launch_build(dcflow_plan *p, hipStream_t s, const double *h_rating,
 // factors (a3)
 hipError_t launch_factors(dcflow_batch *b, hipStream_t s);
 // injections (a4)
+// candidates [c0, c1) (the shared-injection mode: the whole batch only)
 hipError_t launch_injections(dcflow_batch *b, const double *inj, int nvar, int shared,
-                             int prec, void *flows, hipStream_t s);
+                             int prec, void *flows, int c0, int c1, hipStream_t s);
 // score (a5)
 // worst-case lists (agg_i) of the winners; worst_bands = row bands of that pass
 int worst_bands(const dcflow_plan *p);
 hipError_t launch_worst(dcflow_batch *b, const void *flows, int nvar, int prec,
                         const dcflow_score *scores, int top_k, void *ws, dcflow_case *out,
                         hipStream_t s);
+// candidates [c0, c1); a part of the batch runs without the persistent queue and in
+// candidate order
 hipError_t launch_score(dcflow_batch *b, const void *flows, int nvar, int prec,
-                        dcflow_score *out, hipStream_t s);
+                        dcflow_score *out, int c0, int c1, hipStream_t s);
 
 // ------------------------------------------------------ device helpers
 // Row of a 16x16 MFMA accumulator block held by lane group g (= lane / 16) in

@@ -34,14 +34,14 @@ k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
         const int32_t *__restrict__ nsig, const int32_t *__restrict__ sig,
         const double *__restrict__ pnew, const double *__restrict__ kinv,
         const double *__restrict__ Hb, int ld_h, int n, const double *__restrict__ X, int nvar,
-        int shared, double *__restrict__ z, int vmax) {
+        int shared, double *__restrict__ z, int vmax, int cand0) {
   __shared__ int rbr[kMaxRank * kMaxSig];
   __shared__ double rsg[kMaxRank * kMaxSig];
   __shared__ int relem[kMaxRank * kMaxSig];
   __shared__ double red[4][16][17];
   __shared__ double hacc[kMaxRank][16];
   __shared__ int s_R;
-  const int cand = blockIdx.x;
+  const int cand = cand0 + blockIdx.x;
   const int e0 = off[cand];
   const int k = off[cand + 1] - e0;
   if (k == 0) return;
@@ -494,35 +494,35 @@ __global__ void k_bcast(const T *__restrict__ F0, T *__restrict__ F, int ld_f, i
 
 // The GEMM F = X He^T (+ U z) with T operands, or BF16 parts (np = 1 or 3) when T = float
 // and np > 0.
+// X, F and off are taken from column col0 (candidate col0 / nvar) on.
 template <typename T>
 hipError_t launch_gemm(const dcflow_plan *p, const T *He, int np, const double *X, int ncols,
                        int nvar, int shared, T *F, const dcflow_batch *bt, int correct,
-                       hipStream_t s) {
+                       const int32_t *off, size_t col0, hipStream_t s) {
   const int n_mt = p->ld_er / BM, n_nt = (ncols + BN - 1) / BN;
   dim3 grid(kXcd * ((n_nt + kXcd - 1) / kXcd) * n_mt);
   if constexpr (sizeof(T) == 4) {
     const size_t part = (size_t)p->ld_er * p->ld_h;
     if (np == 3 || np == 1) {
-      if ((size_t)ncols > bt->xs_cols) return hipErrorInvalidValue;
+      if (col0 + (size_t)ncols > bt->xs_cols) return hipErrorInvalidValue;
       const size_t xpart = bt->xs_cols * (size_t)bt->ldx;
+      __bf16 *xs = bt->d_xs + col0 * bt->ldx;
       const size_t nthr = (size_t)ncols * (bt->ldx / 8);
       const dim3 sg((unsigned)((nthr + 255) / 256));
       if (np == 3) {
-        k_split_x<3><<<sg, dim3(256), 0, s>>>(X, p->n_inj, p->d_pbase, ncols, bt->ldx, bt->d_xs,
-                                              xpart);
+        k_split_x<3><<<sg, dim3(256), 0, s>>>(X, p->n_inj, p->d_pbase, ncols, bt->ldx, xs, xpart);
         DCF_CHECK_LAUNCH();
-        k_gemm_bf<3><<<grid, dim3(256), 0, s>>>(p->d_heb, part, p->ld_h, bt->d_xs, xpart, bt->ldx,
-                                                p->n_inj, ncols, nvar, shared, F, p->ld_er,
-                                                bt->d_off, bt->d_U, p->ld_er, bt->d_z, bt->vmax,
-                                                correct, n_mt, n_nt, p->d_fber);
+        k_gemm_bf<3><<<grid, dim3(256), 0, s>>>(p->d_heb, part, p->ld_h, xs, xpart, bt->ldx,
+                                                p->n_inj, ncols, nvar, shared, F, p->ld_er, off,
+                                                bt->d_U, p->ld_er, bt->d_z, bt->vmax, correct,
+                                                n_mt, n_nt, p->d_fber);
       } else {
-        k_split_x<1><<<sg, dim3(256), 0, s>>>(X, p->n_inj, p->d_pbase, ncols, bt->ldx, bt->d_xs,
-                                              xpart);
+        k_split_x<1><<<sg, dim3(256), 0, s>>>(X, p->n_inj, p->d_pbase, ncols, bt->ldx, xs, xpart);
         DCF_CHECK_LAUNCH();
-        k_gemm_bf<1><<<grid, dim3(256), 0, s>>>(p->d_heb, part, p->ld_h, bt->d_xs, xpart, bt->ldx,
-                                                p->n_inj, ncols, nvar, shared, F, p->ld_er,
-                                                bt->d_off, bt->d_U, p->ld_er, bt->d_z, bt->vmax,
-                                                correct, n_mt, n_nt, p->d_fber);
+        k_gemm_bf<1><<<grid, dim3(256), 0, s>>>(p->d_heb, part, p->ld_h, xs, xpart, bt->ldx,
+                                                p->n_inj, ncols, nvar, shared, F, p->ld_er, off,
+                                                bt->d_U, p->ld_er, bt->d_z, bt->vmax, correct,
+                                                n_mt, n_nt, p->d_fber);
       }
       DCF_CHECK_LAUNCH();
       return hipSuccess;
@@ -531,27 +531,33 @@ hipError_t launch_gemm(const dcflow_plan *p, const T *He, int np, const double *
   // the GEMM takes x - p_base and the FP64 base flows are added back (the injections are
   // variants of the base case, so this keeps most cancellation out of the sums)
   k_gemm<T><<<grid, dim3(256), 0, s>>>(He, p->ld_h, X, p->n_inj, ncols, nvar, shared, F, p->ld_er,
-                                       bt->d_off, bt->d_U, p->ld_er, bt->d_z, bt->vmax, correct,
-                                       n_mt, n_nt, p->d_pbase, p->d_fber);
+                                       off, bt->d_U, p->ld_er, bt->d_z, bt->vmax, correct, n_mt,
+                                       n_nt, p->d_pbase, p->d_fber);
   DCF_CHECK_LAUNCH();
   return hipSuccess;
 }
 
+// Candidates [c0, c1); the shared-injection mode takes the whole batch only.
 template <typename T>
 hipError_t run_injections(dcflow_batch *bt, const T *He, int np, const double *inj, int nvar,
-                          int shared, T *flows, hipStream_t s) {
+                          int shared, T *flows, int c0, int c1, hipStream_t s) {
   dcflow_plan *p = bt->plan;
   const int ld_f = p->ld_er;
-  hipLaunchKernelGGL(k_sense, dim3(bt->n_cand), dim3(256), 0, s, bt->d_off, bt->d_kind, bt->d_nsig,
+  if (c1 <= c0) return hipSuccess;
+  if (shared && (c0 != 0 || c1 != bt->n_cand)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sense, dim3(c1 - c0), dim3(256), 0, s, bt->d_off, bt->d_kind, bt->d_nsig,
                      bt->d_sig, bt->d_pnew, bt->d_kinv, p->d_hb, p->ld_h, p->n_inj, inj, nvar, shared,
-                     bt->d_z, bt->vmax);
+                     bt->d_z, bt->vmax, c0);
   DCF_CHECK_LAUNCH();
   if (!shared) {
-    const hipError_t e = launch_gemm<T>(p, He, np, inj, bt->n_cand * nvar, nvar, 0, flows, bt, 1, s);
+    const size_t col0 = (size_t)c0 * nvar;
+    const hipError_t e =
+        launch_gemm<T>(p, He, np, inj + col0 * p->n_inj, (c1 - c0) * nvar, nvar, 0,
+                       flows + col0 * ld_f, bt, 1, bt->d_off + c0, col0, s);
     if (e != hipSuccess) return e;
   } else {
     T *f0 = reinterpret_cast<T *>(bt->d_f0);
-    const hipError_t e = launch_gemm<T>(p, He, np, inj, nvar, nvar, 1, f0, bt, 0, s);
+    const hipError_t e = launch_gemm<T>(p, He, np, inj, nvar, nvar, 1, f0, bt, 0, bt->d_off, 0, s);
     if (e != hipSuccess) return e;
     dim3 g2((ld_f + 255) / 256, nvar, bt->n_cand);
     k_bcast<T><<<g2, dim3(256), 0, s>>>(f0, flows, ld_f, nvar, bt->d_off, bt->d_U, p->ld_er,
@@ -564,14 +570,14 @@ hipError_t run_injections(dcflow_batch *bt, const T *He, int np, const double *i
 }  // namespace
 
 hipError_t launch_injections(dcflow_batch *bt, const double *inj, int nvar, int shared, int prec,
-                             void *flows, hipStream_t s) {
+                             void *flows, int c0, int c1, hipStream_t s) {
   if (bt->n_cand == 0) return hipSuccess;
   if (prec == DCFLOW_FP64)
     return run_injections<double>(bt, bt->plan->d_he64, 0, inj, nvar, shared,
-                                  static_cast<double *>(flows), s);
+                                  static_cast<double *>(flows), c0, c1, s);
   const int np = prec == DCFLOW_BF16X6 ? 3 : prec == DCFLOW_BF16 ? 1 : 0;
   return run_injections<float>(bt, bt->plan->d_he32, np, inj, nvar, shared,
-                               static_cast<float *>(flows), s);
+                               static_cast<float *>(flows), c0, c1, s);
 }
 
 }  // namespace dcflow

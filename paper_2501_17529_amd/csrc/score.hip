@@ -112,7 +112,8 @@ struct ScanArgs {
   // workgroups in flight share one band of the seed in L2; candidates in queue order
   // (descending rank) within a band
   int n_cand, nbands;
-  const int32_t *order;  // [n_cand]
+  const int32_t *order;  // [n_cand] queue order, or null: candidates cand0, cand0 + 1, ...
+  int cand0;
   int persistent;        // resident workgroups take items from a queue
   int32_t *queue;        // counters: [variant group] for pass 1, [kQueueWin] for pass 2
   // per-band partial results of pass 2 ([n_cand][nbands])
@@ -138,8 +139,8 @@ template <typename F>
 __device__ __forceinline__ void for_each_item(const ScanArgs &A, int slot, F body) {
   const int n_items = A.n_cand * A.nbands;
   auto run = [&](int q) __attribute__((always_inline)) {
-    const int band = q / A.n_cand;
-    body(A.order[q - band * A.n_cand], band);
+    const int band = q / A.n_cand, i = q - band * A.n_cand;
+    body(A.order ? A.order[i] : A.cand0 + i, band);
   };
   if (!A.persistent) {
     run(blockIdx.x);
@@ -662,8 +663,9 @@ __global__ void __launch_bounds__(256, MINW) k_scan_win(ScanArgs A) {
 
 // One thread per candidate: combines the band partials into the score record.
 __global__ void k_scan_fin(ScanArgs A) {
-  const int cand = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cand >= A.n_cand) return;
+  const int local = blockIdx.x * blockDim.x + threadIdx.x;
+  if (local >= A.n_cand) return;
+  const int cand = A.cand0 + local;
   constexpr long long kNoKey = 0x7fffffffffffffffLL;
   const uint32_t st = A.status[cand];
   dcflow_score r;
@@ -1057,7 +1059,8 @@ hipError_t launch_max_vc(const ScanArgs &a, const dcflow_batch *bt, int nvar, in
 }
 
 template <typename T>
-hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *out, hipStream_t s) {
+hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *out, int c0, int c1,
+                    hipStream_t s) {
   dcflow_plan *p = bt->plan;
   ScanArgs a;
   a.F = flows;
@@ -1086,9 +1089,11 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   a.vmax_ld = bt->vmax;
   a.res = out;
   a.single = nvar == 1;  // one variant: the winner pass alone gives everything
-  a.persistent = bt->tune.persistent ? 1 : 0;
-  a.n_cand = bt->n_cand;
-  a.order = bt->d_order;
+  const bool whole = c0 == 0 && c1 == bt->n_cand;
+  a.persistent = whole && bt->tune.persistent ? 1 : 0;
+  a.n_cand = c1 - c0;
+  a.order = whole ? bt->d_order : nullptr;
+  a.cand0 = c0;
   a.queue = bt->d_queue;
   a.part_m = bt->d_part_m;
   a.part_k = bt->d_part_k;
@@ -1098,10 +1103,10 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   a.band_rows = 0;
   a.nbands = 1;
   {
-    const size_t nv = a.single ? 0 : (size_t)bt->n_cand * bt->vmax;
+    const size_t nv = a.single ? 0 : (size_t)a.n_cand * bt->vmax;
     const size_t n = nv > (size_t)(kQueueWin + 1) ? nv : (size_t)(kQueueWin + 1);
-    k_clear<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(bt->d_queue, kQueueWin + 1, bt->d_vmax,
-                                                        nv);
+    k_clear<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(bt->d_queue, kQueueWin + 1,
+                                                        bt->d_vmax + (size_t)c0 * bt->vmax, nv);
     DCF_CHECK_LAUNCH();
   }
   if (!a.single) {
@@ -1128,7 +1133,7 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   if (lds > kLdsBudget) return hipErrorInvalidValue;
   k_scan_win<T, sizeof(T) == 4 ? 4 : 1><<<dim3(grid_x(bt, a)), dim3(256), lds, s>>>(a);
   DCF_CHECK_LAUNCH();
-  k_scan_fin<<<(bt->n_cand + 255) / 256, 256, 0, s>>>(a);
+  k_scan_fin<<<(a.n_cand + 255) / 256, 256, 0, s>>>(a);
   DCF_CHECK_LAUNCH();
   return hipSuccess;
 }
@@ -1181,6 +1186,7 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   a.persistent = 0;
   a.n_cand = bt->n_cand;
   a.order = bt->d_order;
+  a.cand0 = 0;
   a.queue = nullptr;
   a.part_m = nullptr;
   a.part_k = nullptr;
@@ -1226,10 +1232,11 @@ hipError_t launch_worst(dcflow_batch *bt, const void *flows, int nvar, int prec,
 }
 
 hipError_t launch_score(dcflow_batch *bt, const void *flows, int nvar, int prec, dcflow_score *out,
-                        hipStream_t s) {
-  if (bt->n_cand == 0) return hipSuccess;
-  if (prec == DCFLOW_FP64) return run_scan<double>(bt, static_cast<const double *>(flows), nvar, out, s);
-  return run_scan<float>(bt, static_cast<const float *>(flows), nvar, out, s);
+                        int c0, int c1, hipStream_t s) {
+  if (c1 <= c0) return hipSuccess;
+  if (prec == DCFLOW_FP64)
+    return run_scan<double>(bt, static_cast<const double *>(flows), nvar, out, c0, c1, s);
+  return run_scan<float>(bt, static_cast<const float *>(flows), nvar, out, c0, c1, s);
 }
 
 }  // namespace dcflow

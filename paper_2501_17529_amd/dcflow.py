@@ -62,7 +62,8 @@ class Cands(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """dcflow_tuning: launch shapes of the N-1 scan (0 = automatic)."""
     _fields_ = [("scan_vc", ctypes.c_int32), ("scan_rchunk", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("scan_band", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("scan_band", ctypes.c_int32),
+                ("step_chunks", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -108,6 +109,7 @@ def _load():
         "dcflow_snapshot_flows": (ctypes.c_int, [P, P, I32, P, P, P]),
         "dcflow_n1_worst_workspace_bytes": (ctypes.c_int, [P, I32, P]),
         "dcflow_n1_worst": (ctypes.c_int, [P, P, I32, ctypes.c_int, P, I32, P, SZ, P, P]),
+        "dcflow_step": (ctypes.c_int, [P, P, I32, I32, ctypes.c_int, P, SZ, P, P]),
         "dcflow_batch_set_tuning": (ctypes.c_int, [P, P]),
         "dcflow_batch_get_tuning": (ctypes.c_int, [P, P]),
         "dcflow_graph_capture": (ctypes.c_int, [P, P, I32, I32, ctypes.c_int, P, SZ, P, P]),
@@ -137,7 +139,7 @@ EXPORTED = ("dcflow_plan_workspace_bytes", "dcflow_build_ptdf", "dcflow_plan_vie
             "dcflow_batch_create", "dcflow_batch_destroy", "dcflow_eval_topologies",
             "dcflow_flow_bytes", "dcflow_eval_injections", "dcflow_n1_score",
             "dcflow_batch_variant_max", "dcflow_strerror", "dcflow_n1_worst_workspace_bytes",
-            "dcflow_n1_worst", "dcflow_batch_set_tuning",
+            "dcflow_n1_worst", "dcflow_step", "dcflow_batch_set_tuning",
             "dcflow_batch_get_tuning", "dcflow_graph_capture", "dcflow_graph_launch", "dcflow_mlp_param_count",
             "dcflow_mlp_bf16_bytes", "dcflow_mlp_workspace_bytes", "dcflow_snapshot_flows",
             "dcflow_snapshot_pairs", "dcflow_action_features", "dcflow_improvement_labels",
@@ -381,8 +383,9 @@ class Batch:
         raw = out.cpu().numpy()[: n_cand * top_k * CASE_DTYPE.itemsize]
         return raw.view(CASE_DTYPE).reshape(n_cand, top_k)
 
-    def set_tuning(self, scan_vc=0, scan_rchunk=0, persistent=0, scan_band=0):
-        t = Tuning(int(scan_vc), int(scan_rchunk), int(persistent), int(scan_band))
+    def set_tuning(self, scan_vc=0, scan_rchunk=0, persistent=0, scan_band=0, step_chunks=0):
+        t = Tuning(int(scan_vc), int(scan_rchunk), int(persistent), int(scan_band),
+                   int(step_chunks))
         _check(_lib.dcflow_batch_set_tuning(self.h, ctypes.byref(t)), "dcflow_batch_set_tuning")
 
     def get_tuning(self):
@@ -391,15 +394,26 @@ class Batch:
         return t.as_dict()
 
     def capture(self, inj, n_var, shared, prec, flows, out, stream):
-        """Captures eval_topologies -> eval_injections -> n1_score with these
-        buffers into the batch's HIP graph (stream: a torch.cuda.Stream, not the
-        null stream); replay() then runs the whole step with one launch."""
+        """Captures the whole step (dcflow_step: eval_topologies -> eval_injections
+        -> n1_score, in the tuning's step chunks) with these buffers into the
+        batch's HIP graph (stream: a torch.cuda.Stream, not the null stream);
+        replay() then runs it with one launch."""
         _check(_lib.dcflow_graph_capture(self.h, ctypes.c_void_p(inj.data_ptr()), int(n_var),
                                          int(bool(shared)), PREC[prec],
                                          ctypes.c_void_p(flows.data_ptr()),
                                          flows.numel() * flows.element_size(),
                                          ctypes.c_void_p(out.data_ptr()), _stream(stream)),
                "dcflow_graph_capture")
+
+    def step(self, inj, n_var, shared, prec, flows, out, stream=None):
+        """The whole step (eval_topologies, eval_injections, n1_score) in one call,
+        in the tuning's step chunks (see dcflow_step)."""
+        _check(_lib.dcflow_step(self.h, ctypes.c_void_p(inj.data_ptr()), int(n_var),
+                                int(bool(shared)), PREC[prec], ctypes.c_void_p(flows.data_ptr()),
+                                flows.numel() * flows.element_size(),
+                                ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+               "dcflow_step")
+        return out
 
     def replay(self, stream=None):
         _check(_lib.dcflow_graph_launch(self.h, _stream(stream)), "dcflow_graph_launch")

@@ -74,7 +74,8 @@ def test_launch_shapes_agree(prec):
               for b in (64, 128) for rc in (0, 64) for pe in (0, 1)]
     for cfg in autotune.candidates(bt, nv, prec) + banded:
         bt.set_tuning(**cfg)
-        assert bt.get_tuning() == cfg
+        got = bt.get_tuning()
+        assert {k: got[k] for k in cfg} == cfg and got["step_chunks"] == 0
         _same(_scores(D, bt, flows, nv, prec), ref, f"{prec} {cfg}")
     # the default launch itself against the oracle
     r = oracle_rating(w)
@@ -153,13 +154,54 @@ def test_autotune_records_and_reuses(tmp_path, monkeypatch):
     flows = bt.eval_injections(x, nv, False, "fp32")
     ref = _scores(D, bt, flows, nv, "fp32")
     cfg, times = autotune.tune_scan(bt, flows, nv, "fp32")
-    assert bt.get_tuning() == cfg
+    got = bt.get_tuning()
+    assert {k: got[k] for k in cfg} == cfg
     assert all(v is not None for v in times.values()), times
     data = json.load(open(tmp_path / "tune.json"))
     key = autotune.shape_key(bt, nv, "fp32")
     assert data[key]["config"] == cfg
     bt.set_tuning()
     cfg2, _ = autotune.tune_scan(bt, flows, nv, "fp32")   # cache hit
-    assert cfg2 == cfg and bt.get_tuning() == cfg
+    got = bt.get_tuning()
+    assert cfg2 == cfg and {k: got[k] for k in cfg} == cfg
     _same(_scores(D, bt, flows, nv, "fp32"), ref, "tuned")
     say(f"autotune picked {cfg}")
+
+
+@pytest.mark.parametrize("chunks", [2, 3, 5])
+def test_chunked_step_matches_separate_calls(chunks):
+    """dcflow_step in candidate chunks (injections of one chunk beside the scan of
+    the previous one on the batch's second stream) gives the same flows and
+    scores, bit for bit, as the three calls over the whole batch; also captured
+    into a graph and replayed."""
+    import torch
+    from paper_2501_17529_amd import dcflow as D
+    w = _workload(seed=24)
+    nv = w.inj.shape[1]
+    plan = D.Plan.from_workload(w)
+    bt = D.Batch(plan, w.cands, nv)
+    x = torch.from_numpy(np.ascontiguousarray(w.inj)).cuda()
+    bt.eval_topologies()
+    ref_flows = bt.eval_injections(x, nv, False, "fp32").clone()
+    ref = _scores(D, bt, ref_flows, nv, "fp32")
+    bt.set_tuning(step_chunks=chunks)
+    assert bt.get_tuning()["step_chunks"] == chunks
+    flows, _ = bt.flow_buffer(nv, "fp32")
+    out = torch.empty(bt.n_cand * D.SCORE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        flows.zero_()
+        bt.step(x, nv, False, "fp32", flows, out, s)
+        torch.cuda.synchronize()
+        assert torch.equal(flows, ref_flows)
+        _same(D.Batch.scores_to_numpy(out, bt.n_cand), ref, f"step chunks={chunks}")
+        bt.capture(x, nv, False, "fp32", flows, out, s)
+        for rep in range(3):
+            out.zero_()
+            flows.zero_()
+            torch.cuda.synchronize()
+            bt.replay(s)
+            torch.cuda.synchronize()
+            assert torch.equal(flows, ref_flows), rep
+            _same(D.Batch.scores_to_numpy(out, bt.n_cand), ref, f"replay {rep} chunks={chunks}")
+    say(f"chunked step ({chunks} chunks) matches the separate calls")
