@@ -38,23 +38,31 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_medium_traffic.txt")
 def _oracle_worker(args):
     from threadpoolctl import threadpool_limits
     from oracle import dcflow_oracle as O
-    n_bus, f, t, b, slack, elems, x, mon, out, rating = args
+    n_bus, f, t, b, slack, elems, x, mon, out, rating, controls = args
+    kw = {}
+    if controls:
+        kw = dict(controls=controls, ctrl=x[:, n_bus:])
+        x = x[:, :n_bus]
     with threadpool_limits(limits=1):
-        O.score_candidate(n_bus, f, t, b, slack, elems, x, mon, out, rating)
+        O.score_candidate(n_bus, f, t, b, slack, elems, x, mon, out, rating, **kw)
     return x.shape[0] * len(out)
 
 
-def cpu_baseline(w, n_sample: int):
-    """The oracle (dense LU per candidate) on the first n_sample candidates,
-    process-parallel over candidates, one BLAS thread per process."""
+def cpu_baseline(w, n_sample: int, max_var: int = 0):
+    """The oracle (dense LU per candidate) on the first n_sample candidates (and
+    their first max_var variants, if given), process-parallel over candidates,
+    one BLAS thread per process."""
     import multiprocessing as mp
     from oracle import dcflow_oracle as O
     g = w.grid
     rating = O.ratings(g.n_bus, g.f, g.t, g.b, g.slack, g.p, w.mon, w.rating_scale,
                        w.rating_offset)
     cores = max(1, min(16, os.cpu_count() or 1))
-    jobs = [(g.n_bus, g.f, g.t, g.b, g.slack, w.cands.elements(i),
-             w.inj[i] if not w.inj_shared else w.inj, w.mon, w.out, rating)
+    def xs(i):
+        x = w.inj[i] if not w.inj_shared else w.inj
+        return x[:max_var] if max_var else x
+    jobs = [(g.n_bus, g.f, g.t, g.b, g.slack, w.cands.elements(i), xs(i), w.mon, w.out, rating,
+             getattr(w, "controls", None))
             for i in range(n_sample)]
     ctx = mp.get_context("fork")     # forked before this process touches the GPU
     t0 = time.perf_counter()
@@ -62,8 +70,9 @@ def cpu_baseline(w, n_sample: int):
         lf = sum(pool.map(_oracle_worker, jobs, chunksize=1))
     dt = time.perf_counter() - t0
     return dict(value=lf / dt, unit="loadflows/s", cores=cores, kind="oracle",
-                sample=f"first {n_sample} of {w.cands.n_cand} candidates of the same workload "
-                       f"({lf} loadflows, {dt:.1f} s wall)")
+                sample=f"first {n_sample} of {w.cands.n_cand} candidates of the same workload"
+                       + (f", first {max_var} of {w.n_var} variants" if max_var else "")
+                       + f" ({lf} loadflows, {dt:.1f} s wall)")
 
 
 # ------------------------------------------------------------------ GPU timing
@@ -169,6 +178,10 @@ WORKLOADS = {
     "uneven": ("uneven-10000bus, one GPU's share: 10,000 buses / 15,500 branches, {n} candidates "
                "of rank uniform in 1..8 (of the 65,536-candidate batch), 1 injection each, every "
                "branch monitored, N-1 over 2,000 contingencies, persistent launch"),
+    "brute": ("brute-2000bus: 2,000 buses / 3,100 branches with 20 phase shifters and 4 HVDC "
+              "links, {n} topologies x 4,096 shared control/load combinations (one GEMM over the "
+              "combinations, control columns folded into K), every branch monitored, N-1 over "
+              "1,000 contingencies"),
 }
 
 
@@ -179,9 +192,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="medium")
     ap.add_argument("--cands", type=int, default=0, help="candidates (default: 4,096 medium, "
-                    "8,192 uneven)")
+                    "8,192 uneven, 1,024 brute)")
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="oracle sample size (default: 128 medium, 2 uneven)")
+                    help="oracle sample size (default: 128 medium, 2 uneven, 1 brute)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", choices=["all", "fp32", "fp64", "bf16x6", "bf16"], default="all")
     ap.add_argument("--no-autotune", action="store_true")
@@ -214,11 +227,16 @@ def main():
         w = G.workload_medium(0, n_cand=a.cands or 4096)
         precs = ["fp32", "fp64", "bf16x6"] if a.prec == "all" else [a.prec]
         sample = a.cpu_sample or 128
-    else:
+    elif a.workload == "uneven":
         w = G.workload_uneven(0, n_cand=a.cands or 8192)
         precs = ["fp32", "bf16x6"] if a.prec == "all" else [a.prec]
         sample = a.cpu_sample or 2
-    cpu = None if a.no_cpu_baseline else cpu_baseline(w, min(sample, w.cands.n_cand))
+    else:
+        w = G.workload_brute(0, n_topo=a.cands or 1024)
+        precs = ["fp32", "bf16x6"] if a.prec == "all" else [a.prec]
+        sample = a.cpu_sample or 1
+    max_var = 128 if a.workload == "brute" else 0   # the oracle holds all N-1 flows at once
+    cpu = None if a.no_cpu_baseline else cpu_baseline(w, min(sample, w.cands.n_cand), max_var)
 
     import torch
     from paper_2501_17529_amd import dcflow as D

@@ -187,7 +187,8 @@ void batch_layout(dcflow_batch *b, const dcflow_plan *p, const BatchDims &d, Are
   b->d_vmax = a.take<double>(nc * d.vmax);
   b->d_f0 = a.take<double>((size_t)d.vmax * p->ld_er);
   b->ldx = (p->n_inj + 31) / 32 * 32;
-  b->xs_cols = nc * (size_t)d.vmax;
+  // BF16 parts of x - p_base for at most kXsMaxCols columns (larger GEMMs run in blocks)
+  b->xs_cols = std::min(nc * (size_t)d.vmax, kXsMaxCols);
   b->d_xs = a.take<__bf16>(3 * b->xs_cols * (size_t)b->ldx);
   b->d_queue = a.take<int32_t>(16);
   const size_t np = nc * (size_t)(p->mon_pad / 64);

@@ -15,6 +15,7 @@ constexpr int kMaxRank = DCFLOW_MAX_RANK;
 constexpr int kMaxSig = DCFLOW_MAX_SPLIT_DEG;  // sensing branches per element
 constexpr int kWave = 64;
 constexpr int kMaxStepChunks = 16;  // most candidate chunks of the overlapped step
+constexpr size_t kXsMaxCols = size_t(1) << 20;  // columns of the BF16 split buffer
 constexpr double kIslandTol = 1e-9;   // |LODF denominator| below this: islanding
 constexpr double kSingularTol = 1e-10; // relative pivot threshold of the k x k solve
 
@@ -93,7 +94,7 @@ struct dcflow_batch {
   double *d_f0;     // [vmax][ld_er] shared-injection GEMM output
   __bf16 *d_xs;     // [3][xs_cols][ldx] BF16 parts of x - p_base (BF16 GEMM modes)
   int ldx;          // n_inj rounded up to 32
-  size_t xs_cols;   // n_cand * vmax
+  size_t xs_cols;   // min(n_cand * vmax, kXsMaxCols)
   int32_t *d_queue; // [16] work-queue counters of the persistent scan
   int max_bands;    // mon_pad / 64: most row bands of one candidate
   double *d_part_m, *d_part_ov;  // [n_cand][max_bands] band partials of the winner pass

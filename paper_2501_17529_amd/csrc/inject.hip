@@ -504,9 +504,23 @@ hipError_t launch_gemm(const dcflow_plan *p, const T *He, int np, const double *
   if constexpr (sizeof(T) == 4) {
     const size_t part = (size_t)p->ld_er * p->ld_h;
     if (np == 3 || np == 1) {
-      if (col0 + (size_t)ncols > bt->xs_cols) return hipErrorInvalidValue;
+      // the split buffer holds xs_cols columns: larger GEMMs run in blocks of whole
+      // candidates (the parts of a block are written just before its GEMM)
       const size_t xpart = bt->xs_cols * (size_t)bt->ldx;
-      __bf16 *xs = bt->d_xs + col0 * bt->ldx;
+      const int blk = (int)std::min<size_t>((size_t)ncols, bt->xs_cols / nvar * nvar);
+      if (blk <= 0) return hipErrorInvalidValue;
+      if (ncols > blk) {
+        for (int cb = 0; cb < ncols; cb += blk) {
+          const int nc = std::min(blk, ncols - cb);
+          const hipError_t e = launch_gemm<T>(p, He, np, X + (size_t)cb * p->n_inj, nc, nvar, shared,
+                                              F + (size_t)cb * p->ld_er, bt, correct,
+                                              off + (correct ? cb / nvar : 0), 0, s);
+          if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+      }
+      (void)col0;
+      __bf16 *xs = bt->d_xs;  // columns from 0: each launch splits its own columns first
       const size_t nthr = (size_t)ncols * (bt->ldx / 8);
       const dim3 sg((unsigned)((nthr + 255) / 256));
       if (np == 3) {
