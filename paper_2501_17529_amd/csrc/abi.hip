@@ -8,6 +8,8 @@
 #include <new>
 #include <numeric>
 
+#include <cstdlib>
+
 #include "dcflow_internal.h"
 
 using namespace dcflow;
@@ -187,8 +189,15 @@ void batch_layout(dcflow_batch *b, const dcflow_plan *p, const BatchDims &d, Are
   b->d_vmax = a.take<double>(nc * d.vmax);
   b->d_f0 = a.take<double>((size_t)d.vmax * p->ld_er);
   b->ldx = (p->n_inj + 31) / 32 * 32;
-  // BF16 parts of x - p_base for at most kXsMaxCols columns (larger GEMMs run in blocks)
-  b->xs_cols = std::min(nc * (size_t)d.vmax, kXsMaxCols);
+  // BF16 parts of x - p_base for at most kXsMaxCols columns (larger GEMMs run in
+  // blocks of whole candidates); DCFLOW_SPLIT_COLS lowers the cap (tests use it to
+  // run the blocked path on small batches)
+  size_t cap = kXsMaxCols;
+  if (const char *env = std::getenv("DCFLOW_SPLIT_COLS")) {
+    const long long v = std::atoll(env);
+    if (v > 0 && (size_t)v < cap) cap = (size_t)v;
+  }
+  b->xs_cols = std::min(nc * (size_t)d.vmax, cap);
   b->d_xs = a.take<__bf16>(3 * b->xs_cols * (size_t)b->ldx);
   b->d_queue = a.take<int32_t>(16);
   const size_t np = nc * (size_t)(p->mon_pad / 64);

@@ -190,3 +190,23 @@ def test_bf16_flows_within_rounding_bound():
         worst = max(worst, float((err / bound).max()))
         assert (err <= bound).all(), (i, float((err / bound).max()))
     say(f"bf16: worst error / bound = {worst:.3f}")
+
+
+def test_bf16x6_gemm_in_column_blocks(monkeypatch):
+    """With the BF16 split buffer capped below the batch's columns the GEMM runs in
+    blocks of whole candidates: the flows are the same, bit for bit."""
+    import torch
+    from paper_2501_17529_amd import dcflow as D
+    w = G.workload_medium(3, n_cand=40, n_var=4)
+    plan = D.Plan.from_workload(w)
+    x = torch.from_numpy(np.ascontiguousarray(w.inj)).cuda()
+    got = []
+    for cap in (None, "24"):   # 24 columns = 6 candidates of 4 variants per block
+        if cap:
+            monkeypatch.setenv("DCFLOW_SPLIT_COLS", cap)
+        bt = D.Batch(plan, w.cands, 4)
+        bt.eval_topologies()
+        fl = bt.eval_injections(x, 4, False, "bf16x6")
+        torch.cuda.synchronize()
+        got.append(fl.clone())
+    assert torch.equal(got[0], got[1])
