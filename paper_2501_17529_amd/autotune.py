@@ -90,7 +90,7 @@ def _time_scan(batch, flows, n_var, prec, out, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def tune_scan(batch: "D.Batch", flows, n_var: int, prec: str, reps: int = 3,
+def tune_scan(batch: "D.Batch", flows, n_var: int, prec: str, reps: int = 10,
               use_cache: bool = True, verbose: bool = False):
     """Picks (and applies to `batch`) the fastest scan launch shape; returns
     (config dict, {config string: ms})."""
