@@ -351,6 +351,23 @@ def workload_tiny(seed: int = 0, n_cand: int = 100) -> Workload:
                     meta=dict(n_bus=30, n_branch=41, n_cand=n_cand, n_var=1))
 
 
+def busbar_injection_topologies(grid: Grid, cands: Candidates, rng, n_var: int,
+                                n_parts: int = 4) -> np.ndarray:
+    """Injection topologies T_i (Sec. III-A) for the split elements of a candidate
+    set: the base injection of each split bus is cut into n_parts random shares
+    (standing in for the loads and generators of the substation), and variant v
+    puts a random subset of them on the new busbar.  Returns [n_elem][n_var] (0 for
+    outage elements): the injection moved to busbar B per element and variant."""
+    out = np.zeros((cands.n_elem, n_var))
+    for e in range(cands.n_elem):
+        if int(cands.kind[e]) != KIND_SPLIT:
+            continue
+        share = rng.dirichlet(np.ones(n_parts)) * float(grid.p[int(cands.id[e])])
+        pick = rng.integers(0, 2, size=(n_var, n_parts))
+        out[e] = pick @ share
+    return out
+
+
 def workload_medium(seed: int = 0, n_cand: int = 4096, n_var: int = 16,
                     n_out: int = 500) -> Workload:
     """1,000 buses / 1,600 branches, 1-3 splits plus 0-2 outages per candidate,

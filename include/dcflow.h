@@ -238,6 +238,18 @@ int dcflow_eval_injections(dcflow_batch *batch, const double *dev_inj, int32_t n
 int dcflow_n1_score(dcflow_batch *batch, const void *dev_flows, int32_t n_var,
                     dcflow_prec prec, dcflow_score *dev_out, hipStream_t stream);
 
+/* Injection topologies (T_i of Sec. III-A): per split element and variant, the
+ * injection placed on the split's new busbar, replacing the candidate's fixed
+ * p_new in every later dcflow_eval_injections / dcflow_step (and graphs captured
+ * after this call).  A variant can then regroup the injections of a split
+ * substation between its two busbars while the nodal injection vector, in base
+ * numbering, stays the same; the argmin over the variants is t_i*.  dev_pnew:
+ * device array [n_elem][n_var] in the candidates' element order (values of
+ * outage elements are ignored), read during each evaluation; NULL restores the
+ * fixed p_new.  E_SHAPE unless 1 <= n_var <= n_var_max; evaluations with another
+ * n_var then fail with E_SHAPE. */
+int dcflow_set_busbar_injections(dcflow_batch *batch, const double *dev_pnew, int32_t n_var);
+
 /* One case of the worst-case list (agg_i of Sec. III-A). */
 typedef struct {
   double load;      /* |p| / rating; -1 for an unused entry                      */

@@ -189,7 +189,10 @@ def rebuild(n, f, t, elems):
                         f2[br] = newbus
                     else:
                         t2[br] = newbus
-            splits.append((a, newbus, float(p_new)))
+            # p_new: one value, or one per injection variant (injection topologies T_i
+            # of Sec. III-A regroup a substation's injections between its busbars)
+            pn = np.asarray(p_new, np.float64)
+            splits.append((a, newbus, float(pn) if pn.ndim == 0 else pn))
         elif kind == KIND_OUTAGE:
             alive[int(ident)] = False
         else:
@@ -199,8 +202,8 @@ def rebuild(n, f, t, elems):
 
 def candidate_injections(n_nodes, x, splits, slack):
     """Injections of the rebuilt network for base-numbered variants ``x``
-    ([V, n]): busbar B_j receives p_new_j, taken from its parent bus A_j; the
-    slack absorbs the imbalance."""
+    ([V, n]): busbar B_j receives p_new_j (a number, or one per variant), taken
+    from its parent bus A_j; the slack absorbs the imbalance."""
     x = np.atleast_2d(np.asarray(x, np.float64))
     v, n = x.shape
     p = np.zeros((v, n_nodes))

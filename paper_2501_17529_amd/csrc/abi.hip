@@ -505,6 +505,8 @@ int dcflow_batch_create(dcflow_plan *p, const dcflow_cands *c, int32_t n_var_max
   b->factored = 0;
   b->flows_prec = -1;
   b->flows_nvar = 0;
+  b->d_pnv = nullptr;
+  b->pnv_nvar = 0;
   b->tune = dcflow_tuning{0, 0, 0, 0, 0};
   b->aux = nullptr;
   for (int i = 0; i <= kMaxStepChunks; ++i) b->step_ev[i] = nullptr;
@@ -617,6 +619,7 @@ int check_step(dcflow_batch *b, const double *dev_inj, int32_t n_var, dcflow_pre
   if (!b || !dev_inj || !dev_flows || !dev_out) return DCFLOW_E_ARG;
   if (n_var < 1 || n_var > b->vmax) return DCFLOW_E_SHAPE;
   if (!prec_valid(prec)) return DCFLOW_E_ARG;
+  if (b->d_pnv && b->pnv_nvar != n_var) return DCFLOW_E_SHAPE;
   size_t need = 0;
   dcflow_flow_bytes(b, n_var, prec, &need, nullptr);
   if (flow_bytes < need) return DCFLOW_E_WORKSPACE;
@@ -711,6 +714,7 @@ int dcflow_eval_injections(dcflow_batch *b, const double *dev_inj, int32_t n_var
   if (n_var < 1 || n_var > b->vmax) return DCFLOW_E_SHAPE;
   if (!prec_valid(prec)) return DCFLOW_E_ARG;
   if (!b->factored) return DCFLOW_E_ARG;
+  if (b->d_pnv && b->pnv_nvar != n_var) return DCFLOW_E_SHAPE;
   size_t need = 0;
   dcflow_flow_bytes(b, n_var, prec, &need, nullptr);
   if (flow_bytes < need) return DCFLOW_E_WORKSPACE;
@@ -756,6 +760,14 @@ int dcflow_n1_worst(dcflow_batch *b, const void *dev_flows, int32_t n_var, dcflo
   if (ws_bytes < need) return DCFLOW_E_WORKSPACE;
   hipError_t e = launch_worst(b, dev_flows, n_var, prec, dev_scores, top_k, dev_ws, dev_out, s);
   if (e != hipSuccess) return hip_fail(e, "dcflow_n1_worst");
+  return DCFLOW_OK;
+}
+
+int dcflow_set_busbar_injections(dcflow_batch *b, const double *dev_pnew, int32_t n_var) {
+  if (!b) return DCFLOW_E_ARG;
+  if (dev_pnew && (n_var < 1 || n_var > b->vmax)) return DCFLOW_E_SHAPE;
+  b->d_pnv = dev_pnew;
+  b->pnv_nvar = dev_pnew ? n_var : 0;
   return DCFLOW_OK;
 }
 

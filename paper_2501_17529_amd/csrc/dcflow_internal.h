@@ -107,6 +107,8 @@ struct dcflow_batch {
   hipGraph_t graph;       // captured step (dcflow_graph_capture), or null
   hipGraphExec_t graph_exec;
   int factored;     // eval_topologies enqueued
+  const double *d_pnv;  // [n_elem][pnv_nvar] per-variant new-busbar injections, or null
+  int pnv_nvar;
   int flows_prec;   // precision of the last eval_injections (-1 none)
   int flows_nvar;
 };

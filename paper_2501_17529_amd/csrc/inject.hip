@@ -34,7 +34,8 @@ k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
         const int32_t *__restrict__ nsig, const int32_t *__restrict__ sig,
         const double *__restrict__ pnew, const double *__restrict__ kinv,
         const double *__restrict__ Hb, int ld_h, int n, const double *__restrict__ X, int nvar,
-        int shared, double *__restrict__ z, int vmax, int cand0) {
+        int shared, double *__restrict__ z, int vmax, int cand0,
+        const double *__restrict__ pnv) {
   __shared__ int rbr[kMaxRank * kMaxSig];
   __shared__ double rsg[kMaxRank * kMaxSig];
   __shared__ int relem[kMaxRank * kMaxSig];
@@ -128,8 +129,15 @@ k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
       if (v < nvar) {
         double h[kMaxRank];
 #pragma unroll
-        for (int j = 0; j < kMaxRank; ++j)
-          h[j] = j < k ? hacc[j][tid] - (kind[e0 + j] == DCFLOW_SPLIT ? pnew[e0 + j] : 0.0) : 0.0;
+        for (int j = 0; j < kMaxRank; ++j) {
+          h[j] = 0.0;
+          if (j < k) {
+            // injection on the split's new busbar: per variant (injection topologies)
+            // if given, else the candidate's fixed value
+            const double pb = pnv ? pnv[(size_t)(e0 + j) * nvar + v] : pnew[e0 + j];
+            h[j] = hacc[j][tid] - (kind[e0 + j] == DCFLOW_SPLIT ? pb : 0.0);
+          }
+        }
         const double *Ki = kinv + (size_t)cand * 64;
 #pragma unroll
         for (int j = 0; j < kMaxRank; ++j) {
@@ -561,7 +569,7 @@ hipError_t run_injections(dcflow_batch *bt, const T *He, int np, const double *i
   if (shared && (c0 != 0 || c1 != bt->n_cand)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_sense, dim3(c1 - c0), dim3(256), 0, s, bt->d_off, bt->d_kind, bt->d_nsig,
                      bt->d_sig, bt->d_pnew, bt->d_kinv, p->d_hb, p->ld_h, p->n_inj, inj, nvar, shared,
-                     bt->d_z, bt->vmax, c0);
+                     bt->d_z, bt->vmax, c0, bt->d_pnv);
   DCF_CHECK_LAUNCH();
   if (!shared) {
     const size_t col0 = (size_t)c0 * nvar;

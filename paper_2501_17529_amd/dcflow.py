@@ -110,6 +110,7 @@ def _load():
         "dcflow_n1_worst_workspace_bytes": (ctypes.c_int, [P, I32, P]),
         "dcflow_n1_worst": (ctypes.c_int, [P, P, I32, ctypes.c_int, P, I32, P, SZ, P, P]),
         "dcflow_step": (ctypes.c_int, [P, P, I32, I32, ctypes.c_int, P, SZ, P, P]),
+        "dcflow_set_busbar_injections": (ctypes.c_int, [P, P, I32]),
         "dcflow_batch_set_tuning": (ctypes.c_int, [P, P]),
         "dcflow_batch_get_tuning": (ctypes.c_int, [P, P]),
         "dcflow_graph_capture": (ctypes.c_int, [P, P, I32, I32, ctypes.c_int, P, SZ, P, P]),
@@ -139,7 +140,8 @@ EXPORTED = ("dcflow_plan_workspace_bytes", "dcflow_build_ptdf", "dcflow_plan_vie
             "dcflow_batch_create", "dcflow_batch_destroy", "dcflow_eval_topologies",
             "dcflow_flow_bytes", "dcflow_eval_injections", "dcflow_n1_score",
             "dcflow_batch_variant_max", "dcflow_strerror", "dcflow_n1_worst_workspace_bytes",
-            "dcflow_n1_worst", "dcflow_step", "dcflow_batch_set_tuning",
+            "dcflow_n1_worst", "dcflow_step", "dcflow_set_busbar_injections",
+            "dcflow_batch_set_tuning",
             "dcflow_batch_get_tuning", "dcflow_graph_capture", "dcflow_graph_launch", "dcflow_mlp_param_count",
             "dcflow_mlp_bf16_bytes", "dcflow_mlp_workspace_bytes", "dcflow_snapshot_flows",
             "dcflow_snapshot_pairs", "dcflow_action_features", "dcflow_improvement_labels",
@@ -404,6 +406,19 @@ class Batch:
                                          flows.numel() * flows.element_size(),
                                          ctypes.c_void_p(out.data_ptr()), _stream(stream)),
                "dcflow_graph_capture")
+
+    def set_busbar_injections(self, pnew=None, n_var=0):
+        """Per-variant injections on the splits' new busbars (injection topologies):
+        a float64 device tensor [n_elem][n_var], or None for the candidates' fixed
+        p_new.  The tensor must stay alive while evaluations use it."""
+        if pnew is None:
+            _check(_lib.dcflow_set_busbar_injections(self.h, None, 0), "dcflow_set_busbar_injections")
+            self._pnv = None
+            return
+        assert pnew.dtype.is_floating_point and pnew.element_size() == 8 and pnew.is_contiguous()
+        _check(_lib.dcflow_set_busbar_injections(self.h, ctypes.c_void_p(pnew.data_ptr()), int(n_var)),
+               "dcflow_set_busbar_injections")
+        self._pnv = pnew
 
     def step(self, inj, n_var, shared, prec, flows, out, stream=None):
         """The whole step (eval_topologies, eval_injections, n1_score) in one call,

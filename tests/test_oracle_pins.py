@@ -458,3 +458,30 @@ def test_n1_with_controls_matches_bruteforce():
             sup = cf["p0"] + cf["lodf"][:, ci][None, :] * cf["p0"][:, c][:, None]
             sup[:, c] = 0.0
             np.testing.assert_allclose(sup, p1[:, ci, :], atol=1e-10)
+
+
+def test_per_variant_busbar_injections_match_fixed_ones():
+    """Injection topologies: a candidate whose split moves a different share of the
+    substation's injection to the new busbar in each variant gives, variant by
+    variant, the flows of the same candidate with that share as its fixed p_new;
+    Kirchhoff's law holds at the new busbar with the moved injection."""
+    w = G.workload_tiny(5)
+    g = w.grid
+    rng = np.random.default_rng(5)
+    i = next(j for j in range(w.cands.n_cand) if any(e[0] == G.KIND_SPLIT for e in w.cands.elements(j)))
+    el = w.cands.elements(i)
+    x = np.repeat(np.atleast_2d(w.inj if w.inj_shared else w.inj[i])[:1], 6, axis=0)
+    shares = rng.normal(0.0, 0.7, size=6)
+    elv = [(k, b, m, shares if k == G.KIND_SPLIT else 0.0) for (k, b, m, _) in el]
+    cf = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, elv, x, w.out)
+    for v in range(6):
+        elf = [(k, b, m, float(shares[v]) if k == G.KIND_SPLIT else 0.0) for (k, b, m, _) in el]
+        one = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, elf, x[v:v + 1], w.out)
+        np.testing.assert_allclose(cf["p0"][v], one["p0"][0], atol=1e-12)
+    # balance at the new busbar: its branches carry the moved injection away
+    n2, f2, t2, alive, splits = O.rebuild(g.n_bus, g.f, g.t, elv)
+    a, bnew, pn = splits[0]
+    for v in range(6):
+        out_b = sum(cf["p0"][v][l] for l in range(len(f2)) if alive[l] and f2[l] == bnew) - \
+            sum(cf["p0"][v][l] for l in range(len(f2)) if alive[l] and t2[l] == bnew)
+        assert abs(out_b - pn[v]) < 1e-10
