@@ -129,6 +129,8 @@ class Workload:
     # controls: None or dict(pst=[branch ids], pst_scale, hvdc=[(i, j)], hvdc_scale);
     # their values follow the n nodal entries of every injection vector
     controls: Optional[dict] = None
+    # generator-outage N-1 cases: None or (bus ids int32 [G], lost outputs float64 [G])
+    gens: Optional[tuple] = None
 
     @property
     def n_var(self) -> int:
@@ -334,6 +336,18 @@ def perturbed_injections(grid: Grid, rng, shape, rel_sigma: float) -> np.ndarray
     """Load perturbations P_v = P_base (1 + rel_sigma g), g ~ N(0, 1) per bus."""
     g = rng.normal(0.0, 1.0, tuple(shape) + (grid.n_bus,))
     return balanced(grid.p * (1.0 + rel_sigma * g), grid.slack)
+
+
+def generator_outages(grid: Grid, rng, n_gen: int):
+    """Generator-outage N-1 cases: n_gen generators at distinct buses drawn among
+    those with a positive base injection (the slack left out), each losing
+    between half and all of its bus's base injection.  Returns (bus ids, outputs)."""
+    gen_buses = np.flatnonzero(grid.p > 0.0)
+    gen_buses = gen_buses[gen_buses != grid.slack]
+    n_gen = min(n_gen, len(gen_buses))
+    bus = np.sort(rng.choice(gen_buses, size=n_gen, replace=False)).astype(np.int32)
+    pg = grid.p[bus] * rng.uniform(0.5, 1.0, size=n_gen)
+    return bus, pg.astype(np.float64)
 
 
 # ------------------------------------------------------------- workloads

@@ -17,8 +17,10 @@
  *   dcflow_eval_injections  Sec. III-C injection module step 8a: post-change
  *                           N-0 flows F' = PTDF' P for every injection
  *                           variant (Eq. ptdf_times_nodal_inj).
- *   dcflow_n1_score         Steps 8b and 8e: N-1 flows p0 + LODF[:,c] p0[c]
- *                           (Eq. lodf_delta) reduced to agg_m (maximum
+ *   dcflow_n1_score         Steps 8b, 8d and 8e: N-1 flows p0 + LODF[:,c] p0[c]
+ *                           (Eq. lodf_delta) and p0 - P_g PTDF'[:, bus_g] for
+ *                           generator outages (Eq. ptdf_delta), reduced to
+ *                           agg_m (maximum
  *                           relative load), t_i* = argmin over the variants,
  *                           then (metric-first, Sec. IV-B) the winner's
  *                           overload sum and worst (branch, contingency).
@@ -127,6 +129,17 @@ typedef struct {
   const int32_t *hvdc_from;    /* [n_hvdc] bus ids                               */
   const int32_t *hvdc_to;      /* [n_hvdc] bus ids, != hvdc_from                 */
   double hvdc_scale;           /* p.u. per unit                                  */
+  /* Generator outages (optional: 0 and NULLs for none).  N-1 case g loses the
+   * output gen_p[g] of a generator at bus gen_bus[g] and the slack takes it up:
+   * the flows change by -gen_p[g] PTDF'[:, gen_bus[g]] (Eq. ptdf_delta, Sec.
+   * III-C step 8d), PTDF' being the candidate grid's.  The generator stays on
+   * busbar A when its bus is split (the lost output leaves A).  Generator cases
+   * come after the n_out branch contingencies in every contingency-indexed
+   * array and are reported with outage id -2 - g.  A generator at the slack
+   * changes no flow.  Several generators may share a bus. */
+  int32_t n_gen_out;
+  const int32_t *gen_bus;      /* [n_gen_out] bus ids                            */
+  const double *gen_p;         /* [n_gen_out] lost output (p.u.), finite         */
 } dcflow_grid_desc;
 
 /* Topology candidates in CSR form (host pointers).  Candidate i owns
@@ -152,7 +165,8 @@ typedef struct {
   double overload_sum;   /* sum of max(0, |p|/r - 1) over the same set at t_i*  */
   int32_t best_variant;  /* t_i* (lowest index on ties); -1 if disconnected     */
   int32_t worst_branch;  /* monitored branch id of the maximum                  */
-  int32_t worst_outage;  /* contingency branch id of the maximum, -1 for N-0    */
+  int32_t worst_outage;  /* contingency branch id of the maximum, -1 for N-0,
+                            -2 - g for generator outage g                       */
   uint32_t status;       /* DCFLOW_ST_* bits, island count in bits 8..31       */
 } dcflow_score;
 
@@ -161,13 +175,15 @@ typedef struct {
 typedef struct {
   int32_t n_bus, n_branch, n_mon, n_out, n_er; /* n_er = |E_m u O| rows kept   */
   int32_t ld_h;      /* leading dim of ptdf (>= n_bus)                          */
-  int32_t ld_o;      /* leading dim of hdo  (>= n_out)                          */
+  int32_t ld_o;      /* leading dim of hdo  (>= n_out + n_gen_out)              */
   const double *ptdf;    /* [n_branch][ld_h] full PTDF, slack column 0         */
-  const double *hdo;     /* [n_branch][ld_o] PTDF[:, f_c] - PTDF[:, t_c], c in O */
+  const double *hdo;     /* [n_branch][ld_o] PTDF[:, f_c] - PTDF[:, t_c], c in O;
+                            column n_out + g: PTDF[:, gen_bus[g]]              */
   const double *f_base;  /* [n_branch] base flows PTDF p_base                   */
   const double *rating;  /* [n_mon] ratings used by the score                   */
   const int32_t *er;     /* [n_er] kept rows: E_m first, then O \ E_m          */
   int32_t n_inj;         /* entries per injection vector (n_bus + controls)    */
+  int32_t n_gen_out;     /* generator outages (columns after the n_out ones)   */
 } dcflow_plan_view;
 
 typedef struct dcflow_plan dcflow_plan;
@@ -254,7 +270,8 @@ int dcflow_set_busbar_injections(dcflow_batch *batch, const double *dev_pnew, in
 typedef struct {
   double load;      /* |p| / rating; -1 for an unused entry                      */
   int32_t branch;   /* monitored branch id; -1 for an unused entry               */
-  int32_t outage;   /* contingency branch id, -1 for the N-0 case (or unused)    */
+  int32_t outage;   /* contingency branch id, -1 for the N-0 case (or unused),
+                       -2 - g for generator outage g                            */
 } dcflow_case;
 
 #define DCFLOW_WORST_MAX 16 /* most cases per candidate in one call */
@@ -267,14 +284,14 @@ int dcflow_n1_worst_workspace_bytes(const dcflow_batch *batch, int32_t top_k, si
  * loads of its winning variant over the monitored branches in N-0 and in every
  * scored N-1 case (islanding contingencies excluded, as in the score), ordered
  * by load descending, ties by case (N-0 first, then contingencies in the
- * order of the grid's list) and then by the branch's position in the monitored
+ * order of the grid's list, then generator outages) and then by the branch's position in the monitored
  * list.  The winner is dev_scores[i].best_variant from a dcflow_n1_score call on
  * the same batch and flows (device array, read on the stream); the entry with
  * the largest load equals that call's (max_load, worst_branch, worst_outage).
  * Candidates that are disconnected or have non-finite flows, and entries past
  * the number of scored cases, are unused (load -1).  dev_ws: workspace of
  * dcflow_n1_worst_workspace_bytes bytes; dev_out: [n_cand][top_k] (device).
- * E_ARG for top_k outside 1..DCFLOW_WORST_MAX, or if (n_out + 1) * n_mon
+ * E_ARG for top_k outside 1..DCFLOW_WORST_MAX, or if (n_out + n_gen_out + 1) * n_mon
  * exceeds 2^31 - 1 (the case keys are 32-bit); E_WORKSPACE if ws_bytes is too
  * small. */
 int dcflow_n1_worst(dcflow_batch *batch, const void *dev_flows, int32_t n_var, dcflow_prec prec,

@@ -19,6 +19,9 @@ for topology optimization"):
     flows p = PTDF P (Eq. ptdf_times_nodal_inj).
   * Sec. II, Def. of the LODF and Eq. lodf_delta for N-1 flows, applied with
     the candidate network's own PTDF.
+  * Sec. II, Eq. ptdf_delta (flow change = PTDF times the injection change)
+    and Sec. III-C step 8d: generator-outage N-1 cases, here by solving the
+    candidate network again with the lost output removed.
   * Sec. III-A, task definition: N-0 and N-1 flows over monitored branches,
     agg_m = maximum relative branch load, t_i* = argmin over the injection
     variants (Eq. solver_end_to_end).
@@ -31,6 +34,9 @@ Readings where the paper is silent:
     of the grid: it is excluded from the score and counted;
   * an N-1 contingency already removed by a remedial outage leaves the N-0
     flows unchanged (it is still scored);
+  * a generator outage removes the generator's output from its bus (busbar A
+    when the candidate splits that bus) and the slack takes it up; generator
+    cases come after the branch contingencies and are reported as -2 - g;
   * agg_m covers N-0 and every valid N-1 case over the monitored branches;
     the overload sum adds max(0, |p|/r - 1) over the same set for the best
     variant; ties pick the lowest variant, then the lowest (outage, branch)
@@ -261,7 +267,7 @@ def control_terms(n2, f2, t2, alive, b, controls, ctrl):
     return dp, dflow
 
 
-def candidate_flows(n, f, t, b, slack, elems, x, out, controls=None, ctrl=None):
+def candidate_flows(n, f, t, b, slack, elems, x, out, controls=None, ctrl=None, gens=None):
     """N-0 flows and N-1 flows of a candidate, by rebuild + dense LU.
 
     Returns dict with
@@ -271,6 +277,9 @@ def candidate_flows(n, f, t, b, slack, elems, x, out, controls=None, ctrl=None):
       lodf [m, |O|]      LODF columns of the candidate network (Def. eq_lodf,
                          with LODF[c, c] = -1), zero for states 1 and 2;
       den [|O|]          LODF denominators 1 - (PTDF'[c, f_c] - PTDF'[c, t_c]);
+      gcol [m, G]        PTDF' column of each generator's bus (gens = (bus ids,
+                         outputs); G = 0 without gens): losing generator g
+                         changes the flows by -P_g gcol[:, g] (Eq. ptdf_delta);
       connected          False if the candidate network itself is islanded.
     """
     n2, f2, t2, alive, splits = rebuild(n, f, t, elems)
@@ -321,21 +330,34 @@ def candidate_flows(n, f, t, b, slack, elems, x, out, controls=None, ctrl=None):
         lodf[:, valid] = col / dd
         lodf[cs, valid] = -1.0
         den[valid] = dd
-    res.update(state=state, lodf=lodf, den=den)
+    gb = np.asarray([] if gens is None else gens[0], np.int64)
+    gcol = np.zeros((m, len(gb)))
+    if len(gb):
+        # unit injection at the generator's bus, taken up by the slack
+        e = np.zeros((n2, len(gb)))
+        e[gb, np.arange(len(gb))] = 1.0
+        th = np.zeros((n2, len(gb)))
+        th[keep] = sla.lu_solve(lu, e[keep])
+        gcol[alive] = ba[:, None] * (th[fa] - th[ta])
+    res.update(state=state, lodf=lodf, den=den, gcol=gcol)
     return res
 
 
-def n1_flows_bruteforce(n, f, t, b, slack, elems, x, out, controls=None, ctrl=None):
+def n1_flows_bruteforce(n, f, t, b, slack, elems, x, out, controls=None, ctrl=None, gens=None):
     """N-1 flows by rebuilding the candidate network without each contingency
     and solving again (one factorisation per case), controls included with the
-    model of control_terms on each post-contingency network.  Returns
-    (p1 [V, |O|, m], islanded [|O|])."""
+    model of control_terms on each post-contingency network; then, for each
+    generator outage of gens = (bus ids, outputs), the candidate network solved
+    with that output removed from its bus (the slack re-balances).  Returns
+    (p1 [V, |O| + G, m], islanded [|O| + G])."""
     n2, f2, t2, alive, splits = rebuild(n, f, t, elems)
     p = candidate_injections(n2, x, splits, slack)
     m = len(f2)
     out = np.asarray(out, np.int64)
-    p1 = np.zeros((p.shape[0], len(out), m))
-    isl = np.zeros(len(out), bool)
+    gb = np.asarray([] if gens is None else gens[0], np.int64)
+    gp = np.asarray([] if gens is None else gens[1], np.float64)
+    p1 = np.zeros((p.shape[0], len(out) + len(gb), m))
+    isl = np.zeros(len(out) + len(gb), bool)
     keep = _keep(n2, slack)
     for ci, c in enumerate(out):
         al = alive.copy()
@@ -354,11 +376,33 @@ def n1_flows_bruteforce(n, f, t, b, slack, elems, x, out, controls=None, ctrl=No
         p1[:, ci, al] = ba * (theta[:, fa] - theta[:, ta])
         if dflow is not None:
             p1[:, ci, :] += dflow
+    if len(gb):
+        fa, ta, ba = f2[alive], t2[alive], np.asarray(b)[alive]
+        if not connected(n2, fa, ta):
+            isl[len(out):] = True
+            return p1, isl
+        br = nodal_susceptance(n2, fa, ta, ba)[np.ix_(keep, keep)]
+        pc, dflow = p, None
+        if controls is not None:
+            dp, dflow = control_terms(n2, f2, t2, alive, np.asarray(b), controls, ctrl)
+            pc = p + dp
+        for gi in range(len(gb)):
+            pg = pc.copy()
+            pg[:, gb[gi]] -= gp[gi]
+            pg[:, slack] = 0.0
+            pg[:, slack] = -pg.sum(axis=1)
+            theta = np.zeros((p.shape[0], n2))
+            theta[:, keep] = sla.solve(br, pg[:, keep].T).T
+            p1[:, len(out) + gi, alive] = ba * (theta[:, fa] - theta[:, ta])
+            if dflow is not None:
+                p1[:, len(out) + gi, :] += dflow
     return p1, isl
 
 
-def score_candidate(n, f, t, b, slack, elems, x, mon, out, rating, controls=None, ctrl=None):
-    """Score one candidate over its injection variants (Sec. III-A).
+def score_candidate(n, f, t, b, slack, elems, x, mon, out, rating, controls=None, ctrl=None,
+                    gens=None):
+    """Score one candidate over its injection variants (Sec. III-A); gens =
+    (bus ids, outputs) adds the generator-outage N-1 cases (Sec. III-C step 8d).
 
     Returns dict(max_load [V], best_variant, best_max_load, overload_sum,
     worst_branch, worst_outage, n_island, status)."""
@@ -369,7 +413,7 @@ def score_candidate(n, f, t, b, slack, elems, x, mon, out, rating, controls=None
         # the N-1 step below superposes the LODF on the N-0 flows, which holds for a
         # fixed phase shift only while the tripped branch carries none
         assert not set(int(c) for c in out) & set(int(l) for l in controls.get("pst", []))
-    cf = candidate_flows(n, f, t, b, slack, elems, x, out, controls, ctrl)
+    cf = candidate_flows(n, f, t, b, slack, elems, x, out, controls, ctrl, gens)
     nv = np.atleast_2d(x).shape[0]
     if not cf["connected"]:
         return dict(max_load=np.full(nv, np.inf), best_variant=-1, best_max_load=np.inf,
@@ -381,24 +425,31 @@ def score_candidate(n, f, t, b, slack, elems, x, mon, out, rating, controls=None
     scored = np.flatnonzero(state != 2)
     # N-1 flows on the monitored rows: p1[v, c, l] = p0[v, l] + LODF[l, c] p0[v, c]
     p1 = p0[:, None, mon] + lodf[mon][:, scored].T[None, :, :] * p0[:, out[scored]][:, :, None]
+    case_ids = out[scored]
+    if gens is not None and len(gens[0]):
+        # generator g lost: p0 - P_g PTDF'[:, bus_g] (Eq. ptdf_delta)
+        gp = np.asarray(gens[1], np.float64)
+        pg = p0[:, None, mon] - gp[None, :, None] * cf["gcol"][mon].T[None, :, :]
+        p1 = np.concatenate([p1, pg], axis=1)
+        case_ids = np.concatenate([case_ids, -2 - np.arange(len(gp))])
     load0 = np.abs(p0[:, mon]) / r
     load1 = np.abs(p1) / r
     maxl = load0.max(axis=1)
-    if len(scored):
+    if p1.shape[1]:
         maxl = np.maximum(maxl, load1.reshape(nv, -1).max(axis=1))
     best = int(np.argmin(maxl))
     allload = np.concatenate([load0[best][None, :], load1[best]], axis=0)
     ov = float(np.maximum(allload - 1.0, 0.0).sum())
     flat = int(np.argmax(allload))
     ci, li = divmod(flat, len(mon))
-    worst_out = -1 if ci == 0 else int(out[scored[ci - 1]])
+    worst_out = -1 if ci == 0 else int(case_ids[ci - 1])
     status = 0
     if not np.all(np.isfinite(maxl)):
         status |= ST_NONFINITE
     return dict(max_load=maxl, best_variant=best, best_max_load=float(maxl[best]),
                 overload_sum=ov, worst_branch=int(mon[li]), worst_outage=worst_out,
                 n_island=int((state == 2).sum()), status=status, flows=cf,
-                loads_best=allload, scored_out=out[scored])
+                loads_best=allload, scored_out=case_ids)
 
 
 def worst_cases(sc, mon, out, k):
@@ -406,8 +457,8 @@ def worst_cases(sc, mon, out, k):
     the details are produced for t_i* only): the k largest relative loads over
     the monitored branches in N-0 and in every scored N-1 case, as a list of
     (load, branch, outage) with outage -1 for N-0.  Order: load descending, ties
-    by case (N-0 first, then contingencies in the order of `out`), then by the
-    branch's position in `mon`.  `sc` is a result of score_candidate; a
+    by case (N-0 first, then contingencies in the order of `out`, then generator
+    outages), then by the branch's position in `mon`.  `sc` is a result of score_candidate; a
     disconnected candidate has no entries."""
     if sc["best_variant"] < 0:
         return []
@@ -415,6 +466,8 @@ def worst_cases(sc, mon, out, k):
     out = np.asarray(out, np.int64)
     loads = sc["loads_best"]               # [1 + n_scored, n_mon]
     pos = {int(o): i for i, o in enumerate(out)}
+    # generator g (id -2 - g) ranks after every branch contingency
+    pos.update({int(o): len(out) - 2 - int(o) for o in sc["scored_out"] if o <= -2})
     cases = np.asarray([-1] + [int(o) for o in sc["scored_out"]], np.int64)
     # ordering key of every entry: the branch's position for N-0, else
     # (position of the contingency in `out` + 1) * n_mon + position
@@ -444,5 +497,5 @@ def score_workload(w, idx=None, rating=None):
     for i in idx:
         x = w.inj if w.inj_shared else w.inj[i]
         res.append(score_candidate(g.n_bus, g.f, g.t, g.b, g.slack, w.cands.elements(int(i)),
-                                   x, w.mon, w.out, rating))
+                                   x, w.mon, w.out, rating, gens=getattr(w, "gens", None)))
     return res, rating

@@ -76,6 +76,14 @@ int check_grid(const dcflow_grid_desc *g) {
       if (i < 0 || i >= g->n_bus || j < 0 || j >= g->n_bus || i == j) return DCFLOW_E_SHAPE;
     }
   }
+  if (g->n_gen_out < 0) return DCFLOW_E_SHAPE;
+  if (g->n_gen_out > 0) {
+    if (!g->gen_bus || !g->gen_p) return DCFLOW_E_ARG;
+    for (int q = 0; q < g->n_gen_out; ++q) {
+      if (g->gen_bus[q] < 0 || g->gen_bus[q] >= g->n_bus) return DCFLOW_E_SHAPE;
+      if (!std::isfinite(g->gen_p[q])) return DCFLOW_E_ARG;
+    }
+  }
   if (g->rating) {
     for (int i = 0; i < g->n_mon; ++i)
       if (!finite_pos(g->rating[i])) return DCFLOW_E_ARG;
@@ -104,7 +112,7 @@ bool grid_connected(const dcflow_grid_desc *g) {
 }
 
 struct Dims {
-  int n, m, n_mon, n_out, n_er, ld_h, ld_er, ld_o, mon_pad, n_ctrl;
+  int n, m, n_mon, n_out, n_gen, n_er, ld_h, ld_er, ld_o, mon_pad, n_ctrl;
 };
 
 Dims grid_dims(const dcflow_grid_desc *g) {
@@ -113,6 +121,7 @@ Dims grid_dims(const dcflow_grid_desc *g) {
   d.m = g->n_branch;
   d.n_mon = g->n_mon;
   d.n_out = g->n_out;
+  d.n_gen = g->n_gen_out;
   std::vector<uint8_t> inmon(d.m, 0);
   for (int i = 0; i < g->n_mon; ++i) inmon[g->mon[i]] = 1;
   int extra = 0;
@@ -121,7 +130,7 @@ Dims grid_dims(const dcflow_grid_desc *g) {
   d.n_ctrl = g->n_pst + g->n_hvdc;
   d.ld_h = round_up(d.n + d.n_ctrl, 16);
   d.ld_er = round_up(d.n_er, 128);
-  d.ld_o = std::max(64, round_up(d.n_out, 64));
+  d.ld_o = std::max(64, round_up(d.n_out + d.n_gen, 64));
   d.mon_pad = round_up(d.n_mon, 64);
   return d;
 }
@@ -138,8 +147,9 @@ void plan_layout(dcflow_plan *p, const Dims &d, Arena &a) {
   p->d_er = a.take<int32_t>(d.n_er);
   p->d_pos_of_br = a.take<int32_t>(d.m);
   p->d_out_pos = a.take<int32_t>(d.n_out);
-  p->d_out_f = a.take<int32_t>(d.n_out);
-  p->d_out_t = a.take<int32_t>(d.n_out);
+  p->d_out_f = a.take<int32_t>(d.n_out + d.n_gen);
+  p->d_out_t = a.take<int32_t>(d.n_out + d.n_gen);
+  p->d_gen_y = a.take<double>(std::max(d.n_gen, 1));
   p->d_binv = a.take<double>((size_t)d.ld_h * d.ld_h);
   p->d_piv = a.take<double>(4 * (size_t)d.ld_h);
   p->d_hb = a.take<double>((size_t)d.m * d.ld_h);
@@ -338,6 +348,7 @@ int dcflow_build_ptdf(const dcflow_grid_desc *g, void *dev_ws, size_t ws_bytes, 
   p->slack = g->slack;
   p->n_mon = d.n_mon;
   p->n_out = d.n_out;
+  p->n_gen = d.n_gen;
   p->n_er = d.n_er;
   p->ld_h = d.ld_h;
   p->ld_er = d.ld_er;
@@ -363,8 +374,14 @@ int dcflow_build_ptdf(const dcflow_grid_desc *g, void *dev_ws, size_t ws_bytes, 
   std::vector<int32_t> er(g->mon, g->mon + d.n_mon);
   p->pos_of_br.assign(d.m, -1);
   for (int i = 0; i < d.n_mon; ++i) p->pos_of_br[g->mon[i]] = i;
-  std::vector<int32_t> out_pos(std::max(d.n_out, 1), 0), of(std::max(d.n_out, 1), 0),
-      ot(std::max(d.n_out, 1), 0);
+  std::vector<int32_t> out_pos(std::max(d.n_out, 1), 0), of(std::max(d.n_out + d.n_gen, 1), 0),
+      ot(std::max(d.n_out + d.n_gen, 1), 0);
+  std::vector<double> gen_y(std::max(d.n_gen, 1), 0.0);
+  for (int q = 0; q < d.n_gen; ++q) {  // generator column: PTDF[:, bus], coefficient -P_g
+    of[d.n_out + q] = g->gen_bus[q];
+    ot[d.n_out + q] = -1;
+    gen_y[q] = -g->gen_p[q];
+  }
   p->is_out.assign(d.m, 0);
   for (int c = 0; c < d.n_out; ++c) {
     int l = g->out[c];
@@ -414,6 +431,7 @@ int dcflow_build_ptdf(const dcflow_grid_desc *g, void *dev_ws, size_t ws_bytes, 
       up(p->d_out_pos, out_pos.data(), 4 * out_pos.size()) != hipSuccess ||
       up(p->d_out_f, of.data(), 4 * of.size()) != hipSuccess ||
       up(p->d_out_t, ot.data(), 4 * ot.size()) != hipSuccess ||
+      up(p->d_gen_y, gen_y.data(), 8 * gen_y.size()) != hipSuccess ||
       up(p->d_pbase, pb.data(), 8 * pb.size()) != hipSuccess ||
       (d.n_ctrl > 0 && (up(p->d_ctl_a, ca.data(), 4 * ca.size()) != hipSuccess ||
                         up(p->d_ctl_c, cc.data(), 4 * cc.size()) != hipSuccess ||
@@ -439,6 +457,7 @@ int dcflow_plan_view_get(const dcflow_plan *p, dcflow_plan_view *v) {
   v->n_branch = p->m;
   v->n_mon = p->n_mon;
   v->n_out = p->n_out;
+  v->n_gen_out = p->n_gen;
   v->n_er = p->n_er;
   v->ld_h = p->ld_h;
   v->ld_o = p->ld_o;
@@ -754,7 +773,8 @@ int dcflow_n1_worst(dcflow_batch *b, const void *dev_flows, int32_t n_var, dcflo
   if (!prec_valid(prec)) return DCFLOW_E_ARG;
   if (!b->factored) return DCFLOW_E_ARG;
   if (b->flows_prec != prec || b->flows_nvar != n_var) return DCFLOW_E_ARG;
-  if (((int64_t)b->plan->n_out + 1) * b->plan->n_mon > 0x7fffffffLL) return DCFLOW_E_ARG;
+  if (((int64_t)b->plan->n_out + b->plan->n_gen + 1) * b->plan->n_mon > 0x7fffffffLL)
+    return DCFLOW_E_ARG;
   size_t need = 0;
   dcflow_n1_worst_workspace_bytes(b, top_k, &need);
   if (ws_bytes < need) return DCFLOW_E_WORKSPACE;

@@ -130,13 +130,18 @@ __global__ void k_copy_he(double *He, float *He32, __bf16 *Heb, int ld_h, const 
   }
 }
 
+// Contingency columns: PTDF[:, f_c] - PTDF[:, t_c] for a branch, PTDF[:, bus_g]
+// for a generator outage (ot = -1: the slack takes up the lost output).
 __global__ void k_hdo(double *hdo, int ld_o, const double *H, int ld_h, int m,
-                      const int32_t *of, const int32_t *ot, int n_out) {
+                      const int32_t *of, const int32_t *ot, int n_ctg) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   int l = blockIdx.y;
   if (c >= ld_o || l >= m) return;
   double v = 0.0;
-  if (c < n_out) v = H[(size_t)l * ld_h + of[c]] - H[(size_t)l * ld_h + ot[c]];
+  if (c < n_ctg) {
+    v = H[(size_t)l * ld_h + of[c]];
+    if (ot[c] >= 0) v -= H[(size_t)l * ld_h + ot[c]];
+  }
   hdo[(size_t)l * ld_o + c] = v;
 }
 
@@ -166,14 +171,17 @@ __global__ void k_rating(double *r, double *inv_r, int mon_pad, const int32_t *m
 }
 
 __global__ void k_lsd(double *lsd, int ld_o, const double *hdo, const int32_t *mon, int n_mon,
-                      const int32_t *out, int n_out, const double *inv_r, int mon_pad) {
+                      const int32_t *out, int n_out, int n_ctg, const double *inv_r,
+                      int mon_pad) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   int i = blockIdx.y;
   if (c >= ld_o || i >= mon_pad) return;
   double v = 0.0;
-  if (i < n_mon && c < n_out) {
+  if (i < n_mon && c < n_ctg) {
+    // a branch contingency's own row carries -1 (LODF[c, c] = -1); a generator
+    // column has no such entry
     int l = mon[i];
-    v = (hdo[(size_t)l * ld_o + c] - (l == out[c] ? 1.0 : 0.0)) * inv_r[i];
+    v = (hdo[(size_t)l * ld_o + c] - (c < n_out && l == out[c] ? 1.0 : 0.0)) * inv_r[i];
   }
   lsd[(size_t)i * ld_o + c] = v;
 }
@@ -254,7 +262,7 @@ hipError_t launch_build(dcflow_plan *p, hipStream_t s, const double *h_rating, d
                      p->d_he32, p->d_heb, ld, p->d_hb, p->d_er, p->n_er, p->ld_er);
   DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_hdo, dim3(nblk(p->ld_o, 256), m), dim3(256), 0, s, p->d_hdo, p->ld_o,
-                     p->d_hb, ld, m, p->d_out_f, p->d_out_t, p->n_out);
+                     p->d_hb, ld, m, p->d_out_f, p->d_out_t, p->n_out + p->n_gen);
   DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_fbase, dim3(nblk(m, 4)), dim3(256), 0, s, p->d_fbase, p->d_hb, ld,
                      p->d_pbase, m);
@@ -272,8 +280,8 @@ hipError_t launch_build(dcflow_plan *p, hipStream_t s, const double *h_rating, d
                      rscale, roffset);
   DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_lsd, dim3(nblk(p->ld_o, 256), p->mon_pad), dim3(256), 0, s, p->d_lsd,
-                     p->ld_o, p->d_hdo, p->d_mon, p->n_mon, p->d_out, p->n_out, p->d_inv_r,
-                     p->mon_pad);
+                     p->ld_o, p->d_hdo, p->d_mon, p->n_mon, p->d_out, p->n_out,
+                     p->n_out + p->n_gen, p->d_inv_r, p->mon_pad);
   DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_lsd32, dim3(nblk((size_t)p->mon_pad * p->ld_o / 4, 256)), dim3(256), 0, s,
                      p->d_lsd32, p->d_lsd, p->ld_o, p->mon_pad);

@@ -35,6 +35,7 @@ inline bool prec_valid(int prec) { return prec == DCFLOW_FP64 || prec_is_f32(pre
 // workspace.  All device matrices are row-major.
 struct dcflow_plan {
   int n, m, slack, n_mon, n_out, n_er;
+  int n_gen;   // generator outages: contingency columns n_out .. n_out + n_gen - 1
   int n_ctrl;  // control columns (phase shifters, then HVDC links)
   int n_inj;   // entries per injection vector: n + n_ctrl
   int ld_h;    // columns of Hb / Binv / He (n rounded up to 16, the GEMM K step)
@@ -45,7 +46,8 @@ struct dcflow_plan {
   // device arrays (all inside the workspace)
   int32_t *d_f, *d_t, *d_adj_off, *d_adj_br;
   double *d_b;
-  int32_t *d_mon, *d_out, *d_er, *d_pos_of_br, *d_out_pos, *d_out_f, *d_out_t;
+  int32_t *d_mon, *d_out, *d_er, *d_pos_of_br, *d_out_pos;
+  int32_t *d_out_f, *d_out_t;  // [n_out + n_gen] column terminals (generator: bus, -1)
   double *d_binv;   // [ld_h][ld_h] inverse of the slack-reduced Laplacian (slack row/col: unit)
   double *d_piv;    // [2][ld_h] pivot row/column scratch of the inversion
   double *d_hb;     // [m][ld_h] PTDF, all branches
@@ -53,7 +55,7 @@ struct dcflow_plan {
   double *d_he64;   // [ld_er][ld_h] kept rows of the PTDF, GEMM operand
   float *d_he32;    // [ld_er][ld_h] same in FP32
   __bf16 *d_heb;    // [3][ld_er][ld_h] same split into three BF16 parts (sum = FP64 value to ~2^-24)
-  double *d_hdo;    // [m][ld_o] PTDF[:, f_c] - PTDF[:, t_c]
+  double *d_hdo;    // [m][ld_o] PTDF[:, f_c] - PTDF[:, t_c]; generator columns PTDF[:, bus]
   double *d_lsd;    // [mon_pad][ld_o] (hdo[mon] - [mon == out]) / rating
   float *d_lsd32;   // same in FP32, fragment-major: 16 x 16 blocks [mon_pad/16][ld_o/16], each
                     // 64 lanes x 4 rows in the FP32 MFMA accumulator order (rows 4 (lane/16) + r)
@@ -65,6 +67,7 @@ struct dcflow_plan {
   // control column q of the PTDF: w_q (PTDF[:, a_q] - PTDF[:, c_q]) + d_q e_{br_q}
   int32_t *d_ctl_a, *d_ctl_c, *d_ctl_br;
   double *d_ctl_w, *d_ctl_d;
+  double *d_gen_y;  // [max(n_gen, 1)] N-1 coefficient of each generator column: -P_g
   // host copies used for validation and packing
   std::vector<int32_t> f, t, adj_off, adj_br, out, pos_of_br;
   std::vector<uint8_t> is_out;  // per branch: contingency?

@@ -21,6 +21,9 @@
 //   For a contingency c (post-change terminals) the LODF column of the changed
 //   grid is col_c = H_O[:, c] + U W[:, c], W = K^-1 R,
 //   R[i, c] = sigma_i . H_O[:, c] - pi_i . d_c, den_c = 1 - col_c[c].
+//   A generator outage (Eq. ptdf_delta, Sec. III-C step 8d) is one more column
+//   with H_O[:, g] = H e_bus and d_g = e_bus: col_g is the changed grid's PTDF
+//   column of the bus, with no denominator (1/den stored as 1).
 //
 // Outputs per candidate (element-major, no padding between uneven ranks):
 //   U [elem][ld_er], W [elem][ld_o], K^-1 (8 x 8), 1/den_c (0 for islanding
@@ -47,7 +50,8 @@ k_factors(const int32_t *__restrict__ order, const int32_t *__restrict__ off,
           const int32_t *__restrict__ adj_off, const int32_t *__restrict__ adj_br,
           const double *__restrict__ Hb, int ld_h, const double *__restrict__ Ht, int ld_er,
           int n_er, const double *__restrict__ hdo, int ld_o, const int32_t *__restrict__ out,
-          const int32_t *__restrict__ out_pos, int n_out, const int32_t *__restrict__ pos_of_br,
+          const int32_t *__restrict__ out_pos, int n_out, int n_ctg,
+          const int32_t *__restrict__ pos_of_br,
           int32_t *__restrict__ nsig_g, int32_t *__restrict__ sig_g, double *__restrict__ U,
           double *__restrict__ W, double *__restrict__ kinv_g, double *__restrict__ invden,
           uint32_t *__restrict__ isl, uint32_t *__restrict__ status) {
@@ -213,8 +217,10 @@ k_factors(const int32_t *__restrict__ order, const int32_t *__restrict__ off,
     double r[kMaxRank];
     double w[kMaxRank];
     bool removed = false;
-    if (c < n_out && !bad) {
-      int oc = out[c];
+    if (c < n_ctg && !bad) {
+      // generator column (c >= n_out): no branch of its own; the lost output is
+      // taken from busbar A, so the busbar-B term pi_i . d_c is zero as well
+      const int oc = c < n_out ? out[c] : -1;
       for (int i = 0; i < k; ++i) {
         const Elem &ei = E[i];
         double acc = 0.0;
@@ -247,6 +253,8 @@ k_factors(const int32_t *__restrict__ order, const int32_t *__restrict__ off,
       } else {
         inv = 1.0 / den;
       }
+    } else if (c >= n_out && c < n_ctg && !bad) {
+      inv = 1.0;  // generator outage: no denominator, never islanding
     }
     invden[(size_t)cand * ld_o + c] = inv;
     // islanding bits, one 32-bit word per 32 contingencies (ballot within the wave)
@@ -289,7 +297,8 @@ hipError_t launch_factors(dcflow_batch *bt, hipStream_t s) {
   hipLaunchKernelGGL(k_factors, dim3(bt->n_cand), dim3(256), 0, s, bt->d_order, bt->d_off,
                      bt->d_kind, bt->d_id, bt->d_mask, p->d_f, p->d_t, p->d_b, p->d_adj_off,
                      p->d_adj_br, p->d_hb, p->ld_h, p->d_ht, p->ld_er, p->n_er, p->d_hdo, p->ld_o,
-                     p->d_out, p->d_out_pos, p->n_out, p->d_pos_of_br, bt->d_nsig, bt->d_sig,
+                     p->d_out, p->d_out_pos, p->n_out, p->n_out + p->n_gen, p->d_pos_of_br,
+                     bt->d_nsig, bt->d_sig,
                      bt->d_U, bt->d_W, bt->d_kinv, bt->d_invden, bt->d_isl, bt->d_status);
   DCF_CHECK_LAUNCH();
   const size_t n_elem = bt->n_elem, tot = n_elem * (p->mon_pad + p->ld_o);

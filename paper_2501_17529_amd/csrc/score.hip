@@ -12,6 +12,10 @@
 //     L~ = (H_O[E_m, :] - [l == c]) / r  +  (U / r) W      (LODF' numerators, -den on the diagonal)
 //     y[c, v] = F'[c, v] / den_c                         (0 for islanding / removed c)
 //
+// Generator outages (step 8d, Eq. ptdf_delta) are further columns c >= n_out:
+// L~[:, c] is the changed grid's PTDF column of the generator's bus over r, and
+// y[c, v] = -P_g for every variant.
+//
 // L~ is built per 16 x 16 block on the matrix cores, with the shared seed Lsd as
 // the accumulator input, U/r as A and W as B (k <= 4: one MFMA, k <= 8: two).
 // The FP32 path seeds from an FP32 copy of Lsd stored in accumulator order (one
@@ -101,6 +105,8 @@ struct ScanArgs {
   int n_mon, mon_pad;
   const int32_t *out_pos;
   int n_out;
+  int n_ctg;              // n_out branch columns, then the generator columns
+  const double *gen_y;    // [n_ctg - n_out] -P_g of each generator column
   const int32_t *mon, *out;
   double *vmax;  // [n_cand][vmax_ld]
   int vmax_ld;
@@ -316,13 +322,24 @@ __device__ __forceinline__ T ftilde(const T *Fv, const double *inv_r, int row, i
   return (T)(fv * inv_r[row]);
 }
 
-// y = F'[c] / den_c
+// y = F'[c] / den_c for a branch column, -P_g for a generator column (times the
+// stored 1/den of 1, or 0 for a candidate whose correction failed)
 template <typename T>
 __device__ __forceinline__ T ycol(const T *Fv, const ScanArgs &A, int cand, int c, bool &nonfinite) {
-  if (c >= A.n_out) return (T)0;
+  if (c >= A.n_out) {
+    if (c >= A.n_ctg) return (T)0;
+    return (T)(A.gen_y[c - A.n_out] * A.invden[(size_t)cand * A.ld_o + c]);
+  }
   const double fv = (double)Fv[A.out_pos[c]];
   if (!finite_bits(fv)) nonfinite = true;
   return (T)(fv * A.invden[(size_t)cand * A.ld_o + c]);
+}
+
+// reported id of contingency column c: the branch id, -2 - g for generator g,
+// -1 for the N-0 case (c < 0)
+__device__ __forceinline__ int outage_id(const ScanArgs &A, int c) {
+  if (c < 0) return -1;
+  return c < A.n_out ? A.out[c] : -2 - (c - A.n_out);
 }
 
 // ---------------------------------------------------------------- pass 1
@@ -493,7 +510,7 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
   for (int c = tid; c < ld_o; c += blockDim.x) {
     ys[c] = ycol(Fv, A, cand, c, nf);
     const bool valid =
-        c < A.n_out && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
+        c < A.n_ctg && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
     colw[c] = valid ? (T)1 : (T)0;
   }
   const int r0 = band * A.band_rows, r1 = min(r0 + A.band_rows, A.mon_pad);
@@ -715,7 +732,7 @@ __global__ void k_scan_fin(ScanArgs A) {
   r.overload_sum = ov;
   r.best_variant = best;
   r.worst_branch = found ? A.mon[row] : -1;
-  r.worst_outage = c >= 0 ? A.out[c] : -1;
+  r.worst_outage = outage_id(A, c);
   A.res[cand] = r;
   if (A.single) A.vmax[(size_t)cand * A.vmax_ld] = r.max_load;
 }
@@ -789,7 +806,7 @@ __device__ __forceinline__ void scan_worst_item(const ScanArgs &A, int cand, int
     for (int c = tid; c < ld_o; c += blockDim.x) {
       ys[c] = ycol(Fv, A, cand, c, nf);
       const bool valid =
-          c < A.n_out && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
+          c < A.n_ctg && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
       colw[c] = valid ? (T)1 : (T)0;
     }
     const int r0 = band * A.band_rows, r1 = min(r0 + A.band_rows, A.mon_pad);
@@ -968,7 +985,7 @@ __global__ void __launch_bounds__(64) k_worst_fin(ScanArgs A, dcflow_case *out) 
         const int c = n0 ? -1 : wk / A.n_mon - 1;
         e.load = wv;
         e.branch = A.mon[row];
-        e.outage = c >= 0 ? A.out[c] : -1;
+        e.outage = outage_id(A, c);
       }
       out[(size_t)cand * A.top_k + j] = e;
     }
@@ -1083,6 +1100,8 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   a.mon_pad = p->mon_pad;
   a.out_pos = p->d_out_pos;
   a.n_out = p->n_out;
+  a.n_ctg = p->n_out + p->n_gen;
+  a.gen_y = p->d_gen_y;
   a.mon = p->d_mon;
   a.out = p->d_out;
   a.vmax = bt->d_vmax;
@@ -1177,6 +1196,8 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   a.mon_pad = p->mon_pad;
   a.out_pos = p->d_out_pos;
   a.n_out = p->n_out;
+  a.n_ctg = p->n_out + p->n_gen;
+  a.gen_y = p->d_gen_y;
   a.mon = p->d_mon;
   a.out = p->d_out;
   a.vmax = nullptr;

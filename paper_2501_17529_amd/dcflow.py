@@ -51,7 +51,8 @@ class GridDesc(ctypes.Structure):
                 ("n_pst", ctypes.c_int32), ("pst_branch", ctypes.c_void_p),
                 ("pst_scale", ctypes.c_double), ("n_hvdc", ctypes.c_int32),
                 ("hvdc_from", ctypes.c_void_p), ("hvdc_to", ctypes.c_void_p),
-                ("hvdc_scale", ctypes.c_double)]
+                ("hvdc_scale", ctypes.c_double), ("n_gen_out", ctypes.c_int32),
+                ("gen_bus", ctypes.c_void_p), ("gen_p", ctypes.c_void_p)]
 
 
 class Cands(ctypes.Structure):
@@ -74,7 +75,7 @@ class PlanView(ctypes.Structure):
                 ("n_out", ctypes.c_int32), ("n_er", ctypes.c_int32), ("ld_h", ctypes.c_int32),
                 ("ld_o", ctypes.c_int32), ("ptdf", ctypes.c_void_p), ("hdo", ctypes.c_void_p),
                 ("f_base", ctypes.c_void_p), ("rating", ctypes.c_void_p), ("er", ctypes.c_void_p),
-                ("n_inj", ctypes.c_int32)]
+                ("n_inj", ctypes.c_int32), ("n_gen_out", ctypes.c_int32)]
 
 
 def _load():
@@ -169,10 +170,15 @@ class _GridArgs:
     """Keeps the host arrays of a grid description alive."""
 
     def __init__(self, n_bus, f, t, b, mon, out, p_base, slack=0, rating=None,
-                 rating_scale=1.2, rating_offset=0.1, controls=None):
+                 rating_scale=1.2, rating_offset=0.1, controls=None, gens=None):
         """controls: None or dict(pst=[branch ids], pst_scale=rad per unit,
-        hvdc=[(from bus, to bus)], hvdc_scale=p.u. per unit)."""
+        hvdc=[(from bus, to bus)], hvdc_scale=p.u. per unit).
+        gens: None or (bus ids, lost outputs) of the generator-outage N-1 cases."""
         c = controls or {}
+        gb, gp = ([], []) if gens is None else gens
+        self.gen_bus = _arr(gb, np.int32)
+        self.gen_p = _arr(gp, np.float64)
+        assert len(self.gen_bus) == len(self.gen_p)
         self.pst = _arr(c.get("pst", []), np.int32)
         hv = np.asarray(c.get("hvdc", []), np.int32).reshape(-1, 2)
         self.hv_from = _arr(hv[:, 0], np.int32)
@@ -193,7 +199,9 @@ class _GridArgs:
             float(c.get("pst_scale", np.pi / 180.0)), len(self.hv_from),
             self.hv_from.ctypes.data if len(self.hv_from) else None,
             self.hv_to.ctypes.data if len(self.hv_to) else None,
-            float(c.get("hvdc_scale", 1.0)))
+            float(c.get("hvdc_scale", 1.0)), len(self.gen_bus),
+            self.gen_bus.ctypes.data if len(self.gen_bus) else None,
+            self.gen_p.ctypes.data if len(self.gen_p) else None)
 
 
 class _CandArgs:
@@ -233,10 +241,11 @@ class Plan:
     """dcflow_build_ptdf: one-time FP64 base build on the current CUDA device."""
 
     def __init__(self, n_bus, f, t, b, mon, out, p_base, slack=0, rating=None,
-                 rating_scale=1.2, rating_offset=0.1, device="cuda", stream=None, controls=None):
+                 rating_scale=1.2, rating_offset=0.1, device="cuda", stream=None, controls=None,
+                 gens=None):
         import torch
         self.args = _GridArgs(n_bus, f, t, b, mon, out, p_base, slack, rating, rating_scale,
-                              rating_offset, controls)
+                              rating_offset, controls, gens)
         nbytes = ctypes.c_size_t(0)
         _check(_lib.dcflow_plan_workspace_bytes(ctypes.byref(self.args.desc), ctypes.byref(nbytes)),
                "dcflow_plan_workspace_bytes")
@@ -255,6 +264,7 @@ class Plan:
     def from_workload(cls, w, rating=None, **kw):
         g = w.grid
         kw.setdefault("controls", getattr(w, "controls", None))
+        kw.setdefault("gens", getattr(w, "gens", None))
         return cls(g.n_bus, g.f, g.t, g.b, w.mon, w.out, g.p, g.slack, rating,
                    w.rating_scale, w.rating_offset, **kw)
 
@@ -275,10 +285,13 @@ class Plan:
         return self._dev(v.ptdf, (v.n_branch, v.ld_h), torch.float64)[
             :, : (v.n_inj if controls else v.n_bus)]
 
-    def hdo(self):
+    def hdo(self, gens=False):
+        """Contingency columns [n_branch][n_out] (with gens=True also the generator
+        columns PTDF[:, bus_g], [n_branch][n_out + n_gen_out])."""
         import torch
         v = self.view
-        return self._dev(v.hdo, (v.n_branch, v.ld_o), torch.float64)[:, :v.n_out]
+        return self._dev(v.hdo, (v.n_branch, v.ld_o), torch.float64)[
+            :, :v.n_out + (v.n_gen_out if gens else 0)]
 
     def f_base(self):
         import torch

@@ -79,7 +79,7 @@ def compare(w, gpu, oracle_res, rating, idx, prec, check_flows=True):
         if s["best_variant"] == o["best_variant"]:
             loads = o["loads_best"]
             row = int(np.flatnonzero(np.asarray(w.mon) == s["worst_branch"])[0])
-            if s["worst_outage"] < 0:
+            if s["worst_outage"] == -1:    # N-0 (generator outages are -2 - g)
                 lv = loads[0, row]
             else:
                 cpos = np.flatnonzero(o["scored_out"] == s["worst_outage"])
@@ -107,9 +107,9 @@ def oracle_scores(w, idx, rating, variants=None):
         x = w.inj if w.inj_shared else w.inj[int(i)]
         if variants is not None:
             x = x[np.asarray(variants)]
-        kw = {}
+        kw = {"gens": getattr(w, "gens", None)}
         if getattr(w, "controls", None):
-            kw = dict(controls=w.controls, ctrl=x[:, g.n_bus:])
+            kw.update(controls=w.controls, ctrl=x[:, g.n_bus:])
             x = x[:, :g.n_bus]
         res.append(O.score_candidate(g.n_bus, g.f, g.t, g.b, g.slack, w.cands.elements(int(i)),
                                      x, w.mon, w.out, rating, **kw))

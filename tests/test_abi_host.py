@@ -96,6 +96,16 @@ def test_grid_validation_errors(d):
     with pytest.raises(d.DcflowError) as ei:
         d.validate_candidates(ga, w.cands)
     assert ei.value.code == -2
+    for gens, code in [(([3, g.n_bus], [0.5, 0.5]), -2),      # generator bus out of range
+                       (([3, -1], [0.5, 0.5]), -2),
+                       (([3, 4], [0.5, np.inf]), -1),          # non-finite lost output
+                       (([3, 4], [0.5, np.nan]), -1)]:
+        ga = d._GridArgs(g.n_bus, g.f, g.t, g.b, w.mon, w.out, g.p, gens=gens)
+        with pytest.raises(d.DcflowError) as ei:
+            d.validate_candidates(ga, w.cands)
+        assert ei.value.code == code, gens
+    ga = d._GridArgs(g.n_bus, g.f, g.t, g.b, w.mon, w.out, g.p, gens=([3, 3, 0], [0.5, 0.1, 2.0]))
+    d.validate_candidates(ga, w.cands)   # shared buses and the slack are allowed
 
 
 def test_library_binds_to_torch_hip_runtime():

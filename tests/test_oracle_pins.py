@@ -485,3 +485,88 @@ def test_per_variant_busbar_injections_match_fixed_ones():
         out_b = sum(cf["p0"][v][l] for l in range(len(f2)) if alive[l] and f2[l] == bnew) - \
             sum(cf["p0"][v][l] for l in range(len(f2)) if alive[l] and t2[l] == bnew)
         assert abs(out_b - pn[v]) < 1e-10
+
+
+# ------------------------------------------------------- generator outages
+
+def test_triangle_generator_outage_by_hand():
+    # unit susceptances; bus 1 injects 1, bus 2 is a net load of 0.5 that holds a
+    # 0.4 generator, the slack 0 another of 0.3.  N-0 = (1/2, 1/2, 0).  Losing the bus-2
+    # generator adds -0.4 PTDF[:, 2] = -0.4 (1/3, -1/3, 2/3): (11/30, 19/30, -4/15);
+    # losing the slack's changes nothing.  With ratings (1, 1/2, 1) the bus-2 case
+    # gives the maximum 19/15 on edge 1.
+    f = np.array([1, 1, 2])
+    t = np.array([0, 2, 0])
+    x = np.array([[-0.5, 1.0, -0.5]])
+    r = np.array([1.0, 0.5, 1.0])
+    gens = (np.array([0, 2]), np.array([0.3, 0.4]))
+    sc = O.score_candidate(3, f, t, np.ones(3), 0, [], x, np.arange(3), [], r, gens=gens)
+    np.testing.assert_allclose(sc["flows"]["gcol"][:, 1], [1 / 3, -1 / 3, 2 / 3], atol=1e-15)
+    np.testing.assert_allclose(sc["flows"]["gcol"][:, 0], 0.0, atol=0)
+    np.testing.assert_allclose(sc["loads_best"][2], [11 / 30, 19 / 15, 4 / 15], atol=1e-15)
+    assert sc["best_max_load"] == pytest.approx(19 / 15, abs=1e-14)
+    assert (sc["worst_branch"], sc["worst_outage"]) == (1, -3)
+    assert sc["overload_sum"] == pytest.approx(4 / 15, abs=1e-14)
+    got = O.worst_cases(sc, np.arange(3), np.zeros(0, np.int64), 6)
+    want = [(19 / 15, 1, -3), (1.0, 1, -1), (1.0, 1, -2), (0.5, 0, -1), (0.5, 0, -2),
+            (11 / 30, 0, -3)]
+    np.testing.assert_allclose([v for v, _, _ in got], [v for v, _, _ in want], atol=1e-14)
+    # the slack generator's case equals N-0 bit for bit, so the ties are ordered by case
+    assert [(b, o) for _, b, o in got] == [(b, o) for _, b, o in want]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_generator_outages_match_bruteforce(seed):
+    """-P_g PTDF'[:, bus] on the candidate network equals solving that network
+    again without the generator's output, for a generator at every bus (split
+    buses, whose generator stays on busbar A, and the slack included)."""
+    g, cands, rng = _mixed_workload(seed, n_cand=10)
+    x = G.perturbed_injections(g, rng, (2,), 0.3)
+    gens = (np.arange(g.n_bus), 0.2 + rng.uniform(0.0, 1.0, g.n_bus))
+    out = np.arange(0, g.n_branch, 7)
+    n_split = 0
+    for els in cands:
+        for k, (kind, d, m, _p) in enumerate(els):
+            if kind == G.KIND_SPLIT:
+                els[k] = (kind, d, m, float(rng.normal()))    # move some injection too
+                n_split += 1
+        cf = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, els, x, out, gens=gens)
+        if not cf["connected"]:
+            continue
+        p1b, isl = O.n1_flows_bruteforce(g.n_bus, g.f, g.t, g.b, g.slack, els, x, out, gens=gens)
+        assert not isl[len(out):].any()
+        pg = cf["p0"][:, None, :] - gens[1][None, :, None] * cf["gcol"].T[None]
+        np.testing.assert_allclose(pg, p1b[:, len(out):], atol=1e-10)
+        np.testing.assert_allclose(cf["gcol"][:, g.slack], 0.0, atol=0)
+    assert n_split > 0
+
+
+def test_generator_outages_in_the_score():
+    """The score's maximum covers the generator cases: it equals the largest load
+    over N-0, the non-islanding branch contingencies and the generator outages,
+    each taken from the brute-force re-solves; generator cases are reported as
+    -2 - g."""
+    w = G.workload_tiny(3)
+    g = w.grid
+    rng = np.random.default_rng(3)
+    gens = G.generator_outages(g, rng, 8)
+    assert len(gens[0]) == 8 and np.all(gens[1] > 0)
+    r = O.ratings(g.n_bus, g.f, g.t, g.b, g.slack, g.p, w.mon, 1.0, 0.05)
+    x = G.perturbed_injections(g, rng, (3,), 0.2)
+    n_gen_worst = 0
+    for i in range(12):
+        els = w.cands.elements(i)
+        sc = O.score_candidate(g.n_bus, g.f, g.t, g.b, g.slack, els, x, w.mon, w.out, r,
+                               gens=gens)
+        if sc["best_variant"] < 0:
+            continue
+        p1b, isl = O.n1_flows_bruteforce(g.n_bus, g.f, g.t, g.b, g.slack, els, x, w.out,
+                                         gens=gens)
+        p0 = sc["flows"]["p0"]
+        loads = [np.abs(p0[:, w.mon]) / r]
+        loads += [np.abs(p1b[:, c, w.mon]) / r for c in np.flatnonzero(~isl)]
+        want = np.max(np.stack(loads, 1), axis=(1, 2))
+        np.testing.assert_allclose(sc["max_load"], want, atol=1e-10)
+        n_gen_worst += sc["worst_outage"] <= -2
+        assert -2 - len(gens[0]) < sc["worst_outage"] < g.n_branch
+    assert n_gen_worst >= 1     # a generator case is the worst one at least once
