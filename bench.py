@@ -171,6 +171,79 @@ def run_path(D, torch, plan, w, prec, steps, warmup, tune=True, graph=True, pers
     return res
 
 
+def ti_sweep(sizes, n_cand, top_k, steps, prec):
+    """|T_i| sweep with the two running modes of the injection loop (synthetic
+    analogue of the paper's Fig. 2 comparison on the medium grid).  The candidates
+    stay fixed; variant v of a candidate regroups its split substations' injections
+    between the busbars (injection topologies) over shared nodal injections.
+      metric-first: per-variant maxima, t_i*, then agg_i (top_k worst cases) for
+                    t_i* only;
+      output-first: the same plus agg_i for every variant, one worst-case pass per
+                    variant (the winner's list included).
+    Prints one JSON line per |T_i|."""
+    import torch
+    import gridgen as G
+    from paper_2501_17529_amd import dcflow as D
+    w = G.workload_medium(0, n_cand=n_cand, n_var=1)
+    plan = D.Plan.from_workload(w)
+    n_out = len(w.out)
+    for nv in sizes:
+        rng = np.random.default_rng(100 + nv)
+        bt = D.Batch(plan, w.cands, nv)
+        pnv = torch.from_numpy(G.busbar_injection_topologies(w.grid, w.cands, rng, nv)).cuda()
+        bt.set_busbar_injections(pnv, nv)
+        x = torch.from_numpy(np.repeat(G.balanced(w.grid.p, w.grid.slack)[None], nv, 0)).cuda()
+        flows, _ = bt.flow_buffer(nv, prec)
+        sc = torch.empty(bt.n_cand * D.SCORE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        cases = torch.empty(bt.n_cand * top_k * D.CASE_DTYPE.itemsize, dtype=torch.uint8,
+                            device="cuda")
+
+        def front():
+            bt.eval_topologies()
+            bt.eval_injections(x, nv, True, prec, flows=flows)
+            bt.n1_score(flows, nv, prec, out=sc)
+
+        front()
+        torch.cuda.synchronize()
+        # score records naming each variant as the one to list (status kept, so
+        # disconnected candidates stay skipped)
+        per_v = []
+        for v in range(nv):
+            s_v = sc.clone()
+            iv = s_v.view(torch.int32).view(bt.n_cand, D.SCORE_DTYPE.itemsize // 4)
+            iv[:, 4] = torch.where(iv[:, 4] >= 0, v, iv[:, 4])
+            per_v.append(s_v)
+
+        def metric_first():
+            front()
+            bt.n1_worst(flows, nv, prec, sc, top_k, out=cases)
+
+        def output_first():
+            front()
+            for v in range(nv):
+                bt.n1_worst(flows, nv, prec, per_v[v], top_k, out=cases)
+
+        res = {}
+        for name, fn in (("metric_first", metric_first), ("output_first", output_first)):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                fn()
+            torch.cuda.synchronize()
+            res[name] = (time.perf_counter() - t0) / steps * 1e3
+        n_lf = bt.n_cand * nv * n_out
+        print(json.dumps({
+            "ti": nv, "candidates": bt.n_cand, "top_k": top_k, "prec": prec,
+            "metric_first_ms": res["metric_first"], "output_first_ms": res["output_first"],
+            "metric_first_loadflows_per_s": n_lf / (res["metric_first"] / 1e3),
+            "output_first_loadflows_per_s": n_lf / (res["output_first"] / 1e3),
+            "metric_first_us_per_injection": res["metric_first"] * 1e3 / (bt.n_cand * nv),
+            "output_first_us_per_injection": res["output_first"] * 1e3 / (bt.n_cand * nv),
+        }), flush=True)
+        del bt, flows, per_v, pnv, x
+
+
 WORKLOADS = {
     "medium": ("medium-1000bus: 1,000 buses / 1,600 branches, 4,096 candidates (1-3 bus splits + "
                "0-2 outages), 16 injection variants each, N-1 over 500 contingencies = monitored "
@@ -202,6 +275,9 @@ def main():
     ap.add_argument("--tune-cache", default="", metavar="PATH",
                     help="autotuner cache file: shapes found there are reused without a sweep "
                          "(so that a profiled run times the same launch shapes as the bench run)")
+    ap.add_argument("--ti-sweep", default="", metavar="SIZES",
+                    help="only run the |T_i| sweep, metric-first vs output-first, for the "
+                         "comma-separated numbers of injection topologies per candidate")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run three plain device copies of MIB MiB (HBM counter scale)")
     a = ap.parse_args()
@@ -220,6 +296,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 3}))
+        return
+
+    if a.ti_sweep:
+        ti_sweep([int(v) for v in a.ti_sweep.split(",")], a.cands or 512, 16, a.steps,
+                 "fp32" if a.prec == "all" else a.prec)
         return
 
     import gridgen as G
