@@ -131,6 +131,8 @@ class Workload:
     controls: Optional[dict] = None
     # generator-outage N-1 cases: None or (bus ids int32 [G], lost outputs float64 [G])
     gens: Optional[tuple] = None
+    # multi-outage N-1 cases: None or a list of branch-id lists (each within `out`)
+    multi: Optional[list] = None
 
     @property
     def n_var(self) -> int:
@@ -348,6 +350,28 @@ def generator_outages(grid: Grid, rng, n_gen: int):
     bus = np.sort(rng.choice(gen_buses, size=n_gen, replace=False)).astype(np.int32)
     pg = grid.p[bus] * rng.uniform(0.5, 1.0, size=n_gen)
     return bus, pg.astype(np.float64)
+
+
+def multi_outage_cases(grid: Grid, out, rng, n_cases: int, max_size: int = 4):
+    """Multi-outage N-1 cases drawn from the contingency list: half of them trip
+    2..max_size contingency branches at one bus (a busbar fault; when they are all
+    of the bus's branches the bus islands), the rest 2..max_size contingency
+    branches anywhere (common-mode outages).  Returns a list of branch-id lists."""
+    out = np.asarray(out, np.int64)
+    in_out = np.zeros(grid.n_branch, bool)
+    in_out[out] = True
+    buses = [a for a in range(grid.n_bus) if in_out[grid.incident(a)].sum() >= 2]
+    cases = []
+    while len(cases) < n_cases:
+        if len(cases) % 2 == 0 and buses:
+            a = int(rng.choice(buses))
+            inc = [int(l) for l in grid.incident(a) if in_out[l]]
+            k = int(rng.integers(2, min(max_size, len(inc)) + 1))
+            cases.append(sorted(int(x) for x in rng.choice(inc, size=k, replace=False)))
+        else:
+            k = int(rng.integers(2, max_size + 1))
+            cases.append(sorted(int(x) for x in rng.choice(out, size=k, replace=False)))
+    return cases
 
 
 # ------------------------------------------------------------- workloads

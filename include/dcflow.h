@@ -13,14 +13,17 @@
  *                           Eq. bsdf_application) and remedial outages
  *                           (Def. eq_modf), joined into one k x k solve, and
  *                           the LODF denominators of every contingency in the
- *                           changed grid (Def. eq_lodf).
+ *                           changed grid (Def. eq_lodf); for multi-outage N-1
+ *                           cases the inverse of each case's MODF system
+ *                           (step 5).
  *   dcflow_eval_injections  Sec. III-C injection module step 8a: post-change
  *                           N-0 flows F' = PTDF' P for every injection
  *                           variant (Eq. ptdf_times_nodal_inj).
- *   dcflow_n1_score         Steps 8b, 8d and 8e: N-1 flows p0 + LODF[:,c] p0[c]
- *                           (Eq. lodf_delta) and p0 - P_g PTDF'[:, bus_g] for
- *                           generator outages (Eq. ptdf_delta), reduced to
- *                           agg_m (maximum
+ *   dcflow_n1_score         Steps 8b-8e: N-1 flows p0 + LODF[:,c] p0[c]
+ *                           (Eq. lodf_delta), multi-outage cases through a
+ *                           per-case MODF (Def. eq_modf), and p0 - P_g
+ *                           PTDF'[:, bus_g] for generator outages (Eq.
+ *                           ptdf_delta), reduced to agg_m (maximum
  *                           relative load), t_i* = argmin over the variants,
  *                           then (metric-first, Sec. IV-B) the winner's
  *                           overload sum and worst (branch, contingency).
@@ -88,6 +91,7 @@ typedef enum {
 
 #define DCFLOW_MAX_RANK 8       /* elements per candidate                       */
 #define DCFLOW_MAX_SPLIT_DEG 32 /* incident branches of a splittable bus        */
+#define DCFLOW_MULTI_MAX 4      /* branches per multi-outage N-1 case           */
 
 /* Status bits of dcflow_score.status. */
 #define DCFLOW_ST_DISCONNECTED 0x1u /* candidate grid islanded: max_load=+inf  */
@@ -140,6 +144,18 @@ typedef struct {
   int32_t n_gen_out;
   const int32_t *gen_bus;      /* [n_gen_out] bus ids                            */
   const double *gen_p;         /* [n_gen_out] lost output (p.u.), finite         */
+  /* Multi-outage N-1 cases (optional: 0 and NULLs for none), such as a busbar
+   * or a three-winding transformer: case q trips the branches multi_br[
+   * multi_off[q]] .. multi_br[multi_off[q+1] - 1] together (Def. eq_modf; Sec.
+   * III-C branch-module step 5 and injection-module step 8c).  Each case has 1
+   * to DCFLOW_MULTI_MAX branches, distinct, each one of the n_out contingencies.
+   * A case that islands the candidate grid is excluded and counted like an
+   * islanding contingency; branches the candidate removed drop out of the case.
+   * Multi cases come after the generator outages in the case order and are
+   * reported with outage id -2 - n_gen_out - q. */
+  int32_t n_multi_out;
+  const int32_t *multi_off;    /* [n_multi_out + 1], multi_off[0] = 0            */
+  const int32_t *multi_br;     /* [multi_off[n_multi_out]] branch ids            */
 } dcflow_grid_desc;
 
 /* Topology candidates in CSR form (host pointers).  Candidate i owns
@@ -166,7 +182,8 @@ typedef struct {
   int32_t best_variant;  /* t_i* (lowest index on ties); -1 if disconnected     */
   int32_t worst_branch;  /* monitored branch id of the maximum                  */
   int32_t worst_outage;  /* contingency branch id of the maximum, -1 for N-0,
-                            -2 - g for generator outage g                       */
+                            -2 - g for generator outage g, -2 - n_gen_out - q
+                            for multi-outage case q                             */
   uint32_t status;       /* DCFLOW_ST_* bits, island count in bits 8..31       */
 } dcflow_score;
 
@@ -184,6 +201,7 @@ typedef struct {
   const int32_t *er;     /* [n_er] kept rows: E_m first, then O \ E_m          */
   int32_t n_inj;         /* entries per injection vector (n_bus + controls)    */
   int32_t n_gen_out;     /* generator outages (columns after the n_out ones)   */
+  int32_t n_multi_out;   /* multi-outage N-1 cases                             */
 } dcflow_plan_view;
 
 typedef struct dcflow_plan dcflow_plan;
@@ -271,7 +289,8 @@ typedef struct {
   double load;      /* |p| / rating; -1 for an unused entry                      */
   int32_t branch;   /* monitored branch id; -1 for an unused entry               */
   int32_t outage;   /* contingency branch id, -1 for the N-0 case (or unused),
-                       -2 - g for generator outage g                            */
+                       -2 - g for generator outage g, -2 - n_gen_out - q for
+                       multi-outage case q                                      */
 } dcflow_case;
 
 #define DCFLOW_WORST_MAX 16 /* most cases per candidate in one call */
@@ -284,14 +303,16 @@ int dcflow_n1_worst_workspace_bytes(const dcflow_batch *batch, int32_t top_k, si
  * loads of its winning variant over the monitored branches in N-0 and in every
  * scored N-1 case (islanding contingencies excluded, as in the score), ordered
  * by load descending, ties by case (N-0 first, then contingencies in the
- * order of the grid's list, then generator outages) and then by the branch's position in the monitored
+ * order of the grid's list, then generator outages, then multi-outage cases)
+ * and then by the branch's position in the monitored
  * list.  The winner is dev_scores[i].best_variant from a dcflow_n1_score call on
  * the same batch and flows (device array, read on the stream); the entry with
  * the largest load equals that call's (max_load, worst_branch, worst_outage).
  * Candidates that are disconnected or have non-finite flows, and entries past
  * the number of scored cases, are unused (load -1).  dev_ws: workspace of
  * dcflow_n1_worst_workspace_bytes bytes; dev_out: [n_cand][top_k] (device).
- * E_ARG for top_k outside 1..DCFLOW_WORST_MAX, or if (n_out + n_gen_out + 1) * n_mon
+ * E_ARG for top_k outside 1..DCFLOW_WORST_MAX, or if (n_out + n_gen_out +
+ * n_multi_out + 1) * n_mon
  * exceeds 2^31 - 1 (the case keys are 32-bit); E_WORKSPACE if ws_bytes is too
  * small. */
 int dcflow_n1_worst(dcflow_batch *batch, const void *dev_flows, int32_t n_var, dcflow_prec prec,

@@ -22,6 +22,9 @@ for topology optimization"):
   * Sec. II, Eq. ptdf_delta (flow change = PTDF times the injection change)
     and Sec. III-C step 8d: generator-outage N-1 cases, here by solving the
     candidate network again with the lost output removed.
+  * Def. eq_modf and Sec. III-C steps 5 and 8c: multi-outage N-1 cases (several
+    branches tripped together), here by solving the candidate network again
+    without all of them.
   * Sec. III-A, task definition: N-0 and N-1 flows over monitored branches,
     agg_m = maximum relative branch load, t_i* = argmin over the injection
     variants (Eq. solver_end_to_end).
@@ -37,6 +40,10 @@ Readings where the paper is silent:
   * a generator outage removes the generator's output from its bus (busbar A
     when the candidate splits that bus) and the slack takes it up; generator
     cases come after the branch contingencies and are reported as -2 - g;
+  * a multi-outage case that islands the candidate network is excluded and
+    counted with the islanding contingencies; branches the candidate removed
+    drop out of it; multi cases come after the generator outages and are
+    reported as -2 - G - q (G generator outages);
   * agg_m covers N-0 and every valid N-1 case over the monitored branches;
     the overload sum adds max(0, |p|/r - 1) over the same set for the best
     variant; ties pick the lowest variant, then the lowest (outage, branch)
@@ -399,10 +406,41 @@ def n1_flows_bruteforce(n, f, t, b, slack, elems, x, out, controls=None, ctrl=No
     return p1, isl
 
 
+def multi_outage_flows(n, f, t, b, slack, elems, x, cases, controls=None, ctrl=None):
+    """Flows of the candidate network with every branch of a case tripped
+    together (cases: lists of branch ids), by solving that network again; the
+    controls follow control_terms on it.  Returns (p [V, Q, m], islanded [Q])."""
+    n2, f2, t2, alive, splits = rebuild(n, f, t, elems)
+    p = candidate_injections(n2, x, splits, slack)
+    m = len(f2)
+    keep = _keep(n2, slack)
+    pm = np.zeros((p.shape[0], len(cases), m))
+    isl = np.zeros(len(cases), bool)
+    for qi, case in enumerate(cases):
+        al = alive.copy()
+        al[np.asarray(case, np.int64)] = False
+        fa, ta, ba = f2[al], t2[al], np.asarray(b)[al]
+        if not connected(n2, fa, ta):
+            isl[qi] = True
+            continue
+        br = nodal_susceptance(n2, fa, ta, ba)[np.ix_(keep, keep)]
+        pc, dflow = p, None
+        if controls is not None:
+            dp, dflow = control_terms(n2, f2, t2, al, np.asarray(b), controls, ctrl)
+            pc = p + dp
+        theta = np.zeros((p.shape[0], n2))
+        theta[:, keep] = sla.solve(br, pc[:, keep].T).T
+        pm[:, qi, al] = ba * (theta[:, fa] - theta[:, ta])
+        if dflow is not None:
+            pm[:, qi, :] += dflow
+    return pm, isl
+
+
 def score_candidate(n, f, t, b, slack, elems, x, mon, out, rating, controls=None, ctrl=None,
-                    gens=None):
+                    gens=None, multi=None):
     """Score one candidate over its injection variants (Sec. III-A); gens =
-    (bus ids, outputs) adds the generator-outage N-1 cases (Sec. III-C step 8d).
+    (bus ids, outputs) adds the generator-outage N-1 cases (Sec. III-C step 8d),
+    multi = [branch id lists] the multi-outage cases (steps 5 and 8c).
 
     Returns dict(max_load [V], best_variant, best_max_load, overload_sum,
     worst_branch, worst_outage, n_island, status)."""
@@ -432,6 +470,14 @@ def score_candidate(n, f, t, b, slack, elems, x, mon, out, rating, controls=None
         pg = p0[:, None, mon] - gp[None, :, None] * cf["gcol"][mon].T[None, :, :]
         p1 = np.concatenate([p1, pg], axis=1)
         case_ids = np.concatenate([case_ids, -2 - np.arange(len(gp))])
+    n_isl_multi = 0
+    if multi is not None and len(multi):
+        pm, isl_m = multi_outage_flows(n, f, t, b, slack, elems, x, multi, controls, ctrl)
+        okq = np.flatnonzero(~isl_m)
+        p1 = np.concatenate([p1, pm[:, okq][:, :, mon]], axis=1)
+        n_gen = 0 if gens is None else len(gens[0])
+        case_ids = np.concatenate([case_ids, -2 - n_gen - okq])
+        n_isl_multi = int(isl_m.sum())
     load0 = np.abs(p0[:, mon]) / r
     load1 = np.abs(p1) / r
     maxl = load0.max(axis=1)
@@ -448,7 +494,7 @@ def score_candidate(n, f, t, b, slack, elems, x, mon, out, rating, controls=None
         status |= ST_NONFINITE
     return dict(max_load=maxl, best_variant=best, best_max_load=float(maxl[best]),
                 overload_sum=ov, worst_branch=int(mon[li]), worst_outage=worst_out,
-                n_island=int((state == 2).sum()), status=status, flows=cf,
+                n_island=int((state == 2).sum()) + n_isl_multi, status=status, flows=cf,
                 loads_best=allload, scored_out=case_ids)
 
 
@@ -458,7 +504,7 @@ def worst_cases(sc, mon, out, k):
     the monitored branches in N-0 and in every scored N-1 case, as a list of
     (load, branch, outage) with outage -1 for N-0.  Order: load descending, ties
     by case (N-0 first, then contingencies in the order of `out`, then generator
-    outages), then by the branch's position in `mon`.  `sc` is a result of score_candidate; a
+    outages, then multi-outage cases), then by the branch's position in `mon`.  `sc` is a result of score_candidate; a
     disconnected candidate has no entries."""
     if sc["best_variant"] < 0:
         return []
@@ -466,7 +512,8 @@ def worst_cases(sc, mon, out, k):
     out = np.asarray(out, np.int64)
     loads = sc["loads_best"]               # [1 + n_scored, n_mon]
     pos = {int(o): i for i, o in enumerate(out)}
-    # generator g (id -2 - g) ranks after every branch contingency
+    # generator g (id -2 - g) ranks after every branch contingency, multi case q
+    # (id -2 - G - q) after every generator
     pos.update({int(o): len(out) - 2 - int(o) for o in sc["scored_out"] if o <= -2})
     cases = np.asarray([-1] + [int(o) for o in sc["scored_out"]], np.int64)
     # ordering key of every entry: the branch's position for N-0, else
@@ -497,5 +544,6 @@ def score_workload(w, idx=None, rating=None):
     for i in idx:
         x = w.inj if w.inj_shared else w.inj[i]
         res.append(score_candidate(g.n_bus, g.f, g.t, g.b, g.slack, w.cands.elements(int(i)),
-                                   x, w.mon, w.out, rating, gens=getattr(w, "gens", None)))
+                                   x, w.mon, w.out, rating, gens=getattr(w, "gens", None),
+                                   multi=getattr(w, "multi", None)))
     return res, rating

@@ -76,6 +76,23 @@ int check_grid(const dcflow_grid_desc *g) {
       if (i < 0 || i >= g->n_bus || j < 0 || j >= g->n_bus || i == j) return DCFLOW_E_SHAPE;
     }
   }
+  if (g->n_multi_out < 0) return DCFLOW_E_SHAPE;
+  if (g->n_multi_out > 0) {
+    if (!g->multi_off || !g->multi_br || g->multi_off[0] != 0) return DCFLOW_E_ARG;
+    std::vector<uint8_t> is_out(g->n_branch, 0);
+    for (int i = 0; i < g->n_out; ++i) is_out[g->out[i]] = 1;
+    for (int q = 0; q < g->n_multi_out; ++q) {
+      const int a = g->multi_off[q], b = g->multi_off[q + 1];
+      if (b - a < 1 || b - a > DCFLOW_MULTI_MAX) return DCFLOW_E_SHAPE;
+      for (int i = a; i < b; ++i) {
+        const int l = g->multi_br[i];
+        if (l < 0 || l >= g->n_branch || !is_out[l]) return DCFLOW_E_SHAPE;
+        for (int j = a; j < i; ++j)
+          if (g->multi_br[j] == l) return DCFLOW_E_SHAPE;
+      }
+    }
+    if (g->multi_off[g->n_multi_out] > 65535) return DCFLOW_E_SHAPE;  // sub-columns
+  }
   if (g->n_gen_out < 0) return DCFLOW_E_SHAPE;
   if (g->n_gen_out > 0) {
     if (!g->gen_bus || !g->gen_p) return DCFLOW_E_ARG;
@@ -112,7 +129,7 @@ bool grid_connected(const dcflow_grid_desc *g) {
 }
 
 struct Dims {
-  int n, m, n_mon, n_out, n_gen, n_er, ld_h, ld_er, ld_o, mon_pad, n_ctrl;
+  int n, m, n_mon, n_out, n_gen, n_multi, n_msub, n_er, ld_h, ld_er, ld_o, mon_pad, n_ctrl;
 };
 
 Dims grid_dims(const dcflow_grid_desc *g) {
@@ -122,6 +139,8 @@ Dims grid_dims(const dcflow_grid_desc *g) {
   d.n_mon = g->n_mon;
   d.n_out = g->n_out;
   d.n_gen = g->n_gen_out;
+  d.n_multi = g->n_multi_out;
+  d.n_msub = d.n_multi > 0 ? g->multi_off[d.n_multi] : 0;
   std::vector<uint8_t> inmon(d.m, 0);
   for (int i = 0; i < g->n_mon; ++i) inmon[g->mon[i]] = 1;
   int extra = 0;
@@ -150,6 +169,10 @@ void plan_layout(dcflow_plan *p, const Dims &d, Arena &a) {
   p->d_out_f = a.take<int32_t>(d.n_out + d.n_gen);
   p->d_out_t = a.take<int32_t>(d.n_out + d.n_gen);
   p->d_gen_y = a.take<double>(std::max(d.n_gen, 1));
+  p->d_moff = a.take<int32_t>(d.n_multi + 1);
+  p->d_mcol = a.take<int32_t>(std::max(d.n_msub, 1));
+  p->d_lsdm = a.take<double>((size_t)d.n_msub * d.mon_pad);
+  p->d_lsdm32 = a.take<float>((size_t)d.n_msub * d.mon_pad);
   p->d_binv = a.take<double>((size_t)d.ld_h * d.ld_h);
   p->d_piv = a.take<double>(4 * (size_t)d.ld_h);
   p->d_hb = a.take<double>((size_t)d.m * d.ld_h);
@@ -210,11 +233,14 @@ void batch_layout(dcflow_batch *b, const dcflow_plan *p, const BatchDims &d, Are
   b->xs_cols = std::min(nc * (size_t)d.vmax, cap);
   b->d_xs = a.take<__bf16>(3 * b->xs_cols * (size_t)b->ldx);
   b->d_queue = a.take<int32_t>(16);
-  const size_t np = nc * (size_t)(p->mon_pad / 64);
+  const size_t nmb = p->n_multi > 0 ? (p->n_mon + kMultiRows - 1) / kMultiRows : 0;
+  const size_t np = nc * (size_t)(p->mon_pad / 64 + nmb);
   b->d_part_m = a.take<double>(np);
   b->d_part_ov = a.take<double>(np);
   b->d_part_k = a.take<long long>(np);
   b->d_part_nf = a.take<int32_t>(np);
+  b->d_mcoef = a.take<double>(nc * (size_t)p->n_multi * 16);
+  b->d_mok = a.take<int32_t>(nc * (size_t)p->n_multi);
 }
 
 void pst_flags(const dcflow_grid_desc *g, std::vector<uint8_t> &br, std::vector<uint8_t> &bus) {
@@ -349,6 +375,8 @@ int dcflow_build_ptdf(const dcflow_grid_desc *g, void *dev_ws, size_t ws_bytes, 
   p->n_mon = d.n_mon;
   p->n_out = d.n_out;
   p->n_gen = d.n_gen;
+  p->n_multi = d.n_multi;
+  p->n_msub = d.n_msub;
   p->n_er = d.n_er;
   p->ld_h = d.ld_h;
   p->ld_er = d.ld_er;
@@ -394,6 +422,14 @@ int dcflow_build_ptdf(const dcflow_grid_desc *g, void *dev_ws, size_t ws_bytes, 
     of[c] = g->from[l];
     ot[c] = g->to[l];
   }
+  // multi-outage sub-columns: the contingency column of each branch of each case
+  std::vector<int32_t> moff(d.n_multi + 1, 0), mcol(std::max(d.n_msub, 1), 0);
+  {
+    std::vector<int32_t> col_of(d.m, -1);
+    for (int c = 0; c < d.n_out; ++c) col_of[g->out[c]] = c;
+    for (int q = 0; q <= d.n_multi && d.n_multi > 0; ++q) moff[q] = g->multi_off[q];
+    for (int i = 0; i < d.n_msub; ++i) mcol[i] = col_of[g->multi_br[i]];
+  }
   std::vector<double> pb(d.ld_h, 0.0);  // controls of the base case: 0
   std::copy(g->p_base, g->p_base + d.n, pb.begin());
   // control columns: phase shifter on l = f -> t: pst_scale b_l (e_f - e_t) injection pattern
@@ -432,6 +468,8 @@ int dcflow_build_ptdf(const dcflow_grid_desc *g, void *dev_ws, size_t ws_bytes, 
       up(p->d_out_f, of.data(), 4 * of.size()) != hipSuccess ||
       up(p->d_out_t, ot.data(), 4 * ot.size()) != hipSuccess ||
       up(p->d_gen_y, gen_y.data(), 8 * gen_y.size()) != hipSuccess ||
+      up(p->d_moff, moff.data(), 4 * moff.size()) != hipSuccess ||
+      up(p->d_mcol, mcol.data(), 4 * mcol.size()) != hipSuccess ||
       up(p->d_pbase, pb.data(), 8 * pb.size()) != hipSuccess ||
       (d.n_ctrl > 0 && (up(p->d_ctl_a, ca.data(), 4 * ca.size()) != hipSuccess ||
                         up(p->d_ctl_c, cc.data(), 4 * cc.size()) != hipSuccess ||
@@ -458,6 +496,7 @@ int dcflow_plan_view_get(const dcflow_plan *p, dcflow_plan_view *v) {
   v->n_mon = p->n_mon;
   v->n_out = p->n_out;
   v->n_gen_out = p->n_gen;
+  v->n_multi_out = p->n_multi;
   v->n_er = p->n_er;
   v->ld_h = p->ld_h;
   v->ld_o = p->ld_o;
@@ -530,6 +569,7 @@ int dcflow_batch_create(dcflow_plan *p, const dcflow_cands *c, int32_t n_var_max
   b->aux = nullptr;
   for (int i = 0; i <= kMaxStepChunks; ++i) b->step_ev[i] = nullptr;
   b->max_bands = p->mon_pad / 64;
+  b->nmb = p->n_multi > 0 ? (p->n_mon + kMultiRows - 1) / kMultiRows : 0;
   b->graph = nullptr;
   b->graph_exec = nullptr;
   {
@@ -760,7 +800,8 @@ int dcflow_n1_score(dcflow_batch *b, const void *dev_flows, int32_t n_var, dcflo
 int dcflow_n1_worst_workspace_bytes(const dcflow_batch *b, int32_t top_k, size_t *bytes) {
   if (!b || !bytes || top_k < 1 || top_k > DCFLOW_WORST_MAX) return DCFLOW_E_ARG;
   // one 16-byte entry (load, key) per case, band and candidate
-  *bytes = std::max<size_t>((size_t)b->n_cand * worst_bands(b->plan) * top_k * 16, 256);
+  *bytes = std::max<size_t>(
+      (size_t)b->n_cand * (worst_bands(b->plan) + b->nmb) * top_k * 16, 256);
   return DCFLOW_OK;
 }
 
@@ -773,7 +814,8 @@ int dcflow_n1_worst(dcflow_batch *b, const void *dev_flows, int32_t n_var, dcflo
   if (!prec_valid(prec)) return DCFLOW_E_ARG;
   if (!b->factored) return DCFLOW_E_ARG;
   if (b->flows_prec != prec || b->flows_nvar != n_var) return DCFLOW_E_ARG;
-  if (((int64_t)b->plan->n_out + b->plan->n_gen + 1) * b->plan->n_mon > 0x7fffffffLL)
+  if (((int64_t)b->plan->n_out + b->plan->n_gen + b->plan->n_multi + 1) * b->plan->n_mon >
+      0x7fffffffLL)
     return DCFLOW_E_ARG;
   size_t need = 0;
   dcflow_n1_worst_workspace_bytes(b, top_k, &need);

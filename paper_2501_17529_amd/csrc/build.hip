@@ -186,6 +186,18 @@ __global__ void k_lsd(double *lsd, int ld_o, const double *hdo, const int32_t *m
   lsd[(size_t)i * ld_o + c] = v;
 }
 
+// Seeds of the multi-outage sub-columns, each contiguous over the monitored rows
+// (the multi-outage scan reads one row per thread): lsdm[s][i] = lsd[i][mcol[s]].
+__global__ void k_lsd_multi(double *lsdm, float *lsdm32, const double *lsd, int ld_o,
+                            const int32_t *mcol, int n_msub, int mon_pad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sc = blockIdx.y;
+  if (i >= mon_pad || sc >= n_msub) return;
+  const double v = lsd[(size_t)i * ld_o + mcol[sc]];
+  lsdm[(size_t)sc * mon_pad + i] = v;
+  lsdm32[(size_t)sc * mon_pad + i] = (float)v;
+}
+
 // Control columns of the PTDF (phase-shifter and HVDC distribution factors):
 // column n + q of row l = w_q (PTDF[l, a_q] - PTDF[l, c_q]) + [l == br_q] d_q.
 __global__ void k_ctrl_cols(double *Hb, int ld_h, int m, int n, int n_ctrl, const int32_t *ca,
@@ -286,6 +298,12 @@ hipError_t launch_build(dcflow_plan *p, hipStream_t s, const double *h_rating, d
   hipLaunchKernelGGL(k_lsd32, dim3(nblk((size_t)p->mon_pad * p->ld_o / 4, 256)), dim3(256), 0, s,
                      p->d_lsd32, p->d_lsd, p->ld_o, p->mon_pad);
   DCF_CHECK_LAUNCH();
+  if (p->n_msub > 0) {
+    hipLaunchKernelGGL(k_lsd_multi, dim3(nblk(p->mon_pad, 256), p->n_msub), dim3(256), 0, s,
+                       p->d_lsdm, p->d_lsdm32, p->d_lsd, p->ld_o, p->d_mcol, p->n_msub,
+                       p->mon_pad);
+    DCF_CHECK_LAUNCH();
+  }
   return hipSuccess;
 }
 

@@ -17,6 +17,7 @@ constexpr int kWave = 64;
 constexpr int kMaxStepChunks = 16;  // most candidate chunks of the overlapped step
 constexpr size_t kXsMaxCols = size_t(1) << 20;  // columns of the BF16 split buffer
 constexpr double kIslandTol = 1e-9;   // |LODF denominator| below this: islanding
+constexpr int kMultiRows = 256;       // monitored rows per work item of the multi-outage scan
 constexpr double kSingularTol = 1e-10; // relative pivot threshold of the k x k solve
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
@@ -68,6 +69,13 @@ struct dcflow_plan {
   int32_t *d_ctl_a, *d_ctl_c, *d_ctl_br;
   double *d_ctl_w, *d_ctl_d;
   double *d_gen_y;  // [max(n_gen, 1)] N-1 coefficient of each generator column: -P_g
+  // multi-outage N-1 cases: case q owns sub-columns moff[q] .. moff[q+1]-1, each the
+  // contingency column of one of its branches
+  int n_multi, n_msub;
+  int32_t *d_moff;  // [n_multi + 1]
+  int32_t *d_mcol;  // [max(n_msub, 1)] contingency column of each sub-column
+  double *d_lsdm;   // [n_msub][mon_pad] seed Lsd of each sub-column, row-contiguous
+  float *d_lsdm32;  // same in FP32
   // host copies used for validation and packing
   std::vector<int32_t> f, t, adj_off, adj_br, out, pos_of_br;
   std::vector<uint8_t> is_out;  // per branch: contingency?
@@ -103,6 +111,10 @@ struct dcflow_batch {
   double *d_part_m, *d_part_ov;  // [n_cand][max_bands] band partials of the winner pass
   long long *d_part_k;
   int32_t *d_part_nf;
+  int nmb;          // row chunks of the multi-outage scan (0 without multi cases); the
+                    // band partials hold max_bands + nmb slots per candidate
+  double *d_mcoef;  // [n_cand][n_multi][16] -N^-1 of each multi case (z = coef p1_S)
+  int32_t *d_mok;   // [n_cand][n_multi] 1 = scored, 0 = islanding or failed candidate
   dcflow_tuning tune;
   hipStream_t aux;                 // second stream of the chunked step (default priority)
   hipEvent_t step_ev[dcflow::kMaxStepChunks + 1];  // fork points and the join of the chunked step

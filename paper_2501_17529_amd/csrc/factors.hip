@@ -291,6 +291,95 @@ k_frags(const double *__restrict__ U, int ld_er, const double *__restrict__ inv_
   }
 }
 
+namespace {
+
+// Branch-module step 5 for multi-outage N-1 cases.  With the LODF' numerator
+// columns n_j = col_{s_j} - e_{s_j} of the changed grid (col as above), tripping
+// the branch set S of a case gives p = p1 + sum_j n_j z_j with z = -N^-1 p1[S] and
+// N[i][j] = n_j[s_i]: the flows on every branch of S become zero (Def. eq_modf,
+// one system per case).  N singular: S islands the candidate grid.  A branch the
+// candidate already removed drops out (identity row and column of N, z_j = 0); a
+// branch whose single outage islands makes the whole case island.
+// One thread per (candidate, case); coef holds -N^-1 (row j: coefficients of z_j).
+__global__ void __launch_bounds__(64) k_multi_prep(
+    const int32_t *__restrict__ off, const double *__restrict__ U, int ld_er,
+    const double *__restrict__ W, int ld_o, const double *__restrict__ hdo,
+    const int32_t *__restrict__ out, const int32_t *__restrict__ out_pos,
+    const double *__restrict__ invden, const uint32_t *__restrict__ isl,
+    uint32_t *__restrict__ status, const int32_t *__restrict__ moff,
+    const int32_t *__restrict__ mcol, int n_multi, double *__restrict__ coef,
+    int32_t *__restrict__ mok) {
+  __shared__ int s_isl;
+  const int cand = blockIdx.x;
+  const int e0 = off[cand], k = off[cand + 1] - e0;
+  const uint32_t st = status[cand];
+  const bool bad = (st & (DCFLOW_ST_DISCONNECTED | DCFLOW_ST_SINGULAR)) != 0;
+  if (threadIdx.x == 0) s_isl = 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < n_multi; q += blockDim.x) {
+    const int a = moff[q], m = moff[q + 1] - a;
+    int col[DCFLOW_MULTI_MAX], pos[DCFLOW_MULTI_MAX];
+    bool rem[DCFLOW_MULTI_MAX];
+    bool island = false;
+    for (int j = 0; j < DCFLOW_MULTI_MAX; ++j) {
+      col[j] = j < m ? mcol[a + j] : 0;
+      pos[j] = out_pos[col[j]];
+      const bool ib = ((isl[(size_t)cand * (ld_o / 32) + col[j] / 32] >> (col[j] % 32)) & 1u) != 0;
+      rem[j] = j < m && !ib && invden[(size_t)cand * ld_o + col[j]] == 0.0;
+      island = island || (j < m && ib);
+    }
+    double A[DCFLOW_MULTI_MAX][2 * DCFLOW_MULTI_MAX];
+    bool ok = !bad && !island;
+    if (ok) {
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+          double v = i == j ? 1.0 : 0.0;
+          if (!rem[i] && !rem[j]) {
+            v = hdo[(size_t)out[col[i]] * ld_o + col[j]] - v;
+            for (int e = 0; e < k; ++e)
+              v += U[(size_t)(e0 + e) * ld_er + pos[i]] * W[(size_t)(e0 + e) * ld_o + col[j]];
+          }
+          A[i][j] = v;
+          A[i][m + j] = i == j ? 1.0 : 0.0;
+        }
+      // Gauss-Jordan with partial pivoting
+      for (int c = 0; c < m && ok; ++c) {
+        int pr = c;
+        for (int r = c + 1; r < m; ++r)
+          if (fabs(A[r][c]) > fabs(A[pr][c])) pr = r;
+        if (fabs(A[pr][c]) < kIslandTol) {
+          ok = false;
+          break;
+        }
+        if (pr != c)
+          for (int x = 0; x < 2 * m; ++x) {
+            const double t = A[c][x];
+            A[c][x] = A[pr][x];
+            A[pr][x] = t;
+          }
+        const double inv = 1.0 / A[c][c];
+        for (int x = 0; x < 2 * m; ++x) A[c][x] *= inv;
+        for (int r = 0; r < m; ++r) {
+          if (r == c) continue;
+          const double f = A[r][c];
+          for (int x = 0; x < 2 * m; ++x) A[r][x] -= f * A[c][x];
+        }
+      }
+      if (!ok) island = true;
+    }
+    if (!bad && island) atomicAdd(&s_isl, 1);
+    double *cq = coef + ((size_t)cand * n_multi + q) * 16;
+    for (int j = 0; j < DCFLOW_MULTI_MAX; ++j)
+      for (int i = 0; i < DCFLOW_MULTI_MAX; ++i)
+        cq[j * 4 + i] = (ok && j < m && i < m && !rem[j]) ? -A[j][m + i] : 0.0;
+    mok[(size_t)cand * n_multi + q] = ok ? 1 : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && s_isl > 0) status[cand] = st + ((uint32_t)s_isl << DCFLOW_ST_ISLAND_SHIFT);
+}
+
+}  // namespace
+
 hipError_t launch_factors(dcflow_batch *bt, hipStream_t s) {
   dcflow_plan *p = bt->plan;
   if (bt->n_cand == 0) return hipSuccess;
@@ -307,6 +396,13 @@ hipError_t launch_factors(dcflow_batch *bt, hipStream_t s) {
     k_frags<<<dim3((unsigned)nb), dim3(256), 0, s>>>(bt->d_U, p->ld_er, p->d_inv_r, p->mon_pad,
                                                      bt->d_W, p->ld_o, n_elem, bt->d_ur32,
                                                      bt->d_w32);
+    DCF_CHECK_LAUNCH();
+  }
+  if (p->n_multi > 0) {
+    k_multi_prep<<<dim3(bt->n_cand), dim3(64), 0, s>>>(
+        bt->d_off, bt->d_U, p->ld_er, bt->d_W, p->ld_o, p->d_hdo, p->d_out, p->d_out_pos,
+        bt->d_invden, bt->d_isl, bt->d_status, p->d_moff, p->d_mcol, p->n_multi, bt->d_mcoef,
+        bt->d_mok);
     DCF_CHECK_LAUNCH();
   }
   return hipSuccess;

@@ -130,7 +130,16 @@ struct ScanArgs {
   // worst-case lists (dcflow_n1_worst)
   const dcflow_score *scores;  // [n_cand] winners of a preceding n1_score
   int top_k;
-  WEntry *wpart;       // [n_cand][nbands][top_k] band lists of dcflow_n1_worst
+  WEntry *wpart;       // [n_cand][nbt][top_k] band lists of dcflow_n1_worst
+  // multi-outage N-1 cases (scanned apart, in row chunks of kMultiRows)
+  int n_multi;
+  const int32_t *moff, *mcol;   // case q: sub-columns moff[q] .. moff[q+1]-1
+  const double *lsdm;           // [n_msub][mon_pad] seeds
+  const float *lsdm32;
+  const double *mcoef;          // [n_cand][n_multi][16]
+  const int32_t *mok;           // [n_cand][n_multi]
+  int nmb;                      // row chunks per candidate (0: no multi cases)
+  int nbt;                      // partial slots per candidate: nbands row bands, then nmb chunks
 };
 
 constexpr int kQueueWin = 15;  // counter slot of pass 2
@@ -485,7 +494,7 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
   const int e0 = A.off[cand];
   const int k = A.off[cand + 1] - e0;
   const uint32_t st = A.status[cand];
-  const size_t pidx = (size_t)cand * A.nbands + band;
+  const size_t pidx = (size_t)cand * A.nbt + band;
   if (st & DCFLOW_ST_DISCONNECTED) return;  // k_scan_fin writes the record
 
   if (tid == 0) {
@@ -710,17 +719,18 @@ __global__ void k_scan_fin(ScanArgs A) {
       }
     }
   }
-  const double *pm = A.part_m + (size_t)cand * A.nbands;
-  const long long *pk = A.part_k + (size_t)cand * A.nbands;
+  const double *pm = A.part_m + (size_t)cand * A.nbt;
+  const long long *pk = A.part_k + (size_t)cand * A.nbt;
   double M = pm[0], ov = 0.0;
   int nf = 0;
-  for (int b = 0; b < A.nbands; ++b) {
+  // row bands, then the chunks of the multi-outage cases
+  for (int b = 0; b < A.nbt; ++b) {
     M = fmax(M, pm[b]);
-    ov += A.part_ov[(size_t)cand * A.nbands + b];
-    nf |= A.part_nf[(size_t)cand * A.nbands + b];
+    ov += A.part_ov[(size_t)cand * A.nbt + b];
+    nf |= A.part_nf[(size_t)cand * A.nbt + b];
   }
   long long key = kNoKey;
-  for (int b = 0; b < A.nbands; ++b)
+  for (int b = 0; b < A.nbt; ++b)
     if (pm[b] == M && pk[b] < key) key = pk[b];
   // a variant whose flows were not finite was given +inf by pass 1; the
   // winner's own non-finite flows make its maximum +inf
@@ -789,7 +799,7 @@ __device__ __forceinline__ void scan_worst_item(const ScanArgs &A, int cand, int
   const int e0 = A.off[cand];
   const int k = A.off[cand + 1] - e0;
   const dcflow_score sc = A.scores[cand];
-  WEntry *dst = A.wpart + ((size_t)cand * A.nbands + band) * A.top_k;
+  WEntry *dst = A.wpart + ((size_t)cand * A.nbt + band) * A.top_k;
   const bool skip = (sc.status & (DCFLOW_ST_DISCONNECTED | DCFLOW_ST_NONFINITE)) != 0 ||
                     sc.best_variant < 0 || sc.best_variant >= A.nvar;
   T lv[KM];
@@ -938,7 +948,7 @@ constexpr int kFinBandsPerLane = 8, kFinBands = 64 * kFinBandsPerLane;
 __global__ void __launch_bounds__(64) k_worst_fin(ScanArgs A, dcflow_case *out) {
   constexpr int kEmpty = 0x7fffffff;
   const int cand = blockIdx.x, lane = threadIdx.x;
-  const WEntry *base = A.wpart + (size_t)cand * A.nbands * A.top_k;
+  const WEntry *base = A.wpart + (size_t)cand * A.nbt * A.top_k;
   int pos[kFinBandsPerLane];
 #pragma unroll
   for (int q = 0; q < kFinBandsPerLane; ++q) pos[q] = 0;
@@ -948,7 +958,7 @@ __global__ void __launch_bounds__(64) k_worst_fin(ScanArgs A, dcflow_case *out) 
 #pragma unroll
     for (int q = 0; q < kFinBandsPerLane; ++q) {
       const int b = lane + 64 * q;
-      if (b < A.nbands && pos[q] < A.top_k) {
+      if (b < A.nbt && pos[q] < A.top_k) {
         const WEntry e = base[(size_t)b * A.top_k + pos[q]];
         if (e.k != kEmpty && better(e.v, e.k, bv, bk)) {
           bv = e.v;
@@ -988,6 +998,283 @@ __global__ void __launch_bounds__(64) k_worst_fin(ScanArgs A, dcflow_case *out) 
         e.outage = outage_id(A, c);
       }
       out[(size_t)cand * A.top_k + j] = e;
+    }
+  }
+}
+
+// ---------------------------------------------------------- multi-outage cases
+// Injection-module step 8c: the N-1 flows of multi-outage case q (branch set S,
+// m = |S| <= 4) for variant v are p~ = F~ + sum_j L~[:, c_j] z_j with z = coef_q
+// p1[S] (coef_q = -N^-1 from the branch module, c_j the contingency column of the
+// j-th branch).  One thread per monitored row builds the m entries L~[row, c_j] =
+// Lsd[row, c_j] + (U / r)[row, :] W[:, c_j] once per case and applies them to every
+// variant of the workgroup; the cases' z are staged in LDS, kMultiQC at a time.
+//   MODE 0: per-variant maxima merged into vmax (after pass 1, before pass 2);
+//   MODE 1: for v* (the argmin of vmax, as in pass 2) the chunk's maximum, its
+//           lowest key ((n_ctg + q + 1) n_mon + row) and overload sum, written to
+//           the partial slot nbands + chunk that k_scan_fin combines;
+//   MODE 2: for the winner of a score record the chunk's top-KM list, written
+//           to the worst-case slot nbands + chunk that k_worst_fin merges.
+// The N-0 rows are covered by the band passes.
+constexpr int kMultiQC = 32;  // cases staged per round
+constexpr int kMultiVC = 8;   // variants per workgroup of the maxima
+
+template <typename T>
+struct MultiOps;
+template <>
+struct MultiOps<double> {
+  static __device__ __forceinline__ double seed(const ScanArgs &A, int sc, int row) {
+    return A.lsdm[(size_t)sc * A.mon_pad + row];
+  }
+  static __device__ __forceinline__ double ur(const ScanArgs &A, int e, int row) {
+    return A.U[(size_t)e * A.ld_er + row] * A.inv_r[row];
+  }
+  static __device__ __forceinline__ double w(const ScanArgs &A, int e, int c) {
+    return A.W[(size_t)e * A.ld_o + c];
+  }
+};
+template <>
+struct MultiOps<float> {
+  static __device__ __forceinline__ float seed(const ScanArgs &A, int sc, int row) {
+    return A.lsdm32[(size_t)sc * A.mon_pad + row];
+  }
+  static __device__ __forceinline__ float ur(const ScanArgs &A, int e, int row) {
+    return A.ur32[(size_t)e * A.mon_pad + row];
+  }
+  static __device__ __forceinline__ float w(const ScanArgs &A, int e, int c) {
+    return A.w32[(size_t)e * A.ld_o + c];
+  }
+};
+
+template <typename T, int MODE, int KM>
+__global__ void __launch_bounds__(256) k_scan_multi(ScanArgs A) {
+  constexpr int VC = MODE == 0 ? kMultiVC : 1;
+  constexpr int QC = kMultiQC, MM = DCFLOW_MULTI_MAX;
+  constexpr long long kNoKey = 0x7fffffffffffffffLL;
+  constexpr int kEmpty = 0x7fffffff;
+  __shared__ T zs[QC][VC][MM];
+  __shared__ int s_m[QC], s_a[QC];
+  __shared__ double s_red[4][VC];
+  __shared__ double s_ov[4];
+  __shared__ long long s_key[4];
+  __shared__ T s_bv[4];
+  __shared__ int s_bk[4];
+  __shared__ int s_vstar;
+
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+  const int local = blockIdx.x / A.nmb, chunk = blockIdx.x - local * A.nmb;
+  const int cand = A.cand0 + local;
+  const int e0 = A.off[cand], k = A.off[cand + 1] - e0;
+  const int row = chunk * kMultiRows + tid;
+  const bool has_row = row < A.n_mon;
+  const uint32_t st = A.status[cand];
+  const int vbeg = MODE == 0 ? blockIdx.y * VC : 0;
+  const int nv = MODE == 0 ? min(VC, A.nvar - vbeg) : 1;
+  const size_t slot = (size_t)cand * A.nbt + A.nbands + chunk;
+
+  // the variant of MODE 1 and 2; skip = nothing to scan (the slot still gets
+  // an empty partial, so that the merges never read stale values)
+  bool skip = (st & DCFLOW_ST_DISCONNECTED) != 0;
+  if (MODE == 2) {
+    const dcflow_score sc = A.scores[cand];
+    skip = skip || (sc.status & DCFLOW_ST_NONFINITE) != 0 || sc.best_variant < 0 ||
+           sc.best_variant >= A.nvar;
+    if (tid == 0) s_vstar = skip ? 0 : sc.best_variant;
+  } else if (MODE == 1 && tid == 0) {
+    int best = 0;
+    if (!A.single) {
+      double bv = A.vmax[(size_t)cand * A.vmax_ld];
+      for (int v = 1; v < A.nvar; ++v) {
+        const double x = A.vmax[(size_t)cand * A.vmax_ld + v];
+        if (x < bv) {
+          bv = x;
+          best = v;
+        }
+      }
+    }
+    s_vstar = best;
+  }
+  if (MODE == 0 && skip) return;  // pass 1 gave the disconnected candidate +inf
+  __syncthreads();
+  const int v0 = MODE == 0 ? vbeg : s_vstar;
+
+  T fv[VC];
+  T ur[kMaxRank];
+#pragma unroll
+  for (int i = 0; i < VC; ++i) {
+    fv[i] = (T)0;
+    if (!skip && has_row && i < nv) {
+      bool nf = false;
+      fv[i] = ftilde(static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + v0 + i) * A.ld_f,
+                     A.inv_r, row, A.n_mon, nf);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kMaxRank; ++e)
+    ur[e] = (!skip && has_row && e < k) ? MultiOps<T>::ur(A, e0 + e, row) : (T)0;
+
+  T mx[VC];
+#pragma unroll
+  for (int i = 0; i < VC; ++i) mx[i] = (T)-1;
+  long long bkey = kNoKey;
+  double ov = 0.0;
+  T lv[KM];
+  int lk[KM];
+#pragma unroll
+  for (int j = 0; j < KM; ++j) {
+    lv[j] = (T)-1;
+    lk[j] = kEmpty;
+  }
+  const int n_ctg = A.n_ctg;
+  for (int q0 = 0; q0 < A.n_multi && !skip; q0 += QC) {
+    __syncthreads();
+    // z of the round's cases for the workgroup's variants
+    for (int i = tid; i < QC * VC; i += blockDim.x) {
+      const int qq = i / VC, vi = i - qq * VC, q = q0 + qq;
+      const bool live = q < A.n_multi && vi < nv && A.mok[(size_t)cand * A.n_multi + q] != 0;
+      const int a = live ? A.moff[q] : 0, m = live ? A.moff[q + 1] - a : 0;
+      double p1s[MM];
+      const T *Fv =
+          static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + v0 + (live ? vi : 0)) * A.ld_f;
+#pragma unroll
+      for (int j = 0; j < MM; ++j)
+        p1s[j] = j < m ? (double)Fv[A.out_pos[A.mcol[a + j]]] : 0.0;
+      const double *cq = A.mcoef + ((size_t)cand * A.n_multi + (live ? q : 0)) * 16;
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        double z = 0.0;
+#pragma unroll
+        for (int t = 0; t < MM; ++t) z += live ? cq[j * 4 + t] * p1s[t] : 0.0;
+        zs[qq][vi][j] = (T)z;
+      }
+      if (vi == 0) {
+        s_m[qq] = live ? m : 0;
+        s_a[qq] = a;
+      }
+    }
+    __syncthreads();
+    if (!has_row) continue;
+    const int qn = min(QC, A.n_multi - q0);
+    for (int qq = 0; qq < qn; ++qq) {
+      const int m = s_m[qq];
+      if (m == 0) continue;
+      const int a = s_a[qq];
+      T lt[MM];
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        lt[j] = (T)0;
+        if (j < m) {
+          const int sc = a + j, c = A.mcol[sc];
+          T acc = MultiOps<T>::seed(A, sc, row);
+#pragma unroll
+          for (int e = 0; e < kMaxRank; ++e)
+            if (e < k) acc = tfma(ur[e], MultiOps<T>::w(A, e0 + e, c), acc);
+          lt[j] = acc;
+        }
+      }
+      const int q = q0 + qq;
+#pragma unroll
+      for (int vi = 0; vi < VC; ++vi) {
+        T p = fv[vi];
+#pragma unroll
+        for (int j = 0; j < MM; ++j) p = tfma(lt[j], zs[qq][vi][j], p);
+        const T ap = tabs(p);
+        if (MODE == 0) {
+          mx[vi] = tmax(mx[vi], ap);
+        } else if (MODE == 1) {
+          if (ap > mx[0]) {  // cases in increasing order: the first hit has the lowest key
+            mx[0] = ap;
+            bkey = (long long)(n_ctg + q + 1) * A.n_mon + row;
+          }
+          ov += fmax((double)ap - 1.0, 0.0);
+        } else {
+          const int key = (n_ctg + q + 1) * A.n_mon + row;
+          if (better(ap, key, lv[KM - 1], lk[KM - 1])) list_insert(lv, lk, ap, key);
+        }
+      }
+    }
+  }
+
+  if (MODE == 0) {
+#pragma unroll
+    for (int i = 0; i < VC; ++i) {
+      const T m = wave_max(mx[i]);
+      if (lane == 0) s_red[wv][i] = (double)m;
+    }
+    __syncthreads();
+    if (tid < nv) {
+      const double m = fmax(fmax(s_red[0][tid], s_red[1][tid]), fmax(s_red[2][tid], s_red[3][tid]));
+      if (m >= 0.0) global_max_nonneg(A.vmax + (size_t)cand * A.vmax_ld + vbeg + tid, m);
+    }
+  } else if (MODE == 1) {
+    const T wm = wave_max(mx[0]);
+    const double os = wave_sum(ov);
+    if (lane == 0) {
+      s_red[wv][0] = (double)wm;
+      s_ov[wv] = os;
+    }
+    __syncthreads();
+    const double M = fmax(fmax(s_red[0][0], s_red[1][0]), fmax(s_red[2][0], s_red[3][0]));
+    long long kk = (double)mx[0] == M ? bkey : kNoKey;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const long long w = __shfl_xor(kk, o);
+      kk = w < kk ? w : kk;
+    }
+    if (lane == 0) s_key[wv] = kk;
+    __syncthreads();
+    if (tid == 0) {
+      long long k2 = s_key[0];
+      for (int w = 1; w < 4; ++w) k2 = s_key[w] < k2 ? s_key[w] : k2;
+      A.part_m[slot] = M;   // -1 when the chunk has no scored case
+      A.part_k[slot] = M >= 0.0 ? k2 : kNoKey;
+      A.part_ov[slot] = s_ov[0] + s_ov[1] + s_ov[2] + s_ov[3];
+      A.part_nf[slot] = 0;
+    }
+  } else {
+    WEntry *dst = A.wpart + slot * A.top_k;
+    for (int j = 0; j < A.top_k; ++j) {
+      T bv = lv[0];
+      int bk = lk[0];
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const T ov2 = __shfl_xor(bv, o);
+        const int ok = __shfl_xor(bk, o);
+        if (better(ov2, ok, bv, bk)) {
+          bv = ov2;
+          bk = ok;
+        }
+      }
+      if (lane == 0) {
+        s_bv[wv] = bv;
+        s_bk[wv] = bk;
+      }
+      __syncthreads();
+      T wbv = s_bv[0];
+      int wbk = s_bk[0];
+#pragma unroll
+      for (int w = 1; w < 4; ++w)
+        if (better(s_bv[w], s_bk[w], wbv, wbk)) {
+          wbv = s_bv[w];
+          wbk = s_bk[w];
+        }
+      if (tid == 0) {
+        WEntry e;
+        e.v = wbk == kEmpty ? -1.0 : (double)wbv;
+        e.k = wbk;
+        e.pad = 0;
+        dst[j] = e;
+      }
+      if (wbk != kEmpty && lk[0] == wbk) {
+#pragma unroll
+        for (int t = 0; t < KM - 1; ++t) {
+          lv[t] = lv[t + 1];
+          lk[t] = lk[t + 1];
+        }
+        lv[KM - 1] = (T)-1;
+        lk[KM - 1] = kEmpty;
+      }
+      __syncthreads();
     }
   }
 }
@@ -1075,6 +1362,18 @@ hipError_t launch_max_vc(const ScanArgs &a, const dcflow_batch *bt, int nvar, in
   return launch_max<T, 1, 1>(a, bt, nvar, s);
 }
 
+inline void set_multi(ScanArgs &a, const dcflow_plan *p, const dcflow_batch *bt) {
+  a.n_multi = p->n_multi;
+  a.moff = p->d_moff;
+  a.mcol = p->d_mcol;
+  a.lsdm = p->d_lsdm;
+  a.lsdm32 = p->d_lsdm32;
+  a.mcoef = bt->d_mcoef;
+  a.mok = bt->d_mok;
+  a.nmb = bt->nmb;
+  a.nbt = 1 + bt->nmb;
+}
+
 template <typename T>
 hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *out, int c0, int c1,
                     hipStream_t s) {
@@ -1121,6 +1420,7 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   a.rchunk = 0;
   a.band_rows = 0;
   a.nbands = 1;
+  set_multi(a, p, bt);
   {
     const size_t nv = a.single ? 0 : (size_t)a.n_cand * bt->vmax;
     const size_t n = nv > (size_t)(kQueueWin + 1) ? nv : (size_t)(kQueueWin + 1);
@@ -1144,14 +1444,24 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
     }
     const hipError_t e = launch_max_vc<T>(a, bt, nvar, vc, s);
     if (e != hipSuccess) return e;
+    if (a.nmb > 0) {
+      const int ny = (nvar + kMultiVC - 1) / kMultiVC;
+      k_scan_multi<T, 0, 1><<<dim3((unsigned)((size_t)a.n_cand * a.nmb), ny), dim3(256), 0, s>>>(a);
+      DCF_CHECK_LAUNCH();
+    }
   }
   const size_t fixed = sizeof(T) * 2 * (size_t)p->ld_o;
   choose_rows(bt, fixed, sizeof(T), p->mon_pad, p->ld_o, sizeof(T), kLdsOccupancy, a);
   if (a.nbands > bt->max_bands) return hipErrorInvalidValue;
+  a.nbt = a.nbands + a.nmb;
   const size_t lds = fixed + sizeof(T) * (size_t)a.rchunk;
   if (lds > kLdsBudget) return hipErrorInvalidValue;
   k_scan_win<T, sizeof(T) == 4 ? 4 : 1><<<dim3(grid_x(bt, a)), dim3(256), lds, s>>>(a);
   DCF_CHECK_LAUNCH();
+  if (a.nmb > 0) {
+    k_scan_multi<T, 1, 1><<<dim3((unsigned)((size_t)a.n_cand * a.nmb)), dim3(256), 0, s>>>(a);
+    DCF_CHECK_LAUNCH();
+  }
   k_scan_fin<<<(a.n_cand + 255) / 256, 256, 0, s>>>(a);
   DCF_CHECK_LAUNCH();
   return hipSuccess;
@@ -1216,6 +1526,7 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   a.scores = scores;
   a.top_k = top_k;
   a.wpart = static_cast<WEntry *>(ws);
+  set_multi(a, p, bt);
   const size_t fixed = sizeof(T) * (2 * (size_t)p->ld_o + 4 * (size_t)(4 * NB) * kWave);
   int band = worst_band_rows(p);
   int rc = choose_rchunk(0, fixed, sizeof(T), p->mon_pad, kLdsOccupancy);
@@ -1223,6 +1534,8 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   a.rchunk = rc;
   a.band_rows = band;  // a multiple of 64; the last chunk of a band may be shorter
   a.nbands = worst_bands(p);
+  a.nbt = a.nbands + a.nmb;
+  if (a.nbt > kFinBands) return hipErrorInvalidValue;
   const size_t lds = fixed + sizeof(T) * (size_t)rc;
   if (lds > kLdsBudget) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((size_t)a.n_cand * a.nbands));
@@ -1231,6 +1544,14 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   else
     k_scan_worst<T, 16, 1><<<grid, dim3(256), lds, s>>>(a);
   DCF_CHECK_LAUNCH();
+  if (a.nmb > 0) {
+    const dim3 gm((unsigned)((size_t)a.n_cand * a.nmb));
+    if (top_k <= 8)
+      k_scan_multi<T, 2, 8><<<gm, dim3(256), 0, s>>>(a);
+    else
+      k_scan_multi<T, 2, 16><<<gm, dim3(256), 0, s>>>(a);
+    DCF_CHECK_LAUNCH();
+  }
   k_worst_fin<<<dim3(bt->n_cand), dim3(64), 0, s>>>(a, out);
   DCF_CHECK_LAUNCH();
   return hipSuccess;

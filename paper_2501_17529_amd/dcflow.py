@@ -52,7 +52,9 @@ class GridDesc(ctypes.Structure):
                 ("pst_scale", ctypes.c_double), ("n_hvdc", ctypes.c_int32),
                 ("hvdc_from", ctypes.c_void_p), ("hvdc_to", ctypes.c_void_p),
                 ("hvdc_scale", ctypes.c_double), ("n_gen_out", ctypes.c_int32),
-                ("gen_bus", ctypes.c_void_p), ("gen_p", ctypes.c_void_p)]
+                ("gen_bus", ctypes.c_void_p), ("gen_p", ctypes.c_void_p),
+                ("n_multi_out", ctypes.c_int32), ("multi_off", ctypes.c_void_p),
+                ("multi_br", ctypes.c_void_p)]
 
 
 class Cands(ctypes.Structure):
@@ -75,7 +77,8 @@ class PlanView(ctypes.Structure):
                 ("n_out", ctypes.c_int32), ("n_er", ctypes.c_int32), ("ld_h", ctypes.c_int32),
                 ("ld_o", ctypes.c_int32), ("ptdf", ctypes.c_void_p), ("hdo", ctypes.c_void_p),
                 ("f_base", ctypes.c_void_p), ("rating", ctypes.c_void_p), ("er", ctypes.c_void_p),
-                ("n_inj", ctypes.c_int32), ("n_gen_out", ctypes.c_int32)]
+                ("n_inj", ctypes.c_int32), ("n_gen_out", ctypes.c_int32),
+                ("n_multi_out", ctypes.c_int32)]
 
 
 def _load():
@@ -170,15 +173,19 @@ class _GridArgs:
     """Keeps the host arrays of a grid description alive."""
 
     def __init__(self, n_bus, f, t, b, mon, out, p_base, slack=0, rating=None,
-                 rating_scale=1.2, rating_offset=0.1, controls=None, gens=None):
+                 rating_scale=1.2, rating_offset=0.1, controls=None, gens=None, multi=None):
         """controls: None or dict(pst=[branch ids], pst_scale=rad per unit,
         hvdc=[(from bus, to bus)], hvdc_scale=p.u. per unit).
-        gens: None or (bus ids, lost outputs) of the generator-outage N-1 cases."""
+        gens: None or (bus ids, lost outputs) of the generator-outage N-1 cases.
+        multi: None or a list of branch-id lists, the multi-outage N-1 cases."""
         c = controls or {}
         gb, gp = ([], []) if gens is None else gens
         self.gen_bus = _arr(gb, np.int32)
         self.gen_p = _arr(gp, np.float64)
         assert len(self.gen_bus) == len(self.gen_p)
+        cases = [] if multi is None else [list(c) for c in multi]
+        self.multi_off = _arr(np.cumsum([0] + [len(c) for c in cases]), np.int32)
+        self.multi_br = _arr([x for c in cases for x in c], np.int32)
         self.pst = _arr(c.get("pst", []), np.int32)
         hv = np.asarray(c.get("hvdc", []), np.int32).reshape(-1, 2)
         self.hv_from = _arr(hv[:, 0], np.int32)
@@ -201,7 +208,9 @@ class _GridArgs:
             self.hv_to.ctypes.data if len(self.hv_to) else None,
             float(c.get("hvdc_scale", 1.0)), len(self.gen_bus),
             self.gen_bus.ctypes.data if len(self.gen_bus) else None,
-            self.gen_p.ctypes.data if len(self.gen_p) else None)
+            self.gen_p.ctypes.data if len(self.gen_p) else None, len(cases),
+            self.multi_off.ctypes.data if cases else None,
+            self.multi_br.ctypes.data if len(self.multi_br) else None)
 
 
 class _CandArgs:
@@ -242,10 +251,10 @@ class Plan:
 
     def __init__(self, n_bus, f, t, b, mon, out, p_base, slack=0, rating=None,
                  rating_scale=1.2, rating_offset=0.1, device="cuda", stream=None, controls=None,
-                 gens=None):
+                 gens=None, multi=None):
         import torch
         self.args = _GridArgs(n_bus, f, t, b, mon, out, p_base, slack, rating, rating_scale,
-                              rating_offset, controls, gens)
+                              rating_offset, controls, gens, multi)
         nbytes = ctypes.c_size_t(0)
         _check(_lib.dcflow_plan_workspace_bytes(ctypes.byref(self.args.desc), ctypes.byref(nbytes)),
                "dcflow_plan_workspace_bytes")
@@ -265,6 +274,7 @@ class Plan:
         g = w.grid
         kw.setdefault("controls", getattr(w, "controls", None))
         kw.setdefault("gens", getattr(w, "gens", None))
+        kw.setdefault("multi", getattr(w, "multi", None))
         return cls(g.n_bus, g.f, g.t, g.b, w.mon, w.out, g.p, g.slack, rating,
                    w.rating_scale, w.rating_offset, **kw)
 

@@ -107,7 +107,7 @@ def oracle_scores(w, idx, rating, variants=None):
         x = w.inj if w.inj_shared else w.inj[int(i)]
         if variants is not None:
             x = x[np.asarray(variants)]
-        kw = {"gens": getattr(w, "gens", None)}
+        kw = {"gens": getattr(w, "gens", None), "multi": getattr(w, "multi", None)}
         if getattr(w, "controls", None):
             kw.update(controls=w.controls, ctrl=x[:, g.n_bus:])
             x = x[:, :g.n_bus]

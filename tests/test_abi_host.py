@@ -106,6 +106,18 @@ def test_grid_validation_errors(d):
         assert ei.value.code == code, gens
     ga = d._GridArgs(g.n_bus, g.f, g.t, g.b, w.mon, w.out, g.p, gens=([3, 3, 0], [0.5, 0.1, 2.0]))
     d.validate_candidates(ga, w.cands)   # shared buses and the slack are allowed
+    o = [int(c) for c in w.out[:20]]     # a contingency list without branch w.out[25]
+    not_out = int(w.out[25])
+    for multi, code in [([[o[0], not_out]], -2),                 # branch not a contingency
+                        ([[o[0], o[1], o[2], o[3], o[4]]], -2),   # more than four branches
+                        ([[o[0], o[0]]], -2),                     # repeated branch
+                        ([[o[0]], []], -2)]:                      # empty case
+        ga = d._GridArgs(g.n_bus, g.f, g.t, g.b, w.mon, o, g.p, multi=multi)
+        with pytest.raises(d.DcflowError) as ei:
+            d.validate_candidates(ga, w.cands)
+        assert ei.value.code == code, multi
+    ga = d._GridArgs(g.n_bus, g.f, g.t, g.b, w.mon, o, g.p, multi=[[o[0]], o[1:5]])
+    d.validate_candidates(ga, w.cands)
 
 
 def test_library_binds_to_torch_hip_runtime():

@@ -570,3 +570,103 @@ def test_generator_outages_in_the_score():
         n_gen_worst += sc["worst_outage"] <= -2
         assert -2 - len(gens[0]) < sc["worst_outage"] < g.n_branch
     assert n_gen_worst >= 1     # a generator case is the worst one at least once
+
+
+# ------------------------------------------------------- multi-outage cases
+
+def test_multi_outage_by_hand():
+    # buses 0 (slack), 1, 2; two unit lines 1-0 (branches 0, 1) and the detour
+    # 1 -> 2 -> 0 (branches 2, 3); +1 at bus 1.  N-0: 0.4 on each direct line, 0.2 on
+    # the detour.  Tripping {0, 1} sends everything over the detour (1, 1); {0, 2}
+    # leaves line 1 alone (1) and bus 2 hanging on branch 3 (0); {2, 3} islands bus 2.
+    # Rating 0.9 on branch 3 makes (branch 3, case {0, 1}) the unique maximum 1/0.9.
+    f = np.array([1, 1, 1, 2])
+    t = np.array([0, 0, 2, 0])
+    x = np.array([[-1.0, 1.0, 0.0]])
+    r = np.array([1.0, 1.0, 1.0, 0.9])
+    mon = out = np.arange(4)
+    multi = [[0, 1], [0, 2], [2, 3]]
+    pm, isl = O.multi_outage_flows(3, f, t, np.ones(4), 0, [], x, multi)
+    np.testing.assert_allclose(pm[0, 0], [0, 0, 1, 1], atol=1e-15)
+    np.testing.assert_allclose(pm[0, 1], [0, 1, 0, 0], atol=1e-15)
+    assert list(isl) == [False, False, True]
+    sc = O.score_candidate(3, f, t, np.ones(4), 0, [], x, mon, out, r, multi=multi)
+    np.testing.assert_allclose(sc["flows"]["p0"][0], [0.4, 0.4, 0.2, 0.2], atol=1e-15)
+    assert sc["best_max_load"] == pytest.approx(1 / 0.9, abs=1e-14)
+    assert (sc["worst_branch"], sc["worst_outage"]) == (3, -2)
+    assert sc["n_island"] == 1
+    got = O.worst_cases(sc, mon, out, 4)
+    assert [(b, o) for _, b, o in got] == [(3, -2), (2, -2), (1, -3), (1, 0)]
+    np.testing.assert_allclose([v for v, _, _ in got], [1 / 0.9, 1.0, 1.0, 2 / 3], atol=1e-14)
+    # a remedial outage of branch 0: case {0, 1} trips branch 1 alone, with the same flows
+    sc2 = O.score_candidate(3, f, t, np.ones(4), 0, [(G.KIND_OUTAGE, 0, 0, 0.0)], x, mon, out,
+                            r, multi=multi)
+    assert sc2["best_max_load"] == pytest.approx(1 / 0.9, abs=1e-14)
+    assert (sc2["worst_branch"], sc2["worst_outage"]) in {(3, 1), (3, -2)}
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_multi_outage_matches_paper_modf(seed):
+    """Re-solving the candidate network without a case's branches equals the
+    paper's MODF (Def. eq_modf) applied to the candidate network's PTDF: p0 + MODF
+    p0[S] (branches the candidate removed left out of S)."""
+    g, cands, rng = _mixed_workload(seed, n_cand=10)
+    x = G.perturbed_injections(g, rng, (2,), 0.3)
+    out = np.arange(0, g.n_branch, 3)
+    multi = G.multi_outage_cases(g, out, rng, 12)
+    n_checked = n_isl = 0
+    for els in cands:
+        n2, f2, t2, alive, splits = O.rebuild(g.n_bus, g.f, g.t, els)
+        fa, ta, ba = f2[alive], t2[alive], np.asarray(g.b)[alive]
+        if not O.connected(n2, fa, ta):
+            continue
+        pm, isl = O.multi_outage_flows(g.n_bus, g.f, g.t, g.b, g.slack, els, x, multi)
+        p0 = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, els, x, [])["p0"]
+        h = O.ptdf(n2, fa, ta, ba, g.slack)
+        idx = -np.ones(len(f2), np.int64)
+        idx[alive] = np.arange(int(alive.sum()))
+        for qi, case in enumerate(multi):
+            s_alive = [int(idx[c]) for c in case if alive[c]]
+            if isl[qi]:
+                n_isl += 1
+                continue
+            if not s_alive:
+                np.testing.assert_allclose(pm[:, qi], p0, atol=1e-12)
+                continue
+            md = PF.modf(h, fa, ta, s_alive)
+            want = p0[:, alive] + (md @ p0[:, alive][:, s_alive].T).T
+            np.testing.assert_allclose(pm[:, qi][:, alive], want, atol=1e-10)
+            n_checked += 1
+    assert n_checked > 50 and n_isl > 0
+
+
+def test_multi_outage_order_with_generators():
+    """Case order: branch contingencies, then generator outages (-2 - g), then
+    multi-outage cases (-2 - G - q); every listed case carries its own load."""
+    w = G.workload_tiny(4)
+    g = w.grid
+    rng = np.random.default_rng(4)
+    gens = G.generator_outages(g, rng, 5)
+    multi = G.multi_outage_cases(g, w.out, rng, 10)
+    r = O.ratings(g.n_bus, g.f, g.t, g.b, g.slack, g.p, w.mon, 1.0, 0.05)
+    seen_multi = 0
+    for i in range(10):
+        els = w.cands.elements(i)
+        sc = O.score_candidate(g.n_bus, g.f, g.t, g.b, g.slack, els, w.inj, w.mon, w.out, r,
+                               gens=gens, multi=multi)
+        if sc["best_variant"] < 0:
+            continue
+        ids = sc["scored_out"]
+        nb = int((ids >= 0).sum())
+        assert np.all(ids[:nb] >= 0)
+        assert np.all(ids[nb:nb + 5] == -2 - np.arange(5))
+        assert np.all(ids[nb + 5:] <= -7)
+        pm, isl = O.multi_outage_flows(g.n_bus, g.f, g.t, g.b, g.slack, els, w.inj, multi)
+        for v, b, o in O.worst_cases(sc, w.mon, w.out, 16):
+            if o <= -7:
+                q = -7 - o
+                assert not isl[q]
+                li = int(np.flatnonzero(w.mon == b)[0])
+                assert v == pytest.approx(abs(pm[0, q, b]) / r[li], abs=1e-12)
+                seen_multi += 1
+    assert seen_multi > 0
