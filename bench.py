@@ -38,14 +38,15 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_medium_traffic.txt")
 def _oracle_worker(args):
     from threadpoolctl import threadpool_limits
     from oracle import dcflow_oracle as O
-    n_bus, f, t, b, slack, elems, x, mon, out, rating, controls = args
-    kw = {}
+    n_bus, f, t, b, slack, elems, x, mon, out, rating, controls, gens, multi = args
+    kw = dict(gens=gens, multi=multi)
     if controls:
-        kw = dict(controls=controls, ctrl=x[:, n_bus:])
+        kw.update(controls=controls, ctrl=x[:, n_bus:])
         x = x[:, :n_bus]
     with threadpool_limits(limits=1):
         O.score_candidate(n_bus, f, t, b, slack, elems, x, mon, out, rating, **kw)
-    return x.shape[0] * len(out)
+    n_extra = (0 if gens is None else len(gens[0])) + (0 if multi is None else len(multi))
+    return x.shape[0] * (len(out) + n_extra)
 
 
 def cpu_baseline(w, n_sample: int, max_var: int = 0):
@@ -62,7 +63,7 @@ def cpu_baseline(w, n_sample: int, max_var: int = 0):
         x = w.inj[i] if not w.inj_shared else w.inj
         return x[:max_var] if max_var else x
     jobs = [(g.n_bus, g.f, g.t, g.b, g.slack, w.cands.elements(i), xs(i), w.mon, w.out, rating,
-             getattr(w, "controls", None))
+             getattr(w, "controls", None), getattr(w, "gens", None), getattr(w, "multi", None))
             for i in range(n_sample)]
     ctx = mp.get_context("fork")     # forked before this process touches the GPU
     t0 = time.perf_counter()
@@ -275,6 +276,9 @@ def main():
     ap.add_argument("--tune-cache", default="", metavar="PATH",
                     help="autotuner cache file: shapes found there are reused without a sweep "
                          "(so that a profiled run times the same launch shapes as the bench run)")
+    ap.add_argument("--n1-extras", default="", metavar="G,Q",
+                    help="add G generator outages and Q multi-outage cases (2-4 contingency "
+                         "branches each) to the N-1 set of the workload")
     ap.add_argument("--ti-sweep", default="", metavar="SIZES",
                     help="only run the |T_i| sweep, metric-first vs output-first, for the "
                          "comma-separated numbers of injection topologies per candidate")
@@ -316,6 +320,11 @@ def main():
         w = G.workload_brute(0, n_topo=a.cands or 1024)
         precs = ["fp32", "bf16x6"] if a.prec == "all" else [a.prec]
         sample = a.cpu_sample or 1
+    if a.n1_extras:
+        n_g, n_q = (int(v) for v in a.n1_extras.split(","))
+        rng = np.random.default_rng(77)
+        w.gens = G.generator_outages(w.grid, rng, n_g) if n_g else None
+        w.multi = G.multi_outage_cases(w.grid, w.out, rng, n_q) if n_q else None
     max_var = 128 if a.workload == "brute" else 0   # the oracle holds all N-1 flows at once
     cpu = None if a.no_cpu_baseline else cpu_baseline(w, min(sample, w.cands.n_cand), max_var)
 
@@ -327,7 +336,8 @@ def main():
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
 
-    n_lf = w.cands.n_cand * w.n_var * len(w.out)
+    n_extra = (0 if w.gens is None else len(w.gens[0])) + (0 if w.multi is None else len(w.multi))
+    n_lf = w.cands.n_cand * w.n_var * (len(w.out) + n_extra)
     res = {}
     for prec in precs:
         res[prec] = run_path(D, torch, plan, w, prec, a.steps, a.warmup, tune=not a.no_autotune,
@@ -346,7 +356,7 @@ def main():
     flops = 2.0 * w.cands.n_cand * sweeps * len(w.mon) * len(w.out)
     achieved = flops / (scan_ms / 1e3) / 1e12
     traffic = None
-    if a.workload == "medium" and os.path.exists(TRAFFIC_FILE):
+    if a.workload == "medium" and not a.n1_extras and os.path.exists(TRAFFIC_FILE):
         tf = json.load(open(TRAFFIC_FILE))
         if tf.get("source_hash") == _source_hash() and tf.get("prec") == main_prec:
             traffic = tf.get("bytes_per_launch")
@@ -358,7 +368,10 @@ def main():
         "config": {"workload": WORKLOADS[a.workload].format(n=f"{w.cands.n_cand:,}"),
                    "n_bus": g.n_bus, "n_branch": g.n_branch, "candidates": w.cands.n_cand,
                    "variants": w.n_var, "contingencies": len(w.out), "monitored": len(w.mon),
-                   "loadflows_per_step": n_lf, "parallelism": "single GPU"},
+                   "loadflows_per_step": n_lf, "parallelism": "single GPU",
+                   **({"generator_outages": len(w.gens[0]) if w.gens is not None else 0,
+                       "multi_outage_cases": len(w.multi) if w.multi is not None else 0}
+                      if a.n1_extras else {})},
         "roofline": {"bound": "alu", "kernel": "k_scan (per-variant N-1 maxima + winner pass)",
                      "achieved": achieved, "peak": PEAK_VALU_FMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_FMA_TFLOPS, "traffic": traffic},

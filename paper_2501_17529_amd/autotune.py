@@ -38,7 +38,7 @@ def shape_key(batch: "D.Batch", n_var: int, prec: str) -> str:
     v = batch.plan.view
     kmax = int(np.max(np.diff(batch.ca.off))) if batch.n_cand else 0
     return (f"{_arch()}|{prec}|n_cand={batch.n_cand}|n_var={n_var}|n_mon={v.n_mon}|"
-            f"n_out={v.n_out}|ld_o={v.ld_o}|kmax={kmax}")
+            f"n_out={v.n_out}|ld_o={v.ld_o}|n_multi={v.n_multi_out}|kmax={kmax}")
 
 
 def _load(path):
@@ -113,7 +113,12 @@ def tune_scan(batch: "D.Batch", flows, n_var: int, prec: str, reps: int = 10,
     best, best_t = None, float("inf")
     for cfg in candidates(batch, n_var, prec):
         batch.set_tuning(**cfg)
-        t = _time_scan(batch, flows, n_var, prec, out, reps)
+        try:
+            t = _time_scan(batch, flows, n_var, prec, out, reps)
+        except D.DcflowError:
+            # a shape whose LDS block does not fit this batch (wide contingency sets)
+            times[json.dumps(cfg, sort_keys=True)] = None
+            continue
         got = D.Batch.scores_to_numpy(out, batch.n_cand)
         same = (np.array_equal(got["max_load"], ref["max_load"])
                 and np.array_equal(got["best_variant"], ref["best_variant"])

@@ -316,62 +316,85 @@ __global__ void __launch_bounds__(64) k_multi_prep(
   const bool bad = (st & (DCFLOW_ST_DISCONNECTED | DCFLOW_ST_SINGULAR)) != 0;
   if (threadIdx.x == 0) s_isl = 0;
   __syncthreads();
+  constexpr int MM = DCFLOW_MULTI_MAX;
   for (int q = threadIdx.x; q < n_multi; q += blockDim.x) {
     const int a = moff[q], m = moff[q + 1] - a;
-    int col[DCFLOW_MULTI_MAX], pos[DCFLOW_MULTI_MAX];
-    bool rem[DCFLOW_MULTI_MAX];
+    // all loops below run over MM with guards, so that the arrays stay in registers
+    int col[MM], pos[MM];
+    bool rem[MM];
     bool island = false;
-    for (int j = 0; j < DCFLOW_MULTI_MAX; ++j) {
+#pragma unroll
+    for (int j = 0; j < MM; ++j) {
       col[j] = j < m ? mcol[a + j] : 0;
       pos[j] = out_pos[col[j]];
       const bool ib = ((isl[(size_t)cand * (ld_o / 32) + col[j] / 32] >> (col[j] % 32)) & 1u) != 0;
       rem[j] = j < m && !ib && invden[(size_t)cand * ld_o + col[j]] == 0.0;
       island = island || (j < m && ib);
     }
-    double A[DCFLOW_MULTI_MAX][2 * DCFLOW_MULTI_MAX];
+    double A[MM][MM], Bi[MM][MM];  // N, then its inverse by Gauss-Jordan on [N | I]
     bool ok = !bad && !island;
-    if (ok) {
-      for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j) {
-          double v = i == j ? 1.0 : 0.0;
-          if (!rem[i] && !rem[j]) {
-            v = hdo[(size_t)out[col[i]] * ld_o + col[j]] - v;
-            for (int e = 0; e < k; ++e)
-              v += U[(size_t)(e0 + e) * ld_er + pos[i]] * W[(size_t)(e0 + e) * ld_o + col[j]];
-          }
-          A[i][j] = v;
-          A[i][m + j] = i == j ? 1.0 : 0.0;
+#pragma unroll
+    for (int i = 0; i < MM; ++i)
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        double v = i == j ? 1.0 : 0.0;  // identity outside the case and for removed branches
+        if (ok && i < m && j < m && !rem[i] && !rem[j]) {
+          v = hdo[(size_t)out[col[i]] * ld_o + col[j]] - v;
+          for (int e = 0; e < k; ++e)
+            v += U[(size_t)(e0 + e) * ld_er + pos[i]] * W[(size_t)(e0 + e) * ld_o + col[j]];
         }
-      // Gauss-Jordan with partial pivoting
-      for (int c = 0; c < m && ok; ++c) {
-        int pr = c;
-        for (int r = c + 1; r < m; ++r)
-          if (fabs(A[r][c]) > fabs(A[pr][c])) pr = r;
-        if (fabs(A[pr][c]) < kIslandTol) {
-          ok = false;
-          break;
+        A[i][j] = v;
+        Bi[i][j] = i == j ? 1.0 : 0.0;
+      }
+#pragma unroll
+    for (int c = 0; c < MM; ++c) {
+      // partial pivoting: the largest |A[r][c]| among r >= c, swapped into row c
+      int pr = c;
+      double pv = fabs(A[c][c]);
+#pragma unroll
+      for (int r = c + 1; r < MM; ++r)
+        if (fabs(A[r][c]) > pv) {
+          pv = fabs(A[r][c]);
+          pr = r;
         }
-        if (pr != c)
-          for (int x = 0; x < 2 * m; ++x) {
-            const double t = A[c][x];
-            A[c][x] = A[pr][x];
-            A[pr][x] = t;
+      if (c < m && pv < kIslandTol) ok = false;
+#pragma unroll
+      for (int r = c + 1; r < MM; ++r)
+        if (r == pr)
+#pragma unroll
+          for (int x = 0; x < MM; ++x) {
+            double t = A[c][x];
+            A[c][x] = A[r][x];
+            A[r][x] = t;
+            t = Bi[c][x];
+            Bi[c][x] = Bi[r][x];
+            Bi[r][x] = t;
           }
-        const double inv = 1.0 / A[c][c];
-        for (int x = 0; x < 2 * m; ++x) A[c][x] *= inv;
-        for (int r = 0; r < m; ++r) {
-          if (r == c) continue;
-          const double f = A[r][c];
-          for (int x = 0; x < 2 * m; ++x) A[r][x] -= f * A[c][x];
+      const double inv = pv > 0.0 ? 1.0 / A[c][c] : 0.0;
+#pragma unroll
+      for (int x = 0; x < MM; ++x) {
+        A[c][x] *= inv;
+        Bi[c][x] *= inv;
+      }
+#pragma unroll
+      for (int r = 0; r < MM; ++r) {
+        if (r == c) continue;
+        const double f = A[r][c];
+#pragma unroll
+        for (int x = 0; x < MM; ++x) {
+          A[r][x] -= f * A[c][x];
+          Bi[r][x] -= f * Bi[c][x];
         }
       }
-      if (!ok) island = true;
     }
+    if (!bad && !ok) island = true;
     if (!bad && island) atomicAdd(&s_isl, 1);
     double *cq = coef + ((size_t)cand * n_multi + q) * 16;
-    for (int j = 0; j < DCFLOW_MULTI_MAX; ++j)
-      for (int i = 0; i < DCFLOW_MULTI_MAX; ++i)
-        cq[j * 4 + i] = (ok && j < m && i < m && !rem[j]) ? -A[j][m + i] : 0.0;
+#pragma unroll
+    for (int j = 0; j < MM; ++j)
+#pragma unroll
+      for (int i = 0; i < MM; ++i)
+        cq[j * 4 + i] = (ok && j < m && i < m && !rem[j]) ? -Bi[j][i] : 0.0;
     mok[(size_t)cand * n_multi + q] = ok ? 1 : 0;
   }
   __syncthreads();

@@ -29,7 +29,9 @@ constexpr int kSenseUnroll = 4;
 // four doubles at an 8-byte-aligned address (a row of X starts anywhere)
 typedef double d4u __attribute__((ext_vector_type(4), aligned(8)));  // K chunks per wave whose loads are in flight together
 
-__global__ void __launch_bounds__(256)
+// four waves per SIMD (at most 128 VGPRs): the occupancy hides the latency of
+// the kSenseUnroll chunk loads
+__global__ void __launch_bounds__(256, 4)
 k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
         const int32_t *__restrict__ nsig, const int32_t *__restrict__ sig,
         const double *__restrict__ pnew, const double *__restrict__ kinv,
@@ -127,16 +129,16 @@ k_sense(const int32_t *__restrict__ off, const int32_t *__restrict__ kind,
     if (tid < 16) {
       const int v = v0 + tid;
       if (v < nvar) {
+        // injection on the split's new busbar: per variant (injection topologies)
+        // if given, else the candidate's fixed value
+        const double *pbv = pnv ? pnv + (size_t)e0 * nvar + v : pnew + e0;
+        const int pstride = pnv ? nvar : 1;
         double h[kMaxRank];
 #pragma unroll
         for (int j = 0; j < kMaxRank; ++j) {
           h[j] = 0.0;
-          if (j < k) {
-            // injection on the split's new busbar: per variant (injection topologies)
-            // if given, else the candidate's fixed value
-            const double pb = pnv ? pnv[(size_t)(e0 + j) * nvar + v] : pnew[e0 + j];
-            h[j] = hacc[j][tid] - (kind[e0 + j] == DCFLOW_SPLIT ? pb : 0.0);
-          }
+          if (j < k)
+            h[j] = hacc[j][tid] - (kind[e0 + j] == DCFLOW_SPLIT ? pbv[(size_t)j * pstride] : 0.0);
         }
         const double *Ki = kinv + (size_t)cand * 64;
 #pragma unroll

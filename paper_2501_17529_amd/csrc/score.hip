@@ -1008,7 +1008,8 @@ __global__ void __launch_bounds__(64) k_worst_fin(ScanArgs A, dcflow_case *out) 
 // p1[S] (coef_q = -N^-1 from the branch module, c_j the contingency column of the
 // j-th branch).  One thread per monitored row builds the m entries L~[row, c_j] =
 // Lsd[row, c_j] + (U / r)[row, :] W[:, c_j] once per case and applies them to every
-// variant of the workgroup; the cases' z are staged in LDS, kMultiQC at a time.
+// variant of the workgroup; the cases' z and W columns are staged in LDS,
+// kMultiQC cases at a time.
 //   MODE 0: per-variant maxima merged into vmax (after pass 1, before pass 2);
 //   MODE 1: for v* (the argmin of vmax, as in pass 2) the chunk's maximum, its
 //           lowest key ((n_ctg + q + 1) n_mon + row) and overload sum, written to
@@ -1017,7 +1018,10 @@ __global__ void __launch_bounds__(64) k_worst_fin(ScanArgs A, dcflow_case *out) 
 //           to the worst-case slot nbands + chunk that k_worst_fin merges.
 // The N-0 rows are covered by the band passes.
 constexpr int kMultiQC = 32;  // cases staged per round
-constexpr int kMultiVC = 8;   // variants per workgroup of the maxima
+template <typename T>
+struct MultiVc {              // variants per workgroup of the maxima
+  static constexpr int v = sizeof(T) == 4 ? 16 : 8;
+};
 
 template <typename T>
 struct MultiOps;
@@ -1048,11 +1052,12 @@ struct MultiOps<float> {
 
 template <typename T, int MODE, int KM>
 __global__ void __launch_bounds__(256) k_scan_multi(ScanArgs A) {
-  constexpr int VC = MODE == 0 ? kMultiVC : 1;
+  constexpr int VC = MODE == 0 ? MultiVc<T>::v : 1;
   constexpr int QC = kMultiQC, MM = DCFLOW_MULTI_MAX;
   constexpr long long kNoKey = 0x7fffffffffffffffLL;
   constexpr int kEmpty = 0x7fffffff;
   __shared__ T zs[QC][VC][MM];
+  __shared__ T wsm[QC][MM][kMaxRank];  // W[e][c_j] of the round's cases
   __shared__ int s_m[QC], s_a[QC];
   __shared__ double s_red[4][VC];
   __shared__ double s_ov[4];
@@ -1152,6 +1157,16 @@ __global__ void __launch_bounds__(256) k_scan_multi(ScanArgs A) {
         s_a[qq] = a;
       }
     }
+    for (int i = tid; i < QC * MM * kMaxRank; i += blockDim.x) {
+      const int qq = i / (MM * kMaxRank), j = (i / kMaxRank) % MM, e = i % kMaxRank;
+      const int q = q0 + qq;
+      T wv0 = (T)0;
+      if (q < A.n_multi && e < k) {
+        const int a = A.moff[q];
+        if (j < A.moff[q + 1] - a) wv0 = MultiOps<T>::w(A, e0 + e, A.mcol[a + j]);
+      }
+      wsm[qq][j][e] = wv0;
+    }
     __syncthreads();
     if (!has_row) continue;
     const int qn = min(QC, A.n_multi - q0);
@@ -1164,11 +1179,9 @@ __global__ void __launch_bounds__(256) k_scan_multi(ScanArgs A) {
       for (int j = 0; j < MM; ++j) {
         lt[j] = (T)0;
         if (j < m) {
-          const int sc = a + j, c = A.mcol[sc];
-          T acc = MultiOps<T>::seed(A, sc, row);
+          T acc = MultiOps<T>::seed(A, a + j, row);
 #pragma unroll
-          for (int e = 0; e < kMaxRank; ++e)
-            if (e < k) acc = tfma(ur[e], MultiOps<T>::w(A, e0 + e, c), acc);
+          for (int e = 0; e < kMaxRank; ++e) acc = tfma(ur[e], wsm[qq][j][e], acc);  // ur, W 0 past k
           lt[j] = acc;
         }
       }
@@ -1445,7 +1458,7 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
     const hipError_t e = launch_max_vc<T>(a, bt, nvar, vc, s);
     if (e != hipSuccess) return e;
     if (a.nmb > 0) {
-      const int ny = (nvar + kMultiVC - 1) / kMultiVC;
+      const int ny = (nvar + MultiVc<T>::v - 1) / MultiVc<T>::v;
       k_scan_multi<T, 0, 1><<<dim3((unsigned)((size_t)a.n_cand * a.nmb), ny), dim3(256), 0, s>>>(a);
       DCF_CHECK_LAUNCH();
     }
