@@ -340,6 +340,30 @@ def perturbed_injections(grid: Grid, rng, shape, rel_sigma: float) -> np.ndarray
     return balanced(grid.p * (1.0 + rel_sigma * g), grid.slack)
 
 
+def attach_stubs(grid: Grid, rng, n_stubs: int, max_len: int = 3) -> Grid:
+    """The grid with n_stubs radial chains of 1..max_len new buses attached to
+    random buses (power-plant connections and their step-up transformers), each
+    new bus injecting a positive output; the slack balances the total."""
+    f, t, x = list(grid.f), list(grid.t), list(grid.x)
+    p = list(grid.p)
+    pos = [tuple(r) for r in grid.pos]
+    n = grid.n_bus
+    for _ in range(n_stubs):
+        at = int(rng.integers(grid.n_bus))
+        for _ in range(int(rng.integers(1, max_len + 1))):
+            f.append(at)
+            t.append(n)
+            x.append(float(rng.lognormal(-2.5, 0.5)))
+            p.append(float(rng.uniform(0.2, 1.5)))
+            pos.append(tuple(grid.pos[at % grid.n_bus]))
+            at = n
+            n += 1
+    p = balanced(np.asarray(p), grid.slack)
+    x = np.asarray(x)
+    return Grid(n_bus=n, f=np.asarray(f, np.int32), t=np.asarray(t, np.int32), x=x, b=1.0 / x,
+                p=p, pos=np.asarray(pos), slack=grid.slack)
+
+
 def generator_outages(grid: Grid, rng, n_gen: int):
     """Generator-outage N-1 cases: n_gen generators at distinct buses drawn among
     those with a positive base injection (the slack left out), each losing

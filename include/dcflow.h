@@ -147,7 +147,8 @@ typedef struct {
   /* Multi-outage N-1 cases (optional: 0 and NULLs for none), such as a busbar
    * or a three-winding transformer: case q trips the branches multi_br[
    * multi_off[q]] .. multi_br[multi_off[q+1] - 1] together (Def. eq_modf; Sec.
-   * III-C branch-module step 5 and injection-module step 8c).  Each case has 1
+   * III-C branch-module step 5 and injection-module step 8c; Sec. IV-D: the MODF
+   * terms are formed in the branch module and applied in the injection module).  Each case has 1
    * to DCFLOW_MULTI_MAX branches, distinct, each one of the n_out contingencies.
    * A case that islands the candidate grid is excluded and counted like an
    * islanding contingency; branches the candidate removed drop out of the case.
@@ -231,6 +232,38 @@ void dcflow_plan_destroy(dcflow_plan *plan);
 int dcflow_validate_candidates(const dcflow_grid_desc *grid, const dcflow_cands *cands,
                                int32_t *bad_index, int64_t *packed_slots,
                                int64_t *padded_slots);
+
+/* Stub folding (host only; Sec. IV-A): radial stubs hanging off the meshed grid
+ * (a bus of degree one, repeatedly, so that whole radial trees go) are replaced
+ * by their injections at the bus they hang from.  In DC the flows on the rest
+ * of the grid are unchanged, a folded branch carries the sum of the injections
+ * beyond it, and the station gains injections that injection topologies can
+ * regroup.  The slack and buses with protect[b] != 0 (protect may be NULL; e.g.
+ * buses that candidates split) are never folded; parallel branches count
+ * towards a bus's degree.  Outputs, caller-allocated host arrays:
+ *   bus_new [n_bus]     index of a kept bus in the folded grid; for a folded bus,
+ *                       that of the kept bus its tree hangs from;
+ *   branch_new [n_branch] index of a kept branch in the folded grid, -1 if folded;
+ *   up_branch [n_bus]   for a folded bus the branch towards the kept grid, else -1;
+ *   *n_bus_out, *n_branch_out  sizes of the folded grid (kept order preserved;
+ *                       its slack is bus_new[slack]).
+ * E_ARG for null pointers, E_SHAPE for bad sizes or terminals. */
+int dcflow_fold_stubs(int32_t n_bus, int32_t n_branch, int32_t slack, const int32_t *from,
+                      const int32_t *to, const uint8_t *protect, int32_t *bus_new,
+                      int32_t *branch_new, int32_t *up_branch, int32_t *n_bus_out,
+                      int32_t *n_branch_out);
+
+/* Injections of the folded grid (host): x_out[v][bus_new[b]] = sum of x[v][b]
+ * over the buses b mapped there; x [n_var][n_bus], x_out [n_var][n_bus_out]. */
+int dcflow_fold_injections(int32_t n_bus, const int32_t *bus_new, int32_t n_bus_out,
+                           const double *x, int32_t n_var, double *x_out);
+
+/* Flows of the folded branches (host) for injections x [n_var][n_bus]: the sum of
+ * x over the buses beyond the branch, positive when it leaves them towards the
+ * kept grid in the branch's from -> to direction; 0 on kept branches.
+ * flow [n_var][n_branch]. */
+int dcflow_stub_flows(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
+                      const int32_t *up_branch, const double *x, int32_t n_var, double *flow);
 
 /* Device bytes for a batch of these candidates with up to n_var_max
  * injection variants per candidate. */

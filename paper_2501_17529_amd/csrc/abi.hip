@@ -835,6 +835,116 @@ int dcflow_set_busbar_injections(dcflow_batch *b, const double *dev_pnew, int32_
 
 const double *dcflow_batch_variant_max(const dcflow_batch *b) { return b ? b->d_vmax : nullptr; }
 
+// Stub folding: leaves of the branch graph (degree one, not the slack, not
+// protected) are pruned one after another; each pruned bus remembers the branch
+// that connected it, whose other end is its parent.
+int dcflow_fold_stubs(int32_t n_bus, int32_t n_branch, int32_t slack, const int32_t *from,
+                      const int32_t *to, const uint8_t *protect, int32_t *bus_new,
+                      int32_t *branch_new, int32_t *up_branch, int32_t *n_bus_out,
+                      int32_t *n_branch_out) {
+  if (!from || !to || !bus_new || !branch_new || !up_branch || !n_bus_out || !n_branch_out)
+    return DCFLOW_E_ARG;
+  if (n_bus < 1 || n_branch < 0 || slack < 0 || slack >= n_bus) return DCFLOW_E_SHAPE;
+  for (int l = 0; l < n_branch; ++l)
+    if (from[l] < 0 || from[l] >= n_bus || to[l] < 0 || to[l] >= n_bus || from[l] == to[l])
+      return DCFLOW_E_SHAPE;
+  std::vector<int> deg(n_bus, 0), off(n_bus + 1, 0), adj(2 * (size_t)n_branch);
+  for (int l = 0; l < n_branch; ++l) {
+    ++deg[from[l]];
+    ++deg[to[l]];
+  }
+  for (int b = 0; b < n_bus; ++b) off[b + 1] = off[b] + deg[b];
+  {
+    std::vector<int> fill(off.begin(), off.end() - 1);
+    for (int l = 0; l < n_branch; ++l) {
+      adj[fill[from[l]]++] = l;
+      adj[fill[to[l]]++] = l;
+    }
+  }
+  std::vector<uint8_t> br_cut(n_branch, 0), bus_cut(n_bus, 0);
+  auto foldable = [&](int b) { return b != slack && !(protect && protect[b]) && deg[b] == 1; };
+  std::vector<int> stack, order;
+  for (int b = 0; b < n_bus; ++b)
+    if (foldable(b)) stack.push_back(b);
+  for (int b = 0; b < n_bus; ++b) up_branch[b] = -1;
+  while (!stack.empty()) {
+    const int b = stack.back();
+    stack.pop_back();
+    if (bus_cut[b] || !foldable(b)) continue;
+    int l = -1;
+    for (int i = off[b]; i < off[b + 1]; ++i)
+      if (!br_cut[adj[i]]) l = adj[i];
+    const int p = from[l] == b ? to[l] : from[l];
+    bus_cut[b] = 1;
+    br_cut[l] = 1;
+    up_branch[b] = l;
+    order.push_back(b);
+    --deg[b];
+    if (--deg[p] == 1 && foldable(p)) stack.push_back(p);
+  }
+  int nb = 0, nl = 0;
+  for (int b = 0; b < n_bus; ++b) bus_new[b] = bus_cut[b] ? -1 : nb++;
+  for (int l = 0; l < n_branch; ++l) branch_new[l] = br_cut[l] ? -1 : nl++;
+  // a pruned bus's parent is kept or was pruned later: walk the pruning order backwards
+  for (size_t i = order.size(); i-- > 0;) {
+    const int b = order[i], l = up_branch[b];
+    bus_new[b] = bus_new[from[l] == b ? to[l] : from[l]];
+  }
+  *n_bus_out = nb;
+  *n_branch_out = nl;
+  return DCFLOW_OK;
+}
+
+int dcflow_fold_injections(int32_t n_bus, const int32_t *bus_new, int32_t n_bus_out,
+                           const double *x, int32_t n_var, double *x_out) {
+  if (!bus_new || !x || !x_out) return DCFLOW_E_ARG;
+  if (n_bus < 1 || n_bus_out < 1 || n_var < 0) return DCFLOW_E_SHAPE;
+  for (int b = 0; b < n_bus; ++b)
+    if (bus_new[b] < 0 || bus_new[b] >= n_bus_out) return DCFLOW_E_SHAPE;
+  for (int v = 0; v < n_var; ++v) {
+    double *o = x_out + (size_t)v * n_bus_out;
+    std::fill(o, o + n_bus_out, 0.0);
+    for (int b = 0; b < n_bus; ++b) o[bus_new[b]] += x[(size_t)v * n_bus + b];
+  }
+  return DCFLOW_OK;
+}
+
+int dcflow_stub_flows(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
+                      const int32_t *up_branch, const double *x, int32_t n_var, double *flow) {
+  if (!from || !to || !up_branch || !x || !flow) return DCFLOW_E_ARG;
+  if (n_bus < 1 || n_branch < 0 || n_var < 0) return DCFLOW_E_SHAPE;
+  // children before parents: folded buses by decreasing depth below the kept grid
+  std::vector<int> depth(n_bus, -1), folded;
+  for (int b = 0; b < n_bus; ++b) {
+    const int l = up_branch[b];
+    if (l < -1 || l >= n_branch || (l >= 0 && from[l] != b && to[l] != b)) return DCFLOW_E_SHAPE;
+    if (l >= 0) folded.push_back(b);
+  }
+  for (int b : folded) {
+    int d = 0, c = b;
+    while (up_branch[c] >= 0) {
+      const int l = up_branch[c];
+      c = from[l] == c ? to[l] : from[l];
+      if (++d > n_bus) return DCFLOW_E_SHAPE;  // a cycle: not a pruning forest
+    }
+    depth[b] = d;
+  }
+  std::sort(folded.begin(), folded.end(), [&](int a, int b) { return depth[a] > depth[b]; });
+  std::vector<double> sub(n_bus);
+  for (int v = 0; v < n_var; ++v) {
+    const double *xv = x + (size_t)v * n_bus;
+    double *fv = flow + (size_t)v * n_branch;
+    std::fill(fv, fv + n_branch, 0.0);
+    std::copy(xv, xv + n_bus, sub.begin());
+    for (int b : folded) {
+      const int l = up_branch[b], p = from[l] == b ? to[l] : from[l];
+      fv[l] = from[l] == b ? sub[b] : -sub[b];
+      sub[p] += sub[b];
+    }
+  }
+  return DCFLOW_OK;
+}
+
 const char *dcflow_strerror(int st) {
   switch (st) {
     case DCFLOW_OK: return "ok";

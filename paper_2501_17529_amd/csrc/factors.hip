@@ -293,7 +293,8 @@ k_frags(const double *__restrict__ U, int ld_er, const double *__restrict__ inv_
 
 namespace {
 
-// Branch-module step 5 for multi-outage N-1 cases.  With the LODF' numerator
+// Branch-module step 5 for multi-outage N-1 cases (Sec. IV-D: formed once per
+// candidate here, applied to every injection variant by the scan).  With the LODF' numerator
 // columns n_j = col_{s_j} - e_{s_j} of the changed grid (col as above), tripping
 // the branch set S of a case gives p = p1 + sum_j n_j z_j with z = -N^-1 p1[S] and
 // N[i][j] = n_j[s_i]: the flows on every branch of S become zero (Def. eq_modf,

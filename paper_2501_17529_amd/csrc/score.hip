@@ -1003,7 +1003,7 @@ __global__ void __launch_bounds__(64) k_worst_fin(ScanArgs A, dcflow_case *out) 
 }
 
 // ---------------------------------------------------------- multi-outage cases
-// Injection-module step 8c: the N-1 flows of multi-outage case q (branch set S,
+// Injection-module step 8c (Sec. IV-D): the N-1 flows of multi-outage case q (branch set S,
 // m = |S| <= 4) for variant v are p~ = F~ + sum_j L~[:, c_j] z_j with z = coef_q
 // p1[S] (coef_q = -N^-1 from the branch module, c_j the contingency column of the
 // j-th branch).  One thread per monitored row builds the m entries L~[row, c_j] =

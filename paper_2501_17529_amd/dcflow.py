@@ -97,6 +97,10 @@ def _load():
         "dcflow_validate_candidates": (ctypes.c_int, [P, P, ctypes.POINTER(I32),
                                                       ctypes.POINTER(ctypes.c_int64),
                                                       ctypes.POINTER(ctypes.c_int64)]),
+        "dcflow_fold_stubs": (ctypes.c_int, [I32, I32, I32, P, P, P, P, P, P,
+                                             ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "dcflow_fold_injections": (ctypes.c_int, [I32, P, I32, P, I32, P]),
+        "dcflow_stub_flows": (ctypes.c_int, [I32, I32, P, P, P, P, I32, P]),
         "dcflow_batch_bytes": (ctypes.c_int, [P, P, I32, ctypes.POINTER(SZ)]),
         "dcflow_batch_create": (ctypes.c_int, [P, P, I32, P, SZ, P, ctypes.POINTER(P)]),
         "dcflow_batch_destroy": (None, [P]),
@@ -145,6 +149,7 @@ EXPORTED = ("dcflow_plan_workspace_bytes", "dcflow_build_ptdf", "dcflow_plan_vie
             "dcflow_flow_bytes", "dcflow_eval_injections", "dcflow_n1_score",
             "dcflow_batch_variant_max", "dcflow_strerror", "dcflow_n1_worst_workspace_bytes",
             "dcflow_n1_worst", "dcflow_step", "dcflow_set_busbar_injections",
+            "dcflow_fold_stubs", "dcflow_fold_injections", "dcflow_stub_flows",
             "dcflow_batch_set_tuning",
             "dcflow_batch_get_tuning", "dcflow_graph_capture", "dcflow_graph_launch", "dcflow_mlp_param_count",
             "dcflow_mlp_bf16_bytes", "dcflow_mlp_workspace_bytes", "dcflow_snapshot_flows",
@@ -231,6 +236,46 @@ class _CandArgs:
 def cand_args(cands):
     """Candidate arrays from any object with off/kind/id/mask/p_new attributes."""
     return _CandArgs(cands.off, cands.kind, cands.id, cands.mask, getattr(cands, "p_new", None))
+
+
+def fold_stubs(n_bus, f, t, slack=0, protect=None):
+    """dcflow_fold_stubs (host): returns dict(bus_new, branch_new, up_branch, n_bus,
+    n_branch, slack) of the folded grid; ``protect`` is a boolean [n_bus] or None."""
+    f = _arr(f, np.int32)
+    t = _arr(t, np.int32)
+    pr = None if protect is None else _arr(np.asarray(protect, bool), np.uint8)
+    bus_new = np.empty(int(n_bus), np.int32)
+    branch_new = np.empty(len(f), np.int32)
+    up = np.empty(int(n_bus), np.int32)
+    nb, nl = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(_lib.dcflow_fold_stubs(int(n_bus), len(f), int(slack), f.ctypes.data, t.ctypes.data,
+                                  None if pr is None else pr.ctypes.data, bus_new.ctypes.data,
+                                  branch_new.ctypes.data, up.ctypes.data, ctypes.byref(nb),
+                                  ctypes.byref(nl)), "dcflow_fold_stubs")
+    return dict(bus_new=bus_new, branch_new=branch_new, up_branch=up, n_bus=nb.value,
+                n_branch=nl.value, slack=int(bus_new[int(slack)]))
+
+
+def fold_injections(fold, x):
+    """dcflow_fold_injections (host): x [n_var][n_bus] -> [n_var][fold n_bus]."""
+    x = _arr(np.atleast_2d(x), np.float64)
+    out = np.empty((x.shape[0], fold["n_bus"]), np.float64)
+    _check(_lib.dcflow_fold_injections(x.shape[1], fold["bus_new"].ctypes.data, fold["n_bus"],
+                                       x.ctypes.data, x.shape[0], out.ctypes.data),
+           "dcflow_fold_injections")
+    return out
+
+
+def stub_flows(fold, f, t, x):
+    """dcflow_stub_flows (host): flows [n_var][n_branch] of the folded branches."""
+    f = _arr(f, np.int32)
+    t = _arr(t, np.int32)
+    x = _arr(np.atleast_2d(x), np.float64)
+    out = np.empty((x.shape[0], len(f)), np.float64)
+    _check(_lib.dcflow_stub_flows(x.shape[1], len(f), f.ctypes.data, t.ctypes.data,
+                                  fold["up_branch"].ctypes.data, x.ctypes.data, x.shape[0],
+                                  out.ctypes.data), "dcflow_stub_flows")
+    return out
 
 
 def validate_candidates(grid_args: _GridArgs, cands):
