@@ -372,9 +372,11 @@ def main():
                    **({"generator_outages": len(w.gens[0]) if w.gens is not None else 0,
                        "multi_outage_cases": len(w.multi) if w.multi is not None else 0}
                       if a.n1_extras else {})},
-        "roofline": {"bound": "alu", "kernel": "k_scan (per-variant N-1 maxima + winner pass)",
-                     "achieved": achieved, "peak": PEAK_VALU_FMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_VALU_FMA_TFLOPS, "traffic": traffic},
+        # (with --n1-extras the score also runs the multi-outage kernels: no roofline)
+        "roofline": None if a.n1_extras else {
+            "bound": "alu", "kernel": "k_scan (per-variant N-1 maxima + winner pass)",
+            "achieved": achieved, "peak": PEAK_VALU_FMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_VALU_FMA_TFLOPS, "traffic": traffic},
         "phase_ms": {p: {"eval_topologies": float(v["phase_ms"][0]),
                          "eval_injections": float(v["phase_ms"][1]),
                          "n1_score": float(v["phase_ms"][2])} for p, v in res.items()},
