@@ -245,6 +245,55 @@ def ti_sweep(sizes, n_cand, top_k, steps, prec):
         del bt, flows, per_v, pnv, x
 
 
+def rank_sweep(ks, n_cand, steps, prec):
+    """Disconnection sweep (synthetic analogue of the paper's comparison of repeated
+    LODF and MODF over the number of disconnections): n_cand candidates of k
+    remedial outages each (drawn among the medium grid's non-bridges), |T_i| = 1,
+    N-1 over its 500 contingencies.  The k outages of a candidate are joined into
+    one k x k correction (the MODF form).  Prints one JSON line per k: the branch
+    module (eval_topologies) and the whole step."""
+    import torch
+    import gridgen as G
+    from paper_2501_17529_amd import dcflow as D
+    w = G.workload_medium(0, n_cand=1, n_var=1)
+    plan = D.Plan.from_workload(w)
+    rng = np.random.default_rng(11)
+    pool = G.non_bridges(w.grid, rng, 800)
+    x = torch.from_numpy(G.balanced(w.grid.p, w.grid.slack)[None]).cuda()
+    for k in ks:
+        lists = [[(G.KIND_OUTAGE, int(l), 0, 0.0) for l in rng.choice(pool, size=k, replace=False)]
+                 for _ in range(n_cand)]
+        bt = D.Batch(plan, G.Candidates.from_lists(lists), 1)
+        flows, _ = bt.flow_buffer(1, prec)
+        out = torch.empty(bt.n_cand * D.SCORE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+
+        def branch():
+            bt.eval_topologies()
+
+        def step():
+            bt.eval_topologies()
+            bt.eval_injections(x, 1, True, prec, flows=flows)
+            bt.n1_score(flows, 1, prec, out=out)
+
+        res = {}
+        for name, fn in (("branch_module", branch), ("step", step)):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                fn()
+            torch.cuda.synchronize()
+            res[name] = (time.perf_counter() - t0) / steps * 1e3
+        sc = D.Batch.scores_to_numpy(out, bt.n_cand)
+        print(json.dumps({
+            "disconnections": k, "candidates": bt.n_cand, "prec": prec,
+            "branch_module_ms": res["branch_module"], "step_ms": res["step"],
+            "branch_module_us_per_topology": res["branch_module"] * 1e3 / bt.n_cand,
+            "islanded_candidates": int((sc["status"] & 1).sum()),
+        }), flush=True)
+        del bt, flows
+
+
 WORKLOADS = {
     "medium": ("medium-1000bus: 1,000 buses / 1,600 branches, 4,096 candidates (1-3 bus splits + "
                "0-2 outages), 16 injection variants each, N-1 over 500 contingencies = monitored "
@@ -279,6 +328,9 @@ def main():
     ap.add_argument("--n1-extras", default="", metavar="G,Q",
                     help="add G generator outages and Q multi-outage cases (2-4 contingency "
                          "branches each) to the N-1 set of the workload")
+    ap.add_argument("--rank-sweep", default="", metavar="KS",
+                    help="only run the disconnection sweep for the comma-separated numbers of "
+                         "remedial outages per candidate (1..8)")
     ap.add_argument("--ti-sweep", default="", metavar="SIZES",
                     help="only run the |T_i| sweep, metric-first vs output-first, for the "
                          "comma-separated numbers of injection topologies per candidate")
@@ -302,6 +354,10 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 3}))
         return
 
+    if a.rank_sweep:
+        rank_sweep([int(v) for v in a.rank_sweep.split(",")], a.cands or 4096, a.steps,
+                   "fp32" if a.prec == "all" else a.prec)
+        return
     if a.ti_sweep:
         ti_sweep([int(v) for v in a.ti_sweep.split(",")], a.cands or 512, 16, a.steps,
                  "fp32" if a.prec == "all" else a.prec)
