@@ -136,3 +136,38 @@ def test_multi_outages_in_step_chunks():
         for k in ("max_load", "overload_sum", "best_variant", "worst_branch", "worst_outage",
                   "status"):
             assert np.array_equal(got[k], ref[k]), (ch, k)
+
+
+def test_medium_batch_with_extra_cases_sampled():
+    """The medium batch (4,096 candidates x 16 variants, 500 contingencies) with 100
+    generator outages and 100 multi-outage cases, in the launch shapes the bench
+    uses (autotuned FP32 scan, persistent queue allowed): 16 sampled candidates
+    against the oracle."""
+    import torch
+    from paper_2501_17529_amd import autotune
+    from paper_2501_17529_amd import dcflow as D
+    w = G.workload_medium(0)
+    rng = np.random.default_rng(77)
+    w.gens = G.generator_outages(w.grid, rng, 100)
+    w.multi = G.multi_outage_cases(w.grid, w.out, rng, 100)
+    nv = w.n_var
+    plan = D.Plan.from_workload(w)
+    bt = D.Batch(plan, w.cands, nv)
+    bt.eval_topologies()
+    x = torch.from_numpy(np.ascontiguousarray(w.inj)).cuda()
+    flows = bt.eval_injections(x, nv, False, "fp32")
+    autotune.tune_scan(bt, flows, nv, "fp32", reps=2, use_cache=False)
+    out = bt.n1_score(flows, nv, "fp32")
+    torch.cuda.synchronize()
+    gpu = dict(scores=D.Batch.scores_to_numpy(out, bt.n_cand),
+               vmax=bt.variant_max(nv).cpu().numpy(), flows=None)
+    r = oracle_rating(w)
+    idx = sorted(int(i) for i in np.random.default_rng(3).choice(w.cands.n_cand, 16, replace=False))
+    orc = []
+    for j, i in enumerate(idx):   # a few seconds of oracle per candidate
+        orc += oracle_scores(w, [i], r)
+        if j % 4 == 3:
+            say(f"oracle: {j + 1} of {len(idx)} sampled candidates")
+    err = compare(w, gpu, orc, r, idx, "fp32", check_flows=False)
+    say(f"medium batch with 100 generator and 100 multi-outage cases: worst |d max_load| "
+        f"{err:.2e} over 16 sampled candidates, tuning {bt.get_tuning()}")
