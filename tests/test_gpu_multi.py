@@ -171,3 +171,37 @@ def test_medium_batch_with_extra_cases_sampled():
     err = compare(w, gpu, orc, r, idx, "fp32", check_flows=False)
     say(f"medium batch with 100 generator and 100 multi-outage cases: worst |d max_load| "
         f"{err:.2e} over 16 sampled candidates, tuning {bt.get_tuning()}")
+
+
+def test_multi_outages_graph_replay():
+    """A captured step with generator and multi-outage cases replays to the eager
+    scores, with eager work on the same buffers between the replays."""
+    import torch
+    from paper_2501_17529_amd import dcflow as D
+    w = _workload(seed=65)
+    nv = w.inj.shape[1]
+    plan = D.Plan.from_workload(w)
+    bt = D.Batch(plan, w.cands, nv)
+    x = torch.from_numpy(np.ascontiguousarray(w.inj)).cuda()
+    flows, _ = bt.flow_buffer(nv, "fp32")
+    out = torch.empty(bt.n_cand * D.SCORE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    keys = ("max_load", "overload_sum", "best_variant", "worst_branch", "worst_outage", "status")
+    with torch.cuda.stream(s):
+        bt.eval_topologies()
+        bt.eval_injections(x, nv, False, "fp32", flows=flows)
+        bt.n1_score(flows, nv, "fp32", out=out)
+        torch.cuda.synchronize()
+        eager = D.Batch.scores_to_numpy(out, bt.n_cand).copy()
+        bt.capture(x, nv, False, "fp32", flows, out, s)
+        torch.cuda.synchronize()
+        for rep in range(3):
+            out.zero_()
+            bt.replay(s)
+            torch.cuda.synchronize()
+            got = D.Batch.scores_to_numpy(out, bt.n_cand)
+            for k in keys:
+                assert np.array_equal(got[k], eager[k]), (rep, k)
+            other = torch.empty_like(out)
+            bt.n1_score(flows, nv, "fp32", out=other)
+            torch.cuda.synchronize()
