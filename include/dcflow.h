@@ -414,7 +414,7 @@ int dcflow_graph_launch(dcflow_batch *batch, hipStream_t stream);
  * Learned proposal network (an addition: the paper leaves the optimiser that
  * proposes candidates out of scope, Sec. III-A).  A 96 -> 256 -> 256 -> 1 ReLU
  * perceptron scores single-bus-split actions; the exact screen verifies the
- * best-scored ones and exhaustive screening stays the fallback and judge.
+ * best-scored ones and exhaustive screening stays the fallback and arbiter.
  * All pointers are device pointers; buffers are caller-owned.
  * ------------------------------------------------------------------------- */
 #define DCFLOW_MLP_DIN 96     /* feature width (86 used, rest zero)            */

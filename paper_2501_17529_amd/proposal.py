@@ -3,7 +3,7 @@
 A 96 -> 256 -> 256 -> 1 ReLU perceptron, trained on the GPU by the library's
 own kernels on maximum-load labels produced by the exact screen, scores every
 single-split action of a load snapshot; the exact screen then verifies the
-best-scored ones.  Exhaustive screening stays the fallback and the judge.
+best-scored ones.  Exhaustive screening stays the fallback and the arbiter.
 
 All arithmetic runs in libdcflow kernels (features, standardisation, forward,
 backward, Adam, BF16 inference, top-k, exact screen); this module only

@@ -199,7 +199,7 @@ def _tie_recall(ls, top):
 def test_proposal_gain_over_random(medium):
     """Train on 9 load snapshots (about 210k solver-labelled pairs), then on 3
     held-out snapshots let the exact solver evaluate only the network's top-512
-    actions vs 512 random ones; the exhaustive screen is the judge."""
+    actions vs 512 random ones; the exhaustive screen is the arbiter."""
     import torch
     from paper_2501_17529_amd import proposal as PR
     w, plan = medium
@@ -239,7 +239,7 @@ def test_proposal_gain_over_random(medium):
         prop.standardize(f)
         score = prop.infer(f)
         top = PR.topk_smallest(score, 512).cpu().numpy()
-        # exact verification of the proposed 512 (the judge's labels are the exhaustive screen)
+        # exact verification of the proposed 512 (the arbiter's labels are the exhaustive screen)
         ver = PR.exact_scores(plan, PR.action_candidates(bus[top], mask[top], side[top], xs[s]), xs[s])
         np.testing.assert_allclose(ver, ls[top], rtol=0, atol=1e-9)
         best = np.min(ls[np.isfinite(ls)])
