@@ -352,6 +352,23 @@ int dcflow_n1_worst(dcflow_batch *batch, const void *dev_flows, int32_t n_var, d
                     const dcflow_score *dev_scores, int32_t top_k, void *dev_ws, size_t ws_bytes,
                     dcflow_case *dev_out, hipStream_t stream);
 
+/* Bytes of device workspace for dcflow_n1_worst_per_case with this per-case cap. */
+int dcflow_n1_worst_per_case_workspace_bytes(const dcflow_batch *batch, int32_t per_case,
+                                             size_t *bytes);
+
+/* agg_i in the paper's two-level form (Sec. IV-B): the top per_case loads of every
+ * case of the winning variant (the N-0 case, each scored contingency, generator
+ * outage and multi-outage case; over the monitored branches), then the top_k of
+ * that collection, so that no single case fills the list.  Same winner, order,
+ * ids and output layout as dcflow_n1_worst; with per_case >= top_k it returns the
+ * same cases (loads to rounding: these kernels build each LODF' entry with FMAs
+ * instead of the matrix cores).  per_case in 1..DCFLOW_WORST_MAX; dev_ws:
+ * dcflow_n1_worst_per_case_workspace_bytes bytes.  Errors as dcflow_n1_worst. */
+int dcflow_n1_worst_per_case(dcflow_batch *batch, const void *dev_flows, int32_t n_var,
+                             dcflow_prec prec, const dcflow_score *dev_scores, int32_t per_case,
+                             int32_t top_k, void *dev_ws, size_t ws_bytes, dcflow_case *dev_out,
+                             hipStream_t stream);
+
 /* Per-variant maxima of the last n1_score call: device pointer to
  * [n_cand][n_var_max] double (valid after the stream reaches it). */
 const double *dcflow_batch_variant_max(const dcflow_batch *batch);

@@ -532,6 +532,29 @@ def worst_cases(sc, mon, out, k):
     return [(float(flat[j]), int(mon[b]), int(cases[c])) for j, c, b in zip(order, ci, li)]
 
 
+def worst_cases_per_case(sc, mon, out, per_case, k):
+    """agg_i in the two levels of Sec. IV-B: within every case of the winning
+    variant (N-0, each scored contingency, generator and multi-outage case) the
+    per_case largest loads (ties: branch position in `mon`), then the k largest of
+    their collection, ordered as in worst_cases (load descending, then case, then
+    branch position).  A case thus holds at most per_case places."""
+    if sc["best_variant"] < 0:
+        return []
+    mon = np.asarray(mon, np.int64)
+    out = np.asarray(out, np.int64)
+    loads = sc["loads_best"]               # [cases, n_mon]
+    cases = np.asarray([-1] + [int(o) for o in sc["scored_out"]], np.int64)
+    pos = {int(o): i for i, o in enumerate(out)}
+    pos.update({int(o): len(out) - 2 - int(o) for o in sc["scored_out"] if o <= -2})
+    first = [0] + [(pos[int(o)] + 1) * len(mon) for o in cases[1:]]
+    picked = []                            # (load, key, case row, branch position)
+    for ci in range(loads.shape[0]):
+        order = np.lexsort((np.arange(len(mon)), -loads[ci]))[:per_case]
+        picked += [(float(loads[ci, b]), first[ci] + int(b), ci, int(b)) for b in order]
+    picked.sort(key=lambda e: (-e[0], e[1]))
+    return [(v, int(mon[b]), int(cases[ci])) for v, _, ci, b in picked[:k]]
+
+
 def score_workload(w, idx=None, rating=None):
     """Score the candidates ``idx`` (default all) of a gridgen Workload."""
     g = w.grid

@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdcflow.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["abi.hip", "build.hip", "factors.hip", "inject.hip", "score.hip", "mlp.hip",
-           "mlp_abi.hip"]
+SOURCES = ["abi.hip", "build.hip", "factors.hip", "inject.hip", "score.hip", "percase.hip",
+           "mlp.hip", "mlp_abi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 VALU forms are kept off: every kernel is written for the

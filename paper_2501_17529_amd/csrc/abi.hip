@@ -11,6 +11,7 @@
 #include <cstdlib>
 
 #include "dcflow_internal.h"
+#include "percase.h"
 
 using namespace dcflow;
 
@@ -822,6 +823,35 @@ int dcflow_n1_worst(dcflow_batch *b, const void *dev_flows, int32_t n_var, dcflo
   if (ws_bytes < need) return DCFLOW_E_WORKSPACE;
   hipError_t e = launch_worst(b, dev_flows, n_var, prec, dev_scores, top_k, dev_ws, dev_out, s);
   if (e != hipSuccess) return hip_fail(e, "dcflow_n1_worst");
+  return DCFLOW_OK;
+}
+
+int dcflow_n1_worst_per_case_workspace_bytes(const dcflow_batch *b, int32_t per_case,
+                                             size_t *bytes) {
+  if (!b || !bytes || per_case < 1 || per_case > DCFLOW_WORST_MAX) return DCFLOW_E_ARG;
+  // one 16-byte entry (load, key) per list place, case and candidate
+  *bytes = std::max<size_t>((size_t)b->n_cand * per_case_slots(b->plan) * per_case * 16, 256);
+  return DCFLOW_OK;
+}
+
+int dcflow_n1_worst_per_case(dcflow_batch *b, const void *dev_flows, int32_t n_var,
+                             dcflow_prec prec, const dcflow_score *dev_scores, int32_t per_case,
+                             int32_t top_k, void *dev_ws, size_t ws_bytes, dcflow_case *dev_out,
+                             hipStream_t s) {
+  if (!b || !dev_flows || !dev_scores || !dev_ws || !dev_out) return DCFLOW_E_ARG;
+  if (top_k < 1 || top_k > DCFLOW_WORST_MAX) return DCFLOW_E_ARG;
+  if (per_case < 1 || per_case > DCFLOW_WORST_MAX) return DCFLOW_E_ARG;
+  if (n_var < 1 || n_var > b->vmax) return DCFLOW_E_SHAPE;
+  if (!prec_valid(prec)) return DCFLOW_E_ARG;
+  if (!b->factored) return DCFLOW_E_ARG;
+  if (b->flows_prec != prec || b->flows_nvar != n_var) return DCFLOW_E_ARG;
+  if ((int64_t)per_case_slots(b->plan) * b->plan->n_mon > 0x7fffffffLL) return DCFLOW_E_ARG;
+  size_t need = 0;
+  dcflow_n1_worst_per_case_workspace_bytes(b, per_case, &need);
+  if (ws_bytes < need) return DCFLOW_E_WORKSPACE;
+  hipError_t e = launch_worst_per_case(b, dev_flows, n_var, prec, dev_scores, per_case, top_k,
+                                       dev_ws, dev_out, s);
+  if (e != hipSuccess) return hip_fail(e, "dcflow_n1_worst_per_case");
   return DCFLOW_OK;
 }
 

@@ -1,0 +1,380 @@
+// agg_i in two levels (paper Sec. IV-B): for the winning variant t_i* of every
+// candidate, the top per_case loads inside each case (the N-0 case, each scored
+// contingency column, each multi-outage case), then the top_k of that collection.
+// A global top-k would let one dominant outage fill the whole list; the per-case
+// cap keeps the other cases visible.
+//
+// Level 1 runs one thread per case, walking the monitored rows: an LODF' entry is
+// Lsd[row, c] + (U / r)[row, :] W[:, c] (k FMAs), the N-1 flow F~ + L~ y_c, and the
+// thread keeps a sorted list of its case's largest |p~|.  Neighbouring threads
+// hold neighbouring columns, so the seed reads coalesce; U / r and F~ of a row are
+// the same address for the whole wave.  Multi-outage cases use their per-case
+// coefficients z = coef p1[S] and sum the m entries of their branches.  Level 2
+// runs one workgroup per candidate: each thread takes the top_k of its cases'
+// lists, then the block merges the thread lists one entry per round.
+#include "percase.h"
+
+namespace dcflow {
+namespace {
+
+struct PcEntry {  // one list entry: |p| / r and its key (case slot x n_mon + row)
+  double v;
+  int k, pad;
+};
+
+constexpr int kEmptyKey = 0x7fffffff;
+
+__device__ __forceinline__ float pc_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double pc_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T>
+__device__ __forceinline__ bool pc_better(T v, int k, T w, int kw) {
+  return v > w || (v == w && k < kw);
+}
+
+template <typename T, int KM>
+__device__ __forceinline__ void pc_insert(T (&lv)[KM], int (&lk)[KM], T v, int k) {
+#pragma unroll
+  for (int j = KM - 1; j > 0; --j) {
+    const bool up = pc_better(v, k, lv[j - 1], lk[j - 1]);
+    const bool here = pc_better(v, k, lv[j], lk[j]);
+    lv[j] = up ? lv[j - 1] : (here ? v : lv[j]);
+    lk[j] = up ? lk[j - 1] : (here ? k : lk[j]);
+  }
+  if (pc_better(v, k, lv[0], lk[0])) {
+    lv[0] = v;
+    lk[0] = k;
+  }
+}
+
+struct PcArgs {
+  const void *F;  // flows [n_cand][nvar][ld_f]
+  int ld_f, nvar;
+  const int32_t *off;
+  const double *U;  // [n_elem][ld_er]
+  int ld_er;
+  const double *W;  // [n_elem][ld_o]
+  const float *ur32, *w32;
+  int ld_o, mon_pad, n_mon;
+  const double *lsd;     // [mon_pad][ld_o]
+  const double *inv_r;   // [mon_pad]
+  const double *invden;  // [n_cand][ld_o]
+  const uint32_t *isl;   // [n_cand][ld_o / 32]
+  const int32_t *out_pos;
+  int n_out, n_ctg, n_gen;
+  const double *gen_y;
+  int n_multi;
+  const int32_t *moff, *mcol;
+  const double *lsdm;    // [n_msub][mon_pad]
+  const double *mcoef;   // [n_cand][n_multi][16]
+  const int32_t *mok;
+  const int32_t *mon, *out;
+  const dcflow_score *scores;
+  int per_case, top_k, nslots;
+  PcEntry *ws;  // [n_cand][nslots][per_case]
+};
+
+template <typename T>
+struct PcOps;
+template <>
+struct PcOps<double> {
+  static __device__ __forceinline__ double ur(const PcArgs &A, int e, int row) {
+    return A.U[(size_t)e * A.ld_er + row] * A.inv_r[row];
+  }
+  static __device__ __forceinline__ double w(const PcArgs &A, int e, int c) {
+    return A.W[(size_t)e * A.ld_o + c];
+  }
+};
+template <>
+struct PcOps<float> {
+  static __device__ __forceinline__ float ur(const PcArgs &A, int e, int row) {
+    return A.ur32[(size_t)e * A.mon_pad + row];
+  }
+  static __device__ __forceinline__ float w(const PcArgs &A, int e, int c) {
+    return A.w32[(size_t)e * A.ld_o + c];
+  }
+};
+
+__device__ __forceinline__ bool pc_skip(const PcArgs &A, int cand, int &vstar) {
+  const dcflow_score sc = A.scores[cand];
+  vstar = sc.best_variant;
+  return (sc.status & (DCFLOW_ST_DISCONNECTED | DCFLOW_ST_NONFINITE)) != 0 || vstar < 0 ||
+         vstar >= A.nvar;
+}
+
+template <typename T, int KM>
+__device__ __forceinline__ void pc_store(const PcArgs &A, int cand, int slot, const T (&lv)[KM],
+                                         const int (&lk)[KM]) {
+  PcEntry *dst = A.ws + ((size_t)cand * A.nslots + slot) * A.per_case;
+#pragma unroll
+  for (int j = 0; j < KM; ++j)
+    if (j < A.per_case) {
+      PcEntry e;
+      e.v = lk[j] == kEmptyKey ? -1.0 : (double)lv[j];
+      e.k = lk[j];
+      e.pad = 0;
+      dst[j] = e;
+    }
+}
+
+// Level 1, slots 0 .. n_ctg: slot 0 the N-0 case, slot 1 + c contingency column c.
+template <typename T, int KM>
+__global__ void __launch_bounds__(256) k_pc_cols(PcArgs A) {
+  const int cand = blockIdx.x;
+  const int slot = blockIdx.y * blockDim.x + threadIdx.x;
+  if (slot > A.n_ctg) return;
+  T lv[KM];
+  int lk[KM];
+#pragma unroll
+  for (int j = 0; j < KM; ++j) {
+    lv[j] = (T)-1;
+    lk[j] = kEmptyKey;
+  }
+  int vstar = 0;
+  const int c = slot - 1;
+  bool live = !pc_skip(A, cand, vstar);
+  if (live && c >= 0)
+    live = !((A.isl[(size_t)cand * (A.ld_o / 32) + c / 32] >> (c % 32)) & 1u);
+  if (live) {
+    const T *Fv = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vstar) * A.ld_f;
+    const int e0 = A.off[cand], k = A.off[cand + 1] - e0;
+    T y = (T)0, w[kMaxRank];
+#pragma unroll
+    for (int e = 0; e < kMaxRank; ++e) w[e] = (T)0;
+    if (c >= 0) {
+      const double inv = A.invden[(size_t)cand * A.ld_o + c];
+      y = (T)(c < A.n_out ? (double)Fv[A.out_pos[c]] * inv : A.gen_y[c - A.n_out] * inv);
+#pragma unroll
+      for (int e = 0; e < kMaxRank; ++e)
+        if (e < k) w[e] = PcOps<T>::w(A, e0 + e, c);
+    }
+    for (int row = 0; row < A.n_mon; ++row) {
+      const T f = (T)((double)Fv[row] * A.inv_r[row]);
+      T p = f;
+      if (c >= 0) {
+        T l = (T)A.lsd[(size_t)row * A.ld_o + c];
+#pragma unroll
+        for (int e = 0; e < kMaxRank; ++e)
+          if (e < k) l = pc_fma(PcOps<T>::ur(A, e0 + e, row), w[e], l);
+        p = pc_fma(l, y, f);
+      }
+      const T a = p < (T)0 ? -p : p;
+      const int key = slot * A.n_mon + row;
+      if (pc_better(a, key, lv[KM - 1], lk[KM - 1])) pc_insert(lv, lk, a, key);
+    }
+  }
+  pc_store(A, cand, slot, lv, lk);
+}
+
+// Level 1, multi-outage cases: slot 1 + n_ctg + q.
+template <typename T, int KM>
+__global__ void __launch_bounds__(256) k_pc_multi(PcArgs A) {
+  constexpr int MM = DCFLOW_MULTI_MAX;
+  const int cand = blockIdx.x;
+  const int q = blockIdx.y * blockDim.x + threadIdx.x;
+  if (q >= A.n_multi) return;
+  const int slot = 1 + A.n_ctg + q;
+  T lv[KM];
+  int lk[KM];
+#pragma unroll
+  for (int j = 0; j < KM; ++j) {
+    lv[j] = (T)-1;
+    lk[j] = kEmptyKey;
+  }
+  int vstar = 0;
+  const bool live = !pc_skip(A, cand, vstar) && A.mok[(size_t)cand * A.n_multi + q] != 0;
+  if (live) {
+    const T *Fv = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vstar) * A.ld_f;
+    const int e0 = A.off[cand], k = A.off[cand + 1] - e0;
+    const int a = A.moff[q], m = A.moff[q + 1] - a;
+    double p1s[MM];
+#pragma unroll
+    for (int j = 0; j < MM; ++j) p1s[j] = j < m ? (double)Fv[A.out_pos[A.mcol[a + j]]] : 0.0;
+    const double *cq = A.mcoef + ((size_t)cand * A.n_multi + q) * 16;
+    T z[MM], w[MM][kMaxRank];
+#pragma unroll
+    for (int j = 0; j < MM; ++j) {
+      double zz = 0.0;
+#pragma unroll
+      for (int t = 0; t < MM; ++t) zz += cq[j * 4 + t] * p1s[t];
+      z[j] = (T)zz;
+#pragma unroll
+      for (int e = 0; e < kMaxRank; ++e)
+        w[j][e] = (j < m && e < k) ? PcOps<T>::w(A, e0 + e, A.mcol[a + j]) : (T)0;
+    }
+    for (int row = 0; row < A.n_mon; ++row) {
+      T ur[kMaxRank];
+#pragma unroll
+      for (int e = 0; e < kMaxRank; ++e) ur[e] = e < k ? PcOps<T>::ur(A, e0 + e, row) : (T)0;
+      T p = (T)((double)Fv[row] * A.inv_r[row]);
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        if (j < m) {
+          T l = (T)A.lsdm[(size_t)(a + j) * A.mon_pad + row];
+#pragma unroll
+          for (int e = 0; e < kMaxRank; ++e) l = pc_fma(ur[e], w[j][e], l);
+          p = pc_fma(l, z[j], p);
+        }
+      }
+      const T ab = p < (T)0 ? -p : p;
+      const int key = slot * A.n_mon + row;
+      if (pc_better(ab, key, lv[KM - 1], lk[KM - 1])) pc_insert(lv, lk, ab, key);
+    }
+  }
+  pc_store(A, cand, slot, lv, lk);
+}
+
+// Level 2: one workgroup per candidate.  Each thread keeps the top KM of the
+// entries of its slots; the block then takes one entry per round from the heads.
+template <int KM>
+__global__ void __launch_bounds__(256) k_pc_fin(PcArgs A, dcflow_case *out) {
+  __shared__ double s_bv[4];
+  __shared__ int s_bk[4];
+  const int cand = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+  double lv[KM];
+  int lk[KM];
+#pragma unroll
+  for (int j = 0; j < KM; ++j) {
+    lv[j] = -1.0;
+    lk[j] = kEmptyKey;
+  }
+  const PcEntry *base = A.ws + (size_t)cand * A.nslots * A.per_case;
+  for (int s = tid; s < A.nslots; s += blockDim.x)
+    for (int j = 0; j < A.per_case; ++j) {
+      const PcEntry e = base[(size_t)s * A.per_case + j];
+      if (e.k == kEmptyKey) break;  // lists are sorted, empties last
+      if (!pc_better(e.v, e.k, lv[KM - 1], lk[KM - 1])) break;
+      pc_insert(lv, lk, e.v, e.k);
+    }
+  for (int j = 0; j < A.top_k; ++j) {
+    double bv = lv[0];
+    int bk = lk[0];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double ov = __shfl_xor(bv, o);
+      const int ok = __shfl_xor(bk, o);
+      if (pc_better(ov, ok, bv, bk)) {
+        bv = ov;
+        bk = ok;
+      }
+    }
+    if (lane == 0) {
+      s_bv[wv] = bv;
+      s_bk[wv] = bk;
+    }
+    __syncthreads();
+    double wbv = s_bv[0];
+    int wbk = s_bk[0];
+#pragma unroll
+    for (int w = 1; w < 4; ++w)
+      if (pc_better(s_bv[w], s_bk[w], wbv, wbk)) {
+        wbv = s_bv[w];
+        wbk = s_bk[w];
+      }
+    if (tid == 0) {
+      dcflow_case e;
+      if (wbk == kEmptyKey) {
+        e.load = -1.0;
+        e.branch = -1;
+        e.outage = -1;
+      } else {
+        const int slot = wbk / A.n_mon, row = wbk - slot * A.n_mon;
+        e.load = wbv;
+        e.branch = A.mon[row];
+        // slot 0: N-0; 1 + c: contingency column c (branch id, or -2 - g for a
+        // generator); after them the multi-outage cases, -2 - n_gen - q
+        e.outage = slot == 0 ? -1 : (slot - 1 < A.n_out ? A.out[slot - 1] : -2 - (slot - 1 - A.n_out));
+      }
+      out[(size_t)cand * A.top_k + j] = e;
+    }
+    if (wbk != kEmptyKey && lk[0] == wbk) {
+#pragma unroll
+      for (int t = 0; t < KM - 1; ++t) {
+        lv[t] = lv[t + 1];
+        lk[t] = lk[t + 1];
+      }
+      lv[KM - 1] = -1.0;
+      lk[KM - 1] = kEmptyKey;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+hipError_t run_pc(dcflow_batch *bt, const T *flows, int nvar, const dcflow_score *scores,
+                  int per_case, int top_k, void *ws, dcflow_case *out, hipStream_t s) {
+  const dcflow_plan *p = bt->plan;
+  PcArgs a;
+  a.F = flows;
+  a.ld_f = p->ld_er;
+  a.nvar = nvar;
+  a.off = bt->d_off;
+  a.U = bt->d_U;
+  a.ld_er = p->ld_er;
+  a.W = bt->d_W;
+  a.ur32 = bt->d_ur32;
+  a.w32 = bt->d_w32;
+  a.ld_o = p->ld_o;
+  a.mon_pad = p->mon_pad;
+  a.n_mon = p->n_mon;
+  a.lsd = p->d_lsd;
+  a.inv_r = p->d_inv_r;
+  a.invden = bt->d_invden;
+  a.isl = bt->d_isl;
+  a.out_pos = p->d_out_pos;
+  a.n_out = p->n_out;
+  a.n_ctg = p->n_out + p->n_gen;
+  a.n_gen = p->n_gen;
+  a.gen_y = p->d_gen_y;
+  a.n_multi = p->n_multi;
+  a.moff = p->d_moff;
+  a.mcol = p->d_mcol;
+  a.lsdm = p->d_lsdm;
+  a.mcoef = bt->d_mcoef;
+  a.mok = bt->d_mok;
+  a.mon = p->d_mon;
+  a.out = p->d_out;
+  a.scores = scores;
+  a.per_case = per_case;
+  a.top_k = top_k;
+  a.nslots = per_case_slots(p);
+  a.ws = static_cast<PcEntry *>(ws);
+  const unsigned nc = (unsigned)bt->n_cand;
+  const dim3 gcols(nc, (unsigned)((a.n_ctg + 1 + 255) / 256));
+  if (per_case <= 4)
+    k_pc_cols<T, 4><<<gcols, dim3(256), 0, s>>>(a);
+  else
+    k_pc_cols<T, 16><<<gcols, dim3(256), 0, s>>>(a);
+  DCF_CHECK_LAUNCH();
+  if (a.n_multi > 0) {
+    const dim3 gm(nc, (unsigned)((a.n_multi + 255) / 256));
+    if (per_case <= 4)
+      k_pc_multi<T, 4><<<gm, dim3(256), 0, s>>>(a);
+    else
+      k_pc_multi<T, 16><<<gm, dim3(256), 0, s>>>(a);
+    DCF_CHECK_LAUNCH();
+  }
+  if (top_k <= 8)
+    k_pc_fin<8><<<dim3(nc), dim3(256), 0, s>>>(a, out);
+  else
+    k_pc_fin<16><<<dim3(nc), dim3(256), 0, s>>>(a, out);
+  DCF_CHECK_LAUNCH();
+  return hipSuccess;
+}
+
+}  // namespace
+
+int per_case_slots(const dcflow_plan *p) { return 1 + p->n_out + p->n_gen + p->n_multi; }
+
+hipError_t launch_worst_per_case(dcflow_batch *bt, const void *flows, int nvar, int prec,
+                                 const dcflow_score *scores, int per_case, int top_k, void *ws,
+                                 dcflow_case *out, hipStream_t s) {
+  if (bt->n_cand == 0) return hipSuccess;
+  if (prec == DCFLOW_FP64)
+    return run_pc<double>(bt, static_cast<const double *>(flows), nvar, scores, per_case, top_k,
+                          ws, out, s);
+  return run_pc<float>(bt, static_cast<const float *>(flows), nvar, scores, per_case, top_k, ws,
+                       out, s);
+}
+
+}  // namespace dcflow

@@ -97,6 +97,9 @@ def _load():
         "dcflow_validate_candidates": (ctypes.c_int, [P, P, ctypes.POINTER(I32),
                                                       ctypes.POINTER(ctypes.c_int64),
                                                       ctypes.POINTER(ctypes.c_int64)]),
+        "dcflow_n1_worst_per_case_workspace_bytes": (ctypes.c_int, [P, I32, ctypes.POINTER(SZ)]),
+        "dcflow_n1_worst_per_case": (ctypes.c_int, [P, P, I32, ctypes.c_int, P, I32, I32, P, SZ,
+                                                    P, P]),
         "dcflow_fold_stubs": (ctypes.c_int, [I32, I32, I32, P, P, P, P, P, P,
                                              ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "dcflow_fold_injections": (ctypes.c_int, [I32, P, I32, P, I32, P]),
@@ -150,6 +153,7 @@ EXPORTED = ("dcflow_plan_workspace_bytes", "dcflow_build_ptdf", "dcflow_plan_vie
             "dcflow_batch_variant_max", "dcflow_strerror", "dcflow_n1_worst_workspace_bytes",
             "dcflow_n1_worst", "dcflow_step", "dcflow_set_busbar_injections",
             "dcflow_fold_stubs", "dcflow_fold_injections", "dcflow_stub_flows",
+            "dcflow_n1_worst_per_case_workspace_bytes", "dcflow_n1_worst_per_case",
             "dcflow_batch_set_tuning",
             "dcflow_batch_get_tuning", "dcflow_graph_capture", "dcflow_graph_launch", "dcflow_mlp_param_count",
             "dcflow_mlp_bf16_bytes", "dcflow_mlp_workspace_bytes", "dcflow_snapshot_flows",
@@ -446,6 +450,27 @@ class Batch:
                                     ctypes.c_void_p(out.data_ptr()), _stream(stream)),
                "dcflow_n1_worst")
         self._worst_ws = ws  # kept until the stream is done with it (next call or object end)
+        return out
+
+    def n1_worst_per_case(self, flows, n_var, prec, scores, per_case, top_k, out=None,
+                          stream=None):
+        """agg_i in two levels: the top per_case loads of every case of the winning
+        variant, then the top_k of their collection.  Same output as n1_worst."""
+        import torch
+        nb = ctypes.c_size_t(0)
+        _check(_lib.dcflow_n1_worst_per_case_workspace_bytes(self.h, int(per_case),
+                                                             ctypes.byref(nb)),
+               "dcflow_n1_worst_per_case_workspace_bytes")
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=self.plan.device)
+        if out is None:
+            out = torch.empty(max(self.n_cand, 1) * int(top_k) * CASE_DTYPE.itemsize,
+                              dtype=torch.uint8, device=self.plan.device)
+        _check(_lib.dcflow_n1_worst_per_case(
+            self.h, ctypes.c_void_p(flows.data_ptr()), int(n_var), PREC[prec],
+            ctypes.c_void_p(scores.data_ptr()), int(per_case), int(top_k),
+            ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(nb.value),
+            ctypes.c_void_p(out.data_ptr()), _stream(stream)), "dcflow_n1_worst_per_case")
+        self._worst_ws = ws
         return out
 
     @staticmethod

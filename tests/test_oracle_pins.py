@@ -670,3 +670,45 @@ def test_multi_outage_order_with_generators():
                 assert v == pytest.approx(abs(pm[0, q, b]) / r[li], abs=1e-12)
                 seen_multi += 1
     assert seen_multi > 0
+
+
+def test_two_level_worst_cases_by_hand():
+    # the triangle of test_triangle_worst_cases_by_hand: losing edge 2 loads (1.5, 0.5, 0),
+    # edge 0 (0, 1, 1.25), edge 1 (1, 0, 5/12), N-0 (5/6, 1/6, 5/9).  One place per case:
+    # each case's maximum, ordered by load.
+    f = np.array([1, 1, 2])
+    t = np.array([0, 2, 0])
+    x = np.array([[-1.5, 1.0, 0.5]])
+    r = np.array([1.0, 1.0, 1.2])
+    mon = out = np.arange(3)
+    sc = O.score_candidate(3, f, t, np.ones(3), 0, [], x, mon, out, r)
+    got = O.worst_cases_per_case(sc, mon, out, 1, 7)
+    assert [(b, o) for _, b, o in got] == [(0, 2), (2, 0), (0, 1), (0, -1)]
+    np.testing.assert_allclose([v for v, _, _ in got], [1.5, 1.25, 1.0, 5 / 6], atol=1e-14)
+    two = O.worst_cases_per_case(sc, mon, out, 2, 3)
+    assert [(b, o) for _, b, o in two[:2]] == [(0, 2), (2, 0)]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_two_level_worst_cases_reduce_to_global(seed):
+    """With per_case >= k the two levels give the global top-k; with a smaller cap
+    no case holds more than per_case places and every listed load is at least the
+    load of any case's first left-out entry that could have entered."""
+    w = G.workload_tiny(seed)
+    g = w.grid
+    rng = np.random.default_rng(seed)
+    gens = G.generator_outages(g, rng, 4)
+    multi = G.multi_outage_cases(g, w.out, rng, 5)
+    r = O.ratings(g.n_bus, g.f, g.t, g.b, g.slack, g.p, w.mon, 1.0, 0.05)
+    for i in range(6):
+        sc = O.score_candidate(g.n_bus, g.f, g.t, g.b, g.slack, w.cands.elements(i), w.inj,
+                               w.mon, w.out, r, gens=gens, multi=multi)
+        assert O.worst_cases_per_case(sc, w.mon, w.out, 16, 16) == \
+            O.worst_cases(sc, w.mon, w.out, 16)
+        capped = O.worst_cases_per_case(sc, w.mon, w.out, 2, 16)
+        if not capped:
+            continue
+        outs = [o for _, _, o in capped]
+        assert max(outs.count(o) for o in set(outs)) <= 2
+        assert len(capped) == min(16, 2 * sc["loads_best"].shape[0])
+        assert all(a[0] >= b[0] for a, b in zip(capped, capped[1:]))
