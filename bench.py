@@ -167,6 +167,21 @@ def run_path(D, torch, plan, w, prec, steps, warmup, tune=True, graph=True, pers
             for k in ("max_load", "best_variant", "worst_branch", "worst_outage"):
                 assert np.array_equal(sc[k], sc_eager[k]), f"graph replay differs in {k}"
             res["wall"] = res["wall_graph"]
+        # agg_i of the winners after the step (metric-first), outside the timed step:
+        # the global top 16 and the two-level list (3 per case, top 16)
+        agg = {}
+        for name, fn in (("global_top16", lambda: bt.n1_worst(flows, nv, prec, out, 16)),
+                         ("per_case3_top16",
+                          lambda: bt.n1_worst_per_case(flows, nv, prec, out, 3, 16))):
+            fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(3):
+                fn()
+            e1.record(stream)
+            e1.synchronize()
+            agg[name] = e0.elapsed_time(e1) / 3
+        res["agg_i_ms"] = agg
     res["scores"] = sc_eager
     res["batch"] = bt
     return res
@@ -442,6 +457,7 @@ def main():
         "scan_tuning": {p: v.get("tuning") for p, v in res.items()},
         "step_chunks": {p: v.get("step_chunks") for p, v in res.items()},
         "step_chunk_ms": {p: v.get("step_chunk_ms") for p, v in res.items()},
+        "agg_i_ms": {p: v.get("agg_i_ms") for p, v in res.items()},
     }
     for p, v in res.items():
         if p == main_prec:
