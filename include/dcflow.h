@@ -29,6 +29,10 @@
  *                           overload sum and worst (branch, contingency).
  *   dcflow_n1_worst         agg_i: the k worst N-1 cases of the winning
  *                           variant, recomputed after the score (Sec. IV-B).
+ *   dcflow_n1_worst_per_case  agg_i in two levels (a top list per N-1 case,
+ *                           then the top of their collection; Sec. IV-B).
+ *   dcflow_fold_stubs       host preprocessing: radial stubs replaced by their
+ *                           injections at the station (Sec. IV-A).
  *   Together: Eq. solver_end_to_end, (t_b, t_d, T_i) -> (agg_m, agg_i, t_i*).
  *
  * Conventions
