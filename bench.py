@@ -411,7 +411,10 @@ def main():
     n_lf = w.cands.n_cand * w.n_var * (len(w.out) + n_extra)
     res = {}
     for prec in precs:
-        res[prec] = run_path(D, torch, plan, w, prec, a.steps, a.warmup, tune=not a.no_autotune,
+        # (brute: a sweep of launch shapes at 4,096 variants would take minutes; the
+        # library's default shape is timed)
+        res[prec] = run_path(D, torch, plan, w, prec, a.steps, a.warmup,
+                             tune=not a.no_autotune and a.workload != "brute",
                              tune_cache=a.tune_cache or None,
                              graph=not a.no_graph, persistent=a.workload == "uneven")
     main_prec = precs[0]
