@@ -35,6 +35,35 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_medium_traffic.txt")
 
 # ------------------------------------------------------------------ CPU baseline
 
+def host_cores():
+    """The host's CPUs as this process sees them: the logical CPU count, the CPUs
+    it may run on (affinity), the cgroup CPU quota if one is set, and the model.
+    'usable' = the smallest of those limits: every core the job can use."""
+    logical = os.cpu_count() or 1
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = logical
+    quota = None
+    try:
+        q, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = float(q) / float(period)
+    except (OSError, ValueError):
+        pass
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = affinity if quota is None else max(1, min(affinity, int(quota + 0.5)))
+    return dict(logical=logical, affinity=affinity, cgroup_quota=quota, model=model,
+                usable=usable)
+
+
 def _oracle_worker(args):
     from threadpoolctl import threadpool_limits
     from oracle import dcflow_oracle as O
@@ -58,7 +87,7 @@ def cpu_baseline(w, n_sample: int, max_var: int = 0):
     g = w.grid
     rating = O.ratings(g.n_bus, g.f, g.t, g.b, g.slack, g.p, w.mon, w.rating_scale,
                        w.rating_offset)
-    cores = max(1, min(16, os.cpu_count() or 1))
+    cores = host_cores()["usable"]
     def xs(i):
         x = w.inj[i] if not w.inj_shared else w.inj
         return x[:max_var] if max_var else x
@@ -71,6 +100,7 @@ def cpu_baseline(w, n_sample: int, max_var: int = 0):
         lf = sum(pool.map(_oracle_worker, jobs, chunksize=1))
     dt = time.perf_counter() - t0
     return dict(value=lf / dt, unit="loadflows/s", cores=cores, kind="oracle",
+                host=host_cores(),
                 sample=f"first {n_sample} of {w.cands.n_cand} candidates of the same workload"
                        + (f", first {max_var} of {w.n_var} variants" if max_var else "")
                        + f" ({lf} loadflows, {dt:.1f} s wall)")

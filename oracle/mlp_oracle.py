@@ -146,6 +146,31 @@ def forward(params, x):
     return y, (x, z1, h1, z2, h2)
 
 
+def round_bf16(a):
+    """Round to the nearest bfloat16 value, ties to even (the 8-bit-significand
+    format: the upper 16 bits of an IEEE binary32), returned as float64.  The
+    input is first rounded to binary32 (the width the GPU holds it in)."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    keep = (u >> 16) & 1                       # last kept bit: the tie goes to even
+    r = ((u + 0x7FFF + keep) >> 16) << 16
+    nan = np.isnan(np.asarray(a, dtype=np.float32))
+    out = r.astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(nan, np.nan, out)
+
+
+def forward_bf16(params, x):
+    """The forward pass as BF16 inference defines it: the inputs and the first two
+    weight matrices in bfloat16, the first layer's activations stored in bfloat16
+    before the second product, every product summed in wide precision (here
+    FP64), biases, the last layer and the output in full precision."""
+    xb = round_bf16(x)
+    z1 = xb @ round_bf16(params["w1"]) + params["b1"]
+    h1 = round_bf16(np.maximum(z1, 0.0))
+    z2 = h1 @ round_bf16(params["w2"]) + params["b2"]
+    h2 = np.maximum(z2, 0.0)
+    return (h2 @ params["w3"] + params["b3"])[:, 0]
+
+
 def loss(params, x, target):
     y, _ = forward(params, x)
     return float(np.mean((y - target) ** 2))

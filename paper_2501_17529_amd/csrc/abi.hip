@@ -453,8 +453,12 @@ int dcflow_build_ptdf(const dcflow_grid_desc *g, void *dev_ws, size_t ws_bytes, 
     cd.push_back(0.0);
   }
 
+  // uploads; the first failing call's error is kept and named
+  hipError_t up_err = hipSuccess;
   auto up = [&](void *dst, const void *src, size_t bytes) {
-    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    const hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess && up_err == hipSuccess) up_err = e;
+    return e;
   };
   if (up(p->d_f, g->from, 4 * (size_t)d.m) != hipSuccess ||
       up(p->d_t, g->to, 4 * (size_t)d.m) != hipSuccess ||
@@ -478,7 +482,7 @@ int dcflow_build_ptdf(const dcflow_grid_desc *g, void *dev_ws, size_t ws_bytes, 
                         up(p->d_ctl_w, cw.data(), 8 * cw.size()) != hipSuccess ||
                         up(p->d_ctl_d, cd.data(), 8 * cd.size()) != hipSuccess))) {
     delete p;
-    return DCFLOW_E_HIP;
+    return hip_fail(up_err, "dcflow_build_ptdf (upload)");
   }
   hipError_t e = launch_build(p, s, g->rating, g->rating_scale, g->rating_offset);
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // host staging vectors die here
@@ -607,7 +611,7 @@ int dcflow_batch_create(dcflow_plan *p, const dcflow_cands *c, int32_t n_var_max
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // host staging vectors die here
     if (e != hipSuccess) {
       delete b;
-      return DCFLOW_E_HIP;
+      return hip_fail(e, "dcflow_batch_create (upload)");
     }
   }
   *out = b;

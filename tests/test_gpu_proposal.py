@@ -65,10 +65,16 @@ def test_grad_forward_adam_match_reference(medium):
                                     ws.numel(), D._stream()), "grad")
     g = prop.grad.cpu().numpy().astype(np.float64)
     gr = _flat(M.backward(ref, x.astype(np.float64), t.astype(np.float64)))
-    for name, sl in (("w1", slice(0, 96 * 256)), ("w2", slice(96 * 256 + 256, 96 * 256 + 256 + 65536)),
-                     ("all", slice(0, len(gr)))):
-        err = np.linalg.norm(g[sl] - gr[sl]) / np.linalg.norm(gr[sl])
-        assert err <= 1e-4, (name, err)
+    # every parameter block element by element: relative 1e-4, plus an absolute
+    # floor of 2e-5 of the block's largest gradient for entries near zero (FP32
+    # sums over the 96 samples cancel there; their error scales with the terms)
+    o = 0
+    for name, size in (("w1", 96 * 256), ("b1", 256), ("w2", 256 * 256), ("b2", 256),
+                       ("w3", 256), ("b3", 1)):
+        gb, rb = g[o:o + size], gr[o:o + size]
+        o += size
+        np.testing.assert_allclose(gb, rb, rtol=1e-4, atol=2e-5 * np.abs(rb).max(),
+                                   err_msg=f"gradient block {name}")
     assert abs(prop.loss.item() - M.loss(ref, x.astype(np.float64), t)) <= 1e-4 * M.loss(
         ref, x.astype(np.float64), t)
     # two Adam steps against the reference update
@@ -95,11 +101,21 @@ def test_bf16_inference_close_to_fp32(medium):
     x = torch.from_numpy(rng.normal(size=(n, 96)).astype(np.float32)).cuda()
     prop.pack()
     yb = prop.infer(x).cpu().numpy()
-    yr, _ = M.forward(_params_np(prop), x.cpu().numpy().astype(np.float64))
+    xh = x.cpu().numpy().astype(np.float64)
+    yr, _ = M.forward(_params_np(prop), xh)
     err = np.abs(yb - yr).max() / np.abs(yr).std()
     say(f"bf16 max error / output std = {err:.3e}")
     assert err <= 5e-2
     assert np.corrcoef(yb, yr)[0, 1] > 0.999
+    # against the definition of BF16 inference (operands and the stored first-layer
+    # activations rounded to bfloat16, wide sums): what remains is FP32 summation
+    # order, which flips the bfloat16 rounding of an activation now and then (one
+    # step of 2^-8 of it, a few 1e-4 of the output's spread), and never more
+    ye = M.forward_bf16(_params_np(prop), xh)
+    d = np.abs(yb - ye) / np.abs(ye).std()
+    say(f"bf16 vs the bf16 definition: max {d.max():.3e}, median {np.median(d):.3e} of the std")
+    assert d.max() <= 4e-3
+    assert np.median(d) <= 1e-5
 
 
 def test_features_match_reference(medium):

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import gridgen as G
+from oracle import dcflow_oracle as O
 
 from _gpu_common import gpu_available, say
 from test_stub_fold import fold_candidate
@@ -66,5 +67,15 @@ def test_folded_grid_scores_match(prec):
     err = np.abs(fold_vm - full_vm).max()
     assert err <= tol, err
     np.testing.assert_array_equal(fold_sc["status"], full_sc["status"])
+    # the folded-grid scores against the oracle on the unfolded grid (every kept
+    # branch monitored and a contingency, unit ratings)
+    oerr = 0.0
+    for i in range(0, len(pairs), 4):
+        els = [(k, d, m, 0.0) for k, d, m, _ in pairs[i][0]]
+        o = O.score_candidate(g.n_bus, g.f, g.t, g.b, g.slack, els, x, kept, kept, rating)
+        oerr = max(oerr, float(np.abs(fold_vm[i] - o["max_load"]).max()))
+        assert (fold_sc["status"][i] >> 8) == o["n_island"], i
+    assert oerr <= (1e-6 if prec == "fp64" else 1e-4), oerr
     say(f"stub folding {prec}: {fo['n_bus']} of {g.n_bus} buses, {len(kept)} of "
-        f"{g.n_branch} branches kept, {n_moved} moved stubs, max |d max_load| {err:.2e}")
+        f"{g.n_branch} branches kept, {n_moved} moved stubs, max |d max_load| {err:.2e}, "
+        f"against the oracle {oerr:.2e}")

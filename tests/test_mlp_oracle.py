@@ -191,3 +191,42 @@ def test_pair_slots_of_the_feature_vector():
     y = M.action_features(g.n_bus, f, t, np.zeros(len(f)), np.ones(len(f)), g.p, 3, 2, False,
                           (0.5, 0.7), np.zeros(g.n_bus), 1.0, pair_loads=np.ones(8), connected=False)
     assert not y[M.X_PAIRS:M.X_PAIRS + 9].any() and y[M.X_PAIRS + 9] == 1.0
+
+
+def test_round_bf16_by_hand_and_against_torch():
+    """Round-to-nearest-even onto the 8-bit significand: hand values at and
+    around the halfway points, then agreement with torch's CPU conversion."""
+    import torch
+    r = M.round_bf16
+    one = 1.0
+    assert r(one) == 1.0
+    assert r(1 + 2 ** -8) == 1.0                      # tie, 1.0 is even
+    assert r(1 + 3 * 2 ** -8) == 1 + 2 ** -6          # tie, rounds up to the even neighbour
+    assert r(1 + 2 ** -8 + 2 ** -20) == 1 + 2 ** -7   # above the tie
+    assert r(-(1 + 2 ** -8 + 2 ** -20)) == -(1 + 2 ** -7)
+    assert r(0.0) == 0.0 and np.isnan(r(np.nan))
+    rng = np.random.default_rng(0)
+    v = np.concatenate([rng.normal(size=20000) * 10.0 ** rng.integers(-6, 6, size=20000),
+                        np.float32(1.0) + np.arange(-300, 300) * np.float32(2 ** -16)])
+    ref = torch.from_numpy(v.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(r(v), ref)
+
+
+def test_bf16_forward_exact_on_representable_values():
+    """With integer inputs and weights in {-1, 0, 1} (second layer over 64) every
+    operand and first-layer activation is a bfloat16 value, so BF16 inference
+    equals the FP64 forward; a weight moved by less than half a bfloat16 step
+    changes the FP64 forward but not the BF16 one."""
+    rng = np.random.default_rng(1)
+    p = M.init_params(rng)
+    p["w1"] = rng.integers(-1, 2, size=p["w1"].shape).astype(np.float64)
+    p["w1"][0, :] = 1.0
+    p["w2"] = rng.integers(-1, 2, size=p["w2"].shape).astype(np.float64) / 64.0
+    x = rng.integers(-2, 3, size=(5, M.D_IN)).astype(np.float64)
+    x[:, 0] = 1.0
+    y, _ = M.forward(p, x)
+    assert np.array_equal(M.forward_bf16(p, x), y)
+    q = {k: v.copy() for k, v in p.items()}
+    q["w1"][0, :] = 1.0 + 2 ** -12
+    assert np.array_equal(M.forward_bf16(q, x), y)
+    assert not np.array_equal(M.forward(q, x)[0], y)
