@@ -7,10 +7,15 @@ over 500 contingency branches that are also the monitored set):
 dcflow_eval_topologies -> dcflow_eval_injections -> dcflow_n1_score, with the
 candidate records and injections already resident in device memory.
 
-value = N-1 loadflows per second of the mixed path (FP32 MFMA GEMM and FP32
-N-1 scan, FP64 k x k solves / LODF denominators / LODF' tile build);
-loadflows = candidates x variants x contingencies per step.  The plain FP64
-path is timed the same way and reported beside it.
+value = N-1 loadflows per second of the plain FP64 path (the paper's
+precision), loadflows = candidates x variants x contingencies per step.  The
+mixed paths (FP32 and BF16X6 injection GEMM with the FP32 N-1 scan and its
+FP64 error guard) are timed the same way and reported beside it, each with its
+rooflines, its difference to the FP64 path over the whole batch and its error
+against the oracle on the sampled candidates.  The other workloads (30-bus,
+10,000-bus uneven ranks at 65,536 candidates, 2,000-bus control brute force,
+the learned proposal), the end-to-end rate and a repeated-run protocol are
+extra keys of the same line.
 
 Prints one JSON line.
 """
@@ -64,24 +69,37 @@ def host_cores():
                 usable=usable)
 
 
+def _warm(_):
+    """Imports the oracle's modules in a pool process before the timed region."""
+    import threadpoolctl  # noqa: F401
+    from oracle import dcflow_oracle  # noqa: F401
+    return 0
+
+
 def _oracle_worker(args):
     from threadpoolctl import threadpool_limits
     from oracle import dcflow_oracle as O
-    n_bus, f, t, b, slack, elems, x, mon, out, rating, controls, gens, multi = args
+    n_bus, f, t, b, slack, elems, x, mon, out, rating, controls, gens, multi, keep = args
     kw = dict(gens=gens, multi=multi)
     if controls:
         kw.update(controls=controls, ctrl=x[:, n_bus:])
         x = x[:, :n_bus]
     with threadpool_limits(limits=1):
-        O.score_candidate(n_bus, f, t, b, slack, elems, x, mon, out, rating, **kw)
+        sc = O.score_candidate(n_bus, f, t, b, slack, elems, x, mon, out, rating, **kw)
     n_extra = (0 if gens is None else len(gens[0])) + (0 if multi is None else len(multi))
-    return x.shape[0] * (len(out) + n_extra)
+    # what the error report needs: per-variant maxima, islanding count, status and
+    # the N-0 flows of the kept rows
+    res = dict(max_load=sc["max_load"], n_island=sc["n_island"], status=sc["status"])
+    if keep is not None and "p0" in sc["flows"]:
+        res["p0"] = sc["flows"]["p0"][:, keep]
+    return x.shape[0] * (len(out) + n_extra), res
 
 
-def cpu_baseline(w, n_sample: int, max_var: int = 0):
+def cpu_baseline(w, n_sample: int, max_var: int = 0, keep_rows=None):
     """The oracle (dense LU per candidate) on the first n_sample candidates (and
-    their first max_var variants, if given), process-parallel over candidates,
-    one BLAS thread per process."""
+    their first max_var variants, if given), process-parallel over candidates on
+    every usable host core, one BLAS thread per process.  Returns (baseline dict,
+    per-candidate oracle results for the error report)."""
     import multiprocessing as mp
     from oracle import dcflow_oracle as O
     g = w.grid
@@ -92,18 +110,26 @@ def cpu_baseline(w, n_sample: int, max_var: int = 0):
         x = w.inj[i] if not w.inj_shared else w.inj
         return x[:max_var] if max_var else x
     jobs = [(g.n_bus, g.f, g.t, g.b, g.slack, w.cands.elements(i), xs(i), w.mon, w.out, rating,
-             getattr(w, "controls", None), getattr(w, "gens", None), getattr(w, "multi", None))
+             getattr(w, "controls", None), getattr(w, "gens", None), getattr(w, "multi", None),
+             keep_rows)
             for i in range(n_sample)]
-    ctx = mp.get_context("fork")     # forked before this process touches the GPU
-    t0 = time.perf_counter()
-    with ctx.Pool(cores) as pool:
-        lf = sum(pool.map(_oracle_worker, jobs, chunksize=1))
-    dt = time.perf_counter() - t0
-    return dict(value=lf / dt, unit="loadflows/s", cores=cores, kind="oracle",
-                host=host_cores(),
+    # fresh interpreters (this process may already hold the GPU); started and warmed
+    # up before the clock runs
+    ctx = mp.get_context("spawn")
+    nproc = min(cores, max(1, n_sample))
+    with ctx.Pool(nproc) as pool:
+        pool.map(_warm, range(nproc), chunksize=1)
+        t0 = time.perf_counter()
+        outs = pool.map(_oracle_worker, jobs, chunksize=1)
+        dt = time.perf_counter() - t0
+    lf = sum(o[0] for o in outs)
+    base = dict(value=lf / dt, unit="loadflows/s", cores=nproc,
+                kind="oracle",
                 sample=f"first {n_sample} of {w.cands.n_cand} candidates of the same workload"
                        + (f", first {max_var} of {w.n_var} variants" if max_var else "")
-                       + f" ({lf} loadflows, {dt:.1f} s wall)")
+                       + f" ({lf} loadflows, {dt:.1f} s wall)",
+                host=host_cores())
+    return base, [o[1] for o in outs], rating
 
 
 # ------------------------------------------------------------------ GPU timing
@@ -116,11 +142,13 @@ def _source_hash():
 
 
 def run_path(D, torch, plan, w, prec, steps, warmup, tune=True, graph=True, persistent=False,
-             tune_cache=None):
+             tune_cache=None, agg_i=True, tuning=None):
     nv = w.n_var
     bt = D.Batch(plan, w.cands, nv)
     if persistent:
         bt.set_tuning(persistent=1)
+    if tuning:
+        bt.set_tuning(**tuning)
     x = torch.from_numpy(np.ascontiguousarray(w.inj)).cuda()
     flows, _ = bt.flow_buffer(nv, prec)
     out = torch.empty(bt.n_cand * D.SCORE_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
@@ -197,23 +225,26 @@ def run_path(D, torch, plan, w, prec, steps, warmup, tune=True, graph=True, pers
             for k in ("max_load", "best_variant", "worst_branch", "worst_outage"):
                 assert np.array_equal(sc[k], sc_eager[k]), f"graph replay differs in {k}"
             res["wall"] = res["wall_graph"]
-        # agg_i of the winners after the step (metric-first), outside the timed step:
-        # the global top 16 and the two-level list (3 per case, top 16)
-        agg = {}
-        for name, fn in (("global_top16", lambda: bt.n1_worst(flows, nv, prec, out, 16)),
-                         ("per_case3_top16",
-                          lambda: bt.n1_worst_per_case(flows, nv, prec, out, 3, 16))):
-            fn()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(3):
+        if agg_i:
+            # agg_i of the winners after the step (metric-first), outside the timed step:
+            # the global top 16 and the two-level list (3 per case, top 16)
+            agg = {}
+            for name, fn in (("global_top16", lambda: bt.n1_worst(flows, nv, prec, out, 16)),
+                             ("per_case3_top16",
+                              lambda: bt.n1_worst_per_case(flows, nv, prec, out, 3, 16))):
                 fn()
-            e1.record(stream)
-            e1.synchronize()
-            agg[name] = e0.elapsed_time(e1) / 3
-        res["agg_i_ms"] = agg
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(3):
+                    fn()
+                e1.record(stream)
+                e1.synchronize()
+                agg[name] = e0.elapsed_time(e1) / 3
+            res["agg_i_ms"] = agg
     res["scores"] = sc_eager
     res["batch"] = bt
+    res["flows"] = flows
+    res["vmax"] = bt.variant_max(nv).cpu().numpy().copy()
     return res
 
 
@@ -343,14 +374,324 @@ WORKLOADS = {
     "medium": ("medium-1000bus: 1,000 buses / 1,600 branches, 4,096 candidates (1-3 bus splits + "
                "0-2 outages), 16 injection variants each, N-1 over 500 contingencies = monitored "
                "branches"),
-    "uneven": ("uneven-10000bus, one GPU's share: 10,000 buses / 15,500 branches, {n} candidates "
-               "of rank uniform in 1..8 (of the 65,536-candidate batch), 1 injection each, every "
-               "branch monitored, N-1 over 2,000 contingencies, persistent launch"),
+    "uneven": ("uneven-10000bus: 10,000 buses / 15,500 branches, {n} candidates of rank uniform "
+               "in 1..8, 1 injection each, every branch monitored, N-1 over 2,000 contingencies"),
     "brute": ("brute-2000bus: 2,000 buses / 3,100 branches with 20 phase shifters and 4 HVDC "
               "links, {n} topologies x 4,096 shared control/load combinations (one GEMM over the "
               "combinations, control columns folded into K), every branch monitored, N-1 over "
               "1,000 contingencies"),
+    "tiny": ("tiny-30bus: 30 buses / 41 branches, 100 single-split candidates, 1 injection, N-1 "
+             "over all 41 branches"),
 }
+
+# MI355X peaks (TFLOP/s).  VALU: 256 CU x 4 SIMD x 16 lanes x 2 flops (one FMA) x 2.4 GHz for
+# the unpacked FP32 and the FP64 FMA alike; MFMA: the published dense figures.
+PEAK = {"valu": PEAK_VALU_FMA_TFLOPS, "mfma_fp64": 78.6, "mfma_fp32": 157.3, "mfma_bf16": 2500.0}
+HBM_GBS = 8000.0
+PREC_DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x6": "f32 scan, bf16x6 GEMM", "bf16": "bf16"}
+
+
+def ranks(w):
+    return np.diff(np.asarray(w.cands.off))
+
+
+def scan_roofline(w, prec, scan_ms, traffic=None):
+    """The N-1 scan (a5) against the VALU FMA issue rate: 2 flops (one FMA) per N-1
+    element of every variant (V sweeps of E_m x O per candidate), plus the LODF'
+    tile build, k FMAs per (monitored row, contingency) per candidate of rank k."""
+    n_ctg = len(w.out) + (0 if w.gens is None else len(w.gens[0]))
+    per_pair = len(w.mon) * n_ctg
+    flops = 2.0 * per_pair * (w.cands.n_cand * w.n_var + float(ranks(w).sum()))
+    achieved = flops / (scan_ms / 1e3) / 1e12
+    return {"bound": "alu", "kernel": f"n1_score {prec} (k_scan_max + k_scan_win"
+            + (" + error guard" if prec != "fp64" else "") + ")",
+            "achieved": achieved, "peak": PEAK["valu"], "unit": "TFLOP/s",
+            "frac": achieved / PEAK["valu"], "traffic": traffic, "flops_per_call": flops,
+            "ms_per_call": scan_ms}
+
+
+def gemm_roofline(w, plan, prec, inj_ms):
+    """The injection step (a4): per-candidate injections are one GEMM of the kept
+    PTDF rows with every (candidate, variant) column, against the matrix-core peak
+    of its precision (BF16X6: six BF16 products per output); shared injections
+    (the brute-force workload) are one small GEMM and a broadcast of the flows to
+    every topology, bound by writing those flows."""
+    v = plan.view
+    n_inj = v.n_inj
+    if w.inj_shared:
+        nbytes = float(w.cands.n_cand) * w.n_var * v.n_er * (8 if prec == "fp64" else 4)
+        achieved = nbytes / (inj_ms / 1e3) / 1e9
+        return {"bound": "hbm", "kernel": f"eval_injections {prec} (shared GEMM + k_bcast)",
+                "achieved": achieved, "peak": HBM_GBS, "unit": "GB/s", "frac": achieved / HBM_GBS,
+                "traffic": None, "bytes_per_call": nbytes, "ms_per_call": inj_ms}
+    cols = float(w.cands.n_cand) * w.n_var
+    mult = 6.0 if prec == "bf16x6" else 1.0
+    flops = 2.0 * v.n_er * n_inj * cols * mult
+    peak = {"fp64": PEAK["mfma_fp64"], "fp32": PEAK["mfma_fp32"]}.get(prec, PEAK["mfma_bf16"])
+    achieved = flops / (inj_ms / 1e3) / 1e12
+    return {"bound": "mfma", "kernel": f"eval_injections {prec} (k_sense + GEMM)",
+            "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None, "flops_per_call": flops, "ms_per_call": inj_ms}
+
+
+def oracle_error(w, plan, r, oracle_res):
+    """Error of a path against the oracle on the sampled candidates (the first
+    len(oracle_res)): per-variant maxima, islanding counts and the N-0 flows of the
+    kept rows, in rating units (kept rows outside the monitored set: p.u.)."""
+    if not oracle_res:
+        return None
+    sc = r["scores"]
+    nv = w.n_var
+    bt = r["batch"]
+    fl = bt.flows_view(r["flows"], nv)
+    n_er = plan.view.n_er
+    er_mon = len(w.mon)
+    from oracle import dcflow_oracle as O
+    g = w.grid
+    rating = O.ratings(g.n_bus, g.f, g.t, g.b, g.slack, g.p, w.mon, w.rating_scale,
+                       w.rating_offset)
+    rr = np.concatenate([rating, np.ones(n_er - er_mon)])
+    vm_err, fl_err, n_isl_bad = 0.0, 0.0, 0
+    for i, o in enumerate(oracle_res):
+        if not np.all(np.isfinite(o["max_load"])):
+            continue
+        vm_err = max(vm_err, float(np.abs(r["vmax"][i][:len(o["max_load"])] - o["max_load"]).max()))
+        n_isl_bad += int((int(sc["status"][i]) >> 8) != o["n_island"])
+        if "p0" in o:
+            gf = fl[i].double().cpu().numpy()[:len(o["p0"]), :n_er]
+            fl_err = max(fl_err, float((np.abs(gf - o["p0"]) / rr).max()))
+    return {"candidates": len(oracle_res), "variant_max_abs": vm_err,
+            "n0_flows_rel_rating": fl_err, "island_count_mismatches": n_isl_bad}
+
+
+def kept_rows(w):
+    mon = [int(x) for x in w.mon]
+    ms = set(mon)
+    return np.asarray(mon + [int(o) for o in w.out if int(o) not in ms], np.int64)
+
+
+def path_summary(w, plan, r, prec, steps, n_lf, oracle_res, traffic=None, ref=None):
+    ms = r["wall"] / steps * 1e3
+    ph = r["phase_ms"]
+    out = {"value": n_lf / (ms / 1e3), "ms_per_step": ms, "dtype": PREC_DTYPE[prec],
+           "phase_ms": {"eval_topologies": float(ph[0]), "eval_injections": float(ph[1]),
+                        "n1_score": float(ph[2])},
+           "roofline": {"scan": scan_roofline(w, prec, float(ph[2]), traffic),
+                        "injections": gemm_roofline(w, plan, prec, float(ph[1]))},
+           "tuning": r.get("tuning"), "step_chunks": r.get("step_chunks"),
+           "agg_i_ms": r.get("agg_i_ms"),
+           "step_mode": "hip graph replay" if "wall_graph" in r else "eager"}
+    if prec != "fp64":
+        out["guarded_candidates"] = int(((r["scores"]["status"] & 8) != 0).sum())
+    if ref is not None:
+        d = np.abs(r["scores"]["max_load"] - ref["scores"]["max_load"])
+        d = d[np.isfinite(d)]
+        out["vs_fp64_path"] = {"max_load_absdiff_max": float(d.max()) if len(d) else 0.0,
+                               "candidates_over_1e-4": int((d > 1e-4).sum()),
+                               "max_load_absdiff_median": float(np.median(d)) if len(d) else 0.0}
+    out["oracle_error"] = oracle_error(w, plan, r, oracle_res)
+    return out
+
+
+def protocol(bt_replay, runs, min_s, n_lf):
+    """Repeated timed runs of graph replays, each at least min_s seconds."""
+    import torch
+    vals = []
+    for _ in range(runs):
+        n = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while True:
+            for _ in range(20):
+                bt_replay()
+            n += 20
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if dt >= min_s:
+                break
+        vals.append(n_lf * n / dt)
+    return {"runs": runs, "seconds_per_run": min_s, "mean": float(np.mean(vals)),
+            "median": float(np.median(vals)), "min": float(np.min(vals)),
+            "max": float(np.max(vals)), "unit": "loadflows/s"}
+
+
+def end_to_end(D, torch, w, prec):
+    """One cold pass including the one-time base build, the host-to-device copies
+    of the grid, candidates and injections, the step and the copy of the scores
+    back (pageable host memory, as a caller would hold it)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = D.Plan.from_workload(w)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bt = D.Batch(plan, w.cands, w.n_var)
+    x = torch.from_numpy(np.ascontiguousarray(w.inj)).cuda()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    bt.eval_topologies()
+    flows = bt.eval_injections(x, w.n_var, w.inj_shared, prec)
+    out = bt.n1_score(flows, w.n_var, prec)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    sc = D.Batch.scores_to_numpy(out, bt.n_cand)
+    t4 = time.perf_counter()
+    n_lf = w.cands.n_cand * w.n_var * len(w.out)
+    tot = t4 - t0
+    res = {"prec": prec, "build_s": t1 - t0, "h2d_s": t2 - t1, "step_s": t3 - t2,
+           "d2h_s": t4 - t3, "total_s": tot, "loadflows_per_s": n_lf / tot,
+           "h2d_bytes": int(x.numel() * 8), "candidates_scored": int(len(sc))}
+    del bt, flows, x, out, plan
+    return res
+
+
+def section_tiny(D, torch, steps):
+    import gridgen as G
+    w = G.workload_tiny(0)
+    plan = D.Plan.from_workload(w)
+    r = run_path(D, torch, plan, w, "fp64", steps, 3, tune=False, agg_i=False)
+    ms = r["wall"] / steps * 1e3
+    n_lf = w.cands.n_cand * w.n_var * len(w.out)
+    return {"workload": WORKLOADS["tiny"], "prec": "fp64", "ms_per_step": ms,
+            "us_per_candidate": ms * 1e3 / w.cands.n_cand, "value": n_lf / (ms / 1e3),
+            "unit": "loadflows/s", "step_mode": "hip graph replay",
+            "note": "launch-latency bound: 100 candidates fill a fraction of one launch"}
+
+
+def section_uneven(D, torch, n_cand, steps, cpu_n, out_log):
+    """The 10,000-bus uneven-rank batch at its full size on one GPU."""
+    import gridgen as G
+    t0 = time.perf_counter()
+    w = G.workload_uneven(0, n_cand=n_cand)
+    gen_s = time.perf_counter() - t0
+    out_log(f"uneven: {n_cand} candidates generated in {gen_s:.0f} s")
+    cpu, ores = (None, [])
+    if cpu_n:
+        cpu, ores, _ = cpu_baseline(w, cpu_n, keep_rows=kept_rows(w))
+        out_log(f"uneven: oracle sample done ({cpu['sample']})")
+    t0 = time.perf_counter()
+    plan = D.Plan.from_workload(w)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    n_lf = w.cands.n_cand * w.n_var * len(w.out)
+    res, paths = {}, {}
+    tun = {"fp64": dict(scan_band=0), "fp32": dict(scan_band=512), "bf16x6": dict(scan_band=512)}
+    for prec in ("fp64", "fp32", "bf16x6"):
+        r = run_path(D, torch, plan, w, prec, steps, 1, tune=False, graph=False, agg_i=False,
+                     tuning=tun[prec])
+        paths[prec] = path_summary(w, plan, r, prec, steps, n_lf, ores,
+                                   ref=res.get("fp64"))
+        paths[prec]["tuning"] = tun[prec]
+        out_log(f"uneven {prec}: {paths[prec]['ms_per_step']:.1f} ms per step")
+        # keep the FP64 scores for the comparison; free the batch and flows
+        res[prec] = {"scores": r["scores"]}
+        del r
+        torch.cuda.empty_cache()
+    ml = res["fp64"]["scores"]["max_load"]
+    k = ranks(w)
+    return {"workload": WORKLOADS["uneven"].format(n=f"{n_cand:,}"), "candidates": n_cand,
+            "rank_counts": {int(q): int((k == q).sum()) for q in range(1, 9)},
+            "generate_s": gen_s, "build_ptdf_s": build_s, "loadflows_per_step": n_lf,
+            "value": paths["fp64"]["value"], "dtype": "f64", "paths": paths,
+            "fp64_max_load_range": [float(np.min(ml)), float(np.max(ml[np.isfinite(ml)]))],
+            "cpu_baseline": cpu,
+            "device_bytes_note": "one batch of 65,536 candidates holds about 80 GB of factors "
+                                 "(U FP64 37 GB, U/r FP32 18 GB, W 7 GB, BF16 parts 4 GB) plus "
+                                 "8 GB of FP64 flows and 5 GB of injections"}
+
+
+def section_brute(D, torch, n_topo, steps, cpu_n, out_log):
+    import gridgen as G
+    w = G.workload_brute(0, n_topo=n_topo)
+    cpu, ores = (None, [])
+    if cpu_n:
+        cpu, ores, _ = cpu_baseline(w, cpu_n, max_var=128)
+        out_log(f"brute: oracle sample done ({cpu['sample']})")
+    plan = D.Plan.from_workload(w)
+    n_lf = w.cands.n_cand * w.n_var * len(w.out)
+    res, paths = {}, {}
+    for prec in ("fp32", "bf16x6", "fp64"):
+        r = run_path(D, torch, plan, w, prec, steps, 1, tune=False, graph=False, agg_i=False)
+        paths[prec] = path_summary(w, plan, r, prec, steps, n_lf, [],
+                                   ref=None)
+        res[prec] = {"scores": r["scores"]}
+        if ores:
+            # the oracle sample holds the first 128 combinations of each sampled topology
+            errs = [float(np.abs(r["vmax"][i][:len(o["max_load"])] - o["max_load"]).max())
+                    for i, o in enumerate(ores) if np.all(np.isfinite(o["max_load"]))]
+            paths[prec]["oracle_error"] = {"topologies": len(ores), "combinations": 128,
+                                           "variant_max_abs": max(errs) if errs else None}
+        out_log(f"brute {prec}: {paths[prec]['ms_per_step']:.1f} ms per step")
+        del r
+        torch.cuda.empty_cache()
+    for prec in ("fp32", "bf16x6"):
+        d = np.abs(res[prec]["scores"]["max_load"] - res["fp64"]["scores"]["max_load"])
+        d = d[np.isfinite(d)]
+        paths[prec]["vs_fp64_path"] = {"max_load_absdiff_max": float(d.max()),
+                                       "candidates_over_1e-4": int((d > 1e-4).sum())}
+    return {"workload": WORKLOADS["brute"].format(n=f"{n_topo:,}"), "topologies": n_topo,
+            "loadflows_per_step": n_lf, "value": paths["fp64"]["value"], "dtype": "f64",
+            "paths": paths, "cpu_baseline": cpu}
+
+
+def section_proposal(D, torch, reps=5):
+    """The learned proposal on the medium grid: per held-out load snapshot, features
+    of every single-split action, standardisation, fused BF16 inference, top-512
+    and the exact screen of those 512, against the exhaustive exact screen of every
+    action; and one training epoch (forward, backward, Adam) over 2 snapshots'
+    actions.  Timing only (random-initialised weights; the gain is a GPU test)."""
+    import gridgen as G
+    from paper_2501_17529_amd import proposal as PR
+    w = G.workload_medium(0, n_cand=4, n_var=1)
+    g = w.grid
+    plan = D.Plan.from_workload(w)
+    rng = np.random.default_rng(9)
+    xs = G.perturbed_injections(g, rng, (3,), 0.2)
+    bus, mask, side = PR.enumerate_actions(g)
+    na = len(bus)
+    prop = PR.Proposal(plan, seed=1)
+    x_dev, flows, glob = prop.snapshot_summary(xs)
+    snap2 = np.repeat(np.arange(2, dtype=np.int32), na)
+    act2 = np.tile(np.arange(na), 2)
+    feat_t = prop.features(x_dev, flows, glob, snap2, bus[act2], mask[act2], side[act2])
+    yt = torch.zeros(feat_t.shape[0], dtype=torch.float32, device="cuda")
+    prop.set_standardization(feat_t, yt + 1.0)
+    prop.standardize(feat_t)
+    prop.pack()
+    s = 2
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    st = {}
+
+    def feats():
+        st["f"] = prop.features(x_dev, flows, glob, np.full(na, s, np.int32), bus, mask, side)
+        prop.standardize(st["f"])
+    t_feat = timed(feats)
+    t_inf = timed(lambda: st.__setitem__("y", prop.infer(st["f"])))
+    t_top = timed(lambda: st.__setitem__("top", PR.topk_smallest(st["y"], 512)))
+    top = st["top"].cpu().numpy()
+    c512 = PR.action_candidates(bus[top], mask[top], side[top], xs[s])
+    call = PR.action_candidates(bus, mask, side, xs[s])
+    t_ver = timed(lambda: PR.exact_scores(plan, c512, xs[s]))
+    t_exh = timed(lambda: PR.exact_scores(plan, call, xs[s]))
+    t_epoch = timed(lambda: prop.train(feat_t, yt, epochs=1, batch=1024))
+    n_train = (feat_t.shape[0] // 1024) * 1024
+    flops_fwd = 2.0 * (96 * 256 + 256 * 256 + 256)
+    return {"actions": na, "features_ms": t_feat, "infer_ms": t_inf, "topk512_ms": t_top,
+            "verify512_ms": t_ver, "exhaustive_ms": t_exh,
+            "proposal_pipeline_ms": t_feat + t_inf + t_top + t_ver,
+            "infer_tflops": flops_fwd * na / (t_inf / 1e3) / 1e12,
+            "train_epoch_ms": t_epoch, "train_samples": n_train,
+            "train_tflops": 3 * flops_fwd * n_train / (t_epoch / 1e3) / 1e12,
+            "note": "exact-solver calls include their host-side batch set-up; the proposal's "
+                    "gain is measured in exact evaluations by the GPU test"}
 
 
 def main():
@@ -360,13 +701,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="medium")
     ap.add_argument("--cands", type=int, default=0, help="candidates (default: 4,096 medium, "
-                    "8,192 uneven, 1,024 brute)")
+                    "65,536 uneven, 1,024 brute)")
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="oracle sample size (default: 128 medium, 2 uneven, 1 brute)")
+                    help="oracle sample size (default: 128 medium, 16 uneven, 1 brute)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", choices=["all", "fp32", "fp64", "bf16x6", "bf16"], default="all")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--quick", action="store_true",
+                    help="the medium workload only: no other configurations, no repeated-run "
+                         "protocol, no end-to-end pass")
+    ap.add_argument("--protocol-runs", type=int, default=5)
+    ap.add_argument("--protocol-s", type=float, default=10.0)
     ap.add_argument("--tune-cache", default="", metavar="PATH",
                     help="autotuner cache file: shapes found there are reused without a sweep "
                          "(so that a profiled run times the same launch shapes as the bench run)")
@@ -387,6 +733,10 @@ def main():
               "(candidates would shard across GPUs with no communication)",
               file=sys.stderr)
         sys.exit(2)
+    t_start = time.perf_counter()
+
+    def log(msg):
+        print(f"[bench {time.perf_counter() - t_start:6.1f} s] {msg}", file=sys.stderr, flush=True)
 
     if a.copy_calibration:
         import torch
@@ -409,25 +759,35 @@ def main():
         return
 
     import gridgen as G
-    if a.workload == "medium":
-        w = G.workload_medium(0, n_cand=a.cands or 4096)
-        precs = ["fp32", "fp64", "bf16x6"] if a.prec == "all" else [a.prec]
-        sample = a.cpu_sample or 128
-    elif a.workload == "uneven":
-        w = G.workload_uneven(0, n_cand=a.cands or 8192)
-        precs = ["fp32", "bf16x6"] if a.prec == "all" else [a.prec]
-        sample = a.cpu_sample or 2
-    else:
-        w = G.workload_brute(0, n_topo=a.cands or 1024)
-        precs = ["fp32", "bf16x6"] if a.prec == "all" else [a.prec]
-        sample = a.cpu_sample or 1
+    if a.workload != "medium":
+        # one of the other configurations alone, as its own line
+        import torch
+        from paper_2501_17529_amd import dcflow as D
+        torch.cuda.init()
+        if a.workload == "uneven":
+            sec = section_uneven(D, torch, a.cands or 65536, a.steps,
+                                 0 if a.no_cpu_baseline else (a.cpu_sample or 16), log)
+        elif a.workload == "brute":
+            sec = section_brute(D, torch, a.cands or 1024, a.steps,
+                                0 if a.no_cpu_baseline else (a.cpu_sample or 1), log)
+        else:
+            sec = section_tiny(D, torch, a.steps)
+        sec["wall_s"] = time.perf_counter() - t_start
+        print(json.dumps(sec), flush=True)
+        return
+
+    w = G.workload_medium(0, n_cand=a.cands or 4096)
+    precs = ["fp64", "fp32", "bf16x6"] if a.prec == "all" else [a.prec]
+    sample = a.cpu_sample or 128
     if a.n1_extras:
         n_g, n_q = (int(v) for v in a.n1_extras.split(","))
         rng = np.random.default_rng(77)
         w.gens = G.generator_outages(w.grid, rng, n_g) if n_g else None
         w.multi = G.multi_outage_cases(w.grid, w.out, rng, n_q) if n_q else None
-    max_var = 128 if a.workload == "brute" else 0   # the oracle holds all N-1 flows at once
-    cpu = None if a.no_cpu_baseline else cpu_baseline(w, min(sample, w.cands.n_cand), max_var)
+    cpu, ores = None, []
+    if not a.no_cpu_baseline:
+        cpu, ores, _ = cpu_baseline(w, min(sample, w.cands.n_cand), keep_rows=kept_rows(w))
+        log(f"medium: oracle sample done ({cpu['sample']})")
 
     import torch
     from paper_2501_17529_amd import dcflow as D
@@ -439,68 +799,70 @@ def main():
 
     n_extra = (0 if w.gens is None else len(w.gens[0])) + (0 if w.multi is None else len(w.multi))
     n_lf = w.cands.n_cand * w.n_var * (len(w.out) + n_extra)
-    res = {}
+    traffic = None
+    if not a.n1_extras and os.path.exists(TRAFFIC_FILE):
+        tf = json.load(open(TRAFFIC_FILE))
+        if tf.get("source_hash") == _source_hash():
+            traffic = tf
+    res, paths = {}, {}
     for prec in precs:
-        # (brute: a sweep of launch shapes at 4,096 variants would take minutes; the
-        # library's default shape is timed)
         res[prec] = run_path(D, torch, plan, w, prec, a.steps, a.warmup,
-                             tune=not a.no_autotune and a.workload != "brute",
-                             tune_cache=a.tune_cache or None,
-                             graph=not a.no_graph, persistent=a.workload == "uneven")
+                             tune=not a.no_autotune, tune_cache=a.tune_cache or None,
+                             graph=not a.no_graph)
+        tr = traffic.get("bytes_per_launch") if traffic and traffic.get("prec") == prec else None
+        paths[prec] = path_summary(w, plan, res[prec], prec, a.steps, n_lf, ores, traffic=tr,
+                                   ref=res.get("fp64"))
+        log(f"medium {prec}: {paths[prec]['ms_per_step']:.3f} ms per step")
     main_prec = precs[0]
     r = res[main_prec]
-    ms = r["wall"] / a.steps * 1e3
-    value = n_lf / (ms / 1e3)
-
-    # roofline of the dominant kernel (the N-1 scan, both passes): 2 flops (one FMA) per N-1
-    # element, (V + 1) variant sweeps (the winner is re-scanned once; with one variant the
-    # winner pass is the only sweep) over E_m x O per candidate
-    scan_ms = float(r["phase_ms"][2])
-    sweeps = w.n_var + 1 if w.n_var > 1 else 1
-    flops = 2.0 * w.cands.n_cand * sweeps * len(w.mon) * len(w.out)
-    achieved = flops / (scan_ms / 1e3) / 1e12
-    traffic = None
-    if a.workload == "medium" and not a.n1_extras and os.path.exists(TRAFFIC_FILE):
-        tf = json.load(open(TRAFFIC_FILE))
-        if tf.get("source_hash") == _source_hash() and tf.get("prec") == main_prec:
-            traffic = tf.get("bytes_per_launch")
+    mp_ = paths[main_prec]
+    proto = None
+    if not a.quick and a.protocol_runs > 0 and "wall_graph" in r:
+        bt = r["batch"]
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            proto = protocol(lambda: bt.replay(stream), a.protocol_runs, a.protocol_s, n_lf)
+        log(f"protocol: mean {proto['mean']:.3e} loadflows/s")
     g = w.grid
     line = {
-        "metric": METRIC, "value": value, "unit": "loadflows/s", "n_gpus": 1,
-        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": main_prec, "data": "synthetic",
-        "config": {"workload": WORKLOADS[a.workload].format(n=f"{w.cands.n_cand:,}"),
+        "metric": METRIC, "value": mp_["value"], "unit": "loadflows/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": mp_["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": PREC_DTYPE[main_prec], "data": "synthetic",
+        "config": {"workload": WORKLOADS["medium"],
                    "n_bus": g.n_bus, "n_branch": g.n_branch, "candidates": w.cands.n_cand,
                    "variants": w.n_var, "contingencies": len(w.out), "monitored": len(w.mon),
                    "loadflows_per_step": n_lf, "parallelism": "single GPU",
                    **({"generator_outages": len(w.gens[0]) if w.gens is not None else 0,
                        "multi_outage_cases": len(w.multi) if w.multi is not None else 0}
                       if a.n1_extras else {})},
-        # (with --n1-extras the score also runs the multi-outage kernels: no roofline)
+        # the dominant kernel of the headline path: its N-1 scan
         "roofline": None if a.n1_extras else {
-            "bound": "alu", "kernel": "k_scan (per-variant N-1 maxima + winner pass)",
-            "achieved": achieved, "peak": PEAK_VALU_FMA_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_VALU_FMA_TFLOPS, "traffic": traffic},
-        "phase_ms": {p: {"eval_topologies": float(v["phase_ms"][0]),
-                         "eval_injections": float(v["phase_ms"][1]),
-                         "n1_score": float(v["phase_ms"][2])} for p, v in res.items()},
+            k: v for k, v in mp_["roofline"]["scan"].items()
+            if k in ("bound", "kernel", "achieved", "peak", "unit", "frac", "traffic")},
+        "paths": paths,
         "build_ptdf_s": build_s,
-        "step_mode": "hip graph replay" if "wall_graph" in r else "eager",
-        "eager_ms_per_step": r["wall_eager"] / a.steps * 1e3,
-        "scan_tuning": {p: v.get("tuning") for p, v in res.items()},
-        "step_chunks": {p: v.get("step_chunks") for p, v in res.items()},
-        "step_chunk_ms": {p: v.get("step_chunk_ms") for p, v in res.items()},
-        "agg_i_ms": {p: v.get("agg_i_ms") for p, v in res.items()},
     }
-    for p, v in res.items():
-        if p == main_prec:
-            continue
-        msp = v["wall"] / a.steps * 1e3
-        line[f"{p}_path"] = {"value": n_lf / (msp / 1e3), "ms_per_step": msp}
-        if p != "bf16":
-            line[f"{main_prec}_vs_{p}_max_load_absdiff"] = float(
-                np.abs(r["scores"]["max_load"] - v["scores"]["max_load"]).max())
+    for p in precs:
+        for key in ("batch", "flows"):
+            res[p].pop(key, None)
+    del res
+    torch.cuda.empty_cache()
+    if not a.quick:
+        line["end_to_end"] = end_to_end(D, torch, w, main_prec)
+        log("end-to-end pass done")
+    line["protocol"] = proto
+    if not a.quick:
+        cfgs = {}
+        cfgs["tiny"] = section_tiny(D, torch, a.steps)
+        log("tiny done")
+        cfgs["proposal"] = section_proposal(D, torch)
+        log("proposal done")
+        cfgs["brute"] = section_brute(D, torch, 1024, 2, 0 if a.no_cpu_baseline else 1, log)
+        cfgs["uneven"] = section_uneven(D, torch, 65536, 2, 0 if a.no_cpu_baseline else 16, log)
+        line["configs"] = cfgs
     line["cpu_baseline"] = cpu
+    line["wall_s"] = time.perf_counter() - t_start
     print(json.dumps(line), flush=True)
 
 

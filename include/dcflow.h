@@ -101,6 +101,9 @@ typedef enum {
 #define DCFLOW_ST_DISCONNECTED 0x1u /* candidate grid islanded: max_load=+inf  */
 #define DCFLOW_ST_SINGULAR 0x2u     /* k x k correction singular (implies 0x1) */
 #define DCFLOW_ST_NONFINITE 0x4u    /* NaN/Inf met in the injections or flows  */
+#define DCFLOW_ST_GUARDED 0x8u      /* reduced precision: some contingency columns
+                                       were computed in FP64 by the error guard
+                                       (see dcflow_tuning.guard_tol)              */
 #define DCFLOW_ST_ISLAND_SHIFT 8    /* bits 8..31: number of islanding N-1 cases */
 
 /* Grid description (host pointers, read during dcflow_build_ptdf only). */
@@ -387,7 +390,8 @@ const char *dcflow_strerror(int status);
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t scan_vc;     /* variants per pass-1 workgroup: 0 = automatic; FP32 runs accept
-                          16, 8, 4, 1 and FP64 runs 8, 4, 2, 1 (others: automatic) */
+                          16, 8, 4, 1 and FP64 runs 16, 8, 4, 1 (others: automatic;
+                          16 in FP64 needs more than 64 KB of LDS per workgroup) */
   int32_t scan_rchunk; /* monitored rows per LDS chunk, a multiple of 64; 0 = automatic */
   int32_t persistent;  /* nonzero: the scan runs as resident workgroups (4 per compute
                           unit) that take work items from a queue                    */
@@ -399,6 +403,16 @@ typedef struct {
                           the injections of chunk i + 1 running beside the scan of
                           chunk i on a second stream of the batch (per-candidate
                           injections only; the results are the same)               */
+  double guard_tol;    /* error guard of the reduced-precision scan (FP32, BF16,
+                          BF16X6), in rating units: per candidate, a contingency column
+                          whose FP32 error bound (k + 4) 2^-24 S_c max_v |y_cv| exceeds
+                          it (S_c = max_l |Lsd[l, c]| + sum_j max_l |U_j[l] / r_l|
+                          |W_j[c]|, a bound of the LODF' entries' magnitude sums; y_cv
+                          = F'[c, v] / den_c) is left out of the FP32 tiles and computed
+                          in FP64 from the FP64 factors (U, W, seed) and the flows, in
+                          n1_score, n1_worst and n1_worst_per_case alike; such
+                          candidates carry DCFLOW_ST_GUARDED.  0 = the default 4e-5;
+                          negative = off (every column in FP32)                     */
 } dcflow_tuning;
 
 /* Sets / reads the batch's launch shapes (defaults: all zero).  E_ARG for a

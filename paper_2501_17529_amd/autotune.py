@@ -19,7 +19,7 @@ import numpy as np
 
 from . import dcflow as D
 
-VC_SETS = {"fp32": (16, 8, 4, 1), "fp64": (8, 4, 2, 1)}
+VC_SETS = {"fp32": (16, 8, 4, 1), "fp64": (16, 8, 4, 1)}
 
 
 def cache_path() -> str:

@@ -130,7 +130,7 @@ bool grid_connected(const dcflow_grid_desc *g) {
 }
 
 struct Dims {
-  int n, m, n_mon, n_out, n_gen, n_multi, n_msub, n_er, ld_h, ld_er, ld_o, mon_pad, n_ctrl;
+  int n, m, n_mon, n_out, n_gen, n_multi, n_msub, n_er, ld_h, ld_er, ld_o, mon_pad, n_ctrl, ld_b;
 };
 
 Dims grid_dims(const dcflow_grid_desc *g) {
@@ -149,6 +149,7 @@ Dims grid_dims(const dcflow_grid_desc *g) {
   d.n_er = d.n_mon + extra;
   d.n_ctrl = g->n_pst + g->n_hvdc;
   d.ld_h = round_up(d.n + d.n_ctrl, 16);
+  d.ld_b = round_up(d.n, 64);
   d.ld_er = round_up(d.n_er, 128);
   d.ld_o = std::max(64, round_up(d.n_out + d.n_gen, 64));
   d.mon_pad = round_up(d.n_mon, 64);
@@ -174,8 +175,8 @@ void plan_layout(dcflow_plan *p, const Dims &d, Arena &a) {
   p->d_mcol = a.take<int32_t>(std::max(d.n_msub, 1));
   p->d_lsdm = a.take<double>((size_t)d.n_msub * d.mon_pad);
   p->d_lsdm32 = a.take<float>((size_t)d.n_msub * d.mon_pad);
-  p->d_binv = a.take<double>((size_t)d.ld_h * d.ld_h);
-  p->d_piv = a.take<double>(4 * (size_t)d.ld_h);
+  p->d_binv = a.take<double>((size_t)d.ld_b * d.ld_b);
+  p->d_piv = a.take<double>(64 * 64);
   p->d_hb = a.take<double>((size_t)d.m * d.ld_h);
   p->d_ht = a.take<double>((size_t)d.n * d.ld_er);
   p->d_he64 = a.take<double>((size_t)d.ld_er * d.ld_h);
@@ -183,6 +184,7 @@ void plan_layout(dcflow_plan *p, const Dims &d, Arena &a) {
   p->d_heb = a.take<__bf16>(3 * (size_t)d.ld_er * d.ld_h);
   p->d_hdo = a.take<double>((size_t)d.m * d.ld_o);
   p->d_lsd = a.take<double>((size_t)d.mon_pad * d.ld_o);
+  p->d_lsdmax = a.take<double>(d.ld_o);
   p->d_lsd32 = a.take<float>((size_t)d.mon_pad * d.ld_o);
   p->d_fbase = a.take<double>(d.m);
   p->d_fber = a.take<double>(d.ld_er);
@@ -215,6 +217,9 @@ void batch_layout(dcflow_batch *b, const dcflow_plan *p, const BatchDims &d, Are
   b->d_W = a.take<double>(ne * p->ld_o);
   b->d_ur32 = a.take<float>(ne * p->mon_pad);
   b->d_w32 = a.take<float>(ne * p->ld_o);
+  b->d_umax = a.take<float>(ne);
+  b->d_flag = a.take<uint32_t>(nc * (p->ld_o / 32));
+  b->d_nflag = a.take<int32_t>(nc);
   b->d_kinv = a.take<double>(nc * 64);
   b->d_invden = a.take<double>(nc * p->ld_o);
   b->d_isl = a.take<uint32_t>(nc * (p->ld_o / 32));
@@ -235,7 +240,7 @@ void batch_layout(dcflow_batch *b, const dcflow_plan *p, const BatchDims &d, Are
   b->d_xs = a.take<__bf16>(3 * b->xs_cols * (size_t)b->ldx);
   b->d_queue = a.take<int32_t>(16);
   const size_t nmb = p->n_multi > 0 ? (p->n_mon + kMultiRows - 1) / kMultiRows : 0;
-  const size_t np = nc * (size_t)(p->mon_pad / 64 + nmb);
+  const size_t np = nc * (size_t)(p->mon_pad / 64 + nmb + 1);  // + the guard's slot
   b->d_part_m = a.take<double>(np);
   b->d_part_ov = a.take<double>(np);
   b->d_part_k = a.take<long long>(np);
@@ -380,6 +385,7 @@ int dcflow_build_ptdf(const dcflow_grid_desc *g, void *dev_ws, size_t ws_bytes, 
   p->n_msub = d.n_msub;
   p->n_er = d.n_er;
   p->ld_h = d.ld_h;
+  p->ld_b = d.ld_b;
   p->ld_er = d.ld_er;
   p->ld_o = d.ld_o;
   p->mon_pad = d.mon_pad;
@@ -568,9 +574,10 @@ int dcflow_batch_create(dcflow_plan *p, const dcflow_cands *c, int32_t n_var_max
   b->factored = 0;
   b->flows_prec = -1;
   b->flows_nvar = 0;
+  b->guard_valid = 0;
   b->d_pnv = nullptr;
   b->pnv_nvar = 0;
-  b->tune = dcflow_tuning{0, 0, 0, 0, 0};
+  b->tune = dcflow_tuning{0, 0, 0, 0, 0, 0.0};
   b->aux = nullptr;
   for (int i = 0; i <= kMaxStepChunks; ++i) b->step_ev[i] = nullptr;
   b->max_bands = p->mon_pad / 64;
@@ -584,6 +591,11 @@ int dcflow_batch_create(dcflow_plan *p, const dcflow_cands *c, int32_t n_var_max
         ncu < 1)
       ncu = 256;
     b->n_cu = ncu;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        lds < 64 * 1024)
+      lds = 64 * 1024;
+    b->lds_max = (size_t)lds;
   }
   if (d.n_cand > 0) {
     // work queue: descending rank, stable
@@ -655,6 +667,7 @@ int run_step(dcflow_batch *b, const double *inj, int nvar, int shared, int prec,
   hipError_t e = launch_factors(b, s);
   if (e != hipSuccess) return hip_fail(e, "dcflow_step");
   b->factored = 1;
+  b->guard_valid = 0;
   int nch = b->tune.step_chunks;
   if (shared || nch > b->n_cand) nch = shared ? 1 : b->n_cand;
   if (nch <= 1) {
@@ -695,7 +708,7 @@ int dcflow_batch_set_tuning(dcflow_batch *b, const dcflow_tuning *t) {
   if (!b || !t) return DCFLOW_E_ARG;
   if (t->scan_vc < 0 || t->scan_rchunk < 0 || t->scan_rchunk % 64 || t->persistent < 0 ||
       t->scan_band < 0 || t->scan_band % 64 || t->step_chunks < 0 ||
-      t->step_chunks > kMaxStepChunks)
+      t->step_chunks > kMaxStepChunks || !std::isfinite(t->guard_tol))
     return DCFLOW_E_ARG;
   if (t->step_chunks > 1) {
     const hipError_t e = ensure_step_streams(b);
@@ -758,6 +771,7 @@ int dcflow_eval_topologies(dcflow_batch *b, hipStream_t s) {
   hipError_t e = launch_factors(b, s);
   if (e != hipSuccess) return hip_fail(e, "dcflow_eval_topologies");
   b->factored = 1;
+  b->guard_valid = 0;
   return DCFLOW_OK;
 }
 
@@ -786,6 +800,7 @@ int dcflow_eval_injections(dcflow_batch *b, const double *dev_inj, int32_t n_var
       launch_injections(b, dev_inj, n_var, inj_shared ? 1 : 0, prec, dev_flows, 0, b->n_cand, s);
   if (e != hipSuccess) return hip_fail(e, "dcflow_eval_injections");
   b->flows_prec = prec;
+  b->guard_valid = 0;
   b->flows_nvar = n_var;
   return DCFLOW_OK;
 }
@@ -806,14 +821,18 @@ int dcflow_n1_worst_workspace_bytes(const dcflow_batch *b, int32_t top_k, size_t
   if (!b || !bytes || top_k < 1 || top_k > DCFLOW_WORST_MAX) return DCFLOW_E_ARG;
   // one 16-byte entry (load, key) per case, band and candidate
   *bytes = std::max<size_t>(
-      (size_t)b->n_cand * (worst_bands(b->plan) + b->nmb) * top_k * 16, 256);
+      (size_t)b->n_cand * (worst_bands(b->plan) + b->nmb + 1) * top_k * 16, 256);
   return DCFLOW_OK;
 }
 
-int dcflow_n1_worst(dcflow_batch *b, const void *dev_flows, int32_t n_var, dcflow_prec prec,
-                    const dcflow_score *dev_scores, int32_t top_k, void *dev_ws, size_t ws_bytes,
-                    dcflow_case *dev_out, hipStream_t s) {
-  if (!b || !dev_flows || !dev_scores || !dev_ws || !dev_out) return DCFLOW_E_ARG;
+}  // extern "C"
+
+namespace {
+// Arguments of dcflow_n1_worst and its allocation-free variant (all but the workspace).
+int check_worst_args(const dcflow_batch *b, const void *dev_flows, int32_t n_var,
+                     dcflow_prec prec, const dcflow_score *dev_scores, int32_t top_k,
+                     const dcflow_case *dev_out) {
+  if (!b || !dev_flows || !dev_scores || !dev_out) return DCFLOW_E_ARG;
   if (top_k < 1 || top_k > DCFLOW_WORST_MAX) return DCFLOW_E_ARG;
   if (n_var < 1 || n_var > b->vmax) return DCFLOW_E_SHAPE;
   if (!prec_valid(prec)) return DCFLOW_E_ARG;
@@ -822,6 +841,18 @@ int dcflow_n1_worst(dcflow_batch *b, const void *dev_flows, int32_t n_var, dcflo
   if (((int64_t)b->plan->n_out + b->plan->n_gen + b->plan->n_multi + 1) * b->plan->n_mon >
       0x7fffffffLL)
     return DCFLOW_E_ARG;
+  return DCFLOW_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int dcflow_n1_worst(dcflow_batch *b, const void *dev_flows, int32_t n_var, dcflow_prec prec,
+                    const dcflow_score *dev_scores, int32_t top_k, void *dev_ws, size_t ws_bytes,
+                    dcflow_case *dev_out, hipStream_t s) {
+  if (!dev_ws) return DCFLOW_E_ARG;
+  const int st = check_worst_args(b, dev_flows, n_var, prec, dev_scores, top_k, dev_out);
+  if (st != DCFLOW_OK) return st;
   size_t need = 0;
   dcflow_n1_worst_workspace_bytes(b, top_k, &need);
   if (ws_bytes < need) return DCFLOW_E_WORKSPACE;

@@ -3,9 +3,10 @@
 //
 //   B'  : slack-reduced nodal susceptance matrix (Laplacian), assembled per bus
 //         from the adjacency lists (no atomics, deterministic);
-//   B'^-1 by in-place Gauss-Jordan (B' is symmetric positive definite for a
-//         connected grid, so no pivoting is needed); the slack row/column are a
-//         unit so the matrix stays n x n;
+//   B'^-1 by in-place blocked Gauss-Jordan (B' is symmetric positive definite
+//         for a connected grid, so no pivoting is needed; the trailing updates
+//         run on the FP64 matrix cores); the slack row/column are a unit so the
+//         matrix stays n x n;
 //   PTDF rows H[l, x] = b_l (B'^-1[f_l, x] - B'^-1[t_l, x]), slack column 0,
 //         which is PTDF' = C_w' B'^-1 written out per row;
 //   derived operands: node-major kept rows (column gathers of the branch
@@ -50,44 +51,160 @@ __global__ void k_assemble(double *B, int ld, int n, int slack, const int32_t *a
   row[i] += diag;
 }
 
-// Save pivot row/column 0 before the first Gauss-Jordan step.
-__global__ void k_gj_save0(const double *A, int ld, int n, double *prow, double *pcol) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < n) {
-    prow[j] = A[j];
-    pcol[j] = A[(size_t)j * ld];
+// ---------------------------------------------------------------------------
+// Blocked Gauss-Jordan inversion in place (B' is symmetric positive definite,
+// so the pivots need no search).  With the matrix split into 64-wide blocks and
+// K the current diagonal block, one step is
+//   P = A[K, K]^-1                       (k_bgj_panel: one workgroup, in LDS)
+//   A[K, J] <- P A[K, J]          J != K (k_bgj_rows)
+//   A[I, J] <- A[I, J] - A[I, K] A[K, J]   I, J != K (k_bgj_update, FP64 MFMA)
+//   A[I, K] <- -A[I, K] P,  A[K, K] <- P   (k_bgj_cols)
+// and after the last block A holds the inverse.  The matrix is padded to a
+// multiple of 64 with unit diagonal (its inverse stays unit there).
+constexpr int kGjB = 64;
+
+// P = inverse of the 64 x 64 diagonal block at p0 (Gauss-Jordan in LDS).
+__global__ void __launch_bounds__(256) k_bgj_panel(const double *A, int ld, int p0, double *P) {
+  __shared__ double M[kGjB][kGjB + 1];
+  __shared__ double prow[kGjB], pcol[kGjB];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kGjB * kGjB; e += blockDim.x) {
+    const int r = e / kGjB, c = e % kGjB;
+    M[r][c] = A[(size_t)(p0 + r) * ld + p0 + c];
+  }
+  __syncthreads();
+  for (int q = 0; q < kGjB; ++q) {
+    if (tid < kGjB) {
+      prow[tid] = M[q][tid];
+      pcol[tid] = M[tid][q];
+    }
+    __syncthreads();
+    const double ip = 1.0 / prow[q];
+    for (int e = tid; e < kGjB * kGjB; e += blockDim.x) {
+      const int r = e / kGjB, c = e % kGjB;
+      double v;
+      if (r == q)
+        v = c == q ? ip : prow[c] * ip;
+      else if (c == q)
+        v = -pcol[r] * ip;
+      else
+        v = M[r][c] - pcol[r] * (prow[c] * ip);
+      M[r][c] = v;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < kGjB * kGjB; e += blockDim.x) P[e] = M[e / kGjB][e % kGjB];
+}
+
+// A[K, J] <- P A[K, J] for the 64-column block J = blockIdx.x (skipping K).
+__global__ void __launch_bounds__(256) k_bgj_rows(double *A, int ld, int p0, const double *P) {
+  __shared__ double Ps[kGjB][kGjB + 1];
+  __shared__ double X[kGjB][kGjB + 1];
+  const int j0 = blockIdx.x * kGjB;
+  if (j0 == p0) return;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kGjB * kGjB; e += blockDim.x) {
+    const int r = e / kGjB, c = e % kGjB;
+    Ps[r][c] = P[e];
+    X[r][c] = A[(size_t)(p0 + r) * ld + j0 + c];
+  }
+  __syncthreads();
+  for (int e = tid; e < kGjB * kGjB; e += blockDim.x) {
+    const int r = e / kGjB, c = e % kGjB;
+    double v = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < kGjB; ++q) v = __builtin_fma(Ps[r][q], X[q][c], v);
+    A[(size_t)(p0 + r) * ld + j0 + c] = v;
   }
 }
 
-// One Gauss-Jordan sweep on pivot p (in place), reading the old pivot row and
-// column from (prow, pcol) and saving the new row/column p+1 into (nrow, ncol).
-__global__ void k_gj_step(double *A, int ld, int n, int p, const double *prow,
-                          const double *pcol, double *nrow, double *ncol) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  int i = blockIdx.y;
-  if (j >= n) return;
-  double ip = 1.0 / prow[p];
-  double v;
-  if (i == p) {
-    v = (j == p) ? ip : prow[j] * ip;
-  } else if (j == p) {
-    v = -pcol[i] * ip;
-  } else {
-    v = A[(size_t)i * ld + j] - pcol[i] * (prow[j] * ip);
+// A[I, K] <- -A[I, K] P for the 64-row block I = blockIdx.x; the block I = K gets P.
+__global__ void __launch_bounds__(256) k_bgj_cols(double *A, int ld, int p0, const double *P) {
+  __shared__ double Ps[kGjB][kGjB + 1];
+  __shared__ double X[kGjB][kGjB + 1];
+  const int i0 = blockIdx.x * kGjB;
+  const int tid = threadIdx.x;
+  if (i0 == p0) {
+    for (int e = tid; e < kGjB * kGjB; e += blockDim.x)
+      A[(size_t)(p0 + e / kGjB) * ld + p0 + e % kGjB] = P[e];
+    return;
   }
-  A[(size_t)i * ld + j] = v;
-  if (i == p + 1) nrow[j] = v;
-  if (j == p + 1) ncol[i] = v;
+  for (int e = tid; e < kGjB * kGjB; e += blockDim.x) {
+    const int r = e / kGjB, c = e % kGjB;
+    Ps[r][c] = P[e];
+    X[r][c] = A[(size_t)(i0 + r) * ld + p0 + c];
+  }
+  __syncthreads();
+  for (int e = tid; e < kGjB * kGjB; e += blockDim.x) {
+    const int r = e / kGjB, c = e % kGjB;
+    double v = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < kGjB; ++q) v = __builtin_fma(X[r][q], Ps[q][c], v);
+    A[(size_t)(i0 + r) * ld + p0 + c] = -v;
+  }
+}
+
+// Trailing update A[I, J] -= A[I, K] A[K, J] over 128 x 128 tiles (4 waves of
+// 64 x 64, FP64 16x16x4 MFMA, the tile's rows of A[I, K] staged in LDS, the
+// A[K, J] fragments read from global memory: 16 consecutive doubles per lane
+// group).  Rows and columns of K are left alone (the other kernels own them).
+__global__ void __launch_bounds__(256) k_bgj_update(double *A, int ld, int p0) {
+  __shared__ double As[128][kGjB + 1];
+  const int i0 = blockIdx.y * 128, j0 = blockIdx.x * 128;
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, g = lane / 16, li = lane % 16;
+  for (int e = tid; e < 128 * kGjB; e += blockDim.x) {
+    const int r = e / kGjB, c = e % kGjB;
+    const int i = i0 + r;
+    As[r][c] = i < ld ? A[(size_t)i * ld + p0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int wr = (wv / 2) * 64, wc = (wv % 2) * 64;  // this wave's 64 x 64 sub-tile
+  if (i0 + wr >= ld || j0 + wc >= ld) return;
+  if (i0 + wr == p0 || j0 + wc == p0) return;  // a K row or column block
+  d4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        acc[a][b][r] = A[(size_t)(i0 + wr + a * 16 + g + 4 * r) * ld + j0 + wc + b * 16 + li];
+  for (int h = 0; h < kGjB / 4; ++h) {
+    const int kk = 4 * h + g;
+    double fa[4], fb[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) fa[a] = -As[wr + a * 16 + li][kk];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) fb[b] = A[(size_t)(p0 + kk) * ld + j0 + wc + b * 16 + li];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        A[(size_t)(i0 + wr + a * 16 + g + 4 * r) * ld + j0 + wc + b * 16 + li] = acc[a][b][r];
+}
+
+// Unit diagonal on the padding rows n .. ld - 1.
+__global__ void k_pad_diag(double *A, int ld, int n) {
+  const int i = n + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ld) A[(size_t)i * ld + i] = 1.0;
 }
 
 __global__ void k_ptdf_rows(double *H, int ld, int n, int m, int slack, const double *Binv,
-                            const int32_t *f, const int32_t *t, const double *b) {
+                            int lb, const int32_t *f, const int32_t *t, const double *b) {
   int x = blockIdx.x * blockDim.x + threadIdx.x;
   int l = blockIdx.y;
   if (x >= ld || l >= m) return;
   double v = 0.0;
   if (x < n && x != slack)
-    v = b[l] * (Binv[(size_t)f[l] * ld + x] - Binv[(size_t)t[l] * ld + x]);
+    v = b[l] * (Binv[(size_t)f[l] * lb + x] - Binv[(size_t)t[l] * lb + x]);
   H[(size_t)l * ld + x] = v;
 }
 
@@ -170,6 +287,17 @@ __global__ void k_rating(double *r, double *inv_r, int mon_pad, const int32_t *m
   }
 }
 
+// Largest magnitude of each column of Lsd over the monitored rows (one thread
+// per column, rows walked in order: neighbouring threads read neighbouring
+// columns).  The error guard of the FP32 scan bounds the seed by it.
+__global__ void k_colmax(const double *lsd, int ld_o, int n_mon, double *cmax) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ld_o) return;
+  double m = 0.0;
+  for (int r = 0; r < n_mon; ++r) m = fmax(m, fabs(lsd[(size_t)r * ld_o + c]));
+  cmax[c] = m;
+}
+
 __global__ void k_lsd(double *lsd, int ld_o, const double *hdo, const int32_t *mon, int n_mon,
                       const int32_t *out, int n_out, int n_ctg, const double *inv_r,
                       int mon_pad) {
@@ -239,27 +367,35 @@ inline unsigned nblk(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 hipError_t launch_build(dcflow_plan *p, hipStream_t s, const double *h_rating, double rscale,
                         double roffset) {
-  const int n = p->n, m = p->m, ld = p->ld_h;
-  // reduced Laplacian and its inverse
-  hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, p->d_binv, (size_t)ld * ld, 0.0);
+  const int n = p->n, m = p->m, ld = p->ld_h, lb = p->ld_b;
+  // reduced Laplacian (padded to a multiple of 64 with unit diagonal) and its
+  // inverse by blocked Gauss-Jordan
+  hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, p->d_binv, (size_t)lb * lb, 0.0);
   DCF_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_assemble, dim3(nblk(n, 256)), dim3(256), 0, s, p->d_binv, ld, n, p->slack,
+  hipLaunchKernelGGL(k_assemble, dim3(nblk(n, 256)), dim3(256), 0, s, p->d_binv, lb, n, p->slack,
                      p->d_adj_off, p->d_adj_br, p->d_f, p->d_t, p->d_b);
   DCF_CHECK_LAUNCH();
-  double *pr[2] = {p->d_piv, p->d_piv + 2 * ld};
-  double *pc[2] = {p->d_piv + ld, p->d_piv + 3 * ld};
-  hipLaunchKernelGGL(k_gj_save0, dim3(nblk(n, 256)), dim3(256), 0, s, p->d_binv, ld, n, pr[0],
-                     pc[0]);
-  DCF_CHECK_LAUNCH();
-  for (int q = 0; q < n; ++q) {
-    int a = q & 1;
-    hipLaunchKernelGGL(k_gj_step, dim3(nblk(n, 256), n), dim3(256), 0, s, p->d_binv, ld, n, q,
-                       pr[a], pc[a], pr[a ^ 1], pc[a ^ 1]);
+  if (lb > n) {
+    hipLaunchKernelGGL(k_pad_diag, dim3(1), dim3(64), 0, s, p->d_binv, lb, n);
+    DCF_CHECK_LAUNCH();
+  }
+  const int nbk = lb / kGjB, nt = (lb + 127) / 128;
+  for (int q = 0; q < nbk; ++q) {
+    const int p0 = q * kGjB;
+    hipLaunchKernelGGL(k_bgj_panel, dim3(1), dim3(256), 0, s, p->d_binv, lb, p0, p->d_piv);
+    DCF_CHECK_LAUNCH();
+    if (nbk > 1) {
+      hipLaunchKernelGGL(k_bgj_rows, dim3(nbk), dim3(256), 0, s, p->d_binv, lb, p0, p->d_piv);
+      DCF_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_bgj_update, dim3(nt, nt), dim3(256), 0, s, p->d_binv, lb, p0);
+      DCF_CHECK_LAUNCH();
+    }
+    hipLaunchKernelGGL(k_bgj_cols, dim3(nbk), dim3(256), 0, s, p->d_binv, lb, p0, p->d_piv);
     DCF_CHECK_LAUNCH();
   }
   // PTDF and derived operands
   hipLaunchKernelGGL(k_ptdf_rows, dim3(nblk(ld, 256), m), dim3(256), 0, s, p->d_hb, ld, n, m,
-                     p->slack, p->d_binv, p->d_f, p->d_t, p->d_b);
+                     p->slack, p->d_binv, lb, p->d_f, p->d_t, p->d_b);
   DCF_CHECK_LAUNCH();
   if (p->n_ctrl > 0) {
     hipLaunchKernelGGL(k_ctrl_cols, dim3(nblk(m, 256), p->n_ctrl), dim3(256), 0, s, p->d_hb, ld,
@@ -294,6 +430,9 @@ hipError_t launch_build(dcflow_plan *p, hipStream_t s, const double *h_rating, d
   hipLaunchKernelGGL(k_lsd, dim3(nblk(p->ld_o, 256), p->mon_pad), dim3(256), 0, s, p->d_lsd,
                      p->ld_o, p->d_hdo, p->d_mon, p->n_mon, p->d_out, p->n_out,
                      p->n_out + p->n_gen, p->d_inv_r, p->mon_pad);
+  DCF_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_colmax, dim3(nblk(p->ld_o, 256)), dim3(256), 0, s, p->d_lsd, p->ld_o,
+                     p->n_mon, p->d_lsdmax);
   DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_lsd32, dim3(nblk((size_t)p->mon_pad * p->ld_o / 4, 256)), dim3(256), 0, s,
                      p->d_lsd32, p->d_lsd, p->ld_o, p->mon_pad);

@@ -19,6 +19,10 @@ constexpr size_t kXsMaxCols = size_t(1) << 20;  // columns of the BF16 split buf
 constexpr double kIslandTol = 1e-9;   // |LODF denominator| below this: islanding
 constexpr int kMultiRows = 256;       // monitored rows per work item of the multi-outage scan
 constexpr double kSingularTol = 1e-10; // relative pivot threshold of the k x k solve
+// Error guard of the FP32 N-1 scan: a contingency column whose error bound
+// (k + 4) u (max |Lsd| + sum_j max |U_j / r| |W_j|) max_v |y_v| (u = 2^-24) exceeds
+// this many rating units is taken out of the FP32 tiles and computed in FP64.
+constexpr double kGuardTolDefault = 4e-5;
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -39,7 +43,8 @@ struct dcflow_plan {
   int n_gen;   // generator outages: contingency columns n_out .. n_out + n_gen - 1
   int n_ctrl;  // control columns (phase shifters, then HVDC links)
   int n_inj;   // entries per injection vector: n + n_ctrl
-  int ld_h;    // columns of Hb / Binv / He (n rounded up to 16, the GEMM K step)
+  int ld_h;    // columns of Hb / He (n rounded up to 16, the GEMM K step)
+  int ld_b;    // leading dimension of Binv (n rounded up to 64, the inversion's block)
   int ld_er;   // rows kept, rounded up to the GEMM M tile (128); U, F, Ht stride
   int ld_o;    // contingency columns rounded up to 64 (>= 64)
   int mon_pad; // monitored rows rounded up to 64
@@ -49,8 +54,9 @@ struct dcflow_plan {
   double *d_b;
   int32_t *d_mon, *d_out, *d_er, *d_pos_of_br, *d_out_pos;
   int32_t *d_out_f, *d_out_t;  // [n_out + n_gen] column terminals (generator: bus, -1)
-  double *d_binv;   // [ld_h][ld_h] inverse of the slack-reduced Laplacian (slack row/col: unit)
-  double *d_piv;    // [2][ld_h] pivot row/column scratch of the inversion
+  double *d_binv;   // [ld_b][ld_b] inverse of the slack-reduced Laplacian (slack row/col and
+                    // the padding: unit)
+  double *d_piv;    // [64][64] inverse of the current diagonal block of the inversion
   double *d_hb;     // [m][ld_h] PTDF, all branches
   double *d_ht;     // [n][ld_er] PTDF transposed, kept rows only (node-major)
   double *d_he64;   // [ld_er][ld_h] kept rows of the PTDF, GEMM operand
@@ -58,6 +64,7 @@ struct dcflow_plan {
   __bf16 *d_heb;    // [3][ld_er][ld_h] same split into three BF16 parts (sum = FP64 value to ~2^-24)
   double *d_hdo;    // [m][ld_o] PTDF[:, f_c] - PTDF[:, t_c]; generator columns PTDF[:, bus]
   double *d_lsd;    // [mon_pad][ld_o] (hdo[mon] - [mon == out]) / rating
+  double *d_lsdmax; // [ld_o] max over the monitored rows of |d_lsd[:, c]| (error guard)
   float *d_lsd32;   // same in FP32, fragment-major: 16 x 16 blocks [mon_pad/16][ld_o/16], each
                     // 64 lanes x 4 rows in the FP32 MFMA accumulator order (rows 4 (lane/16) + r)
   double *d_fbase;  // [m]
@@ -96,6 +103,9 @@ struct dcflow_batch {
   double *d_W;      // [n_elem][ld_o]
   float *d_ur32;    // [n_elem][mon_pad] FP32 U / r (monitored rows) for the FP32 scan
   float *d_w32;     // [n_elem][ld_o] FP32 W
+  float *d_umax;    // [n_elem] max over the monitored rows of |U / r| (error guard)
+  uint32_t *d_flag; // [n_cand][ld_o / 32] contingency columns the guard computes in FP64
+  int32_t *d_nflag; // [n_cand] number of such columns
   double *d_kinv;   // [n_cand][64]
   double *d_invden; // [n_cand][ld_o]
   uint32_t *d_isl;  // [n_cand][ld_o / 32] islanding contingency bits
@@ -112,13 +122,15 @@ struct dcflow_batch {
   long long *d_part_k;
   int32_t *d_part_nf;
   int nmb;          // row chunks of the multi-outage scan (0 without multi cases); the
-                    // band partials hold max_bands + nmb slots per candidate
+                    // band partials hold max_bands + nmb + 1 slots per candidate (the
+                    // last for the error guard's FP64 columns)
   double *d_mcoef;  // [n_cand][n_multi][16] -N^-1 of each multi case (z = coef p1_S)
   int32_t *d_mok;   // [n_cand][n_multi] 1 = scored, 0 = islanding or failed candidate
   dcflow_tuning tune;
   hipStream_t aux;                 // second stream of the chunked step (default priority)
   hipEvent_t step_ev[dcflow::kMaxStepChunks + 1];  // fork points and the join of the chunked step
   int n_cu;               // compute units of the device the batch was created on
+  size_t lds_max;         // its largest LDS allocation per workgroup (bytes)
   hipGraph_t graph;       // captured step (dcflow_graph_capture), or null
   hipGraphExec_t graph_exec;
   int factored;     // eval_topologies enqueued
@@ -126,6 +138,8 @@ struct dcflow_batch {
   int pnv_nvar;
   int flows_prec;   // precision of the last eval_injections (-1 none)
   int flows_nvar;
+  int guard_valid;  // d_flag / d_nflag describe the current flows (set by an FP32
+                    // n1_score with the guard on, cleared by a new evaluation)
 };
 
 // Returns the launch error of the kernel just enqueued (HIP's last-error slot is

@@ -274,20 +274,32 @@ k_factors(const int32_t *__restrict__ order, const int32_t *__restrict__ off,
 
 // Operands of the FP32 scan's tile build, rounded once per evaluation instead
 // of once per tile: U / r on the padded monitored rows and W, in FP32 (the same
-// FP64 products the tile build would round).
+// FP64 products the tile build would round).  One workgroup per element (grid-
+// stride); it also records the element's largest |U / r| over the monitored rows
+// (inv_r is zero on the padding), which the error guard of the FP32 scan uses.
 __global__ void __launch_bounds__(256)
 k_frags(const double *__restrict__ U, int ld_er, const double *__restrict__ inv_r, int mon_pad,
         const double *__restrict__ W, int ld_o, size_t n_elem, float *__restrict__ ur32,
-        float *__restrict__ w32) {
-  const size_t nu = n_elem * mon_pad, nw = n_elem * ld_o;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nu + nw;
-       i += (size_t)gridDim.x * blockDim.x) {
-    if (i < nu) {
-      const size_t e = i / mon_pad, r = i - e * mon_pad;
-      ur32[i] = (float)(U[e * ld_er + r] * inv_r[r]);
-    } else {
-      w32[i - nu] = (float)W[i - nu];
+        float *__restrict__ w32, float *__restrict__ umax) {
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  for (size_t e = blockIdx.x; e < n_elem; e += gridDim.x) {
+    const double *u = U + e * ld_er;
+    float *ur = ur32 + e * mon_pad;
+    double m = 0.0;
+    for (int r = tid; r < mon_pad; r += blockDim.x) {
+      const double v = u[r] * inv_r[r];
+      ur[r] = (float)v;
+      m = fmax(m, fabs(v));
     }
+    const double *w = W + e * ld_o;
+    float *wf = w32 + e * ld_o;
+    for (int c = tid; c < ld_o; c += blockDim.x) wf[c] = (float)w[c];
+    m = wave_max(m);
+    if (tid % kWave == 0) red[tid / kWave] = m;
+    __syncthreads();
+    if (tid == 0) umax[e] = (float)fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    __syncthreads();
   }
 }
 
@@ -414,12 +426,12 @@ hipError_t launch_factors(dcflow_batch *bt, hipStream_t s) {
                      bt->d_nsig, bt->d_sig,
                      bt->d_U, bt->d_W, bt->d_kinv, bt->d_invden, bt->d_isl, bt->d_status);
   DCF_CHECK_LAUNCH();
-  const size_t n_elem = bt->n_elem, tot = n_elem * (p->mon_pad + p->ld_o);
-  if (tot) {
-    const size_t nb = std::min<size_t>((tot + 255) / 256, 8192);
+  const size_t n_elem = bt->n_elem;
+  if (n_elem) {
+    const size_t nb = std::min<size_t>(n_elem, 16384);
     k_frags<<<dim3((unsigned)nb), dim3(256), 0, s>>>(bt->d_U, p->ld_er, p->d_inv_r, p->mon_pad,
                                                      bt->d_W, p->ld_o, n_elem, bt->d_ur32,
-                                                     bt->d_w32);
+                                                     bt->d_w32, bt->d_umax);
     DCF_CHECK_LAUNCH();
   }
   if (p->n_multi > 0) {

@@ -174,6 +174,8 @@ struct Mfma<float> {
 };
 
 constexpr int BM = 128, BN = 128, KT = 16;
+// K stages per FP32 partial sum before it is added into FP64 (64 and 128 terms)
+constexpr int kFlush32 = 4, kFlushBf = 4;
 // LDS row stride: 16-byte aligned rows so that stores and fragment reads are vector
 // accesses (lane group g reads the 4 consecutive k it owns in one access)
 template <typename T>
@@ -191,8 +193,13 @@ constexpr int kXcd = 8;  // MI355X: workgroups are dealt round-robin to 8 XCDs (
 // 1-D grid, XCD-aware: the n_mt row tiles of one column tile run back to back on
 // one XCD, so the column tile of X is read from HBM once and then hits that L2.
 // 256 threads = 2 x 2 waves of 64 x 64.
-template <typename T>
-__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2)
+// FL > 0 (FP32): the FP32 accumulators are emptied into FP64 ones every FL K stages,
+// so FP32 rounding meets only partial sums over FL * KT terms; over the ten
+// thousand terms of a large grid a running FP32 sum would carry the rounding of
+// its full magnitude at every step (flows of heavily loaded corridors are sums of
+// many same-signed terms).
+template <typename T, int FL>
+__global__ void __launch_bounds__(256, (sizeof(T) == 4 && FL == 0) ? 4 : 2)
 k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, int ncols,
        int nvar, int shared, T *__restrict__ F, int ld_f, const int32_t *__restrict__ off,
        const double *__restrict__ U, int ld_er, const double *__restrict__ z, int vmax,
@@ -247,6 +254,25 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  d4 acc64[FL > 0 ? 4 : 1][FL > 0 ? 4 : 1];
+  if constexpr (FL > 0) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc64[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  auto flush = [&]() {
+    if constexpr (FL > 0) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[a][b][r] += (double)acc[a][b][r];
+          acc[a][b] = acc_t{0, 0, 0, 0};
+        }
+    }
+  };
 
   // single LDS stage (measured faster here than two stages with one barrier): the
   // next k-tile waits in registers while the current one is consumed
@@ -270,6 +296,9 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::op(af[a].x[ks], bf[b].x[ks], acc[a][b]);
+    if constexpr (FL > 0) {
+      if (kt % FL == FL - 1 || kt + 1 == nk) flush();
+    }
     __syncthreads();
     if (kt + 1 < nk) {
       sstore();
@@ -293,7 +322,14 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
       const int mb = m0 + wm * 64 + a * 16;
       double o[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) o[r] = (double)acc[a][b][r] + fber[mb + MfmaRow<T>::row(g, r)];
+      for (int r = 0; r < 4; ++r) {
+        double sum;
+        if constexpr (FL > 0)
+          sum = acc64[a][b][r];
+        else
+          sum = (double)acc[a][b][r];
+        o[r] = sum + fber[mb + MfmaRow<T>::row(g, r)];
+      }
       for (int e = e0; e < e1; ++e) {
         const double ze = z[(size_t)e * vmax + v];
         const double *ue = U + (size_t)e * ld_er + mb;
@@ -352,7 +388,7 @@ k_split_x(const double *__restrict__ X, int n, const double *__restrict__ pbase,
   }
 }
 
-template <int NP>
+template <int NP, int FL>
 __global__ void __launch_bounds__(256)
 k_gemm_bf(const __bf16 *__restrict__ Hp, size_t part, int ld_h, const __bf16 *__restrict__ Xs,
           size_t xpart, int ldx, int n, int ncols, int nvar, int shared, float *__restrict__ F,
@@ -376,6 +412,14 @@ k_gemm_bf(const __bf16 *__restrict__ Hp, size_t part, int ld_h, const __bf16 *__
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  // FL > 0: FP32 partial sums over FL K steps, emptied into FP64 (see k_gemm)
+  d4 acc64[FL > 0 ? 4 : 1][FL > 0 ? 4 : 1];
+  if constexpr (FL > 0) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc64[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  }
   const int nk = (n + BKT - 1) / BKT;
   // register stage of the next K step: A parts (zero past the padded width; ld_h is a
   // multiple of 16) and the parts of 16 injections minus the base case (base flows
@@ -455,6 +499,18 @@ k_gemm_bf(const __bf16 *__restrict__ Hp, size_t part, int ld_h, const __bf16 *__
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][a], bfr[0][b], c, 0, 0, 0);
         acc[a][b] = c;
       }
+    if constexpr (FL > 0) {
+      if (kt % FL == FL - 1 || kt + 1 == nk) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc64[a][b][r] += (double)acc[a][b][r];
+            acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+          }
+      }
+    }
     __syncthreads();
   }
   // epilogue: rank-k correction and store (rows 4 g + r of each block)
@@ -474,7 +530,14 @@ k_gemm_bf(const __bf16 *__restrict__ Hp, size_t part, int ld_h, const __bf16 *__
       const int mb = m0 + wm * 64 + a * 16;
       double o[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) o[r] = (double)acc[a][b][r] + fber[mb + MfmaRow<float>::row(g, r)];
+      for (int r = 0; r < 4; ++r) {
+        double sum;
+        if constexpr (FL > 0)
+          sum = acc64[a][b][r];
+        else
+          sum = (double)acc[a][b][r];
+        o[r] = sum + fber[mb + MfmaRow<float>::row(g, r)];
+      }
       for (int e = e0; e < e1; ++e) {
         const double ze = z[(size_t)e * vmax + v];
         const double *ue = U + (size_t)e * ld_er + mb;
@@ -536,14 +599,14 @@ hipError_t launch_gemm(const dcflow_plan *p, const T *He, int np, const double *
       if (np == 3) {
         k_split_x<3><<<sg, dim3(256), 0, s>>>(X, p->n_inj, p->d_pbase, ncols, bt->ldx, xs, xpart);
         DCF_CHECK_LAUNCH();
-        k_gemm_bf<3><<<grid, dim3(256), 0, s>>>(p->d_heb, part, p->ld_h, xs, xpart, bt->ldx,
+        k_gemm_bf<3, kFlushBf><<<grid, dim3(256), 0, s>>>(p->d_heb, part, p->ld_h, xs, xpart, bt->ldx,
                                                 p->n_inj, ncols, nvar, shared, F, p->ld_er, off,
                                                 bt->d_U, p->ld_er, bt->d_z, bt->vmax, correct,
                                                 n_mt, n_nt, p->d_fber);
       } else {
         k_split_x<1><<<sg, dim3(256), 0, s>>>(X, p->n_inj, p->d_pbase, ncols, bt->ldx, xs, xpart);
         DCF_CHECK_LAUNCH();
-        k_gemm_bf<1><<<grid, dim3(256), 0, s>>>(p->d_heb, part, p->ld_h, xs, xpart, bt->ldx,
+        k_gemm_bf<1, 0><<<grid, dim3(256), 0, s>>>(p->d_heb, part, p->ld_h, xs, xpart, bt->ldx,
                                                 p->n_inj, ncols, nvar, shared, F, p->ld_er, off,
                                                 bt->d_U, p->ld_er, bt->d_z, bt->vmax, correct,
                                                 n_mt, n_nt, p->d_fber);
@@ -554,7 +617,7 @@ hipError_t launch_gemm(const dcflow_plan *p, const T *He, int np, const double *
   }
   // the GEMM takes x - p_base and the FP64 base flows are added back (the injections are
   // variants of the base case, so this keeps most cancellation out of the sums)
-  k_gemm<T><<<grid, dim3(256), 0, s>>>(He, p->ld_h, X, p->n_inj, ncols, nvar, shared, F, p->ld_er,
+  k_gemm<T, sizeof(T) == 4 ? kFlush32 : 0><<<grid, dim3(256), 0, s>>>(He, p->ld_h, X, p->n_inj, ncols, nvar, shared, F, p->ld_er,
                                        off, bt->d_U, p->ld_er, bt->d_z, bt->vmax, correct, n_mt,
                                        n_nt, p->d_pbase, p->d_fber);
   DCF_CHECK_LAUNCH();

@@ -72,6 +72,8 @@ struct PcArgs {
   const dcflow_score *scores;
   int per_case, top_k, nslots;
   PcEntry *ws;  // [n_cand][nslots][per_case]
+  const uint32_t *flag;  // [n_cand][ld_o / 32] columns the FP32 scan's error guard
+                         // computes in FP64 (null: none)
 };
 
 template <typename T>
@@ -135,7 +137,29 @@ __global__ void __launch_bounds__(256) k_pc_cols(PcArgs A) {
   bool live = !pc_skip(A, cand, vstar);
   if (live && c >= 0)
     live = !((A.isl[(size_t)cand * (A.ld_o / 32) + c / 32] >> (c % 32)) & 1u);
-  if (live) {
+  const bool guard = live && c >= 0 && A.flag != nullptr &&
+                     ((A.flag[(size_t)cand * (A.ld_o / 32) + c / 32] >> (c % 32)) & 1u);
+  if (guard) {
+    // a column of the FP32 scan's error guard: the entries in FP64 from the FP64
+    // factors, as the scan computes them
+    const T *Fv = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vstar) * A.ld_f;
+    const int e0 = A.off[cand], k = A.off[cand + 1] - e0;
+    const double inv = A.invden[(size_t)cand * A.ld_o + c];
+    const double y = (c < A.n_out ? (double)Fv[A.out_pos[c]] : A.gen_y[c - A.n_out]) * inv;
+    double w[kMaxRank];
+#pragma unroll
+    for (int e = 0; e < kMaxRank; ++e) w[e] = e < k ? PcOps<double>::w(A, e0 + e, c) : 0.0;
+    for (int row = 0; row < A.n_mon; ++row) {
+      double l = A.lsd[(size_t)row * A.ld_o + c];
+#pragma unroll
+      for (int e = 0; e < kMaxRank; ++e)
+        if (e < k) l = pc_fma(PcOps<double>::ur(A, e0 + e, row), w[e], l);
+      const double p = pc_fma(l, y, (double)Fv[row] * A.inv_r[row]);
+      const T a = (T)(p < 0.0 ? -p : p);
+      const int key = slot * A.n_mon + row;
+      if (pc_better(a, key, lv[KM - 1], lk[KM - 1])) pc_insert(lv, lk, a, key);
+    }
+  } else if (live) {
     const T *Fv = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vstar) * A.ld_f;
     const int e0 = A.off[cand], k = A.off[cand + 1] - e0;
     T y = (T)0, w[kMaxRank];
@@ -339,6 +363,7 @@ hipError_t run_pc(dcflow_batch *bt, const T *flows, int nvar, const dcflow_score
   a.top_k = top_k;
   a.nslots = per_case_slots(p);
   a.ws = static_cast<PcEntry *>(ws);
+  a.flag = sizeof(T) == 4 && bt->guard_valid ? bt->d_flag : nullptr;
   const unsigned nc = (unsigned)bt->n_cand;
   const dim3 gcols(nc, (unsigned)((a.n_ctg + 1 + 255) / 256));
   if (per_case <= 4)

@@ -139,7 +139,12 @@ struct ScanArgs {
   const double *mcoef;          // [n_cand][n_multi][16]
   const int32_t *mok;           // [n_cand][n_multi]
   int nmb;                      // row chunks per candidate (0: no multi cases)
-  int nbt;                      // partial slots per candidate: nbands row bands, then nmb chunks
+  int nbt;                      // partial slots per candidate: nbands row bands, then nmb
+                                // chunks, then ng guard slots
+  // error guard of the FP32 scan (null / 0 in FP64 and with the guard off)
+  const uint32_t *flag;         // [n_cand][ld_o / 32] columns computed in FP64 instead
+  const int32_t *nflag;         // [n_cand] their number
+  int ng;                       // 1: the last partial slot holds the guarded columns
 };
 
 constexpr int kQueueWin = 15;  // counter slot of pass 2
@@ -351,6 +356,13 @@ __device__ __forceinline__ int outage_id(const ScanArgs &A, int c) {
   return c < A.n_out ? A.out[c] : -2 - (c - A.n_out);
 }
 
+// True for a contingency column that the error guard takes out of the FP32 tiles
+// of this candidate (its y is zero there and its elements are not scored; the
+// guard kernels compute the column in FP64).
+__device__ __forceinline__ bool guarded(const ScanArgs &A, int cand, int c) {
+  return A.flag != nullptr && ((A.flag[(size_t)cand * (A.ld_o / 32) + c / 32] >> (c % 32)) & 1u);
+}
+
 // ---------------------------------------------------------------- pass 1
 // Item (cand, band): maxima of the band's N-0 rows and of its N-1 rows against
 // every contingency, for the VC variants of blockIdx.y, merged into vmax by
@@ -389,8 +401,10 @@ __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int b
   // flow marks its variant in s_nf at once (rare, so not kept in registers)
   for (int vi = 0; vi < nv; ++vi) {
     bool nf = false;
-    for (int c = tid; c < ld_o; c += blockDim.x)
-      ys[(size_t)vi * ld_o + c] = ycol(F + (size_t)vi * A.ld_f, A, cand, c, nf);
+    for (int c = tid; c < ld_o; c += blockDim.x) {
+      const T y = ycol(F + (size_t)vi * A.ld_f, A, cand, c, nf);
+      ys[(size_t)vi * ld_o + c] = guarded(A, cand, c) ? (T)0 : y;
+    }
     if (nf) s_nf[vi] = 1;
   }
 
@@ -517,9 +531,11 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
   const T *Fv = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vstar) * A.ld_f;
   bool nf = false;
   for (int c = tid; c < ld_o; c += blockDim.x) {
-    ys[c] = ycol(Fv, A, cand, c, nf);
+    const T y = ycol(Fv, A, cand, c, nf);
+    const bool g = guarded(A, cand, c);
+    ys[c] = g ? (T)0 : y;
     const bool valid =
-        c < A.n_ctg && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
+        c < A.n_ctg && !g && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
     colw[c] = valid ? (T)1 : (T)0;
   }
   const int r0 = band * A.band_rows, r1 = min(r0 + A.band_rows, A.mon_pad);
@@ -734,7 +750,8 @@ __global__ void k_scan_fin(ScanArgs A) {
     if (pm[b] == M && pk[b] < key) key = pk[b];
   // a variant whose flows were not finite was given +inf by pass 1; the
   // winner's own non-finite flows make its maximum +inf
-  r.status = st | ((nf || any_inf) ? DCFLOW_ST_NONFINITE : 0u);
+  r.status = st | ((nf || any_inf) ? DCFLOW_ST_NONFINITE : 0u) |
+             ((A.nflag != nullptr && A.nflag[cand] > 0) ? DCFLOW_ST_GUARDED : 0u);
   const bool found = key != kNoKey;
   const int c = found ? (int)(key / A.n_mon) - 1 : -1;
   const int row = found ? (int)(key % A.n_mon) : -1;
@@ -814,9 +831,11 @@ __device__ __forceinline__ void scan_worst_item(const ScanArgs &A, int cand, int
     T *tvw = tv + (size_t)wv * NE * kWave;
     bool nf = false;
     for (int c = tid; c < ld_o; c += blockDim.x) {
-      ys[c] = ycol(Fv, A, cand, c, nf);
+      const T y = ycol(Fv, A, cand, c, nf);
+      const bool g = guarded(A, cand, c);
+      ys[c] = g ? (T)0 : y;
       const bool valid =
-          c < A.n_ctg && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
+          c < A.n_ctg && !g && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
       colw[c] = valid ? (T)1 : (T)0;
     }
     const int r0 = band * A.band_rows, r1 = min(r0 + A.band_rows, A.mon_pad);
@@ -1292,8 +1311,322 @@ __global__ void __launch_bounds__(256) k_scan_multi(ScanArgs A) {
   }
 }
 
+// ---------------------------------------------------------------- error guard
+// The FP32 tile build rounds the seed, U / r and W to FP32 and sums k products
+// in FP32: an LODF' entry L carries an error of at most (k + 3) u S (u = 2^-24,
+// S = the sum of the magnitudes of its terms), and the N-1 element L y another
+// u |L| |y| from y's rounding.  Where a candidate's heavy rerouting makes the
+// terms large and cancelling, times a large y = F'[c] / den_c, that product can
+// exceed the rating tolerance although every operand is accurate in FP64.
+// k_guard bounds it per (candidate, contingency column): S_c <= max |Lsd[:, c]|
+// + sum_j max |U_j / r| |W_j[c]| and |y_c| <= max over the variants, so
+// E_c = (k + 4) u S_c max_v |y_cv|; columns with E_c above the tolerance are
+// flagged.  The FP32 passes give them y = 0 and leave their elements unscored,
+// and k_guard_fix computes them in FP64 (seed, U, W and y from the FP64
+// factors, the flows as stored): per-variant maxima, the winner's maximum, key
+// and overload sum (the last partial slot), or the winner's worst-case list.
+
+// Iterates the flagged columns of a candidate (the same order in every thread).
+template <typename F>
+__device__ __forceinline__ void for_each_flagged(const ScanArgs &A, int cand, F body) {
+  const uint32_t *fw = A.flag + (size_t)cand * (A.ld_o / 32);
+  for (int w = 0; w < A.ld_o / 32; ++w) {
+    uint32_t bits = fw[w];
+    while (bits) {
+      const int b = __builtin_ctz(bits);
+      bits &= bits - 1;
+      body(32 * w + b);
+    }
+  }
+}
+
+// y of a guarded column in FP64 (the stored flow of the contingency row or the
+// generator's lost output, times the FP64 inverse denominator)
+__device__ __forceinline__ double guard_y(const ScanArgs &A, const float *Fv, int cand, int c) {
+  const double inv = A.invden[(size_t)cand * A.ld_o + c];
+  return (c < A.n_out ? (double)Fv[A.out_pos[c]] : A.gen_y[c - A.n_out]) * inv;
+}
+
+// The LODF' entry of row `row`, column c in FP64 from the FP64 factors.
+__device__ __forceinline__ double guard_l(const ScanArgs &A, int e0, int k, const double (&wc)[kMaxRank],
+                                          int row, int c) {
+  double l = A.lsd[(size_t)row * A.ld_o + c];
+  const double ir = A.inv_r[row];
+#pragma unroll
+  for (int j = 0; j < kMaxRank; ++j)
+    if (j < k) l = __builtin_fma(A.U[(size_t)(e0 + j) * A.ld_er + row] * ir, wc[j], l);
+  return l;
+}
+
+__device__ __forceinline__ void guard_w(const ScanArgs &A, int e0, int k, int c, double (&wc)[kMaxRank]) {
+#pragma unroll
+  for (int j = 0; j < kMaxRank; ++j) wc[j] = j < k ? A.W[(size_t)(e0 + j) * A.ld_o + c] : 0.0;
+}
+
+// One workgroup per candidate of [cand0, cand0 + n_cand): the flag words and count.
+__global__ void __launch_bounds__(256)
+k_guard(ScanArgs A, const float *__restrict__ umax, const double *__restrict__ lsdmax, double tol,
+        uint32_t *__restrict__ flag, int32_t *__restrict__ nflag) {
+  __shared__ int s_cnt[4];
+  const int cand = A.cand0 + blockIdx.x;
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+  const int e0 = A.off[cand], k = A.off[cand + 1] - e0;
+  const bool dead = (A.status[cand] & DCFLOW_ST_DISCONNECTED) != 0;
+  const int nw = A.ld_o / 32;
+  const float *F = static_cast<const float *>(A.F) + (size_t)cand * A.nvar * A.ld_f;
+  const double coef = (k + 4) * 0x1p-24;
+  int cnt = 0;
+  for (int c0 = 0; c0 < A.ld_o; c0 += blockDim.x) {
+    const int c = c0 + tid;  // ld_o is a multiple of 64: a wave is all in or all out
+    if (c0 + wv * kWave >= A.ld_o) break;
+    bool f = false;
+    if (!dead && c < A.n_ctg) {
+      const double inv = A.invden[(size_t)cand * A.ld_o + c];
+      const bool isl = (A.isl[(size_t)cand * nw + c / 32] >> (c % 32)) & 1u;
+      if (inv != 0.0 && !isl) {
+        double S = lsdmax[c];
+        for (int j = 0; j < k; ++j)
+          S += (double)umax[e0 + j] * fabs(A.W[(size_t)(e0 + j) * A.ld_o + c]);
+        double Y = 0.0;
+        if (c < A.n_out) {
+          const float *Fc = F + A.out_pos[c];
+          for (int v = 0; v < A.nvar; ++v) Y = fmax(Y, fabs((double)Fc[(size_t)v * A.ld_f]));
+          Y *= fabs(inv);
+        } else {
+          Y = fabs(A.gen_y[c - A.n_out] * inv);
+        }
+        const double E = coef * S * Y;
+        // a non-finite bound (non-finite flows) stays in the FP32 passes, which flag it
+        f = E > tol && E <= 1.7976931348623157e308;
+      }
+    }
+    const unsigned long long bal = __ballot(f);
+    if (lane == 0) {
+      flag[(size_t)cand * nw + c / 32] = (uint32_t)bal;
+      flag[(size_t)cand * nw + c / 32 + 1] = (uint32_t)(bal >> 32);
+    }
+    cnt += f ? 1 : 0;
+  }
+  cnt = wave_sum(cnt);
+  if (lane == 0) s_cnt[wv] = cnt;
+  __syncthreads();
+  if (tid == 0) nflag[cand] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+}
+
+// Per-variant maxima over the guarded columns (merged into vmax by atomic maxima,
+// after pass 1 and before the winner is chosen).
+__global__ void __launch_bounds__(256) k_guard_max(ScanArgs A) {
+  constexpr int GV = 16;
+  __shared__ double s_red[4][GV];
+  const int cand = A.cand0 + blockIdx.x;
+  if (A.nflag[cand] == 0 || (A.status[cand] & DCFLOW_ST_DISCONNECTED)) return;
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+  const int e0 = A.off[cand], k = A.off[cand + 1] - e0;
+  const float *F = static_cast<const float *>(A.F) + (size_t)cand * A.nvar * A.ld_f;
+  for (int v0 = 0; v0 < A.nvar; v0 += GV) {
+    const int nv = min(GV, A.nvar - v0);
+    double vm[GV];
+#pragma unroll
+    for (int i = 0; i < GV; ++i) vm[i] = 0.0;
+    for_each_flagged(A, cand, [&](int c) {
+      double y[GV], wc[kMaxRank];
+#pragma unroll
+      for (int i = 0; i < GV; ++i) y[i] = i < nv ? guard_y(A, F + (size_t)(v0 + i) * A.ld_f, cand, c) : 0.0;
+      guard_w(A, e0, k, c, wc);
+      for (int row = tid; row < A.n_mon; row += blockDim.x) {
+        const double l = guard_l(A, e0, k, wc, row, c);
+        const double ir = A.inv_r[row];
+#pragma unroll
+        for (int i = 0; i < GV; ++i)
+          if (i < nv) {
+            const double p = __builtin_fma(l, y[i], (double)F[(size_t)(v0 + i) * A.ld_f + row] * ir);
+            vm[i] = fmax(vm[i], fabs(p));
+          }
+      }
+    });
+#pragma unroll
+    for (int i = 0; i < GV; ++i) {
+      const double m = wave_max(vm[i]);
+      if (lane == 0) s_red[wv][i] = m;
+    }
+    __syncthreads();
+    if (tid < nv) {
+      const double m = fmax(fmax(s_red[0][tid], s_red[1][tid]), fmax(s_red[2][tid], s_red[3][tid]));
+      global_max_nonneg(A.vmax + (size_t)cand * A.vmax_ld + v0 + tid, m);
+    }
+    __syncthreads();
+  }
+}
+
+// The winner's maximum, lowest key and overload sum over the guarded columns, in
+// the candidate's last partial slot (neutral values without guarded columns).
+__global__ void __launch_bounds__(256) k_guard_win(ScanArgs A) {
+  constexpr long long kNoKey = 0x7fffffffffffffffLL;
+  __shared__ double s_m[4], s_ov[4];
+  __shared__ long long s_k[4];
+  __shared__ int s_vstar;
+  const int cand = A.cand0 + blockIdx.x;
+  const size_t slot = (size_t)cand * A.nbt + (A.nbt - 1);
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+  if (A.nflag[cand] == 0 || (A.status[cand] & DCFLOW_ST_DISCONNECTED)) {
+    if (tid == 0) {
+      A.part_m[slot] = 0.0;
+      A.part_k[slot] = kNoKey;
+      A.part_ov[slot] = 0.0;
+      A.part_nf[slot] = 0;
+    }
+    return;
+  }
+  if (tid == 0) {
+    int best = 0;
+    if (!A.single) {
+      double bv = A.vmax[(size_t)cand * A.vmax_ld];
+      for (int v = 1; v < A.nvar; ++v) {
+        const double x = A.vmax[(size_t)cand * A.vmax_ld + v];
+        if (x < bv) {
+          bv = x;
+          best = v;
+        }
+      }
+    }
+    s_vstar = best;
+  }
+  __syncthreads();
+  const int e0 = A.off[cand], k = A.off[cand + 1] - e0;
+  const float *Fv = static_cast<const float *>(A.F) + ((size_t)cand * A.nvar + s_vstar) * A.ld_f;
+  double bm = -1.0, ov = 0.0;
+  long long bk = kNoKey;
+  for_each_flagged(A, cand, [&](int c) {
+    double wc[kMaxRank];
+    const double y = guard_y(A, Fv, cand, c);
+    guard_w(A, e0, k, c, wc);
+    for (int row = tid; row < A.n_mon; row += blockDim.x) {
+      const double p = __builtin_fma(guard_l(A, e0, k, wc, row, c), y, (double)Fv[row] * A.inv_r[row]);
+      const double a = fabs(p);
+      const long long key = (long long)(c + 1) * A.n_mon + row;
+      if (a > bm || (a == bm && key < bk)) {
+        bm = a;
+        bk = key;
+      }
+      ov += fmax(a - 1.0, 0.0);
+    }
+  });
+  const double M = wave_max(bm);
+  long long kk = bm == M ? bk : kNoKey;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const long long w = __shfl_xor(kk, o);
+    kk = w < kk ? w : kk;
+  }
+  const double os = wave_sum(ov);
+  if (lane == 0) {
+    s_m[wv] = M;
+    s_k[wv] = kk;
+    s_ov[wv] = os;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double m = fmax(fmax(s_m[0], s_m[1]), fmax(s_m[2], s_m[3]));
+    long long key = kNoKey;
+    for (int w = 0; w < 4; ++w)
+      if (s_m[w] == m && s_k[w] < key) key = s_k[w];
+    A.part_m[slot] = m;
+    A.part_k[slot] = key;
+    A.part_ov[slot] = s_ov[0] + s_ov[1] + s_ov[2] + s_ov[3];
+    A.part_nf[slot] = 0;
+  }
+}
+
+// The winner's top_k cases over the guarded columns: a sorted list in the
+// candidate's last band-list slot (empty entries without guarded columns).
+template <int KM>
+__global__ void __launch_bounds__(256) k_guard_worst(ScanArgs A) {
+  constexpr int kEmpty = 0x7fffffff;
+  __shared__ double s_bv[4];
+  __shared__ int s_bk[4];
+  const int cand = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+  WEntry *dst = A.wpart + ((size_t)cand * A.nbt + (A.nbt - 1)) * A.top_k;
+  const dcflow_score sc = A.scores[cand];
+  const bool skip = A.nflag == nullptr || A.nflag[cand] == 0 ||
+                    (sc.status & (DCFLOW_ST_DISCONNECTED | DCFLOW_ST_NONFINITE)) != 0 ||
+                    sc.best_variant < 0 || sc.best_variant >= A.nvar;
+  double lv[KM];
+  int lk[KM];
+#pragma unroll
+  for (int j = 0; j < KM; ++j) {
+    lv[j] = -1.0;
+    lk[j] = kEmpty;
+  }
+  if (!skip) {
+    const int e0 = A.off[cand], k = A.off[cand + 1] - e0;
+    const float *Fv =
+        static_cast<const float *>(A.F) + ((size_t)cand * A.nvar + sc.best_variant) * A.ld_f;
+    for_each_flagged(A, cand, [&](int c) {
+      double wc[kMaxRank];
+      const double y = guard_y(A, Fv, cand, c);
+      guard_w(A, e0, k, c, wc);
+      for (int row = tid; row < A.n_mon; row += blockDim.x) {
+        const double p =
+            __builtin_fma(guard_l(A, e0, k, wc, row, c), y, (double)Fv[row] * A.inv_r[row]);
+        const double a = fabs(p);
+        const int key = (c + 1) * A.n_mon + row;
+        if (better(a, key, lv[KM - 1], lk[KM - 1])) list_insert(lv, lk, a, key);
+      }
+    });
+  }
+  for (int j = 0; j < A.top_k; ++j) {
+    double bv = lv[0];
+    int bk = lk[0];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double ov = __shfl_xor(bv, o);
+      const int ok = __shfl_xor(bk, o);
+      if (better(ov, ok, bv, bk)) {
+        bv = ov;
+        bk = ok;
+      }
+    }
+    if (lane == 0) {
+      s_bv[wv] = bv;
+      s_bk[wv] = bk;
+    }
+    __syncthreads();
+    double wbv = s_bv[0];
+    int wbk = s_bk[0];
+#pragma unroll
+    for (int w = 1; w < 4; ++w)
+      if (better(s_bv[w], s_bk[w], wbv, wbk)) {
+        wbv = s_bv[w];
+        wbk = s_bk[w];
+      }
+    if (tid == 0) {
+      WEntry e;
+      e.v = wbk == kEmpty ? -1.0 : wbv;
+      e.k = wbk;
+      e.pad = 0;
+      dst[j] = e;
+    }
+    if (wbk != kEmpty && lk[0] == wbk) {
+#pragma unroll
+      for (int q = 0; q < KM - 1; ++q) {
+        lv[q] = lv[q + 1];
+        lk[q] = lk[q + 1];
+      }
+      lv[KM - 1] = -1.0;
+      lk[KM - 1] = kEmpty;
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- launch
-constexpr size_t kLdsBudget = 64 * 1024;   // dynamic LDS per workgroup, at most
+constexpr size_t kLdsBudget = 64 * 1024;   // dynamic LDS per workgroup by default
+// The wider FP64 variant group of pass 1 may use more where the device allows it
+// (gfx950: 160 KB per compute unit); its workgroups then share a unit two at a time.
+inline size_t lds_budget(const dcflow_batch *bt, int vc, size_t elem) {
+  return (elem == 8 && vc == 16) ? bt->lds_max : kLdsBudget;
+}
 constexpr size_t kLdsOccupancy = 38 * 1024; // fits four workgroups per CU
 
 // Rows per band: the requested count (a multiple of 64, capped at the padded
@@ -1344,7 +1677,7 @@ hipError_t launch_max(const ScanArgs &a0, const dcflow_batch *bt, int nvar, hipS
   const size_t fixed = sizeof(T) * (size_t)VC * a.ld_o;
   choose_rows(bt, fixed, sizeof(T) * VC, a.mon_pad, a.ld_o, sizeof(T), kLdsOccupancy, a);
   const size_t lds = fixed + sizeof(T) * (size_t)VC * a.rchunk;
-  if (lds > kLdsBudget) return hipErrorInvalidValue;
+  if (lds > lds_budget(bt, VC, sizeof(T))) return hipErrorInvalidValue;
   const int ny = (nvar + VC - 1) / VC;
   if (ny > kQueueWin) a.persistent = 0;  // one counter per variant group
   k_scan_max<T, VC, MINW><<<dim3(grid_x(bt, a), ny), dim3(256), lds, s>>>(a);
@@ -1361,7 +1694,7 @@ struct VcSet<float> {
 };
 template <>
 struct VcSet<double> {
-  static constexpr int v[4] = {8, 4, 2, 1};
+  static constexpr int v[4] = {16, 8, 4, 1};
 };
 
 template <typename T>
@@ -1371,7 +1704,7 @@ hipError_t launch_max_vc(const ScanArgs &a, const dcflow_batch *bt, int nvar, in
   constexpr int V0 = VcSet<T>::v[0], V1 = VcSet<T>::v[1], V2 = VcSet<T>::v[2];
   if (vc == V0) return launch_max<T, V0, F32 ? 4 : 2>(a, bt, nvar, s);
   if (vc == V1) return launch_max<T, V1, F32 ? 4 : 2>(a, bt, nvar, s);
-  if (vc == V2) return launch_max<T, V2, 1>(a, bt, nvar, s);
+  if (vc == V2) return launch_max<T, V2, F32 ? 1 : 2>(a, bt, nvar, s);
   return launch_max<T, 1, 1>(a, bt, nvar, s);
 }
 
@@ -1385,6 +1718,9 @@ inline void set_multi(ScanArgs &a, const dcflow_plan *p, const dcflow_batch *bt)
   a.mok = bt->d_mok;
   a.nmb = bt->nmb;
   a.nbt = 1 + bt->nmb;
+  a.flag = nullptr;
+  a.nflag = nullptr;
+  a.ng = 0;
 }
 
 template <typename T>
@@ -1434,6 +1770,17 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   a.band_rows = 0;
   a.nbands = 1;
   set_multi(a, p, bt);
+  if (sizeof(T) == 4 && bt->tune.guard_tol >= 0.0) {
+    // the error guard of the FP32 scan flags its columns first
+    const double tol = bt->tune.guard_tol > 0.0 ? bt->tune.guard_tol : kGuardTolDefault;
+    a.flag = bt->d_flag;
+    a.nflag = bt->d_nflag;
+    a.ng = 1;
+    k_guard<<<dim3((unsigned)a.n_cand), dim3(256), 0, s>>>(a, bt->d_umax, p->d_lsdmax, tol,
+                                                          bt->d_flag, bt->d_nflag);
+    DCF_CHECK_LAUNCH();
+  }
+  bt->guard_valid = a.ng;
   {
     const size_t nv = a.single ? 0 : (size_t)a.n_cand * bt->vmax;
     const size_t n = nv > (size_t)(kQueueWin + 1) ? nv : (size_t)(kQueueWin + 1);
@@ -1444,7 +1791,9 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   if (!a.single) {
     // the requested variant group, else the widest whose y fits the LDS budget
     // with one 64-row band and that the variants fill
-    auto fits = [&](int vc) { return sizeof(T) * (size_t)vc * (p->ld_o + 64) <= kLdsBudget; };
+    auto fits = [&](int vc) {
+      return sizeof(T) * (size_t)vc * (p->ld_o + 64) <= lds_budget(bt, vc, sizeof(T));
+    };
     int vc = bt->tune.scan_vc;
     bool known = false;
     for (int i = 0; i < 4; ++i) known |= vc == VcSet<T>::v[i];
@@ -1462,17 +1811,25 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
       k_scan_multi<T, 0, 1><<<dim3((unsigned)((size_t)a.n_cand * a.nmb), ny), dim3(256), 0, s>>>(a);
       DCF_CHECK_LAUNCH();
     }
+    if (a.ng) {
+      k_guard_max<<<dim3((unsigned)a.n_cand), dim3(256), 0, s>>>(a);
+      DCF_CHECK_LAUNCH();
+    }
   }
   const size_t fixed = sizeof(T) * 2 * (size_t)p->ld_o;
   choose_rows(bt, fixed, sizeof(T), p->mon_pad, p->ld_o, sizeof(T), kLdsOccupancy, a);
   if (a.nbands > bt->max_bands) return hipErrorInvalidValue;
-  a.nbt = a.nbands + a.nmb;
+  a.nbt = a.nbands + a.nmb + a.ng;
   const size_t lds = fixed + sizeof(T) * (size_t)a.rchunk;
   if (lds > kLdsBudget) return hipErrorInvalidValue;
   k_scan_win<T, sizeof(T) == 4 ? 4 : 1><<<dim3(grid_x(bt, a)), dim3(256), lds, s>>>(a);
   DCF_CHECK_LAUNCH();
   if (a.nmb > 0) {
     k_scan_multi<T, 1, 1><<<dim3((unsigned)((size_t)a.n_cand * a.nmb)), dim3(256), 0, s>>>(a);
+    DCF_CHECK_LAUNCH();
+  }
+  if (a.ng) {
+    k_guard_win<<<dim3((unsigned)a.n_cand), dim3(256), 0, s>>>(a);
     DCF_CHECK_LAUNCH();
   }
   k_scan_fin<<<(a.n_cand + 255) / 256, 256, 0, s>>>(a);
@@ -1547,7 +1904,13 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   a.rchunk = rc;
   a.band_rows = band;  // a multiple of 64; the last chunk of a band may be shorter
   a.nbands = worst_bands(p);
-  a.nbt = a.nbands + a.nmb;
+  // the last slot always holds the error guard's list (empty without guarded columns)
+  if (sizeof(T) == 4 && bt->guard_valid) {
+    a.flag = bt->d_flag;
+    a.nflag = bt->d_nflag;
+  }
+  a.ng = 1;
+  a.nbt = a.nbands + a.nmb + a.ng;
   if (a.nbt > kFinBands) return hipErrorInvalidValue;
   const size_t lds = fixed + sizeof(T) * (size_t)rc;
   if (lds > kLdsBudget) return hipErrorInvalidValue;
@@ -1565,6 +1928,11 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
       k_scan_multi<T, 2, 16><<<gm, dim3(256), 0, s>>>(a);
     DCF_CHECK_LAUNCH();
   }
+  if (top_k <= 8)
+    k_guard_worst<8><<<dim3(bt->n_cand), dim3(256), 0, s>>>(a);
+  else
+    k_guard_worst<16><<<dim3(bt->n_cand), dim3(256), 0, s>>>(a);
+  DCF_CHECK_LAUNCH();
   k_worst_fin<<<dim3(bt->n_cand), dim3(64), 0, s>>>(a, out);
   DCF_CHECK_LAUNCH();
   return hipSuccess;
