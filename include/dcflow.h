@@ -69,7 +69,8 @@ typedef enum {
   DCFLOW_E_DISCONNECTED = -3, /* base grid is not connected                   */
   DCFLOW_E_WORKSPACE = -4,    /* caller buffer smaller than the query said    */
   DCFLOW_E_HIP = -5,          /* a HIP runtime call failed                    */
-  DCFLOW_E_CAND = -6          /* malformed candidate record (see bad_index)   */
+  DCFLOW_E_CAND = -6,         /* malformed candidate record (see bad_index)   */
+  DCFLOW_E_SCRATCH = -7       /* input exceeds DCFLOW_NOALLOC_SCRATCH_BYTES   */
 } dcflow_status;
 
 typedef enum {
@@ -358,6 +359,26 @@ int dcflow_n1_worst_workspace_bytes(const dcflow_batch *batch, int32_t top_k, si
 int dcflow_n1_worst(dcflow_batch *batch, const void *dev_flows, int32_t n_var, dcflow_prec prec,
                     const dcflow_score *dev_scores, int32_t top_k, void *dev_ws, size_t ws_bytes,
                     dcflow_case *dev_out, hipStream_t stream);
+
+/* Capacity of the library's fixed scratch array (bytes, per device). */
+#define DCFLOW_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* dcflow_n1_worst for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same results as dcflow_n1_worst, with the band lists kept in a fixed
+ * device array of the library instead of a caller workspace.  Nothing is
+ * allocated; the caller passes inputs and outputs as for dcflow_n1_worst.
+ * Every device the library runs on holds one such array of
+ * DCFLOW_NOALLOC_SCRATCH_BYTES until the process ends; its address is looked up
+ * on the first call on each device (call with the batch's device current).
+ * All calls on one device share the array: calls that overlap in time on one
+ * device (different streams or host threads) race and must be serialised by
+ * the caller.  Returns DCFLOW_E_SCRATCH, before launching anything, when
+ * dcflow_n1_worst_workspace_bytes for this batch and top_k exceeds the
+ * capacity; other errors as dcflow_n1_worst. */
+int dcflow_n1_worst_noalloc(dcflow_batch *batch, const void *dev_flows, int32_t n_var,
+                            dcflow_prec prec, const dcflow_score *dev_scores, int32_t top_k,
+                            dcflow_case *dev_out, hipStream_t stream);
 
 /* Bytes of device workspace for dcflow_n1_worst_per_case with this per-case cap. */
 int dcflow_n1_worst_per_case_workspace_bytes(const dcflow_batch *batch, int32_t per_case,

@@ -9,6 +9,7 @@
 #include <numeric>
 
 #include <cstdlib>
+#include <mutex>
 
 #include "dcflow_internal.h"
 #include "percase.h"
@@ -861,6 +862,64 @@ int dcflow_n1_worst(dcflow_batch *b, const void *dev_flows, int32_t n_var, dcflo
   return DCFLOW_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free worst-case call: a file-scope device array,
+// one copy per device, held until the process ends.  In host code `scratch`
+// only names the host-side stand-in of the symbol; its device address is looked
+// up once per device (with that device current) and kept, and only that
+// address reaches kernels.
+static __device__ __align__(256) unsigned char scratch[DCFLOW_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices];
+
+// Device address of the current device's scratch array (looked up on first use).
+hipError_t scratch_of_current_device(void **ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
+int dcflow_n1_worst_noalloc(dcflow_batch *b, const void *dev_flows, int32_t n_var,
+                            dcflow_prec prec, const dcflow_score *dev_scores, int32_t top_k,
+                            dcflow_case *dev_out, hipStream_t s) {
+  const int st = check_worst_args(b, dev_flows, n_var, prec, dev_scores, top_k, dev_out);
+  if (st != DCFLOW_OK) return st;
+  size_t need = 0;
+  dcflow_n1_worst_workspace_bytes(b, top_k, &need);
+  if (need > (size_t)DCFLOW_NOALLOC_SCRATCH_BYTES) {
+    fprintf(stderr,
+            "dcflow_n1_worst_noalloc: %zu bytes of scratch needed (%d candidates, top %d), "
+            "the fixed array holds %zu\n",
+            need, b->n_cand, top_k, (size_t)DCFLOW_NOALLOC_SCRATCH_BYTES);
+    return DCFLOW_E_SCRATCH;
+  }
+  void *ws = nullptr;
+  hipError_t e = scratch_of_current_device(&ws);
+  if (e != hipSuccess) return hip_fail(e, "dcflow_n1_worst_noalloc (scratch address)");
+  e = launch_worst(b, dev_flows, n_var, prec, dev_scores, top_k, ws, dev_out, s);
+  if (e != hipSuccess) return hip_fail(e, "dcflow_n1_worst_noalloc");
+  return DCFLOW_OK;
+}
+
 int dcflow_n1_worst_per_case_workspace_bytes(const dcflow_batch *b, int32_t per_case,
                                              size_t *bytes) {
   if (!b || !bytes || per_case < 1 || per_case > DCFLOW_WORST_MAX) return DCFLOW_E_ARG;
@@ -1019,6 +1078,7 @@ const char *dcflow_strerror(int st) {
     case DCFLOW_E_WORKSPACE: return "device buffer too small";
     case DCFLOW_E_HIP: return "HIP runtime error";
     case DCFLOW_E_CAND: return "malformed candidate record";
+    case DCFLOW_E_SCRATCH: return "input too large for the fixed scratch array";
     default: return "unknown status";
   }
 }

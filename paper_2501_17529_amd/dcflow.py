@@ -122,6 +122,7 @@ def _load():
         "dcflow_snapshot_flows": (ctypes.c_int, [P, P, I32, P, P, P]),
         "dcflow_n1_worst_workspace_bytes": (ctypes.c_int, [P, I32, P]),
         "dcflow_n1_worst": (ctypes.c_int, [P, P, I32, ctypes.c_int, P, I32, P, SZ, P, P]),
+        "dcflow_n1_worst_noalloc": (ctypes.c_int, [P, P, I32, ctypes.c_int, P, I32, P, P]),
         "dcflow_step": (ctypes.c_int, [P, P, I32, I32, ctypes.c_int, P, SZ, P, P]),
         "dcflow_set_busbar_injections": (ctypes.c_int, [P, P, I32]),
         "dcflow_batch_set_tuning": (ctypes.c_int, [P, P]),
@@ -153,7 +154,8 @@ EXPORTED = ("dcflow_plan_workspace_bytes", "dcflow_build_ptdf", "dcflow_plan_vie
             "dcflow_batch_create", "dcflow_batch_destroy", "dcflow_eval_topologies",
             "dcflow_flow_bytes", "dcflow_eval_injections", "dcflow_n1_score",
             "dcflow_batch_variant_max", "dcflow_strerror", "dcflow_n1_worst_workspace_bytes",
-            "dcflow_n1_worst", "dcflow_step", "dcflow_set_busbar_injections",
+            "dcflow_n1_worst", "dcflow_n1_worst_noalloc", "dcflow_step",
+            "dcflow_set_busbar_injections",
             "dcflow_fold_stubs", "dcflow_fold_injections", "dcflow_stub_flows",
             "dcflow_n1_worst_per_case_workspace_bytes", "dcflow_n1_worst_per_case",
             "dcflow_batch_set_tuning",
@@ -452,6 +454,17 @@ class Batch:
                                     ctypes.c_void_p(out.data_ptr()), _stream(stream)),
                "dcflow_n1_worst")
         self._worst_ws = ws  # kept until the stream is done with it (next call or object end)
+        return out
+
+    def n1_worst_noalloc(self, flows, n_var, prec, scores, top_k, out, stream=None):
+        """n1_worst through the allocation-free entry point (the library's fixed
+        scratch array instead of a workspace); `out` is the caller's device
+        buffer of n_cand x top_k CASE_DTYPE records."""
+        _check(_lib.dcflow_n1_worst_noalloc(self.h, ctypes.c_void_p(flows.data_ptr()),
+                                            int(n_var), PREC[prec],
+                                            ctypes.c_void_p(scores.data_ptr()), int(top_k),
+                                            ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+               "dcflow_n1_worst_noalloc")
         return out
 
     def n1_worst_per_case(self, flows, n_var, prec, scores, per_case, top_k, out=None,
