@@ -187,6 +187,7 @@ void plan_layout(dcflow_plan *p, const Dims &d, Arena &a) {
   p->d_lsd = a.take<double>((size_t)d.mon_pad * d.ld_o);
   p->d_lsdmax = a.take<double>(d.ld_o);
   p->d_lsd32 = a.take<float>((size_t)d.mon_pad * d.ld_o);
+  p->d_lsd64f = a.take<double>((size_t)d.mon_pad * d.ld_o);
   p->d_fbase = a.take<double>(d.m);
   p->d_fber = a.take<double>(d.ld_er);
   p->d_pbase = a.take<double>(d.ld_h);

@@ -346,6 +346,24 @@ __global__ void k_fber(double *fber, const double *fb, const int32_t *er, int n_
 
 // FP32 copy of Lsd in the accumulator order of the FP32 16x16x4 MFMA, so that the
 // scan seeds each block with one 16-byte load per lane.
+// The FP64 seed in the same block order, each lane's four values in the FP64
+// 16x16x4 accumulator order (rows g + 4 r of its lane group g): one 32-byte read
+// per lane and block in the FP64 scan.
+__global__ void k_lsd64f(d4 *dst, const double *lsd, int ld_o, int mon_pad) {
+  const int ncb = ld_o / 16;
+  const size_t total = (size_t)(mon_pad / 16) * ncb * kWave;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int lane = (int)(idx % kWave);
+  const size_t blk = idx / kWave;
+  const int cb = (int)(blk % ncb), rb = (int)(blk / ncb);
+  const int g = lane / 16, col = cb * 16 + lane % 16;
+  d4 v;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = lsd[(size_t)(rb * 16 + MfmaRow<double>::row(g, r)) * ld_o + col];
+  dst[idx] = v;
+}
+
 __global__ void k_lsd32(float *dst, const double *lsd, int ld_o, int mon_pad) {
   const int ncb = ld_o / 16;
   const size_t total = (size_t)(mon_pad / 16) * ncb * kWave;
@@ -436,6 +454,9 @@ hipError_t launch_build(dcflow_plan *p, hipStream_t s, const double *h_rating, d
   DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_lsd32, dim3(nblk((size_t)p->mon_pad * p->ld_o / 4, 256)), dim3(256), 0, s,
                      p->d_lsd32, p->d_lsd, p->ld_o, p->mon_pad);
+  DCF_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_lsd64f, dim3(nblk((size_t)p->mon_pad * p->ld_o / 4, 256)), dim3(256), 0, s,
+                     reinterpret_cast<d4 *>(p->d_lsd64f), p->d_lsd, p->ld_o, p->mon_pad);
   DCF_CHECK_LAUNCH();
   if (p->n_msub > 0) {
     hipLaunchKernelGGL(k_lsd_multi, dim3(nblk(p->mon_pad, 256), p->n_msub), dim3(256), 0, s,

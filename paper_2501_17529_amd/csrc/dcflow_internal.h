@@ -67,6 +67,8 @@ struct dcflow_plan {
   double *d_lsdmax; // [ld_o] max over the monitored rows of |d_lsd[:, c]| (error guard)
   float *d_lsd32;   // same in FP32, fragment-major: 16 x 16 blocks [mon_pad/16][ld_o/16], each
                     // 64 lanes x 4 rows in the FP32 MFMA accumulator order (rows 4 (lane/16) + r)
+  double *d_lsd64f; // the FP64 values fragment-major the same way, in the FP64 accumulator
+                    // order (rows lane/16 + 4 r)
   double *d_fbase;  // [m]
   double *d_fber;   // [ld_er] base flows of the kept rows (0 on padding)
   double *d_pbase;  // [ld_h]

@@ -53,8 +53,10 @@ __device__ __forceinline__ float absmax3(float m, float a, float b) {
   asm("v_max3_f32 %0, %1, |%2|, |%3|" : "=v"(r) : "v"(m), "v"(a), "v"(b));
   return r;
 }
+// (FP64 has no three-operand maximum: the pair's maximum first, so that the
+// running maximum waits on one instruction per pair, not two)
 __device__ __forceinline__ double absmax3(double m, double a, double b) {
-  return __builtin_fmax(__builtin_fmax(m, __builtin_fabs(a)), __builtin_fabs(b));
+  return __builtin_fmax(m, __builtin_fmax(__builtin_fabs(a), __builtin_fabs(b)));
 }
 
 // acc + max(|a|, 1) + max(|b|, 1) in four VALU instructions (the compiler's fmax
@@ -67,7 +69,7 @@ __device__ __forceinline__ float add_absmax1(float acc, float a, float b) {
   return acc;
 }
 __device__ __forceinline__ double add_absmax1(double acc, double a, double b) {
-  return acc + __builtin_fmax(__builtin_fabs(a), 1.0) + __builtin_fmax(__builtin_fabs(b), 1.0);
+  return acc + (__builtin_fmax(__builtin_fabs(a), 1.0) + __builtin_fmax(__builtin_fabs(b), 1.0));
 }
 
 // running maximum of non-negative values in LDS: their IEEE bit patterns order
@@ -99,6 +101,7 @@ struct ScanArgs {
   const uint32_t *status; // [n_cand]
   const double *lsd;      // [mon_pad][ld_o]
   const float *lsd32;     // fragment-major FP32 copy
+  const double *lsd64f;   // fragment-major FP64 copy
   const double *inv_r;    // [mon_pad]
   const float *ur32;      // [n_elem][mon_pad] FP32 U / r
   const float *w32;       // [n_elem][ld_o] FP32 W
@@ -278,15 +281,15 @@ __device__ __forceinline__ void tile_load_seed(f4 (&c)[4][4], const ScanArgs &A,
 }
 __device__ __forceinline__ void tile_load_seed(d4 (&c)[4][2], const ScanArgs &A, int rowbase,
                                                int colbase, int g, int li, int lane) {
+  const d4 *seed = reinterpret_cast<const d4 *>(A.lsd64f) +
+                   ((size_t)(rowbase / 16) * (A.ld_o / 16) + colbase / 16) * kWave + lane;
+  const size_t rstride = (size_t)(A.ld_o / 16) * kWave;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const double *src = A.lsd + (size_t)(rowbase + a * 16) * A.ld_o + colbase + b * 16 + li;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) c[a][b][r] = src[(size_t)MfmaRow<double>::row(g, r) * A.ld_o];
-    }
-  (void)lane;
+    for (int b = 0; b < 2; ++b) c[a][b] = seed[a * rstride + b * kWave];
+  (void)g;
+  (void)li;
 }
 // One k step of L = seed + (U / r) W on the matrix cores.
 __device__ __forceinline__ void tile_mfma_step(f4 (&c)[4][4], const float (&fa)[4],
@@ -370,10 +373,15 @@ __device__ __forceinline__ bool guarded(const ScanArgs &A, int cand, int c) {
 template <typename T, int VC>
 __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int band) {
   constexpr int TM = 64, TN = ScanCfg<T>::TN, NB = TN / 16;
+  // y and F~ are stored variant-minor with a stride of VC + 1 (an odd number of
+  // elements: the 16 columns and the 4 row groups a read instruction touches fall
+  // in different banks), so that every read of the variant loop is one base
+  // address per tile plus a compile-time offset
+  constexpr int VS = VC + 1;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int ld_o = A.ld_o, rchunk = A.rchunk;
-  T *ys = reinterpret_cast<T *>(smem_raw);  // [VC][ld_o]
-  T *fs = ys + (size_t)VC * ld_o;           // [VC][rchunk]
+  T *ys = reinterpret_cast<T *>(smem_raw);  // [ld_o][VS]
+  T *fs = ys + (size_t)VS * ld_o;           // [rchunk][VS]
   __shared__ double s_red[4][VC];
   __shared__ T s_n0[VC];
   __shared__ int s_nf[VC];
@@ -397,13 +405,14 @@ __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int b
   const int r0 = band * A.band_rows, r1 = min(r0 + A.band_rows, A.mon_pad);
   __syncthreads();
 
-  // y for every contingency column and variant of the launch; a non-finite
-  // flow marks its variant in s_nf at once (rare, so not kept in registers)
-  for (int vi = 0; vi < nv; ++vi) {
+  // y for every contingency column and variant of the launch (0 for the variants
+  // past nv); a non-finite flow marks its variant in s_nf at once (rare, so not
+  // kept in registers)
+  for (int vi = 0; vi < VC; ++vi) {
     bool nf = false;
     for (int c = tid; c < ld_o; c += blockDim.x) {
-      const T y = ycol(F + (size_t)vi * A.ld_f, A, cand, c, nf);
-      ys[(size_t)vi * ld_o + c] = guarded(A, cand, c) ? (T)0 : y;
+      const T y = vi < nv ? ycol(F + (size_t)vi * A.ld_f, A, cand, c, nf) : (T)0;
+      ys[(size_t)c * VS + vi] = guarded(A, cand, c) ? (T)0 : y;
     }
     if (nf) s_nf[vi] = 1;
   }
@@ -424,7 +433,7 @@ __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int b
       const int vi = i0 / rows, rr = i - vi * rows;
       bool nf = false;
       const T fv = ftilde(F + (size_t)vi * A.ld_f, A.inv_r, rc0 + rr, A.n_mon, nf);
-      fs[(size_t)vi * rchunk + fs_pos(fs, rr)] = fv;
+      fs[(size_t)fs_pos(fs, rr) * VS + vi] = fv;
       const T m = wave_max(tabs(fv));
       if (lane == 0) lds_max_nonneg(&s_n0[vi], m);
       if (nf) s_nf[vi] = 1;
@@ -437,19 +446,20 @@ __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int b
       const int rowbase = rc0 + tr * TM, colbase = tc * TN;
       T L[4][NB][4];
       build_tile(L, A, e0, k, rowbase, colbase, g, li, lane);
+      const T *fsb = fs + (size_t)((rowbase - rc0) + 4 * g) * VS;
+      const T *ysb = ys + (size_t)(colbase + li) * VS;
 #pragma unroll
       for (int vi = 0; vi < VC; ++vi) {
         if (vi >= nv) continue;
-        const T *fsv = fs + (size_t)vi * rchunk + (rowbase - rc0) + 4 * g;
-        const T *ysv = ys + (size_t)vi * ld_o + colbase + li;
         T fr[4][4], yc[NB];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) fr[a][r] = fsv[a * 16 + r];
+          for (int r = 0; r < 4; ++r) fr[a][r] = fsb[(a * 16 + r) * VS + vi];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) yc[b] = ysv[b * 16];
-        T m = mx[vi];
+        for (int b = 0; b < NB; ++b) yc[b] = ysb[b * 16 * VS + vi];
+        // two running maxima (even and odd row blocks) halve the dependent chain
+        T m0 = mx[vi], m1 = (T)0;
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -458,9 +468,12 @@ __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int b
             for (int r = 0; r < 4; r += 2) {
               const T p0 = tfma(L[a][b][r], yc[b], fr[a][r]);
               const T p1 = tfma(L[a][b][r + 1], yc[b], fr[a][r + 1]);
-              m = absmax3(m, p0, p1);
+              if (a % 2 == 0)
+                m0 = absmax3(m0, p0, p1);
+              else
+                m1 = absmax3(m1, p0, p1);
             }
-        mx[vi] = m;
+        mx[vi] = tmax(m0, m1);
       }
     }
   }
@@ -1674,9 +1687,10 @@ inline int grid_x(const dcflow_batch *bt, const ScanArgs &a) {
 template <typename T, int VC, int MINW>
 hipError_t launch_max(const ScanArgs &a0, const dcflow_batch *bt, int nvar, hipStream_t s) {
   ScanArgs a = a0;
-  const size_t fixed = sizeof(T) * (size_t)VC * a.ld_o;
-  choose_rows(bt, fixed, sizeof(T) * VC, a.mon_pad, a.ld_o, sizeof(T), kLdsOccupancy, a);
-  const size_t lds = fixed + sizeof(T) * (size_t)VC * a.rchunk;
+  constexpr int VS = VC + 1;  // variant-minor LDS rows (see scan_max_item)
+  const size_t fixed = sizeof(T) * (size_t)VS * a.ld_o;
+  choose_rows(bt, fixed, sizeof(T) * VS, a.mon_pad, a.ld_o, sizeof(T), kLdsOccupancy, a);
+  const size_t lds = fixed + sizeof(T) * (size_t)VS * a.rchunk;
   if (lds > lds_budget(bt, VC, sizeof(T))) return hipErrorInvalidValue;
   const int ny = (nvar + VC - 1) / VC;
   if (ny > kQueueWin) a.persistent = 0;  // one counter per variant group
@@ -1741,6 +1755,7 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   a.status = bt->d_status;
   a.lsd = p->d_lsd;
   a.lsd32 = p->d_lsd32;
+  a.lsd64f = p->d_lsd64f;
   a.inv_r = p->d_inv_r;
   a.ur32 = bt->d_ur32;
   a.w32 = bt->d_w32;
@@ -1792,7 +1807,7 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
     // the requested variant group, else the widest whose y fits the LDS budget
     // with one 64-row band and that the variants fill
     auto fits = [&](int vc) {
-      return sizeof(T) * (size_t)vc * (p->ld_o + 64) <= lds_budget(bt, vc, sizeof(T));
+      return sizeof(T) * (size_t)(vc + 1) * (p->ld_o + 64) <= lds_budget(bt, vc, sizeof(T));
     };
     int vc = bt->tune.scan_vc;
     bool known = false;
@@ -1869,6 +1884,7 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   a.status = bt->d_status;
   a.lsd = p->d_lsd;
   a.lsd32 = p->d_lsd32;
+  a.lsd64f = p->d_lsd64f;
   a.inv_r = p->d_inv_r;
   a.ur32 = bt->d_ur32;
   a.w32 = bt->d_w32;
