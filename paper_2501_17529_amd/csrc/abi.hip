@@ -188,6 +188,7 @@ void plan_layout(dcflow_plan *p, const Dims &d, Arena &a) {
   p->d_lsdmax = a.take<double>(d.ld_o);
   p->d_lsd32 = a.take<float>((size_t)d.mon_pad * d.ld_o);
   p->d_lsd64f = a.take<double>((size_t)d.mon_pad * d.ld_o);
+  p->d_lsdT = a.take<double>((size_t)d.mon_pad * d.ld_o);
   p->d_fbase = a.take<double>(d.m);
   p->d_fber = a.take<double>(d.ld_er);
   p->d_pbase = a.take<double>(d.ld_h);
@@ -821,9 +822,10 @@ int dcflow_n1_score(dcflow_batch *b, const void *dev_flows, int32_t n_var, dcflo
 
 int dcflow_n1_worst_workspace_bytes(const dcflow_batch *b, int32_t top_k, size_t *bytes) {
   if (!b || !bytes || top_k < 1 || top_k > DCFLOW_WORST_MAX) return DCFLOW_E_ARG;
-  // one 16-byte entry (load, key) per case, band and candidate
-  *bytes = std::max<size_t>(
-      (size_t)b->n_cand * (worst_bands(b->plan) + b->nmb + 1) * top_k * 16, 256);
+  // one 16-byte entry (load, key) per list place, band and candidate (the bands, the
+  // multi-outage chunks and the guard's list), then one threshold per band
+  const int nb = worst_bands(b->plan);
+  *bytes = worst_list_bytes(b->n_cand, nb + b->nmb + 1, top_k) + (size_t)b->n_cand * nb * 8;
   return DCFLOW_OK;
 }
 
@@ -924,8 +926,9 @@ int dcflow_n1_worst_noalloc(dcflow_batch *b, const void *dev_flows, int32_t n_va
 int dcflow_n1_worst_per_case_workspace_bytes(const dcflow_batch *b, int32_t per_case,
                                              size_t *bytes) {
   if (!b || !bytes || per_case < 1 || per_case > DCFLOW_WORST_MAX) return DCFLOW_E_ARG;
-  // one 16-byte entry (load, key) per list place, case and candidate
-  *bytes = std::max<size_t>((size_t)b->n_cand * per_case_slots(b->plan) * per_case * 16, 256);
+  // one 16-byte entry (load, key) per list place, case and candidate, then the case
+  // maxima of the pruning sweep
+  *bytes = std::max<size_t>(per_case_workspace(b, per_case), 256);
   return DCFLOW_OK;
 }
 

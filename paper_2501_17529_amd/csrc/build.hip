@@ -364,6 +364,18 @@ __global__ void k_lsd64f(d4 *dst, const double *lsd, int ld_o, int mon_pad) {
   dst[idx] = v;
 }
 
+// dst[c][r] = src[r][c] for an R x C row-major matrix (32 x 32 LDS tiles).
+__global__ void k_transpose(double *dst, const double *src, int R, int C) {
+  __shared__ double tile[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
+  for (int r = ty; r < 32; r += 8)
+    if (r0 + r < R && c0 + tx < C) tile[r][tx] = src[(size_t)(r0 + r) * C + c0 + tx];
+  __syncthreads();
+  for (int c = ty; c < 32; c += 8)
+    if (c0 + c < C && r0 + tx < R) dst[(size_t)(c0 + c) * R + r0 + tx] = tile[tx][c];
+}
+
 __global__ void k_lsd32(float *dst, const double *lsd, int ld_o, int mon_pad) {
   const int ncb = ld_o / 16;
   const size_t total = (size_t)(mon_pad / 16) * ncb * kWave;
@@ -457,6 +469,9 @@ hipError_t launch_build(dcflow_plan *p, hipStream_t s, const double *h_rating, d
   DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_lsd64f, dim3(nblk((size_t)p->mon_pad * p->ld_o / 4, 256)), dim3(256), 0, s,
                      reinterpret_cast<d4 *>(p->d_lsd64f), p->d_lsd, p->ld_o, p->mon_pad);
+  DCF_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_transpose, dim3(nblk(p->ld_o, 32), nblk(p->mon_pad, 32)), dim3(32, 8), 0, s,
+                     p->d_lsdT, p->d_lsd, p->mon_pad, p->ld_o);
   DCF_CHECK_LAUNCH();
   if (p->n_msub > 0) {
     hipLaunchKernelGGL(k_lsd_multi, dim3(nblk(p->mon_pad, 256), p->n_msub), dim3(256), 0, s,

@@ -69,6 +69,7 @@ struct dcflow_plan {
                     // 64 lanes x 4 rows in the FP32 MFMA accumulator order (rows 4 (lane/16) + r)
   double *d_lsd64f; // the FP64 values fragment-major the same way, in the FP64 accumulator
                     // order (rows lane/16 + 4 r)
+  double *d_lsdT;   // [ld_o][mon_pad] the FP64 values column-major (walks down one column)
   double *d_fbase;  // [m]
   double *d_fber;   // [ld_er] base flows of the kept rows (0 on padding)
   double *d_pbase;  // [ld_h]
@@ -165,11 +166,20 @@ hipError_t launch_factors(dcflow_batch *b, hipStream_t s);
 hipError_t launch_injections(dcflow_batch *b, const double *inj, int nvar, int shared,
                              int prec, void *flows, int c0, int c1, hipStream_t s);
 // score (a5)
-// worst-case lists (agg_i) of the winners; worst_bands = row bands of that pass
+// worst-case lists (agg_i) of the winners; worst_bands = row bands of that pass, and
+// its workspace: the band lists (worst_list_bytes), then one threshold per band
 int worst_bands(const dcflow_plan *p);
+size_t worst_list_bytes(int n_cand, int nbt, int top_k);
 hipError_t launch_worst(dcflow_batch *b, const void *flows, int nvar, int prec,
                         const dcflow_score *scores, int top_k, void *ws, dcflow_case *out,
                         hipStream_t s);
+// The winners' maxima of every contingency column, the N-0 maximum and the top_k-th
+// largest of them (the first sweep of the worst-case pass), per candidate in cmx
+// [n_cand][ld_o + 2]; only when one row band covers the monitored rows
+bool case_maxima_supported(const dcflow_plan *p);
+hipError_t launch_case_maxima(dcflow_batch *b, const void *flows, int nvar, int prec,
+                              const dcflow_score *scores, int top_k, double *cmx,
+                              hipStream_t s);
 // candidates [c0, c1); a part of the batch runs without the persistent queue and in
 // candidate order
 hipError_t launch_score(dcflow_batch *b, const void *flows, int nvar, int prec,

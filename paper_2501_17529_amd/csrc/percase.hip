@@ -17,6 +17,12 @@
 namespace dcflow {
 namespace {
 
+struct PcEntry;
+
+}  // namespace
+size_t pc_list_bytes(int n_cand, int nslots, int per_case);
+namespace {
+
 struct PcEntry {  // one list entry: |p| / r and its key (case slot x n_mon + row)
   double v;
   int k, pad;
@@ -57,6 +63,7 @@ struct PcArgs {
   const float *ur32, *w32;
   int ld_o, mon_pad, n_mon;
   const double *lsd;     // [mon_pad][ld_o]
+  const double *lsdT;    // [ld_o][mon_pad] the same column-major
   const double *inv_r;   // [mon_pad]
   const double *invden;  // [n_cand][ld_o]
   const uint32_t *isl;   // [n_cand][ld_o / 32]
@@ -74,7 +81,28 @@ struct PcArgs {
   PcEntry *ws;  // [n_cand][nslots][per_case]
   const uint32_t *flag;  // [n_cand][ld_o / 32] columns the FP32 scan's error guard
                          // computes in FP64 (null: none)
+  const double *cmx;     // [n_cand][ld_o + 2] the winner's column maxima, N-0 maximum and
+                         // their top_k-th largest (tau), or null: no pruning
+  double prune_margin;   // absolute margin of the pruning test (rating units): the tiles
+                         // and this kernel round an entry differently by at most this
 };
+
+// A case whose maximum (from the tiled sweep) is under tau, the top_k-th largest of
+// the case maxima, cannot place an entry in the final list: top_k other cases reach
+// tau.  The margin covers the difference between the tiles' rounding and this
+// kernel's (twice the FP32 error bound the guard enforces); guarded columns and
+// multi-outage cases are never pruned.
+__device__ __forceinline__ bool pc_pruned(const PcArgs &A, int cand, int slot) {
+  if (!A.cmx || slot > A.n_ctg) return false;
+  const double *o = A.cmx + (size_t)cand * (A.ld_o + 2);
+  const double tau = o[A.ld_o + 1];
+  if (tau < 0.0) return false;
+  const double v = slot == 0 ? o[A.ld_o] : o[slot - 1];
+  if (slot > 0 && A.flag &&
+      ((A.flag[(size_t)cand * (A.ld_o / 32) + (slot - 1) / 32] >> ((slot - 1) % 32)) & 1u))
+    return false;
+  return v + A.prune_margin < tau - A.prune_margin;
+}
 
 template <typename T>
 struct PcOps;
@@ -134,7 +162,7 @@ __global__ void __launch_bounds__(256) k_pc_cols(PcArgs A) {
   }
   int vstar = 0;
   const int c = slot - 1;
-  bool live = !pc_skip(A, cand, vstar);
+  bool live = !pc_skip(A, cand, vstar) && !pc_pruned(A, cand, slot);
   if (live && c >= 0)
     live = !((A.isl[(size_t)cand * (A.ld_o / 32) + c / 32] >> (c % 32)) & 1u);
   const bool guard = live && c >= 0 && A.flag != nullptr &&
@@ -188,6 +216,133 @@ __global__ void __launch_bounds__(256) k_pc_cols(PcArgs A) {
     }
   }
   pc_store(A, cand, slot, lv, lk);
+}
+
+// Level 1 after pruning (one row band): the cases that survive pc_pruned, one wave
+// per case and the rows spread over its lanes.  The block first collects its
+// candidate's surviving slots (N-0 and contingency columns) in LDS; each lane keeps
+// a sorted list of its rows' largest loads, and the wave's list is taken one entry
+// per round from the lanes' heads.  The arithmetic is that of k_pc_cols (guarded
+// columns in FP64), so the lists are the same; pruned slots are not written (the
+// merge skips them).
+template <typename T, int KM, bool STAGE>
+__global__ void __launch_bounds__(256) k_pc_sel(PcArgs A) {
+  // [n_ctg + 1] surviving slots; with STAGE then the candidate's F~ and U / r of its
+  // k elements on the monitored rows ([1 + k][mon_pad] of T), read by every case
+  extern __shared__ __attribute__((aligned(16))) int s_sel[];
+  __shared__ int s_n;
+  const int cand = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+  int vstar = 0;
+  if (pc_skip(A, cand, vstar)) return;
+  if (tid == 0) s_n = 0;
+  T *s_f = reinterpret_cast<T *>(s_sel + ((A.n_ctg + 1 + 3) / 4) * 4);
+  T *s_ur = s_f + A.mon_pad;
+  const int e0s = A.off[cand], ks = A.off[cand + 1] - e0s;
+  if (STAGE) {
+    const T *Fs = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vstar) * A.ld_f;
+    for (int row = tid; row < A.n_mon; row += blockDim.x) {
+      s_f[row] = (T)((double)Fs[row] * A.inv_r[row]);
+      for (int e = 0; e < ks; ++e) s_ur[(size_t)e * A.mon_pad + row] = PcOps<T>::ur(A, e0s + e, row);
+    }
+  }
+  __syncthreads();
+  for (int slot = tid; slot <= A.n_ctg; slot += blockDim.x) {
+    bool keep = !pc_pruned(A, cand, slot);
+    if (keep && slot > 0)
+      keep = !((A.isl[(size_t)cand * (A.ld_o / 32) + (slot - 1) / 32] >> ((slot - 1) % 32)) & 1u);
+    if (keep) s_sel[atomicAdd(&s_n, 1)] = slot;
+  }
+  __syncthreads();
+  const int n_sel = s_n;
+  const T *Fv = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vstar) * A.ld_f;
+  const int e0 = A.off[cand], k = A.off[cand + 1] - e0;
+  for (int q = wv; q < n_sel; q += 4) {
+    const int slot = s_sel[q], c = slot - 1;
+    const bool guard = c >= 0 && A.flag != nullptr &&
+                       ((A.flag[(size_t)cand * (A.ld_o / 32) + c / 32] >> (c % 32)) & 1u);
+    T lv[KM];
+    int lk[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+      lv[j] = (T)-1;
+      lk[j] = kEmptyKey;
+    }
+    double y64 = 0.0, w64[kMaxRank];
+    T y = (T)0, w[kMaxRank];
+#pragma unroll
+    for (int e = 0; e < kMaxRank; ++e) {
+      w64[e] = 0.0;
+      w[e] = (T)0;
+    }
+    if (c >= 0) {
+      const double inv = A.invden[(size_t)cand * A.ld_o + c];
+      y64 = (c < A.n_out ? (double)Fv[A.out_pos[c]] : A.gen_y[c - A.n_out]) * inv;
+      y = (T)y64;
+#pragma unroll
+      for (int e = 0; e < kMaxRank; ++e)
+        if (e < k) {
+          w64[e] = PcOps<double>::w(A, e0 + e, c);
+          w[e] = PcOps<T>::w(A, e0 + e, c);
+        }
+    }
+    for (int row = lane; row < A.n_mon; row += kWave) {
+      T a;
+      if (c < 0) {
+        const T f = STAGE ? s_f[row] : (T)((double)Fv[row] * A.inv_r[row]);
+        a = f < (T)0 ? -f : f;
+      } else if (guard) {
+        double l = A.lsdT[(size_t)c * A.mon_pad + row];
+#pragma unroll
+        for (int e = 0; e < kMaxRank; ++e)
+          if (e < k) l = pc_fma(PcOps<double>::ur(A, e0 + e, row), w64[e], l);
+        const double p = pc_fma(l, y64, (double)Fv[row] * A.inv_r[row]);
+        a = (T)(p < 0.0 ? -p : p);
+      } else {
+        const T f = STAGE ? s_f[row] : (T)((double)Fv[row] * A.inv_r[row]);
+        T l = (T)A.lsdT[(size_t)c * A.mon_pad + row];
+#pragma unroll
+        for (int e = 0; e < kMaxRank; ++e)
+          if (e < k)
+            l = pc_fma(STAGE ? s_ur[(size_t)e * A.mon_pad + row] : PcOps<T>::ur(A, e0 + e, row),
+                       w[e], l);
+        const T p = pc_fma(l, y, f);
+        a = p < (T)0 ? -p : p;
+      }
+      const int key = slot * A.n_mon + row;
+      if (pc_better(a, key, lv[KM - 1], lk[KM - 1])) pc_insert(lv, lk, a, key);
+    }
+    // the case's list: per_case rounds of the best head over the wave
+    PcEntry *dst = A.ws + ((size_t)cand * A.nslots + slot) * A.per_case;
+    for (int j = 0; j < A.per_case; ++j) {
+      T bv = lv[0];
+      int bk = lk[0];
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const T ov = __shfl_xor(bv, o);
+        const int ok = __shfl_xor(bk, o);
+        if (pc_better(ov, ok, bv, bk)) {
+          bv = ov;
+          bk = ok;
+        }
+      }
+      if (lane == 0) {
+        PcEntry e;
+        e.v = bk == kEmptyKey ? -1.0 : (double)bv;
+        e.k = bk;
+        e.pad = 0;
+        dst[j] = e;
+      }
+      if (bk != kEmptyKey && lk[0] == bk) {
+#pragma unroll
+        for (int t = 0; t < KM - 1; ++t) {
+          lv[t] = lv[t + 1];
+          lk[t] = lk[t + 1];
+        }
+        lv[KM - 1] = (T)-1;
+        lk[KM - 1] = kEmptyKey;
+      }
+    }
+  }
 }
 
 // Level 1, multi-outage cases: slot 1 + n_ctg + q.
@@ -263,13 +418,20 @@ __global__ void __launch_bounds__(256) k_pc_fin(PcArgs A, dcflow_case *out) {
     lk[j] = kEmptyKey;
   }
   const PcEntry *base = A.ws + (size_t)cand * A.nslots * A.per_case;
-  for (int s = tid; s < A.nslots; s += blockDim.x)
+  int vstar = 0;
+  const bool skip = A.cmx != nullptr && pc_skip(A, cand, vstar);  // (lists not written)
+  for (int s = tid; s < A.nslots && !skip; s += blockDim.x) {
+    if (pc_pruned(A, cand, s)) continue;
+    if (A.cmx != nullptr && s > 0 && s <= A.n_ctg &&
+        ((A.isl[(size_t)cand * (A.ld_o / 32) + (s - 1) / 32] >> ((s - 1) % 32)) & 1u))
+      continue;  // islanding columns: not written by k_pc_sel
     for (int j = 0; j < A.per_case; ++j) {
       const PcEntry e = base[(size_t)s * A.per_case + j];
       if (e.k == kEmptyKey) break;  // lists are sorted, empties last
       if (!pc_better(e.v, e.k, lv[KM - 1], lk[KM - 1])) break;
       pc_insert(lv, lk, e.v, e.k);
     }
+  }
   for (int j = 0; j < A.top_k; ++j) {
     double bv = lv[0];
     int bk = lk[0];
@@ -342,6 +504,7 @@ hipError_t run_pc(dcflow_batch *bt, const T *flows, int nvar, const dcflow_score
   a.mon_pad = p->mon_pad;
   a.n_mon = p->n_mon;
   a.lsd = p->d_lsd;
+  a.lsdT = p->d_lsdT;
   a.inv_r = p->d_inv_r;
   a.invden = bt->d_invden;
   a.isl = bt->d_isl;
@@ -364,12 +527,40 @@ hipError_t run_pc(dcflow_batch *bt, const T *flows, int nvar, const dcflow_score
   a.nslots = per_case_slots(p);
   a.ws = static_cast<PcEntry *>(ws);
   a.flag = sizeof(T) == 4 && bt->guard_valid ? bt->d_flag : nullptr;
+  a.cmx = nullptr;
+  a.prune_margin = sizeof(T) == 4 ? 2e-4 : 1e-9;
+  if (case_maxima_supported(p)) {
+    // the case maxima of the winners first (after the per-case lists in the workspace)
+    double *cmx = reinterpret_cast<double *>(
+        static_cast<char *>(ws) + pc_list_bytes(bt->n_cand, a.nslots, per_case));
+    const hipError_t e = launch_case_maxima(bt, flows, nvar, sizeof(T) == 4 ? DCFLOW_FP32
+                                                                            : DCFLOW_FP64,
+                                            scores, top_k, cmx, s);
+    if (e != hipSuccess) return e;
+    a.cmx = cmx;
+  }
   const unsigned nc = (unsigned)bt->n_cand;
-  const dim3 gcols(nc, (unsigned)((a.n_ctg + 1 + 255) / 256));
-  if (per_case <= 4)
-    k_pc_cols<T, 4><<<gcols, dim3(256), 0, s>>>(a);
-  else
-    k_pc_cols<T, 16><<<gcols, dim3(256), 0, s>>>(a);
+  if (a.cmx) {
+    const size_t sel = sizeof(int) * (size_t)((a.n_ctg + 1 + 3) / 4 * 4);
+    const size_t staged = sel + sizeof(T) * (size_t)(1 + bt->kmax) * p->mon_pad;
+    if (staged <= 64 * 1024) {
+      if (per_case <= 4)
+        k_pc_sel<T, 4, true><<<dim3(nc), dim3(256), staged, s>>>(a);
+      else
+        k_pc_sel<T, 16, true><<<dim3(nc), dim3(256), staged, s>>>(a);
+    } else {
+      if (per_case <= 4)
+        k_pc_sel<T, 4, false><<<dim3(nc), dim3(256), sel, s>>>(a);
+      else
+        k_pc_sel<T, 16, false><<<dim3(nc), dim3(256), sel, s>>>(a);
+    }
+  } else {
+    const dim3 gcols(nc, (unsigned)((a.n_ctg + 1 + 255) / 256));
+    if (per_case <= 4)
+      k_pc_cols<T, 4><<<gcols, dim3(256), 0, s>>>(a);
+    else
+      k_pc_cols<T, 16><<<gcols, dim3(256), 0, s>>>(a);
+  }
   DCF_CHECK_LAUNCH();
   if (a.n_multi > 0) {
     const dim3 gm(nc, (unsigned)((a.n_multi + 255) / 256));
@@ -390,6 +581,16 @@ hipError_t run_pc(dcflow_batch *bt, const T *flows, int nvar, const dcflow_score
 }  // namespace
 
 int per_case_slots(const dcflow_plan *p) { return 1 + p->n_out + p->n_gen + p->n_multi; }
+
+size_t pc_list_bytes(int n_cand, int nslots, int per_case) {
+  return ((size_t)n_cand * nslots * per_case * sizeof(PcEntry) + 255) / 256 * 256;
+}
+
+size_t per_case_workspace(const dcflow_batch *bt, int per_case) {
+  const dcflow_plan *p = bt->plan;
+  return pc_list_bytes(bt->n_cand, per_case_slots(p), per_case) +
+         (case_maxima_supported(p) ? (size_t)bt->n_cand * (p->ld_o + 3) * sizeof(double) : 0);
+}
 
 hipError_t launch_worst_per_case(dcflow_batch *bt, const void *flows, int nvar, int prec,
                                  const dcflow_score *scores, int per_case, int top_k, void *ws,

@@ -134,6 +134,10 @@ struct ScanArgs {
   const dcflow_score *scores;  // [n_cand] winners of a preceding n1_score
   int top_k;
   WEntry *wpart;       // [n_cand][nbt][top_k] band lists of dcflow_n1_worst
+  double *cmx_out;     // k_scan_colmax, non-null: per candidate the column maxima [ld_o]
+                       // (-1 for unscored columns), the N-0 maximum and tau ([ld_o + 2]);
+                       // one band must cover every monitored row
+  double *tau;         // [n_cand][nbands] lower bounds of the bands' top_k-th case
   // multi-outage N-1 cases (scanned apart, in row chunks of kMultiRows)
   int n_multi;
   const int32_t *moff, *mcol;   // case q: sub-columns moff[q] .. moff[q+1]-1
@@ -545,10 +549,10 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
   bool nf = false;
   for (int c = tid; c < ld_o; c += blockDim.x) {
     const T y = ycol(Fv, A, cand, c, nf);
-    const bool g = guarded(A, cand, c);
-    ys[c] = g ? (T)0 : y;
+    const bool gd = guarded(A, cand, c);
+    ys[c] = gd ? (T)0 : y;
     const bool valid =
-        c < A.n_ctg && !g && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
+        c < A.n_ctg && !gd && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
     colw[c] = valid ? (T)1 : (T)0;
   }
   const int r0 = band * A.band_rows, r1 = min(r0 + A.band_rows, A.mon_pad);
@@ -812,6 +816,150 @@ __device__ __forceinline__ void list_insert(T (&lv)[KM], int (&lk)[KM], T v, int
   }
 }
 
+// Item (cand, band) of the winning variant: the band's column maxima over the
+// scored contingency columns and its N-0 maximum.  They are distinct elements, so
+// the top_k-th largest of them, tau, bounds the band's top_k-th case from below:
+// k_scan_worst reviews only blocks that reach it.  The tiles are built with the
+// same code as there, so the values agree bit for bit.
+template <typename T>
+__device__ __forceinline__ void scan_colmax_item(const ScanArgs &A, int cand, int band) {
+  constexpr int TM = 64, TN = ScanCfg<T>::TN, NB = TN / 16;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  const int ld_o = A.ld_o, rchunk = A.rchunk;
+  T *ys = reinterpret_cast<T *>(smem_raw);  // [ld_o]
+  T *colw = ys + ld_o;                      // [ld_o]
+  T *fs = colw + ld_o;                      // [rchunk]
+  T *cmx = fs + rchunk;                     // [ld_o] column maxima of the band
+  __shared__ T s_bv[4];
+  __shared__ int s_bi[4];
+  __shared__ T s_n0max;
+
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, g = lane / 16, li = lane % 16;
+  const int e0 = A.off[cand];
+  const int k = A.off[cand + 1] - e0;
+  const dcflow_score sc = A.scores[cand];
+  const bool skip = (sc.status & (DCFLOW_ST_DISCONNECTED | DCFLOW_ST_NONFINITE)) != 0 ||
+                    sc.best_variant < 0 || sc.best_variant >= A.nvar;
+  double *co = A.cmx_out ? A.cmx_out + (size_t)cand * (ld_o + 2) : nullptr;
+  if (skip) {
+    if (tid == 0) A.tau[(size_t)cand * A.nbands + band] = -1.0;
+    if (co)
+      for (int c = tid; c < ld_o + 2; c += blockDim.x) co[c] = -1.0;
+    return;
+  }
+  const T *Fv = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + sc.best_variant) * A.ld_f;
+  bool nf = false;
+  for (int c = tid; c < ld_o; c += blockDim.x) {
+    const T y = ycol(Fv, A, cand, c, nf);
+    const bool gd = guarded(A, cand, c);
+    ys[c] = gd ? (T)0 : y;
+    const bool valid =
+        c < A.n_ctg && !gd && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
+    colw[c] = valid ? (T)1 : (T)0;
+    cmx[c] = (T)0;
+  }
+  if (tid == 0) s_n0max = (T)0;
+  const int r0 = band * A.band_rows, r1 = min(r0 + A.band_rows, A.mon_pad);
+  const int ntc = ld_o / TN;
+  for (int rc0 = r0; rc0 < r1; rc0 += rchunk) {
+    const int rows = min(rchunk, r1 - rc0);
+    __syncthreads();
+    for (int rr = tid; rr < rows; rr += blockDim.x) {
+      const int row = rc0 + rr;
+      const T fv = ftilde(Fv, A.inv_r, row, A.n_mon, nf);
+      fs[fs_pos(fs, rr)] = fv;
+      if (row < A.n_mon) lds_max_nonneg(&s_n0max, tabs(fv));
+    }
+    __syncthreads();
+    const int nt = (rows / TM) * ntc;
+    for (int tile = wv; tile < nt; tile += 4) {
+      const int tr = tile / ntc, tc = tile - tr * ntc;
+      const int rowbase = rc0 + tr * TM, colbase = tc * TN;
+      T L[4][NB][4];
+      build_tile(L, A, e0, k, rowbase, colbase, g, li, lane);
+      const T *fsv = fs + (rowbase - rc0) + 4 * g;
+      T fr[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) fr[a][r] = fsv[a * 16 + r];
+      // per column: the maximum over the lane's 16 rows, then over the 4 lane groups
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int c = colbase + b * 16 + li;
+        const T yc = ys[c];
+        T cm = (T)0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int r = 0; r < 4; r += 2)
+            cm = absmax3(cm, tfma(L[a][b][r], yc, fr[a][r]), tfma(L[a][b][r + 1], yc, fr[a][r + 1]));
+        cm = tmax(cm, __shfl_xor(cm, 16));
+        cm = tmax(cm, __shfl_xor(cm, 32));
+        if (g == 0 && colw[c] != (T)0) lds_max_nonneg(&cmx[c], cm);
+      }
+    }
+  }
+  __syncthreads();
+  // tau: top_k rounds of "the largest after the previous one" (ties by index; the
+  // N-0 maximum is index ld_o); -1 when there are fewer values than top_k
+  T prev = (T)0;
+  int prev_i = -1;
+  bool any = true;
+  for (int j = 0; j < A.top_k && any; ++j) {
+    T bv = (T)-1;
+    int bi = 0x7fffffff;
+    for (int c = tid; c <= ld_o; c += blockDim.x) {
+      const T v = c < ld_o ? (colw[c] != (T)0 ? cmx[c] : (T)-1) : s_n0max;
+      const bool after = j == 0 || v < prev || (v == prev && c > prev_i);
+      if (v >= (T)0 && after && (v > bv || (v == bv && c < bi))) {
+        bv = v;
+        bi = c;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const T ov = __shfl_xor(bv, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      s_bv[wv] = bv;
+      s_bi[wv] = bi;
+    }
+    __syncthreads();
+    T wbv = s_bv[0];
+    int wbi = s_bi[0];
+#pragma unroll
+    for (int w = 1; w < 4; ++w)
+      if (s_bv[w] > wbv || (s_bv[w] == wbv && s_bi[w] < wbi)) {
+        wbv = s_bv[w];
+        wbi = s_bi[w];
+      }
+    __syncthreads();
+    any = wbv >= (T)0;
+    prev = wbv;
+    prev_i = wbi;
+  }
+  const double tau = any ? (double)prev : -1.0;
+  if (tid == 0) A.tau[(size_t)cand * A.nbands + band] = tau;
+  if (co) {
+    for (int c = tid; c < ld_o; c += blockDim.x) co[c] = colw[c] != (T)0 ? (double)cmx[c] : -1.0;
+    if (tid == 0) {
+      co[ld_o] = (double)s_n0max;
+      co[ld_o + 1] = tau;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_scan_colmax(ScanArgs A) {
+  for_each_item(A, kQueueWin, [&](int cand, int band) __attribute__((always_inline)) { scan_colmax_item<T>(A, cand, band); });
+}
+
 template <typename T, int KM>
 __device__ __forceinline__ void scan_worst_item(const ScanArgs &A, int cand, int band) {
   constexpr int TM = 64, TN = ScanCfg<T>::TN, NB = TN / 16, NE = 4 * NB;
@@ -824,6 +972,7 @@ __device__ __forceinline__ void scan_worst_item(const ScanArgs &A, int cand, int
   T *tv = fs + rchunk;                      // [4 waves][NE][64] values of a block under review
   __shared__ T s_bv[4];
   __shared__ int s_bk[4];
+  __shared__ T s_tau;
 
   const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, g = lane / 16, li = lane % 16;
   const int e0 = A.off[cand];
@@ -845,14 +994,17 @@ __device__ __forceinline__ void scan_worst_item(const ScanArgs &A, int cand, int
     bool nf = false;
     for (int c = tid; c < ld_o; c += blockDim.x) {
       const T y = ycol(Fv, A, cand, c, nf);
-      const bool g = guarded(A, cand, c);
-      ys[c] = g ? (T)0 : y;
+      const bool gd = guarded(A, cand, c);
+      ys[c] = gd ? (T)0 : y;
       const bool valid =
-          c < A.n_ctg && !g && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
+          c < A.n_ctg && !gd && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
       colw[c] = valid ? (T)1 : (T)0;
     }
     const int r0 = band * A.band_rows, r1 = min(r0 + A.band_rows, A.mon_pad);
     const int ntc = ld_o / TN;
+    // tau (from k_scan_colmax): the top_k-th largest of the band's column maxima and
+    // N-0 maximum, a lower bound of the band's top_k-th case
+    if (tid == 0) s_tau = (T)A.tau[(size_t)cand * A.nbands + band];
     for (int rc0 = r0; rc0 < r1; rc0 += rchunk) {
       const int rows = min(rchunk, r1 - rc0);
       __syncthreads();
@@ -860,7 +1012,8 @@ __device__ __forceinline__ void scan_worst_item(const ScanArgs &A, int cand, int
         const int row = rc0 + rr;
         const T fv = ftilde(Fv, A.inv_r, row, A.n_mon, nf);
         fs[fs_pos(fs, rr)] = fv;
-        if (row < A.n_mon && better(tabs(fv), row, lv[KM - 1], lk[KM - 1]))
+        if (row < A.n_mon && tabs(fv) >= s_tau &&
+            better(tabs(fv), row, lv[KM - 1], lk[KM - 1]))
           list_insert(lv, lk, tabs(fv), row);
       }
       __syncthreads();
@@ -892,13 +1045,15 @@ __device__ __forceinline__ void scan_worst_item(const ScanArgs &A, int cand, int
             }
         }
         // The best of the lanes' last entries bounds the wave's top_k-th case
-        // from below: a value under it cannot enter the result.  A 16-row block
-        // whose lane maximum reaches both bounds is reviewed element by element
-        // through the wave's LDS slot (element i of a lane at i * 64 + lane), so
-        // that one copy of the insertion code serves all its elements.
+        // from below, and so does tau: a value under either cannot enter the
+        // result.  A 16-row block whose lane maximum reaches both bounds is
+        // reviewed element by element through the wave's LDS slot (element i of a
+        // lane at i * 64 + lane), so that one copy of the insertion code serves
+        // all its elements.
         T wt = lv[KM - 1];
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) wt = tmax(wt, __shfl_xor(wt, o));
+        wt = tmax(wt, s_tau);
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
           if (!__any(ma[a] >= lv[KM - 1] && ma[a] >= wt)) continue;
@@ -1784,6 +1939,7 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   a.rchunk = 0;
   a.band_rows = 0;
   a.nbands = 1;
+  a.cmx_out = nullptr;
   set_multi(a, p, bt);
   if (sizeof(T) == 4 && bt->tune.guard_tol >= 0.0) {
     // the error guard of the FP32 scan flags its columns first
@@ -1867,7 +2023,8 @@ inline int worst_band_rows(const dcflow_plan *p) {
 
 template <typename T>
 hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_score *scores,
-                     int top_k, void *ws, dcflow_case *out, hipStream_t s) {
+                     int top_k, void *ws, dcflow_case *out, hipStream_t s,
+                     double *cmx_out = nullptr) {
   dcflow_plan *p = bt->plan;
   constexpr int NB = ScanCfg<T>::TN / 16;
   ScanArgs a;
@@ -1912,6 +2069,7 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   a.scores = scores;
   a.top_k = top_k;
   a.wpart = static_cast<WEntry *>(ws);
+  a.cmx_out = cmx_out;
   set_multi(a, p, bt);
   const size_t fixed = sizeof(T) * (2 * (size_t)p->ld_o + 4 * (size_t)(4 * NB) * kWave);
   int band = worst_band_rows(p);
@@ -1931,6 +2089,14 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   const size_t lds = fixed + sizeof(T) * (size_t)rc;
   if (lds > kLdsBudget) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((size_t)a.n_cand * a.nbands));
+  // the thresholds first (tau after the band lists in the workspace, or in front of
+  // the case maxima of the two-level pass)
+  a.tau = cmx_out ? cmx_out + (size_t)bt->n_cand * (p->ld_o + 2)
+                  : reinterpret_cast<double *>(static_cast<char *>(ws) +
+                                               worst_list_bytes(bt->n_cand, a.nbt, top_k));
+  k_scan_colmax<T><<<grid, dim3(256), lds + sizeof(T) * (size_t)p->ld_o, s>>>(a);
+  DCF_CHECK_LAUNCH();
+  if (cmx_out) return hipSuccess;  // the case maxima only
   if (top_k <= 8)
     k_scan_worst<T, 8, 1><<<grid, dim3(256), lds, s>>>(a);
   else
@@ -1956,6 +2122,10 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
 
 }  // namespace
 
+size_t worst_list_bytes(int n_cand, int nbt, int top_k) {
+  return ((size_t)n_cand * nbt * top_k * sizeof(WEntry) + 255) / 256 * 256;
+}
+
 int worst_bands(const dcflow_plan *p) {
   const int band = worst_band_rows(p);
   return (p->mon_pad + band - 1) / band;
@@ -1968,6 +2138,20 @@ hipError_t launch_worst(dcflow_batch *bt, const void *flows, int nvar, int prec,
   if (prec == DCFLOW_FP64)
     return run_worst<double>(bt, static_cast<const double *>(flows), nvar, scores, top_k, ws, out, s);
   return run_worst<float>(bt, static_cast<const float *>(flows), nvar, scores, top_k, ws, out, s);
+}
+
+bool case_maxima_supported(const dcflow_plan *p) { return worst_bands(p) == 1; }
+
+hipError_t launch_case_maxima(dcflow_batch *bt, const void *flows, int nvar, int prec,
+                              const dcflow_score *scores, int top_k, double *cmx_out,
+                              hipStream_t s) {
+  if (bt->n_cand == 0) return hipSuccess;
+  if (!case_maxima_supported(bt->plan)) return hipErrorInvalidValue;
+  if (prec == DCFLOW_FP64)
+    return run_worst<double>(bt, static_cast<const double *>(flows), nvar, scores, top_k,
+                             nullptr, nullptr, s, cmx_out);
+  return run_worst<float>(bt, static_cast<const float *>(flows), nvar, scores, top_k, nullptr,
+                          nullptr, s, cmx_out);
 }
 
 hipError_t launch_score(dcflow_batch *bt, const void *flows, int nvar, int prec, dcflow_score *out,
