@@ -81,27 +81,37 @@ struct PcArgs {
   PcEntry *ws;  // [n_cand][nslots][per_case]
   const uint32_t *flag;  // [n_cand][ld_o / 32] columns the FP32 scan's error guard
                          // computes in FP64 (null: none)
-  const double *cmx;     // [n_cand][ld_o + 2] the winner's column maxima, N-0 maximum and
-                         // their top_k-th largest (tau), or null: no pruning
-  double prune_margin;   // absolute margin of the pruning test (rating units): the tiles
-                         // and this kernel round an entry differently by at most this
+  const double *cmx;     // [n_cand][ld_o + 2] the winner's column maxima (from the tiles;
+                         // -1 for unscored columns), N-0 maximum and their top_k-th
+                         // largest (tau), or null: no pruning
+  const double *lsdmax;  // [ld_o] max |Lsd| of each column over the monitored rows
+  const float *umax;     // [n_elem] max |U / r| of each element over the monitored rows
+  int32_t *sel;          // [n_cand][n_ctg + 2] with cmx: the number of surviving slots,
+                         // then the slots (k_pc_sel writes, k_pc_fin reads)
 };
 
-// A case whose maximum (from the tiled sweep) is under tau, the top_k-th largest of
-// the case maxima, cannot place an entry in the final list: top_k other cases reach
-// tau.  The margin covers the difference between the tiles' rounding and this
-// kernel's (twice the FP32 error bound the guard enforces); guarded columns and
-// multi-outage cases are never pruned.
-__device__ __forceinline__ bool pc_pruned(const PcArgs &A, int cand, int slot) {
-  if (!A.cmx || slot > A.n_ctg) return false;
-  const double *o = A.cmx + (size_t)cand * (A.ld_o + 2);
-  const double tau = o[A.ld_o + 1];
-  if (tau < 0.0) return false;
-  const double v = slot == 0 ? o[A.ld_o] : o[slot - 1];
-  if (slot > 0 && A.flag &&
-      ((A.flag[(size_t)cand * (A.ld_o / 32) + (slot - 1) / 32] >> ((slot - 1) % 32)) & 1u))
-    return false;
-  return v + A.prune_margin < tau - A.prune_margin;
+// Largest difference between a case maximum of the tiles (k_scan_colmax: L~ on the
+// matrix cores) and the same maximum here (L~ by k FMAs), for contingency column c
+// of a candidate with k elements from e0.  Both sides start from the same rounded
+// seed, fragments and y and end with one fused multiply-add, so they differ by the
+// two ways of accumulating k products: at most (2k + 2) u S |y| with
+// S = max|Lsd[:, c]| + sum_e max|U_e / r| |W_ec| (a bound on |L~| down the column),
+// plus the final roundings of both loads (2 u each, on at most cm + that); u is the
+// unit roundoff of T.  The bound is doubled for the roundings of its own terms.
+template <typename T>
+__device__ __forceinline__ double pc_margin(const PcArgs &A, int cand, int c, int e0, int k,
+                                            double cm) {
+  const double u = sizeof(T) == 4 ? 0x1p-24 : 0x1p-53;
+  const double inv = A.invden[(size_t)cand * A.ld_o + c];
+  int vstar = A.scores[cand].best_variant;
+  const T *Fv = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vstar) * A.ld_f;
+  const double y = (double)(T)(c < A.n_out ? (double)Fv[A.out_pos[c]] * inv
+                                           : A.gen_y[c - A.n_out] * inv);
+  double S = A.lsdmax[c];
+  for (int e = 0; e < k; ++e)
+    S += (double)A.umax[e0 + e] * fabs(A.W[(size_t)(e0 + e) * A.ld_o + c]);
+  const double d = (2 * k + 2) * u * S * fabs(y);
+  return 2.0 * (d + 2.0 * u * (cm + d + cm));
 }
 
 template <typename T>
@@ -162,7 +172,7 @@ __global__ void __launch_bounds__(256) k_pc_cols(PcArgs A) {
   }
   int vstar = 0;
   const int c = slot - 1;
-  bool live = !pc_skip(A, cand, vstar) && !pc_pruned(A, cand, slot);
+  bool live = !pc_skip(A, cand, vstar);
   if (live && c >= 0)
     live = !((A.isl[(size_t)cand * (A.ld_o / 32) + c / 32] >> (c % 32)) & 1u);
   const bool guard = live && c >= 0 && A.flag != nullptr &&
@@ -218,23 +228,29 @@ __global__ void __launch_bounds__(256) k_pc_cols(PcArgs A) {
   pc_store(A, cand, slot, lv, lk);
 }
 
-// Level 1 after pruning (one row band): the cases that survive pc_pruned, one wave
-// per case and the rows spread over its lanes.  The block first collects its
-// candidate's surviving slots (N-0 and contingency columns) in LDS; each lane keeps
-// a sorted list of its rows' largest loads, and the wave's list is taken one entry
-// per round from the lanes' heads.  The arithmetic is that of k_pc_cols (guarded
-// columns in FP64), so the lists are the same; pruned slots are not written (the
-// merge skips them).
+// Level 1 after pruning (one row band), one wave per surviving case and the rows
+// spread over its lanes.  A case whose maximum (from the tiles, plus pc_margin) is
+// under tau (minus the largest margin among the columns that set it) cannot place
+// an entry in the final list: top_k other cases reach tau here too.  The block
+// collects its candidate's surviving slots (N-0 and contingency columns; guarded
+// columns always survive) in LDS and in sel; each lane keeps a sorted list of its
+// rows' largest loads, and the wave's list is taken one entry per round from the
+// lanes' heads.  The arithmetic is that of k_pc_cols (guarded columns in FP64), so
+// the lists are the same; pruned slots are not written (the merge reads sel).
 template <typename T, int KM, bool STAGE>
 __global__ void __launch_bounds__(256) k_pc_sel(PcArgs A) {
   // [n_ctg + 1] surviving slots; with STAGE then the candidate's F~ and U / r of its
   // k elements on the monitored rows ([1 + k][mon_pad] of T), read by every case
   extern __shared__ __attribute__((aligned(16))) int s_sel[];
   __shared__ int s_n;
+  __shared__ unsigned long long s_dtau;  // bit pattern of a non-negative double
   const int cand = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
   int vstar = 0;
   if (pc_skip(A, cand, vstar)) return;
-  if (tid == 0) s_n = 0;
+  if (tid == 0) {
+    s_n = 0;
+    s_dtau = 0ull;
+  }
   T *s_f = reinterpret_cast<T *>(s_sel + ((A.n_ctg + 1 + 3) / 4) * 4);
   T *s_ur = s_f + A.mon_pad;
   const int e0s = A.off[cand], ks = A.off[cand + 1] - e0s;
@@ -245,15 +261,35 @@ __global__ void __launch_bounds__(256) k_pc_sel(PcArgs A) {
       for (int e = 0; e < ks; ++e) s_ur[(size_t)e * A.mon_pad + row] = PcOps<T>::ur(A, e0s + e, row);
     }
   }
+  const double *o = A.cmx + (size_t)cand * (A.ld_o + 2);
+  const double tau = o[A.ld_o + 1];  // -1: fewer than top_k values, nothing pruned
+  if (tau >= 0.0)
+    for (int c = tid; c < A.n_ctg; c += blockDim.x)
+      if (o[c] >= tau)
+        atomicMax(&s_dtau, (unsigned long long)__double_as_longlong(
+                               pc_margin<T>(A, cand, c, e0s, ks, o[c])));
   __syncthreads();
+  const double lim = tau - __longlong_as_double((long long)s_dtau);
   for (int slot = tid; slot <= A.n_ctg; slot += blockDim.x) {
-    bool keep = !pc_pruned(A, cand, slot);
-    if (keep && slot > 0)
-      keep = !((A.isl[(size_t)cand * (A.ld_o / 32) + (slot - 1) / 32] >> ((slot - 1) % 32)) & 1u);
+    const int c = slot - 1;
+    bool keep = true;
+    if (c >= 0 && ((A.isl[(size_t)cand * (A.ld_o / 32) + c / 32] >> (c % 32)) & 1u))
+      keep = false;  // islanding column: not scored
+    else if (tau < 0.0)
+      keep = true;
+    else if (c < 0)
+      keep = o[A.ld_o] >= lim;  // N-0: both sides compute F~ alike
+    else if (A.flag && ((A.flag[(size_t)cand * (A.ld_o / 32) + c / 32] >> (c % 32)) & 1u))
+      keep = true;  // guarded: not in the tiles' maxima
+    else
+      keep = o[c] >= 0.0 && o[c] + pc_margin<T>(A, cand, c, e0s, ks, o[c]) >= lim;
     if (keep) s_sel[atomicAdd(&s_n, 1)] = slot;
   }
   __syncthreads();
   const int n_sel = s_n;
+  int32_t *sl = A.sel + (size_t)cand * (A.n_ctg + 2);
+  for (int q = tid; q < n_sel; q += blockDim.x) sl[1 + q] = s_sel[q];
+  if (tid == 0) sl[0] = n_sel;
   const T *Fv = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vstar) * A.ld_f;
   const int e0 = A.off[cand], k = A.off[cand + 1] - e0;
   for (int q = wv; q < n_sel; q += 4) {
@@ -419,12 +455,14 @@ __global__ void __launch_bounds__(256) k_pc_fin(PcArgs A, dcflow_case *out) {
   }
   const PcEntry *base = A.ws + (size_t)cand * A.nslots * A.per_case;
   int vstar = 0;
-  const bool skip = A.cmx != nullptr && pc_skip(A, cand, vstar);  // (lists not written)
-  for (int s = tid; s < A.nslots && !skip; s += blockDim.x) {
-    if (pc_pruned(A, cand, s)) continue;
-    if (A.cmx != nullptr && s > 0 && s <= A.n_ctg &&
-        ((A.isl[(size_t)cand * (A.ld_o / 32) + (s - 1) / 32] >> ((s - 1) % 32)) & 1u))
-      continue;  // islanding columns: not written by k_pc_sel
+  // after pruning: the surviving slots that k_pc_sel lists, then the multi-outage
+  // slots (a skipped candidate has no lists); else every slot
+  const int32_t *sl = A.cmx ? A.sel + (size_t)cand * (A.n_ctg + 2) : nullptr;
+  const bool skip = A.cmx != nullptr && pc_skip(A, cand, vstar);
+  const int n_live = sl && !skip ? sl[0] : 0;
+  const int n_iter = !sl ? A.nslots : (skip ? 0 : n_live + A.n_multi);
+  for (int i = tid; i < n_iter; i += blockDim.x) {
+    const int s = !sl ? i : (i < n_live ? sl[1 + i] : 1 + A.n_ctg + (i - n_live));
     for (int j = 0; j < A.per_case; ++j) {
       const PcEntry e = base[(size_t)s * A.per_case + j];
       if (e.k == kEmptyKey) break;  // lists are sorted, empties last
@@ -528,7 +566,9 @@ hipError_t run_pc(dcflow_batch *bt, const T *flows, int nvar, const dcflow_score
   a.ws = static_cast<PcEntry *>(ws);
   a.flag = sizeof(T) == 4 && bt->guard_valid ? bt->d_flag : nullptr;
   a.cmx = nullptr;
-  a.prune_margin = sizeof(T) == 4 ? 2e-4 : 1e-9;
+  a.lsdmax = p->d_lsdmax;
+  a.umax = bt->d_umax;
+  a.sel = nullptr;
   if (case_maxima_supported(p)) {
     // the case maxima of the winners first (after the per-case lists in the workspace)
     double *cmx = reinterpret_cast<double *>(
@@ -538,6 +578,7 @@ hipError_t run_pc(dcflow_batch *bt, const T *flows, int nvar, const dcflow_score
                                             scores, top_k, cmx, s);
     if (e != hipSuccess) return e;
     a.cmx = cmx;
+    a.sel = reinterpret_cast<int32_t *>(cmx + (size_t)bt->n_cand * (p->ld_o + 3));
   }
   const unsigned nc = (unsigned)bt->n_cand;
   if (a.cmx) {
@@ -588,8 +629,12 @@ size_t pc_list_bytes(int n_cand, int nslots, int per_case) {
 
 size_t per_case_workspace(const dcflow_batch *bt, int per_case) {
   const dcflow_plan *p = bt->plan;
+  // the lists; with one row band then the case maxima, tau and the surviving slots
   return pc_list_bytes(bt->n_cand, per_case_slots(p), per_case) +
-         (case_maxima_supported(p) ? (size_t)bt->n_cand * (p->ld_o + 3) * sizeof(double) : 0);
+         (case_maxima_supported(p)
+              ? (size_t)bt->n_cand * ((p->ld_o + 3) * sizeof(double) +
+                                      (size_t)(p->n_out + p->n_gen + 2) * sizeof(int32_t))
+              : 0);
 }
 
 hipError_t launch_worst_per_case(dcflow_batch *bt, const void *flows, int nvar, int prec,

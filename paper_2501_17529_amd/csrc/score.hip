@@ -138,6 +138,8 @@ struct ScanArgs {
                        // (-1 for unscored columns), the N-0 maximum and tau ([ld_o + 2]);
                        // one band must cover every monitored row
   double *tau;         // [n_cand][nbands] lower bounds of the bands' top_k-th case
+  uint32_t *hot;       // [n_cand][nbands][ld_o / 32] scored columns whose band maximum
+                       // reaches tau (null: not written / every tile reviewed)
   // multi-outage N-1 cases (scanned apart, in row chunks of kMultiRows)
   int n_multi;
   const int32_t *moff, *mcol;   // case q: sub-columns moff[q] .. moff[q+1]-1
@@ -387,8 +389,7 @@ __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int b
   T *ys = reinterpret_cast<T *>(smem_raw);  // [ld_o][VS]
   T *fs = ys + (size_t)VS * ld_o;           // [rchunk][VS]
   __shared__ double s_red[4][VC];
-  __shared__ T s_n0[VC];
-  __shared__ int s_nf[VC];
+  __shared__ int s_nfm;  // bit vi: a non-finite flow of variant vi was read
 
   const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, g = lane / 16, li = lane % 16;
   const int e0 = A.off[cand];
@@ -401,26 +402,40 @@ __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int b
     if (tid < nv && band == 0) global_max_nonneg(vm + tid, __builtin_inf());
     return;
   }
-  if (tid < VC) {
-    s_nf[tid] = 0;
-    s_n0[tid] = (T)0;
-  }
+  if (tid == 0) s_nfm = 0;
   const T *F = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vbeg) * A.ld_f;
   const int r0 = band * A.band_rows, r1 = min(r0 + A.band_rows, A.mon_pad);
   __syncthreads();
 
   // y for every contingency column and variant of the launch (0 for the variants
-  // past nv); a non-finite flow marks its variant in s_nf at once (rare, so not
-  // kept in registers)
-  for (int vi = 0; vi < VC; ++vi) {
-    bool nf = false;
-    for (int c = tid; c < ld_o; c += blockDim.x) {
-      const T y = vi < nv ? ycol(F + (size_t)vi * A.ld_f, A, cand, c, nf) : (T)0;
-      ys[(size_t)c * VS + vi] = guarded(A, cand, c) ? (T)0 : y;
+  // past nv), one thread per column with its VC flow reads issued together; the
+  // expression is that of ycol
+  unsigned nfm = 0;
+  for (int c = tid; c < ld_o; c += blockDim.x) {
+    T yv[VC];
+    if (c >= A.n_out) {
+      const T gy = c < A.n_ctg ? (T)(A.gen_y[c - A.n_out] * A.invden[(size_t)cand * ld_o + c])
+                               : (T)0;
+#pragma unroll
+      for (int vi = 0; vi < VC; ++vi) yv[vi] = vi < nv ? gy : (T)0;
+    } else {
+      const double inv = A.invden[(size_t)cand * ld_o + c];
+      const T *Fc = F + A.out_pos[c];
+      T fv[VC];
+#pragma unroll
+      for (int vi = 0; vi < VC; ++vi) fv[vi] = vi < nv ? Fc[(size_t)vi * A.ld_f] : (T)0;
+#pragma unroll
+      for (int vi = 0; vi < VC; ++vi) {
+        if (!finite_bits((double)fv[vi])) nfm |= 1u << vi;
+        yv[vi] = (T)((double)fv[vi] * inv);
+      }
     }
-    if (nf) s_nf[vi] = 1;
+    const bool gd = guarded(A, cand, c);
+#pragma unroll
+    for (int vi = 0; vi < VC; ++vi) ys[(size_t)c * VS + vi] = gd ? (T)0 : yv[vi];
   }
 
+  // running maxima of |p| per variant; the N-0 loads enter them while F~ is staged
   T mx[VC];
 #pragma unroll
   for (int i = 0; i < VC; ++i) mx[i] = (T)0;
@@ -428,19 +443,25 @@ __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int b
   for (int rc0 = r0; rc0 < r1; rc0 += rchunk) {
     const int rows = min(rchunk, r1 - rc0);
     __syncthreads();
-    // F~ of the chunk's rows; the N-0 loads enter the maxima here (every thread
-    // takes a share of the variant x row pairs; rows is a multiple of 64, so the 64
-    // pairs of one wave belong to one variant: their N-0 maximum is reduced across
-    // the wave, then kept in LDS by one integer atomic on the non-negative bit pattern)
-    for (int i0 = tid - lane; i0 < nv * rows; i0 += blockDim.x) {
-      const int i = i0 + lane;
-      const int vi = i0 / rows, rr = i - vi * rows;
-      bool nf = false;
-      const T fv = ftilde(F + (size_t)vi * A.ld_f, A.inv_r, rc0 + rr, A.n_mon, nf);
-      fs[(size_t)fs_pos(fs, rr) * VS + vi] = fv;
-      const T m = wave_max(tabs(fv));
-      if (lane == 0) lds_max_nonneg(&s_n0[vi], m);
-      if (nf) s_nf[vi] = 1;
+    // F~ of the chunk's rows (the expression of ftilde), one thread per row with its
+    // VC flow reads issued together; the N-0 loads enter the running maxima.  The
+    // variants past nv get zeros: the FP64 sweep below runs all VC of them without
+    // a branch, so that the compiler can interleave their loads and arithmetic.
+    for (int rr = tid; rr < rows; rr += blockDim.x) {
+      const int row = rc0 + rr;
+      const bool on = row < A.n_mon;
+      const double ir = on ? A.inv_r[row] : 0.0;
+      T fv[VC];
+#pragma unroll
+      for (int vi = 0; vi < VC; ++vi) fv[vi] = (on && vi < nv) ? F[(size_t)vi * A.ld_f + row] : (T)0;
+      T *dst = fs + (size_t)fs_pos(fs, rr) * VS;
+#pragma unroll
+      for (int vi = 0; vi < VC; ++vi) {
+        if (!finite_bits((double)fv[vi])) nfm |= 1u << vi;
+        const T f = (T)((double)fv[vi] * ir);
+        dst[vi] = f;
+        mx[vi] = tmax(mx[vi], tabs(f));
+      }
     }
     __syncthreads();
 
@@ -454,7 +475,9 @@ __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int b
       const T *ysb = ys + (size_t)(colbase + li) * VS;
 #pragma unroll
       for (int vi = 0; vi < VC; ++vi) {
-        if (vi >= nv) continue;
+        // FP32 keeps a branch per variant: without it the hoisted LDS reads of the
+        // 16 variants overflow its 128-register budget (four waves per SIMD)
+        if (sizeof(T) == 4 && vi >= nv) continue;
         T fr[4][4], yc[NB];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -487,11 +510,11 @@ __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int b
     const T m = wave_max(mx[i]);
     if (lane == 0) s_red[wv][i] = (double)m;
   }
+  if (nfm) atomicOr(&s_nfm, (int)nfm);
   __syncthreads();
   if (tid < nv) {
     double m = fmax(fmax(s_red[0][tid], s_red[1][tid]), fmax(s_red[2][tid], s_red[3][tid]));
-    m = fmax(m, (double)s_n0[tid]);
-    if (s_nf[tid]) m = __builtin_inf();
+    if ((s_nfm >> tid) & 1) m = __builtin_inf();
     global_max_nonneg(vm + tid, m);
   }
 }
@@ -843,6 +866,9 @@ __device__ __forceinline__ void scan_colmax_item(const ScanArgs &A, int cand, in
   double *co = A.cmx_out ? A.cmx_out + (size_t)cand * (ld_o + 2) : nullptr;
   if (skip) {
     if (tid == 0) A.tau[(size_t)cand * A.nbands + band] = -1.0;
+    if (A.hot)
+      for (int w = tid; w < ld_o / 32; w += blockDim.x)
+        A.hot[((size_t)cand * A.nbands + band) * (ld_o / 32) + w] = 0u;
     if (co)
       for (int c = tid; c < ld_o + 2; c += blockDim.x) co[c] = -1.0;
     return;
@@ -946,6 +972,19 @@ __device__ __forceinline__ void scan_colmax_item(const ScanArgs &A, int cand, in
   }
   const double tau = any ? (double)prev : -1.0;
   if (tid == 0) A.tau[(size_t)cand * A.nbands + band] = tau;
+  if (A.hot) {
+    // the columns that can place an entry in the band's list (all scored ones
+    // when there are fewer than top_k values)
+    uint32_t *hw = A.hot + ((size_t)cand * A.nbands + band) * (ld_o / 32);
+    for (int w = tid; w < ld_o / 32; w += blockDim.x) {
+      uint32_t m = 0;
+      for (int j = 0; j < 32; ++j) {
+        const int c = w * 32 + j;
+        if (colw[c] != (T)0 && (!any || cmx[c] >= prev)) m |= 1u << j;
+      }
+      hw[w] = m;
+    }
+  }
   if (co) {
     for (int c = tid; c < ld_o; c += blockDim.x) co[c] = colw[c] != (T)0 ? (double)cmx[c] : -1.0;
     if (tid == 0) {
@@ -1005,6 +1044,7 @@ __device__ __forceinline__ void scan_worst_item(const ScanArgs &A, int cand, int
     // tau (from k_scan_colmax): the top_k-th largest of the band's column maxima and
     // N-0 maximum, a lower bound of the band's top_k-th case
     if (tid == 0) s_tau = (T)A.tau[(size_t)cand * A.nbands + band];
+    const uint32_t *hw = A.hot ? A.hot + ((size_t)cand * A.nbands + band) * (ld_o / 32) : nullptr;
     for (int rc0 = r0; rc0 < r1; rc0 += rchunk) {
       const int rows = min(rchunk, r1 - rc0);
       __syncthreads();
@@ -1021,6 +1061,14 @@ __device__ __forceinline__ void scan_worst_item(const ScanArgs &A, int cand, int
       for (int tile = wv; tile < nt; tile += 4) {
         const int tr = tile / ntc, tc = tile - tr * ntc;
         const int rowbase = rc0 + tr * TM, colbase = tc * TN;
+        // a tile without a column whose band maximum reaches tau holds no entry of
+        // the list (its values are those k_scan_colmax maximised, bit for bit)
+        if (hw) {
+          uint32_t h = 0;
+#pragma unroll
+          for (int q = 0; q < TN / 32; ++q) h |= hw[colbase / 32 + q];
+          if (h == 0) continue;
+        }
         T L[4][NB][4];
         build_tile(L, A, e0, k, rowbase, colbase, g, li, lane);
         const T *fsv = fs + (rowbase - rc0) + 4 * g;
@@ -2094,6 +2142,9 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   a.tau = cmx_out ? cmx_out + (size_t)bt->n_cand * (p->ld_o + 2)
                   : reinterpret_cast<double *>(static_cast<char *>(ws) +
                                                worst_list_bytes(bt->n_cand, a.nbt, top_k));
+  // the hot-column masks after the thresholds (not needed for the case maxima)
+  a.hot = cmx_out ? nullptr
+                  : reinterpret_cast<uint32_t *>(a.tau + (size_t)bt->n_cand * a.nbands);
   k_scan_colmax<T><<<grid, dim3(256), lds + sizeof(T) * (size_t)p->ld_o, s>>>(a);
   DCF_CHECK_LAUNCH();
   if (cmx_out) return hipSuccess;  // the case maxima only
