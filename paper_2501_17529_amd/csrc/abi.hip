@@ -823,11 +823,10 @@ int dcflow_n1_score(dcflow_batch *b, const void *dev_flows, int32_t n_var, dcflo
 int dcflow_n1_worst_workspace_bytes(const dcflow_batch *b, int32_t top_k, size_t *bytes) {
   if (!b || !bytes || top_k < 1 || top_k > DCFLOW_WORST_MAX) return DCFLOW_E_ARG;
   // one 16-byte entry (load, key) per list place, band and candidate (the bands, the
-  // multi-outage chunks and the guard's list), then one threshold per band, then one
-  // bit per column and band (the columns whose band maximum reaches the threshold)
+  // multi-outage chunks and the guard's list), then per band a threshold and the
+  // band's hot columns
   const int nb = worst_bands(b->plan);
-  *bytes = worst_list_bytes(b->n_cand, nb + b->nmb + 1, top_k) + (size_t)b->n_cand * nb * 8 +
-           (size_t)b->n_cand * nb * (b->plan->ld_o / 32) * 4;
+  *bytes = worst_list_bytes(b->n_cand, nb + b->nmb + 1, top_k) + worst_aux_bytes(b->n_cand, nb);
   return DCFLOW_OK;
 }
 

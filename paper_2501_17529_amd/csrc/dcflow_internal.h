@@ -167,19 +167,24 @@ hipError_t launch_injections(dcflow_batch *b, const double *inj, int nvar, int s
                              int prec, void *flows, int c0, int c1, hipStream_t s);
 // score (a5)
 // worst-case lists (agg_i) of the winners; worst_bands = row bands of that pass, and
-// its workspace: the band lists (worst_list_bytes), then one threshold per band
+// its workspace: the band lists (worst_list_bytes), then per band a threshold and a
+// hot-column list (worst_aux_bytes)
 int worst_bands(const dcflow_plan *p);
 size_t worst_list_bytes(int n_cand, int nbt, int top_k);
+size_t worst_aux_bytes(int n_cand, int nbands);
+constexpr int kHotLd = 1 + DCFLOW_WORST_MAX;  // a band's hot columns: number, columns
 hipError_t launch_worst(dcflow_batch *b, const void *flows, int nvar, int prec,
                         const dcflow_score *scores, int top_k, void *ws, dcflow_case *out,
                         hipStream_t s);
 // The winners' maxima of every contingency column, the N-0 maximum and the top_k-th
 // largest of them (the first sweep of the worst-case pass), per candidate in cmx
-// [n_cand][ld_o + 2]; only when one row band covers the monitored rows
+// [n_cand][ld_o + 2], followed by worst_aux_bytes(n_cand, 1); with pcl, then the
+// per-case lists of the hot columns ([n_cand][pc_nslots][per_case] 16-byte entries,
+// slot 1 + c).  Only when one row band covers the monitored rows.
 bool case_maxima_supported(const dcflow_plan *p);
 hipError_t launch_case_maxima(dcflow_batch *b, const void *flows, int nvar, int prec,
-                              const dcflow_score *scores, int top_k, double *cmx,
-                              hipStream_t s);
+                              const dcflow_score *scores, int top_k, double *cmx, void *pcl,
+                              int pc_nslots, int per_case, hipStream_t s);
 // candidates [c0, c1); a part of the batch runs without the persistent queue and in
 // candidate order
 hipError_t launch_score(dcflow_batch *b, const void *flows, int nvar, int prec,

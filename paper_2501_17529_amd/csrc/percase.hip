@@ -81,38 +81,14 @@ struct PcArgs {
   PcEntry *ws;  // [n_cand][nslots][per_case]
   const uint32_t *flag;  // [n_cand][ld_o / 32] columns the FP32 scan's error guard
                          // computes in FP64 (null: none)
-  const double *cmx;     // [n_cand][ld_o + 2] the winner's column maxima (from the tiles;
-                         // -1 for unscored columns), N-0 maximum and their top_k-th
-                         // largest (tau), or null: no pruning
-  const double *lsdmax;  // [ld_o] max |Lsd| of each column over the monitored rows
-  const float *umax;     // [n_elem] max |U / r| of each element over the monitored rows
-  int32_t *sel;          // [n_cand][n_ctg + 2] with cmx: the number of surviving slots,
-                         // then the slots (k_pc_sel writes, k_pc_fin reads)
+  const double *cmx;     // [n_cand][ld_o + 2] the winner's column maxima (from the tiles),
+                         // N-0 maximum and their top_k-th largest, or null: every slot
+                         // is listed by k_pc_cols
+  const int32_t *hotl;   // [n_cand][kHotLd] with cmx: the hot columns, whose lists
+                         // k_scan_hot writes
+  int32_t *sel;          // [n_cand][n_ctg + 2] with cmx: the number of slots that
+                         // k_pc_sel lists (N-0 and guarded columns), then the slots
 };
-
-// Largest difference between a case maximum of the tiles (k_scan_colmax: L~ on the
-// matrix cores) and the same maximum here (L~ by k FMAs), for contingency column c
-// of a candidate with k elements from e0.  Both sides start from the same rounded
-// seed, fragments and y and end with one fused multiply-add, so they differ by the
-// two ways of accumulating k products: at most (2k + 2) u S |y| with
-// S = max|Lsd[:, c]| + sum_e max|U_e / r| |W_ec| (a bound on |L~| down the column),
-// plus the final roundings of both loads (2 u each, on at most cm + that); u is the
-// unit roundoff of T.  The bound is doubled for the roundings of its own terms.
-template <typename T>
-__device__ __forceinline__ double pc_margin(const PcArgs &A, int cand, int c, int e0, int k,
-                                            double cm) {
-  const double u = sizeof(T) == 4 ? 0x1p-24 : 0x1p-53;
-  const double inv = A.invden[(size_t)cand * A.ld_o + c];
-  int vstar = A.scores[cand].best_variant;
-  const T *Fv = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vstar) * A.ld_f;
-  const double y = (double)(T)(c < A.n_out ? (double)Fv[A.out_pos[c]] * inv
-                                           : A.gen_y[c - A.n_out] * inv);
-  double S = A.lsdmax[c];
-  for (int e = 0; e < k; ++e)
-    S += (double)A.umax[e0 + e] * fabs(A.W[(size_t)(e0 + e) * A.ld_o + c]);
-  const double d = (2 * k + 2) * u * S * fabs(y);
-  return 2.0 * (d + 2.0 * u * (cm + d + cm));
-}
 
 template <typename T>
 struct PcOps;
@@ -228,61 +204,36 @@ __global__ void __launch_bounds__(256) k_pc_cols(PcArgs A) {
   pc_store(A, cand, slot, lv, lk);
 }
 
-// Level 1 after pruning (one row band), one wave per surviving case and the rows
-// spread over its lanes.  A case whose maximum (from the tiles, plus pc_margin) is
-// under tau (minus the largest margin among the columns that set it) cannot place
-// an entry in the final list: top_k other cases reach tau here too.  The block
-// collects its candidate's surviving slots (N-0 and contingency columns; guarded
-// columns always survive) in LDS and in sel; each lane keeps a sorted list of its
-// rows' largest loads, and the wave's list is taken one entry per round from the
-// lanes' heads.  The arithmetic is that of k_pc_cols (guarded columns in FP64), so
-// the lists are the same; pruned slots are not written (the merge reads sel).
+// Level 1 beside the hot columns (one row band): the N-0 case and the columns that
+// the FP32 scan's error guard computes in FP64, one wave per case and the rows
+// spread over its lanes.  Every other contingency column either is hot (its list
+// comes from k_scan_hot, on the tiles' arithmetic) or has all its entries after
+// top_k entries of other cases.  The block collects its slots in LDS and in sel;
+// each lane keeps a sorted list of its rows' largest loads, and the wave's list is
+// taken one entry per round from the lanes' heads.  The arithmetic is that of
+// k_pc_cols (guarded columns in FP64).
 template <typename T, int KM, bool STAGE>
 __global__ void __launch_bounds__(256) k_pc_sel(PcArgs A) {
-  // [n_ctg + 1] surviving slots; with STAGE then the candidate's F~ and U / r of its
-  // k elements on the monitored rows ([1 + k][mon_pad] of T), read by every case
+  // [n_ctg + 1] listed slots; with STAGE then the candidate's F~ on the monitored
+  // rows ([mon_pad] of T)
   extern __shared__ __attribute__((aligned(16))) int s_sel[];
   __shared__ int s_n;
-  __shared__ unsigned long long s_dtau;  // bit pattern of a non-negative double
   const int cand = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
   int vstar = 0;
   if (pc_skip(A, cand, vstar)) return;
-  if (tid == 0) {
-    s_n = 0;
-    s_dtau = 0ull;
-  }
+  if (tid == 0) s_n = 0;
   T *s_f = reinterpret_cast<T *>(s_sel + ((A.n_ctg + 1 + 3) / 4) * 4);
-  T *s_ur = s_f + A.mon_pad;
-  const int e0s = A.off[cand], ks = A.off[cand + 1] - e0s;
   if (STAGE) {
     const T *Fs = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vstar) * A.ld_f;
-    for (int row = tid; row < A.n_mon; row += blockDim.x) {
+    for (int row = tid; row < A.n_mon; row += blockDim.x)
       s_f[row] = (T)((double)Fs[row] * A.inv_r[row]);
-      for (int e = 0; e < ks; ++e) s_ur[(size_t)e * A.mon_pad + row] = PcOps<T>::ur(A, e0s + e, row);
-    }
   }
-  const double *o = A.cmx + (size_t)cand * (A.ld_o + 2);
-  const double tau = o[A.ld_o + 1];  // -1: fewer than top_k values, nothing pruned
-  if (tau >= 0.0)
-    for (int c = tid; c < A.n_ctg; c += blockDim.x)
-      if (o[c] >= tau)
-        atomicMax(&s_dtau, (unsigned long long)__double_as_longlong(
-                               pc_margin<T>(A, cand, c, e0s, ks, o[c])));
   __syncthreads();
-  const double lim = tau - __longlong_as_double((long long)s_dtau);
   for (int slot = tid; slot <= A.n_ctg; slot += blockDim.x) {
     const int c = slot - 1;
-    bool keep = true;
-    if (c >= 0 && ((A.isl[(size_t)cand * (A.ld_o / 32) + c / 32] >> (c % 32)) & 1u))
-      keep = false;  // islanding column: not scored
-    else if (tau < 0.0)
-      keep = true;
-    else if (c < 0)
-      keep = o[A.ld_o] >= lim;  // N-0: both sides compute F~ alike
-    else if (A.flag && ((A.flag[(size_t)cand * (A.ld_o / 32) + c / 32] >> (c % 32)) & 1u))
-      keep = true;  // guarded: not in the tiles' maxima
-    else
-      keep = o[c] >= 0.0 && o[c] + pc_margin<T>(A, cand, c, e0s, ks, o[c]) >= lim;
+    bool keep = c < 0;  // N-0
+    if (c >= 0 && A.flag && ((A.flag[(size_t)cand * (A.ld_o / 32) + c / 32] >> (c % 32)) & 1u))
+      keep = !((A.isl[(size_t)cand * (A.ld_o / 32) + c / 32] >> (c % 32)) & 1u);
     if (keep) s_sel[atomicAdd(&s_n, 1)] = slot;
   }
   __syncthreads();
@@ -304,45 +255,27 @@ __global__ void __launch_bounds__(256) k_pc_sel(PcArgs A) {
       lk[j] = kEmptyKey;
     }
     double y64 = 0.0, w64[kMaxRank];
-    T y = (T)0, w[kMaxRank];
 #pragma unroll
-    for (int e = 0; e < kMaxRank; ++e) {
-      w64[e] = 0.0;
-      w[e] = (T)0;
-    }
-    if (c >= 0) {
+    for (int e = 0; e < kMaxRank; ++e) w64[e] = 0.0;
+    if (guard) {
       const double inv = A.invden[(size_t)cand * A.ld_o + c];
       y64 = (c < A.n_out ? (double)Fv[A.out_pos[c]] : A.gen_y[c - A.n_out]) * inv;
-      y = (T)y64;
 #pragma unroll
       for (int e = 0; e < kMaxRank; ++e)
-        if (e < k) {
-          w64[e] = PcOps<double>::w(A, e0 + e, c);
-          w[e] = PcOps<T>::w(A, e0 + e, c);
-        }
+        if (e < k) w64[e] = PcOps<double>::w(A, e0 + e, c);
     }
     for (int row = lane; row < A.n_mon; row += kWave) {
       T a;
-      if (c < 0) {
+      if (!guard) {  // N-0
         const T f = STAGE ? s_f[row] : (T)((double)Fv[row] * A.inv_r[row]);
         a = f < (T)0 ? -f : f;
-      } else if (guard) {
+      } else {
         double l = A.lsdT[(size_t)c * A.mon_pad + row];
 #pragma unroll
         for (int e = 0; e < kMaxRank; ++e)
           if (e < k) l = pc_fma(PcOps<double>::ur(A, e0 + e, row), w64[e], l);
         const double p = pc_fma(l, y64, (double)Fv[row] * A.inv_r[row]);
         a = (T)(p < 0.0 ? -p : p);
-      } else {
-        const T f = STAGE ? s_f[row] : (T)((double)Fv[row] * A.inv_r[row]);
-        T l = (T)A.lsdT[(size_t)c * A.mon_pad + row];
-#pragma unroll
-        for (int e = 0; e < kMaxRank; ++e)
-          if (e < k)
-            l = pc_fma(STAGE ? s_ur[(size_t)e * A.mon_pad + row] : PcOps<T>::ur(A, e0 + e, row),
-                       w[e], l);
-        const T p = pc_fma(l, y, f);
-        a = p < (T)0 ? -p : p;
       }
       const int key = slot * A.n_mon + row;
       if (pc_better(a, key, lv[KM - 1], lk[KM - 1])) pc_insert(lv, lk, a, key);
@@ -455,14 +388,19 @@ __global__ void __launch_bounds__(256) k_pc_fin(PcArgs A, dcflow_case *out) {
   }
   const PcEntry *base = A.ws + (size_t)cand * A.nslots * A.per_case;
   int vstar = 0;
-  // after pruning: the surviving slots that k_pc_sel lists, then the multi-outage
-  // slots (a skipped candidate has no lists); else every slot
+  // with the case maxima: the slots that k_pc_sel lists, the hot columns, then the
+  // multi-outage slots (a skipped candidate has no lists); else every slot
   const int32_t *sl = A.cmx ? A.sel + (size_t)cand * (A.n_ctg + 2) : nullptr;
+  const int32_t *hl = A.cmx ? A.hotl + (size_t)cand * kHotLd : nullptr;
   const bool skip = A.cmx != nullptr && pc_skip(A, cand, vstar);
   const int n_live = sl && !skip ? sl[0] : 0;
-  const int n_iter = !sl ? A.nslots : (skip ? 0 : n_live + A.n_multi);
+  const int n_hot = hl && !skip ? hl[0] : 0;
+  const int n_iter = !sl ? A.nslots : (skip ? 0 : n_live + n_hot + A.n_multi);
   for (int i = tid; i < n_iter; i += blockDim.x) {
-    const int s = !sl ? i : (i < n_live ? sl[1 + i] : 1 + A.n_ctg + (i - n_live));
+    const int s = !sl ? i
+                      : (i < n_live ? sl[1 + i]
+                                    : (i < n_live + n_hot ? 1 + hl[1 + i - n_live]
+                                                          : 1 + A.n_ctg + (i - n_live - n_hot)));
     for (int j = 0; j < A.per_case; ++j) {
       const PcEntry e = base[(size_t)s * A.per_case + j];
       if (e.k == kEmptyKey) break;  // lists are sorted, empties last
@@ -566,24 +504,27 @@ hipError_t run_pc(dcflow_batch *bt, const T *flows, int nvar, const dcflow_score
   a.ws = static_cast<PcEntry *>(ws);
   a.flag = sizeof(T) == 4 && bt->guard_valid ? bt->d_flag : nullptr;
   a.cmx = nullptr;
-  a.lsdmax = p->d_lsdmax;
-  a.umax = bt->d_umax;
+  a.hotl = nullptr;
   a.sel = nullptr;
   if (case_maxima_supported(p)) {
-    // the case maxima of the winners first (after the per-case lists in the workspace)
+    // the case maxima of the winners and the hot columns' lists first (the maxima,
+    // tau, the hot-column list and the kept slots after the lists in the workspace)
     double *cmx = reinterpret_cast<double *>(
         static_cast<char *>(ws) + pc_list_bytes(bt->n_cand, a.nslots, per_case));
     const hipError_t e = launch_case_maxima(bt, flows, nvar, sizeof(T) == 4 ? DCFLOW_FP32
                                                                             : DCFLOW_FP64,
-                                            scores, top_k, cmx, s);
+                                            scores, top_k, cmx, a.ws, a.nslots, per_case, s);
     if (e != hipSuccess) return e;
     a.cmx = cmx;
-    a.sel = reinterpret_cast<int32_t *>(cmx + (size_t)bt->n_cand * (p->ld_o + 3));
+    double *tau = cmx + (size_t)bt->n_cand * (p->ld_o + 2);
+    a.hotl = reinterpret_cast<const int32_t *>(tau + bt->n_cand);
+    a.sel = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(tau) +
+                                        worst_aux_bytes(bt->n_cand, 1));
   }
   const unsigned nc = (unsigned)bt->n_cand;
   if (a.cmx) {
     const size_t sel = sizeof(int) * (size_t)((a.n_ctg + 1 + 3) / 4 * 4);
-    const size_t staged = sel + sizeof(T) * (size_t)(1 + bt->kmax) * p->mon_pad;
+    const size_t staged = sel + sizeof(T) * (size_t)p->mon_pad;
     if (staged <= 64 * 1024) {
       if (per_case <= 4)
         k_pc_sel<T, 4, true><<<dim3(nc), dim3(256), staged, s>>>(a);
@@ -629,11 +570,13 @@ size_t pc_list_bytes(int n_cand, int nslots, int per_case) {
 
 size_t per_case_workspace(const dcflow_batch *bt, int per_case) {
   const dcflow_plan *p = bt->plan;
-  // the lists; with one row band then the case maxima, tau and the surviving slots
+  // the lists; with one row band then the case maxima, tau and the hot columns,
+  // and the slots of k_pc_sel
   return pc_list_bytes(bt->n_cand, per_case_slots(p), per_case) +
          (case_maxima_supported(p)
-              ? (size_t)bt->n_cand * ((p->ld_o + 3) * sizeof(double) +
-                                      (size_t)(p->n_out + p->n_gen + 2) * sizeof(int32_t))
+              ? (size_t)bt->n_cand * (p->ld_o + 2) * sizeof(double) +
+                    worst_aux_bytes(bt->n_cand, 1) +
+                    (size_t)bt->n_cand * (p->n_out + p->n_gen + 2) * sizeof(int32_t)
               : 0);
 }
 

@@ -138,8 +138,11 @@ struct ScanArgs {
                        // (-1 for unscored columns), the N-0 maximum and tau ([ld_o + 2]);
                        // one band must cover every monitored row
   double *tau;         // [n_cand][nbands] lower bounds of the bands' top_k-th case
-  uint32_t *hot;       // [n_cand][nbands][ld_o / 32] scored columns whose band maximum
-                       // reaches tau (null: not written / every tile reviewed)
+  int32_t *hotl;       // [n_cand][nbands][kHotLd] the band's hot columns: their number,
+                       // then the columns (see scan_colmax_item)
+  WEntry *pcl;         // two-level lists: [n_cand][pc_nslots][per_case] per-case lists
+                       // (slot 1 + c for contingency column c), or null: one list
+  int pc_nslots, per_case;
   // multi-outage N-1 cases (scanned apart, in row chunks of kMultiRows)
   int n_multi;
   const int32_t *moff, *mcol;   // case q: sub-columns moff[q] .. moff[q+1]-1
@@ -313,6 +316,13 @@ __device__ __forceinline__ void tile_mfma_step(d4 (&c)[4][2], const double (&fa)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
       c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], c[a][b], 0, 0, 0);
+}
+// One k step of a single 16 x 16 block.
+__device__ __forceinline__ f4 mfma_step1(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ d4 mfma_step1(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 // L~ for the tile at (rowbase, colbase): the seed blocks, then per k step (one
 // for k <= 4, two for k <= 8; wave-uniform) its fragments and MFMAs.
@@ -841,8 +851,8 @@ __device__ __forceinline__ void list_insert(T (&lv)[KM], int (&lk)[KM], T v, int
 
 // Item (cand, band) of the winning variant: the band's column maxima over the
 // scored contingency columns and its N-0 maximum.  They are distinct elements, so
-// the top_k-th largest of them, tau, bounds the band's top_k-th case from below:
-// k_scan_worst reviews only blocks that reach it.  The tiles are built with the
+// the top_k-th largest of them, tau, bounds the band's top_k-th case from below,
+// and they name the band's hot columns (k_scan_hot).  The tiles are built with the
 // same code as there, so the values agree bit for bit.
 template <typename T>
 __device__ __forceinline__ void scan_colmax_item(const ScanArgs &A, int cand, int band) {
@@ -866,9 +876,7 @@ __device__ __forceinline__ void scan_colmax_item(const ScanArgs &A, int cand, in
   double *co = A.cmx_out ? A.cmx_out + (size_t)cand * (ld_o + 2) : nullptr;
   if (skip) {
     if (tid == 0) A.tau[(size_t)cand * A.nbands + band] = -1.0;
-    if (A.hot)
-      for (int w = tid; w < ld_o / 32; w += blockDim.x)
-        A.hot[((size_t)cand * A.nbands + band) * (ld_o / 32) + w] = 0u;
+    if (A.hotl && tid == 0) A.hotl[((size_t)cand * A.nbands + band) * kHotLd] = 0;
     if (co)
       for (int c = tid; c < ld_o + 2; c += blockDim.x) co[c] = -1.0;
     return;
@@ -972,18 +980,24 @@ __device__ __forceinline__ void scan_colmax_item(const ScanArgs &A, int cand, in
   }
   const double tau = any ? (double)prev : -1.0;
   if (tid == 0) A.tau[(size_t)cand * A.nbands + band] = tau;
-  if (A.hot) {
-    // the columns that can place an entry in the band's list (all scored ones
-    // when there are fewer than top_k values)
-    uint32_t *hw = A.hot + ((size_t)cand * A.nbands + band) * (ld_o / 32);
-    for (int w = tid; w < ld_o / 32; w += blockDim.x) {
-      uint32_t m = 0;
-      for (int j = 0; j < 32; ++j) {
-        const int c = w * 32 + j;
-        if (colw[c] != (T)0 && (!any || cmx[c] >= prev)) m |= 1u << j;
+  // The hot columns: the scored columns among the top_k of that order (all scored
+  // ones when there are fewer values).  Any other column's entries come after
+  // top_k distinct entries of the band (the chosen column maxima and N-0 maximum)
+  // in the order of the lists (load descending, key ascending; a column's keys
+  // grow with its index and the N-0 keys come first), in either kind of list: the
+  // band's top_k, or the top_k of the per-case lists.
+  if (A.hotl) {
+    __shared__ int s_nh;
+    int32_t *hl = A.hotl + ((size_t)cand * A.nbands + band) * kHotLd;
+    if (tid == 0) s_nh = 0;
+    __syncthreads();
+    for (int c = tid; c < ld_o; c += blockDim.x)
+      if (colw[c] != (T)0 && (!any || cmx[c] > prev || (cmx[c] == prev && c <= prev_i))) {
+        const int q = atomicAdd(&s_nh, 1);
+        if (q < DCFLOW_WORST_MAX) hl[1 + q] = c;
       }
-      hw[w] = m;
-    }
+    __syncthreads();
+    if (tid == 0) hl[0] = min(s_nh, DCFLOW_WORST_MAX);
   }
   if (co) {
     for (int c = tid; c < ld_o; c += blockDim.x) co[c] = colw[c] != (T)0 ? (double)cmx[c] : -1.0;
@@ -999,25 +1013,32 @@ __global__ void __launch_bounds__(256) k_scan_colmax(ScanArgs A) {
   for_each_item(A, kQueueWin, [&](int cand, int band) __attribute__((always_inline)) { scan_colmax_item<T>(A, cand, band); });
 }
 
-template <typename T, int KM>
-__device__ __forceinline__ void scan_worst_item(const ScanArgs &A, int cand, int band) {
-  constexpr int TM = 64, TN = ScanCfg<T>::TN, NB = TN / 16, NE = 4 * NB;
+// Item (cand, band) of the winning variant after k_scan_colmax: only the band's hot
+// columns (at most 16) can place an entry in the list, so they are gathered into
+// one 16-column block (lane column li = the li-th hot column; the padding lanes
+// repeat a hot column and are masked) and built on the matrix cores from the same
+// seed fragments, U / r and W values as the full tiles: every entry is bit for bit
+// the value k_scan_colmax maximised (each MFMA output depends on its own row,
+// column and accumulator only).  The N-0 rows enter while F~ is staged.
+//   One list (PC false): each lane keeps its KM best entries at or above tau; the
+//   band's top_k list is then taken from the lanes' heads, one entry per round.
+//   Two-level lists (PC true, one band): each lane keeps the KM best rows of its
+//   own column; the 16 lists of a column (4 row groups x 4 waves) are merged into
+//   its per-case list of per_case entries (slot 1 + c); the N-0 case is left to
+//   the per-case kernels.
+template <typename T, int KM, bool PC>
+__device__ __forceinline__ void scan_hot_item(const ScanArgs &A, int cand, int band) {
   constexpr int kEmpty = 0x7fffffff;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int ld_o = A.ld_o, rchunk = A.rchunk;
-  T *ys = reinterpret_cast<T *>(smem_raw);  // [ld_o]
-  T *colw = ys + ld_o;                      // [ld_o]
-  T *fs = colw + ld_o;                      // [rchunk]
-  T *tv = fs + rchunk;                      // [4 waves][NE][64] values of a block under review
-  __shared__ T s_bv[4];
-  __shared__ int s_bk[4];
-  __shared__ T s_tau;
+  T *fs = reinterpret_cast<T *>(smem_raw);  // [rchunk]
+  __shared__ T s_bv[4], s_y[16], s_tau;
+  __shared__ int s_bk[4], s_col[16], s_nh;
 
   const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, g = lane / 16, li = lane % 16;
   const int e0 = A.off[cand];
   const int k = A.off[cand + 1] - e0;
   const dcflow_score sc = A.scores[cand];
-  WEntry *dst = A.wpart + ((size_t)cand * A.nbt + band) * A.top_k;
   const bool skip = (sc.status & (DCFLOW_ST_DISCONNECTED | DCFLOW_ST_NONFINITE)) != 0 ||
                     sc.best_variant < 0 || sc.best_variant >= A.nvar;
   T lv[KM];
@@ -1027,105 +1048,135 @@ __device__ __forceinline__ void scan_worst_item(const ScanArgs &A, int cand, int
     lv[j] = (T)-1;
     lk[j] = kEmpty;
   }
-  if (!skip) {
-    const T *Fv = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + sc.best_variant) * A.ld_f;
-    T *tvw = tv + (size_t)wv * NE * kWave;
+  const int32_t *hl = A.hotl + ((size_t)cand * A.nbands + band) * kHotLd;
+  const T *Fv = skip ? nullptr
+                     : static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + sc.best_variant) * A.ld_f;
+  if (tid == 0) {
+    s_nh = skip ? 0 : hl[0];
+    s_tau = (T)A.tau[(size_t)cand * A.nbands + band];
+  }
+  __syncthreads();
+  const int nh = s_nh;
+  if (tid < 16) {
+    const int c = nh > 0 ? hl[1 + (tid < nh ? tid : 0)] : 0;
     bool nf = false;
-    for (int c = tid; c < ld_o; c += blockDim.x) {
-      const T y = ycol(Fv, A, cand, c, nf);
-      const bool gd = guarded(A, cand, c);
-      ys[c] = gd ? (T)0 : y;
-      const bool valid =
-          c < A.n_ctg && !gd && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
-      colw[c] = valid ? (T)1 : (T)0;
-    }
+    s_col[tid] = c;
+    s_y[tid] = nh > 0 ? ycol(Fv, A, cand, c, nf) : (T)0;
+  }
+  if (!skip && (nh > 0 || !PC)) {
+    const T tau = s_tau;
     const int r0 = band * A.band_rows, r1 = min(r0 + A.band_rows, A.mon_pad);
-    const int ntc = ld_o / TN;
-    // tau (from k_scan_colmax): the top_k-th largest of the band's column maxima and
-    // N-0 maximum, a lower bound of the band's top_k-th case
-    if (tid == 0) s_tau = (T)A.tau[(size_t)cand * A.nbands + band];
-    const uint32_t *hw = A.hot ? A.hot + ((size_t)cand * A.nbands + band) * (ld_o / 32) : nullptr;
     for (int rc0 = r0; rc0 < r1; rc0 += rchunk) {
       const int rows = min(rchunk, r1 - rc0);
       __syncthreads();
+      bool nf = false;
       for (int rr = tid; rr < rows; rr += blockDim.x) {
         const int row = rc0 + rr;
         const T fv = ftilde(Fv, A.inv_r, row, A.n_mon, nf);
         fs[fs_pos(fs, rr)] = fv;
-        if (row < A.n_mon && tabs(fv) >= s_tau &&
-            better(tabs(fv), row, lv[KM - 1], lk[KM - 1]))
+        if (!PC && row < A.n_mon && tabs(fv) >= tau && better(tabs(fv), row, lv[KM - 1], lk[KM - 1]))
           list_insert(lv, lk, tabs(fv), row);
       }
       __syncthreads();
-      const int nt = (rows / TM) * ntc;
-      for (int tile = wv; tile < nt; tile += 4) {
-        const int tr = tile / ntc, tc = tile - tr * ntc;
-        const int rowbase = rc0 + tr * TM, colbase = tc * TN;
-        // a tile without a column whose band maximum reaches tau holds no entry of
-        // the list (its values are those k_scan_colmax maximised, bit for bit)
-        if (hw) {
-          uint32_t h = 0;
-#pragma unroll
-          for (int q = 0; q < TN / 32; ++q) h |= hw[colbase / 32 + q];
-          if (h == 0) continue;
+      if (nh == 0) continue;
+      const int col = s_col[li];
+      const T yc = s_y[li];
+      const bool live = li < nh;
+      for (int rb = wv; rb < rows / 16; rb += 4) {
+        const int rowbase = rc0 + rb * 16;
+        // the seed block of (rowbase, col) in the MFMA accumulator layout, then the
+        // k steps with the gathered W values
+        typename TileOf<T>::blk c4;
+        {
+          const typename TileOf<T>::blk *seed =
+              reinterpret_cast<const typename TileOf<T>::blk *>(sizeof(T) == 4 ? (const void *)A.lsd32
+                                                                               : (const void *)A.lsd64f);
+          c4 = seed[((size_t)(rowbase / 16) * (ld_o / 16) + col / 16) * kWave + g * 16 + col % 16];
         }
-        T L[4][NB][4];
-        build_tile(L, A, e0, k, rowbase, colbase, g, li, lane);
+        for (int h = 0; h * 4 < k; ++h) {  // wave-uniform
+          // row li of the block, element 4 h + g (as update_frags, one row and column block)
+          const int e = h * 4 + g;
+          const int es = max(e0 + (e < k ? e : k - 1), 0);
+          T a, b;
+          if (sizeof(T) == 4) {
+            a = (T)A.ur32[(size_t)es * A.mon_pad + rowbase + li];
+            b = (T)A.w32[(size_t)es * ld_o + col];
+          } else {
+            a = (T)(A.U[(size_t)es * A.ld_er + rowbase + li] * A.inv_r[rowbase + li]);
+            b = (T)A.W[(size_t)es * ld_o + col];
+          }
+          const bool on = e < k;
+          a = on ? a : (T)0;
+          b = on ? b : (T)0;
+          c4 = mfma_step1(a, b, c4);
+        }
         const T *fsv = fs + (rowbase - rc0) + 4 * g;
-        T fr[4][4], yc[NB];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) fr[a][r] = fsv[a * 16 + r];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) yc[b] = ys[colbase + b * 16 + li];
-        T pv[4][NB][4], ma[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          ma[a] = (T)0;
-#pragma unroll
-          for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int r = 0; r < 4; r += 2) {
-              pv[a][b][r] = tfma(L[a][b][r], yc[b], fr[a][r]);
-              pv[a][b][r + 1] = tfma(L[a][b][r + 1], yc[b], fr[a][r + 1]);
-              ma[a] = absmax3(ma[a], pv[a][b][r], pv[a][b][r + 1]);
-            }
-        }
-        // The best of the lanes' last entries bounds the wave's top_k-th case
-        // from below, and so does tau: a value under either cannot enter the
-        // result.  A 16-row block whose lane maximum reaches both bounds is
-        // reviewed element by element through the wave's LDS slot (element i of a
-        // lane at i * 64 + lane), so that one copy of the insertion code serves
-        // all its elements.
-        T wt = lv[KM - 1];
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) wt = tmax(wt, __shfl_xor(wt, o));
-        wt = tmax(wt, s_tau);
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          if (!__any(ma[a] >= lv[KM - 1] && ma[a] >= wt)) continue;
-#pragma unroll
-          for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) tvw[(b * 4 + r) * kWave + lane] = pv[a][b][r];
-#pragma unroll 1
-          for (int i = 0; i < NE; ++i) {
-            const int b = i / 4, r = i % 4;
-            const int row = rowbase + a * 16 + MfmaRow<T>::row(g, r);
-            const int c = colbase + b * 16 + li;
-            const T v = tabs(tvw[i * kWave + lane]);
-            const int key = (c + 1) * A.n_mon + row;
-            const bool ok = colw[c] != (T)0 && row < A.n_mon && v >= wt &&
-                            better(v, key, lv[KM - 1], lk[KM - 1]);
-            if (ok) list_insert(lv, lk, v, key);
+        for (int r = 0; r < 4; ++r) {
+          const int row = rowbase + MfmaRow<T>::row(g, r);
+          const T v = tabs(tfma(c4[r], yc, fsv[r]));
+          if (PC) {
+            if (live && row < A.n_mon && better(v, row, lv[KM - 1], lk[KM - 1]))
+              list_insert(lv, lk, v, row);
+          } else {
+            const int key = (col + 1) * A.n_mon + row;
+            if (live && row < A.n_mon && v >= tau && better(v, key, lv[KM - 1], lk[KM - 1]))
+              list_insert(lv, lk, v, key);
           }
         }
       }
     }
   }
+  if (PC) {
+    // merge the 16 lists of each hot column; a skipped candidate writes nothing
+    if (skip || nh == 0) return;
+    T *mv = fs + ((A.rchunk + 1) & ~1);  // [256 lanes][KM] after the F~ chunk
+    int *mk = reinterpret_cast<int *>(mv + (size_t)blockDim.x * KM);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+      mv[(size_t)tid * KM + j] = lv[j];
+      mk[(size_t)tid * KM + j] = lk[j];
+    }
+    __syncthreads();
+    if (tid < nh) {
+      // lists of column tid: lanes tid + 16 g of each wave
+      int pos[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) pos[q] = 0;
+      const int c = s_col[tid];
+      WEntry *dst = A.pcl + ((size_t)cand * A.pc_nslots + 1 + c) * A.per_case;
+      for (int j = 0; j < A.per_case; ++j) {
+        T bv = (T)-1;
+        int bk = kEmpty, bq = -1;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int t = (q / 4) * kWave + (q % 4) * 16 + tid;
+          if (pos[q] < KM) {
+            const T v = mv[(size_t)t * KM + pos[q]];
+            const int kk = mk[(size_t)t * KM + pos[q]];
+            if (kk != kEmpty && better(v, kk, bv, bk)) {
+              bv = v;
+              bk = kk;
+              bq = q;
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (q == bq) ++pos[q];
+        WEntry e;
+        e.v = bk == kEmpty ? -1.0 : (double)bv;
+        e.k = bk == kEmpty ? kEmpty : (1 + c) * A.n_mon + bk;
+        e.pad = 0;
+        dst[j] = e;
+      }
+    }
+    return;
+  }
   // the band's list: rounds of "best head over the block"; the winning lane pops.
   // Keys are unique among real entries, and empty entries never win.
+  WEntry *dst = A.wpart + ((size_t)cand * A.nbt + band) * A.top_k;
   for (int j = 0; j < A.top_k; ++j) {
     T bv = lv[0];
     int bk = lk[0];
@@ -1171,9 +1222,9 @@ __device__ __forceinline__ void scan_worst_item(const ScanArgs &A, int cand, int
   }
 }
 
-template <typename T, int KM, int MINW>
-__global__ void __launch_bounds__(256, MINW) k_scan_worst(ScanArgs A) {
-  for_each_item(A, kQueueWin, [&](int cand, int band) __attribute__((always_inline)) { scan_worst_item<T, KM>(A, cand, band); });
+template <typename T, int KM, bool PC>
+__global__ void __launch_bounds__(256) k_scan_hot(ScanArgs A) {
+  for_each_item(A, kQueueWin, [&](int cand, int band) __attribute__((always_inline)) { scan_hot_item<T, KM, PC>(A, cand, band); });
 }
 
 // One wave per candidate: merges the bands' sorted lists (lane b walks bands b,
@@ -2072,7 +2123,8 @@ inline int worst_band_rows(const dcflow_plan *p) {
 template <typename T>
 hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_score *scores,
                      int top_k, void *ws, dcflow_case *out, hipStream_t s,
-                     double *cmx_out = nullptr) {
+                     double *cmx_out = nullptr, void *pcl = nullptr, int pc_nslots = 0,
+                     int per_case = 0) {
   dcflow_plan *p = bt->plan;
   constexpr int NB = ScanCfg<T>::TN / 16;
   ScanArgs a;
@@ -2118,6 +2170,9 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   a.top_k = top_k;
   a.wpart = static_cast<WEntry *>(ws);
   a.cmx_out = cmx_out;
+  a.pcl = static_cast<WEntry *>(pcl);
+  a.pc_nslots = pc_nslots;
+  a.per_case = per_case;
   set_multi(a, p, bt);
   const size_t fixed = sizeof(T) * (2 * (size_t)p->ld_o + 4 * (size_t)(4 * NB) * kWave);
   int band = worst_band_rows(p);
@@ -2137,21 +2192,30 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   const size_t lds = fixed + sizeof(T) * (size_t)rc;
   if (lds > kLdsBudget) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((size_t)a.n_cand * a.nbands));
-  // the thresholds first (tau after the band lists in the workspace, or in front of
-  // the case maxima of the two-level pass)
+  // the thresholds and hot-column lists first (after the band lists in the
+  // workspace, or after the case maxima of the two-level lists)
   a.tau = cmx_out ? cmx_out + (size_t)bt->n_cand * (p->ld_o + 2)
                   : reinterpret_cast<double *>(static_cast<char *>(ws) +
                                                worst_list_bytes(bt->n_cand, a.nbt, top_k));
-  // the hot-column masks after the thresholds (not needed for the case maxima)
-  a.hot = cmx_out ? nullptr
-                  : reinterpret_cast<uint32_t *>(a.tau + (size_t)bt->n_cand * a.nbands);
+  a.hotl = reinterpret_cast<int32_t *>(a.tau + (size_t)bt->n_cand * a.nbands);
   k_scan_colmax<T><<<grid, dim3(256), lds + sizeof(T) * (size_t)p->ld_o, s>>>(a);
   DCF_CHECK_LAUNCH();
-  if (cmx_out) return hipSuccess;  // the case maxima only
+  // the hot columns: F~ in row chunks of at most 1024 (and the per-case merge area)
+  a.rchunk = std::min(band, 1024);
+  const size_t lhot = sizeof(T) * (size_t)(((a.rchunk + 1) & ~1));
+  if (cmx_out) {
+    if (!pcl) return hipSuccess;  // the case maxima only
+    if (per_case <= 4)
+      k_scan_hot<T, 4, true><<<grid, dim3(256), lhot + 256 * 4 * (sizeof(T) + 4), s>>>(a);
+    else
+      k_scan_hot<T, 16, true><<<grid, dim3(256), lhot + 256 * 16 * (sizeof(T) + 4), s>>>(a);
+    DCF_CHECK_LAUNCH();
+    return hipSuccess;
+  }
   if (top_k <= 8)
-    k_scan_worst<T, 8, 1><<<grid, dim3(256), lds, s>>>(a);
+    k_scan_hot<T, 8, false><<<grid, dim3(256), lhot, s>>>(a);
   else
-    k_scan_worst<T, 16, 1><<<grid, dim3(256), lds, s>>>(a);
+    k_scan_hot<T, 16, false><<<grid, dim3(256), lhot, s>>>(a);
   DCF_CHECK_LAUNCH();
   if (a.nmb > 0) {
     const dim3 gm((unsigned)((size_t)a.n_cand * a.nmb));
@@ -2195,14 +2259,19 @@ bool case_maxima_supported(const dcflow_plan *p) { return worst_bands(p) == 1; }
 
 hipError_t launch_case_maxima(dcflow_batch *bt, const void *flows, int nvar, int prec,
                               const dcflow_score *scores, int top_k, double *cmx_out,
-                              hipStream_t s) {
+                              void *pcl, int pc_nslots, int per_case, hipStream_t s) {
   if (bt->n_cand == 0) return hipSuccess;
   if (!case_maxima_supported(bt->plan)) return hipErrorInvalidValue;
   if (prec == DCFLOW_FP64)
     return run_worst<double>(bt, static_cast<const double *>(flows), nvar, scores, top_k,
-                             nullptr, nullptr, s, cmx_out);
+                             nullptr, nullptr, s, cmx_out, pcl, pc_nslots, per_case);
   return run_worst<float>(bt, static_cast<const float *>(flows), nvar, scores, top_k, nullptr,
-                          nullptr, s, cmx_out);
+                          nullptr, s, cmx_out, pcl, pc_nslots, per_case);
+}
+
+size_t worst_aux_bytes(int n_cand, int nbands) {
+  // per band: tau (double), then the hot-column list
+  return (size_t)n_cand * nbands * (sizeof(double) + kHotLd * sizeof(int32_t));
 }
 
 hipError_t launch_score(dcflow_batch *bt, const void *flows, int nvar, int prec, dcflow_score *out,
