@@ -395,19 +395,41 @@ def ranks(w):
     return np.diff(np.asarray(w.cands.off))
 
 
+# VALU lane instructions per N-1 element of one variant that the sweep cannot do
+# without: one FMA for p = F~ + L~ y and its share of the running maximum of |p|
+# (FP32: a three-input max with absolute-value operands takes two elements; FP64
+# has no such instruction: one two-input max per element, |.| being free).
+SWEEP_OPS = {"fp64": 2.0, "fp32": 1.5, "bf16x6": 1.5}
+
+
 def scan_roofline(w, prec, scan_ms, traffic=None):
-    """The N-1 scan (a5) against the VALU FMA issue rate: 2 flops (one FMA) per N-1
-    element of every variant (V sweeps of E_m x O per candidate), plus the LODF'
-    tile build, k FMAs per (monitored row, contingency) per candidate of rank k."""
+    """The N-1 scan (a5) against a combined VALU + matrix-core bound.  The sweep:
+    every (monitored row, contingency) element of every variant costs SWEEP_OPS
+    VALU lane instructions at the issue rate of 256 CU x 64 lanes x 2.4 GHz (its
+    FMA is 2 of the flops counted).  The LODF' tile build: k FMAs per element of a
+    candidate of rank k on the matrix cores of the scan's precision, once for the
+    variants' maxima and once for the winner (once when there is one variant).
+    t_ideal = sweep ops / issue rate + build flops / MFMA peak; frac = t_ideal / t;
+    achieved = (sweep FMA flops + build flops) / t and peak = the same / t_ideal."""
     n_ctg = len(w.out) + (0 if w.gens is None else len(w.gens[0]))
-    per_pair = len(w.mon) * n_ctg
-    flops = 2.0 * per_pair * (w.cands.n_cand * w.n_var + float(ranks(w).sum()))
-    achieved = flops / (scan_ms / 1e3) / 1e12
+    per_pair = float(len(w.mon)) * n_ctg
+    n_el = per_pair * w.cands.n_cand * w.n_var
+    builds = 1 if w.n_var == 1 else 2
+    build_flops = 2.0 * per_pair * float(ranks(w).sum()) * builds
+    sweep_flops = 2.0 * n_el
+    issue = PEAK_VALU_FMA_TFLOPS / 2 * 1e12          # lane instructions per second
+    mfma = PEAK["mfma_fp64"] if prec == "fp64" else PEAK["mfma_fp32"]
+    t_ideal = SWEEP_OPS["fp64" if prec == "fp64" else "fp32"] * n_el / issue \
+        + build_flops / (mfma * 1e12)
+    t = scan_ms / 1e3
+    flops = sweep_flops + build_flops
     return {"bound": "alu", "kernel": f"n1_score {prec} (k_scan_max + k_scan_win"
             + (" + error guard" if prec != "fp64" else "") + ")",
-            "achieved": achieved, "peak": PEAK["valu"], "unit": "TFLOP/s",
-            "frac": achieved / PEAK["valu"], "traffic": traffic, "flops_per_call": flops,
-            "ms_per_call": scan_ms}
+            "achieved": flops / t / 1e12, "peak": flops / t_ideal / 1e12, "unit": "TFLOP/s",
+            "frac": t_ideal / t, "traffic": traffic, "flops_per_call": flops,
+            "t_ideal_ms": t_ideal * 1e3, "sweep_ops_per_element": SWEEP_OPS[
+                "fp64" if prec == "fp64" else "fp32"],
+            "build_flops": build_flops, "ms_per_call": scan_ms}
 
 
 def gemm_roofline(w, plan, prec, inj_ms):
