@@ -197,13 +197,16 @@ __device__ __forceinline__ void global_max_nonneg(double *p, double v) {
 
 template <typename T>
 struct ScanCfg;
+// Wave tile: RB row blocks of 16 by TN columns (FP32 64 x 64, FP64 32 x 64: the
+// same 32 accumulator values per lane; the FP64 shape reads 8 F~ and 4 y values
+// per variant and lane instead of 16 and 2)
 template <>
 struct ScanCfg<float> {
-  static constexpr int TN = 64;  // columns per wave tile
+  static constexpr int RB = 4, TN = 64;
 };
 template <>
 struct ScanCfg<double> {
-  static constexpr int TN = 32;
+  static constexpr int RB = 2, TN = 64;
 };
 
 // Position of chunk row rr in the staged F~ array: the rows that a block leaves
@@ -221,8 +224,8 @@ __device__ __forceinline__ int fs_pos(double *, int rr) {
 // candidate has none), and frag_mask zeroes the fragments past k only where
 // the MFMA consumes them.  The FP32 path reads U / r and W rounded to FP32 once
 // per evaluation (the same values the FP64 products would round to).
-template <int NB>
-__device__ __forceinline__ void update_frags(double (&af)[4], double (&bfr)[NB], const ScanArgs &A,
+template <int RB, int NB>
+__device__ __forceinline__ void update_frags(double (&af)[RB], double (&bfr)[NB], const ScanArgs &A,
                                              int e0, int k, int h, int rowbase, int colbase, int g,
                                              int li) {
   const int e = h * 4 + g;
@@ -230,15 +233,15 @@ __device__ __forceinline__ void update_frags(double (&af)[4], double (&bfr)[NB],
   const double *u = A.U + (size_t)es * A.ld_er;
   const double *w = A.W + (size_t)es * A.ld_o;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < RB; ++a) {
     const int row = rowbase + a * 16 + li;
     af[a] = u[row] * A.inv_r[row];
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b) bfr[b] = w[colbase + b * 16 + li];
 }
-template <int NB>
-__device__ __forceinline__ void update_frags(float (&af)[4], float (&bfr)[NB], const ScanArgs &A,
+template <int RB, int NB>
+__device__ __forceinline__ void update_frags(float (&af)[RB], float (&bfr)[NB], const ScanArgs &A,
                                              int e0, int k, int h, int rowbase, int colbase, int g,
                                              int li) {
   const int e = h * 4 + g;
@@ -246,99 +249,83 @@ __device__ __forceinline__ void update_frags(float (&af)[4], float (&bfr)[NB], c
   const float *u = A.ur32 + (size_t)es * A.mon_pad;
   const float *w = A.w32 + (size_t)es * A.ld_o;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) af[a] = u[rowbase + a * 16 + li];
+  for (int a = 0; a < RB; ++a) af[a] = u[rowbase + a * 16 + li];
 #pragma unroll
   for (int b = 0; b < NB; ++b) bfr[b] = w[colbase + b * 16 + li];
 }
-template <typename T, int NB>
-__device__ __forceinline__ void frag_mask(T (&af)[4], T (&bfr)[NB], int k, int h, int g) {
+template <typename T, int RB, int NB>
+__device__ __forceinline__ void frag_mask(T (&af)[RB], T (&bfr)[NB], int k, int h, int g) {
   const bool on = h * 4 + g < k;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) af[a] = on ? af[a] : (T)0;
+  for (int a = 0; a < RB; ++a) af[a] = on ? af[a] : (T)0;
 #pragma unroll
   for (int b = 0; b < NB; ++b) bfr[b] = on ? bfr[b] : (T)0;
 }
 
-// A tile of L~ in MFMA accumulator form: FP32 64 x 64 (16 blocks of f4), FP64
-// 64 x 32 (8 blocks of d4).  L[a][b][r] is row 16 a + MfmaRow(g, r), column
-// 16 b + li of the tile.
+// A tile of L~ in MFMA accumulator form (RB x NB blocks of 16 x 16: f4 in FP32,
+// d4 in FP64).  L[a][b][r] is row 16 a + MfmaRow(g, r), column 16 b + li of the
+// tile.
 template <typename T>
 struct TileOf;
 template <>
 struct TileOf<float> {
   typedef f4 blk;
-  static constexpr int NB = 4;
+  static constexpr int RB = ScanCfg<float>::RB, NB = ScanCfg<float>::TN / 16;
 };
 template <>
 struct TileOf<double> {
   typedef d4 blk;
-  static constexpr int NB = 2;
+  static constexpr int RB = ScanCfg<double>::RB, NB = ScanCfg<double>::TN / 16;
 };
 
-// The seed blocks of a tile, loaded into the MFMA accumulators.
-__device__ __forceinline__ void tile_load_seed(f4 (&c)[4][4], const ScanArgs &A, int rowbase,
-                                               int colbase, int g, int li, int lane) {
-  const f4 *seed = reinterpret_cast<const f4 *>(A.lsd32) +
-                   ((size_t)(rowbase / 16) * (A.ld_o / 16) + colbase / 16) * kWave + lane;
-  const size_t rstride = (size_t)(A.ld_o / 16) * kWave;
+// The seed blocks of a tile (fragment-major copies of Lsd: per 16 x 16 block the
+// 64 lanes' accumulator values in a row), loaded into the MFMA accumulators.
+template <typename B, int RB, int NB>
+__device__ __forceinline__ void tile_load_seed(B (&c)[RB][NB], const B *base, int ld_o,
+                                               int rowbase, int colbase, int lane) {
+  const B *seed = base + ((size_t)(rowbase / 16) * (ld_o / 16) + colbase / 16) * kWave + lane;
+  const size_t rstride = (size_t)(ld_o / 16) * kWave;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < RB; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) c[a][b] = seed[a * rstride + b * kWave];
-  (void)g;
-  (void)li;
+    for (int b = 0; b < NB; ++b) c[a][b] = seed[a * rstride + b * kWave];
 }
-__device__ __forceinline__ void tile_load_seed(d4 (&c)[4][2], const ScanArgs &A, int rowbase,
-                                               int colbase, int g, int li, int lane) {
-  const d4 *seed = reinterpret_cast<const d4 *>(A.lsd64f) +
-                   ((size_t)(rowbase / 16) * (A.ld_o / 16) + colbase / 16) * kWave + lane;
-  const size_t rstride = (size_t)(A.ld_o / 16) * kWave;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) c[a][b] = seed[a * rstride + b * kWave];
-  (void)g;
-  (void)li;
+__device__ __forceinline__ const f4 *seed_of(const ScanArgs &A, float) {
+  return reinterpret_cast<const f4 *>(A.lsd32);
+}
+__device__ __forceinline__ const d4 *seed_of(const ScanArgs &A, double) {
+  return reinterpret_cast<const d4 *>(A.lsd64f);
 }
 // One k step of L = seed + (U / r) W on the matrix cores.
-__device__ __forceinline__ void tile_mfma_step(f4 (&c)[4][4], const float (&fa)[4],
-                                               const float (&fb)[4]) {
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-      c[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[b], c[a][b], 0, 0, 0);
-}
-__device__ __forceinline__ void tile_mfma_step(d4 (&c)[4][2], const double (&fa)[4],
-                                               const double (&fb)[2]) {
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-      c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], c[a][b], 0, 0, 0);
-}
-// One k step of a single 16 x 16 block.
 __device__ __forceinline__ f4 mfma_step1(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 __device__ __forceinline__ d4 mfma_step1(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+template <typename T, typename B, int RB, int NB>
+__device__ __forceinline__ void tile_mfma_step(B (&c)[RB][NB], const T (&fa)[RB],
+                                               const T (&fb)[NB]) {
+#pragma unroll
+  for (int a = 0; a < RB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) c[a][b] = mfma_step1(fa[a], fb[b], c[a][b]);
+}
 // L~ for the tile at (rowbase, colbase): the seed blocks, then per k step (one
 // for k <= 4, two for k <= 8; wave-uniform) its fragments and MFMAs.
-template <typename T, int NB>
-__device__ __forceinline__ void build_tile(T (&L)[4][NB][4], const ScanArgs &A, int e0, int k,
+template <typename T, int RB, int NB>
+__device__ __forceinline__ void build_tile(T (&L)[RB][NB][4], const ScanArgs &A, int e0, int k,
                                            int rowbase, int colbase, int g, int li, int lane) {
-  typename TileOf<T>::blk c[4][NB];
-  T fa[4], fb[NB];
-  tile_load_seed(c, A, rowbase, colbase, g, li, lane);
+  typename TileOf<T>::blk c[RB][NB];
+  T fa[RB], fb[NB];
+  tile_load_seed(c, seed_of(A, (T)0), A.ld_o, rowbase, colbase, lane);
   for (int h = 0; h * 4 < k; ++h) {  // wave-uniform
     update_frags(fa, fb, A, e0, k, h, rowbase, colbase, g, li);
     frag_mask(fa, fb, k, h, g);
     tile_mfma_step(c, fa, fb);
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < RB; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -388,7 +375,7 @@ __device__ __forceinline__ bool guarded(const ScanArgs &A, int cand, int c) {
 // atomic maxima (vmax is cleared by k_clear first).
 template <typename T, int VC>
 __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int band) {
-  constexpr int TM = 64, TN = ScanCfg<T>::TN, NB = TN / 16;
+  constexpr int RB = ScanCfg<T>::RB, TM = 16 * RB, TN = ScanCfg<T>::TN, NB = TN / 16;
   // y and F~ are stored variant-minor with a stride of VC + 1 (an odd number of
   // elements: the 16 columns and the 4 row groups a read instruction touches fall
   // in different banks), so that every read of the variant loop is one base
@@ -479,7 +466,7 @@ __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int b
     for (int tile = wv; tile < nt; tile += 4) {
       const int tr = tile / ntc, tc = tile - tr * ntc;
       const int rowbase = rc0 + tr * TM, colbase = tc * TN;
-      T L[4][NB][4];
+      T L[RB][NB][4];
       build_tile(L, A, e0, k, rowbase, colbase, g, li, lane);
       const T *fsb = fs + (size_t)((rowbase - rc0) + 4 * g) * VS;
       const T *ysb = ys + (size_t)(colbase + li) * VS;
@@ -488,9 +475,9 @@ __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int b
         // FP32 keeps a branch per variant: without it the hoisted LDS reads of the
         // 16 variants overflow its 128-register budget (four waves per SIMD)
         if (sizeof(T) == 4 && vi >= nv) continue;
-        T fr[4][4], yc[NB];
+        T fr[RB][4], yc[NB];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < RB; ++a)
 #pragma unroll
           for (int r = 0; r < 4; ++r) fr[a][r] = fsb[(a * 16 + r) * VS + vi];
 #pragma unroll
@@ -498,7 +485,7 @@ __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int b
         // two running maxima (even and odd row blocks) halve the dependent chain
         T m0 = mx[vi], m1 = (T)0;
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < RB; ++a)
 #pragma unroll
           for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -543,7 +530,7 @@ __global__ void __launch_bounds__(256, MINW) k_scan_max(ScanArgs A) {
 // tiles where a lane first reached the band maximum are built again for the key.
 template <typename T>
 __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int band) {
-  constexpr int TM = 64, TN = ScanCfg<T>::TN, NB = TN / 16;
+  constexpr int RB = ScanCfg<T>::RB, TM = 16 * RB, TN = ScanCfg<T>::TN, NB = TN / 16;
   constexpr long long kNoKey = 0x7fffffffffffffffLL;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int ld_o = A.ld_o, rchunk = A.rchunk;
@@ -622,20 +609,20 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
       const int tr = tile / ntc, tc = tile - tr * ntc;
       const int rowbase = rc0 + tr * TM, colbase = tc * TN;
       const int tid_tile = (rowbase / TM) * ntc + tc;
-      T L[4][NB][4];
+      T L[RB][NB][4];
       build_tile(L, A, e0, k, rowbase, colbase, g, li, lane);
       const T *fsv = fs + (rowbase - rc0) + 4 * g;
-      T fr[4][4], yc[NB];
+      T fr[RB][4], yc[NB];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < RB; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) fr[a][r] = fsv[a * 16 + r];
 #pragma unroll
       for (int b = 0; b < NB; ++b) yc[b] = ys[colbase + b * 16 + li];
-      T pv[4][NB][4];
+      T pv[RB][NB][4];
       T mt = (T)0;
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < RB; ++a)
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -649,20 +636,21 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
       first = gt ? tid_tile : first;
       run = gt ? mt : run;
       if (mt > (T)1) {  // overloads in this lane's part of the tile
-        // per column: sum of max(|p|, 1) over the lane's 16 rows, less 16.  Loads
-        // within the rating add exactly 1, so rounding enters only where a
-        // row is overloaded, and the difference with 16 is exact.
+        // per column: sum of max(|p|, 1) over the lane's 4 RB rows, less 4 RB.
+        // Loads within the rating add exactly 1, so rounding enters only where a
+        // row is overloaded, and the difference with 4 RB is exact.
         T acc[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[b] = (T)0;
 #pragma unroll
-        for (int i = 0; i < 16; i += 2)
+        for (int i = 0; i < 4 * RB; i += 2)
 #pragma unroll
           for (int b = 0; b < NB; ++b)
             acc[b] = add_absmax1(acc[b], pv[i / 4][b][i % 4], pv[i / 4][b][i % 4 + 1]);
         T o = (T)0;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) o = tfma(colw[colbase + b * 16 + li], acc[b] - (T)16, o);
+        for (int b = 0; b < NB; ++b)
+          o = tfma(colw[colbase + b * 16 + li], acc[b] - (T)(4 * RB), o);
         ov += (double)o;
       }
     }
@@ -711,10 +699,10 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
       }
       const int tr = t / ntc, tc = t - tr * ntc;
       const int rowbase = tr * TM, colbase = tc * TN;
-      T L[4][NB][4];
+      T L[RB][NB][4];
       build_tile(L, A, e0, k, rowbase, colbase, g, li, lane);
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < RB; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = rowbase + a * 16 + MfmaRow<T>::row(g, r);
@@ -856,7 +844,7 @@ __device__ __forceinline__ void list_insert(T (&lv)[KM], int (&lk)[KM], T v, int
 // same code as there, so the values agree bit for bit.
 template <typename T>
 __device__ __forceinline__ void scan_colmax_item(const ScanArgs &A, int cand, int band) {
-  constexpr int TM = 64, TN = ScanCfg<T>::TN, NB = TN / 16;
+  constexpr int RB = ScanCfg<T>::RB, TM = 16 * RB, TN = ScanCfg<T>::TN, NB = TN / 16;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int ld_o = A.ld_o, rchunk = A.rchunk;
   T *ys = reinterpret_cast<T *>(smem_raw);  // [ld_o]
@@ -909,12 +897,12 @@ __device__ __forceinline__ void scan_colmax_item(const ScanArgs &A, int cand, in
     for (int tile = wv; tile < nt; tile += 4) {
       const int tr = tile / ntc, tc = tile - tr * ntc;
       const int rowbase = rc0 + tr * TM, colbase = tc * TN;
-      T L[4][NB][4];
+      T L[RB][NB][4];
       build_tile(L, A, e0, k, rowbase, colbase, g, li, lane);
       const T *fsv = fs + (rowbase - rc0) + 4 * g;
-      T fr[4][4];
+      T fr[RB][4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < RB; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) fr[a][r] = fsv[a * 16 + r];
       // per column: the maximum over the lane's 16 rows, then over the 4 lane groups
@@ -924,7 +912,7 @@ __device__ __forceinline__ void scan_colmax_item(const ScanArgs &A, int cand, in
         const T yc = ys[c];
         T cm = (T)0;
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < RB; ++a)
 #pragma unroll
           for (int r = 0; r < 4; r += 2)
             cm = absmax3(cm, tfma(L[a][b][r], yc, fr[a][r]), tfma(L[a][b][r + 1], yc, fr[a][r + 1]));
@@ -2126,7 +2114,6 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
                      double *cmx_out = nullptr, void *pcl = nullptr, int pc_nslots = 0,
                      int per_case = 0) {
   dcflow_plan *p = bt->plan;
-  constexpr int NB = ScanCfg<T>::TN / 16;
   ScanArgs a;
   a.F = flows;
   a.ld_f = p->ld_er;
@@ -2174,7 +2161,7 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   a.pc_nslots = pc_nslots;
   a.per_case = per_case;
   set_multi(a, p, bt);
-  const size_t fixed = sizeof(T) * (2 * (size_t)p->ld_o + 4 * (size_t)(4 * NB) * kWave);
+  const size_t fixed = sizeof(T) * 2 * (size_t)p->ld_o;  // k_scan_colmax: y and the weights
   int band = worst_band_rows(p);
   int rc = choose_rchunk(0, fixed, sizeof(T), p->mon_pad, kLdsOccupancy);
   if (rc > band) rc = band;
