@@ -372,13 +372,16 @@ __global__ void __launch_bounds__(256) k_pc_multi(PcArgs A) {
   pc_store(A, cand, slot, lv, lk);
 }
 
-// Level 2: one workgroup per candidate.  Each thread keeps the top KM of the
-// entries of its slots; the block then takes one entry per round from the heads.
+// Level 2: one workgroup per candidate (one wave when the case maxima leave a few
+// lists: the hot columns, N-0, guarded and multi-outage cases; four waves over
+// every slot otherwise).  Each thread keeps the top KM of the entries of its
+// slots; the block then takes one entry per round from the heads.
 template <int KM>
 __global__ void __launch_bounds__(256) k_pc_fin(PcArgs A, dcflow_case *out) {
   __shared__ double s_bv[4];
   __shared__ int s_bk[4];
   const int cand = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+  const int nw = blockDim.x / kWave;  // one wave after pruning (few lists), else four
   double lv[KM];
   int lk[KM];
 #pragma unroll
@@ -427,8 +430,7 @@ __global__ void __launch_bounds__(256) k_pc_fin(PcArgs A, dcflow_case *out) {
     __syncthreads();
     double wbv = s_bv[0];
     int wbk = s_bk[0];
-#pragma unroll
-    for (int w = 1; w < 4; ++w)
+    for (int w = 1; w < nw; ++w)
       if (pc_better(s_bv[w], s_bk[w], wbv, wbk)) {
         wbv = s_bv[w];
         wbk = s_bk[w];
@@ -552,10 +554,11 @@ hipError_t run_pc(dcflow_batch *bt, const T *flows, int nvar, const dcflow_score
       k_pc_multi<T, 16><<<gm, dim3(256), 0, s>>>(a);
     DCF_CHECK_LAUNCH();
   }
+  const dim3 fin_block(a.cmx && a.n_multi <= 64 ? 64 : 256);
   if (top_k <= 8)
-    k_pc_fin<8><<<dim3(nc), dim3(256), 0, s>>>(a, out);
+    k_pc_fin<8><<<dim3(nc), fin_block, 0, s>>>(a, out);
   else
-    k_pc_fin<16><<<dim3(nc), dim3(256), 0, s>>>(a, out);
+    k_pc_fin<16><<<dim3(nc), fin_block, 0, s>>>(a, out);
   DCF_CHECK_LAUNCH();
   return hipSuccess;
 }
