@@ -496,11 +496,12 @@ def workload_brute(seed: int = 0, n_topo: int = 1024, n_comb: int = 4096, n_out:
                    n_hvdc: int = 4) -> Workload:
     """Injection brute force: 2,000 buses / 3,100 branches with 20 phase shifters
     (random non-bridges) and 4 HVDC links (random bus pairs at least 5 hops
-    apart); topologies as in the medium workload (1-3 splits + 0-2 outages) that
-    leave the phase shifters and their buses alone; the same n_comb control and
-    load combinations for every topology (integer shifter degrees in -10..10,
-    HVDC levels 0..7 of 0.25 p.u., loads perturbed by N(0, 0.05)); every branch
-    monitored, n_out contingencies among the non-bridges that are not shifters."""
+    apart); topologies as in the medium workload (1-3 splits + 0-2 outages; a
+    split may move a shifter's branch and an outage may remove one); the same
+    n_comb control and load combinations for every topology (integer shifter
+    degrees in -10..10, HVDC levels 0..7 of 0.25 p.u., loads perturbed by
+    N(0, 0.05)); every branch monitored, n_out contingencies among the
+    non-bridges (shifters included)."""
     rng = np.random.default_rng(seed + 4000)
     grid = make_grid(n_bus, n_branch, seed)
     pst = [int(x) for x in non_bridges(grid, rng, n_pst)]
@@ -510,15 +511,12 @@ def workload_brute(seed: int = 0, n_topo: int = 1024, n_comb: int = 4096, n_out:
         far = np.flatnonzero(_hops(grid, i) >= 5)
         if len(far):
             hvdc.append((i, int(rng.choice(far))))
-    pst_set = set(pst)
-    cand_out = [int(x) for x in non_bridges(grid, rng, n_out + n_pst) if int(x) not in pst_set]
-    out = np.sort(np.asarray(cand_out[:n_out], np.int32))
-    pst_bus = {int(grid.f[l]) for l in pst} | {int(grid.t[l]) for l in pst}
-    sb = np.asarray([a for a in _split_buses(grid) if int(a) not in pst_bus])
+    out = np.sort(np.asarray([int(x) for x in non_bridges(grid, rng, n_out)], np.int32))
+    sb = _split_buses(grid)
     lists = []
     for _ in range(n_topo):
         lists.append(sample_candidate(grid, rng, int(rng.integers(1, 4)), int(rng.integers(0, 3)),
-                                      sb, forbid_out=pst_set))
+                                      sb))
     cands = Candidates.from_lists(lists)
     loads = perturbed_injections(grid, rng, (n_comb,), 0.05)
     deg = rng.integers(-10, 11, size=(n_comb, n_pst)).astype(np.float64)

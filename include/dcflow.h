@@ -132,8 +132,12 @@ typedef struct {
    *     theta_t - pst_scale a), column pst_scale b_l (PTDF[:, f] - PTDF[:, t] - e_l);
    *   HVDC link from bus i to bus j, value P: moves hvdc_scale P from i to j,
    *     column hvdc_scale (PTDF[:, j] - PTDF[:, i]).
-   * The base case has all controls at 0.  Phase-shifter branches may not be
-   * contingencies, outaged or moved by a split (E_ARG / E_CAND). */
+   * The base case has all controls at 0.  Phase-shifter branches may be
+   * contingencies, outaged or moved by a split: the shift's direct term is part
+   * of the flows that the low-rank corrections and the LODF act on, so a shifter
+   * on a removed branch contributes nothing and one on a moved branch keeps its
+   * shift between the branch's post-change terminals (Sec. II end; the tripping
+   * of a branch is a transfer of its N-0 flow, whatever fixed shifts it carries). */
   int32_t n_pst;
   const int32_t *pst_branch;   /* [n_pst] distinct branch ids                    */
   double pst_scale;            /* radians per unit (pi / 180 for degrees)        */

@@ -447,10 +447,9 @@ def score_candidate(n, f, t, b, slack, elems, x, mon, out, rating, controls=None
     mon = np.asarray(mon, np.int64)
     out = np.asarray(out, np.int64)
     r = np.asarray(rating, np.float64)
-    if controls is not None:
-        # the N-1 step below superposes the LODF on the N-0 flows, which holds for a
-        # fixed phase shift only while the tripped branch carries none
-        assert not set(int(c) for c in out) & set(int(l) for l in controls.get("pst", []))
+    # (with controls the N-0 flows carry the phase shifts' direct terms; tripping a
+    # branch, phase shifter or not, leaves the other shifts fixed and moves its N-0
+    # flow through the rest of the network: the LODF superposition below holds)
     cf = candidate_flows(n, f, t, b, slack, elems, x, out, controls, ctrl, gens)
     nv = np.atleast_2d(x).shape[0]
     if not cf["connected"]:

@@ -62,12 +62,10 @@ int check_grid(const dcflow_grid_desc *g) {
   if (g->n_pst < 0 || g->n_hvdc < 0) return DCFLOW_E_SHAPE;
   if (g->n_pst > 0) {
     if (!g->pst_branch || !std::isfinite(g->pst_scale)) return DCFLOW_E_ARG;
-    std::vector<uint8_t> is_out(g->n_branch, 0), is_pst(g->n_branch, 0);
-    for (int i = 0; i < g->n_out; ++i) is_out[g->out[i]] = 1;
+    std::vector<uint8_t> is_pst(g->n_branch, 0);
     for (int q = 0; q < g->n_pst; ++q) {
       const int l = g->pst_branch[q];
       if (l < 0 || l >= g->n_branch || is_pst[l]) return DCFLOW_E_SHAPE;
-      if (is_out[l]) return DCFLOW_E_ARG;  // a tripped phase shifter is not a superposition
       is_pst[l] = 1;
     }
   }
@@ -252,24 +250,10 @@ void batch_layout(dcflow_batch *b, const dcflow_plan *p, const BatchDims &d, Are
   b->d_mok = a.take<int32_t>(nc * (size_t)p->n_multi);
 }
 
-void pst_flags(const dcflow_grid_desc *g, std::vector<uint8_t> &br, std::vector<uint8_t> &bus) {
-  br.clear();
-  bus.clear();
-  if (g->n_pst <= 0) return;
-  br.assign(g->n_branch, 0);
-  bus.assign(g->n_bus, 0);
-  for (int q = 0; q < g->n_pst; ++q) {
-    const int l = g->pst_branch[q];
-    br[l] = 1;
-    bus[g->from[l]] = 1;
-    bus[g->to[l]] = 1;
-  }
-}
-
-// pst_br / pst_bus: phase-shifter branches and their terminal buses (may be
-// empty); candidates may not outage the former nor split the latter.
+// Candidate records against the grid (element kinds, ids, split masks, ranks).
+// Phase-shifter branches may be contingencies, outaged or moved by a split like
+// any other: the shift's direct term is part of the flows the corrections act on.
 int check_cands(int n_bus, int n_branch, const std::vector<int32_t> &adj_off,
-                const std::vector<uint8_t> &pst_br, const std::vector<uint8_t> &pst_bus,
                 const dcflow_cands *c, int32_t *bad, int64_t *packed, int64_t *padded,
                 int *kmax_out) {
   if (bad) *bad = 0;
@@ -302,9 +286,9 @@ int check_cands(int n_bus, int n_branch, const std::vector<int32_t> &adj_off,
     for (int j = a; j < e; ++j) {
       bool ok = true;
       if (c->kind[j] == DCFLOW_OUTAGE) {
-        ok = c->id[j] >= 0 && c->id[j] < n_branch && (pst_br.empty() || !pst_br[c->id[j]]);
+        ok = c->id[j] >= 0 && c->id[j] < n_branch;
       } else if (c->kind[j] == DCFLOW_SPLIT) {
-        ok = c->id[j] >= 0 && c->id[j] < n_bus && (pst_bus.empty() || !pst_bus[c->id[j]]);
+        ok = c->id[j] >= 0 && c->id[j] < n_bus;
         if (ok) {
           int deg = adj_off[c->id[j] + 1] - adj_off[c->id[j]];
           uint32_t mk = c->mask[j];
@@ -394,7 +378,6 @@ int dcflow_build_ptdf(const dcflow_grid_desc *g, void *dev_ws, size_t ws_bytes, 
   p->mon_pad = d.mon_pad;
   p->n_ctrl = d.n_ctrl;
   p->n_inj = d.n + d.n_ctrl;
-  pst_flags(g, p->pst_br, p->pst_bus);
   p->rating_scale = g->rating ? 1.2 : g->rating_scale;
   p->rating_offset = g->rating ? 0.1 : g->rating_offset;
   p->f.assign(g->from, g->from + d.m);
@@ -529,10 +512,8 @@ int dcflow_validate_candidates(const dcflow_grid_desc *g, const dcflow_cands *c,
                                int32_t *bad_index, int64_t *packed, int64_t *padded) {
   int rc = check_grid(g);
   if (rc != DCFLOW_OK) return rc;
-  std::vector<uint8_t> pbr, pbus;
-  pst_flags(g, pbr, pbus);
-  return check_cands(g->n_bus, g->n_branch, host_adj_off(g), pbr, pbus, c, bad_index, packed,
-                     padded, nullptr);
+  return check_cands(g->n_bus, g->n_branch, host_adj_off(g), c, bad_index, packed, padded,
+                     nullptr);
 }
 
 int dcflow_batch_bytes(const dcflow_plan *p, const dcflow_cands *c, int32_t n_var_max,
@@ -555,8 +536,7 @@ int dcflow_batch_create(dcflow_plan *p, const dcflow_cands *c, int32_t n_var_max
   int32_t bad = 0;
   int64_t packed = 0, padded = 0;
   int kmax = 0;
-  int rc = check_cands(p->n, p->m, p->adj_off, p->pst_br, p->pst_bus, c, &bad, &packed, &padded,
-                       &kmax);
+  int rc = check_cands(p->n, p->m, p->adj_off, c, &bad, &packed, &padded, &kmax);
   if (rc != DCFLOW_OK) return rc;
   BatchDims d{c->n_cand, c->n_cand ? c->off[c->n_cand] : 0, n_var_max};
   dcflow_batch *b = new (std::nothrow) dcflow_batch();

@@ -89,7 +89,6 @@ struct dcflow_plan {
   // host copies used for validation and packing
   std::vector<int32_t> f, t, adj_off, adj_br, out, pos_of_br;
   std::vector<uint8_t> is_out;  // per branch: contingency?
-  std::vector<uint8_t> pst_br, pst_bus;  // phase-shifter branches / terminals (empty: none)
 };
 
 struct dcflow_batch {

@@ -138,8 +138,9 @@ def test_library_binds_to_torch_hip_runtime():
 
 
 def test_control_validation(d):
-    """Phase shifters may not be contingencies, outaged or moved by a split;
-    bad control definitions are rejected before any device work."""
+    """Phase shifters may be contingencies, outaged or moved by a split (the
+    grid and the candidates are accepted); bad control definitions are rejected
+    before any device work."""
     import ctypes
     w = G.workload_brute(0, n_topo=2, n_comb=4)
     g = w.grid
@@ -147,22 +148,19 @@ def test_control_validation(d):
     nbytes = ctypes.c_size_t(0)
     assert d._lib.dcflow_plan_workspace_bytes(ctypes.byref(ok.desc), ctypes.byref(nbytes)) == 0
     pst = w.controls["pst"]
-    bad_out = d._GridArgs(g.n_bus, g.f, g.t, g.b, w.mon, np.append(w.out, pst[0]), g.p, g.slack,
-                          controls=w.controls)
-    assert d._lib.dcflow_plan_workspace_bytes(ctypes.byref(bad_out.desc), ctypes.byref(nbytes)) == -1
+    extra = [int(l) for l in pst if int(l) not in set(w.out.tolist())]
+    with_pst = d._GridArgs(g.n_bus, g.f, g.t, g.b, w.mon, np.sort(np.append(w.out, extra[0])), g.p,
+                           g.slack, controls=w.controls)
+    assert d._lib.dcflow_plan_workspace_bytes(ctypes.byref(with_pst.desc), ctypes.byref(nbytes)) == 0
     c2 = dict(w.controls, hvdc=[(3, 3)])
     same = d._GridArgs(g.n_bus, g.f, g.t, g.b, w.mon, w.out, g.p, g.slack, controls=c2)
     assert d._lib.dcflow_plan_workspace_bytes(ctypes.byref(same.desc), ctypes.byref(nbytes)) == -2
-    # candidates: outage of a shifter, split of a shifter's bus
-    nb = np.flatnonzero(~np.isin(np.arange(g.n_branch), pst))
-    fine = [(G.KIND_OUTAGE, int(nb[0]), 0, 0.0)]
-    c = G.Candidates.from_lists([[], fine, [(G.KIND_OUTAGE, pst[0], 0, 0.0)]])
-    with pytest.raises(d.DcflowError) as e:
-        d.validate_candidates(ok, c)
-    assert e.value.bad_index == 1      # element 1: the shifter outage
+    c3 = dict(w.controls, pst=[pst[0], pst[0]] + list(pst[2:]))
+    dup = d._GridArgs(g.n_bus, g.f, g.t, g.b, w.mon, w.out, g.p, g.slack, controls=c3)
+    assert d._lib.dcflow_plan_workspace_bytes(ctypes.byref(dup.desc), ctypes.byref(nbytes)) == -2
+    # candidates: outage of a shifter, split of a shifter's bus (accepted)
     buses = [int(g.f[l]) for l in pst] + [int(g.t[l]) for l in pst]
     a = next(x for x in buses if len(g.incident(x)) >= 3)
-    c = G.Candidates.from_lists([fine, [(G.KIND_SPLIT, a, 2, 0.0)]])
-    with pytest.raises(d.DcflowError) as e:
-        d.validate_candidates(ok, c)
-    assert e.value.bad_index == 1      # element 1: the split of a shifter's bus
+    c = G.Candidates.from_lists([[], [(G.KIND_OUTAGE, pst[0], 0, 0.0)],
+                                 [(G.KIND_SPLIT, a, 2, 0.0)]])
+    d.validate_candidates(ok, c)

@@ -432,8 +432,11 @@ def test_hvdc_on_a_tree_closed_form():
 
 def test_n1_with_controls_matches_bruteforce():
     """LODF superposition on N-0 flows with phase shifters and HVDC links equals
-    re-solving every post-contingency network with the control model, when the
-    contingencies are not phase-shifter branches (also after splits and outages)."""
+    re-solving every post-contingency network with the control model: with
+    phase-shifter branches among the contingencies, a candidate that removes a
+    shifter's branch (the shifter then does nothing) and candidates whose split
+    moves a shifter's branch to the new busbar (the shift acts between its
+    post-change terminals), as well as plain splits and outages."""
     w = G.workload_tiny(0)
     g = w.grid
     nb = np.flatnonzero(~O.bridges(g.n_bus, g.f, g.t))
@@ -442,14 +445,24 @@ def test_n1_with_controls_matches_bruteforce():
     rng = np.random.default_rng(2)
     ctrl = np.column_stack([rng.integers(-10, 11, size=(4, 2)), rng.integers(0, 8, size=(4, 2))])
     x = G.perturbed_injections(g, rng, (4,), 0.2)
-    out = [int(c) for c in nb if int(c) not in pst][:12]
+    out = [int(c) for c in nb][:14]
+    assert set(pst) <= set(out)
     a = int(np.flatnonzero(g.degree() >= 3)[2])
-    cands = [[], [(G.KIND_OUTAGE, out[5], 0, 0.0)], [(G.KIND_SPLIT, a, 2, 0.4)]]
+
+    def moving(branch, bus, extra_bit):
+        # split of `bus` moving `branch` (and the incident branch of bit extra_bit)
+        inc = list(O.incident_branches(g.f, g.t, bus))
+        return (G.KIND_SPLIT, bus, (1 << inc.index(branch)) | (1 << extra_bit), 0.1)
+
+    cands = [[], [(G.KIND_OUTAGE, out[5], 0, 0.0)], [(G.KIND_SPLIT, a, 2, 0.4)],
+             [(G.KIND_OUTAGE, pst[1], 0, 0.0)],
+             [moving(pst[1], int(g.t[pst[1]]), 0), (G.KIND_OUTAGE, out[6], 0, 0.0)],
+             [moving(pst[0], int(g.t[pst[0]]), 0)], [moving(pst[1], int(g.f[pst[1]]), 0)]]
+    n_checked = 0
     for els in cands:
-        if any(k == G.KIND_SPLIT and (g.f[pst] == d).any() | (g.t[pst] == d).any()
-               for k, d, _, _ in els):
-            continue
         cf = O.candidate_flows(g.n_bus, g.f, g.t, g.b, g.slack, els, x, out, controls, ctrl)
+        if not cf["connected"]:
+            continue
         p1, isl = O.n1_flows_bruteforce(g.n_bus, g.f, g.t, g.b, g.slack, els, x, out, controls,
                                         ctrl)
         for ci, c in enumerate(out):
@@ -458,6 +471,8 @@ def test_n1_with_controls_matches_bruteforce():
             sup = cf["p0"] + cf["lodf"][:, ci][None, :] * cf["p0"][:, c][:, None]
             sup[:, c] = 0.0
             np.testing.assert_allclose(sup, p1[:, ci, :], atol=1e-10)
+            n_checked += c in pst
+    assert n_checked >= 8  # shifter contingencies checked across the candidates
 
 
 def test_per_variant_busbar_injections_match_fixed_ones():
