@@ -109,19 +109,37 @@ def cpu_baseline(w, n_sample: int, max_var: int = 0, keep_rows=None):
     def xs(i):
         x = w.inj[i] if not w.inj_shared else w.inj
         return x[:max_var] if max_var else x
-    jobs = [(g.n_bus, g.f, g.t, g.b, g.slack, w.cands.elements(i), xs(i), w.mon, w.out, rating,
-             getattr(w, "controls", None), getattr(w, "gens", None), getattr(w, "multi", None),
-             keep_rows)
-            for i in range(n_sample)]
+    # with fewer candidates than cores, each candidate's variants are split into
+    # chunks (each chunk repeats the candidate's factorisation, as the oracle does)
+    n_var = xs(0).shape[0] if n_sample else 0
+    per = max(1, -(-cores // max(1, n_sample)))          # chunks per candidate
+    step = max(1, -(-n_var // per))
+    jobs, owner = [], []
+    for i in range(n_sample):
+        x = xs(i)
+        for v0 in range(0, x.shape[0], step):
+            jobs.append((g.n_bus, g.f, g.t, g.b, g.slack, w.cands.elements(i), x[v0:v0 + step],
+                         w.mon, w.out, rating, getattr(w, "controls", None),
+                         getattr(w, "gens", None), getattr(w, "multi", None), keep_rows))
+            owner.append(i)
     # fresh interpreters (this process may already hold the GPU); started and warmed
     # up before the clock runs
     ctx = mp.get_context("spawn")
-    nproc = min(cores, max(1, n_sample))
+    nproc = min(cores, max(1, len(jobs)))
     with ctx.Pool(nproc) as pool:
         pool.map(_warm, range(nproc), chunksize=1)
         t0 = time.perf_counter()
-        outs = pool.map(_oracle_worker, jobs, chunksize=1)
+        parts = pool.map(_oracle_worker, jobs, chunksize=1)
         dt = time.perf_counter() - t0
+    # the chunks of a candidate back together (variants in order)
+    outs = []
+    for i in range(n_sample):
+        mine = [parts[j] for j in range(len(jobs)) if owner[j] == i]
+        res = dict(mine[0][1])
+        res["max_load"] = np.concatenate([np.atleast_1d(m[1]["max_load"]) for m in mine])
+        if "p0" in res:
+            res["p0"] = np.concatenate([m[1]["p0"] for m in mine], axis=0)
+        outs.append((sum(m[0] for m in mine), res))
     lf = sum(o[0] for o in outs)
     base = dict(value=lf / dt, unit="loadflows/s", cores=nproc,
                 kind="oracle",
