@@ -63,37 +63,42 @@ __global__ void k_assemble(double *B, int ld, int n, int slack, const int32_t *a
 // multiple of 64 with unit diagonal (its inverse stays unit there).
 constexpr int kGjB = 64;
 
-// P = inverse of the 64 x 64 diagonal block at p0 (Gauss-Jordan in LDS).
+// P = inverse of the 64 x 64 diagonal block at p0 by Gauss-Jordan, the block in
+// registers: thread t holds row t / 4, columns 16 (t % 4) .. + 15.  Per pivot q the
+// owners of row q and of column q post them to LDS (two buffers, so that one
+// barrier per pivot suffices) and every thread updates its 16 values.
 __global__ void __launch_bounds__(256) k_bgj_panel(const double *A, int ld, int p0, double *P) {
-  __shared__ double M[kGjB][kGjB + 1];
-  __shared__ double prow[kGjB], pcol[kGjB];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kGjB * kGjB; e += blockDim.x) {
-    const int r = e / kGjB, c = e % kGjB;
-    M[r][c] = A[(size_t)(p0 + r) * ld + p0 + c];
-  }
-  __syncthreads();
+  __shared__ double prow[2][kGjB], pcol[2][kGjB];
+  const int tid = threadIdx.x, r = tid >> 2, c0 = (tid & 3) * 16;
+  double v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = A[(size_t)(p0 + r) * ld + p0 + c0 + j];
+#pragma unroll
   for (int q = 0; q < kGjB; ++q) {
-    if (tid < kGjB) {
-      prow[tid] = M[q][tid];
-      pcol[tid] = M[tid][q];
-    }
+    const int bf = q & 1;
+    if (r == q)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) prow[bf][c0 + j] = v[j];
+    if ((tid & 3) == q / 16) pcol[bf][r] = v[q % 16];
     __syncthreads();
-    const double ip = 1.0 / prow[q];
-    for (int e = tid; e < kGjB * kGjB; e += blockDim.x) {
-      const int r = e / kGjB, c = e % kGjB;
-      double v;
+    const double ip = 1.0 / prow[bf][q];
+    const double pc = pcol[bf][r];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int c = c0 + j;
+      const double pr = prow[bf][c];
+      double x;
       if (r == q)
-        v = c == q ? ip : prow[c] * ip;
+        x = c == q ? ip : pr * ip;
       else if (c == q)
-        v = -pcol[r] * ip;
+        x = -pc * ip;
       else
-        v = M[r][c] - pcol[r] * (prow[c] * ip);
-      M[r][c] = v;
+        x = v[j] - pc * (pr * ip);
+      v[j] = x;
     }
-    __syncthreads();
   }
-  for (int e = tid; e < kGjB * kGjB; e += blockDim.x) P[e] = M[e / kGjB][e % kGjB];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) P[r * kGjB + c0 + j] = v[j];
 }
 
 // A[K, J] <- P A[K, J] for the 64-column block J = blockIdx.x (skipping K).
@@ -290,12 +295,18 @@ __global__ void k_rating(double *r, double *inv_r, int mon_pad, const int32_t *m
 // Largest magnitude of each column of Lsd over the monitored rows (one thread
 // per column, rows walked in order: neighbouring threads read neighbouring
 // columns).  The error guard of the FP32 scan bounds the seed by it.
+// Column maxima of |Lsd| (cmax cleared to 0 first): blockIdx.y takes a chunk of
+// kColmaxRows rows, and the chunk maxima meet in 64-bit integer atomic maxima on
+// the non-negative bit patterns.
+constexpr int kColmaxRows = 128;
 __global__ void k_colmax(const double *lsd, int ld_o, int n_mon, double *cmax) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r0 = blockIdx.y * kColmaxRows, r1 = min(r0 + kColmaxRows, n_mon);
   if (c >= ld_o) return;
   double m = 0.0;
-  for (int r = 0; r < n_mon; ++r) m = fmax(m, fabs(lsd[(size_t)r * ld_o + c]));
-  cmax[c] = m;
+  for (int r = r0; r < r1; ++r) m = fmax(m, fabs(lsd[(size_t)r * ld_o + c]));
+  atomicMax(reinterpret_cast<unsigned long long *>(cmax + c),
+            (unsigned long long)__double_as_longlong(m));
 }
 
 __global__ void k_lsd(double *lsd, int ld_o, const double *hdo, const int32_t *mon, int n_mon,
@@ -461,8 +472,11 @@ hipError_t launch_build(dcflow_plan *p, hipStream_t s, const double *h_rating, d
                      p->ld_o, p->d_hdo, p->d_mon, p->n_mon, p->d_out, p->n_out,
                      p->n_out + p->n_gen, p->d_inv_r, p->mon_pad);
   DCF_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_colmax, dim3(nblk(p->ld_o, 256)), dim3(256), 0, s, p->d_lsd, p->ld_o,
-                     p->n_mon, p->d_lsdmax);
+  hipLaunchKernelGGL(k_fill, dim3(nblk(p->ld_o, 256)), dim3(256), 0, s, p->d_lsdmax,
+                     (size_t)p->ld_o, 0.0);
+  DCF_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_colmax, dim3(nblk(p->ld_o, 256), nblk(p->n_mon, kColmaxRows)), dim3(256), 0,
+                     s, p->d_lsd, p->ld_o, p->n_mon, p->d_lsdmax);
   DCF_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_lsd32, dim3(nblk((size_t)p->mon_pad * p->ld_o / 4, 256)), dim3(256), 0, s,
                      p->d_lsd32, p->d_lsd, p->ld_o, p->mon_pad);
