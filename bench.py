@@ -767,6 +767,9 @@ def main():
                          "comma-separated numbers of injection topologies per candidate")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run three plain device copies of MIB MiB (HBM counter scale)")
+    ap.add_argument("--plan-builds", type=int, default=0, metavar="N",
+                    help="only build the workload's plan N times in a row and print the wall "
+                         "time of each (one-time FP64 base, host set-up included)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: there is no multi-GPU path here "
@@ -787,6 +790,27 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 3}))
+        return
+
+    if a.plan_builds:
+        import torch
+        import gridgen as G
+        from paper_2501_17529_amd import dcflow as D
+        torch.cuda.init()
+        wl = {"medium": lambda: G.workload_medium(0, n_cand=16),
+              "uneven": lambda: G.workload_uneven(0, n_cand=16),
+              "brute": lambda: G.workload_brute(0, n_topo=2, n_comb=4),
+              "tiny": lambda: G.workload_tiny(0)}[a.workload]()
+        times = []
+        for _ in range(a.plan_builds):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan = D.Plan.from_workload(wl)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+            del plan
+        print(json.dumps({"workload": a.workload, "n_bus": int(wl.grid.n_bus),
+                          "n_branch": int(wl.grid.n_branch), "plan_build_ms": times}))
         return
 
     if a.rank_sweep:
