@@ -598,7 +598,9 @@ def section_tiny(D, torch, steps):
 
 
 def section_uneven(D, torch, n_cand, steps, cpu_n, out_log):
-    """The 10,000-bus uneven-rank batch at its full size on one GPU."""
+    """The 10,000-bus uneven-rank batch at its full size on one GPU: each path is
+    captured into a HIP graph (its replay checked against the eager scores) and
+    timed in replay, with the row bands the autotuner picks on this batch."""
     import gridgen as G
     t0 = time.perf_counter()
     w = G.workload_uneven(0, n_cand=n_cand)
@@ -616,7 +618,7 @@ def section_uneven(D, torch, n_cand, steps, cpu_n, out_log):
     res, paths = {}, {}
     tun = {"fp64": dict(scan_band=0), "fp32": dict(scan_band=512), "bf16x6": dict(scan_band=512)}
     for prec in ("fp64", "fp32", "bf16x6"):
-        r = run_path(D, torch, plan, w, prec, steps, 1, tune=False, graph=False, agg_i=False,
+        r = run_path(D, torch, plan, w, prec, steps, 1, tune=False, graph=True, agg_i=False,
                      tuning=tun[prec])
         paths[prec] = path_summary(w, plan, r, prec, steps, n_lf, ores,
                                    ref=res.get("fp64"))
