@@ -207,8 +207,11 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
        const double *__restrict__ fber) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int LDS_K = Ldk<T>::v;
-  __shared__ __attribute__((aligned(16))) T As[BM][LDS_K];
-  __shared__ __attribute__((aligned(16))) T Bs[BN][LDS_K];
+  // FP64: two LDS stages (one barrier per K step; two workgroups per CU either way);
+  // FP32: one stage, which keeps four workgroups per CU
+  constexpr int NS = sizeof(T) == 8 ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) T As[NS][BM][LDS_K];
+  __shared__ __attribute__((aligned(16))) T Bs[NS][BN][LDS_K];
   const int xcd = blockIdx.x % kXcd, local = blockIdx.x / kXcd;
   const int n_tile = (local / n_mt) * kXcd + xcd, m_tile = local % n_mt;
   if (n_tile >= n_nt) return;
@@ -236,7 +239,7 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
         rb[q] = (brow && kb + q < n) ? (T)(brow[kb + q] - pbase[kb + q]) : (T)0;
     }
   };
-  auto sstore = [&]() {
+  auto sstore = [&](int st) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       V4<T> va, vb;
@@ -245,8 +248,8 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
         va.x[q] = ra[4 * h + q];
         vb.x[q] = rb[4 * h + q];
       }
-      *reinterpret_cast<V4<T> *>(&As[lr][lk + 4 * h]) = va;
-      *reinterpret_cast<V4<T> *>(&Bs[lr][lk + 4 * h]) = vb;
+      *reinterpret_cast<V4<T> *>(&As[st][lr][lk + 4 * h]) = va;
+      *reinterpret_cast<V4<T> *>(&Bs[st][lr][lk + 4 * h]) = vb;
     }
   };
   acc_t acc[4][4];
@@ -274,22 +277,24 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
     }
   };
 
-  // single LDS stage (measured faster here than two stages with one barrier): the
-  // next k-tile waits in registers while the current one is consumed
+  // the next k-tile waits in registers while the current one is consumed; FP32 (one
+  // LDS stage, measured faster there than two) stores it after a barrier, FP64 into
+  // the other stage at once
   gload(0);
-  sstore();
+  sstore(0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
+    const int st = NS == 2 ? (kt & 1) : 0;
     if (kt + 1 < nk) gload(kt + 1);
     // lane group g owns k = 4 g .. 4 g + 3 of the stage and feeds them to the 4 MFMA
     // steps in turn (A and B alike, so every k meets its partner)
     V4<T> af[4], bf[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
-      af[a] = *reinterpret_cast<const V4<T> *>(&As[wm * 64 + a * 16 + li][4 * g]);
+      af[a] = *reinterpret_cast<const V4<T> *>(&As[st][wm * 64 + a * 16 + li][4 * g]);
 #pragma unroll
     for (int b = 0; b < 4; ++b)
-      bf[b] = *reinterpret_cast<const V4<T> *>(&Bs[wn * 64 + b * 16 + li][4 * g]);
+      bf[b] = *reinterpret_cast<const V4<T> *>(&Bs[st][wn * 64 + b * 16 + li][4 * g]);
 #pragma unroll
     for (int ks = 0; ks < KT / 4; ++ks)
 #pragma unroll
@@ -299,10 +304,16 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
     if constexpr (FL > 0) {
       if (kt % FL == FL - 1 || kt + 1 == nk) flush();
     }
-    __syncthreads();
-    if (kt + 1 < nk) {
-      sstore();
+    if constexpr (NS == 2) {
+      // the other stage was last read in step kt - 1, before the previous barrier
+      if (kt + 1 < nk) sstore(st ^ 1);
       __syncthreads();
+    } else {
+      __syncthreads();
+      if (kt + 1 < nk) {
+        sstore(0);
+        __syncthreads();
+      }
     }
   }
   // epilogue: rank-k correction and store
