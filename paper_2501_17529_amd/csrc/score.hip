@@ -370,21 +370,52 @@ __device__ __forceinline__ bool guarded(const ScanArgs &A, int cand, int c) {
 }
 
 // ---------------------------------------------------------------- pass 1
+// Row strides (in elements) of pass 1's variant-minor LDS arrays: y uses VC + 1
+// (odd, so that the 16 columns a read touches fall in different banks); F~ uses
+// VC + 1 too, or in FP64 with an even VC, VC + 2, so that each pair of variants is
+// one aligned 16-byte read (ds_read_b128 takes a 16-bit offset: one base address
+// per tile for all F~ reads; its 4 row groups read broadcast addresses).
+template <typename T, int VC>
+struct VStride {
+  static constexpr bool pair = sizeof(T) == 8 && VC % 2 == 0;
+  static constexpr int y = VC + 1;
+  static constexpr int f = pair ? VC + 2 : VC + 1;
+};
+
+// One variant of a tile: p = L~ y + F~ and the running maximum of |p| (two
+// maxima, even and odd row blocks, halve the dependent chain).
+template <typename T, int RB, int NB>
+__device__ __forceinline__ T sweep_variant(const T (&L)[RB][NB][4], const T (&fr)[RB][4],
+                                           const T (&yc)[NB], T m) {
+  T m0 = m, m1 = (T)0;
+#pragma unroll
+  for (int a = 0; a < RB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; r += 2) {
+        const T p0 = tfma(L[a][b][r], yc[b], fr[a][r]);
+        const T p1 = tfma(L[a][b][r + 1], yc[b], fr[a][r + 1]);
+        if (a % 2 == 0)
+          m0 = absmax3(m0, p0, p1);
+        else
+          m1 = absmax3(m1, p0, p1);
+      }
+  return tmax(m0, m1);
+}
 // Item (cand, band): maxima of the band's N-0 rows and of its N-1 rows against
 // every contingency, for the VC variants of blockIdx.y, merged into vmax by
 // atomic maxima (vmax is cleared by k_clear first).
 template <typename T, int VC>
 __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int band) {
   constexpr int RB = ScanCfg<T>::RB, TM = 16 * RB, TN = ScanCfg<T>::TN, NB = TN / 16;
-  // y and F~ are stored variant-minor with a stride of VC + 1 (an odd number of
-  // elements: the 16 columns and the 4 row groups a read instruction touches fall
-  // in different banks), so that every read of the variant loop is one base
-  // address per tile plus a compile-time offset
-  constexpr int VS = VC + 1;
+  // y and F~ are stored variant-minor (strides VStride), so that every read of the
+  // variant loop is one base address per tile plus a compile-time offset
+  constexpr int VS = VStride<T, VC>::y, VF = VStride<T, VC>::f;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int ld_o = A.ld_o, rchunk = A.rchunk;
   T *ys = reinterpret_cast<T *>(smem_raw);  // [ld_o][VS]
-  T *fs = ys + (size_t)VS * ld_o;           // [rchunk][VS]
+  T *fs = ys + (size_t)VS * ld_o;           // [rchunk][VF] (ld_o even: 16-byte aligned)
   __shared__ double s_red[4][VC];
   __shared__ int s_nfm;  // bit vi: a non-finite flow of variant vi was read
 
@@ -451,7 +482,7 @@ __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int b
       T fv[VC];
 #pragma unroll
       for (int vi = 0; vi < VC; ++vi) fv[vi] = (on && vi < nv) ? F[(size_t)vi * A.ld_f + row] : (T)0;
-      T *dst = fs + (size_t)fs_pos(fs, rr) * VS;
+      T *dst = fs + (size_t)fs_pos(fs, rr) * VF;
 #pragma unroll
       for (int vi = 0; vi < VC; ++vi) {
         if (!finite_bits((double)fv[vi])) nfm |= 1u << vi;
@@ -468,36 +499,44 @@ __device__ __forceinline__ void scan_max_item(const ScanArgs &A, int cand, int b
       const int rowbase = rc0 + tr * TM, colbase = tc * TN;
       T L[RB][NB][4];
       build_tile(L, A, e0, k, rowbase, colbase, g, li, lane);
-      const T *fsb = fs + (size_t)((rowbase - rc0) + 4 * g) * VS;
+      const T *fsb = fs + (size_t)((rowbase - rc0) + 4 * g) * VF;
       const T *ysb = ys + (size_t)(colbase + li) * VS;
+      if constexpr (VStride<T, VC>::pair) {
+        // FP64: two variants per 16-byte read
 #pragma unroll
-      for (int vi = 0; vi < VC; ++vi) {
-        // FP32 keeps a branch per variant: without it the hoisted LDS reads of the
-        // 16 variants overflow its 128-register budget (four waves per SIMD)
-        if (sizeof(T) == 4 && vi >= nv) continue;
-        T fr[RB][4], yc[NB];
+        for (int vp = 0; vp < VC; vp += 2) {
+          T fr[2][RB][4], yc[2][NB];
 #pragma unroll
-        for (int a = 0; a < RB; ++a)
+          for (int a = 0; a < RB; ++a)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) fr[a][r] = fsb[(a * 16 + r) * VS + vi];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) yc[b] = ysb[b * 16 * VS + vi];
-        // two running maxima (even and odd row blocks) halve the dependent chain
-        T m0 = mx[vi], m1 = (T)0;
-#pragma unroll
-        for (int a = 0; a < RB; ++a)
-#pragma unroll
-          for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int r = 0; r < 4; r += 2) {
-              const T p0 = tfma(L[a][b][r], yc[b], fr[a][r]);
-              const T p1 = tfma(L[a][b][r + 1], yc[b], fr[a][r + 1]);
-              if (a % 2 == 0)
-                m0 = absmax3(m0, p0, p1);
-              else
-                m1 = absmax3(m1, p0, p1);
+            for (int r = 0; r < 4; ++r) {
+              const double2 q = *reinterpret_cast<const double2 *>(&fsb[(a * 16 + r) * VF + vp]);
+              fr[0][a][r] = q.x;
+              fr[1][a][r] = q.y;
             }
-        mx[vi] = tmax(m0, m1);
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            yc[0][b] = ysb[b * 16 * VS + vp];
+            yc[1][b] = ysb[b * 16 * VS + vp + 1];
+          }
+          mx[vp] = sweep_variant(L, fr[0], yc[0], mx[vp]);
+          mx[vp + 1] = sweep_variant(L, fr[1], yc[1], mx[vp + 1]);
+        }
+      } else {
+#pragma unroll
+        for (int vi = 0; vi < VC; ++vi) {
+          // FP32 keeps a branch per variant: without it the hoisted LDS reads of the
+          // 16 variants overflow its 128-register budget (four waves per SIMD)
+          if (sizeof(T) == 4 && vi >= nv) continue;
+          T fr[RB][4], yc[NB];
+#pragma unroll
+          for (int a = 0; a < RB; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) fr[a][r] = fsb[(a * 16 + r) * VF + vi];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) yc[b] = ysb[b * 16 * VS + vi];
+          mx[vi] = sweep_variant(L, fr, yc, mx[vi]);
+        }
       }
     }
   }
@@ -1929,10 +1968,11 @@ inline int grid_x(const dcflow_batch *bt, const ScanArgs &a) {
 template <typename T, int VC, int MINW>
 hipError_t launch_max(const ScanArgs &a0, const dcflow_batch *bt, int nvar, hipStream_t s) {
   ScanArgs a = a0;
-  constexpr int VS = VC + 1;  // variant-minor LDS rows (see scan_max_item)
+  // variant-minor LDS rows (see scan_max_item)
+  constexpr int VS = VStride<T, VC>::y, VF = VStride<T, VC>::f;
   const size_t fixed = sizeof(T) * (size_t)VS * a.ld_o;
-  choose_rows(bt, fixed, sizeof(T) * VS, a.mon_pad, a.ld_o, sizeof(T), kLdsOccupancy, a);
-  const size_t lds = fixed + sizeof(T) * (size_t)VS * a.rchunk;
+  choose_rows(bt, fixed, sizeof(T) * VF, a.mon_pad, a.ld_o, sizeof(T), kLdsOccupancy, a);
+  const size_t lds = fixed + sizeof(T) * (size_t)VF * a.rchunk;
   if (lds > lds_budget(bt, VC, sizeof(T))) return hipErrorInvalidValue;
   const int ny = (nvar + VC - 1) / VC;
   if (ny > kQueueWin) a.persistent = 0;  // one counter per variant group
