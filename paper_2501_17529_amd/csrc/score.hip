@@ -1036,7 +1036,7 @@ __device__ __forceinline__ void scan_colmax_item(const ScanArgs &A, int cand, in
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_scan_colmax(ScanArgs A) {
+__global__ void __launch_bounds__(256, 4) k_scan_colmax(ScanArgs A) {
   for_each_item(A, kQueueWin, [&](int cand, int band) __attribute__((always_inline)) { scan_colmax_item<T>(A, cand, band); });
 }
 
@@ -2120,7 +2120,7 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   a.nbt = a.nbands + a.nmb + a.ng;
   const size_t lds = fixed + sizeof(T) * (size_t)a.rchunk;
   if (lds > kLdsBudget) return hipErrorInvalidValue;
-  k_scan_win<T, sizeof(T) == 4 ? 4 : 1><<<dim3(grid_x(bt, a)), dim3(256), lds, s>>>(a);
+  k_scan_win<T, sizeof(T) == 4 ? 4 : 3><<<dim3(grid_x(bt, a)), dim3(256), lds, s>>>(a);
   DCF_CHECK_LAUNCH();
   if (a.nmb > 0) {
     k_scan_multi<T, 1, 1><<<dim3((unsigned)((size_t)a.n_cand * a.nmb)), dim3(256), 0, s>>>(a);
