@@ -393,8 +393,10 @@ int dcflow_n1_worst_per_case_workspace_bytes(const dcflow_batch *batch, int32_t 
  * outage and multi-outage case; over the monitored branches), then the top_k of
  * that collection, so that no single case fills the list.  Same winner, order,
  * ids and output layout as dcflow_n1_worst; with per_case >= top_k it returns the
- * same cases (loads to rounding: these kernels build each LODF' entry with FMAs
- * instead of the matrix cores).  per_case in 1..DCFLOW_WORST_MAX; dev_ws:
+ * same cases (with one row band, loads bit for bit except the FP32 scan's guarded
+ * columns and the multi-outage cases, which are summed in another order; with
+ * several bands every entry is built by k FMAs, equal to rounding).  per_case in
+ * 1..DCFLOW_WORST_MAX; dev_ws:
  * dcflow_n1_worst_per_case_workspace_bytes bytes.  Errors as dcflow_n1_worst. */
 int dcflow_n1_worst_per_case(dcflow_batch *batch, const void *dev_flows, int32_t n_var,
                              dcflow_prec prec, const dcflow_score *dev_scores, int32_t per_case,

@@ -4,14 +4,16 @@
 // A global top-k would let one dominant outage fill the whole list; the per-case
 // cap keeps the other cases visible.
 //
-// Level 1 runs one thread per case, walking the monitored rows: an LODF' entry is
-// Lsd[row, c] + (U / r)[row, :] W[:, c] (k FMAs), the N-1 flow F~ + L~ y_c, and the
-// thread keeps a sorted list of its case's largest |p~|.  Neighbouring threads
-// hold neighbouring columns, so the seed reads coalesce; U / r and F~ of a row are
-// the same address for the whole wave.  Multi-outage cases use their per-case
-// coefficients z = coef p1[S] and sum the m entries of their branches.  Level 2
-// runs one workgroup per candidate: each thread takes the top_k of its cases'
-// lists, then the block merges the thread lists one entry per round.
+// With one row band, level 1 starts from the column-maximum sweep of the
+// worst-case pass: only the hot columns (at most top_k of them) can place an entry
+// in the result, and k_scan_hot builds their per-case lists on the tiles'
+// arithmetic.  k_pc_sel adds the N-0 case and the columns that the FP32 scan's
+// error guard computes in FP64 (one wave per case, rows over the lanes), and
+// k_pc_multi the multi-outage cases (coefficients z = coef p1[S], the m entries of
+// their branches summed).  Otherwise k_pc_cols walks every case, one thread each:
+// an LODF' entry is Lsd[row, c] + (U / r)[row, :] W[:, c] (k FMAs), the N-1 flow
+// F~ + L~ y_c, and a sorted list of the case's largest |p~|.  Level 2 (k_pc_fin)
+// takes the top_k of the lists per candidate.
 #include "percase.h"
 
 namespace dcflow {
