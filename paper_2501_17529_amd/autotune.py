@@ -37,8 +37,9 @@ def _arch() -> str:
 def shape_key(batch: "D.Batch", n_var: int, prec: str) -> str:
     v = batch.plan.view
     kmax = int(np.max(np.diff(batch.ca.off))) if batch.n_cand else 0
+    rec = 1 if batch.get_tuning().get("worst_record") else 0
     return (f"{_arch()}|{prec}|n_cand={batch.n_cand}|n_var={n_var}|n_mon={v.n_mon}|"
-            f"n_out={v.n_out}|ld_o={v.ld_o}|n_multi={v.n_multi_out}|kmax={kmax}")
+            f"n_out={v.n_out}|ld_o={v.ld_o}|n_multi={v.n_multi_out}|kmax={kmax}|rec={rec}")
 
 
 def _load(path):
@@ -98,13 +99,15 @@ def tune_scan(batch: "D.Batch", flows, n_var: int, prec: str, reps: int = 10,
     path = cache_path()
     key = shape_key(batch, n_var, prec)
     cache = _load(path) if use_cache else {}
+    # the batch's other settings (step chunks, the record, the guard) are kept
+    base = batch.get_tuning()
     if key in cache:
         cfg = cache[key]["config"]
-        batch.set_tuning(**cfg)
+        batch.set_tuning(**dict(base, **cfg))
         return cfg, cache[key].get("times_ms", {})
     nb = max(batch.n_cand, 1) * D.SCORE_DTYPE.itemsize
     ref_out = torch.empty(nb, dtype=torch.uint8, device="cuda")
-    batch.set_tuning()
+    batch.set_tuning(**dict(base, scan_vc=0, scan_rchunk=0, persistent=0, scan_band=0))
     batch.n1_score(flows, n_var, prec, out=ref_out)
     torch.cuda.synchronize()
     ref = D.Batch.scores_to_numpy(ref_out, batch.n_cand)
@@ -112,7 +115,7 @@ def tune_scan(batch: "D.Batch", flows, n_var: int, prec: str, reps: int = 10,
     times = {}
     best, best_t = None, float("inf")
     for cfg in candidates(batch, n_var, prec):
-        batch.set_tuning(**cfg)
+        batch.set_tuning(**dict(base, **cfg))
         try:
             t = _time_scan(batch, flows, n_var, prec, out, reps)
         except D.DcflowError:
@@ -132,7 +135,7 @@ def tune_scan(batch: "D.Batch", flows, n_var: int, prec: str, reps: int = 10,
             best, best_t = cfg, t
     if best is None:
         best = dict(scan_vc=0, scan_rchunk=0, persistent=0, scan_band=0)
-    batch.set_tuning(**best)
+    batch.set_tuning(**dict(base, **best))
     if use_cache:
         cache = _load(path)
         cache[key] = {"config": best, "times_ms": times}

@@ -248,6 +248,15 @@ void batch_layout(dcflow_batch *b, const dcflow_plan *p, const BatchDims &d, Are
   b->d_part_nf = a.take<int32_t>(np);
   b->d_mcoef = a.take<double>(nc * (size_t)p->n_multi * 16);
   b->d_mok = a.take<int32_t>(nc * (size_t)p->n_multi);
+  // the winner pass's column-maximum record, for plans whose worst-case pass has
+  // one row band
+  if (case_maxima_supported(p)) {
+    b->d_rec = a.take<double>(nc * (size_t)(p->ld_o + 1));
+    b->d_rec_var = a.take<int32_t>(nc);
+  } else {
+    b->d_rec = nullptr;
+    b->d_rec_var = nullptr;
+  }
 }
 
 // Candidate records against the grid (element kinds, ids, split masks, ranks).
@@ -558,9 +567,15 @@ int dcflow_batch_create(dcflow_plan *p, const dcflow_cands *c, int32_t n_var_max
   b->flows_prec = -1;
   b->flows_nvar = 0;
   b->guard_valid = 0;
+  b->rec_valid = 0;
+  b->rec_prec = -1;
+  b->rec_nvar = 0;
+  b->rec_flows = nullptr;
+  b->rec_scores = nullptr;
+  b->graph_state = dcflow_batch::StepState{};
   b->d_pnv = nullptr;
   b->pnv_nvar = 0;
-  b->tune = dcflow_tuning{0, 0, 0, 0, 0, 0.0};
+  b->tune = dcflow_tuning{0, 0, 0, 0, 0, 0, 0.0};
   b->aux = nullptr;
   for (int i = 0; i <= kMaxStepChunks; ++i) b->step_ev[i] = nullptr;
   b->max_bands = p->mon_pad / 64;
@@ -651,6 +666,7 @@ int run_step(dcflow_batch *b, const double *inj, int nvar, int shared, int prec,
   if (e != hipSuccess) return hip_fail(e, "dcflow_step");
   b->factored = 1;
   b->guard_valid = 0;
+  b->rec_valid = 0;
   int nch = b->tune.step_chunks;
   if (shared || nch > b->n_cand) nch = shared ? 1 : b->n_cand;
   if (nch <= 1) {
@@ -690,7 +706,7 @@ int check_step(dcflow_batch *b, const double *dev_inj, int32_t n_var, dcflow_pre
 int dcflow_batch_set_tuning(dcflow_batch *b, const dcflow_tuning *t) {
   if (!b || !t) return DCFLOW_E_ARG;
   if (t->scan_vc < 0 || t->scan_rchunk < 0 || t->scan_rchunk % 64 || t->persistent < 0 ||
-      t->scan_band < 0 || t->scan_band % 64 || t->step_chunks < 0 ||
+      t->scan_band < 0 || t->scan_band % 64 || t->step_chunks < 0 || t->worst_record < 0 ||
       t->step_chunks > kMaxStepChunks || !std::isfinite(t->guard_tol))
     return DCFLOW_E_ARG;
   if (t->step_chunks > 1) {
@@ -740,13 +756,28 @@ int dcflow_graph_capture(dcflow_batch *b, const double *dev_inj, int32_t n_var,
   }
   b->graph = g;
   b->graph_exec = x;
+  b->graph_state = dcflow_batch::StepState{b->factored,  b->flows_prec, b->flows_nvar,
+                                            b->guard_valid, b->rec_valid, b->rec_prec,
+                                            b->rec_nvar,   b->rec_flows,  b->rec_scores};
   return DCFLOW_OK;
 }
 
 int dcflow_graph_launch(dcflow_batch *b, hipStream_t s) {
   if (!b || !b->graph_exec) return DCFLOW_E_ARG;
   hipError_t e = hipGraphLaunch(b->graph_exec, s);
-  return e == hipSuccess ? DCFLOW_OK : hip_fail(e, "dcflow_graph_launch");
+  if (e != hipSuccess) return hip_fail(e, "dcflow_graph_launch");
+  // the replayed step leaves the batch as the captured one did
+  const dcflow_batch::StepState &g = b->graph_state;
+  b->factored = g.factored;
+  b->flows_prec = g.flows_prec;
+  b->flows_nvar = g.flows_nvar;
+  b->guard_valid = g.guard_valid;
+  b->rec_valid = g.rec_valid;
+  b->rec_prec = g.rec_prec;
+  b->rec_nvar = g.rec_nvar;
+  b->rec_flows = g.rec_flows;
+  b->rec_scores = g.rec_scores;
+  return DCFLOW_OK;
 }
 
 int dcflow_eval_topologies(dcflow_batch *b, hipStream_t s) {
@@ -755,6 +786,7 @@ int dcflow_eval_topologies(dcflow_batch *b, hipStream_t s) {
   if (e != hipSuccess) return hip_fail(e, "dcflow_eval_topologies");
   b->factored = 1;
   b->guard_valid = 0;
+  b->rec_valid = 0;
   return DCFLOW_OK;
 }
 
@@ -784,6 +816,7 @@ int dcflow_eval_injections(dcflow_batch *b, const double *dev_inj, int32_t n_var
   if (e != hipSuccess) return hip_fail(e, "dcflow_eval_injections");
   b->flows_prec = prec;
   b->guard_valid = 0;
+  b->rec_valid = 0;
   b->flows_nvar = n_var;
   return DCFLOW_OK;
 }

@@ -142,6 +142,25 @@ struct dcflow_batch {
   int flows_nvar;
   int guard_valid;  // d_flag / d_nflag describe the current flows (set by an FP32
                     // n1_score with the guard on, cleared by a new evaluation)
+  // column-maximum record of the winner pass (tune.worst_record, plans whose
+  // worst-case pass has one row band): per candidate the winner's maxima over
+  // the monitored rows of every scored contingency column (0 for the others),
+  // then its N-0 maximum, in the scan's element type, and the variant they
+  // describe; n1_worst and n1_worst_per_case read them instead of sweeping the
+  // winner's tiles again when called with the flows and score records of the
+  // n1_score call that wrote them
+  void *d_rec;         // [n_cand][ld_o + 1] (8-byte slots), or null
+  int32_t *d_rec_var;  // [n_cand]
+  int rec_valid;       // set by n1_score with the record on, cleared by a new evaluation
+  int rec_prec, rec_nvar;
+  const void *rec_flows;
+  const void *rec_scores;
+  // the host-side state a captured step leaves (restored on each replay)
+  struct StepState {
+    int factored, flows_prec, flows_nvar, guard_valid, rec_valid, rec_prec, rec_nvar;
+    const void *rec_flows;
+    const void *rec_scores;
+  } graph_state;
 };
 
 // Returns the launch error of the kernel just enqueued (HIP's last-error slot is

@@ -157,6 +157,14 @@ struct ScanArgs {
   const uint32_t *flag;         // [n_cand][ld_o / 32] columns computed in FP64 instead
   const int32_t *nflag;         // [n_cand] their number
   int ng;                       // 1: the last partial slot holds the guarded columns
+  // column-maximum record of the winner (see dcflow_batch::d_rec): [n_cand][ld_o + 1] T
+  void *rec = nullptr;          // k_scan_win writes it, k_scan_colmax may read it
+  int32_t *rec_var = nullptr;   // [n_cand] the variant each candidate's record describes
+  int rec_atomic = 0;           // k_scan_win: several bands per candidate accumulate their
+                                // maxima (the record was cleared first)
+  int rec_use = 0;              // k_scan_colmax: take the maxima of the candidates whose
+                                // record names their winner
+  int rec_sel = 0;              // k_rec_select has done those candidates already
 };
 
 constexpr int kQueueWin = 15;  // counter slot of pass 2
@@ -193,6 +201,9 @@ __device__ __forceinline__ void for_each_item(const ScanArgs &A, int slot, F bod
 // like the values)
 __device__ __forceinline__ void global_max_nonneg(double *p, double v) {
   atomicMax(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
+}
+__device__ __forceinline__ void global_max_nonneg(float *p, float v) {
+  atomicMax(reinterpret_cast<unsigned int *>(p), __float_as_uint(v));
 }
 
 template <typename T>
@@ -567,7 +578,13 @@ __global__ void __launch_bounds__(256, MINW) k_scan_max(ScanArgs A) {
 // as partials that k_scan_fin combines.  Per lane: the running maximum, the
 // first tile reaching it and whether a later tile reached it again; only the
 // tiles where a lane first reached the band maximum are built again for the key.
-template <typename T>
+// The tiles of a chunk are visited column tile first, so that a wave's consecutive
+// tiles share their columns.
+//   REC: the item also records the winner's column maxima over the band's rows and
+//   its N-0 maximum (A.rec): each lane keeps the maxima of its 4 columns in
+//   registers and adds them to the block's LDS maxima only when its column tile
+//   changes.  The tile values are those of every other sweep.
+template <typename T, bool REC>
 __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int band) {
   constexpr int RB = ScanCfg<T>::RB, TM = 16 * RB, TN = ScanCfg<T>::TN, NB = TN / 16;
   constexpr long long kNoKey = 0x7fffffffffffffffLL;
@@ -576,6 +593,7 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
   T *ys = reinterpret_cast<T *>(smem_raw);  // [ld_o]
   T *colw = ys + ld_o;                      // [ld_o] 1 for scored contingencies
   T *fs = colw + ld_o;                      // [rchunk]
+  T *cmx = fs + rchunk;                     // REC: [ld_o] the band's column maxima
   __shared__ double s_m0[4], s_m1[4], s_ov[4];
   __shared__ long long s_key[4];
   __shared__ int s_nf, s_vstar;
@@ -613,8 +631,21 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
     const bool valid =
         c < A.n_ctg && !gd && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
     colw[c] = valid ? (T)1 : (T)0;
+    if (REC) cmx[c] = (T)0;
   }
   const int r0 = band * A.band_rows, r1 = min(r0 + A.band_rows, A.mon_pad);
+  // REC: the lane's maxima of its columns of column tile acc_tc (wave-uniform)
+  T cacc[NB];
+  int acc_tc = -1;
+  auto rec_flush = [&]() __attribute__((always_inline)) {
+    if (acc_tc >= 0) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int c = acc_tc * TN + b * 16 + li;
+        if (colw[c] != (T)0) lds_max_nonneg(&cmx[c], cacc[b]);
+      }
+    }
+  };
 
   // N-0 rows of the band: maximum and the lowest row attaining it
   T b0 = (T)-1;
@@ -643,9 +674,11 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
     }
     __syncthreads();
 
-    const int nt = (rows / TM) * ntc;
+    const int ntr = rows / TM, nt = ntr * ntc;
     for (int tile = wv; tile < nt; tile += 4) {
-      const int tr = tile / ntc, tc = tile - tr * ntc;
+      // column tile first (with or without the record, so that the overload sums
+      // add the same tiles in the same order)
+      const int tc = tile / ntr, tr = tile - tc * ntr;
       const int rowbase = rc0 + tr * TM, colbase = tc * TN;
       const int tid_tile = (rowbase / TM) * ntc + tc;
       T L[RB][NB][4];
@@ -659,7 +692,9 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
 #pragma unroll
       for (int b = 0; b < NB; ++b) yc[b] = ys[colbase + b * 16 + li];
       T pv[RB][NB][4];
-      T mt = (T)0;
+      T mt = (T)0, cm[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) cm[b] = (T)0;
 #pragma unroll
       for (int a = 0; a < RB; ++a)
 #pragma unroll
@@ -668,8 +703,21 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
           for (int r = 0; r < 4; r += 2) {
             pv[a][b][r] = tfma(L[a][b][r], yc[b], fr[a][r]);
             pv[a][b][r + 1] = tfma(L[a][b][r + 1], yc[b], fr[a][r + 1]);
-            mt = absmax3(mt, pv[a][b][r], pv[a][b][r + 1]);
+            if (REC)
+              cm[b] = absmax3(cm[b], pv[a][b][r], pv[a][b][r + 1]);
+            else
+              mt = absmax3(mt, pv[a][b][r], pv[a][b][r + 1]);
           }
+      if (REC) {
+        const bool same = tc == acc_tc;
+        if (!same) rec_flush();
+        acc_tc = tc;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          cacc[b] = same ? tmax(cacc[b], cm[b]) : cm[b];
+          mt = tmax(mt, cm[b]);
+        }
+      }
       const bool gt = mt > run;
       tie = gt ? 0 : (mt == run ? 1 : tie);
       first = gt ? tid_tile : first;
@@ -695,6 +743,8 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
     }
   }
 
+  if (REC) rec_flush();
+
   // ---- band maxima over the block
   {
     const T w0 = wave_max(b0), w1 = wave_max(run);
@@ -709,6 +759,20 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
   __syncthreads();
   const T M0 = (T)fmax(fmax(s_m0[0], s_m0[1]), fmax(s_m0[2], s_m0[3]));
   const T M1 = (T)fmax(fmax(s_m1[0], s_m1[1]), fmax(s_m1[2], s_m1[3]));
+  if (REC) {
+    // the LDS maxima are complete after the barrier above
+    T *rec = static_cast<T *>(A.rec) + (size_t)cand * (ld_o + 1);
+    const T n0 = M0 > (T)0 ? M0 : (T)0;
+    if (A.rec_atomic) {
+      for (int c = tid; c < ld_o; c += blockDim.x)
+        if (cmx[c] > (T)0) global_max_nonneg(&rec[c], cmx[c]);
+      if (tid == 0) global_max_nonneg(&rec[ld_o], n0);
+    } else {
+      for (int c = tid; c < ld_o; c += blockDim.x) rec[c] = cmx[c];
+      if (tid == 0) rec[ld_o] = n0;
+    }
+    if (tid == 0 && band == 0) A.rec_var[cand] = vstar;
+  }
 
   // ---- lowest key attaining the band maximum
   long long bestk = kNoKey;
@@ -775,9 +839,9 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
   }
 }
 
-template <typename T, int MINW>
+template <typename T, int MINW, bool REC>
 __global__ void __launch_bounds__(256, MINW) k_scan_win(ScanArgs A) {
-  for_each_item(A, kQueueWin, [&](int cand, int band) __attribute__((always_inline)) { scan_win_item<T>(A, cand, band); });
+  for_each_item(A, kQueueWin, [&](int cand, int band) __attribute__((always_inline)) { scan_win_item<T, REC>(A, cand, band); });
 }
 
 // One thread per candidate: combines the band partials into the score record.
@@ -841,6 +905,15 @@ __global__ void k_scan_fin(ScanArgs A) {
   if (A.single) A.vmax[(size_t)cand * A.vmax_ld] = r.max_load;
 }
 
+// Zeroes n 32-bit words (a kernel, so that a captured graph clears them too).
+__global__ void k_zero32(uint32_t *p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// Whether n1_score writes the column-maximum record (see dcflow_batch::d_rec).
+inline bool record_on(const dcflow_batch *bt) { return bt->tune.worst_record != 0 && bt->d_rec; }
+
 // Clears the work-queue counters and the per-variant maxima (a kernel, so that a
 // captured graph clears them too).
 __global__ void k_clear(int32_t *q, int nq, double *vmax, size_t n) {
@@ -890,8 +963,6 @@ __device__ __forceinline__ void scan_colmax_item(const ScanArgs &A, int cand, in
   T *colw = ys + ld_o;                      // [ld_o]
   T *fs = colw + ld_o;                      // [rchunk]
   T *cmx = fs + rchunk;                     // [ld_o] column maxima of the band
-  __shared__ T s_bv[4];
-  __shared__ int s_bi[4];
   __shared__ T s_n0max;
 
   const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, g = lane / 16, li = lane % 16;
@@ -909,20 +980,26 @@ __device__ __forceinline__ void scan_colmax_item(const ScanArgs &A, int cand, in
     return;
   }
   const T *Fv = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + sc.best_variant) * A.ld_f;
+  // the winner pass's record of this winner holds the maxima already
+  const bool from_rec = A.rec_use && A.rec_var[cand] == sc.best_variant;
+  if (from_rec && A.rec_sel) return;
+  const T *rec = from_rec ? static_cast<const T *>(A.rec) + (size_t)cand * (ld_o + 1) : nullptr;
   bool nf = false;
   for (int c = tid; c < ld_o; c += blockDim.x) {
-    const T y = ycol(Fv, A, cand, c, nf);
     const bool gd = guarded(A, cand, c);
-    ys[c] = gd ? (T)0 : y;
+    if (!from_rec) {
+      const T y = ycol(Fv, A, cand, c, nf);
+      ys[c] = gd ? (T)0 : y;
+    }
     const bool valid =
         c < A.n_ctg && !gd && !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
     colw[c] = valid ? (T)1 : (T)0;
-    cmx[c] = (T)0;
+    cmx[c] = from_rec ? rec[c] : (T)0;
   }
-  if (tid == 0) s_n0max = (T)0;
+  if (tid == 0) s_n0max = from_rec ? rec[ld_o] : (T)0;
   const int r0 = band * A.band_rows, r1 = min(r0 + A.band_rows, A.mon_pad);
   const int ntc = ld_o / TN;
-  for (int rc0 = r0; rc0 < r1; rc0 += rchunk) {
+  for (int rc0 = r0; rc0 < (from_rec ? r0 : r1); rc0 += rchunk) {
     const int rows = min(rchunk, r1 - rc0);
     __syncthreads();
     for (int rr = tid; rr < rows; rr += blockDim.x) {
@@ -962,16 +1039,21 @@ __device__ __forceinline__ void scan_colmax_item(const ScanArgs &A, int cand, in
     }
   }
   __syncthreads();
-  // tau: top_k rounds of "the largest after the previous one" (ties by index; the
-  // N-0 maximum is index ld_o); -1 when there are fewer values than top_k
+  // The selection is one wave's (k_scan_colmax runs one item per workgroup and no
+  // barrier follows); lane l holds the values of columns l, l + 64, ... and the
+  // N-0 maximum is index ld_o.
+  if (wv != 0) return;
+  const T n0 = s_n0max;
+  // tau: top_k rounds of "the largest after the previous one" (ties by index); -1
+  // when there are fewer values than top_k
   T prev = (T)0;
   int prev_i = -1;
   bool any = true;
   for (int j = 0; j < A.top_k && any; ++j) {
     T bv = (T)-1;
     int bi = 0x7fffffff;
-    for (int c = tid; c <= ld_o; c += blockDim.x) {
-      const T v = c < ld_o ? (colw[c] != (T)0 ? cmx[c] : (T)-1) : s_n0max;
+    for (int c = lane; c <= ld_o; c += kWave) {
+      const T v = c < ld_o ? (colw[c] != (T)0 ? cmx[c] : (T)-1) : n0;
       const bool after = j == 0 || v < prev || (v == prev && c > prev_i);
       if (v >= (T)0 && after && (v > bv || (v == bv && c < bi))) {
         bv = v;
@@ -987,49 +1069,36 @@ __device__ __forceinline__ void scan_colmax_item(const ScanArgs &A, int cand, in
         bi = oi;
       }
     }
-    if (lane == 0) {
-      s_bv[wv] = bv;
-      s_bi[wv] = bi;
-    }
-    __syncthreads();
-    T wbv = s_bv[0];
-    int wbi = s_bi[0];
-#pragma unroll
-    for (int w = 1; w < 4; ++w)
-      if (s_bv[w] > wbv || (s_bv[w] == wbv && s_bi[w] < wbi)) {
-        wbv = s_bv[w];
-        wbi = s_bi[w];
-      }
-    __syncthreads();
-    any = wbv >= (T)0;
-    prev = wbv;
-    prev_i = wbi;
+    any = bv >= (T)0;
+    prev = bv;
+    prev_i = bi;
   }
   const double tau = any ? (double)prev : -1.0;
-  if (tid == 0) A.tau[(size_t)cand * A.nbands + band] = tau;
+  if (lane == 0) A.tau[(size_t)cand * A.nbands + band] = tau;
   // The hot columns: the scored columns among the top_k of that order (all scored
-  // ones when there are fewer values).  Any other column's entries come after
-  // top_k distinct entries of the band (the chosen column maxima and N-0 maximum)
-  // in the order of the lists (load descending, key ascending; a column's keys
-  // grow with its index and the N-0 keys come first), in either kind of list: the
-  // band's top_k, or the top_k of the per-case lists.
+  // ones when there are fewer values), in increasing order.  Any other column's
+  // entries come after top_k distinct entries of the band (the chosen column
+  // maxima and N-0 maximum) in the order of the lists (load descending, key
+  // ascending; a column's keys grow with its index and the N-0 keys come first),
+  // in either kind of list: the band's top_k, or the top_k of the per-case lists.
   if (A.hotl) {
-    __shared__ int s_nh;
     int32_t *hl = A.hotl + ((size_t)cand * A.nbands + band) * kHotLd;
-    if (tid == 0) s_nh = 0;
-    __syncthreads();
-    for (int c = tid; c < ld_o; c += blockDim.x)
-      if (colw[c] != (T)0 && (!any || cmx[c] > prev || (cmx[c] == prev && c <= prev_i))) {
-        const int q = atomicAdd(&s_nh, 1);
-        if (q < DCFLOW_WORST_MAX) hl[1 + q] = c;
-      }
-    __syncthreads();
-    if (tid == 0) hl[0] = min(s_nh, DCFLOW_WORST_MAX);
+    int nh = 0;
+    for (int c0 = 0; c0 < ld_o; c0 += kWave) {
+      const int c = c0 + lane;
+      const bool hot = c < ld_o && colw[c] != (T)0 &&
+                       (!any || cmx[c] > prev || (cmx[c] == prev && c <= prev_i));
+      const unsigned long long m = __ballot(hot);
+      const int pos = nh + __popcll(m & ((1ull << lane) - 1ull));
+      if (hot && pos < DCFLOW_WORST_MAX) hl[1 + pos] = c;
+      nh += __popcll(m);
+    }
+    if (lane == 0) hl[0] = min(nh, DCFLOW_WORST_MAX);
   }
   if (co) {
-    for (int c = tid; c < ld_o; c += blockDim.x) co[c] = colw[c] != (T)0 ? (double)cmx[c] : -1.0;
-    if (tid == 0) {
-      co[ld_o] = (double)s_n0max;
+    for (int c = lane; c < ld_o; c += kWave) co[c] = colw[c] != (T)0 ? (double)cmx[c] : -1.0;
+    if (lane == 0) {
+      co[ld_o] = (double)n0;
       co[ld_o + 1] = tau;
     }
   }
@@ -1038,6 +1107,185 @@ __device__ __forceinline__ void scan_colmax_item(const ScanArgs &A, int cand, in
 template <typename T>
 __global__ void __launch_bounds__(256, 4) k_scan_colmax(ScanArgs A) {
   for_each_item(A, kQueueWin, [&](int cand, int band) __attribute__((always_inline)) { scan_colmax_item<T>(A, cand, band); });
+}
+
+// The candidates whose column-maximum record names their winner (one band): the
+// selection of scan_colmax_item straight from the record, one wave per candidate
+// with the values in registers (lane l: columns l, l + 64, ..., at most 64 NJ;
+// the N-0 maximum is index ld_o, lane 0's).  Same tau, hot columns and case
+// maxima; the other candidates are left to k_scan_colmax.
+//   tau by ranking instead of top_k rounds: the top_k-th of the 64 lane maxima, e,
+// is at or before tau in the order (top_k distinct values reach it), so only the
+// values at or before e (the survivors, at least top_k) can be tau; each survivor
+// counts the survivors before it, and the one with top_k - 1 before it is tau.
+// With fewer than top_k lane maxima every value survives.  (More than kSurv
+// survivors: the rounds.)
+template <typename T, int NJ>
+__global__ void __launch_bounds__(256) k_rec_select(ScanArgs A) {
+  constexpr int kSurv = 256;
+  __shared__ T s_v[4][kSurv];
+  __shared__ int s_i[4][kSurv];
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int cand = blockIdx.x * (blockDim.x / kWave) + wv;
+  if (cand >= A.n_cand) return;
+  const dcflow_score sc = A.scores[cand];
+  const bool skip = (sc.status & (DCFLOW_ST_DISCONNECTED | DCFLOW_ST_NONFINITE)) != 0 ||
+                    sc.best_variant < 0 || sc.best_variant >= A.nvar;
+  if (skip || A.rec_var[cand] != sc.best_variant) return;  // wave-uniform
+  const int ld_o = A.ld_o, top_k = A.top_k;
+  const T *rec = static_cast<const T *>(A.rec) + (size_t)cand * (ld_o + 1);
+  // the scored columns' maxima, -1 elsewhere
+  T v[NJ];
+#pragma unroll
+  for (int q = 0; q < NJ; ++q) {
+    const int c = lane + kWave * q;
+    const bool valid = c < A.n_ctg && !guarded(A, cand, c) &&
+                       !((A.isl[(size_t)cand * (ld_o / 32) + c / 32] >> (c % 32)) & 1u);
+    v[q] = valid ? rec[c] : (T)-1;
+  }
+  const T n0 = rec[ld_o];
+  auto val = [&](int q) __attribute__((always_inline)) {
+    return q < NJ ? v[q] : (lane == 0 ? n0 : (T)-1);
+  };
+  auto idx = [&](int q) __attribute__((always_inline)) { return q < NJ ? lane + kWave * q : ld_o; };
+  auto wave_sync = []() __attribute__((always_inline)) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  T *sv = s_v[wv];
+  int *si = s_i[wv];
+
+  // the lane's best value, its place among the 64, and the threshold e
+  T lm = (T)-1;
+  int lmi = 0x7fffffff;
+#pragma unroll
+  for (int q = 0; q <= NJ; ++q) {
+    const T x = val(q);
+    if (x >= (T)0 && (x > lm || (x == lm && idx(q) < lmi))) {
+      lm = x;
+      lmi = idx(q);
+    }
+  }
+  sv[lane] = lm;
+  si[lane] = lmi;
+  wave_sync();
+  int r = 0;
+  for (int f = 0; f < kWave; ++f) {
+    const T o = sv[f];
+    const int oi = si[f];
+    r += (o > lm || (o == lm && oi < lmi)) ? 1 : 0;
+  }
+  const bool thr = __popcll(__ballot(lm >= (T)0)) >= top_k;
+  T ev = (T)-1;
+  int ei = 0x7fffffff;
+  if (thr) {
+    const int wl = __ffsll((long long)__ballot(lm >= (T)0 && r == top_k - 1)) - 1;
+    ev = __shfl(lm, wl);
+    ei = __shfl(lmi, wl);
+  }
+  wave_sync();
+  // the survivors, compacted into LDS
+  int n_s = 0;
+#pragma unroll
+  for (int q = 0; q <= NJ; ++q) {
+    const T x = val(q);
+    const int c = idx(q);
+    const bool keep = x >= (T)0 && (!thr || x > ev || (x == ev && c <= ei));
+    const unsigned long long m = __ballot(keep);
+    const int pos = n_s + __popcll(m & ((1ull << lane) - 1ull));
+    if (keep && pos < kSurv) {
+      sv[pos] = x;
+      si[pos] = c;
+    }
+    n_s += __popcll(m);
+  }
+  wave_sync();
+  T prev = (T)-1;
+  int prev_i = -1;
+  bool any;
+  if (n_s <= kSurv) {
+    any = n_s >= top_k;
+    if (any) {
+      int found = -1;
+      for (int i0 = 0; i0 < n_s; i0 += kWave) {
+        const int i = i0 + lane;
+        int before = -1;
+        if (i < n_s) {
+          const T x = sv[i];
+          const int c = si[i];
+          before = 0;
+          for (int f = 0; f < n_s; ++f) {
+            const T o = sv[f];
+            const int oi = si[f];
+            before += (o > x || (o == x && oi < c)) ? 1 : 0;
+          }
+        }
+        const unsigned long long m = __ballot(before == top_k - 1);
+        if (m != 0ull && found < 0) found = i0 + __ffsll((long long)m) - 1;
+      }
+      prev = sv[found];
+      prev_i = si[found];
+    }
+  } else {
+    // rounds of "the largest after the previous one" (ties by index)
+    prev = (T)0;
+    any = true;
+    for (int j = 0; j < top_k && any; ++j) {
+      T bv = (T)-1;
+      int bi = 0x7fffffff;
+#pragma unroll
+      for (int q = 0; q <= NJ; ++q) {
+        const T x = val(q);
+        const int c = idx(q);
+        const bool after = j == 0 || x < prev || (x == prev && c > prev_i);
+        if (x >= (T)0 && after && (x > bv || (x == bv && c < bi))) {
+          bv = x;
+          bi = c;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const T ov = __shfl_xor(bv, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      any = bv >= (T)0;
+      prev = bv;
+      prev_i = bi;
+    }
+  }
+  const double tau = any ? (double)prev : -1.0;
+  if (lane == 0) A.tau[(size_t)cand * A.nbands] = tau;
+  if (A.hotl) {
+    int32_t *hl = A.hotl + (size_t)cand * A.nbands * kHotLd;
+    int nh = 0;
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+      const int c = lane + kWave * q;
+      const bool hot = v[q] >= (T)0 && (!any || v[q] > prev || (v[q] == prev && c <= prev_i));
+      const unsigned long long m = __ballot(hot);
+      const int pos = nh + __popcll(m & ((1ull << lane) - 1ull));
+      if (hot && pos < DCFLOW_WORST_MAX) hl[1 + pos] = c;
+      nh += __popcll(m);
+    }
+    if (lane == 0) hl[0] = min(nh, DCFLOW_WORST_MAX);
+  }
+  if (A.cmx_out) {
+    double *co = A.cmx_out + (size_t)cand * (ld_o + 2);
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+      const int c = lane + kWave * q;
+      if (c < ld_o) co[c] = (double)v[q];
+    }
+    if (lane == 0) {
+      co[ld_o] = (double)n0;
+      co[ld_o + 1] = tau;
+    }
+  }
 }
 
 // Item (cand, band) of the winning variant after k_scan_colmax: only the band's hot
@@ -1201,9 +1449,54 @@ __device__ __forceinline__ void scan_hot_item(const ScanArgs &A, int cand, int b
     }
     return;
   }
-  // the band's list: rounds of "best head over the block"; the winning lane pops.
-  // Keys are unique among real entries, and empty entries never win.
+  // The band's list.  The lanes' lists hold every entry that can reach it (all at
+  // or above tau; a lane drops an entry only behind KM better ones of its own), and
+  // the keys of real entries are unique, so an entry's place in the union of the
+  // lists is its place in the band: the union goes to LDS and each entry counts
+  // the entries before it.  (More than kRankCap entries: rounds of "best head
+  // over the block", the winning lane popping.)
   WEntry *dst = A.wpart + ((size_t)cand * A.nbt + band) * A.top_k;
+  {
+    constexpr int kRankCap = 512;
+    __shared__ WEntry s_re[kRankCap];
+    __shared__ int s_rn;
+    if (tid == 0) s_rn = 0;
+    __syncthreads();
+    int n = 0;
+#pragma unroll
+    for (int j = 0; j < KM; ++j) n += lk[j] != kEmpty ? 1 : 0;
+    const int base = n > 0 ? atomicAdd(&s_rn, n) : 0;
+#pragma unroll
+    for (int j = 0; j < KM; ++j)
+      if (j < n && base + j < kRankCap) {
+        WEntry e;
+        e.v = (double)lv[j];
+        e.k = lk[j];
+        e.pad = 0;
+        s_re[base + j] = e;
+      }
+    __syncthreads();
+    const int N = s_rn;
+    if (N <= kRankCap) {
+      for (int i = tid; i < N; i += blockDim.x) {
+        const WEntry e = s_re[i];
+        int rank = 0;
+        for (int f = 0; f < N; ++f) {
+          const WEntry o = s_re[f];
+          rank += better(o.v, o.k, e.v, e.k) ? 1 : 0;
+        }
+        if (rank < A.top_k) dst[rank] = e;
+      }
+      for (int j = N + tid; j < A.top_k; j += blockDim.x) {
+        WEntry e;
+        e.v = -1.0;
+        e.k = kEmpty;
+        e.pad = 0;
+        dst[j] = e;
+      }
+      return;
+    }
+  }
   for (int j = 0; j < A.top_k; ++j) {
     T bv = lv[0];
     int bk = lk[0];
@@ -1845,6 +2138,16 @@ __global__ void __launch_bounds__(256) k_guard_worst(ScanArgs A) {
   const bool skip = A.nflag == nullptr || A.nflag[cand] == 0 ||
                     (sc.status & (DCFLOW_ST_DISCONNECTED | DCFLOW_ST_NONFINITE)) != 0 ||
                     sc.best_variant < 0 || sc.best_variant >= A.nvar;
+  if (skip) {  // block-uniform: the empty list
+    for (int j = tid; j < A.top_k; j += blockDim.x) {
+      WEntry e;
+      e.v = -1.0;
+      e.k = kEmpty;
+      e.pad = 0;
+      dst[j] = e;
+    }
+    return;
+  }
   double lv[KM];
   int lk[KM];
 #pragma unroll
@@ -1852,7 +2155,7 @@ __global__ void __launch_bounds__(256) k_guard_worst(ScanArgs A) {
     lv[j] = -1.0;
     lk[j] = kEmpty;
   }
-  if (!skip) {
+  {
     const int e0 = A.off[cand], k = A.off[cand + 1] - e0;
     const float *Fv =
         static_cast<const float *>(A.F) + ((size_t)cand * A.nvar + sc.best_variant) * A.ld_f;
@@ -2114,13 +2417,30 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
       DCF_CHECK_LAUNCH();
     }
   }
-  const size_t fixed = sizeof(T) * 2 * (size_t)p->ld_o;
+  // y, the column weights and, with the record, the band's column maxima
+  const bool rec = record_on(bt);
+  const size_t fixed = sizeof(T) * (rec ? 3 : 2) * (size_t)p->ld_o;
   choose_rows(bt, fixed, sizeof(T), p->mon_pad, p->ld_o, sizeof(T), kLdsOccupancy, a);
   if (a.nbands > bt->max_bands) return hipErrorInvalidValue;
   a.nbt = a.nbands + a.nmb + a.ng;
   const size_t lds = fixed + sizeof(T) * (size_t)a.rchunk;
   if (lds > kLdsBudget) return hipErrorInvalidValue;
-  k_scan_win<T, sizeof(T) == 4 ? 4 : 3><<<dim3(grid_x(bt, a)), dim3(256), lds, s>>>(a);
+  constexpr int kWinWaves = sizeof(T) == 4 ? 4 : 3;
+  if (rec) {
+    a.rec = bt->d_rec;
+    a.rec_var = bt->d_rec_var;
+    a.rec_atomic = a.nbands > 1;
+    if (a.rec_atomic) {
+      // the bands' maxima accumulate: the candidates' records start at zero
+      const size_t n = (size_t)(c1 - c0) * (p->ld_o + 1) * sizeof(T) / 4;
+      k_zero32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
+          reinterpret_cast<uint32_t *>(static_cast<T *>(bt->d_rec) + (size_t)c0 * (p->ld_o + 1)), n);
+      DCF_CHECK_LAUNCH();
+    }
+    k_scan_win<T, kWinWaves, true><<<dim3(grid_x(bt, a)), dim3(256), lds, s>>>(a);
+  } else {
+    k_scan_win<T, kWinWaves, false><<<dim3(grid_x(bt, a)), dim3(256), lds, s>>>(a);
+  }
   DCF_CHECK_LAUNCH();
   if (a.nmb > 0) {
     k_scan_multi<T, 1, 1><<<dim3((unsigned)((size_t)a.n_cand * a.nmb)), dim3(256), 0, s>>>(a);
@@ -2150,7 +2470,7 @@ inline int worst_band_rows(const dcflow_plan *p) {
 
 template <typename T>
 hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_score *scores,
-                     int top_k, void *ws, dcflow_case *out, hipStream_t s,
+                     int top_k, bool rec_use, void *ws, dcflow_case *out, hipStream_t s,
                      double *cmx_out = nullptr, void *pcl = nullptr, int pc_nslots = 0,
                      int per_case = 0) {
   dcflow_plan *p = bt->plan;
@@ -2200,6 +2520,11 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   a.pcl = static_cast<WEntry *>(pcl);
   a.pc_nslots = pc_nslots;
   a.per_case = per_case;
+  if (rec_use) {
+    a.rec = bt->d_rec;
+    a.rec_var = bt->d_rec_var;
+    a.rec_use = 1;
+  }
   set_multi(a, p, bt);
   const size_t fixed = sizeof(T) * 2 * (size_t)p->ld_o;  // k_scan_colmax: y and the weights
   int band = worst_band_rows(p);
@@ -2225,6 +2550,18 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
                   : reinterpret_cast<double *>(static_cast<char *>(ws) +
                                                worst_list_bytes(bt->n_cand, a.nbt, top_k));
   a.hotl = reinterpret_cast<int32_t *>(a.tau + (size_t)bt->n_cand * a.nbands);
+  if (a.rec_use && a.nbands == 1 && p->ld_o <= 16 * kWave) {
+    // the candidates whose record names their winner, one wave each
+    const dim3 gs((unsigned)((bt->n_cand + 3) / 4));
+    if (p->ld_o <= 4 * kWave)
+      k_rec_select<T, 4><<<gs, dim3(256), 0, s>>>(a);
+    else if (p->ld_o <= 8 * kWave)
+      k_rec_select<T, 8><<<gs, dim3(256), 0, s>>>(a);
+    else
+      k_rec_select<T, 16><<<gs, dim3(256), 0, s>>>(a);
+    DCF_CHECK_LAUNCH();
+    a.rec_sel = 1;
+  }
   k_scan_colmax<T><<<grid, dim3(256), lds + sizeof(T) * (size_t)p->ld_o, s>>>(a);
   DCF_CHECK_LAUNCH();
   // the hot columns: F~ in row chunks of at most 1024 (and the per-case merge area)
@@ -2273,13 +2610,25 @@ int worst_bands(const dcflow_plan *p) {
   return (p->mon_pad + band - 1) / band;
 }
 
+// Whether the column-maximum record describes these flows and score records (the
+// n1_score call that wrote it); candidates whose record names another variant than
+// their score record are swept as without it.
+bool record_matches(const dcflow_batch *bt, const void *flows, int nvar, int prec,
+                    const dcflow_score *scores) {
+  return bt->d_rec && bt->rec_valid && bt->rec_prec == prec && bt->rec_nvar == nvar &&
+         bt->rec_flows == flows && bt->rec_scores == scores && worst_bands(bt->plan) == 1;
+}
+
 hipError_t launch_worst(dcflow_batch *bt, const void *flows, int nvar, int prec,
                         const dcflow_score *scores, int top_k, void *ws, dcflow_case *out,
                         hipStream_t s) {
   if (bt->n_cand == 0) return hipSuccess;
+  const bool ru = record_matches(bt, flows, nvar, prec, scores);
   if (prec == DCFLOW_FP64)
-    return run_worst<double>(bt, static_cast<const double *>(flows), nvar, scores, top_k, ws, out, s);
-  return run_worst<float>(bt, static_cast<const float *>(flows), nvar, scores, top_k, ws, out, s);
+    return run_worst<double>(bt, static_cast<const double *>(flows), nvar, scores, top_k, ru, ws,
+                             out, s);
+  return run_worst<float>(bt, static_cast<const float *>(flows), nvar, scores, top_k, ru, ws, out,
+                          s);
 }
 
 bool case_maxima_supported(const dcflow_plan *p) { return worst_bands(p) == 1; }
@@ -2289,10 +2638,11 @@ hipError_t launch_case_maxima(dcflow_batch *bt, const void *flows, int nvar, int
                               void *pcl, int pc_nslots, int per_case, hipStream_t s) {
   if (bt->n_cand == 0) return hipSuccess;
   if (!case_maxima_supported(bt->plan)) return hipErrorInvalidValue;
+  const bool ru = record_matches(bt, flows, nvar, prec, scores);
   if (prec == DCFLOW_FP64)
-    return run_worst<double>(bt, static_cast<const double *>(flows), nvar, scores, top_k,
+    return run_worst<double>(bt, static_cast<const double *>(flows), nvar, scores, top_k, ru,
                              nullptr, nullptr, s, cmx_out, pcl, pc_nslots, per_case);
-  return run_worst<float>(bt, static_cast<const float *>(flows), nvar, scores, top_k, nullptr,
+  return run_worst<float>(bt, static_cast<const float *>(flows), nvar, scores, top_k, ru, nullptr,
                           nullptr, s, cmx_out, pcl, pc_nslots, per_case);
 }
 
@@ -2304,9 +2654,18 @@ size_t worst_aux_bytes(int n_cand, int nbands) {
 hipError_t launch_score(dcflow_batch *bt, const void *flows, int nvar, int prec, dcflow_score *out,
                         int c0, int c1, hipStream_t s) {
   if (c1 <= c0) return hipSuccess;
-  if (prec == DCFLOW_FP64)
-    return run_scan<double>(bt, static_cast<const double *>(flows), nvar, out, c0, c1, s);
-  return run_scan<float>(bt, static_cast<const float *>(flows), nvar, out, c0, c1, s);
+  const hipError_t e =
+      prec == DCFLOW_FP64
+          ? run_scan<double>(bt, static_cast<const double *>(flows), nvar, out, c0, c1, s)
+          : run_scan<float>(bt, static_cast<const float *>(flows), nvar, out, c0, c1, s);
+  // the record describes these flows and records once every chunk of the batch is
+  // enqueued (a part of the batch comes from dcflow_step, which scores them all)
+  bt->rec_valid = e == hipSuccess && record_on(bt);
+  bt->rec_prec = prec;
+  bt->rec_nvar = nvar;
+  bt->rec_flows = flows;
+  bt->rec_scores = out;
+  return e;
 }
 
 }  // namespace dcflow

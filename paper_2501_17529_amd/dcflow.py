@@ -66,7 +66,8 @@ class Tuning(ctypes.Structure):
     """dcflow_tuning: launch shapes of the N-1 scan (0 = automatic)."""
     _fields_ = [("scan_vc", ctypes.c_int32), ("scan_rchunk", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("scan_band", ctypes.c_int32),
-                ("step_chunks", ctypes.c_int32), ("guard_tol", ctypes.c_double)]
+                ("step_chunks", ctypes.c_int32), ("worst_record", ctypes.c_int32),
+                ("guard_tol", ctypes.c_double)]
 
     def as_dict(self):
         d = {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "guard_tol"}
@@ -494,9 +495,9 @@ class Batch:
         return raw.view(CASE_DTYPE).reshape(n_cand, top_k)
 
     def set_tuning(self, scan_vc=0, scan_rchunk=0, persistent=0, scan_band=0, step_chunks=0,
-                   guard_tol=0.0):
+                   worst_record=0, guard_tol=0.0):
         t = Tuning(int(scan_vc), int(scan_rchunk), int(persistent), int(scan_band),
-                   int(step_chunks), float(guard_tol))
+                   int(step_chunks), int(worst_record), float(guard_tol))
         _check(_lib.dcflow_batch_set_tuning(self.h, ctypes.byref(t)), "dcflow_batch_set_tuning")
 
     def get_tuning(self):
