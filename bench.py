@@ -245,19 +245,37 @@ def run_path(D, torch, plan, w, prec, steps, warmup, tune=True, graph=True, pers
             res["wall"] = res["wall_graph"]
         if agg_i:
             # agg_i of the winners after the step (metric-first), outside the timed step:
-            # the global top 16 and the two-level list (3 per case, top 16)
-            agg = {}
-            for name, fn in (("global_top16", lambda: bt.n1_worst(flows, nv, prec, out, 16)),
-                             ("per_case3_top16",
-                              lambda: bt.n1_worst_per_case(flows, nv, prec, out, 3, 16))):
+            # the global top 16 and the two-level list (3 per case, top 16); first
+            # sweeping the winners' tiles, then from the column-maximum record of a
+            # winner pass run with it (and that pass's extra time)
+            def timed(fn, reps):
                 fn()
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-                for _ in range(3):
+                for _ in range(reps):
                     fn()
                 e1.record(stream)
                 e1.synchronize()
-                agg[name] = e0.elapsed_time(e1) / 3
+                return e0.elapsed_time(e1) / reps
+
+            calls = (("global_top16", lambda: bt.n1_worst(flows, nv, prec, out, 16)),
+                     ("per_case3_top16", lambda: bt.n1_worst_per_case(flows, nv, prec, out, 3, 16)))
+            agg = {"sweep": {}, "record": {}}
+            lists = {}
+            for name, fn in calls:
+                agg["sweep"][name] = timed(fn, 3)
+                lists[name] = fn().cpu().numpy().copy()
+            base_cfg = bt.get_tuning()
+            score = lambda: bt.n1_score(flows, nv, prec, out=out)
+            agg["n1_score_ms"] = timed(score, 5)
+            bt.set_tuning(**dict(base_cfg, worst_record=1))
+            agg["n1_score_with_record_ms"] = timed(score, 5)
+            for name, fn in calls:
+                agg["record"][name] = timed(fn, 3)
+                assert np.array_equal(fn().cpu().numpy(), lists[name]), \
+                    f"agg_i from the record differs ({name})"
+            bt.set_tuning(**base_cfg)
+            score()
             res["agg_i_ms"] = agg
     res["scores"] = sc_eager
     res["batch"] = bt

@@ -31,6 +31,7 @@ struct PcEntry {  // one list entry: |p| / r and its key (case slot x n_mon + ro
 };
 
 constexpr int kEmptyKey = 0x7fffffff;
+constexpr int kFinRankCap = 256;  // k_pc_fin ranks up to this many entries in LDS
 
 __device__ __forceinline__ float pc_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double pc_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -376,8 +377,10 @@ __global__ void __launch_bounds__(256) k_pc_multi(PcArgs A) {
 
 // Level 2: one workgroup per candidate (one wave when the case maxima leave a few
 // lists: the hot columns, N-0, guarded and multi-outage cases; four waves over
-// every slot otherwise).  Each thread keeps the top KM of the entries of its
-// slots; the block then takes one entry per round from the heads.
+// every slot otherwise).  With the case maxima and at most kFinRankCap entries in
+// the listed slots, the entries go to LDS and each counts the entries before it;
+// else each thread keeps the top KM of the entries of its slots and the block
+// takes one entry per round from the heads.
 template <int KM>
 __global__ void __launch_bounds__(256) k_pc_fin(PcArgs A, dcflow_case *out) {
   __shared__ double s_bv[4];
@@ -401,11 +404,59 @@ __global__ void __launch_bounds__(256) k_pc_fin(PcArgs A, dcflow_case *out) {
   const int n_live = sl && !skip ? sl[0] : 0;
   const int n_hot = hl && !skip ? hl[0] : 0;
   const int n_iter = !sl ? A.nslots : (skip ? 0 : n_live + n_hot + A.n_multi);
+  auto slot_of = [&](int i) __attribute__((always_inline)) {
+    return !sl ? i
+               : (i < n_live ? sl[1 + i]
+                             : (i < n_live + n_hot ? 1 + hl[1 + i - n_live]
+                                                   : 1 + A.n_ctg + (i - n_live - n_hot)));
+  };
+  auto emit = [&](int j, double v, int k) __attribute__((always_inline)) {
+    dcflow_case e;
+    if (k == kEmptyKey) {
+      e.load = -1.0;
+      e.branch = -1;
+      e.outage = -1;
+    } else {
+      const int slot = k / A.n_mon, row = k - slot * A.n_mon;
+      e.load = v;
+      e.branch = A.mon[row];
+      // slot 0: N-0; 1 + c: contingency column c (branch id, or -2 - g for a
+      // generator); after them the multi-outage cases, -2 - n_gen - q
+      e.outage = slot == 0 ? -1 : (slot - 1 < A.n_out ? A.out[slot - 1] : -2 - (slot - 1 - A.n_out));
+    }
+    out[(size_t)cand * A.top_k + j] = e;
+  };
+  if (A.cmx && (size_t)n_iter * A.per_case <= (size_t)kFinRankCap) {  // block-uniform
+    // the listed slots' entries in LDS; a real entry's place is the number of
+    // entries before it (the keys are unique)
+    __shared__ PcEntry s_e[kFinRankCap];
+    __shared__ int s_n;
+    if (tid == 0) s_n = 0;
+    __syncthreads();
+    for (int i = tid; i < n_iter; i += blockDim.x) {
+      const int s = slot_of(i);
+      for (int j = 0; j < A.per_case; ++j) {
+        const PcEntry e = base[(size_t)s * A.per_case + j];
+        if (e.k == kEmptyKey) break;  // lists are sorted, empties last
+        s_e[atomicAdd(&s_n, 1)] = e;
+      }
+    }
+    __syncthreads();
+    const int n = s_n;
+    for (int i = tid; i < n; i += blockDim.x) {
+      const PcEntry e = s_e[i];
+      int rank = 0;
+      for (int f = 0; f < n; ++f) {
+        const PcEntry o = s_e[f];
+        rank += pc_better(o.v, o.k, e.v, e.k) ? 1 : 0;
+      }
+      if (rank < A.top_k) emit(rank, e.v, e.k);
+    }
+    for (int j = n + tid; j < A.top_k; j += blockDim.x) emit(j, -1.0, kEmptyKey);
+    return;
+  }
   for (int i = tid; i < n_iter; i += blockDim.x) {
-    const int s = !sl ? i
-                      : (i < n_live ? sl[1 + i]
-                                    : (i < n_live + n_hot ? 1 + hl[1 + i - n_live]
-                                                          : 1 + A.n_ctg + (i - n_live - n_hot)));
+    const int s = slot_of(i);
     for (int j = 0; j < A.per_case; ++j) {
       const PcEntry e = base[(size_t)s * A.per_case + j];
       if (e.k == kEmptyKey) break;  // lists are sorted, empties last
@@ -437,22 +488,7 @@ __global__ void __launch_bounds__(256) k_pc_fin(PcArgs A, dcflow_case *out) {
         wbv = s_bv[w];
         wbk = s_bk[w];
       }
-    if (tid == 0) {
-      dcflow_case e;
-      if (wbk == kEmptyKey) {
-        e.load = -1.0;
-        e.branch = -1;
-        e.outage = -1;
-      } else {
-        const int slot = wbk / A.n_mon, row = wbk - slot * A.n_mon;
-        e.load = wbv;
-        e.branch = A.mon[row];
-        // slot 0: N-0; 1 + c: contingency column c (branch id, or -2 - g for a
-        // generator); after them the multi-outage cases, -2 - n_gen - q
-        e.outage = slot == 0 ? -1 : (slot - 1 < A.n_out ? A.out[slot - 1] : -2 - (slot - 1 - A.n_out));
-      }
-      out[(size_t)cand * A.top_k + j] = e;
-    }
+    if (tid == 0) emit(j, wbv, wbk);
     if (wbk != kEmptyKey && lk[0] == wbk) {
 #pragma unroll
       for (int t = 0; t < KM - 1; ++t) {

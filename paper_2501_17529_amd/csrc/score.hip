@@ -165,7 +165,12 @@ struct ScanArgs {
   int rec_use = 0;              // k_scan_colmax: take the maxima of the candidates whose
                                 // record names their winner
   int rec_sel = 0;              // k_rec_select has done those candidates already
+  int32_t *hot_q = nullptr;     // [1 + n_cand nbands] items whose entries at or above tau
+                                // outgrew k_scan_hot's LDS: their number, then the items
+  int hot_cap = 0;              // entries k_scan_hot keeps in LDS (at most kHotUnionCap)
 };
+
+constexpr int kHotUnionCap = 1024;
 
 constexpr int kQueueWin = 15;  // counter slot of pass 2
 
@@ -1106,6 +1111,7 @@ __device__ __forceinline__ void scan_colmax_item(const ScanArgs &A, int cand, in
 
 template <typename T>
 __global__ void __launch_bounds__(256, 4) k_scan_colmax(ScanArgs A) {
+  if (A.hot_q && blockIdx.x == 0 && threadIdx.x == 0) *A.hot_q = 0;  // k_scan_hot's queue
   for_each_item(A, kQueueWin, [&](int cand, int band) __attribute__((always_inline)) { scan_colmax_item<T>(A, cand, band); });
 }
 
@@ -1294,15 +1300,247 @@ __global__ void __launch_bounds__(256) k_rec_select(ScanArgs A) {
 // repeat a hot column and are masked) and built on the matrix cores from the same
 // seed fragments, U / r and W values as the full tiles: every entry is bit for bit
 // the value k_scan_colmax maximised (each MFMA output depends on its own row,
-// column and accumulator only).  The N-0 rows enter while F~ is staged.
-//   One list (PC false): each lane keeps its KM best entries at or above tau; the
-//   band's top_k list is then taken from the lanes' heads, one entry per round.
-//   Two-level lists (PC true, one band): each lane keeps the KM best rows of its
-//   own column; the 16 lists of a column (4 row groups x 4 waves) are merged into
-//   its per-case list of per_case entries (slot 1 + c); the N-0 case is left to
-//   the per-case kernels.
+// column and accumulator only).  A wave takes its row blocks G at a time, their
+// seed and U / r loads issued together (W is the same for all of them).  Only
+// entries at or above tau can reach either kind of list: the chosen column
+// maxima and N-0 maximum are top_k entries at or above it, in both.
+//   One list (PC false): the N-0 rows (while F~ is staged) and the hot entries at
+//   or above tau go to an LDS array, and each counts the entries before it in
+//   the list order: its place in the band's list (the keys of real entries are
+//   unique).  More than hot_cap such entries: the item is queued for
+//   k_scan_hot_lists.
+//   Two-level lists (PC true, one band): each lane keeps the KM best rows at or
+//   above tau of its own column; the 16 lists of a column (4 row groups x 4 waves)
+//   are merged into its per-case list of at most per_case entries (slot 1 + c);
+//   the N-0 case is left to the per-case kernels.
 template <typename T, int KM, bool PC>
 __device__ __forceinline__ void scan_hot_item(const ScanArgs &A, int cand, int band) {
+  constexpr int kEmpty = 0x7fffffff;
+  constexpr int G = 4;
+  constexpr int kUnionCap = PC ? 1 : kHotUnionCap;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  const int ld_o = A.ld_o, rchunk = A.rchunk;
+  T *fs = reinterpret_cast<T *>(smem_raw);  // [rchunk]
+  __shared__ T s_y[16], s_tau;
+  __shared__ int s_col[16], s_nh, s_rn;
+  __shared__ WEntry s_re[kUnionCap];
+
+  const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave, g = lane / 16, li = lane % 16;
+  const int e0 = A.off[cand];
+  const int k = A.off[cand + 1] - e0;
+  const dcflow_score sc = A.scores[cand];
+  const bool skip = (sc.status & (DCFLOW_ST_DISCONNECTED | DCFLOW_ST_NONFINITE)) != 0 ||
+                    sc.best_variant < 0 || sc.best_variant >= A.nvar;
+  T lv[PC ? KM : 1];
+  int lk[PC ? KM : 1];
+#pragma unroll
+  for (int j = 0; j < (PC ? KM : 1); ++j) {
+    lv[j] = (T)-1;
+    lk[j] = kEmpty;
+  }
+  const int32_t *hl = A.hotl + ((size_t)cand * A.nbands + band) * kHotLd;
+  const T *Fv = skip ? nullptr
+                     : static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + sc.best_variant) * A.ld_f;
+  if (tid == 0) {
+    s_nh = skip ? 0 : hl[0];
+    s_tau = (T)A.tau[(size_t)cand * A.nbands + band];
+    s_rn = 0;
+  }
+  __syncthreads();
+  const int nh = s_nh;
+  if (tid < 16) {
+    const int c = nh > 0 ? hl[1 + (tid < nh ? tid : 0)] : 0;
+    bool nf = false;
+    s_col[tid] = c;
+    s_y[tid] = nh > 0 ? ycol(Fv, A, cand, c, nf) : (T)0;
+  }
+  // an entry at or above tau joins the LDS array (one list)
+  auto keep = [&](T v, int key) __attribute__((always_inline)) {
+    const int pos = atomicAdd(&s_rn, 1);
+    if (pos < kUnionCap) {
+      WEntry e;
+      e.v = (double)v;
+      e.k = key;
+      e.pad = 0;
+      s_re[pos] = e;
+    }
+  };
+  if (!skip && (nh > 0 || !PC)) {
+    const T tau = s_tau;
+    const int r0 = band * A.band_rows, r1 = min(r0 + A.band_rows, A.mon_pad);
+    const int steps = (k + 3) / 4;  // at most 2 (k <= DCFLOW_MAX_RANK)
+    bool first = true;
+    int col = 0;
+    T yc = (T)0, b0 = (T)0, b1 = (T)0;
+    bool live = false;
+    for (int rc0 = r0; rc0 < r1; rc0 += rchunk) {
+      const int rows = min(rchunk, r1 - rc0);
+      __syncthreads();
+      bool nf = false;
+      for (int rr = tid; rr < rows; rr += blockDim.x) {
+        const int row = rc0 + rr;
+        const T fv = ftilde(Fv, A.inv_r, row, A.n_mon, nf);
+        fs[fs_pos(fs, rr)] = fv;
+        if (!PC && row < A.n_mon && tabs(fv) >= tau) keep(tabs(fv), row);
+      }
+      __syncthreads();
+      if (nh == 0) continue;
+      if (first) {
+        // the hot column of lane column li and its W fragments (row-independent)
+        first = false;
+        col = s_col[li];
+        yc = s_y[li];
+        live = li < nh;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int e = h * 4 + g;
+          const int es = max(e0 + (e < k ? e : k - 1), 0);
+          T b = sizeof(T) == 4 ? (T)A.w32[(size_t)es * ld_o + col] : (T)A.W[(size_t)es * ld_o + col];
+          b = (h < steps && e < k) ? b : (T)0;
+          if (h == 0)
+            b0 = b;
+          else
+            b1 = b;
+        }
+      }
+      const typename TileOf<T>::blk *seed = reinterpret_cast<const typename TileOf<T>::blk *>(
+          sizeof(T) == 4 ? (const void *)A.lsd32 : (const void *)A.lsd64f);
+      const int nrb = rows / 16;
+      for (int i0 = wv; i0 < nrb; i0 += 4 * G) {
+        typename TileOf<T>::blk c4[G];
+        T a0[G], a1[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+          const int rb = i0 + 4 * q < nrb ? i0 + 4 * q : i0;  // wave-uniform; in bounds
+          const int rowbase = rc0 + rb * 16;
+          c4[q] = seed[((size_t)(rowbase / 16) * (ld_o / 16) + col / 16) * kWave + g * 16 + col % 16];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int e = h * 4 + g;
+            const int es = max(e0 + (e < k ? e : k - 1), 0);
+            T a = (T)0;
+            if (h < steps) {  // wave-uniform
+              if (sizeof(T) == 4)
+                a = (T)A.ur32[(size_t)es * A.mon_pad + rowbase + li];
+              else
+                a = (T)(A.U[(size_t)es * A.ld_er + rowbase + li] * A.inv_r[rowbase + li]);
+              a = e < k ? a : (T)0;
+            }
+            if (h == 0)
+              a0[q] = a;
+            else
+              a1[q] = a;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+          if (steps > 0) c4[q] = mfma_step1(a0[q], b0, c4[q]);
+          if (steps > 1) c4[q] = mfma_step1(a1[q], b1, c4[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+          if (i0 + 4 * q >= nrb) break;  // wave-uniform
+          const int rowbase = rc0 + (i0 + 4 * q) * 16;
+          const T *fsv = fs + (rowbase - rc0) + 4 * g;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = rowbase + MfmaRow<T>::row(g, r);
+            const T v = tabs(tfma(c4[q][r], yc, fsv[r]));
+            if (live && row < A.n_mon && v >= tau) {
+              if (PC) {
+                if (better(v, row, lv[KM - 1], lk[KM - 1])) list_insert(lv, lk, v, row);
+              } else {
+                keep(v, (col + 1) * A.n_mon + row);
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  if (PC) {
+    // merge the 16 lists of each hot column; a skipped candidate writes nothing
+    if (skip || nh == 0) return;
+    T *mv = fs + ((A.rchunk + 1) & ~1);  // [256 lanes][KM] after the F~ chunk
+    int *mk = reinterpret_cast<int *>(mv + (size_t)blockDim.x * KM);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+      mv[(size_t)tid * KM + j] = lv[j];
+      mk[(size_t)tid * KM + j] = lk[j];
+    }
+    __syncthreads();
+    if (tid < nh) {
+      // lists of column tid: lanes tid + 16 g of each wave
+      int pos[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) pos[q] = 0;
+      const int c = s_col[tid];
+      WEntry *dst = A.pcl + ((size_t)cand * A.pc_nslots + 1 + c) * A.per_case;
+      for (int j = 0; j < A.per_case; ++j) {
+        T bv = (T)-1;
+        int bk = kEmpty, bq = -1;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int t = (q / 4) * kWave + (q % 4) * 16 + tid;
+          if (pos[q] < KM) {
+            const T v = mv[(size_t)t * KM + pos[q]];
+            const int kk = mk[(size_t)t * KM + pos[q]];
+            if (kk != kEmpty && better(v, kk, bv, bk)) {
+              bv = v;
+              bk = kk;
+              bq = q;
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (q == bq) ++pos[q];
+        WEntry e;
+        e.v = bk == kEmpty ? -1.0 : (double)bv;
+        e.k = bk == kEmpty ? kEmpty : (1 + c) * A.n_mon + bk;
+        e.pad = 0;
+        dst[j] = e;
+      }
+    }
+    return;
+  }
+  // the band's list: each entry of the array counts the entries before it
+  __syncthreads();
+  const int N = s_rn;
+  if (N > A.hot_cap) {
+    if (tid == 0) {
+      const int q = atomicAdd(A.hot_q, 1);
+      A.hot_q[1 + q] = cand * A.nbands + band;
+    }
+    return;
+  }
+  WEntry *dst = A.wpart + ((size_t)cand * A.nbt + band) * A.top_k;
+  for (int i = tid; i < N; i += blockDim.x) {
+    const WEntry e = s_re[i];
+    int rank = 0;
+    for (int f = 0; f < N; ++f) {
+      const WEntry o = s_re[f];
+      rank += better(o.v, o.k, e.v, e.k) ? 1 : 0;
+    }
+    if (rank < A.top_k) dst[rank] = e;
+  }
+  for (int j = N + tid; j < A.top_k; j += blockDim.x) {
+    WEntry e;
+    e.v = -1.0;
+    e.k = kEmpty;
+    e.pad = 0;
+    dst[j] = e;
+  }
+}
+
+// The items k_scan_hot queued (more entries at or above tau than its LDS array
+// holds): each lane keeps its KM best entries at or above tau in registers; an
+// entry's place in the union of the lanes' lists is its place in the band (a lane
+// drops an entry only behind KM better ones of its own).
+template <typename T, int KM>
+__device__ __forceinline__ void scan_hot_lists_item(const ScanArgs &A, int cand, int band) {
+  constexpr bool PC = false;
   constexpr int kEmpty = 0x7fffffff;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int ld_o = A.ld_o, rchunk = A.rchunk;
@@ -1402,53 +1640,6 @@ __device__ __forceinline__ void scan_hot_item(const ScanArgs &A, int cand, int b
       }
     }
   }
-  if (PC) {
-    // merge the 16 lists of each hot column; a skipped candidate writes nothing
-    if (skip || nh == 0) return;
-    T *mv = fs + ((A.rchunk + 1) & ~1);  // [256 lanes][KM] after the F~ chunk
-    int *mk = reinterpret_cast<int *>(mv + (size_t)blockDim.x * KM);
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < KM; ++j) {
-      mv[(size_t)tid * KM + j] = lv[j];
-      mk[(size_t)tid * KM + j] = lk[j];
-    }
-    __syncthreads();
-    if (tid < nh) {
-      // lists of column tid: lanes tid + 16 g of each wave
-      int pos[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) pos[q] = 0;
-      const int c = s_col[tid];
-      WEntry *dst = A.pcl + ((size_t)cand * A.pc_nslots + 1 + c) * A.per_case;
-      for (int j = 0; j < A.per_case; ++j) {
-        T bv = (T)-1;
-        int bk = kEmpty, bq = -1;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const int t = (q / 4) * kWave + (q % 4) * 16 + tid;
-          if (pos[q] < KM) {
-            const T v = mv[(size_t)t * KM + pos[q]];
-            const int kk = mk[(size_t)t * KM + pos[q]];
-            if (kk != kEmpty && better(v, kk, bv, bk)) {
-              bv = v;
-              bk = kk;
-              bq = q;
-            }
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-          if (q == bq) ++pos[q];
-        WEntry e;
-        e.v = bk == kEmpty ? -1.0 : (double)bv;
-        e.k = bk == kEmpty ? kEmpty : (1 + c) * A.n_mon + bk;
-        e.pad = 0;
-        dst[j] = e;
-      }
-    }
-    return;
-  }
   // The band's list.  The lanes' lists hold every entry that can reach it (all at
   // or above tau; a lane drops an entry only behind KM better ones of its own), and
   // the keys of real entries are unique, so an entry's place in the union of the
@@ -1547,14 +1738,67 @@ __global__ void __launch_bounds__(256) k_scan_hot(ScanArgs A) {
   for_each_item(A, kQueueWin, [&](int cand, int band) __attribute__((always_inline)) { scan_hot_item<T, KM, PC>(A, cand, band); });
 }
 
-// One wave per candidate: merges the bands' sorted lists (lane b walks bands b,
-// b + 64, ..., at most kFinBands in all) into the final list of top_k cases.
+template <typename T, int KM>
+__global__ void __launch_bounds__(256) k_scan_hot_lists(ScanArgs A) {
+  const int n = *reinterpret_cast<volatile int32_t *>(A.hot_q);
+  for (int q = blockIdx.x; q < n; q += gridDim.x) {
+    __syncthreads();  // the previous item is done with shared memory
+    const int item = A.hot_q[1 + q];
+    scan_hot_lists_item<T, KM>(A, item / A.nbands, item % A.nbands);
+  }
+}
+
+// One wave per candidate: merges the bands' sorted lists into the final list of
+// top_k cases.  Up to kRankCap entries in all (the usual case) each real entry
+// counts the real entries before it in LDS; else rounds of "best head", lane b
+// walking bands b, b + 64, ..., at most kFinBands in all.
 constexpr int kFinBandsPerLane = 8, kFinBands = 64 * kFinBandsPerLane;
 
 __global__ void __launch_bounds__(64) k_worst_fin(ScanArgs A, dcflow_case *out) {
   constexpr int kEmpty = 0x7fffffff;
+  constexpr int kRankCap = 256;
+  __shared__ WEntry s_e[kRankCap];
   const int cand = blockIdx.x, lane = threadIdx.x;
   const WEntry *base = A.wpart + (size_t)cand * A.nbt * A.top_k;
+  auto emit = [&](int j, double v, int k) __attribute__((always_inline)) {
+    dcflow_case e;
+    if (k == kEmpty) {
+      e.load = -1.0;
+      e.branch = -1;
+      e.outage = -1;
+    } else {
+      const bool n0 = k < A.n_mon;
+      const int row = n0 ? k : k % A.n_mon;
+      const int c = n0 ? -1 : k / A.n_mon - 1;
+      e.load = v;
+      e.branch = A.mon[row];
+      e.outage = outage_id(A, c);
+    }
+    out[(size_t)cand * A.top_k + j] = e;
+  };
+  const int m = A.nbt * A.top_k;
+  if (m <= kRankCap) {
+    // every list entry in LDS; a real entry's place is the number of real entries
+    // before it (the keys are unique)
+    for (int i = lane; i < m; i += kWave) s_e[i] = base[i];
+    __syncthreads();
+    int n_real = 0;
+    for (int i0 = 0; i0 < m; i0 += kWave) {
+      const int i = i0 + lane;
+      const bool real = i < m && s_e[i].k != kEmpty;
+      n_real += __popcll(__ballot(real));
+      if (!real) continue;
+      const WEntry e = s_e[i];
+      int rank = 0;
+      for (int f = 0; f < m; ++f) {
+        const WEntry o = s_e[f];
+        rank += (o.k != kEmpty && better(o.v, o.k, e.v, e.k)) ? 1 : 0;
+      }
+      if (rank < A.top_k) emit(rank, e.v, e.k);
+    }
+    for (int j = n_real + lane; j < A.top_k; j += kWave) emit(j, -1.0, kEmpty);
+    return;
+  }
   int pos[kFinBandsPerLane];
 #pragma unroll
   for (int q = 0; q < kFinBandsPerLane; ++q) pos[q] = 0;
@@ -1589,22 +1833,7 @@ __global__ void __launch_bounds__(64) k_worst_fin(ScanArgs A, dcflow_case *out) 
       for (int q = 0; q < kFinBandsPerLane; ++q)
         if (q == bq) ++pos[q];
     }
-    if (lane == 0) {
-      dcflow_case e;
-      if (wk == kEmpty) {
-        e.load = -1.0;
-        e.branch = -1;
-        e.outage = -1;
-      } else {
-        const bool n0 = wk < A.n_mon;
-        const int row = n0 ? wk : wk % A.n_mon;
-        const int c = n0 ? -1 : wk / A.n_mon - 1;
-        e.load = wv;
-        e.branch = A.mon[row];
-        e.outage = outage_id(A, c);
-      }
-      out[(size_t)cand * A.top_k + j] = e;
-    }
+    if (lane == 0) emit(j, wv, wk);
   }
 }
 
@@ -2550,6 +2779,14 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
                   : reinterpret_cast<double *>(static_cast<char *>(ws) +
                                                worst_list_bytes(bt->n_cand, a.nbt, top_k));
   a.hotl = reinterpret_cast<int32_t *>(a.tau + (size_t)bt->n_cand * a.nbands);
+  a.hot_q = a.hotl + (size_t)bt->n_cand * a.nbands * kHotLd;
+  // DCFLOW_HOT_CAP lowers the entries k_scan_hot keeps in LDS (tests use it to run
+  // the queued list kernel on small batches)
+  a.hot_cap = kHotUnionCap;
+  if (const char *env = std::getenv("DCFLOW_HOT_CAP")) {
+    const long long v = std::atoll(env);
+    if (v >= 0 && v < kHotUnionCap) a.hot_cap = (int)v;
+  }
   if (a.rec_use && a.nbands == 1 && p->ld_o <= 16 * kWave) {
     // the candidates whose record names their winner, one wave each
     const dim3 gs((unsigned)((bt->n_cand + 3) / 4));
@@ -2576,10 +2813,13 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
     DCF_CHECK_LAUNCH();
     return hipSuccess;
   }
+  k_scan_hot<T, 1, false><<<grid, dim3(256), lhot, s>>>(a);
+  DCF_CHECK_LAUNCH();
+  // the items whose entries at or above tau outgrew the LDS array (usually none)
   if (top_k <= 8)
-    k_scan_hot<T, 8, false><<<grid, dim3(256), lhot, s>>>(a);
+    k_scan_hot_lists<T, 8><<<dim3(64), dim3(256), lhot, s>>>(a);
   else
-    k_scan_hot<T, 16, false><<<grid, dim3(256), lhot, s>>>(a);
+    k_scan_hot_lists<T, 16><<<dim3(64), dim3(256), lhot, s>>>(a);
   DCF_CHECK_LAUNCH();
   if (a.nmb > 0) {
     const dim3 gm((unsigned)((size_t)a.n_cand * a.nmb));
@@ -2647,8 +2887,10 @@ hipError_t launch_case_maxima(dcflow_batch *bt, const void *flows, int nvar, int
 }
 
 size_t worst_aux_bytes(int n_cand, int nbands) {
-  // per band: tau (double), then the hot-column list
-  return (size_t)n_cand * nbands * (sizeof(double) + kHotLd * sizeof(int32_t));
+  // per band: tau (double), then the hot-column lists, then the queue of k_scan_hot
+  const size_t items = (size_t)n_cand * nbands;
+  return (items * (sizeof(double) + kHotLd * sizeof(int32_t)) + (items + 1) * sizeof(int32_t) +
+          255) / 256 * 256;
 }
 
 hipError_t launch_score(dcflow_batch *bt, const void *flows, int nvar, int prec, dcflow_score *out,

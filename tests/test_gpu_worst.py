@@ -127,3 +127,34 @@ def test_worst_rejects_bad_arguments():
                                 ctypes.c_size_t(nb.value - 1), ctypes.c_void_p(out.data_ptr()), None)
     assert rc == -4  # DCFLOW_E_WORKSPACE
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_worst_hot_queue_fallback(prec):
+    """Items with more entries at or above tau than the hot kernel keeps in LDS
+    go to the queued list kernel (DCFLOW_HOT_CAP lowers the cap): same lists."""
+    import os
+    import torch
+    from paper_2501_17529_amd import dcflow as D
+    w = _mixed(seed=33)
+    nv = w.inj.shape[1]
+    plan = D.Plan.from_workload(w)
+    bt = D.Batch(plan, w.cands, nv)
+    bt.eval_topologies()
+    x = torch.from_numpy(np.ascontiguousarray(w.inj)).cuda()
+    flows = bt.eval_injections(x, nv, False, prec)
+    sc = bt.n1_score(flows, nv, prec)
+    outs = {}
+    for cap in (None, "0", "7"):
+        if cap is None:
+            os.environ.pop("DCFLOW_HOT_CAP", None)
+        else:
+            os.environ["DCFLOW_HOT_CAP"] = cap
+        try:
+            for k in (5, 16):
+                outs[(cap, k)] = bt.n1_worst(flows, nv, prec, sc, k).cpu().numpy().copy()
+        finally:
+            os.environ.pop("DCFLOW_HOT_CAP", None)
+    for k in (5, 16):
+        for cap in ("0", "7"):
+            assert np.array_equal(outs[(cap, k)], outs[(None, k)]), f"cap {cap} top {k}"
