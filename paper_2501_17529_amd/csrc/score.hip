@@ -2762,12 +2762,13 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   a.rchunk = rc;
   a.band_rows = band;  // a multiple of 64; the last chunk of a band may be shorter
   a.nbands = worst_bands(p);
-  // the last slot always holds the error guard's list (empty without guarded columns)
+  // with the error guard's flags of the score call, a last slot holds the list of
+  // the guarded columns (empty where a candidate has none)
   if (sizeof(T) == 4 && bt->guard_valid) {
     a.flag = bt->d_flag;
     a.nflag = bt->d_nflag;
   }
-  a.ng = 1;
+  a.ng = a.flag ? 1 : 0;
   a.nbt = a.nbands + a.nmb + a.ng;
   if (a.nbt > kFinBands) return hipErrorInvalidValue;
   const size_t lds = fixed + sizeof(T) * (size_t)rc;
@@ -2829,11 +2830,13 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
       k_scan_multi<T, 2, 16><<<gm, dim3(256), 0, s>>>(a);
     DCF_CHECK_LAUNCH();
   }
-  if (top_k <= 8)
-    k_guard_worst<8><<<dim3(bt->n_cand), dim3(256), 0, s>>>(a);
-  else
-    k_guard_worst<16><<<dim3(bt->n_cand), dim3(256), 0, s>>>(a);
-  DCF_CHECK_LAUNCH();
+  if (a.ng) {
+    if (top_k <= 8)
+      k_guard_worst<8><<<dim3(bt->n_cand), dim3(256), 0, s>>>(a);
+    else
+      k_guard_worst<16><<<dim3(bt->n_cand), dim3(256), 0, s>>>(a);
+    DCF_CHECK_LAUNCH();
+  }
   k_worst_fin<<<dim3(bt->n_cand), dim3(64), 0, s>>>(a, out);
   DCF_CHECK_LAUNCH();
   return hipSuccess;
