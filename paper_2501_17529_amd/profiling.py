@@ -81,6 +81,8 @@ def traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, copy_bytes, prec, 
             continue
         if prec == "fp32" and "<float" not in k or prec == "fp64" and "<double" not in k:
             continue
+        if k.startswith("k_scan_win") and k.rstrip(">").endswith("true"):
+            continue  # the winner pass that writes the column-maximum record (not in the step)
         fv, wv = fetch.get(k, [0.0]), write.get(k, [0.0])
         fb = sum(fv) / len(fv) * 1024.0 * rs
         wb = sum(wv) / len(wv) * 1024.0 * ws
