@@ -276,6 +276,7 @@ def run_path(D, torch, plan, w, prec, steps, warmup, tune=True, graph=True, pers
                     f"agg_i from the record differs ({name})"
             bt.set_tuning(**base_cfg)
             score()
+            torch.cuda.synchronize()  # the maxima below are read on another stream
             res["agg_i_ms"] = agg
     res["scores"] = sc_eager
     res["batch"] = bt

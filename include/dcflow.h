@@ -70,7 +70,11 @@ typedef enum {
   DCFLOW_E_WORKSPACE = -4,    /* caller buffer smaller than the query said    */
   DCFLOW_E_HIP = -5,          /* a HIP runtime call failed                    */
   DCFLOW_E_CAND = -6,         /* malformed candidate record (see bad_index)   */
-  DCFLOW_E_SCRATCH = -7       /* input exceeds DCFLOW_NOALLOC_SCRATCH_BYTES   */
+  DCFLOW_E_SCRATCH = -7,      /* input exceeds DCFLOW_NOALLOC_SCRATCH_BYTES   */
+  DCFLOW_E_TUNING = -8        /* the tuning's launch shape needs more LDS per
+                                 workgroup than this batch allows; nothing was
+                                 enqueued after the failing launch (others of
+                                 the call may have run)                        */
 } dcflow_status;
 
 typedef enum {

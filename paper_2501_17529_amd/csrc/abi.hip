@@ -335,6 +335,7 @@ std::vector<int32_t> host_adj_off(const dcflow_grid_desc *g) {
 // Maps a HIP failure to DCFLOW_E_HIP and names it on stderr (the status code
 // alone cannot say which runtime error it was).
 int hip_fail(hipError_t e, const char *where) {
+  if (e == kShapeMisfit) return DCFLOW_E_TUNING;  // a status, not a runtime failure
   fprintf(stderr, "dcflow: %s: %s\n", where, hipGetErrorString(e));
   return DCFLOW_E_HIP;
 }
@@ -1097,6 +1098,7 @@ const char *dcflow_strerror(int st) {
     case DCFLOW_E_HIP: return "HIP runtime error";
     case DCFLOW_E_CAND: return "malformed candidate record";
     case DCFLOW_E_SCRATCH: return "input too large for the fixed scratch array";
+    case DCFLOW_E_TUNING: return "launch shape of the tuning does not fit this batch";
     default: return "unknown status";
   }
 }

@@ -163,6 +163,10 @@ struct dcflow_batch {
   } graph_state;
 };
 
+// What the launch code returns when the tuning's launch shape needs more LDS per
+// workgroup than the budget (the entry points report it as DCFLOW_E_TUNING).
+constexpr hipError_t kShapeMisfit = hipErrorInvalidConfiguration;
+
 // Returns the launch error of the kernel just enqueued (HIP's last-error slot is
 // overwritten by later successful calls, so every launch is checked at once).
 #define DCF_CHECK_LAUNCH()                      \

@@ -2505,7 +2505,7 @@ hipError_t launch_max(const ScanArgs &a0, const dcflow_batch *bt, int nvar, hipS
   const size_t fixed = sizeof(T) * (size_t)VS * a.ld_o;
   choose_rows(bt, fixed, sizeof(T) * VF, a.mon_pad, a.ld_o, sizeof(T), kLdsOccupancy, a);
   const size_t lds = fixed + sizeof(T) * (size_t)VF * a.rchunk;
-  if (lds > lds_budget(bt, VC, sizeof(T))) return hipErrorInvalidValue;
+  if (lds > lds_budget(bt, VC, sizeof(T))) return kShapeMisfit;
   const int ny = (nvar + VC - 1) / VC;
   if (ny > kQueueWin) a.persistent = 0;  // one counter per variant group
   k_scan_max<T, VC, MINW><<<dim3(grid_x(bt, a), ny), dim3(256), lds, s>>>(a);
@@ -2653,7 +2653,7 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   if (a.nbands > bt->max_bands) return hipErrorInvalidValue;
   a.nbt = a.nbands + a.nmb + a.ng;
   const size_t lds = fixed + sizeof(T) * (size_t)a.rchunk;
-  if (lds > kLdsBudget) return hipErrorInvalidValue;
+  if (lds > kLdsBudget) return kShapeMisfit;
   constexpr int kWinWaves = sizeof(T) == 4 ? 4 : 3;
   if (rec) {
     a.rec = bt->d_rec;
@@ -2772,7 +2772,7 @@ hipError_t run_worst(dcflow_batch *bt, const T *flows, int nvar, const dcflow_sc
   a.nbt = a.nbands + a.nmb + a.ng;
   if (a.nbt > kFinBands) return hipErrorInvalidValue;
   const size_t lds = fixed + sizeof(T) * (size_t)rc;
-  if (lds > kLdsBudget) return hipErrorInvalidValue;
+  if (lds > kLdsBudget) return kShapeMisfit;
   const dim3 grid((unsigned)((size_t)a.n_cand * a.nbands));
   // the thresholds and hot-column lists first (after the band lists in the
   // workspace, or after the case maxima of the two-level lists)

@@ -164,3 +164,17 @@ def test_control_validation(d):
     c = G.Candidates.from_lists([[], [(G.KIND_OUTAGE, pst[0], 0, 0.0)],
                                  [(G.KIND_SPLIT, a, 2, 0.0)]])
     d.validate_candidates(ok, c)
+
+
+def test_status_strings(d):
+    """Every status of the header has its own message (the launch-shape status
+    of a tuning included); unknown codes are named as such."""
+    import ctypes
+    f = d._lib.dcflow_strerror
+    f.restype = ctypes.c_char_p
+    f.argtypes = [ctypes.c_int]
+    msgs = [f(c).decode() for c in range(0, -9, -1)]
+    assert len(set(msgs)) == len(msgs)
+    assert "unknown" not in " ".join(msgs)
+    assert "launch shape" in msgs[8]
+    assert f(-9).decode() == "unknown status"
