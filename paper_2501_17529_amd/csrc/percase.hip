@@ -503,7 +503,7 @@ __global__ void __launch_bounds__(256) k_pc_fin(PcArgs A, dcflow_case *out) {
 }
 
 template <typename T>
-hipError_t run_pc(dcflow_batch *bt, const T *flows, int nvar, const dcflow_score *scores,
+hipError_t run_pc(dcflow_batch *bt, const T *flows, int nvar, int prec, const dcflow_score *scores,
                   int per_case, int top_k, void *ws, dcflow_case *out, hipStream_t s) {
   const dcflow_plan *p = bt->plan;
   PcArgs a;
@@ -551,9 +551,8 @@ hipError_t run_pc(dcflow_batch *bt, const T *flows, int nvar, const dcflow_score
     // tau, the hot-column list and the kept slots after the lists in the workspace)
     double *cmx = reinterpret_cast<double *>(
         static_cast<char *>(ws) + pc_list_bytes(bt->n_cand, a.nslots, per_case));
-    const hipError_t e = launch_case_maxima(bt, flows, nvar, sizeof(T) == 4 ? DCFLOW_FP32
-                                                                            : DCFLOW_FP64,
-                                            scores, top_k, cmx, a.ws, a.nslots, per_case, s);
+    const hipError_t e = launch_case_maxima(bt, flows, nvar, prec, scores, top_k, cmx, a.ws,
+                                            a.nslots, per_case, s);
     if (e != hipSuccess) return e;
     a.cmx = cmx;
     double *tau = cmx + (size_t)bt->n_cand * (p->ld_o + 2);
@@ -626,10 +625,10 @@ hipError_t launch_worst_per_case(dcflow_batch *bt, const void *flows, int nvar, 
                                  dcflow_case *out, hipStream_t s) {
   if (bt->n_cand == 0) return hipSuccess;
   if (prec == DCFLOW_FP64)
-    return run_pc<double>(bt, static_cast<const double *>(flows), nvar, scores, per_case, top_k,
-                          ws, out, s);
-  return run_pc<float>(bt, static_cast<const float *>(flows), nvar, scores, per_case, top_k, ws,
-                       out, s);
+    return run_pc<double>(bt, static_cast<const double *>(flows), nvar, prec, scores, per_case,
+                          top_k, ws, out, s);
+  return run_pc<float>(bt, static_cast<const float *>(flows), nvar, prec, scores, per_case, top_k,
+                       ws, out, s);
 }
 
 }  // namespace dcflow

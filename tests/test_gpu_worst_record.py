@@ -148,3 +148,31 @@ def test_record_medium_batch():
         bt.set_tuning(worst_record=1)
         bt.n1_score(flows, nv, prec, out=sc_dev)
         _same(ref, _lists(D, bt, flows, nv, prec, sc_dev), f"medium {prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
+def test_record_is_read(prec):
+    """White-box: with the record's flows pointer and score array, the worst-case
+    calls read the record and do not sweep again.  The flows are zeroed in place
+    after the score call (outside the calls' contract): a sweep would fill the lists
+    with loads of 0, while the record's thresholds (from the real flows) admit no
+    hot-column entry (the two-level list keeps only its N-0 case, 3 entries)."""
+    import torch
+    w = _mixed(seed=44)
+    D, bt, x, flows, nv = _setup(w, prec)
+    bt.set_tuning(worst_record=1)
+    sc_dev = bt.n1_score(flows, nv, prec)
+    torch.cuda.synchronize()
+    flows.zero_()
+    a, b = _lists(D, bt, flows, nv, prec, sc_dev)
+    n = bt.n_cand
+    sc = D.Batch.scores_to_numpy(sc_dev, n)
+    # scored candidates without guarded columns (those are listed from the flows)
+    live = (sc["status"] & 13) == 0
+    assert live.sum() > 10
+    for raw, name, first in ((a, "global", 0), (b, "per-case", 3)):
+        cases = raw[: n * 16 * D.CASE_DTYPE.itemsize].view(D.CASE_DTYPE).reshape(n, 16)
+        # the record's tau is positive for these candidates: no zero load of a hot
+        # column passes it
+        assert np.all(cases["load"][live][:, first:] == -1.0), \
+            f"{prec} {name}: the record was not read"
