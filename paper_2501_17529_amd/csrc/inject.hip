@@ -226,10 +226,29 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
   if (bcol < ncols) brow = X + (size_t)bcol * n;
   T ra[8], rb[8];
   const int nk = (n + KT - 1) / KT;
+  // FP64: B goes to LDS as loaded (x) with p_base per k in Ps, subtracted from the
+  // fragments: no instruction touches the next k-tile's loads before the MFMAs of
+  // the current one, so they stay in flight under them.  The columns past ncols
+  // read row 0 of X (never stored) and the last k-tile clamps its indices (He is
+  // zero there).  FP32 forms x - p_base in FP64 before rounding it, in registers.
+  __shared__ double Ps[NS][KT];
+  const double *xr = brow ? brow : X;
+  double pv = 0.0;
   auto gload = [&](int kt) {
     const int kb = kt * KT + lk;
 #pragma unroll
     for (int q = 0; q < 8; ++q) ra[q] = arow[kb + q];  // He padded to ld_h (multiple of 16)
+    if constexpr (sizeof(T) == 8) {
+      if (kt + 1 < nk) {  // uniform: a whole k-tile
+#pragma unroll
+        for (int q = 0; q < 8; ++q) rb[q] = xr[kb + q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) rb[q] = xr[min(kb + q, n - 1)];
+      }
+      if (tid < KT) pv = pbase[min(kt * KT + tid, n - 1)];
+      return;
+    }
     if (brow && kb + 8 <= n) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) rb[q] = (T)(brow[kb + q] - pbase[kb + q]);
@@ -251,6 +270,7 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
       *reinterpret_cast<V4<T> *>(&As[st][lr][lk + 4 * h]) = va;
       *reinterpret_cast<V4<T> *>(&Bs[st][lr][lk + 4 * h]) = vb;
     }
+    if (sizeof(T) == 8 && tid < KT) Ps[st][tid] = pv;
   };
   acc_t acc[4][4];
 #pragma unroll
@@ -295,6 +315,14 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
 #pragma unroll
     for (int b = 0; b < 4; ++b)
       bf[b] = *reinterpret_cast<const V4<T> *>(&Bs[st][wn * 64 + b * 16 + li][4 * g]);
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const double pk = Ps[st][4 * g + ks];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bf[b].x[ks] -= pk;
+      }
+    }
 #pragma unroll
     for (int ks = 0; ks < KT / 4; ++ks)
 #pragma unroll
