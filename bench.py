@@ -245,9 +245,9 @@ def run_path(D, torch, plan, w, prec, steps, warmup, tune=True, graph=True, pers
             res["wall"] = res["wall_graph"]
         if agg_i:
             # agg_i of the winners after the step (metric-first), outside the timed step:
-            # the global top 16 and the two-level list (3 per case, top 16); first
-            # sweeping the winners' tiles, then from the column-maximum record of a
-            # winner pass run with it (and that pass's extra time)
+            # the global top 16 and the two-level list (3 per case, top 16); first with
+            # the record off (sweeping the winners' tiles), then from the column-maximum
+            # record the winner pass keeps by default (and n1_score's time either way)
             def timed(fn, reps):
                 fn()
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -262,14 +262,15 @@ def run_path(D, torch, plan, w, prec, steps, warmup, tune=True, graph=True, pers
                      ("per_case3_top16", lambda: bt.n1_worst_per_case(flows, nv, prec, out, 3, 16)))
             agg = {"sweep": {}, "record": {}}
             lists = {}
+            base_cfg = bt.get_tuning()
+            score = lambda: bt.n1_score(flows, nv, prec, out=out)
+            bt.set_tuning(**dict(base_cfg, worst_record=-1))
+            agg["n1_score_without_record_ms"] = timed(score, 5)
             for name, fn in calls:
                 agg["sweep"][name] = timed(fn, 3)
                 lists[name] = fn().cpu().numpy().copy()
-            base_cfg = bt.get_tuning()
-            score = lambda: bt.n1_score(flows, nv, prec, out=out)
+            bt.set_tuning(**dict(base_cfg, worst_record=0))
             agg["n1_score_ms"] = timed(score, 5)
-            bt.set_tuning(**dict(base_cfg, worst_record=1))
-            agg["n1_score_with_record_ms"] = timed(score, 5)
             for name, fn in calls:
                 agg["record"][name] = timed(fn, 3)
                 assert np.array_equal(fn().cpu().numpy(), lists[name]), \

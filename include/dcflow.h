@@ -434,17 +434,18 @@ typedef struct {
                           the injections of chunk i + 1 running beside the scan of
                           chunk i on a second stream of the batch (per-candidate
                           injections only; the results are the same)               */
-  int32_t worst_record; /* nonzero: the winner pass of n1_score also records, per
-                          candidate, the winner's maximum load of every scored
-                          contingency column and of N-0 (plans whose monitored rows
-                          form one band of the worst-case pass, the case of
-                          dcflow_n1_worst_per_case; ignored otherwise).  A following
+  int32_t worst_record; /* 0 (default) or positive: the winner pass of n1_score also
+                          records, per candidate, the winner's maximum load of every
+                          scored contingency column and of N-0 (plans whose monitored
+                          rows form one band of the worst-case pass, the case of
+                          dcflow_n1_worst_per_case; nothing otherwise).  A following
                           n1_worst or n1_worst_per_case call with the same flows and
                           score array reads them instead of sweeping the winner's
                           LODF' tiles again (same results, bit for bit); a new
                           evaluation or score call replaces the record.  Costs one
-                          [n_cand][ld_o + 1] array of the batch (always reserved for
-                          such plans) and a little of the winner pass's time      */
+                          [n_cand][ld_o + 1] array of the batch (reserved for such
+                          plans) and about 1% of n1_score.  Negative: off (the
+                          worst-case calls sweep)                                    */
   double guard_tol;    /* error guard of the reduced-precision scan (FP32, BF16,
                           BF16X6), in rating units: per candidate, a contingency column
                           whose FP32 error bound (k + 4) 2^-24 S_c max_v |y_cv| exceeds

@@ -37,7 +37,7 @@ def _arch() -> str:
 def shape_key(batch: "D.Batch", n_var: int, prec: str) -> str:
     v = batch.plan.view
     kmax = int(np.max(np.diff(batch.ca.off))) if batch.n_cand else 0
-    rec = 1 if batch.get_tuning().get("worst_record") else 0
+    rec = 0 if batch.get_tuning().get("worst_record", 0) < 0 else 1
     return (f"{_arch()}|{prec}|n_cand={batch.n_cand}|n_var={n_var}|n_mon={v.n_mon}|"
             f"n_out={v.n_out}|ld_o={v.ld_o}|n_multi={v.n_multi_out}|kmax={kmax}|rec={rec}")
 

@@ -707,7 +707,7 @@ int check_step(dcflow_batch *b, const double *dev_inj, int32_t n_var, dcflow_pre
 int dcflow_batch_set_tuning(dcflow_batch *b, const dcflow_tuning *t) {
   if (!b || !t) return DCFLOW_E_ARG;
   if (t->scan_vc < 0 || t->scan_rchunk < 0 || t->scan_rchunk % 64 || t->persistent < 0 ||
-      t->scan_band < 0 || t->scan_band % 64 || t->step_chunks < 0 || t->worst_record < 0 ||
+      t->scan_band < 0 || t->scan_band % 64 || t->step_chunks < 0 ||
       t->step_chunks > kMaxStepChunks || !std::isfinite(t->guard_tol))
     return DCFLOW_E_ARG;
   if (t->step_chunks > 1) {

@@ -917,7 +917,7 @@ __global__ void k_zero32(uint32_t *p, size_t n) {
 }
 
 // Whether n1_score writes the column-maximum record (see dcflow_batch::d_rec).
-inline bool record_on(const dcflow_batch *bt) { return bt->tune.worst_record != 0 && bt->d_rec; }
+inline bool record_on(const dcflow_batch *bt) { return bt->tune.worst_record >= 0 && bt->d_rec; }
 
 // Clears the work-queue counters and the per-variant maxima (a kernel, so that a
 // captured graph clears them too).

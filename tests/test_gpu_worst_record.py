@@ -1,10 +1,11 @@
-"""agg_i from the winner pass's column-maximum record (tuning worst_record): the
-n1_score winner pass keeps each candidate's column maxima of the winning variant
-(Sec. III-A agg_i, metric-first recompute of Sec. IV-B), and n1_worst /
-n1_worst_per_case read them instead of sweeping the winner's tiles again.  The
-lists must be bit for bit those of the sweep: with one and several scan bands,
-the FP32 error guard, score records naming another variant, a chunked step and
-graph replays; and they must still match the oracle."""
+"""agg_i from the winner pass's column-maximum record (tuning worst_record, on by
+default): the n1_score winner pass keeps each candidate's column maxima of the
+winning variant (Sec. III-A agg_i, metric-first recompute of Sec. IV-B), and
+n1_worst / n1_worst_per_case read them instead of sweeping the winner's tiles
+again.  The lists must be bit for bit those of the sweep (worst_record < 0): with
+one and several scan bands, the FP32 error guard, score records naming another
+variant, a chunked step and graph replays; and they must still match the
+oracle."""
 import numpy as np
 import pytest
 
@@ -67,7 +68,7 @@ def _same(ref, got, what):
 def test_record_gives_the_sweeps_lists(prec, tuning):
     w = _mixed()
     D, bt, x, flows, nv = _setup(w, prec)
-    bt.set_tuning(**tuning)
+    bt.set_tuning(**dict(tuning, worst_record=-1))
     sc_dev = bt.n1_score(flows, nv, prec)
     ref = _lists(D, bt, flows, nv, prec, sc_dev)
     sc_ref = sc_dev.cpu().numpy().copy()
@@ -102,6 +103,7 @@ def test_record_other_variant_falls_back():
         sel[::3] = True
         iv[:, col] = torch.where(sel & (iv[:, col] >= 0), (iv[:, col] + 1) % nv, iv[:, col])
 
+    bt.set_tuning(worst_record=-1)
     sc_dev = bt.n1_score(flows, nv, "fp64")
     edit(sc_dev)
     ref = _lists(D, bt, flows, nv, "fp64", sc_dev)
@@ -118,6 +120,7 @@ def test_record_chunked_step_and_replay(prec):
     import torch
     w = _mixed(seed=43)
     D, bt, x, flows, nv = _setup(w, prec)
+    bt.set_tuning(worst_record=-1)
     sc_dev = bt.n1_score(flows, nv, prec)
     ref = _lists(D, bt, flows, nv, prec, sc_dev)
     bt.set_tuning(worst_record=1, step_chunks=3)
@@ -143,9 +146,10 @@ def test_record_medium_batch():
     w = G.workload_medium(0, n_cand=384)
     for prec in ("fp64", "fp32"):
         D, bt, x, flows, nv = _setup(w, prec)
+        bt.set_tuning(worst_record=-1)
         sc_dev = bt.n1_score(flows, nv, prec)
         ref = _lists(D, bt, flows, nv, prec, sc_dev)
-        bt.set_tuning(worst_record=1)
+        bt.set_tuning()  # the default keeps the record
         bt.n1_score(flows, nv, prec, out=sc_dev)
         _same(ref, _lists(D, bt, flows, nv, prec, sc_dev), f"medium {prec}")
 
