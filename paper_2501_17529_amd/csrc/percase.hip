@@ -246,6 +246,8 @@ __global__ void __launch_bounds__(256) k_pc_sel(PcArgs A) {
   if (tid == 0) sl[0] = n_sel;
   const T *Fv = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vstar) * A.ld_f;
   const int e0 = A.off[cand], k = A.off[cand + 1] - e0;
+  // with the case maxima, only entries at or above tau can reach the final list
+  const T thr = A.cmx ? (T)A.cmx[(size_t)cand * (A.ld_o + 2) + A.ld_o + 1] : (T)-1;
   for (int q = wv; q < n_sel; q += 4) {
     const int slot = s_sel[q], c = slot - 1;
     const bool guard = c >= 0 && A.flag != nullptr &&
@@ -281,7 +283,7 @@ __global__ void __launch_bounds__(256) k_pc_sel(PcArgs A) {
         a = (T)(p < 0.0 ? -p : p);
       }
       const int key = slot * A.n_mon + row;
-      if (pc_better(a, key, lv[KM - 1], lk[KM - 1])) pc_insert(lv, lk, a, key);
+      if (a >= thr && pc_better(a, key, lv[KM - 1], lk[KM - 1])) pc_insert(lv, lk, a, key);
     }
     // the case's list: per_case rounds of the best head over the wave
     PcEntry *dst = A.ws + ((size_t)cand * A.nslots + slot) * A.per_case;
@@ -317,13 +319,17 @@ __global__ void __launch_bounds__(256) k_pc_sel(PcArgs A) {
   }
 }
 
-// Level 1, multi-outage cases: slot 1 + n_ctg + q.
+// Level 1, multi-outage cases: slot 1 + n_ctg + q, one thread per case.  The
+// candidate's U / r rows and F~ (the same for all its cases) are staged in LDS 64
+// rows at a time; each thread reads its case's seed entries for kPcRows rows at once.
 template <typename T, int KM>
 __global__ void __launch_bounds__(256) k_pc_multi(PcArgs A) {
-  constexpr int MM = DCFLOW_MULTI_MAX;
+  constexpr int MM = DCFLOW_MULTI_MAX, kRows = 64, kPcRows = 8;
+  __shared__ T s_ur[kMaxRank][kRows];
+  __shared__ T s_f[kRows];
   const int cand = blockIdx.x;
   const int q = blockIdx.y * blockDim.x + threadIdx.x;
-  if (q >= A.n_multi) return;
+  const bool act = q < A.n_multi;  // the threads past the last case still stage rows
   const int slot = 1 + A.n_ctg + q;
   T lv[KM];
   int lk[KM];
@@ -333,54 +339,80 @@ __global__ void __launch_bounds__(256) k_pc_multi(PcArgs A) {
     lk[j] = kEmptyKey;
   }
   int vstar = 0;
-  const bool live = !pc_skip(A, cand, vstar) && A.mok[(size_t)cand * A.n_multi + q] != 0;
-  if (live) {
+  const bool cand_live = !pc_skip(A, cand, vstar);  // block-uniform
+  const bool live = cand_live && act && A.mok[(size_t)cand * A.n_multi + q] != 0;
+  // with the case maxima, only entries at or above tau can reach the final list
+  const T thr = A.cmx ? (T)A.cmx[(size_t)cand * (A.ld_o + 2) + A.ld_o + 1] : (T)-1;
+  if (cand_live) {
     const T *Fv = static_cast<const T *>(A.F) + ((size_t)cand * A.nvar + vstar) * A.ld_f;
     const int e0 = A.off[cand], k = A.off[cand + 1] - e0;
-    const int a = A.moff[q], m = A.moff[q + 1] - a;
-    double p1s[MM];
-#pragma unroll
-    for (int j = 0; j < MM; ++j) p1s[j] = j < m ? (double)Fv[A.out_pos[A.mcol[a + j]]] : 0.0;
-    const double *cq = A.mcoef + ((size_t)cand * A.n_multi + q) * 16;
+    const int a = live ? A.moff[q] : 0, m = live ? A.moff[q + 1] - a : 0;
     T z[MM], w[MM][kMaxRank];
+    {
+      double p1s[MM];
 #pragma unroll
-    for (int j = 0; j < MM; ++j) {
-      double zz = 0.0;
-#pragma unroll
-      for (int t = 0; t < MM; ++t) zz += cq[j * 4 + t] * p1s[t];
-      z[j] = (T)zz;
-#pragma unroll
-      for (int e = 0; e < kMaxRank; ++e)
-        w[j][e] = (j < m && e < k) ? PcOps<T>::w(A, e0 + e, A.mcol[a + j]) : (T)0;
-    }
-    for (int row = 0; row < A.n_mon; ++row) {
-      T ur[kMaxRank];
-#pragma unroll
-      for (int e = 0; e < kMaxRank; ++e) ur[e] = e < k ? PcOps<T>::ur(A, e0 + e, row) : (T)0;
-      T p = (T)((double)Fv[row] * A.inv_r[row]);
+      for (int j = 0; j < MM; ++j) p1s[j] = j < m ? (double)Fv[A.out_pos[A.mcol[a + j]]] : 0.0;
+      const double *cq = A.mcoef + ((size_t)cand * A.n_multi + (live ? q : 0)) * 16;
 #pragma unroll
       for (int j = 0; j < MM; ++j) {
-        if (j < m) {
-          T l = (T)A.lsdm[(size_t)(a + j) * A.mon_pad + row];
+        double zz = 0.0;
 #pragma unroll
-          for (int e = 0; e < kMaxRank; ++e) l = pc_fma(ur[e], w[j][e], l);
-          p = pc_fma(l, z[j], p);
+        for (int t = 0; t < MM; ++t) zz += (j < m ? cq[j * 4 + t] : 0.0) * p1s[t];
+        z[j] = (T)zz;
+#pragma unroll
+        for (int e = 0; e < kMaxRank; ++e)
+          w[j][e] = (j < m && e < k) ? PcOps<T>::w(A, e0 + e, A.mcol[a + j]) : (T)0;
+      }
+    }
+    for (int c0 = 0; c0 < A.n_mon; c0 += kRows) {
+      __syncthreads();  // the previous chunk is consumed
+      for (int i = threadIdx.x; i < kRows * (kMaxRank + 1); i += blockDim.x) {
+        const int e = i / kRows, r = i - e * kRows, row = c0 + r;  // row < mon_pad
+        if (e < kMaxRank)
+          s_ur[e][r] = e < k ? PcOps<T>::ur(A, e0 + e, row) : (T)0;
+        else
+          s_f[r] = (T)((double)Fv[row] * A.inv_r[row]);
+      }
+      __syncthreads();
+      if (!live) continue;
+      const int rows = min(kRows, A.n_mon - c0);
+      // branch-free: the sub-columns past m read the case's last one (finite) and
+      // meet z = 0 and W = 0, which leaves p unchanged
+      for (int r0 = 0; r0 < rows; r0 += kPcRows) {
+        T l[kPcRows][MM];
+#pragma unroll
+        for (int u = 0; u < kPcRows; ++u)
+#pragma unroll
+          for (int j = 0; j < MM; ++j)
+            l[u][j] = (T)A.lsdm[(size_t)(a + max(min(j, m - 1), 0)) * A.mon_pad + c0 + r0 + u];
+#pragma unroll
+        for (int u = 0; u < kPcRows; ++u) {
+          const int r = r0 + u, row = c0 + r;
+          T p = s_f[r];
+#pragma unroll
+          for (int j = 0; j < MM; ++j) {
+            T lj = l[u][j];
+#pragma unroll
+            for (int e = 0; e < kMaxRank; ++e) lj = pc_fma(s_ur[e][r], w[j][e], lj);
+            p = pc_fma(lj, z[j], p);
+          }
+          const T ab = p < (T)0 ? -p : p;
+          const int key = slot * A.n_mon + row;
+          if (r < rows && ab >= thr && pc_better(ab, key, lv[KM - 1], lk[KM - 1]))
+            pc_insert(lv, lk, ab, key);
         }
       }
-      const T ab = p < (T)0 ? -p : p;
-      const int key = slot * A.n_mon + row;
-      if (pc_better(ab, key, lv[KM - 1], lk[KM - 1])) pc_insert(lv, lk, ab, key);
     }
   }
-  pc_store(A, cand, slot, lv, lk);
+  if (act) pc_store(A, cand, slot, lv, lk);
 }
 
 // Level 2: one workgroup per candidate (one wave when the case maxima leave a few
 // lists: the hot columns, N-0, guarded and multi-outage cases; four waves over
-// every slot otherwise).  With the case maxima and at most kFinRankCap entries in
-// the listed slots, the entries go to LDS and each counts the entries before it;
-// else each thread keeps the top KM of the entries of its slots and the block
-// takes one entry per round from the heads.
+// every slot otherwise).  With the case maxima the listed slots' entries go to LDS
+// and each counts the entries before it (up to kFinRankCap entries); else each
+// thread keeps the top KM of the entries of its slots and the block takes one
+// entry per round from the heads.
 template <int KM>
 __global__ void __launch_bounds__(256) k_pc_fin(PcArgs A, dcflow_case *out) {
   __shared__ double s_bv[4];
@@ -426,9 +458,9 @@ __global__ void __launch_bounds__(256) k_pc_fin(PcArgs A, dcflow_case *out) {
     }
     out[(size_t)cand * A.top_k + j] = e;
   };
-  if (A.cmx && (size_t)n_iter * A.per_case <= (size_t)kFinRankCap) {  // block-uniform
+  if (A.cmx) {  // block-uniform
     // the listed slots' entries in LDS; a real entry's place is the number of
-    // entries before it (the keys are unique)
+    // entries before it (the keys are unique); more than kFinRankCap: the rounds
     __shared__ PcEntry s_e[kFinRankCap];
     __shared__ int s_n;
     if (tid == 0) s_n = 0;
@@ -438,11 +470,13 @@ __global__ void __launch_bounds__(256) k_pc_fin(PcArgs A, dcflow_case *out) {
       for (int j = 0; j < A.per_case; ++j) {
         const PcEntry e = base[(size_t)s * A.per_case + j];
         if (e.k == kEmptyKey) break;  // lists are sorted, empties last
-        s_e[atomicAdd(&s_n, 1)] = e;
+        const int pos = atomicAdd(&s_n, 1);
+        if (pos < kFinRankCap) s_e[pos] = e;
       }
     }
     __syncthreads();
     const int n = s_n;
+    if (n > kFinRankCap) goto rounds;
     for (int i = tid; i < n; i += blockDim.x) {
       const PcEntry e = s_e[i];
       int rank = 0;
@@ -455,6 +489,7 @@ __global__ void __launch_bounds__(256) k_pc_fin(PcArgs A, dcflow_case *out) {
     for (int j = n + tid; j < A.top_k; j += blockDim.x) emit(j, -1.0, kEmptyKey);
     return;
   }
+rounds:
   for (int i = tid; i < n_iter; i += blockDim.x) {
     const int s = slot_of(i);
     for (int j = 0; j < A.per_case; ++j) {

@@ -1966,6 +1966,12 @@ __global__ void __launch_bounds__(256) k_scan_multi(ScanArgs A) {
     lk[j] = kEmpty;
   }
   const int n_ctg = A.n_ctg;
+  T thr = (T)-1;  // MODE 2: the largest of the candidate's band thresholds
+  if (MODE == 2 && A.tau) {
+    double t = -1.0;
+    for (int b = 0; b < A.nbands; ++b) t = fmax(t, A.tau[(size_t)cand * A.nbands + b]);
+    thr = (T)t;
+  }
   for (int q0 = 0; q0 < A.n_multi && !skip; q0 += QC) {
     __syncthreads();
     // z of the round's cases for the workgroup's variants
@@ -2036,8 +2042,10 @@ __global__ void __launch_bounds__(256) k_scan_multi(ScanArgs A) {
           }
           ov += fmax((double)ap - 1.0, 0.0);
         } else {
+          // only entries at or above the candidate's largest band threshold can
+          // reach its list (each band has top_k entries at or above its tau)
           const int key = (n_ctg + q + 1) * A.n_mon + row;
-          if (better(ap, key, lv[KM - 1], lk[KM - 1])) list_insert(lv, lk, ap, key);
+          if (ap >= thr && better(ap, key, lv[KM - 1], lk[KM - 1])) list_insert(lv, lk, ap, key);
         }
       }
     }
@@ -2081,6 +2089,49 @@ __global__ void __launch_bounds__(256) k_scan_multi(ScanArgs A) {
     }
   } else {
     WEntry *dst = A.wpart + slot * A.top_k;
+    // the chunk's list: the union of the lanes' lists ranked in LDS (each real entry
+    // counts the entries before it; the keys are unique), else rounds
+    {
+      constexpr int kRankCap = 512;
+      __shared__ WEntry s_re[kRankCap];
+      __shared__ int s_rn;
+      if (tid == 0) s_rn = 0;
+      __syncthreads();
+      int n = 0;
+#pragma unroll
+      for (int j = 0; j < KM; ++j) n += lk[j] != kEmpty ? 1 : 0;
+      const int base = n > 0 ? atomicAdd(&s_rn, n) : 0;
+#pragma unroll
+      for (int j = 0; j < KM; ++j)
+        if (j < n && base + j < kRankCap) {
+          WEntry e;
+          e.v = (double)lv[j];
+          e.k = lk[j];
+          e.pad = 0;
+          s_re[base + j] = e;
+        }
+      __syncthreads();
+      const int N = s_rn;
+      if (N <= kRankCap) {
+        for (int i = tid; i < N; i += blockDim.x) {
+          const WEntry e = s_re[i];
+          int rank = 0;
+          for (int f = 0; f < N; ++f) {
+            const WEntry o = s_re[f];
+            rank += better(o.v, o.k, e.v, e.k) ? 1 : 0;
+          }
+          if (rank < A.top_k) dst[rank] = e;
+        }
+        for (int j = N + tid; j < A.top_k; j += blockDim.x) {
+          WEntry e;
+          e.v = -1.0;
+          e.k = kEmpty;
+          e.pad = 0;
+          dst[j] = e;
+        }
+        return;
+      }
+    }
     for (int j = 0; j < A.top_k; ++j) {
       T bv = lv[0];
       int bk = lk[0];
