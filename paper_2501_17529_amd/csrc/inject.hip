@@ -198,13 +198,13 @@ constexpr int kXcd = 8;  // MI355X: workgroups are dealt round-robin to 8 XCDs (
 // thousand terms of a large grid a running FP32 sum would carry the rounding of
 // its full magnitude at every step (flows of heavily loaded corridors are sums of
 // many same-signed terms).
-template <typename T, int FL>
+template <typename T, int FL, bool PRE = false>
 __global__ void __launch_bounds__(256, (sizeof(T) == 4 && FL == 0) ? 4 : 2)
 k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, int ncols,
        int nvar, int shared, T *__restrict__ F, int ld_f, const int32_t *__restrict__ off,
        const double *__restrict__ U, int ld_er, const double *__restrict__ z, int vmax,
        int correct, int n_mt, int n_nt, const double *__restrict__ pbase,
-       const double *__restrict__ fber) {
+       const double *__restrict__ fber, const float *__restrict__ Xf = nullptr, int ldx = 0) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int LDS_K = Ldk<T>::v;
   // FP64: two LDS stages (one barrier per K step; two workgroups per CU either way);
@@ -230,7 +230,9 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
   // fragments: no instruction touches the next k-tile's loads before the MFMAs of
   // the current one, so they stay in flight under them.  The columns past ncols
   // read row 0 of X (never stored) and the last k-tile clamps its indices (He is
-  // zero there).  FP32 forms x - p_base in FP64 before rounding it, in registers.
+  // zero there).  FP32 (PRE) reads x - p_base rounded to FP32 by k_sub_f32 (rows of
+  // ldx, zero past n; the columns past ncols read row 0): plain loads, consumed only
+  // when stored.
   __shared__ double Ps[NS][KT];
   const double *xr = brow ? brow : X;
   double pv = 0.0;
@@ -247,6 +249,12 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
         for (int q = 0; q < 8; ++q) rb[q] = xr[min(kb + q, n - 1)];
       }
       if (tid < KT) pv = pbase[min(kt * KT + tid, n - 1)];
+      return;
+    }
+    if constexpr (PRE) {
+      const float *xf = Xf + (size_t)(bcol < ncols ? bcol : 0) * ldx;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) rb[q] = xf[kb + q];  // kb + 8 <= n rounded to 16 <= ldx
       return;
     }
     if (brow && kb + 8 <= n) {
@@ -425,6 +433,29 @@ k_split_x(const double *__restrict__ X, int n, const double *__restrict__ pbase,
     }
     *reinterpret_cast<bf8 *>(dst + q * xpart) = v;
   }
+}
+
+// FP32 mode: x - p_base of every column rounded to FP32 once per call (the values
+// the GEMM's B operand takes), rows of ldx, zero past n.  Eight k per thread.
+__global__ void __launch_bounds__(256)
+k_sub_f32(const double *__restrict__ X, int n, const double *__restrict__ pbase, int ncols,
+          int ldx, float *__restrict__ Xf) {
+  const int groups = ldx / 8;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)ncols * groups) return;
+  const int col = (int)(idx / groups), k0 = (int)(idx - (size_t)col * groups) * 8;
+  const double *src = X + (size_t)col * n;
+  float v[8];
+  if (k0 + 8 <= n) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (float)(src[k0 + e] - pbase[k0 + e]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = k0 + e < n ? (float)(src[k0 + e] - pbase[k0 + e]) : 0.0f;
+  }
+  float *dst = Xf + (size_t)col * ldx + k0;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) dst[e] = v[e];
 }
 
 template <int NP, int FL>
@@ -615,6 +646,33 @@ hipError_t launch_gemm(const dcflow_plan *p, const T *He, int np, const double *
   dim3 grid(kXcd * ((n_nt + kXcd - 1) / kXcd) * n_mt);
   if constexpr (sizeof(T) == 4) {
     const size_t part = (size_t)p->ld_er * p->ld_h;
+    if (np == 0) {
+      // x - p_base in FP32 into the split buffer (it holds at least xs_cols columns of
+      // ldx floats), then the GEMM with plain B loads; larger GEMMs in column blocks
+      const int blk = (int)std::min<size_t>((size_t)ncols, bt->xs_cols / nvar * nvar);
+      if (blk <= 0) return hipErrorInvalidValue;
+      if (ncols > blk) {
+        for (int cb = 0; cb < ncols; cb += blk) {
+          const int nc = std::min(blk, ncols - cb);
+          const hipError_t e = launch_gemm<T>(p, He, np, X + (size_t)cb * p->n_inj, nc, nvar, shared,
+                                              F + (size_t)cb * p->ld_er, bt, correct,
+                                              off + (correct ? cb / nvar : 0), 0, s);
+          if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+      }
+      (void)col0;
+      float *xf = reinterpret_cast<float *>(bt->d_xs);
+      const size_t nthr = (size_t)ncols * (bt->ldx / 8);
+      k_sub_f32<<<dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s>>>(X, p->n_inj, p->d_pbase,
+                                                                          ncols, bt->ldx, xf);
+      DCF_CHECK_LAUNCH();
+      k_gemm<float, kFlush32, true><<<grid, dim3(256), 0, s>>>(
+          He, p->ld_h, X, p->n_inj, ncols, nvar, shared, F, p->ld_er, off, bt->d_U, p->ld_er,
+          bt->d_z, bt->vmax, correct, n_mt, n_nt, p->d_pbase, p->d_fber, xf, bt->ldx);
+      DCF_CHECK_LAUNCH();
+      return hipSuccess;
+    }
     if (np == 3 || np == 1) {
       // the split buffer holds xs_cols columns: larger GEMMs run in blocks of whole
       // candidates (the parts of a block are written just before its GEMM)
