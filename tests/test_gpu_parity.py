@@ -192,9 +192,11 @@ def test_bf16_flows_within_rounding_bound():
     say(f"bf16: worst error / bound = {worst:.3f}")
 
 
-def test_bf16x6_gemm_in_column_blocks(monkeypatch):
-    """With the BF16 split buffer capped below the batch's columns the GEMM runs in
-    blocks of whole candidates: the flows are the same, bit for bit."""
+@pytest.mark.parametrize("prec", ["bf16x6", "fp32"])
+def test_bf16x6_gemm_in_column_blocks(monkeypatch, prec):
+    """With the split buffer (BF16 parts, or x - p_base in FP32) capped below the
+    batch's columns the GEMM runs in blocks of whole candidates: the flows are the
+    same, bit for bit; and in FP32 they equal the FP64 path's within FP32 rounding."""
     import torch
     from paper_2501_17529_amd import dcflow as D
     w = G.workload_medium(3, n_cand=40, n_var=4)
@@ -206,7 +208,16 @@ def test_bf16x6_gemm_in_column_blocks(monkeypatch):
             monkeypatch.setenv("DCFLOW_SPLIT_COLS", cap)
         bt = D.Batch(plan, w.cands, 4)
         bt.eval_topologies()
-        fl = bt.eval_injections(x, 4, False, "bf16x6")
+        fl = bt.eval_injections(x, 4, False, prec)
         torch.cuda.synchronize()
         got.append(fl.clone())
     assert torch.equal(got[0], got[1])
+    if prec == "fp32":
+        monkeypatch.delenv("DCFLOW_SPLIT_COLS", raising=False)
+        bt = D.Batch(plan, w.cands, 4)
+        bt.eval_topologies()
+        f64 = bt.eval_injections(x, 4, False, "fp64").double()
+        torch.cuda.synchronize()
+        f32 = got[0].double()
+        scale = f64.abs().max().item()
+        assert (f32 - f64).abs().max().item() <= 1e-4 * scale + 1e-9
