@@ -180,3 +180,37 @@ def test_record_is_read(prec):
         # column passes it
         assert np.all(cases["load"][live][:, first:] == -1.0), \
             f"{prec} {name}: the record was not read"
+
+
+def test_record_wide_contingency_set():
+    """More than 1,024 contingency columns (ld_o 1,152) on one band of 384 monitored
+    rows: k_rec_select does not take them, k_scan_colmax reads the record into LDS.
+    The lists equal the sweep's, and the oracle's for sampled candidates."""
+    rng = np.random.default_rng(45)
+    g = G.make_grid(700, 1300, 45)
+    lists = []
+    for i in range(12):
+        k = int(rng.integers(1, 6))
+        ns = min(int(rng.binomial(k, 0.5)), 4)
+        lists.append(G.sample_candidate(g, rng, ns, k - ns))
+    cands = G.Candidates.from_lists(lists)
+    mon = np.sort(rng.choice(1300, size=380, replace=False)).astype(np.int32)
+    out = np.sort(rng.choice(1300, size=1100, replace=False)).astype(np.int32)
+    inj = G.perturbed_injections(g, rng, (len(lists), 3), 0.2)
+    w = G.Workload("worst-record-wide", g, mon, out, cands, inj, False)
+    for prec in ("fp64", "fp32"):
+        D, bt, x, flows, nv = _setup(w, prec)
+        assert bt.plan.view.ld_o > 1024
+        bt.set_tuning(worst_record=-1)
+        sc_dev = bt.n1_score(flows, nv, prec)
+        ref = _lists(D, bt, flows, nv, prec, sc_dev)
+        bt.set_tuning(worst_record=1)
+        bt.n1_score(flows, nv, prec, out=sc_dev)
+        got = _lists(D, bt, flows, nv, prec, sc_dev)
+        _same(ref, got, f"wide {prec}")
+    r = oracle_rating(w)
+    idx = [0, 5]
+    sc = D.Batch.scores_to_numpy(sc_dev, bt.n_cand)
+    cases = got[0][: bt.n_cand * 16 * D.CASE_DTYPE.itemsize].view(D.CASE_DTYPE).reshape(bt.n_cand, 16)
+    for i, o in zip(idx, oracle_scores(w, idx, r)):
+        compare_worst(w, cases[i], sc[i], o, 16, "fp32", f"wide cand {i}")
