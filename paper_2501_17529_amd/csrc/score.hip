@@ -696,22 +696,37 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
         for (int r = 0; r < 4; ++r) fr[a][r] = fsv[a * 16 + r];
 #pragma unroll
       for (int b = 0; b < NB; ++b) yc[b] = ys[colbase + b * 16 + li];
-      T pv[RB][NB][4];
-      T mt = (T)0, cm[NB];
+      // per column: the sum of max(|p|, 1) over the lane's 4 RB rows, less 4 RB, is its
+      // overload sum (loads within the rating add exactly 1, so rounding enters only
+      // where a row is overloaded, and the difference with 4 RB is exact; a tile
+      // without overloads adds 0).  FP64 accumulates it as the elements are made (no
+      // tile held in registers: four waves per SIMD); FP32 keeps the tile and sums it
+      // only where the lane's part holds an overload (fewer instructions; the same bits)
+      constexpr bool kInline = sizeof(T) == 8;
+      T mt = (T)0, cm[NB], acc[NB], pv[RB][NB][4];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) cm[b] = (T)0;
+      for (int b = 0; b < NB; ++b) {
+        cm[b] = (T)0;
+        acc[b] = (T)0;
+      }
 #pragma unroll
       for (int a = 0; a < RB; ++a)
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
           for (int r = 0; r < 4; r += 2) {
-            pv[a][b][r] = tfma(L[a][b][r], yc[b], fr[a][r]);
-            pv[a][b][r + 1] = tfma(L[a][b][r + 1], yc[b], fr[a][r + 1]);
+            const T p0 = tfma(L[a][b][r], yc[b], fr[a][r]);
+            const T p1 = tfma(L[a][b][r + 1], yc[b], fr[a][r + 1]);
             if (REC)
-              cm[b] = absmax3(cm[b], pv[a][b][r], pv[a][b][r + 1]);
+              cm[b] = absmax3(cm[b], p0, p1);
             else
-              mt = absmax3(mt, pv[a][b][r], pv[a][b][r + 1]);
+              mt = absmax3(mt, p0, p1);
+            if (kInline) {
+              acc[b] = add_absmax1(acc[b], p0, p1);
+            } else {
+              pv[a][b][r] = p0;
+              pv[a][b][r + 1] = p1;
+            }
           }
       if (REC) {
         const bool same = tc == acc_tc;
@@ -727,18 +742,16 @@ __device__ __forceinline__ void scan_win_item(const ScanArgs &A, int cand, int b
       tie = gt ? 0 : (mt == run ? 1 : tie);
       first = gt ? tid_tile : first;
       run = gt ? mt : run;
-      if (mt > (T)1) {  // overloads in this lane's part of the tile
-        // per column: sum of max(|p|, 1) over the lane's 4 RB rows, less 4 RB.
-        // Loads within the rating add exactly 1, so rounding enters only where a
-        // row is overloaded, and the difference with 4 RB is exact.
-        T acc[NB];
+      if (kInline || mt > (T)1) {
+        if (!kInline) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc[b] = (T)0;
+          for (int a = 0; a < RB; ++a)
 #pragma unroll
-        for (int i = 0; i < 4 * RB; i += 2)
+            for (int b = 0; b < NB; ++b)
 #pragma unroll
-          for (int b = 0; b < NB; ++b)
-            acc[b] = add_absmax1(acc[b], pv[i / 4][b][i % 4], pv[i / 4][b][i % 4 + 1]);
+              for (int r = 0; r < 4; r += 2)
+                acc[b] = add_absmax1(acc[b], pv[a][b][r], pv[a][b][r + 1]);
+        }
         T o = (T)0;
 #pragma unroll
         for (int b = 0; b < NB; ++b)
@@ -2705,7 +2718,7 @@ hipError_t run_scan(dcflow_batch *bt, const T *flows, int nvar, dcflow_score *ou
   a.nbt = a.nbands + a.nmb + a.ng;
   const size_t lds = fixed + sizeof(T) * (size_t)a.rchunk;
   if (lds > kLdsBudget) return kShapeMisfit;
-  constexpr int kWinWaves = sizeof(T) == 4 ? 4 : 3;
+  constexpr int kWinWaves = 4;
   if (rec) {
     a.rec = bt->d_rec;
     a.rec_var = bt->d_rec_var;
