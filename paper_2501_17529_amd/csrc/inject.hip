@@ -331,12 +331,17 @@ k_gemm(const T *__restrict__ He, int ld_h, const double *__restrict__ X, int n, 
         for (int b = 0; b < 4; ++b) bf[b].x[ks] -= pk;
       }
     }
+    // FP64: the wave holds a raised issue priority through its MFMAs, so that the
+    // other wave on the SIMD issues its loads and LDS traffic around them rather
+    // than between (measured 2% faster in FP64, 1.5% slower in FP32)
+    if constexpr (sizeof(T) == 8) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int ks = 0; ks < KT / 4; ++ks)
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::op(af[a].x[ks], bf[b].x[ks], acc[a][b]);
+    if constexpr (sizeof(T) == 8) __builtin_amdgcn_s_setprio(0);
     if constexpr (FL > 0) {
       if (kt % FL == FL - 1 || kt + 1 == nk) flush();
     }

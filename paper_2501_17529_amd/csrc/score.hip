@@ -335,11 +335,16 @@ __device__ __forceinline__ void build_tile(T (&L)[RB][NB][4], const ScanArgs &A,
   typename TileOf<T>::blk c[RB][NB];
   T fa[RB], fb[NB];
   tile_load_seed(c, seed_of(A, (T)0), A.ld_o, rowbase, colbase, lane);
+  // raised issue priority through the fragment loads and MFMAs: the build of one
+  // wave goes ahead of the VALU sweeps of the others on its SIMD, whose work then
+  // fills the MFMA cycles (measured about 1% faster in both precisions)
+  __builtin_amdgcn_s_setprio(1);
   for (int h = 0; h * 4 < k; ++h) {  // wave-uniform
     update_frags(fa, fb, A, e0, k, h, rowbase, colbase, g, li);
     frag_mask(fa, fb, k, h, g);
     tile_mfma_step(c, fa, fb);
   }
+  __builtin_amdgcn_s_setprio(0);
 #pragma unroll
   for (int a = 0; a < RB; ++a)
 #pragma unroll
